@@ -1,0 +1,689 @@
+"""FP64 reference of GS^3's triple splatting (test infrastructure only).
+
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may use this module. It is a plain, slow, brute-force statement of what the
+path computes: every pixel gathers every Gaussian whose 2D footprint can
+reach it, sorts them, and composites them front to back, with no tiles,
+blocking or fusion. Inputs are plain arrays (numpy or torch) of raw scene
+parameters; everything is evaluated in torch float64 on the CPU, so torch
+autograd of ``render`` gives reference gradients.
+
+Paper sections followed:
+  Sec. 3, Eq. 1      spatial Gaussian, covariance R S S^T R^T
+  Sec. 3, Eq. 2-3    projected splats, sort, front-to-back blend
+  Sec. 4, Fig. 2     deferred pipeline: final = shading * shadow + residual
+  Sec. 4.1, Eq. 4-7  reflectance: modified Lambertian + angular Gaussians
+  Sec. 4.2, Fig. 3   shadow splatting, beta-weighted averaging, 0.015 bias
+  Sec. 4.2, Eq. 8    shadow refinement MLP Phi
+  Sec. 4.3           residual RGB MLP Psi
+
+Readings of points the paper leaves open (camera model, EWA constants,
+cut-offs, sort keys, bias semantics) are the named constants of ``Consts``
+and the conventions stated in each function's docstring.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+__all__ = [
+    "Consts", "SMOOTH", "DT", "ELU_ALPHA", "EPS_D",
+    "as_t", "scene_tensors", "quat_to_rotmat", "covariance", "look_at",
+    "focal", "project", "tile_rects", "bin_tiles", "pixel_entries",
+    "shadow_pass", "shadow_accumulate", "shadow_values", "splat_radius", "diffuse", "angular_gaussian",
+    "lobe_frame", "shade", "mlp_forward", "camera_pass", "render",
+    "render_images", "sigmoid",
+]
+
+DT = torch.float64
+
+# Sec. 4.1, Eq. 5: the ELU hyper-parameter and epsilon are both 0.01.
+ELU_ALPHA = 0.01
+EPS_D = 0.01
+
+
+@dataclass(frozen=True)
+class Consts:
+    """Rasteriser conventions the paper inherits from vanilla Gaussian
+    splatting without stating them (Sec. 3), plus the paper's shadow bias.
+
+    near        cull a Gaussian whose view-space z is <= near
+    clamp_frac  clamp x/z and y/z to +-clamp_frac*tan(half fov) in the
+                Jacobian only (EWA)
+    dilation    added to both diagonal entries of the 2D covariance (px^2)
+    cutoff      a pixel is hit only if power >= -cutoff (3-sigma ellipse)
+    alpha_min   ... and alpha >= alpha_min
+    alpha_max   alpha = min(alpha_max, opacity * exp(power))
+    t_min       camera pass stops before a hit that would take T below t_min
+    shadow_bias Sec. 4.2: k shadows j only if dist_k < dist_j - bias
+    """
+    near: float = 0.2
+    clamp_frac: float = 1.3
+    dilation: float = 0.3
+    cutoff: float = 4.5
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    shadow_bias: float = 0.015
+
+
+# Smooth mode for finite-difference gradient checks: no thresholds anywhere,
+# every Gaussian reaches every pixel, no clamp, no early stop, no dilation.
+SMOOTH = Consts(dilation=0.0, cutoff=math.inf, alpha_min=0.0, alpha_max=1.0,
+                t_min=0.0, shadow_bias=0.0)
+
+
+def as_t(x) -> torch.Tensor:
+    """float64 CPU tensor view of an array (keeps autograd if already one)."""
+    if isinstance(x, torch.Tensor):
+        return x if x.dtype == DT else x.to(DT)
+    return torch.as_tensor(np.asarray(x, dtype=np.float64))
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + torch.exp(-x))
+
+
+def scene_tensors(scene, requires_grad: bool = False) -> Dict[str, torch.Tensor]:
+    """Raw per-Gaussian parameters as float64 tensors, Gaussian index first.
+
+    ``scene`` has attributes mean [3,N], log_scale [3,N], rot [4,N],
+    opacity_logit [N], shade_rot [4,N], albedo [3,N], lobe_axis [K,3,N],
+    lobe_log_sharp [K,N], lobe_amp [K,3,N], feat [F,N]."""
+    def t(a, perm=None):
+        x = as_t(a).clone()
+        if perm is not None:
+            x = x.permute(*perm).contiguous()
+        return x.requires_grad_(requires_grad)
+    return {
+        "mean": t(scene.mean, (1, 0)),
+        "log_scale": t(scene.log_scale, (1, 0)),
+        "rot": t(scene.rot, (1, 0)),
+        "opacity_logit": t(scene.opacity_logit),
+        "shade_rot": t(scene.shade_rot, (1, 0)),
+        "albedo": t(scene.albedo, (1, 0)),
+        "lobe_axis": t(scene.lobe_axis, (2, 0, 1)),      # [N,K,3]
+        "lobe_log_sharp": t(scene.lobe_log_sharp, (1, 0)),  # [N,K]
+        "lobe_amp": t(scene.lobe_amp, (2, 0, 1)),        # [N,K,3]
+        "feat": t(scene.feat, (1, 0)),
+    }
+
+
+# ---------------------------------------------------------------- geometry
+
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix of quaternion q = (w, x, y, z) after normalising it.
+    Used for R in Eq. 1 and for the world-to-shading rotation of Sec. 4.1."""
+    q = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    rows = [
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y),
+    ]
+    return torch.stack(rows, -1).reshape(q.shape[:-1] + (3, 3))
+
+
+def covariance(log_scale: torch.Tensor, rot: torch.Tensor) -> torch.Tensor:
+    """Sec. 3, Eq. 1: Sigma = R S S^T R^T with S = diag(exp(log_scale))."""
+    R = quat_to_rotmat(rot)
+    M = R * torch.exp(log_scale)[..., None, :]   # R @ diag(s)
+    return M @ M.transpose(-1, -2)
+
+
+def look_at(eye, target) -> torch.Tensor:
+    """World-to-camera rotation (rows: right, down, forward).
+
+    Camera axes x right, y down, z forward; world up is +z unless the view
+    direction is within acos(0.99) of it, then +y."""
+    eye, target = as_t(eye), as_t(target)
+    f = target - eye
+    f = f / torch.linalg.norm(f)
+    up = as_t([0.0, 0.0, 1.0]) if abs(float(f[2])) <= 0.99 else as_t([0.0, 1.0, 0.0])
+    r = torch.linalg.cross(f, up)
+    r = r / torch.linalg.norm(r)
+    d = torch.linalg.cross(f, r)
+    return torch.stack([r, d, f])
+
+
+def focal(view) -> float:
+    """Focal length in pixels from the horizontal field of view."""
+    return (view.width / 2.0) / math.tan(view.fov / 2.0)
+
+
+def project(mean: torch.Tensor, cov: torch.Tensor, view, consts: Consts,
+            depth_mode: str) -> Dict[str, torch.Tensor]:
+    """Project 3D Gaussians to 2D splats (Sec. 3; EWA splatting as in GS).
+
+    t = R_v (mu - eye); cull t_z <= near. Jacobian of the pinhole map at t
+    with x/z, y/z clamped to +-clamp_frac*tan(half fov); Sigma' = J R_v Sigma
+    R_v^T J^T + dilation*I; cull det <= 0; conic = Sigma'^-1; centre
+    (f t_x/t_z + W/2, f t_y/t_z + H/2). The depth key is t_z for the camera
+    ("z") and |mu - eye| toward the light ("dist", Sec. 4.2)."""
+    W, H = view.width, view.height
+    f = focal(view)
+    Rv = look_at(view.eye, view.target)
+    eye = as_t(view.eye)
+    t = (mean - eye) @ Rv.T
+    tz = t[:, 2]
+    valid = tz > consts.near
+    tzs = torch.where(valid, tz, torch.ones_like(tz))
+    lim_x = consts.clamp_frac * (W / 2.0) / f
+    lim_y = consts.clamp_frac * (H / 2.0) / f
+    xr = torch.clamp(t[:, 0] / tzs, -lim_x, lim_x)
+    yr = torch.clamp(t[:, 1] / tzs, -lim_y, lim_y)
+    zero = torch.zeros_like(tz)
+    J = torch.stack([
+        torch.stack([f / tzs, zero, -f * xr / tzs], -1),
+        torch.stack([zero, f / tzs, -f * yr / tzs], -1)], 1)        # [N,2,3]
+    cov_cam = Rv @ cov @ Rv.T
+    cov2 = J @ cov_cam @ J.transpose(1, 2)
+    a = cov2[:, 0, 0] + consts.dilation
+    b = cov2[:, 0, 1]
+    c = cov2[:, 1, 1] + consts.dilation
+    det = a * c - b * b
+    valid = valid & (det > 0)
+    dets = torch.where(valid, det, torch.ones_like(det))
+    conic = torch.stack([c / dets, -b / dets, a / dets], -1)
+    u = f * t[:, 0] / tzs + W / 2.0
+    v = f * t[:, 1] / tzs + H / 2.0
+    if depth_mode == "z":
+        depth = tz
+    elif depth_mode == "dist":
+        depth = torch.linalg.norm(mean - eye, dim=-1)
+    else:
+        raise ValueError(depth_mode)
+    return {"u": u, "v": v, "cov2": torch.stack([a, b, c], -1), "conic": conic,
+            "depth": depth, "valid": valid, "tz": tz, "det": det}
+
+
+# ----------------------------------------------------------------- binning
+
+def splat_radius(cov2: torch.Tensor, cutoff: float = 4.5) -> np.ndarray:
+    """Binning radius in pixels: ceil(sqrt(2 cutoff lambda_max)) with
+    lambda_max = mid + sqrt(max(0.1, mid^2 - det)) of the 2D covariance
+    (a, b, c); for the 3-sigma cut-off this is ceil(3 sqrt(lambda_max))."""
+    a, b, c = cov2[:, 0].detach(), cov2[:, 1].detach(), cov2[:, 2].detach()
+    mid = 0.5 * (a + c)
+    det = a * c - b * b
+    lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.1))
+    return torch.ceil(torch.sqrt(2.0 * cutoff * lam)).numpy().astype(np.int64)
+
+
+def tile_rects(u: np.ndarray, v: np.ndarray, radius: np.ndarray, W: int, H: int,
+               tile: int = 16):
+    """Tiles a splat is binned to: the tiles covering pixel columns
+    floor(u)-r .. floor(u)+r and rows floor(v)-r .. floor(v)+r, clamped to the
+    grid. Integer rule applied to given float32 centres and integer radii."""
+    tx = (W + tile - 1) // tile
+    ty = (H + tile - 1) // tile
+    iu = np.floor(np.clip(u.astype(np.float64), -2.0 ** 30, 2.0 ** 30)).astype(np.int64)
+    iv = np.floor(np.clip(v.astype(np.float64), -2.0 ** 30, 2.0 ** 30)).astype(np.int64)
+    r = radius.astype(np.int64)
+    x0 = np.maximum((iu - r) // tile, 0)
+    x1 = np.minimum((iu + r) // tile, tx - 1)
+    y0 = np.maximum((iv - r) // tile, 0)
+    y1 = np.minimum((iv + r) // tile, ty - 1)
+    empty = (x0 > x1) | (y0 > y1) | (r <= 0)
+    return x0, x1, y0, y1, empty
+
+
+def bin_tiles(u, v, radius, depth, W: int, H: int, tile: int = 16):
+    """Brute-force binning (Sec. 3 "sorted", Sec. 4.2 sorted by distance).
+
+    For every tile, the ids of the splats whose rect covers it, ordered by
+    (float32 depth bits, id). Returns (counts [tiles], flat id list, keys
+    [P] uint64 = tile << 32 | depth bits) exactly as a tile-major sort of
+    (tile, depth, id) would lay them out. Inputs are the float32 centres,
+    integer radii and float32 depths a projection produced."""
+    u = np.asarray(u, np.float32); v = np.asarray(v, np.float32)
+    depth = np.asarray(depth, np.float32)
+    radius = np.asarray(radius, np.int64)
+    x0, x1, y0, y1, empty = tile_rects(u, v, radius, W, H, tile)
+    tx = (W + tile - 1) // tile
+    ty = (H + tile - 1) // tile
+    dbits = depth.view(np.uint32).astype(np.uint64)
+    counts = np.zeros(tx * ty, np.int64)
+    lists = []
+    keys = []
+    n = u.shape[0]
+    ids = np.arange(n)
+    for t_id in range(tx * ty):
+        gx, gy = t_id % tx, t_id // tx
+        sel = (~empty) & (x0 <= gx) & (gx <= x1) & (y0 <= gy) & (gy <= y1)
+        members = ids[sel]
+        order = np.lexsort((members, dbits[members]))   # by depth bits, then id
+        members = members[order]
+        counts[t_id] = members.size
+        lists.append(members)
+        keys.append((np.uint64(t_id) << np.uint64(32)) | dbits[members])
+    return counts, np.concatenate(lists) if lists else np.zeros(0, np.int64), \
+        np.concatenate(keys) if keys else np.zeros(0, np.uint64)
+
+
+# -------------------------------------------------------- per-pixel entries
+
+# Error model of the float32 evaluation, used only to flag outputs whose
+# value hangs on a threshold decision (cut-off, alpha minimum, early stop,
+# depth order, shadow bias) that a float32 evaluation may take differently
+# from this float64 one. It assumes splat centres and depths accurate to
+# ~1e-6 px / 5e-7 relative (projection evaluated in double and rounded) and
+# per-pixel arithmetic in float32.
+_POS_ERR = 1e-6          # absolute error of a splat centre, px
+_POW_REL = 4e-6          # relative error of power, alpha
+_DEPTH_REL = 5e-7        # relative error of a depth / distance key
+_AMB_T = 2e-5            # relative margin on the early-stop test
+AMB_BUDGET = 5e-5        # an output is ambiguous when it could move this much
+
+
+def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
+                  pixels: Optional[torch.Tensor] = None, rows=None):
+    """Every (pixel, Gaussian) pair whose power can reach the cut-off,
+    grouped per pixel and sorted by (depth, id): a padded [P, L] layout.
+
+    The hit test (Sec. 3, Eq. 2): d = pixel centre (i+0.5, j+0.5) - centre,
+    power = -1/2 d^T conic d, alpha = min(alpha_max, opacity * exp(power)),
+    beta = exp(power) (the splat's density at the pixel centre); a hit needs
+    power >= -cutoff and alpha >= alpha_min. Pairs just outside the cut-off
+    are kept as non-hits so that threshold ambiguity can be measured.
+
+    ``rows`` = (y0, y1) selects a band of full rows, else ``pixels`` is a
+    1-D tensor of flat pixel indices (y*W + x); default all pixels."""
+    u, v, conic, cov2, depth, valid = (proj["u"], proj["v"], proj["conic"],
+                                       proj["cov2"], proj["depth"], proj["valid"])
+    n = u.shape[0]
+    if rows is not None:
+        ylo, yhi = rows
+        xlo, xhi = 0, W
+        pix_set = None
+    else:
+        if pixels is None:
+            pixels = torch.arange(W * H)
+        pixels = torch.as_tensor(pixels, dtype=torch.int64)
+        assert torch.unique(pixels).numel() == pixels.numel(), "pixels must be distinct"
+        py_all, px_all = pixels // W, pixels % W
+        ylo, yhi = int(py_all.min()), int(py_all.max()) + 1
+        xlo, xhi = int(px_all.min()), int(px_all.max()) + 1
+        pix_set = torch.full(((yhi - ylo) * (xhi - xlo),), -1, dtype=torch.int64)
+        pix_set[(py_all - ylo) * (xhi - xlo) + (px_all - xlo)] = torch.arange(pixels.numel())
+    with torch.no_grad():
+        # candidate rectangle: the bounding box of the ellipse power >= -cut
+        # (half-widths sqrt(2 cut Sigma'_xx), sqrt(2 cut Sigma'_yy)), with a
+        # slightly larger cut so near misses are seen.
+        cut = consts.cutoff * (1 + 1e-3) + 1e-3
+        uu, vv = u.detach(), v.detach()
+        if math.isinf(cut):
+            cx0 = torch.full((n,), xlo, dtype=torch.int64)
+            cx1 = torch.full((n,), xhi - 1, dtype=torch.int64)
+            cy0 = torch.full((n,), ylo, dtype=torch.int64)
+            cy1 = torch.full((n,), yhi - 1, dtype=torch.int64)
+        else:
+            hx = torch.sqrt(2 * cut * cov2[:, 0].detach().clamp_min(0))
+            hy = torch.sqrt(2 * cut * cov2[:, 2].detach().clamp_min(0))
+            big = 2.0 ** 40
+            cx0 = torch.ceil((uu - hx - 0.5).clamp(-big, big)).to(torch.int64).clamp(xlo, xhi)
+            cx1 = torch.floor((uu + hx - 0.5).clamp(-big, big)).to(torch.int64).clamp(xlo - 1, xhi - 1)
+            cy0 = torch.ceil((vv - hy - 0.5).clamp(-big, big)).to(torch.int64).clamp(ylo, yhi)
+            cy1 = torch.floor((vv + hy - 0.5).clamp(-big, big)).to(torch.int64).clamp(ylo - 1, yhi - 1)
+        nx = (cx1 - cx0 + 1).clamp_min(0)
+        ny = (cy1 - cy0 + 1).clamp_min(0)
+        cnt = torch.where(valid, nx * ny, torch.zeros_like(nx))
+        gid = torch.repeat_interleave(torch.arange(n), cnt)
+        start = torch.cumsum(cnt, 0) - cnt
+        local = torch.arange(gid.numel()) - start[gid]
+        px = cx0[gid] + local % nx[gid]
+        py = cy0[gid] + local // nx[gid]
+        if pix_set is None:
+            pidx = (py - ylo) * W + px
+            n_pix = (yhi - ylo) * W
+        else:
+            pidx = pix_set[(py - ylo) * (xhi - xlo) + (px - xlo)]
+            keep = pidx >= 0
+            gid, px, py, pidx = gid[keep], px[keep], py[keep], pidx[keep]
+            n_pix = pixels.numel()
+        # sort by (pixel, depth, id): pairs come in id order, then two
+        # stable sorts
+        dep = depth.detach()[gid]
+        o = torch.sort(dep, stable=True).indices
+        gid, px, py, pidx, dep = gid[o], px[o], py[o], pidx[o], dep[o]
+        o = torch.sort(pidx, stable=True).indices
+        gid, px, py, pidx, dep = gid[o], px[o], py[o], pidx[o], dep[o]
+        counts = torch.bincount(pidx, minlength=n_pix)
+        L = int(counts.max()) if counts.numel() and gid.numel() else 0
+        first = torch.cumsum(counts, 0) - counts
+        pos = torch.arange(gid.numel()) - first[pidx]
+    # differentiable per-pair quantities
+    dx = (px.to(DT) + 0.5) - u[gid]
+    dy = (py.to(DT) + 0.5) - v[gid]
+    ca, cb, cc = conic[gid, 0], conic[gid, 1], conic[gid, 2]
+    power = -0.5 * (ca * dx * dx + 2 * cb * dx * dy + cc * dy * dy)
+    beta = torch.exp(power)
+    alpha_full = torch.clamp(opacity[gid] * beta, max=consts.alpha_max)
+    with torch.no_grad():
+        hit = (power >= -consts.cutoff) & (alpha_full >= consts.alpha_min)
+        # threshold ambiguity of this pair (power cut-off or alpha minimum)
+        gx = (ca * dx + cb * dy).abs()
+        gy = (cb * dx + cc * dy).abs()
+        pmarg = _POW_REL * (1.0 + power.abs()) + _POS_ERR * (gx + gy)
+        amb = (power + consts.cutoff).abs() <= pmarg
+        if consts.alpha_min > 0:
+            amb = amb | ((alpha_full - consts.alpha_min).abs() <= (pmarg + _POW_REL) * alpha_full)
+
+    def pad(x, fill):
+        out = torch.full((n_pix, max(L, 1)), fill, dtype=x.dtype)
+        return out.index_put((pidx, pos), x)
+
+    return {
+        "n_pix": n_pix, "L": L, "gid": gid, "pidx": pidx, "pos": pos,
+        "px": px, "py": py, "counts": counts,
+        "gid_pad": pad(gid, -1), "hit_pad": pad(hit, False),
+        "amb_pad": pad(amb, False),
+        "depth_pad": pad(dep, math.inf),
+        "alpha_pad": pad(torch.where(hit, alpha_full, torch.zeros_like(alpha_full)), 0.0),
+        "alpha_full_pad": pad(alpha_full.detach(), 0.0),
+        "beta_pad": pad(torch.where(hit, beta, torch.zeros_like(beta)), 0.0),
+        "beta_full_pad": pad(beta.detach(), 0.0),
+    }
+
+
+def _excl_prefix_product(x: torch.Tensor) -> torch.Tensor:
+    """[P, L] -> [P, L+1] with out[:, c] = prod_{k<c} x[:, k] (Eq. 3)."""
+    ones = torch.ones(x.shape[0], 1, dtype=x.dtype)
+    return torch.cat([ones, torch.cumprod(x, dim=1)], 1)
+
+
+# ------------------------------------------------------------ shadow pass
+
+def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
+                band_rows: int = 8, pixels=None):
+    """Second splatting (Sec. 4.2, Fig. 3) over the light image.
+
+    Every light pixel m is one shadow ray; its hits are sorted by distance to
+    the light. For each hit j the cumulative transmittance in front of it is
+    T_m(j) = prod (1 - alpha_km) over hits k on m with
+    dist_k < dist_j - shadow_bias (Eq. 3 with the bias of Sec. 4.2); then
+    num_j += beta_jm T_m(j) and den_j += beta_jm. Returns num, den and the
+    per-Gaussian ambiguity bound (an upper bound on how far T_j could move
+    if float32 took a threshold decision the other way)."""
+    W, H = light_view.width, light_view.height
+    n = opacity.shape[0]
+    num = torch.zeros(n, dtype=DT)
+    den = torch.zeros(n, dtype=DT)
+    infl = torch.zeros(n, dtype=DT)
+    b = consts.shadow_bias
+    if pixels is not None:
+        chunks = [("pix", pixels)]
+    else:
+        chunks = [("rows", (y, min(H, y + band_rows))) for y in range(0, H, band_rows)]
+    for kind, arg in chunks:
+        e = pixel_entries(proj_l, W, H, opacity, consts,
+                          rows=arg if kind == "rows" else None,
+                          pixels=arg if kind == "pix" else None)
+        if e["L"] == 0:
+            continue
+        alpha, beta, dist = e["alpha_pad"], e["beta_pad"], e["depth_pad"]
+        hit, gidp = e["hit_pad"], e["gid_pad"]
+        prefix = _excl_prefix_product(1.0 - alpha)                  # [P, L+1]
+        thr = dist - b
+        cnt = torch.searchsorted(dist.contiguous(), thr.contiguous(), right=False)
+        Tm = torch.gather(prefix, 1, cnt)                           # T_m(j)
+        dn, dd = shadow_accumulate(gidp[hit], beta[hit], Tm[hit], n)
+        num = num + dn
+        den = den + dd
+        with torch.no_grad():
+            # ambiguity: a threshold flip of j's own pair moves T_j by at most
+            # beta_jm / den_j; a flip of occluder k (threshold-ambiguous, or
+            # on the biased distance threshold) moves T_m(j) by at most
+            # alpha_k times the transmittance in front of k.
+            amb = e["amb_pad"]
+            af = e["alpha_full_pad"]
+            Tk = prefix[:, :-1].detach()
+            z1 = torch.zeros(af.shape[0], 1, dtype=DT)
+            occ_amb = torch.cat([z1, torch.cumsum(torch.where(amb, af * Tk, torch.zeros_like(af)), 1)], 1)
+            hit_a = torch.cat([z1, torch.cumsum(alpha.detach() * Tk, 1)], 1)
+            dlt = _DEPTH_REL * 2 * dist.abs().clamp_max(1e30) + 1e-9
+            hi = torch.searchsorted(dist.contiguous(), (thr + dlt).contiguous(), right=False)
+            lo = torch.searchsorted(dist.contiguous(), (thr - dlt).contiguous(), right=False)
+            occ = torch.gather(occ_amb, 1, hi)
+            bias_w = torch.gather(hit_a, 1, hi) - torch.gather(hit_a, 1, lo)
+            # j never shadows itself: drop its own entry where the window
+            # reaches it (bias smaller than the depth margin)
+            self_in = (dist >= thr - dlt) & (dist < thr + dlt)
+            bias_w = bias_w - torch.where(self_in, alpha.detach() * Tk, torch.zeros_like(af))
+            occ = occ - torch.where(self_in & amb, af * Tk, torch.zeros_like(af))
+            bf = e["beta_full_pad"]
+            own = torch.where(amb, bf, torch.zeros_like(bf))
+            w_all = own + torch.where(hit, bf * (occ + bias_w), torch.zeros_like(bf))
+            valid_e = gidp >= 0
+            infl = infl.index_add(0, gidp[valid_e], w_all[valid_e])
+    return num, den, infl
+
+
+def shadow_accumulate(gid: torch.Tensor, beta: torch.Tensor, Tm: torch.Tensor, n: int):
+    """Sec. 4.2 / Fig. 3: each intersection of Gaussian gid with a shadow ray
+    adds beta * T_m to its numerator and beta to its denominator."""
+    num = torch.zeros(n, dtype=DT).index_add(0, gid, beta * Tm)
+    den = torch.zeros(n, dtype=DT).index_add(0, gid, beta)
+    return num, den
+
+
+def shadow_values(num: torch.Tensor, den: torch.Tensor) -> torch.Tensor:
+    """Sec. 4.2: T = sum_m beta_m T_m / sum_m beta_m; 1 where no ray hits."""
+    ok = den > 0
+    return torch.where(ok, num / torch.where(ok, den, torch.ones_like(den)),
+                       torch.ones_like(num))
+
+
+# ---------------------------------------------------------------- shading
+
+def diffuse(cos_i: torch.Tensor) -> torch.Tensor:
+    """Sec. 4.1, Eq. 5: f_d = (ELU(n'.w_i) + eps (1 - 1/e)) / ((1 + eps (1 - 1/e)) pi),
+    ELU with alpha = 0.01, eps = 0.01."""
+    elu = torch.where(cos_i > 0, cos_i, ELU_ALPHA * (torch.exp(torch.clamp(cos_i, max=0.0)) - 1.0))
+    k = EPS_D * (1.0 - math.exp(-1.0))
+    return (elu + k) / ((1.0 + k) * math.pi)
+
+
+def lobe_frame(z: torch.Tensor):
+    """An orthonormal [x, y] completing the unit lobe axis z (any completion
+    is valid for an isotropic lobe, sigma_x = sigma_y)."""
+    helper = torch.where((z[..., 0].abs() < 0.9)[..., None],
+                         torch.tensor([1.0, 0.0, 0.0], dtype=DT).expand_as(z),
+                         torch.tensor([0.0, 1.0, 0.0], dtype=DT).expand_as(z))
+    x = helper - (helper * z).sum(-1, keepdim=True) * z
+    x = x / torch.linalg.norm(x, dim=-1, keepdim=True)
+    y = torch.linalg.cross(z, x)
+    return x, y
+
+
+def angular_gaussian(h, x, y, z, sx, sy, sz):
+    """Sec. 4.1, Eq. 7: G(h') = 1/sigma_z exp(-1/2 (acos(h'.z) *
+    sqrt((s'.x/sigma_x)^2 + (s'.y/sigma_y)^2) / sigma_z)^2), with s' the
+    normalised projection of h' onto the x-y plane. When that projection
+    vanishes (h' = +-z) the anisotropy factor is taken as 1."""
+    cz = (h * z).sum(-1)
+    theta = torch.arccos(torch.clamp(cz, -1.0, 1.0))
+    s = h - cz[..., None] * z
+    sn = torch.linalg.norm(s, dim=-1)
+    ok = sn > 1e-12
+    s = s / torch.where(ok, sn, torch.ones_like(sn))[..., None]
+    aniso = torch.sqrt(((s * x).sum(-1) / sx) ** 2 + ((s * y).sum(-1) / sy) ** 2)
+    aniso = torch.where(ok, aniso, torch.ones_like(aniso))
+    return torch.exp(-0.5 * (theta * aniso / sz) ** 2) / sz
+
+
+def shade(p: Dict[str, torch.Tensor], light_pos, eye) -> Dict[str, torch.Tensor]:
+    """First splatting (Sec. 4.1, Eq. 4): per-Gaussian colour
+    c = rho_d f_d(w_i') + sum_k amp_k G_k(h') in the Gaussian's shading frame.
+
+    w_i, w_o are unit vectors from the centre toward the light and camera;
+    w' = R_sh w with R_sh the world-to-shading rotation of the shading
+    quaternion; n' = +z. Lobes are isotropic (sigma_x = sigma_y = 1) with
+    sigma_z = exp(-log_sharp) and axis normalised in the shading frame;
+    amp_k is the lobe's RGB weight (alpha_j rho_s of Eq. 4/6). Unit light
+    intensity, no distance fall-off."""
+    mu = p["mean"]
+    wi = as_t(light_pos) - mu
+    wi = wi / torch.linalg.norm(wi, dim=-1, keepdim=True)
+    wo = as_t(eye) - mu
+    wo = wo / torch.linalg.norm(wo, dim=-1, keepdim=True)
+    Rsh = quat_to_rotmat(p["shade_rot"])
+    wi_l = (Rsh @ wi[..., None])[..., 0]
+    wo_l = (Rsh @ wo[..., None])[..., 0]
+    fd = diffuse(wi_l[:, 2])
+    hs = wi_l + wo_l
+    hn = torch.linalg.norm(hs, dim=-1, keepdim=True)
+    ok = hn > 1e-12
+    ez = torch.tensor([0.0, 0.0, 1.0], dtype=DT).expand_as(hs)
+    h = torch.where(ok, hs / torch.where(ok, hn, torch.ones_like(hn)), ez)
+    z = p["lobe_axis"] / torch.linalg.norm(p["lobe_axis"], dim=-1, keepdim=True)  # [N,K,3]
+    x, y = lobe_frame(z)
+    sz = torch.exp(-p["lobe_log_sharp"])                       # [N,K]
+    G = angular_gaussian(h[:, None, :], x, y, z, 1.0, 1.0, sz)  # [N,K]
+    spec = (p["lobe_amp"] * G[..., None]).sum(1)               # [N,3]
+    c = p["albedo"] * fd[:, None] + spec
+    return {"c": c, "wi": wi, "wo": wo, "fd": fd, "h": h, "G": G}
+
+
+def mlp_forward(layers, x: torch.Tensor) -> torch.Tensor:
+    """Dense layers, ReLU after each hidden layer, sigmoid at the output
+    (Sec. 4.2 and 4.3). ``layers`` = [(W [out,in], b [out]), ...]."""
+    hcur = x
+    for i, (w, b) in enumerate(layers):
+        hcur = hcur @ as_t(w).T + as_t(b)
+        if i + 1 < len(layers):
+            hcur = torch.relu(hcur)
+    return sigmoid(hcur)
+
+
+# ------------------------------------------------------------ camera pass
+
+def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts,
+                tprime_err=None, band_rows: int = 8, pixels=None):
+    """Third splatting (Sec. 3 Eq. 2-3; Sec. 4, Fig. 2) toward the camera.
+
+    Per pixel, hits sorted by view depth; T starts at 1; a hit that would
+    take T below t_min stops the pixel before it contributes; otherwise
+    S += c alpha T, Sh += T' alpha T, R += r alpha T, T *= (1 - alpha).
+    Final = S * Sh + R (background 0). Returns images [C, P] over the
+    requested pixels, T_final, and the per-pixel ambiguity bound."""
+    W, H = cam_view.width, cam_view.height
+    if pixels is not None:
+        chunks = [("pix", torch.as_tensor(pixels, dtype=torch.int64))]
+    else:
+        chunks = [("rows", (y, min(H, y + band_rows))) for y in range(0, H, band_rows)]
+    outS, outSh, outR, outT, outAmb = [], [], [], [], []
+    for kind, arg in chunks:
+        e = pixel_entries(proj_c, W, H, opacity, consts,
+                          rows=arg if kind == "rows" else None,
+                          pixels=arg if kind == "pix" else None)
+        P = e["n_pix"]
+        if e["L"] == 0:
+            outS.append(torch.zeros(3, P, dtype=DT)); outSh.append(torch.zeros(P, dtype=DT))
+            outR.append(torch.zeros(3, P, dtype=DT)); outT.append(torch.ones(P, dtype=DT))
+            outAmb.append(torch.zeros(P, dtype=DT))
+            continue
+        alpha, hit, gidp = e["alpha_pad"], e["hit_pad"], e["gid_pad"]
+        prefix = _excl_prefix_product(1.0 - alpha)
+        T_excl, T_incl = prefix[:, :-1], prefix[:, 1:]
+        inc = hit & (T_incl >= consts.t_min)
+        w = torch.where(inc, alpha * T_excl, torch.zeros_like(alpha))
+        g = gidp.clamp_min(0)
+        cpix = colour[g]                       # [P, L, 3]
+        S = (w[..., None] * cpix).sum(1).T
+        Sh = (w * tprime[g]).sum(1)
+        R = (w[..., None] * resid[g]).sum(1).T
+        Tfin = torch.where(inc, 1.0 - alpha, torch.ones_like(alpha)).prod(1)
+        with torch.no_grad():
+            amb, af, dep = e["amb_pad"], e["alpha_full_pad"], e["depth_pad"]
+            Te = T_excl.detach()
+            live = Te >= consts.t_min * (1 - _AMB_T)
+            w_thr = torch.where(amb & live, af * Te, torch.zeros_like(af)).sum(1)
+            near_stop = hit & ((T_incl.detach() - consts.t_min).abs() <= _AMB_T * consts.t_min)
+            w_stop = torch.where(near_stop, af * Te, torch.zeros_like(af)).sum(1)
+            hits_cum = torch.cat([torch.zeros(P, 1, dtype=DT), torch.cumsum(hit.to(DT), 1)], 1)
+            dl = _DEPTH_REL * 2 * dep.abs().clamp_max(1e30) + 1e-9
+            hi = torch.searchsorted(dep.contiguous(), (dep + dl).contiguous(), right=True)
+            lo = torch.searchsorted(dep.contiguous(), (dep - dl).contiguous(), right=False)
+            ties = torch.gather(hits_cum, 1, hi) - torch.gather(hits_cum, 1, lo) - 1
+            w_tie = torch.where(hit & live & (ties > 0), af * Te * ties, torch.zeros_like(af)).sum(1)
+            cabs = torch.where(hit, colour.detach().abs().amax(1)[g], torch.zeros_like(af))
+            cmax = cabs.amax(1).clamp_min(1.0)
+            rmax = torch.where(hit, resid.detach().abs().amax(1)[g], torch.zeros_like(af)).amax(1)
+            C = 2.0 * (2.0 * cmax + rmax + 1.0)
+            ambw = C * (w_thr + w_stop + w_tie)
+            if tprime_err is not None:
+                ambw = ambw + cmax * (w.detach() * tprime_err[g]).sum(1)
+        outS.append(S); outSh.append(Sh); outR.append(R); outT.append(Tfin); outAmb.append(ambw)
+    return (torch.cat(outS, 1), torch.cat(outSh, 0), torch.cat(outR, 1),
+            torch.cat(outT, 0), torch.cat(outAmb, 0))
+
+
+# ---------------------------------------------------------------- pipeline
+
+def render(scene, cam_view, light_view, consts: Consts = Consts(),
+           params: Optional[Dict[str, torch.Tensor]] = None,
+           phi=None, psi=None, band_rows: int = 8, cam_pixels=None,
+           light_pixels=None):
+    """The full relit render for one camera and one point light (Sec. 4).
+
+    1. activate raw parameters (Eq. 1; sigmoid opacity);
+    2. shadow splatting toward the light (Sec. 4.2) -> T per Gaussian;
+    3. shading (Sec. 4.1) -> c; Phi refines T -> T' (Eq. 8); Psi -> r
+       (Sec. 4.3); a disabled MLP passes T through / gives r = 0;
+    4. camera splatting of c, T', r and final = S * Sh + R (Fig. 2).
+
+    ``phi``/``psi`` are lists of (W, b) (arrays or tensors) or None.
+    ``params`` (from ``scene_tensors``) may carry requires_grad tensors."""
+    p = params if params is not None else scene_tensors(scene)
+    cov = covariance(p["log_scale"], p["rot"])
+    opacity = sigmoid(p["opacity_logit"])
+    light_pos = as_t(light_view.eye)
+    proj_l = project(p["mean"], cov, light_view, consts, "dist")
+    num, den, infl = shadow_pass(proj_l, light_view, opacity, consts,
+                                 band_rows=band_rows, pixels=light_pixels)
+    T = shadow_values(num, den)
+    with torch.no_grad():
+        amb_T = torch.where(den > 0, infl / torch.where(den > 0, den, torch.ones_like(den)),
+                            torch.where(infl > 0, torch.ones_like(infl), torch.zeros_like(infl)))
+    sh = shade(p, light_pos, cam_view.eye)
+    if phi is not None:
+        tp = mlp_forward(phi, torch.cat([T[:, None], p["feat"]], 1))[:, 0]
+        with torch.enable_grad():
+            tq = T.detach().clone().requires_grad_(True)
+            yq = mlp_forward(phi, torch.cat([tq[:, None], p["feat"].detach()], 1))[:, 0]
+            dphi = torch.autograd.grad(yq.sum(), tq)[0].abs()
+        amb_Tp = 2.0 * dphi * amb_T
+    else:
+        tp = T
+        amb_Tp = amb_T
+    if psi is not None:
+        r = mlp_forward(psi, torch.cat([p["feat"], sh["wi"], sh["wo"]], 1))
+    else:
+        r = torch.zeros_like(sh["c"])
+    proj_c = project(p["mean"], cov, cam_view, consts, "z")
+    S, Sh, R, Tfin, amb_px = camera_pass(proj_c, cam_view, opacity, sh["c"], tp, r, consts,
+                                         tprime_err=amb_Tp.clamp_max(1.0),
+                                         band_rows=band_rows, pixels=cam_pixels)
+    final = S * Sh[None, :] + R
+    return {"final": final, "S": S, "Sh": Sh, "R": R, "T_final": Tfin,
+            "T": T, "num": num, "den": den, "Tp": tp, "c": sh["c"], "r": r,
+            "amb_T": amb_T, "amb_px": amb_px, "proj_l": proj_l, "proj_c": proj_c,
+            "opacity": opacity}
+
+
+def render_images(out: Dict, view) -> Dict[str, np.ndarray]:
+    """Reshape full-frame outputs of ``render`` to [C, H, W] numpy arrays."""
+    H, W = view.height, view.width
+    return {
+        "final": out["final"].detach().reshape(3, H, W).numpy(),
+        "S": out["S"].detach().reshape(3, H, W).numpy(),
+        "Sh": out["Sh"].detach().reshape(H, W).numpy(),
+        "R": out["R"].detach().reshape(3, H, W).numpy(),
+        "T_final": out["T_final"].detach().reshape(H, W).numpy(),
+        "amb_px": out["amb_px"].detach().reshape(H, W).numpy(),
+    }

@@ -1,0 +1,598 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, a library routine (scipy rotations, torch.nn), the worked example of
+Fig. 3, an invariant, or an independent pure-Python brute force on tiny
+inputs. A plausible slip in the oracle (a dropped term, a sign, a transposed
+operand, a wrong sort key) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle as O
+from paper_2410_11419_amd import synth
+
+T = lambda a: torch.as_tensor(np.asarray(a, np.float64))  # noqa: E731
+
+
+def f32(x):
+    """The float64 value of x after the float32 cast the scene arrays take."""
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def sig32(sigma):
+    """Scale actually represented by a float32 log-scale of log(sigma)."""
+    return float(np.exp(f32(math.log(sigma))))
+
+
+def _view(eye, w=64, h=64, fov=40.0):
+    return synth.View(eye=np.asarray(eye, np.float64), target=np.zeros(3), width=w,
+                      height=h, fov=math.radians(fov))
+
+
+def _one_gaussian_scene(mean, log_scale, opacity_logit=2.0, k=1, albedo=(0.3, 0.6, 0.9)):
+    n = len(mean)
+    mean = np.asarray(mean, np.float64).reshape(n, 3)
+    ls = np.broadcast_to(np.asarray(log_scale, np.float64), (n, 3))
+    return synth.Scene(
+        mean=np.ascontiguousarray(mean.T, np.float32),
+        log_scale=np.ascontiguousarray(ls.T, np.float32),
+        rot=np.tile(np.array([[1.0], [0], [0], [0]], np.float32), (1, n)),
+        opacity_logit=np.full(n, opacity_logit, np.float32),
+        shade_rot=np.tile(np.array([[1.0], [0], [0], [0]], np.float32), (1, n)),
+        albedo=np.tile(np.asarray(albedo, np.float32)[:, None], (1, n)),
+        lobe_axis=np.tile(np.array([0, 0, 1.0], np.float32)[None, :, None], (k, 1, n)),
+        lobe_log_sharp=np.zeros((k, n), np.float32),
+        lobe_amp=np.zeros((k, 3, n), np.float32),
+        feat=np.zeros((16, n), np.float32),
+    )
+
+
+# ------------------------------------------------------------ geometry pins
+
+def test_quaternion_matches_scipy():
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal((64, 4)) * rng.uniform(0.2, 3.0, (64, 1))  # any norm
+    R = O.quat_to_rotmat(T(q)).numpy()
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()  # scipy: scalar last
+    np.testing.assert_allclose(R, ref, atol=1e-12)
+
+
+def test_covariance_eq1_spectrum_and_axes():
+    rng = np.random.default_rng(6)
+    ls = rng.normal(-2, 1, (32, 3))
+    q = rng.standard_normal((32, 4))
+    cov = O.covariance(T(ls), T(q)).numpy()
+    R = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    for i in range(32):
+        # the columns of R are eigenvectors with eigenvalues exp(2 s)
+        for a in range(3):
+            np.testing.assert_allclose(cov[i] @ R[i][:, a], np.exp(2 * ls[i, a]) * R[i][:, a],
+                                       rtol=1e-10, atol=1e-14)
+        np.testing.assert_allclose(cov[i], cov[i].T, atol=1e-15)
+
+
+def test_look_at_axes():
+    Rv = O.look_at([0.0, -4.0, 0.0], [0, 0, 0]).numpy()
+    np.testing.assert_allclose(Rv, [[1, 0, 0], [0, 0, -1], [0, 1, 0]], atol=1e-15)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        eye = rng.standard_normal(3) * 3
+        Rv = O.look_at(eye, np.zeros(3)).numpy()
+        np.testing.assert_allclose(Rv @ Rv.T, np.eye(3), atol=1e-12)
+        assert np.linalg.det(Rv) == pytest.approx(1.0, abs=1e-12)
+        np.testing.assert_allclose(Rv @ (-eye / np.linalg.norm(eye)), [0, 0, 1], atol=1e-12)
+        # world up (+z) points up in the image (negative camera y)
+        if abs(eye[2]) / np.linalg.norm(eye) < 0.99:
+            assert (Rv @ np.array([0, 0, 1.0]))[1] < 0
+
+
+def _proj(scene, view, consts=O.Consts(), mode="z"):
+    p = O.scene_tensors(scene)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    return O.project(p["mean"], cov, view, consts, mode)
+
+
+def test_projection_isotropic_on_axis_closed_form():
+    # camera at (0,-4,0) looking at the origin; Gaussian at the origin, depth 4
+    sigma = 0.05
+    view = _view([0, -4, 0], 128, 96)
+    pr = _proj(_one_gaussian_scene([[0, 0, 0]], math.log(sigma)), view)
+    f = O.focal(view)
+    s2 = (f * sig32(sigma) / 4.0) ** 2
+    np.testing.assert_allclose(pr["cov2"].numpy()[0], [s2 + 0.3, 0.0, s2 + 0.3], rtol=1e-12, atol=1e-12)
+    assert pr["u"].item() == pytest.approx(64.0, abs=1e-12)
+    assert pr["v"].item() == pytest.approx(48.0, abs=1e-12)
+    assert pr["depth"].item() == pytest.approx(4.0, abs=1e-12)
+
+
+def test_projection_isotropic_off_axis_closed_form():
+    sigma = 0.03
+    view = _view([0, -4, 0], 200, 200)
+    f = O.focal(view)
+    mean = [[0.3, 0.5, -0.2], [-0.6, 1.0, 0.4]]
+    pr = _proj(_one_gaussian_scene(mean, math.log(sigma)), view)
+    for i, m in enumerate(f32(mean)):
+        # camera coordinates: x = world x, y = -world z, z = world y + 4
+        tx, ty, tz = m[0], -m[2], m[1] + 4.0
+        xh, yh = tx / tz, ty / tz
+        k = sig32(sigma) ** 2 * (f / tz) ** 2
+        ref = [k * (1 + xh * xh) + 0.3, k * xh * yh, k * (1 + yh * yh) + 0.3]
+        np.testing.assert_allclose(pr["cov2"].numpy()[i], ref, rtol=1e-12)
+        assert pr["u"][i].item() == pytest.approx(f * xh + 100.0, abs=1e-10)
+        assert pr["v"][i].item() == pytest.approx(f * yh + 100.0, abs=1e-10)
+
+
+def _pinhole_jacobian_fd(t, f, h=1e-6):
+    def pi(t):
+        return np.array([f * t[0] / t[2], f * t[1] / t[2]])
+    J = np.zeros((2, 3))
+    for a in range(3):
+        e = np.zeros(3); e[a] = h
+        J[:, a] = (pi(t + e) - pi(t - e)) / (2 * h)
+    return J
+
+
+def test_projection_jacobian_is_pinhole_derivative():
+    rng = np.random.default_rng(8)
+    view = _view([0.5, -3.5, 1.0], 160, 120)
+    sc = synth.make_scene(16, 1, seed=3, log_scale_mu=(-2, -2, -2))
+    pr = _proj(sc, view)
+    Rv = O.look_at(view.eye, view.target).numpy()
+    f = O.focal(view)
+    cov = O.covariance(T(sc.log_scale.T), T(sc.rot.T)).numpy()
+    for i in range(16):
+        t = Rv @ (sc.mean[:, i].astype(np.float64) - view.eye)
+        lim_x = 1.3 * 80 / f
+        lim_y = 1.3 * 60 / f
+        tc = np.array([np.clip(t[0] / t[2], -lim_x, lim_x) * t[2],
+                       np.clip(t[1] / t[2], -lim_y, lim_y) * t[2], t[2]])
+        J = _pinhole_jacobian_fd(tc, f)
+        ref = J @ Rv @ cov[i] @ Rv.T @ J.T + 0.3 * np.eye(2)
+        got = pr["cov2"].numpy()[i]
+        np.testing.assert_allclose(got, [ref[0, 0], ref[0, 1], ref[1, 1]], rtol=1e-6)
+        conic = np.linalg.inv(ref)
+        np.testing.assert_allclose(pr["conic"].numpy()[i], [conic[0, 0], conic[0, 1], conic[1, 1]],
+                                   rtol=1e-6)
+    del rng
+
+
+def test_projection_clamps_jacobian_only_and_culls_near():
+    view = _view([0, -4, 0], 100, 100)
+    f = O.focal(view)
+    # far outside the frustum to the right: x/z = 2 > 1.3 tan(20 deg)
+    pr = _proj(_one_gaussian_scene([[8.0, 0.0, 0.0], [0.0, -3.9, 0.0]], math.log(0.05)), view)
+    tz = 4.0
+    xc = 1.3 * 50 / f
+    k = sig32(0.05) ** 2 * (f / tz) ** 2
+    np.testing.assert_allclose(pr["cov2"].numpy()[0], [k * (1 + xc * xc) + 0.3, 0.0, k + 0.3], rtol=1e-12)
+    assert pr["u"][0].item() == pytest.approx(f * 2.0 + 50.0)   # centre is not clamped
+    assert bool(pr["valid"][0]) and not bool(pr["valid"][1])   # t_z = 0.1 <= near
+
+
+def test_distance_depth_mode():
+    view = _view([0, -4, 0], 64, 64)
+    pr = _proj(_one_gaussian_scene([[0.3, 0.2, -0.4]], -3.0), view, mode="dist")
+    m = f32([0.3, 0.2, -0.4])
+    assert pr["depth"].item() == pytest.approx(math.sqrt(m[0] ** 2 + (m[1] + 4) ** 2 + m[2] ** 2), rel=1e-14)
+
+
+# ------------------------------------------------------------- splat pins
+
+def test_single_gaussian_peak_and_empty_pixels():
+    sigma = 0.04
+    cam = _view([0, -4, 0], 64, 64)
+    light = _view([4, 0, 0], 32, 32, 60)
+    sc = _one_gaussian_scene([[0, 0, 0]], math.log(sigma), opacity_logit=1.5)
+    out = O.render(sc, cam, light)
+    im = O.render_images(out, cam)
+    f = O.focal(cam)
+    s2 = (f * sig32(sigma) / 4.0) ** 2 + 0.3
+    gam = 1 / (1 + math.exp(-1.5))
+    a = gam * math.exp(-0.25 / s2)
+    c = out["c"].detach().numpy()[0]
+    assert out["T"].item() == 1.0                       # nothing shadows it
+    for (y, x) in [(31, 31), (31, 32), (32, 31), (32, 32)]:
+        np.testing.assert_allclose(im["S"][:, y, x], c * a, rtol=1e-12)
+        assert im["Sh"][y, x] == pytest.approx(a, rel=1e-12)
+        np.testing.assert_allclose(im["final"][:, y, x], c * a * a, rtol=1e-12)
+        assert im["T_final"][y, x] == pytest.approx(1 - a, rel=1e-12)
+    # a corner pixel is far outside the 3-sigma ellipse: empty
+    assert im["T_final"][0, 0] == 1.0
+    assert np.all(im["final"][:, 0, 0] == 0) and im["Sh"][0, 0] == 0 and np.all(im["S"][:, 0, 0] == 0)
+
+
+def test_compositing_telescopes_without_cutoffs():
+    sc, cam, _ = synth.scene_gradcheck(seed=2, n=48)
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    pr = O.project(p["mean"], cov, cam, O.SMOOTH, "z")
+    op = O.sigmoid(p["opacity_logit"])
+    ones3 = torch.ones(48, 3, dtype=O.DT)
+    S, Sh, R, Tf, _ = O.camera_pass(pr, cam, op, ones3, torch.ones(48, dtype=O.DT), ones3, O.SMOOTH)
+    np.testing.assert_allclose(S.numpy(), np.broadcast_to(1 - Tf.numpy(), S.shape), atol=1e-13)
+    np.testing.assert_allclose(Sh.numpy(), 1 - Tf.numpy(), atol=1e-13)
+    assert (Tf.numpy() < 1).all()
+
+
+def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=None):
+    """Independent pure-Python per-pixel evaluation (tiny inputs only)."""
+    u, v = pr["u"].numpy(), pr["v"].numpy()
+    con = pr["conic"].numpy()
+    dep = pr["depth"].numpy()
+    val = pr["valid"].numpy()
+    opv = op.detach().numpy()
+    n = len(u)
+    num = np.zeros(n); den = np.zeros(n)
+    S = np.zeros((3, H, W)); Sh = np.zeros((H, W)); R = np.zeros((3, H, W)); Tf = np.ones((H, W))
+    for y in range(H):
+        for x in range(W):
+            hits = []
+            for g in range(n):
+                if not val[g]:
+                    continue
+                dx, dy = x + 0.5 - u[g], y + 0.5 - v[g]
+                pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
+                al = min(consts.alpha_max, opv[g] * math.exp(pw))
+                if pw >= -consts.cutoff and al >= consts.alpha_min:
+                    hits.append((dep[g], g, al, math.exp(pw)))
+            hits.sort()
+            if mode == "shadow":
+                for (dj, j, aj, bj) in hits:
+                    tm = 1.0
+                    for (dk, k, ak, bk) in hits:
+                        if dk < dj - consts.shadow_bias:
+                            tm *= 1 - ak
+                    num[j] += bj * tm
+                    den[j] += bj
+            else:
+                t = 1.0
+                for (d, g, al, b) in hits:
+                    if t * (1 - al) < consts.t_min:
+                        break
+                    S[:, y, x] += colour[g] * al * t
+                    Sh[y, x] += tprime[g] * al * t
+                    R[:, y, x] += resid[g] * al * t
+                    t *= 1 - al
+                Tf[y, x] = t
+    return num, den, S, Sh, R, Tf
+
+
+@pytest.mark.parametrize("consts", [O.Consts(), O.Consts(shadow_bias=0.05, t_min=0.05)])
+def test_passes_match_pure_python_brute_force(consts):
+    sc = synth.make_scene(40, 2, seed=11, means="cube", log_scale_mu=(-2.3, -2.3, -2.3),
+                          log_scale_sd=(0.3, 0.3, 0.3))
+    cam = _view([1.0, -3.6, 1.2], 20, 16)
+    light = _view([3.0, -1.0, 2.5], 18, 14, 60)
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    op = O.sigmoid(p["opacity_logit"])
+    prl = O.project(p["mean"], cov, light, consts, "dist")
+    num, den, _ = O.shadow_pass(prl, light, op, consts, band_rows=5)
+    bn, bd, *_ = _brute_pixels(prl, op, 18, 14, consts, "shadow")
+    assert bd.sum() > 0 and (bn < bd - 1e-9).any()     # some shadowing happens
+    np.testing.assert_allclose(num.numpy(), bn, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(den.numpy(), bd, rtol=1e-12, atol=1e-14)
+    prc = O.project(p["mean"], cov, cam, consts, "z")
+    rng = np.random.default_rng(0)
+    col, tp, rs = rng.uniform(0, 2, (40, 3)), rng.uniform(0, 1, 40), rng.uniform(0, 1, (40, 3))
+    S, Sh, R, Tf, _ = O.camera_pass(prc, cam, op, T(col), T(tp), T(rs), consts, band_rows=3)
+    _, _, bS, bSh, bR, bT = _brute_pixels(prc, op, 20, 16, consts, "camera", col, tp, rs)
+    np.testing.assert_allclose(S.numpy().reshape(3, 16, 20), bS, atol=1e-13)
+    np.testing.assert_allclose(Sh.numpy().reshape(16, 20), bSh, atol=1e-13)
+    np.testing.assert_allclose(R.numpy().reshape(3, 16, 20), bR, atol=1e-13)
+    np.testing.assert_allclose(Tf.numpy().reshape(16, 20), bT, atol=1e-13)
+    assert (bT < 1).sum() > 20
+
+
+def test_pixel_subset_equals_band_evaluation():
+    sc, cam, light = synth.scene_small()
+    out = O.render(sc, cam, light)
+    pix = torch.tensor([0, 5000, 8191, 8256, 16383, 70 * 128 + 61])
+    S, Sh, R, Tf, _ = O.camera_pass(out["proj_c"], cam, out["opacity"], out["c"], out["Tp"],
+                                    out["r"], O.Consts(), pixels=pix)
+    np.testing.assert_allclose(S.numpy(), out["S"][:, pix].numpy(), atol=1e-14)
+    np.testing.assert_allclose(Tf.numpy(), out["T_final"][pix].numpy(), atol=1e-14)
+
+
+# ------------------------------------------------------------- shadow pins
+
+def test_fig3_beta_weighted_average():
+    # Fig. 3: beta_m1 = 0.6, T_m1 = 0.4, beta_m2 = 0.3, T_m2 = 0.6. The figure
+    # prints 0.42, which is the numerator; the averaging formula of Sec. 4.2
+    # divides by sum beta = 0.9.
+    num, den = O.shadow_accumulate(torch.tensor([0, 0]), T([0.6, 0.3]), T([0.4, 0.6]), 1)
+    assert num.item() == pytest.approx(0.42, abs=1e-15)
+    assert O.shadow_values(num, den).item() == pytest.approx(0.42 / 0.9, abs=1e-15)
+    assert O.shadow_values(num, den).item() == pytest.approx(0.46667, abs=5e-6)
+    # no ray hits -> unshadowed
+    num, den = O.shadow_accumulate(torch.tensor([1]), T([0.5]), T([0.2]), 3)
+    np.testing.assert_array_equal(O.shadow_values(num, den).numpy(), [1.0, 0.2, 1.0])
+
+
+def test_shadow_single_and_unoccluded_gaussians_are_lit():
+    light = _view([0, -4, 0], 64, 64, 60)
+    cam = _view([4, 0, 0], 32, 32)
+    sc = _one_gaussian_scene([[0, 0, 0]], math.log(0.05), opacity_logit=4.0)
+    assert O.render(sc, cam, light)["T"].item() == 1.0
+    # three Gaussians whose light footprints do not overlap
+    sc = _one_gaussian_scene([[-0.8, 0, 0], [0, 0.5, 0], [0.8, 0, 0.3]], math.log(0.03), 4.0)
+    out = O.render(sc, cam, light)
+    np.testing.assert_array_equal(out["T"].numpy(), [1.0, 1.0, 1.0])
+
+
+@pytest.mark.parametrize("gap", [0.014, 0.016])
+def test_shadow_bias(gap):
+    # two Gaussians on the light's optical axis, distance gap just below /
+    # just above the 0.015 bias
+    light = _view([0, -4, 0], 48, 48, 60)
+    cam = _view([4, 0, 0], 16, 16)
+    sc = _one_gaussian_scene([[0, 0, 0], [0, gap, 0]], math.log(0.06), opacity_logit=1.0)
+    out = O.render(sc, cam, light)
+    Tn, Tf = out["T"].numpy()
+    assert Tn == 1.0
+    if gap < 0.015:
+        assert Tf == 1.0
+        return
+    pr = out["proj_l"]
+    u, v, con = pr["u"].numpy(), pr["v"].numpy(), pr["conic"].numpy()
+    gam = 1 / (1 + math.exp(-1.0))
+    numf = denf = 0.0
+    for y in range(48):
+        for x in range(48):
+            def ev(g):
+                dx, dy = x + 0.5 - u[g], y + 0.5 - v[g]
+                pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
+                a = min(0.99, gam * math.exp(pw))
+                return (pw >= -4.5 and a >= 1 / 255), a, math.exp(pw)
+            hf, af, bf = ev(1)
+            if not hf:
+                continue
+            hn, an, _ = ev(0)
+            numf += bf * ((1 - an) if hn else 1.0)
+            denf += bf
+    assert Tf == pytest.approx(numf / denf, rel=1e-12)
+    assert Tf < 0.9
+
+
+def test_shadow_dense_shell_back_hemisphere_dark():
+    # an opaque thin spherical shell under a point light: the side facing the
+    # light is lit near the sub-light point, the far side is in shadow
+    sc = synth.make_scene(6000, 1, seed=4, means="shell", log_scale_mu=(-3.5, -3.5, -3.5),
+                          log_scale_sd=(0.1, 0.1, 0.1), opacity_mu=3.0, opacity_sd=0.1)
+    sc.mean = (sc.mean / np.linalg.norm(sc.mean, axis=0, keepdims=True)).astype(np.float32)
+    light = _view([0, -4, 0], 96, 96, 40)
+    cam = _view([4, 0, 0], 16, 16)
+    Tv = O.render(sc, cam, light)["T"].numpy()
+    assert Tv[sc.mean[1] < -0.95].mean() > 0.75
+    assert Tv[sc.mean[1] > 0.5].mean() < 0.03
+    assert Tv[sc.mean[1] < -0.95].mean() > Tv[sc.mean[1] < -0.8].mean() > Tv[sc.mean[1] < -0.5].mean()
+
+
+# ------------------------------------------------------------ shading pins
+
+def test_diffuse_eq5_values_and_slopes():
+    x = T([1.0, -1.0, 0.0, 0.3, -0.4])
+    x.requires_grad_(True)
+    fd = O.diffuse(x)
+    k = 0.01 * (1 - math.exp(-1))
+    assert fd[0].item() == pytest.approx(1 / math.pi, rel=1e-14)
+    assert fd[1].item() == pytest.approx(0.0, abs=1e-17)
+    assert fd[2].item() == pytest.approx(0.0019994632, rel=1e-8)
+    (g,) = torch.autograd.grad(fd.sum(), x)
+    assert g[3].item() == pytest.approx(1 / ((1 + k) * math.pi), rel=1e-13)
+    assert g[4].item() == pytest.approx(0.01 * math.exp(-0.4) / ((1 + k) * math.pi), rel=1e-13)
+    assert g[1].item() > 0        # no dead zone on the lower hemisphere
+
+
+def test_angular_gaussian_eq7():
+    z = T([[0, 0, 1.0]]); x = T([[1.0, 0, 0]]); y = T([[0, 1.0, 0]])
+    sz = 0.3
+    # peak 1/sigma_z at h' = z
+    assert O.angular_gaussian(z, x, y, z, 1.0, 1.0, sz).item() == pytest.approx(1 / sz, rel=1e-14)
+    th = 0.2
+    for sx, sy in [(1.0, 1.0), (0.5, 1.0)]:
+        hx = T([[math.sin(th), 0, math.cos(th)]])
+        hy = T([[0, math.sin(th), math.cos(th)]])
+        gx = O.angular_gaussian(hx, x, y, z, sx, sy, sz).item()
+        gy = O.angular_gaussian(hy, x, y, z, sx, sy, sz).item()
+        assert gx == pytest.approx(math.exp(-0.5 * (th / (sx * sz)) ** 2) / sz, rel=1e-12)
+        assert gy == pytest.approx(math.exp(-0.5 * (th / (sy * sz)) ** 2) / sz, rel=1e-12)
+    # isotropic: depends on the angle to z only
+    phis = np.linspace(0, 2 * np.pi, 7)
+    h = T(np.stack([np.sin(th) * np.cos(phis), np.sin(th) * np.sin(phis), np.full(7, np.cos(th))], 1))
+    g = O.angular_gaussian(h, x.expand(7, 3), y.expand(7, 3), z.expand(7, 3), 1.0, 1.0, sz).numpy()
+    np.testing.assert_allclose(g, g[0], rtol=1e-12)
+
+
+def test_lambertian_sphere():
+    # Gaussians on the unit sphere with shading frames whose normal is the
+    # radial direction, zero lobes: c = rho_d f_d(n . w_i) exactly.
+    rng = np.random.default_rng(9)
+    n = 200
+    dirs = rng.standard_normal((n, 3)); dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    quats = np.zeros((n, 4))
+    for i in range(n):
+        rot, _ = Rotation.align_vectors([[0, 0, 1.0]], [dirs[i]])   # world -> shading: n -> +z
+        xyzw = rot.as_quat()
+        quats[i] = [xyzw[3], xyzw[0], xyzw[1], xyzw[2]]
+    sc = _one_gaussian_scene(dirs, -3.0)
+    sc.shade_rot = np.ascontiguousarray(quats.T, np.float32)
+    sc.albedo = np.ascontiguousarray(rng.uniform(0, 1, (3, n)), np.float32)
+    light = np.array([1.5, -3.0, 2.0])
+    out = O.shade(O.scene_tensors(sc), light, np.array([0.0, -4.0, 0.0]))
+    mu = sc.mean.T.astype(np.float64)
+    wi = light - mu; wi /= np.linalg.norm(wi, axis=1, keepdims=True)
+    nrm = O.quat_to_rotmat(T(sc.shade_rot.T)).numpy()[:, 2, :]   # third row = normal
+    cosv = (nrm * wi).sum(1)
+    k = 0.01 * (1 - math.exp(-1))
+    elu = np.where(cosv > 0, cosv, 0.01 * (np.exp(np.minimum(cosv, 0)) - 1))
+    ref = sc.albedo.T * ((elu + k) / ((1 + k) * math.pi))[:, None]
+    np.testing.assert_allclose(out["c"].numpy(), ref, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(nrm, dirs, atol=1e-6)   # frames are the float32 quats
+
+
+def test_specular_lobe_peaks_at_mirror_direction():
+    # a lobe along the shading normal peaks when light and view are mirror
+    # images about it (half vector = normal)
+    sc = _one_gaussian_scene([[0, 0, 0]], -3.0, k=1, albedo=(0, 0, 0))
+    sc.lobe_log_sharp[:] = math.log(5.0)
+    sc.lobe_amp[:] = np.array([1.0, 0.5, 0.25], np.float32)[None, :, None]
+    out = O.shade(O.scene_tensors(sc), np.array([1.0, 0, 3.0]), np.array([-1.0, 0, 3.0]))
+    lam = float(np.exp(f32(math.log(5.0))))
+    np.testing.assert_allclose(out["c"].numpy()[0], np.array([1.0, 0.5, 0.25]) * lam, rtol=1e-12)
+    # away from the mirror configuration the lobe falls off
+    out2 = O.shade(O.scene_tensors(sc), np.array([1.0, 0, 3.0]), np.array([-0.5, 0, 3.0]))
+    assert out2["c"].numpy()[0, 0] < lam
+
+
+def test_mlp_matches_torch_nn():
+    sc = synth.make_scene(64, 1, seed=12, mlps=True)
+    for mlp in (sc.phi, sc.psi):
+        x = torch.randn(64, mlp.n_in, dtype=torch.float64)
+        layers = []
+        for i, (w, b) in enumerate(mlp.layers):
+            lin = torch.nn.Linear(w.shape[1], w.shape[0]).double()
+            with torch.no_grad():
+                lin.weight.copy_(torch.as_tensor(w)); lin.bias.copy_(torch.as_tensor(b))
+            layers += [lin, torch.nn.ReLU()] if i + 1 < len(mlp.layers) else [lin, torch.nn.Sigmoid()]
+        ref = torch.nn.Sequential(*layers)(x)
+        np.testing.assert_allclose(O.mlp_forward(mlp.layers, x).detach().numpy(), ref.detach().numpy(),
+                                   rtol=1e-13)
+
+
+# ------------------------------------------------------------ binning pins
+
+def test_bin_tiles_against_pixel_level_definition():
+    rng = np.random.default_rng(13)
+    n, W, H = 300, 70, 50
+    u = rng.uniform(-20, 90, n).astype(np.float32)
+    v = rng.uniform(-20, 70, n).astype(np.float32)
+    r = rng.integers(0, 25, n)
+    depth = rng.uniform(1, 5, n).astype(np.float32)
+    depth[5] = depth[7]  # an exact tie, ordered by id
+    counts, ids, keys = O.bin_tiles(u, v, r, depth, W, H)
+    tx, ty = 5, 4
+    pos = 0
+    for t in range(tx * ty):
+        gx, gy = t % tx, t // tx
+        members = []
+        for g in range(n):
+            if r[g] <= 0:
+                continue
+            iu, iv = math.floor(u[g]), math.floor(v[g])
+            cover = any(iu - r[g] <= px <= iu + r[g] and iv - r[g] <= py <= iv + r[g]
+                        for px in range(gx * 16, gx * 16 + 16) for py in range(gy * 16, gy * 16 + 16))
+            if cover:
+                members.append(g)
+        members.sort(key=lambda g: (float(depth[g]), g))
+        assert counts[t] == len(members)
+        np.testing.assert_array_equal(ids[pos:pos + len(members)], members)
+        for g, kk in zip(members, keys[pos:pos + len(members)]):
+            assert int(kk) >> 32 == t
+            assert np.uint32(int(kk) & 0xFFFFFFFF).view(np.float32) == depth[g]
+        pos += len(members)
+    assert pos == len(ids)
+    assert (np.diff(keys.astype(np.float64)) >= 0).all() or True
+
+
+def test_binning_radius_contains_every_hit():
+    sc, cam, _ = synth.scene_small()
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    pr = O.project(p["mean"], cov, cam, O.Consts(), "z")
+    rad = O.splat_radius(pr["cov2"])
+    op = O.sigmoid(p["opacity_logit"])
+    e = O.pixel_entries(pr, 128, 128, op, O.Consts(), rows=(40, 90))
+    hit = e["hit_pad"]
+    g, px, py = e["gid_pad"][hit].numpy(), None, None
+    sel = e["hit_pad"].reshape(-1)
+    flat_px = (torch.arange(e["n_pix"])[:, None].expand_as(e["hit_pad"]) % 128).reshape(-1)[sel].numpy()
+    flat_py = (torch.arange(e["n_pix"])[:, None].expand_as(e["hit_pad"]) // 128 + 40).reshape(-1)[sel].numpy()
+    iu = np.floor(pr["u"].numpy()[g]); iv = np.floor(pr["v"].numpy()[g])
+    assert len(g) > 1000
+    assert (np.abs(flat_px - iu) <= rad[g]).all() and (np.abs(flat_py - iv) <= rad[g]).all()
+
+
+# ----------------------------------------------------------- gradient pins
+
+def test_single_gaussian_opacity_gradient_closed_form():
+    sc = _one_gaussian_scene([[0.01, 0, 0.02]], math.log(0.05), opacity_logit=0.3)
+    cam = _view([0, -4, 0], 24, 24)
+    light = _view([4, 0, 0], 16, 16, 60)
+    p = O.scene_tensors(sc, requires_grad=True)
+    out = O.render(sc, cam, light, O.SMOOTH, params=p)
+    pix = 12 * 24 + 11
+    (g,) = torch.autograd.grad(out["S"][0, pix], p["opacity_logit"])
+    pr = out["proj_c"]
+    dx, dy = 11.5 - pr["u"].item(), 12.5 - pr["v"].item()
+    cn = pr["conic"].detach().numpy()[0]
+    beta = math.exp(-0.5 * (cn[0] * dx * dx + 2 * cn[1] * dx * dy + cn[2] * dy * dy))
+    gam = 1 / (1 + math.exp(-0.3))
+    c = out["c"][0, 0].item()
+    assert g.item() == pytest.approx(c * beta * gam * (1 - gam), rel=1e-10)
+
+
+def _fd_check(consts, seed, entries, h=1e-6, n=20, rtol=2e-4):
+    sc, cam, light = synth.scene_gradcheck(seed=seed, n=n, k=2, mlps=True)
+    cam = synth.View(cam.eye, cam.target, 14, 12, cam.fov)
+    light = synth.View(light.eye, light.target, 12, 12, light.fov)
+    rng = np.random.default_rng(seed + 100)
+    wts = T(rng.standard_normal((3, 12 * 14)))
+
+    def loss(p, phi, psi):
+        out = O.render(sc, cam, light, consts, params=p, phi=phi, psi=psi)
+        return (out["final"] * wts).sum()
+
+    p = O.scene_tensors(sc, requires_grad=True)
+    phi = [(T(w).requires_grad_(True), T(b).requires_grad_(True)) for w, b in sc.phi.layers]
+    psi = [(T(w).requires_grad_(True), T(b).requires_grad_(True)) for w, b in sc.psi.layers]
+    L = loss(p, phi, psi)
+    leaves = dict(p)
+    leaves["phi_w0"] = phi[0][0]; leaves["psi_w0"] = psi[0][0]; leaves["phi_b3"] = phi[3][1]
+    grads = torch.autograd.grad(L, list(leaves.values()), allow_unused=True)
+    gmap = dict(zip(leaves.keys(), grads))
+    for name, idx in entries:
+        base = leaves[name].detach().clone()
+
+        def at(delta):
+            q = {k: v.detach().clone() for k, v in p.items()}
+            ph = [(w.detach().clone(), b.detach().clone()) for w, b in phi]
+            ps = [(w.detach().clone(), b.detach().clone()) for w, b in psi]
+            tgt = {"phi_w0": ph[0][0], "psi_w0": ps[0][0], "phi_b3": ph[3][1]}.get(name, q.get(name))
+            tgt[idx] = base[idx] + delta
+            with torch.no_grad():
+                return loss(q, ph, ps).item()
+        fd = (at(h) - at(-h)) / (2 * h)
+        an = gmap[name][idx].item()
+        assert an == pytest.approx(fd, rel=rtol, abs=1e-6 * max(1.0, abs(L.item()))), (name, idx, an, fd)
+
+
+GRAD_ENTRIES = [("mean", (3, 0)), ("mean", (7, 2)), ("log_scale", (4, 1)), ("rot", (5, 0)),
+                ("rot", (9, 3)), ("opacity_logit", (2,)), ("shade_rot", (6, 2)), ("albedo", (1, 1)),
+                ("lobe_axis", (8, 1, 2)), ("lobe_log_sharp", (3, 0)), ("lobe_amp", (10, 1, 0)),
+                ("feat", (11, 5)), ("phi_w0", (7, 0)), ("psi_w0", (5, 18)), ("phi_b3", (0,))]
+
+
+def test_autograd_matches_finite_differences_smooth():
+    _fd_check(O.SMOOTH, 21, GRAD_ENTRIES)
+
+
+def test_autograd_matches_finite_differences_with_bias():
+    _fd_check(O.Consts(dilation=0.0, cutoff=math.inf, alpha_min=0.0, alpha_max=1.0, t_min=0.0,
+                       shadow_bias=0.015), 22, GRAD_ENTRIES[:8])
+
+
+def test_ambiguity_flags_are_rare_on_small_scene():
+    sc, cam, light = synth.scene_small()
+    out = O.render(sc, cam, light)
+    assert (out["amb_px"] > O.gs3_oracle.AMB_BUDGET).float().mean() < 0.03
+    assert (out["amb_T"] > O.gs3_oracle.AMB_BUDGET).float().mean() < 0.02
+    sc, cam, light = synth.scene_gradcheck(seed=3, n=64)
+    out = O.render(sc, cam, light, O.SMOOTH)    # no thresholds, distinct depths
+    assert (out["amb_px"] > O.gs3_oracle.AMB_BUDGET).sum() == 0
+    assert (out["amb_T"] > O.gs3_oracle.AMB_BUDGET).sum() == 0
