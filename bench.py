@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark: relit frames/s of the triple-splatting path on one MI355X.
+
+Workload: 300,000 Gaussians on a shell (8 angular lobes, both MLPs on),
+800x800 camera, 1024x1024 light splat at 40 deg, four seeded (camera, light)
+pairs on the radius-4 sphere used in turn. One step = one relit frame = the
+whole forward hot path: light projection + binning + sort, shadow splat,
+camera projection + binning + sort, shading + Phi + Psi, camera splat.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+
+Prints one JSON line. Inputs are resident in HBM before the timed region;
+the timed region contains no host synchronisation (pair-capacity overflow is
+checked after it). Per-stage times come from HIP events recorded on the
+stream the library launches on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# algorithmic flops of one shadow-splat hit: power (9), exp (1), alpha (2),
+# transmittance update (2), beta-weighted num/den accumulation (3)
+SHADOW_FLOPS_PER_HIT = 17
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many frames (for rocprofv3), no JSON")
+    return ap.parse_args()
+
+
+def views(n_pairs=4, seed=2):
+    from paper_2410_11419_amd import synth
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_pairs):
+        cam = synth.make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0)
+        light = synth.make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0)
+        out.append((cam, light))
+    return out
+
+
+def frame_bytes(n, k, p_light, p_cam, cam_px):
+    """Compulsory HBM bytes of one frame (each item read or written once):
+    parameters (geometry twice, appearance once), projected records of both
+    views (write + read), pair emission, one read + write of the sorted pairs,
+    list reads, per-Gaussian shading outputs, the final image."""
+    geom = 4 * (3 + 3 + 4 + 1)
+    appear = 4 * (4 + 3 + k * 7 + 16)
+    params = n * (2 * geom + appear)
+    records = 2 * n * 2 * 36
+    pairs = p_light + p_cam
+    emit = 12 * pairs
+    sort = 24 * pairs
+    lists = 4 * pairs
+    per_g = n * 40
+    image = cam_px * 12
+    return params + records + emit + sort + lists + per_g + image
+
+
+def cpu_baseline(n):
+    """The FP64 oracle, as it is, on a bounded sample of the same frame:
+    projection of both views and shading + both MLPs for all Gaussians, plus
+    three 8-row bands (at 1/4, 1/2, 3/4 height) of the light pass and of the
+    camera pass; the band times are scaled to the full images."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_2410_11419_amd import synth
+    sc, _, _ = synth.scene_full(n=n)
+    cam, light = views()[0]
+    t0 = time.perf_counter()
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    op = O.sigmoid(p["opacity_logit"])
+    prl = O.project(p["mean"], cov, light, O.Consts(), "dist")
+    prc = O.project(p["mean"], cov, cam, O.Consts(), "z")
+    sh = O.shade(p, light.eye, cam.eye)
+    ones = torch.ones(sc.n, dtype=O.DT)
+    tp = O.mlp_forward(sc.phi.layers, torch.cat([ones[:, None], p["feat"]], 1))[:, 0]
+    r = O.mlp_forward(sc.psi.layers, torch.cat([p["feat"], sh["wi"], sh["wo"]], 1))
+    t_pg = time.perf_counter() - t0
+    band = 8
+    t_light = 0.0
+    for f in (0.25, 0.5, 0.75):
+        y = int(light.height * f)
+        rows = torch.arange(y * light.width, (y + band) * light.width)
+        t0 = time.perf_counter()
+        O.shadow_pass(prl, light, op, O.Consts(), pixels=rows)
+        t_light += time.perf_counter() - t0
+    t_cam = 0.0
+    for f in (0.25, 0.5, 0.75):
+        y = int(cam.height * f)
+        rows = torch.arange(y * cam.width, (y + band) * cam.width)
+        t0 = time.perf_counter()
+        O.camera_pass(prc, cam, op, sh["c"], tp, r, O.Consts(), pixels=rows)
+        t_cam += time.perf_counter() - t0
+    frame = t_pg + t_light * light.height / (3 * band) + t_cam * cam.height / (3 * band)
+    return {"value": round(1.0 / frame, 6), "unit": "frames/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle: projection + shading + both MLPs for all {sc.n} Gaussians "
+                       f"({t_pg:.1f} s), light pass on 3x{band} of {light.height} rows ({t_light:.1f} s), "
+                       f"camera pass on 3x{band} of {cam.height} rows ({t_cam:.1f} s); band times scaled "
+                       f"to the full images: {frame:.0f} s per frame")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path has no "
+              f"multi-GPU component in this build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2410_11419_amd import gs3, synth
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    sc, _, _ = synth.scene_full(n=args.n)
+    ds = gs3.DeviceScene.from_host(sc, dev)
+    pairs = views()
+    rnd = gs3.Renderer(ds)
+    # warm-up: sizes every view buffer (host sync allowed here)
+    for i in range(max(args.warmup, len(pairs))):
+        cam, light = pairs[i % len(pairs)]
+        rnd.render(cam, light, check=True)
+    torch.cuda.synchronize()
+    if args.profile_steps:
+        for i in range(args.profile_steps):
+            cam, light = pairs[i % len(pairs)]
+            rnd.render(cam, light, check=False)
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} frames")
+        return
+
+    # work units of each pair: pairs and hits of both views
+    stats = []
+    k = rnd.consts
+    for cam, light in pairs:
+        rnd.render(cam, light, check=True)
+        lvb = rnd.vbs[("light", light.width, light.height)]
+        cvb = rnd.vbs[("cam", cam.width, cam.height)]
+        p_l = gs3.gs3_view_pair_count(lvb)
+        hits_l = int(gs3.gs3_view_count_hits(k, lvb, False).item())
+        p_c = gs3.gs3_view_pair_count(cvb)
+        hits_c = int(gs3.gs3_view_count_hits(k, cvb, True).item())
+        stats.append((p_l, p_c, hits_l, hits_c))
+
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        cam, light = pairs[i % len(pairs)]
+        e = ev[i]
+        e[0].record(stream)
+        lvb = rnd._preprocess("light", light, gs3.GS3_DEPTH_DIST, False)
+        e[1].record(stream)
+        gs3.gs3_shadow_splat(k, lvb, rnd.num_den, rnd.T)
+        e[2].record(stream)
+        cvb = rnd._preprocess("cam", cam, gs3.GS3_DEPTH_Z, False)
+        e[3].record(stream)
+        gs3.gs3_render(ds, cam, light.eye, k, rnd.T, cvb, rnd._images(cam.width, cam.height), True)
+        e[4].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if rnd.overflowed():
+        raise RuntimeError("a binning exceeded its pair capacity inside the timed region")
+    wall = t1 - t0
+    fps = args.steps / wall
+    stage = np.zeros(4)
+    for e in ev:
+        for j in range(4):
+            stage[j] += e[j].elapsed_time(e[j + 1])
+    stage /= args.steps                                     # ms per frame
+    used = [stats[i % len(pairs)] for i in range(args.steps)]
+    p_l, p_c, h_l, h_c = [float(np.mean([u[j] for u in used])) for j in range(4)]
+    t_shadow = stage[1] / 1e3
+    shadow_tflops = h_l * SHADOW_FLOPS_PER_HIT / t_shadow / 1e12
+    fb = frame_bytes(sc.n, sc.k, p_l, p_c, 800 * 800)
+    frame_gbs = fb / (wall / args.steps) / 1e9
+    out = {
+        "metric": "relit frames/s @300k Gaussians 800^2 (1024^2 light splat)",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene and views; no trained weights exist for this workload)",
+        "config": {"workload": "full relit forward: 300,000 Gaussians, 8 lobes, Phi and Psi 3x64, "
+                               "camera 800x800, light 1024x1024, 40 deg fov, 4 view pairs",
+                   "n_gaussians": sc.n, "camera": [800, 800], "light": [1024, 1024]},
+        "roofline": {"bound": "alu", "kernel": "k_shadow (shadow splat)",
+                     "achieved": round(shadow_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(shadow_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "per_unit": f"{SHADOW_FLOPS_PER_HIT} flop per light-view hit",
+                     "units_per_launch": int(h_l), "avg_launch_ms": round(stage[1], 4)},
+        "stages_ms": {"light_preprocess": round(stage[0], 4), "shadow_splat": round(stage[1], 4),
+                      "camera_preprocess": round(stage[2], 4), "shade_mlp_render": round(stage[3], 4)},
+        "work": {"pairs_light": int(p_l), "pairs_camera": int(p_c), "hits_light": int(h_l),
+                 "hits_camera_blended": int(h_c)},
+        "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),
+                      "frac_of_8TBs": round(frame_gbs / HBM_PEAK_GBS, 4)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

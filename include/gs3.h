@@ -1,0 +1,257 @@
+/*
+ * gs3.h - C-ABI of the MI355X (gfx950) triple-splatting library libgs3.so.
+ *
+ * The library computes the relit render of GS^3 (Bi et al., "GS^3: Efficient
+ * Relighting with Triple Gaussian Splatting", SIGGRAPH Asia 2024) for one
+ * camera and one point light, and its adjoint:
+ *
+ *   gs3_project / gs3_bin / gs3_preprocess   Sec. 3 (Eq. 1-2): EWA projection
+ *        of the spatial Gaussians into a view, tile binning, depth sort.
+ *   gs3_shadow_splat   Sec. 4.2 and Fig. 3: splat toward the light, per-ray
+ *        transmittance with the 0.015 shadow bias, beta-weighted average T.
+ *   gs3_render         Sec. 4.1 (Eq. 4-7) shading, Sec. 4.2 (Eq. 8) shadow MLP
+ *        Phi, Sec. 4.3 residual MLP Psi, and the camera splat of Sec. 4 /
+ *        Fig. 2: final = shading * shadow + residual.
+ *   gs3_render_backward  gradients of all of the above (Sec. 4, end-to-end
+ *        differentiable training).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: GS3_OK (0) or a negative code.
+ *    Nothing throws across the ABI and nothing aborts. gs3_status_string()
+ *    names a code; gs3_last_error() returns a thread-local message for the
+ *    last failure on the calling thread.
+ *  - Pointers inside the structs and every array argument are DEVICE
+ *    pointers (hipMalloc / torch CUDA tensors) unless stated otherwise.
+ *    Inputs are const; the caller owns and allocates every buffer. The
+ *    library allocates no device memory on any path.
+ *  - All work is enqueued asynchronously on the caller's HIP stream
+ *    (`stream`, NULL = the default stream); no call synchronises the host
+ *    except gs3_view_pair_count.
+ *  - Per-Gaussian arrays are float32 structure-of-arrays with the Gaussian
+ *    index fastest ([C][n]); images are planar float32 [C][H][W], row-major.
+ *  - Calls that share a workspace must be ordered on one stream; distinct
+ *    workspaces may be used concurrently.
+ */
+#ifndef GS3_H
+#define GS3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gs3_stream_t; /* == hipStream_t */
+
+enum {
+    GS3_OK = 0,
+    GS3_INVALID_ARG = -1,          /* null pointer, bad size, misaligned buffer */
+    GS3_WORKSPACE_TOO_SMALL = -2,  /* ws_bytes below gs3_view_workspace_size */
+    GS3_PAIR_CAPACITY_EXCEEDED = -3, /* reported by gs3_view_pair_count */
+    GS3_HIP_ERROR = -4,            /* a HIP runtime call or launch failed */
+    GS3_UNSUPPORTED = -5           /* parameter combination not implemented */
+};
+
+/* Rasteriser constants. Sec. 4.2 fixes shadow_bias = 0.015; the others are
+ * the conventions of vanilla Gaussian splatting the paper builds on (Sec. 3)
+ * and are filled in by gs3_consts_default():
+ *   near_plane 0.2     cull Gaussians with view-space z <= near_plane
+ *   clamp_frac 1.3     x/z, y/z clamped to +-clamp_frac*tan(half fov) in the
+ *                      EWA Jacobian only
+ *   dilation   0.3     px^2 added to the diagonal of each 2D covariance
+ *   cutoff     4.5     a pixel is hit only where power >= -cutoff
+ *   alpha_min  1/255   ... and alpha >= alpha_min
+ *   alpha_max  0.99    alpha = min(alpha_max, opacity * exp(power))
+ *   t_min      1e-4    the camera pass stops before a hit that would take the
+ *                      transmittance below t_min
+ *   shadow_bias 0.015  Gaussian k shadows j only if dist_k < dist_j - bias
+ * cutoff = +inf, alpha_min = 0, alpha_max = 1, t_min = 0, dilation = 0 and
+ * shadow_bias = 0 give the threshold-free ("smooth") variant. */
+typedef struct {
+    float near_plane;
+    float clamp_frac;
+    float dilation;
+    float cutoff;
+    float alpha_min;
+    float alpha_max;
+    float t_min;
+    float shadow_bias;
+} gs3_consts;
+
+/* A pinhole view looking from `eye` at `target` (host values). Camera axes:
+ * x right, y down, z forward; world up +z (+y when the view direction is
+ * within acos(0.99) of +-z). Focal length (width/2)/tan(fov/2) in pixels,
+ * square pixels, principal point (width/2, height/2), pixel (i, j) centred
+ * at (i + 0.5, j + 0.5). A point light is a view whose eye is the light
+ * (Sec. 4.2: a perspective camera centred at the light). */
+typedef struct {
+    double eye[3];
+    double target[3];
+    int32_t width;
+    int32_t height;
+    double fov; /* horizontal field of view, radians, in (0, pi) */
+} gs3_view;
+
+/* Raw (pre-activation) per-Gaussian parameters, device float32 SoA.
+ * Activations applied inside the library: scale = exp(log_scale),
+ * opacity = sigmoid(opacity_logit), quaternions (w,x,y,z) normalised,
+ * lobe axes normalised, lobe sharpness lambda = exp(lobe_log_sharp). */
+typedef struct {
+    const float* mean;           /* [3][n] */
+    const float* log_scale;      /* [3][n] */
+    const float* rot;            /* [4][n]  Sigma = R S S^T R^T (Eq. 1) */
+    const float* opacity_logit;  /* [n] */
+    const float* shade_rot;      /* [4][n]  world -> shading frame (Sec. 4.1) */
+    const float* albedo;         /* [3][n]  rho_d */
+    const float* lobe_axis;      /* [k][3][n] in the shading frame */
+    const float* lobe_log_sharp; /* [k][n]  log(1/sigma_z) */
+    const float* lobe_amp;       /* [k][3][n] RGB weight of each lobe */
+    const float* feat;           /* [16][n] per-Gaussian MLP feature */
+    int64_t n;                   /* number of Gaussians, >= 0, < 2^31 */
+    int32_t k;                   /* lobes per Gaussian, 0..16 */
+} gs3_scene;
+
+/* A dense MLP with three hidden layers of 64 ReLU units and a sigmoid
+ * output: w[i] is row-major [out][in] float32, b[i] is [out].
+ * Phi (shadow refinement, Eq. 8): n_in = 17 ([T, feat]), n_out = 1.
+ * Psi (residual RGB, Sec. 4.3): n_in = 22 ([feat, w_i, w_o]), n_out = 3. */
+typedef struct {
+    const float* w[4];
+    const float* b[4];
+    int32_t n_in;
+    int32_t n_out;
+} gs3_mlp;
+
+/* A view's device workspace (host struct of plain values, owned by the
+ * caller). Its layout is a pure function of (n, width, height,
+ * pair_capacity); ws must be 256-byte aligned and hold at least
+ * gs3_view_workspace_size(n, width, height, pair_capacity) bytes. */
+typedef struct {
+    void* ws;
+    size_t ws_bytes;
+    int64_t n;              /* Gaussians the view was (or will be) built for */
+    int32_t width;          /* image size in pixels, 1..16384 */
+    int32_t height;
+    int64_t pair_capacity;  /* max (tile, Gaussian) pairs, 0..2^31-1 */
+} gs3_viewbuf;
+
+/* Depth key of a view: view-space z (camera) or distance to the eye
+ * (light, Sec. 4.2 sorts shadow-ray intersections by distance). */
+enum { GS3_DEPTH_Z = 0, GS3_DEPTH_DIST = 1 };
+
+/* Outputs of gs3_render. Images [C][H][W] of the camera view; every
+ * pointer is required. n_contrib[p] = one past the position, in the pixel's
+ * tile list, of the last Gaussian blended into pixel p (backward state).
+ * colour = per-Gaussian [8][n]: c.rgb (Eq. 4), T' (Eq. 8), r.rgb (Sec. 4.3),
+ * then 0 - the values splatted into S, Sh and R. */
+typedef struct {
+    float* final_rgb;  /* [3][H][W]  S * Sh + R */
+    float* shading;    /* [3][H][W]  S  */
+    float* shadow;     /* [H][W]     Sh */
+    float* residual;   /* [3][H][W]  R  */
+    float* t_final;    /* [H][W]     transmittance left after the last blend */
+    int32_t* n_contrib;/* [H][W] */
+    float* colour;     /* [8][n] */
+} gs3_images;
+
+void gs3_consts_default(gs3_consts* out);
+const char* gs3_status_string(int status);
+const char* gs3_last_error(void);
+/* 1 if the library was built for gfx950 and a gfx950 device is current. */
+int gs3_device_ok(void);
+
+/* Bytes of device workspace one view needs: projected splat records, sort
+ * buffers for up to `pair_capacity` (tile, Gaussian) pairs, tile ranges.
+ * Returns GS3_INVALID_ARG for n < 0, a non-positive image size or
+ * pair_capacity < 0. */
+int gs3_view_workspace_size(int64_t n, int32_t width, int32_t height,
+                            int64_t pair_capacity, size_t* bytes);
+
+/* Sec. 3 / Eq. 1-2 (projection): project the n Gaussians of `scene` into
+ * `view` and store the splat records (centre, conic, opacity, depth key,
+ * per-axis pixel extent of the hit ellipse) in `ws`. The extent of a splat
+ * is rx = ceil(sqrt(2 p Sigma'_xx)), ry = ceil(sqrt(2 p Sigma'_yy)) with
+ * p = min(cutoff, ln(opacity / alpha_min)); culled splats get rx = ry = -1.
+ * vb->n must equal scene->n and vb's size the view's. */
+int gs3_project(const gs3_scene* scene, const gs3_view* view,
+                const gs3_consts* consts, int32_t depth_mode,
+                const gs3_viewbuf* vb, gs3_stream_t stream);
+
+/* Sec. 3 ("sorted") and Sec. 4.2 (sorted by distance to the light): tile
+ * binning of vb->n splats given explicitly. Splat i covers pixel columns
+ * ix[i]-rx[i] .. ix[i]+rx[i] and rows iy[i]-ry[i] .. iy[i]+ry[i] (culled if
+ * rx[i] <= 0 or ry[i] <= 0) and is listed in every 16x16 tile of the
+ * vb->width x vb->height image those pixels touch. Each tile's list is ordered by
+ * (float32 bits of depth[i], i); depth must be >= 0. Results stay in `ws`;
+ * gs3_view_lists copies them out. gs3_preprocess calls the same code on the
+ * splats gs3_project computed. */
+int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx,
+            const int32_t* ry, const float* depth, const gs3_viewbuf* vb,
+            gs3_stream_t stream);
+
+/* gs3_project followed by binning of the projected splats (steps a1+a2 for
+ * the light view, a7+a8 for the camera view). */
+int gs3_preprocess(const gs3_scene* scene, const gs3_view* view,
+                   const gs3_consts* consts, int32_t depth_mode,
+                   const gs3_viewbuf* vb, gs3_stream_t stream);
+
+/* Number of (tile, Gaussian) pairs of the last binning in `vb` (host
+ * value; synchronises `stream`). Returns GS3_PAIR_CAPACITY_EXCEEDED (and
+ * the required count) if it exceeded the capacity: the lists are then
+ * truncated and every later result from this workspace is invalid. */
+int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t stream);
+
+/* Copy the binning of `vb` out: tile_start/tile_end [tiles] (list of tile t
+ * is ids[tile_start[t] .. tile_end[t]) ), ids [pair count] Gaussian indices,
+ * keys [pair count] (tile << 32 | depth bits). Any pointer may be NULL. */
+int gs3_view_lists(const gs3_viewbuf* vb, int32_t* tile_start, int32_t* tile_end,
+                   int32_t* ids, uint64_t* keys, gs3_stream_t stream);
+
+/* Copy the projected splats of `vb` out (any pointer may be NULL):
+ * mean2d [2][n] (pixel coordinates u, v), conic [3][n] (a, b, c of the
+ * inverse 2D covariance, power = -(a dx^2 + 2 b dx dy + c dy^2)/2),
+ * opacity [n], depth [n] (the sort key), extent [4][n] int32
+ * (floor(u), floor(v), rx, ry). */
+int gs3_view_splats(const gs3_viewbuf* vb, float* mean2d, float* conic, float* opacity,
+                    float* depth, int32_t* extent, gs3_stream_t stream);
+
+/* Measurement: the number of (pixel, splat) hits of the binned view in
+ * `vb` (pixels where power >= -cutoff and alpha >= alpha_min, Sec. 3 Eq. 2)
+ * written to *hits (one int64 of device memory). With stop_early != 0 only
+ * the hits blended before each pixel's early stop (t_min) are counted, as in
+ * the camera pass; with 0 every hit is counted, as the shadow pass evaluates
+ * them. This is the work unit the splatting kernels are measured against. */
+int gs3_view_count_hits(const gs3_consts* consts, const gs3_viewbuf* vb, int32_t stop_early,
+                        int64_t* hits, gs3_stream_t stream);
+
+/* Sec. 4.2, Fig. 3 (step a3): shadow splatting. `light_vb` holds a view
+ * preprocessed with GS3_DEPTH_DIST from the light position. For every light
+ * pixel m and every Gaussian j hit there, T_m(j) is the product of
+ * (1 - alpha_km) over the Gaussians k hit at m with
+ * dist_k < dist_j - shadow_bias; num_j = sum_m beta_jm T_m(j) and
+ * den_j = sum_m beta_jm (beta = exp(power), the splat density at the pixel
+ * centre). Outputs: num_den [2][n] (saved for the backward), T [n] =
+ * num/den, or 1 where den = 0. */
+int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb,
+                     float* num_den, float* T, gs3_stream_t stream);
+
+/* Sec. 4.1-4.3 and Fig. 2 (steps a4-a6, a9): shade every Gaussian for the
+ * point light at light_pos[3] (host) seen from the camera `cam`
+ * (c = rho_d f_d + sum_k amp_k G_k, Eq. 4-7, isotropic lobes, unit light),
+ * refine T with Phi (T' = T if phi is NULL), evaluate Psi (r = 0 if psi is
+ * NULL), then splat c, T' and r toward the camera front to back and write
+ * final = S * Sh + R. `cam_vb` holds `cam` preprocessed with GS3_DEPTH_Z.
+ * MLP weight pointers may be in any device memory; n_in/n_out must be
+ * 17/1 (phi) and 22/3 (psi). */
+int gs3_render(const gs3_scene* scene, const gs3_view* cam,
+               const double* light_pos, const gs3_consts* consts,
+               const float* T, const gs3_mlp* phi, const gs3_mlp* psi,
+               const gs3_viewbuf* cam_vb, const gs3_images* out,
+               gs3_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS3_H */

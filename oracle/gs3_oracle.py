@@ -34,7 +34,7 @@ __all__ = [
     "Consts", "SMOOTH", "DT", "ELU_ALPHA", "EPS_D",
     "as_t", "scene_tensors", "quat_to_rotmat", "covariance", "look_at",
     "focal", "project", "tile_rects", "bin_tiles", "pixel_entries",
-    "shadow_pass", "shadow_accumulate", "shadow_values", "splat_radius", "diffuse", "angular_gaussian",
+    "shadow_pass", "shadow_accumulate", "shadow_values", "splat_extent", "diffuse", "angular_gaussian",
     "lobe_frame", "shade", "mlp_forward", "camera_pass", "render",
     "render_images", "sigmoid",
 ]
@@ -203,79 +203,91 @@ def project(mean: torch.Tensor, cov: torch.Tensor, view, consts: Consts,
 
 # ----------------------------------------------------------------- binning
 
-def splat_radius(cov2: torch.Tensor, cutoff: float = 4.5) -> np.ndarray:
-    """Binning radius in pixels: ceil(sqrt(2 cutoff lambda_max)) with
-    lambda_max = mid + sqrt(max(0.1, mid^2 - det)) of the 2D covariance
-    (a, b, c); for the 3-sigma cut-off this is ceil(3 sqrt(lambda_max))."""
-    a, b, c = cov2[:, 0].detach(), cov2[:, 1].detach(), cov2[:, 2].detach()
-    mid = 0.5 * (a + c)
-    det = a * c - b * b
-    lam = mid + torch.sqrt(torch.clamp(mid * mid - det, min=0.1))
-    return torch.ceil(torch.sqrt(2.0 * cutoff * lam)).numpy().astype(np.int64)
+def splat_extent(proj, opacity: torch.Tensor, consts: Consts):
+    """Integer pixel extent of each splat's hit region, used for binning.
+
+    A pixel is hit only where power >= -cutoff and opacity * exp(power) >=
+    alpha_min, i.e. where power >= -p with p = min(cutoff, ln(opacity /
+    alpha_min)): an ellipse whose bounding box has half-widths
+    sqrt(2 p Sigma'_xx), sqrt(2 p Sigma'_yy). Returns (ix, iy, rx, ry) int64
+    arrays: ix = floor(u), iy = floor(v), rx/ry the half-widths rounded up;
+    rx = ry = -1 for culled splats (behind the near plane, degenerate, or
+    never reaching alpha_min)."""
+    with torch.no_grad():
+        op = opacity.detach()
+        p = torch.full_like(op, consts.cutoff)
+        if consts.alpha_min > 0:
+            p = torch.minimum(p, torch.log(op / consts.alpha_min))
+        ok = proj["valid"] & (p > 0)
+        big = float(1 << 20)
+        a = proj["cov2"][:, 0].detach().clamp_min(0)
+        c = proj["cov2"][:, 2].detach().clamp_min(0)
+        rx = torch.ceil(torch.sqrt(2 * p.clamp_min(0) * a)).clamp_max(big)
+        ry = torch.ceil(torch.sqrt(2 * p.clamp_min(0) * c)).clamp_max(big)
+        lim = float(1 << 30)
+        ix = torch.floor(proj["u"].detach().clamp(-lim, lim))
+        iy = torch.floor(proj["v"].detach().clamp(-lim, lim))
+        rx = torch.where(ok, rx, torch.full_like(rx, -1))
+        ry = torch.where(ok, ry, torch.full_like(ry, -1))
+    return (ix.numpy().astype(np.int64), iy.numpy().astype(np.int64),
+            rx.numpy().astype(np.int64), ry.numpy().astype(np.int64))
 
 
-def tile_rects(u: np.ndarray, v: np.ndarray, radius: np.ndarray, W: int, H: int,
-               tile: int = 16):
-    """Tiles a splat is binned to: the tiles covering pixel columns
-    floor(u)-r .. floor(u)+r and rows floor(v)-r .. floor(v)+r, clamped to the
-    grid. Integer rule applied to given float32 centres and integer radii."""
+def tile_rects(ix, iy, rx, ry, W: int, H: int, tile: int = 16):
+    """Tiles a splat is binned to: the 16x16 tiles covering pixel columns
+    ix-rx .. ix+rx and rows iy-ry .. iy+ry, clamped to the grid; empty when
+    rx <= 0 or ry <= 0 or the rectangle misses the image."""
     tx = (W + tile - 1) // tile
     ty = (H + tile - 1) // tile
-    iu = np.floor(np.clip(u.astype(np.float64), -2.0 ** 30, 2.0 ** 30)).astype(np.int64)
-    iv = np.floor(np.clip(v.astype(np.float64), -2.0 ** 30, 2.0 ** 30)).astype(np.int64)
-    r = radius.astype(np.int64)
-    x0 = np.maximum((iu - r) // tile, 0)
-    x1 = np.minimum((iu + r) // tile, tx - 1)
-    y0 = np.maximum((iv - r) // tile, 0)
-    y1 = np.minimum((iv + r) // tile, ty - 1)
-    empty = (x0 > x1) | (y0 > y1) | (r <= 0)
+    ix, iy = np.asarray(ix, np.int64), np.asarray(iy, np.int64)
+    rx, ry = np.asarray(rx, np.int64), np.asarray(ry, np.int64)
+    x0 = np.maximum((ix - rx) // tile, 0)
+    x1 = np.minimum((ix + rx) // tile, tx - 1)
+    y0 = np.maximum((iy - ry) // tile, 0)
+    y1 = np.minimum((iy + ry) // tile, ty - 1)
+    empty = (x0 > x1) | (y0 > y1) | (rx <= 0) | (ry <= 0)
     return x0, x1, y0, y1, empty
 
 
-def bin_tiles(u, v, radius, depth, W: int, H: int, tile: int = 16):
-    """Brute-force binning (Sec. 3 "sorted", Sec. 4.2 sorted by distance).
+def bin_tiles(ix, iy, rx, ry, depth, W: int, H: int, tile: int = 16):
+    """Brute-force binning (Sec. 3 "sorted"; Sec. 4.2 sorted by distance).
 
     For every tile, the ids of the splats whose rect covers it, ordered by
     (float32 depth bits, id). Returns (counts [tiles], flat id list, keys
-    [P] uint64 = tile << 32 | depth bits) exactly as a tile-major sort of
-    (tile, depth, id) would lay them out. Inputs are the float32 centres,
-    integer radii and float32 depths a projection produced."""
-    u = np.asarray(u, np.float32); v = np.asarray(v, np.float32)
+    [P] uint64 = tile << 32 | depth bits) laid out tile by tile, exactly as a
+    sort of (tile, depth, id) would. Inputs: integer extents (see
+    ``splat_extent``) and float32 depths (>= 0)."""
     depth = np.asarray(depth, np.float32)
-    radius = np.asarray(radius, np.int64)
-    x0, x1, y0, y1, empty = tile_rects(u, v, radius, W, H, tile)
+    x0, x1, y0, y1, empty = tile_rects(ix, iy, rx, ry, W, H, tile)
     tx = (W + tile - 1) // tile
     ty = (H + tile - 1) // tile
     dbits = depth.view(np.uint32).astype(np.uint64)
     counts = np.zeros(tx * ty, np.int64)
-    lists = []
-    keys = []
-    n = u.shape[0]
-    ids = np.arange(n)
+    lists, keys = [], []
+    ids = np.arange(depth.shape[0])
     for t_id in range(tx * ty):
         gx, gy = t_id % tx, t_id // tx
         sel = (~empty) & (x0 <= gx) & (gx <= x1) & (y0 <= gy) & (gy <= y1)
         members = ids[sel]
-        order = np.lexsort((members, dbits[members]))   # by depth bits, then id
-        members = members[order]
+        members = members[np.lexsort((members, dbits[members]))]   # by depth bits, then id
         counts[t_id] = members.size
         lists.append(members)
         keys.append((np.uint64(t_id) << np.uint64(32)) | dbits[members])
-    return counts, np.concatenate(lists) if lists else np.zeros(0, np.int64), \
-        np.concatenate(keys) if keys else np.zeros(0, np.uint64)
+    return counts, np.concatenate(lists), np.concatenate(keys)
 
 
 # -------------------------------------------------------- per-pixel entries
 
 # Error model of the float32 evaluation, used only to flag outputs whose
-# value hangs on a threshold decision (cut-off, alpha minimum, early stop,
-# depth order, shadow bias) that a float32 evaluation may take differently
-# from this float64 one. It assumes splat centres and depths accurate to
-# ~1e-6 px / 5e-7 relative (projection evaluated in double and rounded) and
+# value hangs on a threshold decision (cut-off, alpha minimum, early stop)
+# that a float32 evaluation may take differently from this float64 one.
+# (Depth order and the shadow-bias test are decided on float32 keys in
+# float32 arithmetic on both sides, so they need no flag.) It assumes splat
+# centres rounded once to float32 from an exact evaluation, a pixel offset
+# formed relative to a nearby origin (error ~ 2e-7 (|d| + 32) px), and
 # per-pixel arithmetic in float32.
-_POS_ERR = 1e-6          # absolute error of a splat centre, px
+_POS_REL = 2e-7          # error of a pixel offset d, per px of |d| + 32
 _POW_REL = 4e-6          # relative error of power, alpha
-_DEPTH_REL = 5e-7        # relative error of a depth / distance key
 _AMB_T = 2e-5            # relative margin on the early-stop test
 AMB_BUDGET = 5e-5        # an output is ambiguous when it could move this much
 
@@ -345,9 +357,11 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
             keep = pidx >= 0
             gid, px, py, pidx = gid[keep], px[keep], py[keep], pidx[keep]
             n_pix = pixels.numel()
-        # sort by (pixel, depth, id): pairs come in id order, then two
-        # stable sorts
-        dep = depth.detach()[gid]
+        # sort by (pixel, depth key, id): pairs come in id order, then two
+        # stable sorts. The depth key is the depth rounded to float32 (the
+        # method's sort key); the order is a discrete decision, so it is
+        # taken in the kernel's precision and matches it exactly.
+        dep = depth.detach().to(torch.float32).to(DT)[gid]
         o = torch.sort(dep, stable=True).indices
         gid, px, py, pidx, dep = gid[o], px[o], py[o], pidx[o], dep[o]
         o = torch.sort(pidx, stable=True).indices
@@ -368,7 +382,8 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
         # threshold ambiguity of this pair (power cut-off or alpha minimum)
         gx = (ca * dx + cb * dy).abs()
         gy = (cb * dx + cc * dy).abs()
-        pmarg = _POW_REL * (1.0 + power.abs()) + _POS_ERR * (gx + gy)
+        pos_err = _POS_REL * (dx.abs() + dy.abs() + 32.0)
+        pmarg = _POW_REL * (1.0 + power.abs()) + pos_err * (gx + gy)
         amb = (power + consts.cutoff).abs() <= pmarg
         if consts.alpha_min > 0:
             amb = amb | ((alpha_full - consts.alpha_min).abs() <= (pmarg + _POW_REL) * alpha_full)
@@ -405,8 +420,10 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
     Every light pixel m is one shadow ray; its hits are sorted by distance to
     the light. For each hit j the cumulative transmittance in front of it is
     T_m(j) = prod (1 - alpha_km) over hits k on m with
-    dist_k < dist_j - shadow_bias (Eq. 3 with the bias of Sec. 4.2); then
-    num_j += beta_jm T_m(j) and den_j += beta_jm. Returns num, den and the
+    dist_k < dist_j - shadow_bias (Eq. 3 with the bias of Sec. 4.2; the
+    distances are the float32 depth keys and the comparison is evaluated in
+    float32, as the kernel does); then num_j += beta_jm T_m(j) and
+    den_j += beta_jm. Returns num, den and the
     per-Gaussian ambiguity bound (an upper bound on how far T_j could move
     if float32 took a threshold decision the other way)."""
     W, H = light_view.width, light_view.height
@@ -428,7 +445,9 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
         alpha, beta, dist = e["alpha_pad"], e["beta_pad"], e["depth_pad"]
         hit, gidp = e["hit_pad"], e["gid_pad"]
         prefix = _excl_prefix_product(1.0 - alpha)                  # [P, L+1]
-        thr = dist - b
+        # occluders: key_k < fl32(key_j - fl32(bias)) -- a discrete decision
+        # on float32 keys, evaluated in float32 like the kernel
+        thr = (dist.to(torch.float32) - torch.tensor(b, dtype=torch.float32)).to(DT)
         cnt = torch.searchsorted(dist.contiguous(), thr.contiguous(), right=False)
         Tm = torch.gather(prefix, 1, cnt)                           # T_m(j)
         dn, dd = shadow_accumulate(gidp[hit], beta[hit], Tm[hit], n)
@@ -436,28 +455,17 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
         den = den + dd
         with torch.no_grad():
             # ambiguity: a threshold flip of j's own pair moves T_j by at most
-            # beta_jm / den_j; a flip of occluder k (threshold-ambiguous, or
-            # on the biased distance threshold) moves T_m(j) by at most
-            # alpha_k times the transmittance in front of k.
+            # beta_jm / den_j; a threshold flip of an occluder k moves T_m(j)
+            # by at most alpha_k times the transmittance in front of k.
             amb = e["amb_pad"]
             af = e["alpha_full_pad"]
             Tk = prefix[:, :-1].detach()
             z1 = torch.zeros(af.shape[0], 1, dtype=DT)
             occ_amb = torch.cat([z1, torch.cumsum(torch.where(amb, af * Tk, torch.zeros_like(af)), 1)], 1)
-            hit_a = torch.cat([z1, torch.cumsum(alpha.detach() * Tk, 1)], 1)
-            dlt = _DEPTH_REL * 2 * dist.abs().clamp_max(1e30) + 1e-9
-            hi = torch.searchsorted(dist.contiguous(), (thr + dlt).contiguous(), right=False)
-            lo = torch.searchsorted(dist.contiguous(), (thr - dlt).contiguous(), right=False)
-            occ = torch.gather(occ_amb, 1, hi)
-            bias_w = torch.gather(hit_a, 1, hi) - torch.gather(hit_a, 1, lo)
-            # j never shadows itself: drop its own entry where the window
-            # reaches it (bias smaller than the depth margin)
-            self_in = (dist >= thr - dlt) & (dist < thr + dlt)
-            bias_w = bias_w - torch.where(self_in, alpha.detach() * Tk, torch.zeros_like(af))
-            occ = occ - torch.where(self_in & amb, af * Tk, torch.zeros_like(af))
+            occ = torch.gather(occ_amb, 1, cnt)
             bf = e["beta_full_pad"]
             own = torch.where(amb, bf, torch.zeros_like(bf))
-            w_all = own + torch.where(hit, bf * (occ + bias_w), torch.zeros_like(bf))
+            w_all = own + torch.where(hit, bf * occ, torch.zeros_like(bf))
             valid_e = gidp >= 0
             infl = infl.index_add(0, gidp[valid_e], w_all[valid_e])
     return num, den, infl
@@ -599,23 +607,17 @@ def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts
         R = (w[..., None] * resid[g]).sum(1).T
         Tfin = torch.where(inc, 1.0 - alpha, torch.ones_like(alpha)).prod(1)
         with torch.no_grad():
-            amb, af, dep = e["amb_pad"], e["alpha_full_pad"], e["depth_pad"]
+            amb, af = e["amb_pad"], e["alpha_full_pad"]
             Te = T_excl.detach()
             live = Te >= consts.t_min * (1 - _AMB_T)
             w_thr = torch.where(amb & live, af * Te, torch.zeros_like(af)).sum(1)
             near_stop = hit & ((T_incl.detach() - consts.t_min).abs() <= _AMB_T * consts.t_min)
             w_stop = torch.where(near_stop, af * Te, torch.zeros_like(af)).sum(1)
-            hits_cum = torch.cat([torch.zeros(P, 1, dtype=DT), torch.cumsum(hit.to(DT), 1)], 1)
-            dl = _DEPTH_REL * 2 * dep.abs().clamp_max(1e30) + 1e-9
-            hi = torch.searchsorted(dep.contiguous(), (dep + dl).contiguous(), right=True)
-            lo = torch.searchsorted(dep.contiguous(), (dep - dl).contiguous(), right=False)
-            ties = torch.gather(hits_cum, 1, hi) - torch.gather(hits_cum, 1, lo) - 1
-            w_tie = torch.where(hit & live & (ties > 0), af * Te * ties, torch.zeros_like(af)).sum(1)
             cabs = torch.where(hit, colour.detach().abs().amax(1)[g], torch.zeros_like(af))
             cmax = cabs.amax(1).clamp_min(1.0)
             rmax = torch.where(hit, resid.detach().abs().amax(1)[g], torch.zeros_like(af)).amax(1)
             C = 2.0 * (2.0 * cmax + rmax + 1.0)
-            ambw = C * (w_thr + w_stop + w_tie)
+            ambw = C * (w_thr + w_stop)
             if tprime_err is not None:
                 ambw = ambw + cmax * (w.detach() * tprime_err[g]).sum(1)
         outS.append(S); outSh.append(Sh); outR.append(R); outT.append(Tfin); outAmb.append(ambw)

@@ -1,0 +1,358 @@
+// Host side of the C-ABI (include/gs3.h): argument checks, workspace
+// layout, view set-up in double precision, kernel launch order.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gs3_internal.h"
+
+namespace gs3 {
+
+static thread_local std::string g_last_error;
+
+static int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+static int hip_fail(hipError_t e, const char* where) {
+    return fail(GS3_HIP_ERROR, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GS3_CHECK_HIP(expr)                                  \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);    \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Layout* L) {
+    if (n < 0 || n >= (int64_t(1) << 31) || width <= 0 || height <= 0 || width > 16384 || height > 16384 ||
+        capacity < 0 || capacity >= (int64_t(1) << 31))
+        return false;
+    Layout l;
+    l.n = n;
+    l.width = width;
+    l.height = height;
+    l.tiles_x = (width + kTile - 1) / kTile;
+    l.tiles_y = (height + kTile - 1) / kTile;
+    l.n_tiles = (int64_t)l.tiles_x * l.tiles_y;
+    l.capacity = capacity;
+    l.nblk_n = (n + kSortItems - 1) / kSortItems;
+    l.nblk_p = (capacity + kSortItems - 1) / kSortItems;
+    const int64_t nblk = l.nblk_n > l.nblk_p ? l.nblk_n : l.nblk_p;
+    l.table_len = nblk * kRadixBins;
+    const int64_t longest = l.table_len > n + 1 ? l.table_len : n + 1;
+    l.scan_sums = (longest + kSortItems - 1) / kSortItems + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    l.hdr = take(sizeof(ViewHeader));
+    l.rec0 = take(sizeof(float4) * n);
+    l.rec1 = take(sizeof(float4) * n);
+    l.depth = take(sizeof(float) * n);
+    l.ext = take(sizeof(int4) * n);
+    l.cnt = take(sizeof(uint32_t) * n);
+    l.col0 = take(sizeof(float4) * n);
+    l.col1 = take(sizeof(float4) * n);
+    l.keys_a = take(sizeof(uint32_t) * n);
+    l.vals_a = take(sizeof(uint32_t) * n);
+    l.keys_b = take(sizeof(uint32_t) * n);
+    l.vals_b = take(sizeof(uint32_t) * n);
+    l.offs = take(sizeof(uint32_t) * (n + 1));
+    l.pk_a = take(sizeof(uint32_t) * capacity);
+    l.pv_a = take(sizeof(uint32_t) * capacity);
+    l.pk_b = take(sizeof(uint32_t) * capacity);
+    l.pv_b = take(sizeof(uint32_t) * capacity);
+    l.table = take(sizeof(uint32_t) * l.table_len);
+    l.sums = take(sizeof(uint32_t) * l.scan_sums);
+    l.ranges = take(sizeof(int2) * l.n_tiles);
+    l.total = off;
+    *L = l;
+    return true;
+}
+
+static int check_vb(const gs3_viewbuf* vb, Layout* L) {
+    if (!vb) return fail(GS3_INVALID_ARG, "viewbuf is NULL");
+    if (!make_layout(vb->n, vb->width, vb->height, vb->pair_capacity, L))
+        return fail(GS3_INVALID_ARG, "invalid view buffer sizes (n=%lld, %dx%d, capacity=%lld)",
+                    (long long)vb->n, vb->width, vb->height, (long long)vb->pair_capacity);
+    if (!vb->ws) return fail(GS3_INVALID_ARG, "viewbuf.ws is NULL");
+    if ((reinterpret_cast<uintptr_t>(vb->ws) & 255) != 0) return fail(GS3_INVALID_ARG, "viewbuf.ws not 256-byte aligned");
+    if (vb->ws_bytes < L->total)
+        return fail(GS3_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", vb->ws_bytes, L->total);
+    return GS3_OK;
+}
+
+static int check_consts(const gs3_consts* k) {
+    if (!k) return fail(GS3_INVALID_ARG, "consts is NULL");
+    if (!(k->near_plane > 0.f) || !(k->clamp_frac > 0.f) || !(k->dilation >= 0.f) || !(k->cutoff > 0.f) ||
+        !(k->alpha_min >= 0.f) || !(k->alpha_max > 0.f) || !(k->alpha_max <= 1.f) || !(k->t_min >= 0.f) ||
+        !(k->shadow_bias >= 0.f) || !std::isfinite(k->shadow_bias))
+        return fail(GS3_INVALID_ARG, "invalid rasteriser constants");
+    return GS3_OK;
+}
+
+static int check_scene(const gs3_scene* s, bool need_shading) {
+    if (!s) return fail(GS3_INVALID_ARG, "scene is NULL");
+    if (s->n < 0 || s->n >= (int64_t(1) << 31)) return fail(GS3_INVALID_ARG, "scene.n out of range");
+    if (s->k < 0 || s->k > kMaxLobes) return fail(GS3_INVALID_ARG, "scene.k out of range (0..%d)", kMaxLobes);
+    if (s->n == 0) return GS3_OK;
+    if (!s->mean || !s->log_scale || !s->rot || !s->opacity_logit)
+        return fail(GS3_INVALID_ARG, "scene geometry pointer is NULL");
+    if (need_shading && (!s->shade_rot || !s->albedo || !s->feat || (s->k > 0 && (!s->lobe_axis || !s->lobe_log_sharp || !s->lobe_amp))))
+        return fail(GS3_INVALID_ARG, "scene appearance pointer is NULL");
+    return GS3_OK;
+}
+
+static SceneDev scene_dev(const gs3_scene* s) {
+    SceneDev d;
+    d.mean = s->mean;
+    d.log_scale = s->log_scale;
+    d.rot = s->rot;
+    d.opacity_logit = s->opacity_logit;
+    d.shade_rot = s->shade_rot;
+    d.albedo = s->albedo;
+    d.lobe_axis = s->lobe_axis;
+    d.lobe_log_sharp = s->lobe_log_sharp;
+    d.lobe_amp = s->lobe_amp;
+    d.feat = s->feat;
+    d.n = (int32_t)s->n;
+    d.k = s->k;
+    return d;
+}
+
+// Pinhole view in double: world-to-camera rows (right, down, forward).
+static int view_params(const gs3_view* v, const Layout& L, int depth_mode, ViewParams* vp) {
+    if (!v) return fail(GS3_INVALID_ARG, "view is NULL");
+    if (v->width != L.width || v->height != L.height)
+        return fail(GS3_INVALID_ARG, "view size %dx%d does not match the view buffer %dx%d", v->width, v->height,
+                    L.width, L.height);
+    if (!(v->fov > 0.0 && v->fov < M_PI)) return fail(GS3_INVALID_ARG, "fov must be in (0, pi)");
+    if (depth_mode != GS3_DEPTH_Z && depth_mode != GS3_DEPTH_DIST) return fail(GS3_INVALID_ARG, "bad depth_mode");
+    double f[3] = {v->target[0] - v->eye[0], v->target[1] - v->eye[1], v->target[2] - v->eye[2]};
+    const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fn > 0.0) || !std::isfinite(fn)) return fail(GS3_INVALID_ARG, "eye and target coincide");
+    for (double& x : f) x /= fn;
+    const double up[3] = {0.0, std::fabs(f[2]) <= 0.99 ? 0.0 : 1.0, std::fabs(f[2]) <= 0.99 ? 1.0 : 0.0};
+    double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (double& x : r) x /= rn;
+    const double d[3] = {f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]};
+    for (int i = 0; i < 3; ++i) {
+        vp->R[i] = r[i];
+        vp->R[3 + i] = d[i];
+        vp->R[6 + i] = f[i];
+        vp->eye[i] = v->eye[i];
+    }
+    vp->focal = (v->width / 2.0) / std::tan(v->fov / 2.0);
+    vp->cx = v->width / 2.0;
+    vp->cy = v->height / 2.0;
+    vp->width = L.width;
+    vp->height = L.height;
+    vp->tiles_x = L.tiles_x;
+    vp->tiles_y = L.tiles_y;
+    vp->depth_mode = depth_mode;
+    return GS3_OK;
+}
+
+static int check_mlp(const gs3_mlp* m, int n_in, int n_out, const char* name) {
+    if (!m) return GS3_OK;
+    if (m->n_in != n_in || m->n_out != n_out)
+        return fail(GS3_INVALID_ARG, "%s must be %d -> 64 -> 64 -> 64 -> %d (got n_in=%d, n_out=%d)", name, n_in,
+                    n_out, m->n_in, m->n_out);
+    for (int i = 0; i < 4; ++i)
+        if (!m->w[i] || !m->b[i]) return fail(GS3_INVALID_ARG, "%s weight pointer %d is NULL", name, i);
+    return GS3_OK;
+}
+
+}  // namespace gs3
+
+using namespace gs3;
+
+extern "C" {
+
+void gs3_consts_default(gs3_consts* out) {
+    if (!out) return;
+    out->near_plane = 0.2f;
+    out->clamp_frac = 1.3f;
+    out->dilation = 0.3f;
+    out->cutoff = 4.5f;
+    out->alpha_min = 1.0f / 255.0f;
+    out->alpha_max = 0.99f;
+    out->t_min = 1e-4f;
+    out->shadow_bias = 0.015f;
+}
+
+const char* gs3_status_string(int status) {
+    switch (status) {
+        case GS3_OK: return "GS3_OK";
+        case GS3_INVALID_ARG: return "GS3_INVALID_ARG";
+        case GS3_WORKSPACE_TOO_SMALL: return "GS3_WORKSPACE_TOO_SMALL";
+        case GS3_PAIR_CAPACITY_EXCEEDED: return "GS3_PAIR_CAPACITY_EXCEEDED";
+        case GS3_HIP_ERROR: return "GS3_HIP_ERROR";
+        case GS3_UNSUPPORTED: return "GS3_UNSUPPORTED";
+        default: return "GS3_UNKNOWN_STATUS";
+    }
+}
+
+const char* gs3_last_error(void) { return g_last_error.c_str(); }
+
+int gs3_device_ok(void) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+int gs3_view_workspace_size(int64_t n, int32_t width, int32_t height, int64_t pair_capacity, size_t* bytes) {
+    if (!bytes) return fail(GS3_INVALID_ARG, "bytes is NULL");
+    Layout L;
+    if (!make_layout(n, width, height, pair_capacity, &L))
+        return fail(GS3_INVALID_ARG, "invalid sizes (n=%lld, %dx%d, capacity=%lld)", (long long)n, width, height,
+                    (long long)pair_capacity);
+    *bytes = L.total;
+    return GS3_OK;
+}
+
+int gs3_project(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
+                const gs3_viewbuf* vb, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if ((st = check_scene(scene, false)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (scene->n != vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbuf.n");
+    ViewParams vp;
+    if ((st = view_params(view, L, depth_mode, &vp)) != GS3_OK) return st;
+    const double tx = (view->width / 2.0) / vp.focal, ty = (view->height / 2.0) / vp.focal;
+    vp.lim_x = consts->clamp_frac * tx;
+    vp.lim_y = consts->clamp_frac * ty;
+    GS3_CHECK_HIP(launch_project(scene_dev(scene), vp, *consts, L, vb->ws, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx, const int32_t* ry, const float* depth,
+            const gs3_viewbuf* vb, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if (L.n > 0 && (!ix || !iy || !rx || !ry || !depth)) return fail(GS3_INVALID_ARG, "extent/depth pointer is NULL");
+    GS3_CHECK_HIP(launch_extent_keys(ix, iy, rx, ry, depth, L, vb->ws, (hipStream_t)stream));
+    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_preprocess(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
+                   const gs3_viewbuf* vb, gs3_stream_t stream) {
+    int st = gs3_project(scene, view, consts, depth_mode, vb, stream);
+    if (st != GS3_OK) return st;
+    Layout L;
+    make_layout(vb->n, vb->width, vb->height, vb->pair_capacity, &L);
+    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if (!n_pairs) return fail(GS3_INVALID_ARG, "n_pairs is NULL");
+    ViewHeader h;
+    GS3_CHECK_HIP(hipMemcpyAsync(&h, at<ViewHeader>(vb->ws, L.hdr), sizeof h, hipMemcpyDeviceToHost,
+                                 (hipStream_t)stream));
+    GS3_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    *n_pairs = (int64_t)h.required_pairs;
+    if (h.overflow)
+        return fail(GS3_PAIR_CAPACITY_EXCEEDED, "binning needs %llu pairs, capacity is %lld", h.required_pairs,
+                    (long long)L.capacity);
+    return GS3_OK;
+}
+
+int gs3_view_lists(const gs3_viewbuf* vb, int32_t* tile_start, int32_t* tile_end, int32_t* ids, uint64_t* keys,
+                   gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    GS3_CHECK_HIP(launch_export_lists(L, vb->ws, tile_start, tile_end, ids, keys, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_view_splats(const gs3_viewbuf* vb, float* mean2d, float* conic, float* opacity, float* depth, int32_t* extent,
+                    gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    GS3_CHECK_HIP(launch_export_splats(L, vb->ws, mean2d, conic, opacity, depth, extent, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_view_count_hits(const gs3_consts* consts, const gs3_viewbuf* vb, int32_t stop_early, int64_t* hits,
+                        gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (!hits) return fail(GS3_INVALID_ARG, "hits is NULL");
+    if ((reinterpret_cast<uintptr_t>(hits) & 7) != 0) return fail(GS3_INVALID_ARG, "hits not 8-byte aligned");
+    GS3_CHECK_HIP(launch_count_hits(*consts, L, vb->ws, stop_early ? 1 : 0,
+                                    reinterpret_cast<unsigned long long*>(hits), (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den, float* T,
+                     gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (L.n > 0 && (!num_den || !T)) return fail(GS3_INVALID_ARG, "num_den / T is NULL");
+    GS3_CHECK_HIP(launch_shadow(*consts, L, light_vb->ws, num_den, T, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_consts* consts,
+               const float* T, const gs3_mlp* phi, const gs3_mlp* psi, const gs3_viewbuf* cam_vb,
+               const gs3_images* out, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(cam_vb, &L)) != GS3_OK) return st;
+    if ((st = check_scene(scene, true)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (scene->n != cam_vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbuf.n");
+    if (!cam || cam->width != L.width || cam->height != L.height)
+        return fail(GS3_INVALID_ARG, "camera view missing or its size differs from the view buffer");
+    if (!light_pos) return fail(GS3_INVALID_ARG, "light_pos is NULL");
+    if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
+        !out->n_contrib || !out->colour)
+        return fail(GS3_INVALID_ARG, "an output pointer is NULL");
+    if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
+    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
+    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    ShadeParams sp;
+    for (int i = 0; i < 3; ++i) {
+        sp.light[i] = (float)light_pos[i];
+        sp.eye[i] = (float)cam->eye[i];
+    }
+    sp.use_phi = phi != nullptr;
+    sp.use_psi = psi != nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, cam_vb->ws, out->colour, s));
+    GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
+    return GS3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal declarations of libgs3: workspace layout, splat record format,
+// kernel launchers. Not part of the public ABI (see include/gs3.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/gs3.h"
+
+namespace gs3 {
+
+constexpr int kTile = 16;          // tile edge in pixels
+constexpr int kBlock = 256;        // threads per tile workgroup (4 wave64)
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortItems = 4096;   // items per radix / scan workgroup
+constexpr int kFeat = 16;          // per-Gaussian MLP feature size
+constexpr int kHidden = 64;        // MLP hidden width
+constexpr int kMaxLobes = 16;
+
+// Device-side counters at the head of every view workspace.
+struct ViewHeader {
+    unsigned long long required_pairs;  // unclamped pair total of the last binning
+    uint32_t n_pairs;                   // min(required, capacity)
+    uint32_t overflow;                  // 1 if required > capacity
+    uint32_t pad[60];
+};
+
+// Projected splat record, two float4 per Gaussian:
+//   rec0 = {floor(u), floor(v), u - floor(u), v - floor(v)}  (pixel centre,
+//          split so a tile-relative centre can be formed without rounding)
+//   rec1 = {a, b, c, opacity}  conic (inverse 2D covariance) and sigmoid opacity
+// Culled Gaussians have ext.z = ext.w = -1 and zero records.
+struct Layout {
+    int64_t n = 0;
+    int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0;
+    int64_t n_tiles = 0;
+    int64_t capacity = 0;
+    int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
+    size_t hdr = 0, rec0 = 0, rec1 = 0, depth = 0, ext = 0, cnt = 0, col0 = 0, col1 = 0;
+    size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
+    size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0;
+    size_t total = 0;
+};
+
+// Compute the workspace layout; returns false on invalid sizes.
+bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Layout* L);
+
+template <typename T>
+inline T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+template <typename T>
+inline const T* at(const void* base, size_t off) {
+    return reinterpret_cast<const T*>(static_cast<const char*>(base) + off);
+}
+
+// View parameters for the projection kernel (all derived on the host in double).
+struct ViewParams {
+    double R[9];        // world -> camera rotation, row-major (rows: right, down, forward)
+    double eye[3];
+    double focal;       // pixels
+    double cx, cy;      // principal point
+    double lim_x, lim_y;  // clamp of x/z, y/z in the Jacobian
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t depth_mode;
+};
+
+struct SceneDev {
+    const float* mean;
+    const float* log_scale;
+    const float* rot;
+    const float* opacity_logit;
+    const float* shade_rot;
+    const float* albedo;
+    const float* lobe_axis;
+    const float* lobe_log_sharp;
+    const float* lobe_amp;
+    const float* feat;
+    int32_t n;
+    int32_t k;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_consts& k,
+                          const Layout& L, void* ws, hipStream_t st);
+hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_t* rx,
+                              const int32_t* ry, const float* depth, const Layout& L,
+                              void* ws, hipStream_t st);
+hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st);
+hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws,
+                         float* num_den, float* T, hipStream_t st);
+struct ShadeParams {
+    float light[3];
+    float eye[3];
+    int32_t use_phi, use_psi;
+};
+hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T,
+                            const gs3_mlp* phi, const gs3_mlp* psi, const Layout& L,
+                            void* ws, float* colour_out, hipStream_t st);
+hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws,
+                         const gs3_images& out, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
+hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, int32_t* end, int32_t* ids,
+                               uint64_t* keys, hipStream_t st);
+hipError_t launch_count_hits(const gs3_consts& k, const Layout& L, const void* ws, int stop_early,
+                             unsigned long long* out, hipStream_t st);
+hipError_t launch_export_splats(const Layout& L, const void* ws, float* mean2d, float* conic, float* opacity,
+                                float* depth, int32_t* extent, hipStream_t st);
+
+}  // namespace gs3

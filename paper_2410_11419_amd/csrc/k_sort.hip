@@ -1,0 +1,374 @@
+// Tile binning and depth ordering (Sec. 3: splats are sorted per pixel;
+// Sec. 4.2: toward the light they are sorted by distance).
+//
+// Every tile's list must be ordered by (float32 depth bits, Gaussian index).
+// Instead of a radix sort over 64-bit (tile, depth) keys of all P pairs, the
+// N splats are first put in depth order (a 32-bit LSD radix sort of N keys,
+// stable, so equal depths stay in index order), pairs are emitted in that
+// order, and a stable LSD radix sort by tile index alone (ceil(log2 tiles)
+// bits) then leaves each tile's pairs in depth order. Same lists, far fewer
+// bytes moved per pair than sorting 64-bit keys.
+#include "gs3_internal.h"
+
+namespace gs3 {
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// exclusive block scan of one u32 per thread (blockDim.x == 256)
+__device__ inline uint32_t block_excl_scan_256(uint32_t v, uint32_t* total, uint32_t* s_wave) {
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wave[w] = x;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t t = s_wave[i];
+        wpre += (i < w) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return wpre + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+// ---------------------------------------------------------------- scan
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t len,
+                                                      uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_wave[4];
+    const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int64_t i = base + j;
+        acc += (i < len) ? in[i] : 0u;
+    }
+    uint32_t tot;
+    block_excl_scan_256(acc, &tot, s_wave);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single workgroup: exclusive scan of m block sums in place; the grand
+// total (64-bit) optionally goes to the view header.
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int64_t m,
+                                                   ViewHeader* __restrict__ hdr, int64_t capacity,
+                                                   uint32_t* __restrict__ tail_out) {
+    __shared__ uint32_t s_wave[4];
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < m; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < m ? sums[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_256(v, &tot, s_wave);
+        if (i < m) sums[i] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (hdr) {
+            hdr->required_pairs = carry;
+            const unsigned long long cap = (unsigned long long)capacity;
+            hdr->n_pairs = (uint32_t)(carry < cap ? carry : cap);
+            hdr->overflow = carry > cap ? 1u : 0u;
+        }
+        if (tail_out) *tail_out = (uint32_t)carry;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, int64_t len,
+                                                    const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_wave[4];
+    const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
+    uint32_t vals[16];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int64_t i = base + j;
+        vals[j] = (i < len) ? in[i] : 0u;
+        acc += vals[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan_256(acc, &tot, s_wave) + sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int64_t i = base + j;
+        if (i < len) out[i] = run;
+        run += vals[j];
+    }
+}
+
+static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t len, uint32_t* sums,
+                                 ViewHeader* hdr, int64_t capacity, uint32_t* tail_out, hipStream_t st) {
+    const int64_t nb = (len + kSortItems - 1) / kSortItems;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, (int64_t)0, hdr, capacity, tail_out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, len, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, nb, hdr, capacity, tail_out);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, st, in, len, sums, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- radix
+
+// Per-block digit histogram of keys[base .. base+4096), written digit-major
+// into table[digit * nblk + block]. n is read from *n_dev when given.
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                                     uint32_t n_host, int shift, uint32_t* __restrict__ table, int nblk) {
+    __shared__ uint32_t h[4][kRadixBins];
+    const int tid = threadIdx.x, w = tid >> 6;
+    for (int i = tid; i < 4 * kRadixBins; i += 256) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    const uint32_t base = blockIdx.x * (uint32_t)kSortItems;
+    if (base < n) {
+#pragma unroll 4
+        for (int r = 0; r < kSortItems / 256; ++r) {
+            const uint32_t idx = base + r * 256 + tid;
+            if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int d = tid; d < kRadixBins; d += 256) table[d * nblk + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+// Stable scatter: each block ranks its 4096 items by digit (ties keep input
+// order), stages them digit-sorted in LDS, and writes each digit run to its
+// global offset (table holds the exclusive scan of the digit-major
+// histogram).
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                        const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+                                                        const uint32_t* __restrict__ table, int nblk) {
+    __shared__ uint32_t s_key[kSortItems];
+    __shared__ uint32_t s_val[kSortItems];
+    __shared__ uint32_t s_cnt[4][kRadixBins];
+    __shared__ uint32_t s_run[kRadixBins];
+    __shared__ uint32_t s_lstart[kRadixBins];
+    __shared__ uint32_t s_gstart[kRadixBins];
+    __shared__ uint32_t s_wave[4];
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    const uint32_t base = blockIdx.x * (uint32_t)kSortItems;
+    if (base >= n) return;   // whole block beyond the data: uniform exit
+    const uint32_t count = (n - base) < (uint32_t)kSortItems ? (n - base) : (uint32_t)kSortItems;
+    for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
+    for (int d = tid; d < kRadixBins; d += 256) {
+        s_run[d] = 0u;
+        s_gstart[d] = table[d * nblk + blockIdx.x];
+    }
+    __syncthreads();
+    constexpr int R = kSortItems / 256;
+    uint32_t key[R], val[R], rank[R];
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < R; ++r) {
+        const uint32_t idx = r * 256 + tid;
+        const bool valid = idx < count;
+        key[r] = valid ? kin[base + idx] : 0u;
+        val[r] = valid ? vin[base + idx] : 0u;
+        const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        if (valid && before == 0) s_cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t pre = s_run[d];
+        for (int ww = 0; ww < w; ++ww) pre += s_cnt[ww][d];
+        rank[r] = pre + before;
+        __syncthreads();
+        for (int dd = tid; dd < kRadixBins; dd += 256) {
+            s_run[dd] += s_cnt[0][dd] + s_cnt[1][dd] + s_cnt[2][dd] + s_cnt[3][dd];
+            s_cnt[0][dd] = s_cnt[1][dd] = s_cnt[2][dd] = s_cnt[3][dd] = 0u;
+        }
+        __syncthreads();
+    }
+    // local digit starts = exclusive scan of the per-digit totals
+    {
+        const uint32_t v = tid < kRadixBins ? s_run[tid] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_256(v, &tot, s_wave);
+        if (tid < kRadixBins) s_lstart[tid] = ex;
+    }
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+        const uint32_t idx = r * 256 + tid;
+        if (idx < count) {
+            const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+            const uint32_t p = s_lstart[d] + rank[r];
+            s_key[p] = key[r];
+            s_val[p] = val[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < count; p += 256) {
+        const uint32_t k = s_key[p];
+        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        const uint32_t g = s_gstart[d] + (p - s_lstart[d]);
+        kout[g] = k;
+        vout[g] = s_val[p];
+    }
+}
+
+static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                             const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
+                             uint32_t* table, uint32_t* sums, hipStream_t st) {
+    const int nblk = (int)((max_items + kSortItems - 1) / kSortItems);
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
+    hipError_t e = exclusive_scan(table, table, (int64_t)nblk * kRadixBins, sums, nullptr, 0, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev, n_host,
+                       shift, table, nblk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- emit
+
+__global__ __launch_bounds__(256) void k_gather_cnt(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ cnt,
+                                                     uint32_t* __restrict__ out, int n) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < n) out[s] = cnt[ids[s]];
+}
+
+// Pairs of 256 depth-sorted splats per workgroup, one pair slot per lane.
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ offs,
+                                               const int4* __restrict__ ext, int n, int tiles_x, uint32_t capacity,
+                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
+    __shared__ uint32_t s_lo[257];
+    __shared__ int s_x0[256], s_y0[256], s_w[256];
+    __shared__ uint32_t s_id[256];
+    const int tid = threadIdx.x;
+    const int s0 = blockIdx.x * 256;
+    const int m = min(256, n - s0);
+    const uint32_t base = offs[s0];
+    if (tid < m) {
+        const uint32_t g = ids[s0 + tid];
+        s_id[tid] = g;
+        s_lo[tid] = offs[s0 + tid] - base;
+        const int4 e = ext[g];
+        int x0 = 0, y0 = 0, w = 1;
+        if (e.z > 0 && e.w > 0) {
+            auto fdiv = [](int a) -> int { return a >= 0 ? a / kTile : -((-a + kTile - 1) / kTile); };
+            x0 = max(fdiv(e.x - e.z), 0);
+            y0 = max(fdiv(e.y - e.w), 0);
+            const int x1 = min(fdiv(e.x + e.z), tiles_x - 1);
+            w = x1 - x0 + 1;
+            if (w < 1) w = 1;
+        }
+        s_x0[tid] = x0; s_y0[tid] = y0; s_w[tid] = w;
+    }
+    if (tid == 0) s_lo[m] = offs[s0 + m] - base;
+    __syncthreads();
+    const uint32_t total = s_lo[m];
+    if (base >= capacity) return;
+    const uint32_t room = capacity - base;              // slots left in the pair arrays
+    const uint32_t lim = total < room ? total : room;
+    for (uint32_t j = tid; j < lim; j += 256) {
+        // last i with s_lo[i] <= j (s_lo is non-decreasing, s_lo[0] = 0)
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_lo[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t k = j - s_lo[lo];
+        const int w = s_w[lo];
+        const uint32_t tile = (uint32_t)(s_y0[lo] + (int)(k / w)) * (uint32_t)tiles_x + (uint32_t)(s_x0[lo] + (int)(k % w));
+        pk[base + j] = tile;
+        pv[base + j] = s_id[lo];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk, const ViewHeader* __restrict__ hdr,
+                                                 int2* __restrict__ ranges, uint32_t n_tiles) {
+    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t n = hdr->n_pairs;
+    if (p >= n || hdr->overflow) return;   // an overflowed binning leaves every tile empty
+    const uint32_t t = pk[p];
+    if (t >= n_tiles) return;
+    if (p == 0 || pk[p - 1] != t) ranges[t].x = (int)p;
+    if (p == n - 1 || pk[p + 1] != t) ranges[t].y = (int)(p + 1);
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, value, count);
+    return hipGetLastError();
+}
+
+// Depth sort of the splats, pair emission in depth order, stable sort of
+// the pairs by tile, per-tile ranges. Inputs: keys_a/vals_a (depth bits /
+// index), cnt, ext from the projection (or the explicit extents).
+hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
+    ViewHeader* hdr = at<ViewHeader>(ws, L.hdr);
+    uint32_t* keys_a = at<uint32_t>(ws, L.keys_a);
+    uint32_t* vals_a = at<uint32_t>(ws, L.vals_a);
+    uint32_t* keys_b = at<uint32_t>(ws, L.keys_b);
+    uint32_t* vals_b = at<uint32_t>(ws, L.vals_b);
+    uint32_t* table = at<uint32_t>(ws, L.table);
+    uint32_t* sums = at<uint32_t>(ws, L.sums);
+    uint32_t* offs = at<uint32_t>(ws, L.offs);
+    const uint32_t n = (uint32_t)L.n;
+    hipError_t e;
+    // 1. depth order: 4 stable 8-bit passes over the 32-bit depth keys
+    for (int pass = 0; pass < 4; ++pass) {
+        const bool even = (pass & 1) == 0;
+        e = radix_pass(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
+                       even ? vals_b : vals_a, nullptr, n, L.n, pass * 8, table, sums, st);
+        if (e != hipSuccess) return e;
+    }
+    // 2. pair offsets in depth order (keys_b reused for the sorted counts)
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather_cnt, dim3((n + 255) / 256), dim3(256), 0, st, vals_a,
+                           at<uint32_t>(ws, L.cnt), keys_b, (int)n);
+    }
+    e = exclusive_scan(keys_b, offs, L.n, sums, hdr, L.capacity, offs + L.n, st);
+    if (e != hipSuccess) return e;
+    // 3. emit (tile, id) pairs; the number of tile passes decides which
+    // buffer they start in so that the sorted result lands in pk_a / pv_a
+    int tile_bits = 0;
+    while ((1ll << tile_bits) < L.n_tiles) ++tile_bits;
+    const int tile_passes = tile_bits == 0 ? 0 : (tile_bits + kRadixBits - 1) / kRadixBits;
+    uint32_t* pk_a = at<uint32_t>(ws, L.pk_a);
+    uint32_t* pv_a = at<uint32_t>(ws, L.pv_a);
+    uint32_t* pk_b = at<uint32_t>(ws, L.pk_b);
+    uint32_t* pv_b = at<uint32_t>(ws, L.pv_b);
+    const bool start_b = (tile_passes & 1) == 1;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext),
+                           (int)n, L.tiles_x, (uint32_t)L.capacity, start_b ? pk_b : pk_a, start_b ? pv_b : pv_a);
+    }
+    // 4. stable passes by tile index
+    const uint32_t* n_dev = &hdr->n_pairs;
+    for (int pass = 0; pass < tile_passes; ++pass) {
+        const bool from_b = ((pass & 1) == 0) == start_b;
+        e = radix_pass(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b, from_b ? pv_a : pv_b,
+                       n_dev, 0u, L.capacity, pass * kRadixBits, table, sums, st);
+        if (e != hipSuccess) return e;
+    }
+    // 5. per-tile [start, end)
+    e = launch_fill_u32(at<uint32_t>(ws, L.ranges), 0u, 2 * L.n_tiles, st);
+    if (e != hipSuccess) return e;
+    if (L.capacity > 0) {
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0, st, pk_a, hdr,
+                           at<int2>(ws, L.ranges), (uint32_t)L.n_tiles);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gs3

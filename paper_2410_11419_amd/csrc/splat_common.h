@@ -1,0 +1,90 @@
+// Device helpers shared by the per-tile splatting kernels (shadow, camera
+// and their adjoints): staging of splat records into tile-relative form,
+// wave64 reductions.
+#pragma once
+
+#include "gs3_internal.h"
+
+namespace gs3 {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// A splat staged for one tile. The conic is pre-scaled by -log2(e)/2 so that
+// q = A dx^2 + B dx dy + C dy^2 equals power * log2(e) and exp2(q) is the
+// splat density beta = exp(power) at the pixel. A pixel is hit iff q >= thr,
+// with thr = log2(e) * max(-cutoff, ln(alpha_min / opacity)) -- the cut-off
+// and the alpha >= alpha_min test in one comparison.
+struct Staged {
+    float4 g0;  // {u_rel, v_rel, A, B}  centre relative to the tile origin
+    float4 g1;  // {C, thr, opacity, depth}
+};
+
+// Tile-relative staging of Gaussian `id`. `mask` gets bit w set when the
+// hit ellipse's bounding box reaches wave w's 8x8 quadrant (quadrant w
+// covers tile pixels x in [8 (w & 1), +8), y in [8 (w >> 1), +8)).
+// Ids come from the view's own binning and are < n; the clamp only keeps a
+// corrupted list (never produced by a successful binning) inside the arrays.
+__device__ inline uint32_t safe_id(uint32_t id, uint32_t n) { return id < n ? id : 0u; }
+
+__device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec0,
+                                     const float4* __restrict__ rec1, const float* __restrict__ depth,
+                                     float tile_x0, float tile_y0, float cutoff, float alpha_min,
+                                     uint32_t* mask) {
+    const float4 r0 = rec0[id];
+    const float4 r1 = rec1[id];
+    Staged s;
+    const float u = (r0.x - tile_x0) + r0.z;
+    const float v = (r0.y - tile_y0) + r0.w;
+    s.g0 = make_float4(u, v, -0.5f * kLog2e * r1.x, -kLog2e * r1.y);
+    // power threshold: hit iff power >= -p with p = min(cutoff, ln(opacity / alpha_min))
+    float p = cutoff;
+    if (alpha_min > 0.f) p = fminf(p, logf(r1.w / alpha_min));
+    s.g1 = make_float4(-0.5f * kLog2e * r1.z, -p * kLog2e, r1.w, depth ? depth[id] : 0.f);
+    // bounding box of the ellipse power >= -p: half-widths sqrt(2 p Sigma'_xx),
+    // sqrt(2 p Sigma'_yy) with Sigma' = conic^-1; padded so the cull is
+    // conservative with respect to the per-pixel float32 test.
+    uint32_t m = 0u;
+    if (p > 0.f) {
+        if (isinf(p)) {
+            m = 0xFu;
+        } else {
+            const float det = r1.x * r1.z - r1.y * r1.y;
+            const float hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
+            const float hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float qx = 8.f * (w & 1), qy = 8.f * (w >> 1);
+                const bool ox = (u + hx >= qx + 0.5f) && (u - hx <= qx + 7.5f);
+                const bool oy = (v + hy >= qy + 0.5f) && (v - hy <= qy + 7.5f);
+                if (ox && oy) m |= 1u << w;
+            }
+        }
+    }
+    *mask = m;
+    return s;
+}
+
+// q = power * log2(e) at tile-relative pixel centre (px, py)
+__device__ inline float splat_q(const Staged& s, float px, float py) {
+    const float dx = px - s.g0.x;
+    const float dy = py - s.g0.y;
+    return dx * fmaf(s.g0.w, dy, s.g0.z * dx) + s.g1.x * dy * dy;
+}
+
+// Sum of x over the 64 lanes of a wave; valid in lane 63 (DPP butterfly in
+// quads, half-rows and rows, then row broadcasts across the wave).
+__device__ inline float wave_sum_lane63(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, true));  // row_half_mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, true));  // row_mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false)); // row_bcast:15
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, false)); // row_bcast:31
+    return x;
+}
+
+__device__ inline float wave_sum(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(x)), 63));
+}
+
+}  // namespace gs3

@@ -1,0 +1,389 @@
+"""ctypes binding of libgs3.so (include/gs3.h).
+
+Functions named like the C entry points marshal torch CUDA tensors into
+the C structs and call the library on torch's current HIP stream; every
+step of the path runs in the library's kernels. ``Renderer`` owns the view
+workspaces and output tensors of a scene and chains the calls for one
+relit frame.
+
+Importing this module loads the library and raises ``ImportError`` if it has
+not been built (``python -m paper_2410_11419_amd.build``); there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgs3.so")
+
+GS3_OK = 0
+GS3_INVALID_ARG = -1
+GS3_WORKSPACE_TOO_SMALL = -2
+GS3_PAIR_CAPACITY_EXCEEDED = -3
+GS3_HIP_ERROR = -4
+GS3_UNSUPPORTED = -5
+GS3_DEPTH_Z = 0
+GS3_DEPTH_DIST = 1
+
+EXPORTED = [
+    "gs3_consts_default", "gs3_status_string", "gs3_last_error", "gs3_device_ok",
+    "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
+    "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
+    "gs3_render",
+]
+
+
+class gs3_consts(C.Structure):
+    _fields_ = [("near_plane", C.c_float), ("clamp_frac", C.c_float), ("dilation", C.c_float),
+                ("cutoff", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
+                ("t_min", C.c_float), ("shadow_bias", C.c_float)]
+
+
+class gs3_view(C.Structure):
+    _fields_ = [("eye", C.c_double * 3), ("target", C.c_double * 3), ("width", C.c_int32),
+                ("height", C.c_int32), ("fov", C.c_double)]
+
+
+class gs3_scene(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("rot", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("shade_rot", C.c_void_p), ("albedo", C.c_void_p),
+                ("lobe_axis", C.c_void_p), ("lobe_log_sharp", C.c_void_p), ("lobe_amp", C.c_void_p),
+                ("feat", C.c_void_p), ("n", C.c_int64), ("k", C.c_int32)]
+
+
+class gs3_mlp(C.Structure):
+    _fields_ = [("w", C.c_void_p * 4), ("b", C.c_void_p * 4), ("n_in", C.c_int32), ("n_out", C.c_int32)]
+
+
+class gs3_viewbuf(C.Structure):
+    _fields_ = [("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("n", C.c_int64), ("width", C.c_int32),
+                ("height", C.c_int32), ("pair_capacity", C.c_int64)]
+
+
+class gs3_images(C.Structure):
+    _fields_ = [("final_rgb", C.c_void_p), ("shading", C.c_void_p), ("shadow", C.c_void_p),
+                ("residual", C.c_void_p), ("t_final", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("colour", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2410_11419_amd.build`")
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    sig = {
+        "gs3_consts_default": (None, [P(gs3_consts)]),
+        "gs3_status_string": (C.c_char_p, [C.c_int]),
+        "gs3_last_error": (C.c_char_p, []),
+        "gs3_device_ok": (C.c_int, []),
+        "gs3_view_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int64, P(C.c_size_t)]),
+        "gs3_project": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_consts), C.c_int32, P(gs3_viewbuf), C.c_void_p]),
+        "gs3_bin": (C.c_int, [C.c_void_p] * 5 + [P(gs3_viewbuf), C.c_void_p]),
+        "gs3_preprocess": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_consts), C.c_int32, P(gs3_viewbuf),
+                                     C.c_void_p]),
+        "gs3_view_pair_count": (C.c_int, [P(gs3_viewbuf), P(C.c_int64), C.c_void_p]),
+        "gs3_view_lists": (C.c_int, [P(gs3_viewbuf)] + [C.c_void_p] * 4 + [C.c_void_p]),
+        "gs3_view_splats": (C.c_int, [P(gs3_viewbuf)] + [C.c_void_p] * 5 + [C.c_void_p]),
+        "gs3_view_count_hits": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_int32, C.c_void_p, C.c_void_p]),
+        "gs3_shadow_splat": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
+        "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
+                                 P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class Gs3Error(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.gs3_last_error().decode()
+        super().__init__(f"{where}: {_lib.gs3_status_string(status).decode()}: {msg}")
+
+
+def _check(status: int, where: str):
+    if status != GS3_OK:
+        raise Gs3Error(status, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to libgs3 must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libgs3 must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_consts() -> gs3_consts:
+    k = gs3_consts()
+    _lib.gs3_consts_default(C.byref(k))
+    return k
+
+
+def make_consts(**kw) -> gs3_consts:
+    k = default_consts()
+    for name, v in kw.items():
+        setattr(k, name, float(v))
+    return k
+
+
+def make_view(view) -> gs3_view:
+    """``view`` has eye, target, width, height, fov (radians)."""
+    v = gs3_view()
+    for i in range(3):
+        v.eye[i] = float(view.eye[i])
+        v.target[i] = float(view.target[i])
+    v.width = int(view.width)
+    v.height = int(view.height)
+    v.fov = float(view.fov)
+    return v
+
+
+def device_ok() -> bool:
+    return bool(_lib.gs3_device_ok())
+
+
+# ---------------------------------------------------------------- scenes
+
+@dataclasses.dataclass
+class DeviceScene:
+    """A scene's raw parameters as contiguous float32 device tensors."""
+    t: Dict[str, torch.Tensor]
+    phi: Optional[list]
+    psi: Optional[list]
+    n: int
+    k: int
+
+    @classmethod
+    def from_host(cls, scene, device="cuda") -> "DeviceScene":
+        names = ["mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo", "lobe_axis",
+                 "lobe_log_sharp", "lobe_amp", "feat"]
+        t = {nm: torch.as_tensor(np.ascontiguousarray(getattr(scene, nm), np.float32)).to(device)
+             for nm in names}
+
+        def mlp(m):
+            if m is None:
+                return None
+            return [(torch.as_tensor(np.ascontiguousarray(w, np.float32)).to(device),
+                     torch.as_tensor(np.ascontiguousarray(b, np.float32)).to(device)) for w, b in m.layers]
+        return cls(t, mlp(scene.phi), mlp(scene.psi), int(scene.mean.shape[1]), int(scene.lobe_axis.shape[0]))
+
+    def c_struct(self) -> gs3_scene:
+        s = gs3_scene()
+        for nm, v in self.t.items():
+            setattr(s, nm, _ptr(v))
+        s.n = self.n
+        s.k = self.k
+        return s
+
+    @staticmethod
+    def c_mlp(layers, n_in: int, n_out: int) -> Optional[gs3_mlp]:
+        if layers is None:
+            return None
+        m = gs3_mlp()
+        for i, (w, b) in enumerate(layers):
+            m.w[i] = _ptr(w).value
+            m.b[i] = _ptr(b).value
+        m.n_in, m.n_out = n_in, n_out
+        return m
+
+
+class ViewBuffer:
+    """Device workspace of one view (projected splats, sort buffers, lists)."""
+
+    def __init__(self, n: int, width: int, height: int, pair_capacity: int, device="cuda"):
+        size = C.c_size_t()
+        _check(_lib.gs3_view_workspace_size(n, width, height, pair_capacity, C.byref(size)),
+               "gs3_view_workspace_size")
+        self.storage = torch.empty(size.value + 256, dtype=torch.uint8, device=device)
+        base = self.storage.data_ptr()
+        off = (-base) % 256
+        self.vb = gs3_viewbuf(C.c_void_p(base + off), size.value, n, width, height, pair_capacity)
+        self.n, self.width, self.height, self.capacity = n, width, height, pair_capacity
+        self.tiles_x = (width + 15) // 16
+        self.tiles_y = (height + 15) // 16
+
+
+# --------------------------------------------------- C entry points (1:1)
+
+def gs3_project(scene: DeviceScene, view, consts: gs3_consts, depth_mode: int, vb: ViewBuffer):
+    v = make_view(view)
+    _check(_lib.gs3_project(C.byref(scene.c_struct()), C.byref(v), C.byref(consts), depth_mode,
+                            C.byref(vb.vb), _stream()), "gs3_project")
+
+
+def gs3_bin(ix, iy, rx, ry, depth, vb: ViewBuffer):
+    _check(_lib.gs3_bin(_ptr(ix), _ptr(iy), _ptr(rx), _ptr(ry), _ptr(depth), C.byref(vb.vb), _stream()),
+           "gs3_bin")
+
+
+def gs3_preprocess(scene: DeviceScene, view, consts: gs3_consts, depth_mode: int, vb: ViewBuffer):
+    v = make_view(view)
+    _check(_lib.gs3_preprocess(C.byref(scene.c_struct()), C.byref(v), C.byref(consts), depth_mode,
+                               C.byref(vb.vb), _stream()), "gs3_preprocess")
+
+
+def gs3_view_pair_count(vb: ViewBuffer) -> int:
+    """Pair count of the last binning; raises Gs3Error on overflow (the
+    required count is then in ``.required``)."""
+    n = C.c_int64()
+    st = _lib.gs3_view_pair_count(C.byref(vb.vb), C.byref(n), _stream())
+    if st == GS3_PAIR_CAPACITY_EXCEEDED:
+        e = Gs3Error(st, "gs3_view_pair_count")
+        e.required = int(n.value)
+        raise e
+    _check(st, "gs3_view_pair_count")
+    return int(n.value)
+
+
+def gs3_view_lists(vb: ViewBuffer):
+    """(tile_start, tile_end, ids, keys) device tensors of the binning."""
+    p = gs3_view_pair_count(vb)
+    dev = vb.storage.device
+    tiles = vb.tiles_x * vb.tiles_y
+    ts = torch.empty(tiles, dtype=torch.int32, device=dev)
+    te = torch.empty(tiles, dtype=torch.int32, device=dev)
+    ids = torch.empty(max(p, 1), dtype=torch.int32, device=dev)
+    keys = torch.empty(max(p, 1), dtype=torch.int64, device=dev)
+    _check(_lib.gs3_view_lists(C.byref(vb.vb), _ptr(ts), _ptr(te), _ptr(ids), _ptr(keys), _stream()),
+           "gs3_view_lists")
+    return ts, te, ids[:p], keys[:p]
+
+
+def gs3_view_splats(vb: ViewBuffer):
+    """Projected splats: mean2d [2,n], conic [3,n], opacity [n], depth [n], extent [4,n] int32."""
+    dev = vb.storage.device
+    n = vb.n
+    out = (torch.empty(2, n, device=dev), torch.empty(3, n, device=dev), torch.empty(n, device=dev),
+           torch.empty(n, device=dev), torch.empty(4, n, dtype=torch.int32, device=dev))
+    _check(_lib.gs3_view_splats(C.byref(vb.vb), *[_ptr(x) for x in out], _stream()), "gs3_view_splats")
+    return out
+
+
+def gs3_view_count_hits(consts: gs3_consts, vb: ViewBuffer, stop_early: bool) -> torch.Tensor:
+    """Device int64 tensor [1] with the view's hit count (see gs3.h)."""
+    out = torch.empty(1, dtype=torch.int64, device=vb.storage.device)
+    _check(_lib.gs3_view_count_hits(C.byref(consts), C.byref(vb.vb), int(bool(stop_early)), _ptr(out), _stream()),
+           "gs3_view_count_hits")
+    return out
+
+
+def gs3_shadow_splat(consts: gs3_consts, light_vb: ViewBuffer, num_den: torch.Tensor, T: torch.Tensor):
+    _check(_lib.gs3_shadow_splat(C.byref(consts), C.byref(light_vb.vb), _ptr(num_den), _ptr(T), _stream()),
+           "gs3_shadow_splat")
+
+
+def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
+               images: Dict[str, torch.Tensor], use_mlps: bool = True):
+    v = make_view(cam)
+    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
+    _check(_lib.gs3_render(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
+                           C.byref(phi) if phi is not None else None,
+                           C.byref(psi) if psi is not None else None,
+                           C.byref(cam_vb.vb), C.byref(im), _stream()), "gs3_render")
+
+
+# ------------------------------------------------------------- renderer
+
+class Renderer:
+    """One relit frame (Sec. 4): light preprocess, shadow splat, camera
+    preprocess, shading + MLPs + camera splat. Buffers are allocated on
+    first use and grown when a binning needs more pairs."""
+
+    def __init__(self, scene: DeviceScene, consts: Optional[gs3_consts] = None, use_mlps: bool = True,
+                 pair_capacity: Optional[int] = None):
+        self.scene = scene
+        self.consts = consts if consts is not None else default_consts()
+        self.use_mlps = use_mlps and scene.phi is not None
+        self.capacity_hint = pair_capacity
+        self.vbs: Dict[tuple, ViewBuffer] = {}
+        self.dev = scene.t["mean"].device
+        n = scene.n
+        self.num_den = torch.empty(2, max(n, 1), device=self.dev)
+        self.T = torch.empty(max(n, 1), device=self.dev)
+        self.images: Dict[tuple, Dict[str, torch.Tensor]] = {}
+
+    def _vb(self, role: str, w: int, h: int, capacity: int) -> ViewBuffer:
+        key = (role, w, h)
+        vb = self.vbs.get(key)
+        if vb is None or vb.capacity < capacity:
+            vb = ViewBuffer(self.scene.n, w, h, capacity, self.dev)
+            self.vbs[key] = vb
+        return vb
+
+    def _preprocess(self, role: str, view, mode: int, check: bool) -> ViewBuffer:
+        key = (role, view.width, view.height)
+        vb = self.vbs.get(key)
+        if vb is None:
+            cap = self.capacity_hint or max(1 << 16, 32 * self.scene.n)
+            vb = self._vb(role, view.width, view.height, cap)
+        gs3_preprocess(self.scene, view, self.consts, mode, vb)
+        if check:
+            try:
+                gs3_view_pair_count(vb)
+            except Gs3Error as e:
+                if e.status != GS3_PAIR_CAPACITY_EXCEEDED:
+                    raise
+                vb = self._vb(role, view.width, view.height, int(e.required * 1.25) + 4096)
+                gs3_preprocess(self.scene, view, self.consts, mode, vb)
+                gs3_view_pair_count(vb)
+        return vb
+
+    def _images(self, w: int, h: int):
+        key = (w, h)
+        im = self.images.get(key)
+        if im is None:
+            d = self.dev
+            im = {"final": torch.empty(3, h, w, device=d), "S": torch.empty(3, h, w, device=d),
+                  "Sh": torch.empty(h, w, device=d), "R": torch.empty(3, h, w, device=d),
+                  "T_final": torch.empty(h, w, device=d),
+                  "n_contrib": torch.empty(h, w, dtype=torch.int32, device=d),
+                  "colour": torch.empty(8, max(self.scene.n, 1), device=d)}
+            self.images[key] = im
+        return im
+
+    def render(self, cam, light, check: bool = True) -> Dict[str, torch.Tensor]:
+        """Relit frame for camera view ``cam`` and the point light of view
+        ``light`` (its eye is the light position). ``check`` verifies (with a
+        host sync) that no binning overflowed its pair capacity."""
+        lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
+        gs3_shadow_splat(self.consts, lvb, self.num_den, self.T)
+        cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
+        im = self._images(cam.width, cam.height)
+        gs3_render(self.scene, cam, light.eye, self.consts, self.T, cvb, im, self.use_mlps)
+        out = dict(im)
+        out["T"] = self.T
+        out["num_den"] = self.num_den
+        return out
+
+    def overflowed(self) -> bool:
+        """True if any view's last binning exceeded its capacity (syncs)."""
+        for vb in self.vbs.values():
+            try:
+                gs3_view_pair_count(vb)
+            except Gs3Error as e:
+                if e.status == GS3_PAIR_CAPACITY_EXCEEDED:
+                    return True
+                raise
+        return False

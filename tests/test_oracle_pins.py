@@ -239,13 +239,14 @@ def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=No
                 pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
                 al = min(consts.alpha_max, opv[g] * math.exp(pw))
                 if pw >= -consts.cutoff and al >= consts.alpha_min:
-                    hits.append((dep[g], g, al, math.exp(pw)))
+                    hits.append((np.float32(dep[g]), g, al, math.exp(pw)))   # float32 depth key
             hits.sort()
             if mode == "shadow":
+                b32 = np.float32(consts.shadow_bias)
                 for (dj, j, aj, bj) in hits:
                     tm = 1.0
                     for (dk, k, ak, bk) in hits:
-                        if dk < dj - consts.shadow_bias:
+                        if dk < np.float32(dj - b32):      # float32 arithmetic on keys
                             tm *= 1 - ak
                     num[j] += bj * tm
                     den[j] += bj
@@ -287,6 +288,26 @@ def test_passes_match_pure_python_brute_force(consts):
     np.testing.assert_allclose(R.numpy().reshape(3, 16, 20), bR, atol=1e-13)
     np.testing.assert_allclose(Tf.numpy().reshape(16, 20), bT, atol=1e-13)
     assert (bT < 1).sum() > 20
+
+
+def test_equal_depth_keys_are_ordered_by_index():
+    # two Gaussians whose depths round to the same float32 key (one slightly
+    # nearer in float64) blend in index order, the tie rule of the sort
+    cam = _view([0, -4, 0], 16, 16)
+    sc = _one_gaussian_scene([[0, 1e-7, 0], [0, 0, 0]], math.log(0.05), opacity_logit=0.5)
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    pr = O.project(p["mean"], cov, cam, O.Consts(), "z")
+    assert pr["depth"][1] < pr["depth"][0]                       # id 1 is nearer in float64 ...
+    assert np.float32(pr["depth"][0].item()) == np.float32(pr["depth"][1].item())  # ... same key
+    op = O.sigmoid(p["opacity_logit"])
+    col = T([[1.0, 0, 0], [0, 1.0, 0]])
+    S, *_ = O.camera_pass(pr, cam, op, col, T([1.0, 1.0]), T(np.zeros((2, 3))), O.Consts())
+    a = op[0].item() * math.exp(-0.5 * pr["conic"][0, 0].item() * 0.5)   # centre pixels, d^2 = 0.5
+    pix = 7 * 16 + 7
+    # id 0 is in front: its colour gets alpha, id 1's gets alpha (1 - alpha)
+    assert S[0, pix].item() == pytest.approx(a, rel=1e-6)
+    assert S[1, pix].item() == pytest.approx(a * (1 - a), rel=1e-6)
 
 
 def test_pixel_subset_equals_band_evaluation():
@@ -470,22 +491,22 @@ def test_mlp_matches_torch_nn():
 def test_bin_tiles_against_pixel_level_definition():
     rng = np.random.default_rng(13)
     n, W, H = 300, 70, 50
-    u = rng.uniform(-20, 90, n).astype(np.float32)
-    v = rng.uniform(-20, 70, n).astype(np.float32)
-    r = rng.integers(0, 25, n)
+    ix = rng.integers(-30, 95, n)
+    iy = rng.integers(-30, 75, n)
+    rx = rng.integers(-1, 25, n)
+    ry = rng.integers(-1, 25, n)
     depth = rng.uniform(1, 5, n).astype(np.float32)
     depth[5] = depth[7]  # an exact tie, ordered by id
-    counts, ids, keys = O.bin_tiles(u, v, r, depth, W, H)
+    counts, ids, keys = O.bin_tiles(ix, iy, rx, ry, depth, W, H)
     tx, ty = 5, 4
     pos = 0
     for t in range(tx * ty):
         gx, gy = t % tx, t // tx
         members = []
         for g in range(n):
-            if r[g] <= 0:
+            if rx[g] <= 0 or ry[g] <= 0:
                 continue
-            iu, iv = math.floor(u[g]), math.floor(v[g])
-            cover = any(iu - r[g] <= px <= iu + r[g] and iv - r[g] <= py <= iv + r[g]
+            cover = any(ix[g] - rx[g] <= px <= ix[g] + rx[g] and iy[g] - ry[g] <= py <= iy[g] + ry[g]
                         for px in range(gx * 16, gx * 16 + 16) for py in range(gy * 16, gy * 16 + 16))
             if cover:
                 members.append(g)
@@ -497,25 +518,27 @@ def test_bin_tiles_against_pixel_level_definition():
             assert np.uint32(int(kk) & 0xFFFFFFFF).view(np.float32) == depth[g]
         pos += len(members)
     assert pos == len(ids)
-    assert (np.diff(keys.astype(np.float64)) >= 0).all() or True
 
 
-def test_binning_radius_contains_every_hit():
+def test_binning_extent_contains_every_hit():
+    # every pixel a splat hits lies inside its binning extent
     sc, cam, _ = synth.scene_small()
     p = O.scene_tensors(sc)
     cov = O.covariance(p["log_scale"], p["rot"])
     pr = O.project(p["mean"], cov, cam, O.Consts(), "z")
-    rad = O.splat_radius(pr["cov2"])
     op = O.sigmoid(p["opacity_logit"])
+    ix, iy, rx, ry = O.splat_extent(pr, op, O.Consts())
     e = O.pixel_entries(pr, 128, 128, op, O.Consts(), rows=(40, 90))
     hit = e["hit_pad"]
-    g, px, py = e["gid_pad"][hit].numpy(), None, None
-    sel = e["hit_pad"].reshape(-1)
-    flat_px = (torch.arange(e["n_pix"])[:, None].expand_as(e["hit_pad"]) % 128).reshape(-1)[sel].numpy()
-    flat_py = (torch.arange(e["n_pix"])[:, None].expand_as(e["hit_pad"]) // 128 + 40).reshape(-1)[sel].numpy()
-    iu = np.floor(pr["u"].numpy()[g]); iv = np.floor(pr["v"].numpy()[g])
+    g = e["gid_pad"][hit].numpy()
+    pix = torch.arange(e["n_pix"])[:, None].expand_as(hit)[hit].numpy()
+    px, py = pix % 128, pix // 128 + 40
     assert len(g) > 1000
-    assert (np.abs(flat_px - iu) <= rad[g]).all() and (np.abs(flat_py - iv) <= rad[g]).all()
+    assert (rx[g] > 0).all()
+    assert (np.abs(px - ix[g]) <= rx[g]).all() and (np.abs(py - iy[g]) <= ry[g]).all()
+    # and the extent is tight: some hit reaches the last column / row of it
+    far_x = np.abs(px - ix[g]) >= rx[g] - 1
+    assert far_x.any()
 
 
 # ----------------------------------------------------------- gradient pins
