@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
             const Staged sj = s_rec[j];
             const float q = splat_q(sj, pxc, pyc);
             bool hit = !done && q >= sj.g1.y;
-            const float al = fminf(a.alpha_max, sj.g1.z * exp2f(q));
+            const float al = fminf(a.alpha_max, sj.g1.z * fast_exp2(q));
             const float tn = T * (1.f - al);
             if (hit && tn < a.t_min) {
                 done = true;

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_count_hits(const int2* __restrict__ ran
         const float q = splat_q(s, pxc, pyc);
         if (!done && q >= s.g1.y) {
             if (stop_early) {
-                const float al = fminf(alpha_max, s.g1.z * exp2f(q));
+                const float al = fminf(alpha_max, s.g1.z * fast_exp2(q));
                 const float tn = T * (1.f - al);
                 if (tn < t_min) {
                     done = true;

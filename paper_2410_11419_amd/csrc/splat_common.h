@@ -19,13 +19,53 @@ struct Staged {
     float4 g1;  // {C, thr, opacity, depth}
 };
 
-// Tile-relative staging of Gaussian `id`. `mask` gets bit w set when the
-// hit ellipse's bounding box reaches wave w's 8x8 quadrant (quadrant w
-// covers tile pixels x in [8 (w & 1), +8), y in [8 (w >> 1), +8)).
+// Tiles a splat with extent (ix, iy, rx, ry) is binned to: those covering
+// pixel columns ix-rx..ix+rx and rows iy-ry..iy+ry (the binning rule).
+__device__ inline bool tile_rect_i(int ix, int iy, int rx, int ry, int tiles_x, int tiles_y, int* x0, int* x1,
+                                   int* y0, int* y1) {
+    if (rx <= 0 || ry <= 0) return false;
+    auto fdiv = [](long long v) -> long long { return v >= 0 ? v / kTile : -((-v + kTile - 1) / kTile); };
+    long long a0 = fdiv((long long)ix - rx), a1 = fdiv((long long)ix + rx);
+    long long b0 = fdiv((long long)iy - ry), b1 = fdiv((long long)iy + ry);
+    a0 = a0 < 0 ? 0 : a0;
+    b0 = b0 < 0 ? 0 : b0;
+    a1 = a1 > tiles_x - 1 ? tiles_x - 1 : a1;
+    b1 = b1 > tiles_y - 1 ? tiles_y - 1 : b1;
+    if (a0 > a1 || b0 > b1) return false;
+    *x0 = (int)a0; *x1 = (int)a1; *y0 = (int)b0; *y1 = (int)b1;
+    return true;
+}
+
 // Ids come from the view's own binning and are < n; the clamp only keeps a
 // corrupted list (never produced by a successful binning) inside the arrays.
 __device__ inline uint32_t safe_id(uint32_t id, uint32_t n) { return id < n ? id : 0u; }
 
+// Scaled conic and hit threshold of a splat record (shared by every kernel
+// that tests pixels against a splat, so they take identical decisions).
+// Returns p, the power threshold (hit iff power >= -p); p <= 0 never hits.
+__device__ inline float stage_coeffs(const float4 r1, float cutoff, float alpha_min, float* A, float* B, float* C,
+                                     float* thr) {
+    float p = cutoff;
+    if (alpha_min > 0.f) p = fminf(p, logf(r1.w / alpha_min));
+    *A = -0.5f * kLog2e * r1.x;
+    *B = -kLog2e * r1.y;
+    *C = -0.5f * kLog2e * r1.z;
+    *thr = -p * kLog2e;
+    return p;
+}
+
+// q = power * log2(e) for offset (dx, dy) from the splat centre; written with
+// explicit fmaf so that every kernel rounds it the same way.
+__device__ inline float quad_q(float dx, float dy, float A, float B, float C) {
+    return fmaf(dx, fmaf(B, dy, A * dx), (C * dy) * dy);
+}
+
+// Tile-relative centre of a splat for the tile whose origin is (x0, y0).
+__device__ inline float rel_centre(float hi, float lo, float origin) { return (hi - origin) + lo; }
+
+// Tile-relative staging of Gaussian `id`. `mask` gets bit w set when the
+// hit ellipse's bounding box reaches wave w's 8x8 quadrant (quadrant w
+// covers tile pixels x in [8 (w & 1), +8), y in [8 (w >> 1), +8)).
 __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec0,
                                      const float4* __restrict__ rec1, const float* __restrict__ depth,
                                      float tile_x0, float tile_y0, float cutoff, float alpha_min,
@@ -33,13 +73,12 @@ __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec
     const float4 r0 = rec0[id];
     const float4 r1 = rec1[id];
     Staged s;
-    const float u = (r0.x - tile_x0) + r0.z;
-    const float v = (r0.y - tile_y0) + r0.w;
-    s.g0 = make_float4(u, v, -0.5f * kLog2e * r1.x, -kLog2e * r1.y);
-    // power threshold: hit iff power >= -p with p = min(cutoff, ln(opacity / alpha_min))
-    float p = cutoff;
-    if (alpha_min > 0.f) p = fminf(p, logf(r1.w / alpha_min));
-    s.g1 = make_float4(-0.5f * kLog2e * r1.z, -p * kLog2e, r1.w, depth ? depth[id] : 0.f);
+    const float u = rel_centre(r0.x, r0.z, tile_x0);
+    const float v = rel_centre(r0.y, r0.w, tile_y0);
+    float A, B, C, thr;
+    const float p = stage_coeffs(r1, cutoff, alpha_min, &A, &B, &C, &thr);
+    s.g0 = make_float4(u, v, A, B);
+    s.g1 = make_float4(C, thr, r1.w, depth ? depth[id] : 0.f);
     // bounding box of the ellipse power >= -p: half-widths sqrt(2 p Sigma'_xx),
     // sqrt(2 p Sigma'_yy) with Sigma' = conic^-1; padded so the cull is
     // conservative with respect to the per-pixel float32 test.
@@ -66,10 +105,11 @@ __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec
 
 // q = power * log2(e) at tile-relative pixel centre (px, py)
 __device__ inline float splat_q(const Staged& s, float px, float py) {
-    const float dx = px - s.g0.x;
-    const float dy = py - s.g0.y;
-    return dx * fmaf(s.g0.w, dy, s.g0.z * dx) + s.g1.x * dy * dy;
+    return quad_q(px - s.g0.x, py - s.g0.y, s.g0.z, s.g0.w, s.g1.x);
 }
+
+// 2^q on the hardware exp unit (q >= thr > -126 wherever the value is used)
+__device__ inline float fast_exp2(float q) { return __builtin_amdgcn_exp2f(q); }
 
 // Sum of x over the 64 lanes of a wave; valid in lane 63 (DPP butterfly in
 // quads, half-rows and rows, then row broadcasts across the wave).

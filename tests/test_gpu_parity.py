@@ -216,7 +216,7 @@ def test_render_edge_cases(gs3):
     assert (out["T_final"] == 1).all() and (out["final"] == 0).all()
     # every Gaussian behind the camera
     back = synth.subset(sc, np.arange(300))
-    back.mean = (back.mean * 0.1 - 6.0 * cam.eye[:, None] / 4.0).astype(np.float32)
+    back.mean = (back.mean * 0.1 + 1.5 * cam.eye[:, None]).astype(np.float32)   # 2 units behind the eye
     out = gs3.Renderer(gs3.DeviceScene.from_host(back), use_mlps=False).render(cam, light)
     assert (out["T_final"] == 1).all() and (out["final"] == 0).all()
     # a one-pixel camera and a tiny light view
