@@ -28,9 +28,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# algorithmic flops of one shadow-splat hit: power (9), exp (1), alpha (2),
-# transmittance update (2), beta-weighted num/den accumulation (3)
-SHADOW_FLOPS_PER_HIT = 17
+# flops the definition spends on one (light pixel, Gaussian) hit in the
+# numerator pass: offset (2), conic quadratic (5), cut-off test (1), exp (1),
+# alpha = min(alpha_max, o * beta) (2), T_m update (2), num += beta * T_m (2)
+SHADOW_NUM_FLOPS_PER_HIT = 15
+# counter summary of the numerator kernel (HBM bytes per launch), valid while
+# the kernel's sources hash to the value recorded in it
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_shadow_num_300k_light1024.md")
+KERNEL_SOURCES = ("paper_2410_11419_amd/csrc/k_shadow.hip", "paper_2410_11419_amd/csrc/splat_common.h")
 
 
 def parse():
@@ -73,6 +78,35 @@ def frame_bytes(n, k, p_light, p_cam, cam_px):
     per_g = n * 40
     image = cam_px * 12
     return params + records + emit + sort + lists + per_g + image
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the numerator kernel from the committed
+    counter summary, or None when the kernel changed since it was taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(n):
@@ -146,8 +180,13 @@ def main():
         for i in range(args.profile_steps):
             cam, light = pairs[i % len(pairs)]
             rnd.render(cam, light, check=False)
+        # a plain copy of known size, to calibrate the HBM byte counters
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"profiled {args.profile_steps} frames")
+        print(f"profiled {args.profile_steps} frames and one {src.numel() * 4 >> 20} MiB copy")
         return
 
     # work units of each pair: pairs and hits of both views
@@ -163,8 +202,11 @@ def main():
         hits_c = int(gs3.gs3_view_count_hits(k, cvb, True).item())
         stats.append((p_l, p_c, hits_l, hits_c))
 
+    # the library launches on torch's current stream; the events are
+    # recorded on that same stream
     stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    n_ev = 7
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -173,27 +215,32 @@ def main():
         e[0].record(stream)
         lvb = rnd._preprocess("light", light, gs3.GS3_DEPTH_DIST, False)
         e[1].record(stream)
-        gs3.gs3_shadow_splat(k, lvb, rnd.num_den, rnd.T)
+        gs3.gs3_shadow_den(k, lvb, rnd.num_den)
         e[2].record(stream)
-        cvb = rnd._preprocess("cam", cam, gs3.GS3_DEPTH_Z, False)
+        gs3.gs3_shadow_num(k, lvb, rnd.num_den)
         e[3].record(stream)
-        gs3.gs3_render(ds, cam, light.eye, k, rnd.T, cvb, rnd._images(cam.width, cam.height), True)
+        gs3.gs3_shadow_resolve(lvb, rnd.num_den, rnd.T)
         e[4].record(stream)
+        cvb = rnd._preprocess("cam", cam, gs3.GS3_DEPTH_Z, False)
+        e[5].record(stream)
+        gs3.gs3_render(ds, cam, light.eye, k, rnd.T, cvb, rnd._images(cam.width, cam.height), True)
+        e[6].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if rnd.overflowed():
         raise RuntimeError("a binning exceeded its pair capacity inside the timed region")
     wall = t1 - t0
     fps = args.steps / wall
-    stage = np.zeros(4)
+    stage = np.zeros(n_ev - 1)
     for e in ev:
-        for j in range(4):
+        for j in range(n_ev - 1):
             stage[j] += e[j].elapsed_time(e[j + 1])
     stage /= args.steps                                     # ms per frame
     used = [stats[i % len(pairs)] for i in range(args.steps)]
     p_l, p_c, h_l, h_c = [float(np.mean([u[j] for u in used])) for j in range(4)]
-    t_shadow = stage[1] / 1e3
-    shadow_tflops = h_l * SHADOW_FLOPS_PER_HIT / t_shadow / 1e12
+    t_num = stage[2] / 1e3
+    num_tflops = h_l * SHADOW_NUM_FLOPS_PER_HIT / t_num / 1e12
+    traffic = profiled_traffic()
     fb = frame_bytes(sc.n, sc.k, p_l, p_c, 800 * 800)
     frame_gbs = fb / (wall / args.steps) / 1e9
     out = {
@@ -212,14 +259,15 @@ def main():
         "config": {"workload": "full relit forward: 300,000 Gaussians, 8 lobes, Phi and Psi 3x64, "
                                "camera 800x800, light 1024x1024, 40 deg fov, 4 view pairs",
                    "n_gaussians": sc.n, "camera": [800, 800], "light": [1024, 1024]},
-        "roofline": {"bound": "alu", "kernel": "k_shadow (shadow splat)",
-                     "achieved": round(shadow_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(shadow_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": None,
-                     "per_unit": f"{SHADOW_FLOPS_PER_HIT} flop per light-view hit",
-                     "units_per_launch": int(h_l), "avg_launch_ms": round(stage[1], 4)},
-        "stages_ms": {"light_preprocess": round(stage[0], 4), "shadow_splat": round(stage[1], 4),
-                      "camera_preprocess": round(stage[2], 4), "shade_mlp_render": round(stage[3], 4)},
+        "roofline": {"bound": "alu", "kernel": "k_shadow (shadow splat numerator, gs3_shadow_num)",
+                     "achieved": round(num_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(num_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": traffic,
+                     "per_unit": f"{SHADOW_NUM_FLOPS_PER_HIT} flop per light-view hit",
+                     "units_per_launch": int(h_l), "avg_launch_ms": round(stage[2], 4)},
+        "stages_ms": {"light_preprocess": round(stage[0], 4), "shadow_den": round(stage[1], 4),
+                      "shadow_num": round(stage[2], 4), "shadow_resolve": round(stage[3], 4),
+                      "camera_preprocess": round(stage[4], 4), "shade_mlp_render": round(stage[5], 4)},
         "work": {"pairs_light": int(p_l), "pairs_camera": int(p_c), "hits_light": int(h_l),
                  "hits_camera_blended": int(h_c)},
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),

@@ -236,6 +236,23 @@ int gs3_view_count_hits(const gs3_consts* consts, const gs3_viewbuf* vb, int32_t
 int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb,
                      float* num_den, float* T, gs3_stream_t stream);
 
+/* The three parts of gs3_shadow_splat (Sec. 4.2), callable one by one so
+ * that each can be timed or overlapped on its own; gs3_shadow_splat is
+ * exactly gs3_shadow_den, gs3_shadow_num, gs3_shadow_resolve in that order.
+ *   gs3_shadow_den      writes den_j = sum_m beta_jm into num_den[n .. 2n).
+ *   gs3_shadow_num      writes num_j = sum_m beta_jm T_m(j) into
+ *                       num_den[0 .. n); terms of a pixel whose transmittance
+ *                       in front of j is below 2^-20 are left out, which
+ *                       moves num_j / den_j by less than 2^-20.
+ *   gs3_shadow_resolve  T[j] = num_j / den_j, or 1 where den_j = 0.
+ * Same arguments, layout and errors as gs3_shadow_splat (T is not used by
+ * the first two and num_den is only read by the third). */
+int gs3_shadow_den(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den,
+                   gs3_stream_t stream);
+int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den,
+                   gs3_stream_t stream);
+int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float* T, gs3_stream_t stream);
+
 /* Sec. 4.1-4.3 and Fig. 2 (steps a4-a6, a9): shade every Gaussian for the
  * point light at light_pos[3] (host) seen from the camera `cam`
  * (c = rho_d f_d + sum_k amp_k G_k, Eq. 4-7, isotropic lobes, unit light),

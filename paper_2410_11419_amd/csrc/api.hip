@@ -79,6 +79,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.table = take(sizeof(uint32_t) * l.table_len);
     l.sums = take(sizeof(uint32_t) * l.scan_sums);
     l.ranges = take(sizeof(int2) * l.n_tiles);
+    l.order = take(sizeof(uint32_t) * l.n_tiles);
     l.total = off;
     *L = l;
     return true;
@@ -321,6 +322,35 @@ int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb, floa
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (L.n > 0 && (!num_den || !T)) return fail(GS3_INVALID_ARG, "num_den / T is NULL");
     GS3_CHECK_HIP(launch_shadow(*consts, L, light_vb->ws, num_den, T, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_shadow_den(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (L.n > 0 && !num_den) return fail(GS3_INVALID_ARG, "num_den is NULL");
+    GS3_CHECK_HIP(launch_shadow_den(*consts, L, light_vb->ws, num_den, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (L.n > 0 && !num_den) return fail(GS3_INVALID_ARG, "num_den is NULL");
+    GS3_CHECK_HIP(launch_shadow_num(*consts, L, light_vb->ws, num_den, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float* T, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if (L.n > 0 && (!num_den || !T)) return fail(GS3_INVALID_ARG, "num_den / T is NULL");
+    GS3_CHECK_HIP(launch_shadow_resolve(L, num_den, T, (hipStream_t)stream));
     return GS3_OK;
 }
 

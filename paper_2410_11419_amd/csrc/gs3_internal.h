@@ -40,7 +40,7 @@ struct Layout {
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
     size_t hdr = 0, rec0 = 0, rec1 = 0, depth = 0, ext = 0, cnt = 0, col0 = 0, col1 = 0;
     size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
-    size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0;
+    size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0, order = 0;
     size_t total = 0;
 };
 
@@ -89,6 +89,9 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
 hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st);
 hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws,
                          float* num_den, float* T, hipStream_t st);
+hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
+hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
+hipError_t launch_shadow_resolve(const Layout& L, const float* num_den, float* T, hipStream_t st);
 struct ShadeParams {
     float light[3];
     float eye[3];

@@ -13,6 +13,7 @@ namespace gs3 {
 
 struct RenderArgs {
     const int2* ranges;
+    const uint32_t* order;   // launch order of the tiles
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
     __shared__ float4 s_c0[256];
     __shared__ float4 s_c1[256];
     __shared__ uint32_t s_mask[256];
-    const int tile = blockIdx.x;
+    const int tile = (int)a.order[blockIdx.x];
     const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
@@ -107,6 +108,7 @@ hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, c
                          hipStream_t st) {
     RenderArgs a;
     a.ranges = at<int2>(ws, L.ranges);
+    a.order = at<uint32_t>(ws, L.order);
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);

@@ -27,9 +27,12 @@
 namespace gs3 {
 
 constexpr float kShadowEps = 9.5367431640625e-07f;   // 2^-20
+constexpr int kShadowBatch = 128;                     // list entries staged at a time
+constexpr int kRingMask = 2 * kShadowBatch - 1;       // the LDS ring holds two batches
 
 struct ShadowArgs {
     const int2* ranges;
+    const uint32_t* order;   // launch order of the tiles
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
@@ -42,80 +45,157 @@ struct ShadowArgs {
     float* den;
 };
 
-__global__ __launch_bounds__(256) void k_shadow(ShadowArgs a) {
-    __shared__ Staged s_rec[512];      // ring: list position (p - s) & 511
-    __shared__ uint32_t s_mask[512];
-    __shared__ uint32_t s_id[256];
-    __shared__ float s_part[4][256];
-    const int tile = blockIdx.x;
+// 128-bit set of batch entries (two 64-bit halves).
+struct Bits128 {
+    unsigned long long lo, hi;
+};
+__device__ inline Bits128 range_bits(int lo, int hi) {   // entries lo .. hi-1, 0 <= lo <= hi <= 128
+    auto upto = [](int k) -> unsigned long long { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); };
+    Bits128 b;
+    b.lo = upto(min(hi, 64)) & ~upto(min(lo, 64));
+    b.hi = upto(max(hi - 64, 0)) & ~upto(max(lo - 64, 0));
+    return b;
+}
+__device__ inline int first_bit(const Bits128& b) {
+    return b.lo ? __builtin_ctzll(b.lo) : 64 + __builtin_ctzll(b.hi);
+}
+__device__ inline void clear_bit(Bits128& b, int k) {
+    if (k < 64) b.lo &= ~(1ull << k); else b.hi &= ~(1ull << (k - 64));
+}
+
+// One wave per (tile, 8x8 quadrant): the four quadrants of a light tile run
+// as independent single-wave workgroups, one pixel per lane. The wave stages
+// its tile's list 128 entries at a time into an LDS ring that also keeps the
+// previous batch for the trailing pointer; a ballot marks the entries whose
+// hit ellipse can reach the quadrant, and both pointers visit only those, so
+// the wave's sequential chain is as short as its quadrant allows. For each
+// lead entry j, L(j) (the first list position not more than `bias` closer to
+// the light) comes from a binary search over the ring's distances; when it
+// lies before the ring the trailing pointer walks and compares instead. The
+// wave exits when all its pixels are dark.
+__global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
+    __shared__ Staged s_rec[2 * kShadowBatch];
+    __shared__ uint32_t s_id[2 * kShadowBatch];
+    const int tile = (int)a.order[blockIdx.x >> 2];
+    const int qd = blockIdx.x & 3;
     const int2 rg = a.ranges[tile];
     const int s = rg.x, e = rg.y;
-    if (e <= s) return;  // uniform
-    const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
+    if (e <= s) return;
+    const int lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
-    const bool inside = (tx * kTile + lx < a.width) && (ty * kTile + ly < a.height);
+    const int lx = (qd & 1) * 8 + (lane & 7), ly = (qd >> 1) * 8 + (lane >> 3);
     const float pxc = lx + 0.5f, pyc = ly + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
-    const uint32_t wbit = 1u << w;
-    float t_trail = 1.f;
-    bool alive = inside;
+    bool alive = (tx * kTile + lx < a.width) && (ty * kTile + ly < a.height);
+    if (!__ballot(alive)) return;
+    const uint32_t qbit = 1u << qd;
+    float tt = 1.f;
+    Bits128 cur{0ull, 0ull}, prv{0ull, 0ull};
     int trail = s;
-    for (int b = s; b < e; b += 256) {
-        if (__syncthreads_count(alive) == 0) break;   // every pixel of the tile is dark
-        const int m = min(256, e - b);
-        const int base = (b - s) & 511;
-        if (tid < m) {
-            const uint32_t id = safe_id(a.list[b + tid], a.n);
-            uint32_t mk;
-            s_rec[base + tid] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff, a.alpha_min, &mk);
-            s_mask[base + tid] = mk;
-            s_id[tid] = id;
-        }
+    // multiply (1 - alpha) of occluder k into tt where it hits
+    auto occlude = [&](const Staged& k) {
+        const float q = splat_q(k, pxc, pyc);
+        if (alive && q >= k.g1.y) tt *= 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
+    };
+    for (int b = s; b < e; b += kShadowBatch) {
+        const int m = min(kShadowBatch, e - b);
+        const int base = (b - s) & kRingMask;          // ring slot of entry b
+        bool qm[2];
 #pragma unroll
-        for (int ww = 0; ww < 4; ++ww) s_part[ww][tid] = 0.f;
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            qm[h] = false;
+            if (jj < m) {
+                uint32_t mk;
+                const uint32_t id = safe_id(a.list[b + jj], a.n);
+                s_rec[base + jj] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                               a.alpha_min, &mk);
+                s_id[base + jj] = id;
+                qm[h] = (mk & qbit) != 0u;
+            }
+        }
+        cur.lo = __ballot(qm[0]);
+        cur.hi = __ballot(qm[1]);
         __syncthreads();
-        if (__ballot(alive)) {
-            for (int j = 0; j < m; ++j) {
-                const float thr_d = s_rec[base + j].g1.w - a.bias;
-                // trailing pointer: every k with dist_k < dist_j - bias shadows j
-                while (trail < b + j) {
-                    Staged tk;
-                    uint32_t tm;
-                    if (trail >= b - 256) {
-                        tk = s_rec[(trail - s) & 511];
-                        tm = s_mask[(trail - s) & 511];
-                    } else {
-                        tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0, tile_y0,
-                                         a.cutoff, a.alpha_min, &tm);
+        // L(j) for the lane's two entries: the first position in
+        // [lo_pos, b + j) whose distance is not below dist_j - bias (b + j
+        // if none); -1 when it lies before the ring
+        const int lo_pos = max(s, b - kShadowBatch);
+        int Lh[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            Lh[h] = b + min(jj, m);
+            if (jj < m) {
+                const float thr = s_rec[base + jj].g1.w - a.bias;
+                if (lo_pos > s && !(s_rec[(lo_pos - s) & kRingMask].g1.w < thr)) {
+                    Lh[h] = -1;
+                } else {
+                    int lo = lo_pos, hi = b + jj;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_rec[(mid - s) & kRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
                     }
-                    if (!(tk.g1.w < thr_d)) break;
-                    if (tm & wbit) {
-                        const float q = splat_q(tk, pxc, pyc);
-                        if (alive && q >= tk.g1.y) t_trail *= 1.f - fminf(a.alpha_max, tk.g1.z * fast_exp2(q));
-                    }
-                    ++trail;
-                }
-                alive = alive && t_trail >= kShadowEps;
-                if (!__ballot(alive)) break;       // the wave's pixels are all dark
-                const Staged sj = s_rec[base + j];
-                const uint32_t mj = s_mask[base + j];
-                if (mj & wbit) {
-                    const float q = splat_q(sj, pxc, pyc);
-                    const bool hit = alive && q >= sj.g1.y;
-                    if (__ballot(hit)) {
-                        const float vn = hit ? fast_exp2(q) * t_trail : 0.f;
-                        const float sn = wave_sum_lane63(vn);
-                        if (lane == 63) s_part[w][j] = sn;
-                    }
+                    Lh[h] = lo;
                 }
             }
         }
-        __syncthreads();
-        if (tid < m) {
-            const float v = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
-            if (v > 0.f) atomicAdd(&a.num[s_id[tid]], v);
+        Bits128 todo = cur;
+        while (todo.lo | todo.hi) {
+            const int j = first_bit(todo);
+            clear_bit(todo, j);
+            const Staged sj = s_rec[base + j];
+            const int L0 = __builtin_amdgcn_readlane(Lh[0], j & 63);
+            const int L1 = __builtin_amdgcn_readlane(Lh[1], j & 63);
+            const int Lj = j < 64 ? L0 : L1;
+            const float thr_d = sj.g1.w - a.bias;
+            const int stop = Lj >= 0 ? Lj : b + j;
+            while (trail < stop) {
+                if (trail < lo_pos) {
+                    // older than the ring: re-stage from global memory
+                    uint32_t mk;
+                    const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
+                                                  tile_y0, a.cutoff, a.alpha_min, &mk);
+                    if (Lj < 0 && !(tk.g1.w < thr_d)) break;
+                    if (mk & qbit) occlude(tk);
+                    ++trail;
+                    continue;
+                }
+                // ring entries of one batch, only those that reach the quadrant
+                const bool in_cur = trail >= b;
+                const int bstart = in_cur ? b : b - kShadowBatch;
+                const int lo = trail - bstart, hi = min(stop - bstart, kShadowBatch);
+                Bits128 rel = range_bits(lo, hi);
+                const Bits128 msk = in_cur ? cur : prv;
+                rel.lo &= msk.lo;
+                rel.hi &= msk.hi;
+                bool stopped = false;
+                while (rel.lo | rel.hi) {
+                    const int k = first_bit(rel);
+                    clear_bit(rel, k);
+                    const Staged tk = s_rec[(bstart + k - s) & kRingMask];
+                    if (Lj < 0 && !(tk.g1.w < thr_d)) {
+                        trail = bstart + k;
+                        stopped = true;
+                        break;
+                    }
+                    occlude(tk);
+                }
+                if (stopped) break;
+                trail = bstart + hi;
+            }
+            alive = alive && tt >= kShadowEps;
+            if (!__ballot(alive)) return;          // every pixel of the quadrant is dark
+            const float q = splat_q(sj, pxc, pyc);
+            const bool hit = alive && q >= sj.g1.y;
+            if (__ballot(hit)) {
+                const float v = hit ? fast_exp2(q) * tt : 0.f;
+                const float sn = wave_sum_lane63(v);
+                if (lane == 63) atomicAdd(&a.num[s_id[base + j]], sn);
+            }
         }
+        prv = cur;
+        __syncthreads();
     }
 }
 
@@ -179,13 +259,10 @@ __global__ __launch_bounds__(256) void k_shadow_finish(const float* __restrict__
     if (i < n) T[i] = den[i] > 0.f ? num[i] / den[i] : 1.f;
 }
 
-hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, float* T,
-                         hipStream_t st) {
-    if (L.n == 0) return hipSuccess;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(num_den), 0u, L.n, st);
-    if (e != hipSuccess) return e;
+static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* ws, float* num_den) {
     ShadowArgs a;
     a.ranges = at<int2>(ws, L.ranges);
+    a.order = at<uint32_t>(ws, L.order);
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);
@@ -201,13 +278,39 @@ hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws, f
     a.bias = k.shadow_bias;
     a.num = num_den;
     a.den = num_den + L.n;
-    int den_grid = (int)((L.n + 3) / 4);
-    if (den_grid > 8192) den_grid = 8192;
-    hipLaunchKernelGGL(k_shadow_den, dim3(den_grid), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_shadow, dim3((unsigned)L.n_tiles), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, a.num, a.den, T,
-                       (int)L.n);
+    return a;
+}
+
+hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st) {
+    if (L.n == 0) return hipSuccess;
+    int grid = (int)((L.n + 3) / 4);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_shadow_den, dim3(grid), dim3(256), 0, st, shadow_args(k, L, ws, num_den));
     return hipGetLastError();
+}
+
+hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st) {
+    if (L.n == 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(num_den), 0u, L.n, st);
+    if (e != hipSuccess) return e;
+    if (L.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shadow, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, shadow_args(k, L, ws, num_den));
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow_resolve(const Layout& L, const float* num_den, float* T, hipStream_t st) {
+    if (L.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, num_den,
+                       num_den + L.n, T, (int)L.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, float* T,
+                         hipStream_t st) {
+    hipError_t e = launch_shadow_den(k, L, ws, num_den, st);
+    if (e == hipSuccess) e = launch_shadow_num(k, L, ws, num_den, st);
+    if (e == hipSuccess) e = launch_shadow_resolve(L, num_den, T, st);
+    return e;
 }
 
 }  // namespace gs3

@@ -305,6 +305,41 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk,
     if (p == n - 1 || pk[p + 1] != t) ranges[t].y = (int)(p + 1);
 }
 
+// Launch order of the tiles: longest list first (lengths bucketed by 8), so
+// the few long tiles start early instead of forming the tail of the
+// splatting kernels. Only the schedule depends on it, not any result.
+__global__ __launch_bounds__(1024) void k_tile_order(const int2* __restrict__ ranges, int n_tiles,
+                                                      uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[1024];
+    __shared__ uint32_t s_wave[16];
+    const int tid = threadIdx.x;
+    hist[tid] = 0u;
+    __syncthreads();
+    auto bucket = [&](int t) -> int {
+        const int2 r = ranges[t];
+        const int len = r.y - r.x;
+        return 1023 - min(1023, max(len, 0) >> 3);
+    };
+    for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&hist[bucket(t)], 1u);
+    __syncthreads();
+    // exclusive scan of the 1024 bucket counts
+    const uint32_t v = hist[tid];
+    uint32_t x = v;
+    const int lane = __lane_id(), w = tid >> 6;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wave[w] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int i = 0; i < w; ++i) pre += s_wave[i];
+    __syncthreads();
+    hist[tid] = pre + x - v;
+    __syncthreads();
+    for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, value, count);
@@ -368,6 +403,8 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0, st, pk_a, hdr,
                            at<int2>(ws, L.ranges), (uint32_t)L.n_tiles);
     }
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles,
+                       at<uint32_t>(ws, L.order));
     return hipGetLastError();
 }
 

@@ -103,6 +103,47 @@ __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec
     return s;
 }
 
+// Row-group mask of a staged splat: bit r set when the hit ellipse's
+// bounding box (padded like stage_splat's) reaches tile rows 4r .. 4r+3.
+__device__ inline uint32_t rowgroup_mask(const float4 r1, float v, float p) {
+    if (!(p > 0.f)) return 0u;
+    if (isinf(p)) return 0xFu;
+    const float det = r1.x * r1.z - r1.y * r1.y;
+    const float hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float y0 = 4.f * r;
+        if (v + hy >= y0 + 0.5f && v - hy <= y0 + 3.5f) m |= 1u << r;
+    }
+    return m;
+}
+
+// Stage splat `id` for the tile with origin (tile_x0, tile_y0): the record
+// and its row-group mask (bit r: the splat can hit tile rows 4r..4r+3; 0 if
+// its bounding box misses the tile's columns).
+__device__ inline Staged stage_rows(uint32_t id, const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+                                    const float* __restrict__ depth, float tile_x0, float tile_y0, float cutoff,
+                                    float alpha_min, uint32_t* mask) {
+    const float4 r0 = rec0[id];
+    const float4 r1 = rec1[id];
+    Staged s;
+    const float u = rel_centre(r0.x, r0.z, tile_x0);
+    const float v = rel_centre(r0.y, r0.w, tile_y0);
+    float A, B, C, thr;
+    const float p = stage_coeffs(r1, cutoff, alpha_min, &A, &B, &C, &thr);
+    s.g0 = make_float4(u, v, A, B);
+    s.g1 = make_float4(C, thr, r1.w, depth ? depth[id] : 0.f);
+    uint32_t m = rowgroup_mask(r1, v, p);
+    if (m && !isinf(p)) {
+        const float det = r1.x * r1.z - r1.y * r1.y;
+        const float hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
+        if (u + hx < 0.5f || u - hx > 15.5f) m = 0u;
+    }
+    *mask = m;
+    return s;
+}
+
 // q = power * log2(e) at tile-relative pixel centre (px, py)
 __device__ inline float splat_q(const Staged& s, float px, float py) {
     return quad_q(px - s.g0.x, py - s.g0.y, s.g0.z, s.g0.w, s.g1.x);

@@ -36,7 +36,7 @@ EXPORTED = [
     "gs3_consts_default", "gs3_status_string", "gs3_last_error", "gs3_device_ok",
     "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
-    "gs3_render",
+    "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
 ]
 
 
@@ -93,6 +93,9 @@ def _load():
         "gs3_view_splats": (C.c_int, [P(gs3_viewbuf)] + [C.c_void_p] * 5 + [C.c_void_p]),
         "gs3_view_count_hits": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_int32, C.c_void_p, C.c_void_p]),
         "gs3_shadow_splat": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
+        "gs3_shadow_den": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
+        "gs3_shadow_num": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
+        "gs3_shadow_resolve": (C.c_int, [P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
         "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
                                  P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
     }
@@ -289,6 +292,18 @@ def gs3_view_count_hits(consts: gs3_consts, vb: ViewBuffer, stop_early: bool) ->
 def gs3_shadow_splat(consts: gs3_consts, light_vb: ViewBuffer, num_den: torch.Tensor, T: torch.Tensor):
     _check(_lib.gs3_shadow_splat(C.byref(consts), C.byref(light_vb.vb), _ptr(num_den), _ptr(T), _stream()),
            "gs3_shadow_splat")
+
+
+def gs3_shadow_den(consts: gs3_consts, light_vb: ViewBuffer, num_den: torch.Tensor):
+    _check(_lib.gs3_shadow_den(C.byref(consts), C.byref(light_vb.vb), _ptr(num_den), _stream()), "gs3_shadow_den")
+
+
+def gs3_shadow_num(consts: gs3_consts, light_vb: ViewBuffer, num_den: torch.Tensor):
+    _check(_lib.gs3_shadow_num(C.byref(consts), C.byref(light_vb.vb), _ptr(num_den), _stream()), "gs3_shadow_num")
+
+
+def gs3_shadow_resolve(light_vb: ViewBuffer, num_den: torch.Tensor, T: torch.Tensor):
+    _check(_lib.gs3_shadow_resolve(C.byref(light_vb.vb), _ptr(num_den), _ptr(T), _stream()), "gs3_shadow_resolve")
 
 
 def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
