@@ -155,6 +155,27 @@ typedef struct {
     float* colour;     /* [8][n] */
 } gs3_images;
 
+/* Gradients written by gs3_render_backward: device pointers with the
+ * layouts of gs3_scene (raw parameters) and gs3_mlp. Every call ADDS to
+ * them (zero them once per optimisation step; a batch of views accumulates).
+ * The MLP pointers of a NULL phi / psi are not used. */
+typedef struct gs3_grads {
+    float* mean;           /* [3][n] */
+    float* log_scale;      /* [3][n] */
+    float* rot;            /* [4][n] */
+    float* opacity_logit;  /* [n] */
+    float* shade_rot;      /* [4][n] */
+    float* albedo;         /* [3][n] */
+    float* lobe_axis;      /* [k][3][n] */
+    float* lobe_log_sharp; /* [k][n] */
+    float* lobe_amp;       /* [k][3][n] */
+    float* feat;           /* [16][n] */
+    float* phi_w[4];       /* like gs3_mlp.w of phi */
+    float* phi_b[4];
+    float* psi_w[4];
+    float* psi_b[4];
+} gs3_grads;
+
 void gs3_consts_default(gs3_consts* out);
 const char* gs3_status_string(int status);
 const char* gs3_last_error(void);
@@ -266,6 +287,36 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam,
                const float* T, const gs3_mlp* phi, const gs3_mlp* psi,
                const gs3_viewbuf* cam_vb, const gs3_images* out,
                gs3_stream_t stream);
+
+/* Bytes of device workspace gs3_render_backward needs for n Gaussians and
+ * a light image of light_width x light_height: per-Gaussian splat and
+ * colour gradients, per-light-pixel sums, and the MLP activations kept for
+ * the weight gradients (about 3.3 KB per Gaussian with both MLPs). */
+int gs3_backward_workspace_size(int64_t n, int32_t light_width, int32_t light_height, size_t* bytes);
+
+/* Sec. 4.4 (training by gradient descent on an image loss): the adjoint of
+ * gs3_shadow_splat followed by gs3_render. Given dL_dfinal [3][H][W] (the
+ * gradient of a loss with respect to the camera image `final`), ADDS dL/d
+ * of every raw scene parameter and MLP weight to `grads`.
+ * Inputs are the forward's, unchanged since it ran: `light` and `cam` the
+ * two views (light->eye is the light position), `light_vb` / `cam_vb`
+ * their preprocessed buffers (light with GS3_DEPTH_DIST, cam with
+ * GS3_DEPTH_Z; cam_vb also holds the per-Gaussian colours gs3_render left
+ * there), T and num_den from gs3_shadow_splat, and fwd->shading, ->shadow,
+ * ->residual from gs3_render (the other image pointers are not used).
+ * Nothing per (pixel, splat) pair is stored by the forward: the splats are
+ * recomputed per tile with the forward's arithmetic, so the gradient is that
+ * of the function the forward evaluated (threshold decisions fixed). Terms
+ * of light rays with transmittance below 2^-20, which the forward numerator
+ * leaves out, are left out here as well. `ws` (256-byte aligned,
+ * gs3_backward_workspace_size bytes) is scratch. Errors: GS3_INVALID_ARG
+ * for NULL or mismatched arguments, GS3_WORKSPACE_TOO_SMALL. */
+int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
+                        const gs3_consts* consts, const float* T, const float* num_den,
+                        const gs3_mlp* phi, const gs3_mlp* psi,
+                        const gs3_viewbuf* light_vb, const gs3_viewbuf* cam_vb,
+                        const gs3_images* fwd, const float* dL_dfinal,
+                        const gs3_grads* grads, void* ws, size_t ws_bytes, gs3_stream_t stream);
 
 #ifdef __cplusplus
 }

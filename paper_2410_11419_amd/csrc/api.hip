@@ -385,4 +385,123 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_
     return GS3_OK;
 }
 
+// Backward workspace: per-Gaussian splat gradients of both views, colour
+// gradients, dL/dT, dL/dnum, per-light-pixel sums, the MLP scratch rows and
+// the weight-gradient partial sums.
+struct BwdLayout {
+    size_t gcam, gcol, glight, dT, dnum, gray, rows, partial, total;
+};
+static bool bwd_layout(int64_t n, int32_t lw, int32_t lh, BwdLayout* B) {
+    if (n < 0 || n >= (int64_t(1) << 31) || lw <= 0 || lh <= 0 || lw > 16384 || lh > 16384) return false;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t nn = (size_t)n;
+    const int64_t chunks = (n + kWgChunkHost - 1) / kWgChunkHost;
+    B->gcam = take(4 * 6 * nn);
+    B->gcol = take(4 * 7 * nn);
+    B->glight = take(4 * 6 * nn);
+    B->dT = take(4 * nn);
+    B->dnum = take(4 * nn);
+    B->gray = take(4 * (size_t)lw * lh);
+    B->rows = take(4 * (size_t)mlp_scratch_rows() * nn);
+    B->partial = take(4 * (size_t)chunks * wgrad_total_params(true, true));
+    B->total = off;
+    return true;
+}
+
+int gs3_backward_workspace_size(int64_t n, int32_t light_width, int32_t light_height, size_t* bytes) {
+    if (!bytes) return fail(GS3_INVALID_ARG, "bytes is NULL");
+    BwdLayout B;
+    if (!bwd_layout(n, light_width, light_height, &B))
+        return fail(GS3_INVALID_ARG, "invalid sizes (n=%lld, light %dx%d)", (long long)n, light_width, light_height);
+    *bytes = B.total;
+    return GS3_OK;
+}
+
+static int proj_params(const gs3_view* v, const Layout& L, int depth_mode, const gs3_consts* k, ViewParams* vp) {
+    int st = view_params(v, L, depth_mode, vp);
+    if (st != GS3_OK) return st;
+    vp->lim_x = k->clamp_frac * ((v->width / 2.0) / vp->focal);
+    vp->lim_y = k->clamp_frac * ((v->height / 2.0) / vp->focal);
+    return GS3_OK;
+}
+
+int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
+                        const gs3_consts* consts, const float* T, const float* num_den, const gs3_mlp* phi,
+                        const gs3_mlp* psi, const gs3_viewbuf* light_vb, const gs3_viewbuf* cam_vb,
+                        const gs3_images* fwd, const float* dL_dfinal, const gs3_grads* grads, void* ws,
+                        size_t ws_bytes, gs3_stream_t stream) {
+    Layout Lc, Ll;
+    int st;
+    if ((st = check_vb(cam_vb, &Lc)) != GS3_OK) return st;
+    if ((st = check_vb(light_vb, &Ll)) != GS3_OK) return st;
+    if ((st = check_scene(scene, true)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (scene->n != cam_vb->n || scene->n != light_vb->n)
+        return fail(GS3_INVALID_ARG, "scene.n differs from a view buffer's n");
+    ViewParams vpc, vpl;
+    if ((st = proj_params(cam, Lc, GS3_DEPTH_Z, consts, &vpc)) != GS3_OK) return st;
+    if ((st = proj_params(light, Ll, GS3_DEPTH_DIST, consts, &vpl)) != GS3_OK) return st;
+    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
+    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    if (!fwd || !fwd->shading || !fwd->shadow || !fwd->residual)
+        return fail(GS3_INVALID_ARG, "forward images (shading, shadow, residual) missing");
+    if (scene->n > 0 && (!T || !num_den)) return fail(GS3_INVALID_ARG, "T / num_den is NULL");
+    if (!dL_dfinal) return fail(GS3_INVALID_ARG, "dL_dfinal is NULL");
+    if (!grads || !grads->mean || !grads->log_scale || !grads->rot || !grads->opacity_logit || !grads->shade_rot ||
+        !grads->albedo || !grads->lobe_axis || !grads->lobe_log_sharp || !grads->lobe_amp || !grads->feat)
+        return fail(GS3_INVALID_ARG, "a scene gradient pointer is NULL");
+    for (int i = 0; i < 4; ++i) {
+        if (phi && (!grads->phi_w[i] || !grads->phi_b[i])) return fail(GS3_INVALID_ARG, "phi gradient pointer is NULL");
+        if (psi && (!grads->psi_w[i] || !grads->psi_b[i])) return fail(GS3_INVALID_ARG, "psi gradient pointer is NULL");
+    }
+    BwdLayout B;
+    if (!bwd_layout(scene->n, light->width, light->height, &B)) return fail(GS3_INVALID_ARG, "invalid sizes");
+    if (!ws) return fail(GS3_INVALID_ARG, "ws is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GS3_INVALID_ARG, "ws not 256-byte aligned");
+    if (ws_bytes < B.total)
+        return fail(GS3_WORKSPACE_TOO_SMALL, "backward workspace has %zu bytes, needs %zu", ws_bytes, B.total);
+    if (scene->n == 0) return GS3_OK;
+    hipStream_t s = (hipStream_t)stream;
+    float* gcam = at<float>(ws, B.gcam);
+    float* gcol = at<float>(ws, B.gcol);
+    float* glight = at<float>(ws, B.glight);
+    float* dT = at<float>(ws, B.dT);
+    float* dnum = at<float>(ws, B.dnum);
+    float* gray = at<float>(ws, B.gray);
+    float* rows = at<float>(ws, B.rows);
+    float* partial = at<float>(ws, B.partial);
+    const int64_t n = scene->n;
+    GS3_CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(gcam), 0u, 6 * n, s));
+    GS3_CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(gcol), 0u, 7 * n, s));
+    GradDev g;
+    g.mean = grads->mean;
+    g.log_scale = grads->log_scale;
+    g.rot = grads->rot;
+    g.opacity_logit = grads->opacity_logit;
+    g.shade_rot = grads->shade_rot;
+    g.albedo = grads->albedo;
+    g.lobe_axis = grads->lobe_axis;
+    g.lobe_log_sharp = grads->lobe_log_sharp;
+    g.lobe_amp = grads->lobe_amp;
+    g.feat = grads->feat;
+    ShadeParams sp;
+    for (int i = 0; i < 3; ++i) {
+        sp.light[i] = (float)light->eye[i];
+        sp.eye[i] = (float)cam->eye[i];
+    }
+    sp.use_phi = phi != nullptr;
+    sp.use_psi = psi != nullptr;
+    const SceneDev sd = scene_dev(scene);
+    GS3_CHECK_HIP(launch_render_bwd(*consts, Lc, cam_vb->ws, *fwd, dL_dfinal, gcam, gcol, s));
+    GS3_CHECK_HIP(launch_shade_bwd(sd, sp, T, phi, psi, gcol, dT, g, rows, partial, grads, s));
+    GS3_CHECK_HIP(launch_shadow_bwd(*consts, Ll, light_vb->ws, T, num_den, dT, dnum, gray, glight, s));
+    GS3_CHECK_HIP(launch_project_bwd(sd, vpc, vpl, *consts, gcam, glight, g, s));
+    return GS3_OK;
+}
+
 }  // extern "C"

@@ -102,6 +102,33 @@ hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const flo
                             void* ws, float* colour_out, hipStream_t st);
 hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws,
                          const gs3_images& out, hipStream_t st);
+// Device pointers of the scene gradients (+=), mirror of SceneDev.
+struct GradDev {
+    float* mean;
+    float* log_scale;
+    float* rot;
+    float* opacity_logit;
+    float* shade_rot;
+    float* albedo;
+    float* lobe_axis;
+    float* lobe_log_sharp;
+    float* lobe_amp;
+    float* feat;
+};
+int mlp_scratch_rows();
+int wgrad_total_params(bool phi, bool psi);
+constexpr int kWgChunkHost = 1024;   // Gaussians per weight-gradient partial sum
+hipError_t launch_render_bwd(const gs3_consts& k, const Layout& L, const void* ws, const gs3_images& fwd,
+                             const float* dF, float* gsplat, float* gcol, hipStream_t st);
+hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* ws, const float* T,
+                             const float* num_den, const float* dT, float* dnum, float* gray, float* gsplat,
+                             hipStream_t st);
+hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                            const gs3_mlp* psi, const float* gcol, float* dT, const GradDev& g, float* rows,
+                            float* partial, const gs3_grads* gr, hipStream_t st);
+hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const ViewParams& light,
+                              const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
+                              hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, int32_t* end, int32_t* ids,
                                uint64_t* keys, hipStream_t st);

@@ -1,0 +1,641 @@
+// Per-Gaussian adjoints: shading (Sec. 4.1, Eq. 4-7), the MLPs Phi (Sec.
+// 4.2, Eq. 8) and Psi (Sec. 4.3), their weight gradients, and the EWA
+// projection (Sec. 3, Eq. 1) of both views.
+#include "mlp_common.h"
+
+namespace gs3 {
+
+constexpr float kLog2eF = 1.4426950408889634f;
+
+// Rows of the per-Gaussian MLP scratch ([row][n] floats): the layer inputs
+// and the pre-activation gradients the weight gradients are formed from.
+struct MlpRows {
+    int x, h1, h2, h3, dz1, dz2, dz3, dz4, size;
+};
+__host__ __device__ constexpr MlpRows mlp_rows(int base, int n_in, int n_out) {
+    return MlpRows{base,           base + n_in,           base + n_in + 64,      base + n_in + 128,
+                   base + n_in + 192, base + n_in + 256, base + n_in + 320,     base + n_in + 384,
+                   n_in + 384 + n_out};
+}
+constexpr MlpRows kPhiRows = mlp_rows(0, kPhiIn, 1);
+constexpr MlpRows kPsiRows = mlp_rows(kPhiRows.size, kPsiIn, 3);
+constexpr int kMlpRows = kPhiRows.size + kPsiRows.size;
+int mlp_scratch_rows() { return kMlpRows; }
+
+constexpr MlpTSmem kPhiT = mlp_tsmem(kShadeSmem);
+constexpr MlpTSmem kPsiT = mlp_tsmem(kShadeSmem + kPhiT.size);
+constexpr int kShadeBwdSmem = kShadeSmem + kPhiT.size + kPsiT.size;
+static_assert(kShadeBwdSmem * 4 <= 160 * 1024, "shading adjoint LDS exceeds 160 KiB");
+
+struct ShadeBwdArgs {
+    SceneDev sc;
+    float light[3];
+    float eye[3];
+    int use_phi, use_psi;
+    const float* T;
+    MlpArgs phi, psi;
+    const float* gcol;   // [7][n] dL/d{c.rgb, T', r.rgb}
+    float* dT;           // [n] = dL/dT
+    GradDev g;           // += scene gradients (shading part)
+    float* rows;         // [kMlpRows][n] MLP scratch
+};
+
+// Adjoint of the quaternion -> rotation map (q normalised inside): dR -> dq.
+__device__ inline void quat_grad(float qw, float qx, float qy, float qz, float qn, const float dR[9], float dq[4]) {
+    // (qw..qz) is the normalised quaternion, qn the raw norm
+    const float g00 = dR[0], g01 = dR[1], g02 = dR[2], g10 = dR[3], g11 = dR[4], g12 = dR[5], g20 = dR[6],
+                g21 = dR[7], g22 = dR[8];
+    const float dw = 2.f * (-qz * g01 + qy * g02 + qz * g10 - qx * g12 - qy * g20 + qx * g21);
+    const float dx = 2.f * (qy * g01 + qz * g02 + qy * g10 - 2.f * qx * g11 - qw * g12 + qz * g20 + qw * g21 -
+                            2.f * qx * g22);
+    const float dy = 2.f * (-2.f * qy * g00 + qx * g01 + qw * g02 + qx * g10 + qz * g12 - qw * g20 + qz * g21 -
+                            2.f * qy * g22);
+    const float dz = 2.f * (-2.f * qz * g00 - qw * g01 + qx * g02 + qw * g10 - 2.f * qz * g11 + qy * g12 +
+                            qx * g20 + qy * g21);
+    const float dot = dw * qw + dx * qx + dy * qy + dz * qz;
+    const float inv = 1.f / qn;
+    dq[0] = (dw - dot * qw) * inv;
+    dq[1] = (dx - dot * qx) * inv;
+    dq[2] = (dy - dot * qy) * inv;
+    dq[3] = (dz - dot * qz) * inv;
+}
+
+// Store a D-layout 64-vector of one Gaussian into scratch rows row0 ..
+// row0 + 63: lane (g, q) writes rows row0 + 16 m + 4 q + i. The per-lane
+// base is formed once; the row offsets (16 m + i) n are wave-uniform.
+__device__ inline void store_rows(float* rows, int row0, int q, int g, int n, const floatx4 v[4]) {
+    float* p = rows + (size_t)(row0 + 4 * q) * n + g;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[(size_t)(16 * m + i) * n] = v[m][i];
+}
+
+__global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
+    __shared__ float sm[kShadeBwdSmem];
+    const SceneDev& sc = a.sc;
+    const int n = sc.n;
+    if (a.use_phi) {
+        load_mlp(sm, kPhiS, kPhiK1, kPhiIn, 1, a.phi);
+        load_mlp_t(sm, kPhiT, kPhiIn, a.phi);
+    }
+    if (a.use_psi) {
+        load_mlp(sm, kPsiS, kPsiK1, kPsiIn, 3, a.psi);
+        load_mlp_t(sm, kPsiT, kPsiIn, a.psi);
+    }
+    __syncthreads();
+    const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4, l16 = lane & 15;
+    const int waves = blockDim.x >> 6;
+    const float kd = 0.01f * (1.f - 0.36787944117144233f);
+    const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
+    for (int base = (blockIdx.x * waves + w) * 16; base < n; base += gridDim.x * waves * 16) {
+        // keeps the weight operands' LDS reads inside the loop: hoisted out of
+        // it they would need several hundred registers
+        asm volatile("" ::: "memory");
+        const int g_raw = base + l16;
+        const bool valid = g_raw < n;
+        const int g = valid ? g_raw : n - 1;
+        // ---- forward recompute of the shading inputs
+        const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
+        float wix = a.light[0] - mx, wiy = a.light[1] - my, wiz = a.light[2] - mz;
+        const float ri = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
+        wix *= ri; wiy *= ri; wiz *= ri;
+        float wox = a.eye[0] - mx, woy = a.eye[1] - my, woz = a.eye[2] - mz;
+        const float ro = rsqrtf(wox * wox + woy * woy + woz * woz);
+        wox *= ro; woy *= ro; woz *= ro;
+        float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
+        const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        const float rq = 1.f / qn;
+        qw *= rq; qx *= rq; qy *= rq; qz *= rq;
+        const float R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
+        const float R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
+        const float R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
+        const float lix = R00 * wix + R01 * wiy + R02 * wiz;
+        const float liy = R10 * wix + R11 * wiy + R12 * wiz;
+        const float liz = R20 * wix + R21 * wiy + R22 * wiz;
+        const float lox = R00 * wox + R01 * woy + R02 * woz;
+        const float loy = R10 * wox + R11 * woy + R12 * woz;
+        const float loz = R20 * wox + R21 * woy + R22 * woz;
+        const float elu = liz > 0.f ? liz : 0.01f * (expf(fminf(liz, 0.f)) - 1.f);
+        const float delu = liz > 0.f ? 1.f : 0.01f * expf(fminf(liz, 0.f));
+        const float fd = (elu + kd) * fd_norm;
+        float hx = lix + lox, hy = liy + loy, hz = liz + loz;
+        const float hn2 = hx * hx + hy * hy + hz * hz;
+        const bool hok = hn2 > 1e-24f;
+        float rh = 0.f;
+        if (hok) {
+            rh = rsqrtf(hn2);
+            hx *= rh; hy *= rh; hz *= rh;
+        } else {
+            hx = 0.f; hy = 0.f; hz = 1.f;
+        }
+        // ---- upstream gradients
+        const float dc0 = a.gcol[g], dc1 = a.gcol[(size_t)n + g], dc2 = a.gcol[(size_t)2 * n + g];
+        const float dtp = a.gcol[(size_t)3 * n + g];
+        const float dr0 = a.gcol[(size_t)4 * n + g], dr1 = a.gcol[(size_t)5 * n + g], dr2 = a.gcol[(size_t)6 * n + g];
+        // ---- lobes (Eq. 7): G = lambda exp(-(lambda theta)^2 / 2)
+        float dhx = 0.f, dhy = 0.f, dhz = 0.f;
+        for (int kl = q; kl < sc.k; kl += 4) {
+            const size_t ab = (size_t)kl * 3 * n;
+            const float ax = sc.lobe_axis[ab + g], ay = sc.lobe_axis[ab + n + g], az = sc.lobe_axis[ab + 2 * n + g];
+            const float ra = rsqrtf(ax * ax + ay * ay + az * az);
+            const float zx = ax * ra, zy = ay * ra, zz = az * ra;
+            const float cz = hx * zx + hy * zy + hz * zz;
+            const float cx = hy * zz - hz * zy, cy = hz * zx - hx * zz, cw = hx * zy - hy * zx;
+            const float sn = sqrtf(cx * cx + cy * cy + cw * cw);
+            const float theta = atan2f(sn, cz);
+            const float lam = expf(sc.lobe_log_sharp[(size_t)kl * n + g]);
+            const float t = lam * theta;
+            const float ex = expf(-0.5f * t * t);
+            const float G = lam * ex;
+            const float am0 = sc.lobe_amp[ab + g], am1 = sc.lobe_amp[ab + n + g], am2 = sc.lobe_amp[ab + 2 * n + g];
+            const float dG = fmaf(dc0, am0, fmaf(dc1, am1, dc2 * am2));
+            // dtheta/dh = -(z - cz h)/sin(theta); dG/dtheta = -lam^3 theta ex
+            const float ratio = sn > 1e-6f ? theta / sn : 1.f;
+            const float coef = dG * lam * lam * lam * ex * ratio;
+            dhx = fmaf(coef, zx - cz * hx, dhx);
+            dhy = fmaf(coef, zy - cz * hy, dhy);
+            dhz = fmaf(coef, zz - cz * hz, dhz);
+            float dzx = coef * (hx - cz * zx), dzy = coef * (hy - cz * zy), dzz = coef * (hz - cz * zz);
+            const float dzd = dzx * zx + dzy * zy + dzz * zz;
+            dzx = (dzx - dzd * zx) * ra;
+            dzy = (dzy - dzd * zy) * ra;
+            dzz = (dzz - dzd * zz) * ra;
+            if (valid) {
+                a.g.lobe_amp[ab + g] += dc0 * G;
+                a.g.lobe_amp[ab + n + g] += dc1 * G;
+                a.g.lobe_amp[ab + 2 * n + g] += dc2 * G;
+                a.g.lobe_log_sharp[(size_t)kl * n + g] += dG * ex * (1.f - t * t) * lam;
+                a.g.lobe_axis[ab + g] += dzx;
+                a.g.lobe_axis[ab + n + g] += dzy;
+                a.g.lobe_axis[ab + 2 * n + g] += dzz;
+            }
+        }
+        dhx += __shfl_xor(dhx, 16, 64); dhx += __shfl_xor(dhx, 32, 64);
+        dhy += __shfl_xor(dhy, 16, 64); dhy += __shfl_xor(dhy, 32, 64);
+        dhz += __shfl_xor(dhz, 16, 64); dhz += __shfl_xor(dhz, 32, 64);
+        // ---- Phi([T, feat]) adjoint
+        const float Tg = a.T[g];
+        float dTg = dtp;
+        float phi_dx0[4] = {0.f, 0.f, 0.f, 0.f}, phi_dx1[4] = {0.f, 0.f, 0.f, 0.f};
+        if (a.use_phi) {
+            floatx4 h[3][4];
+            auto xin = [&](int k) -> float {
+                if (k == 0) return Tg;
+                if (k <= kFeat) return sc.feat[(size_t)(k - 1) * n + g];
+                return 0.f;
+            };
+            mlp_hidden_all<kPhiK1>(sm, kPhiS, lane, xin, h);
+            const float tp = mlp_out(sm, kPhiS, lane, h[2], 0);
+            const float d4 = dtp * tp * (1.f - tp);
+            floatx4 dh3[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dh3[m][i] = sm[kPhiS.w4 + 16 * m + 4 * q + i] * d4;
+            floatx4 dx[2];
+            auto store_dz = [&](int l, const floatx4 dz[4]) {
+                if (!valid) return;
+                store_rows(a.rows, l == 0 ? kPhiRows.dz1 : (l == 1 ? kPhiRows.dz2 : kPhiRows.dz3), q, g, n, dz);
+            };
+            mlp_backward(sm, kPhiT, lane, h, dh3, store_dz, dx);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                phi_dx0[i] = dx[0][i];
+                phi_dx1[i] = dx[1][i];
+            }
+            if (valid) {
+                float* R = a.rows;
+                for (int k = q; k < kPhiIn; k += 4) R[(size_t)(kPhiRows.x + k) * n + g] = xin(k);
+                store_rows(R, kPhiRows.h1, q, g, n, h[0]);
+                store_rows(R, kPhiRows.h2, q, g, n, h[1]);
+                store_rows(R, kPhiRows.h3, q, g, n, h[2]);
+                if (q == 0) R[(size_t)kPhiRows.dz4 * n + g] = d4;
+            }
+            // dL/dT = dx row 0 (tile 0, quarter 0, i = 0)
+            dTg = __shfl(phi_dx0[0], l16, 64);
+        }
+        // ---- Psi([feat, w_i, w_o]) adjoint
+        float psi_dx0[4] = {0.f, 0.f, 0.f, 0.f};
+        float pdwx = 0.f, pdwy = 0.f, pdwz = 0.f, pdox = 0.f, pdoy = 0.f, pdoz = 0.f;
+        if (a.use_psi) {
+            floatx4 h[3][4];
+            auto xin = [&](int k) -> float {
+                if (k < kFeat) return sc.feat[(size_t)k * n + g];
+                switch (k - kFeat) {
+                    case 0: return wix;
+                    case 1: return wiy;
+                    case 2: return wiz;
+                    case 3: return wox;
+                    case 4: return woy;
+                    case 5: return woz;
+                    default: return 0.f;
+                }
+            };
+            mlp_hidden_all<kPsiK1>(sm, kPsiS, lane, xin, h);
+            const float r0 = mlp_out(sm, kPsiS, lane, h[2], 0);
+            const float r1 = mlp_out(sm, kPsiS, lane, h[2], 1);
+            const float r2 = mlp_out(sm, kPsiS, lane, h[2], 2);
+            const float d40 = dr0 * r0 * (1.f - r0), d41 = dr1 * r1 * (1.f - r1), d42 = dr2 * r2 * (1.f - r2);
+            floatx4 dh3[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + 4 * q + i;
+                    dh3[m][i] = fmaf(sm[kPsiS.w4 + r], d40,
+                                     fmaf(sm[kPsiS.w4 + 64 + r], d41, sm[kPsiS.w4 + 128 + r] * d42));
+                }
+            floatx4 dx[2];
+            auto store_dz = [&](int l, const floatx4 dz[4]) {
+                if (!valid) return;
+                store_rows(a.rows, l == 0 ? kPsiRows.dz1 : (l == 1 ? kPsiRows.dz2 : kPsiRows.dz3), q, g, n, dz);
+            };
+            mlp_backward(sm, kPsiT, lane, h, dh3, store_dz, dx);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) psi_dx0[i] = dx[0][i];
+            // rows 16..21 = w_i, w_o live in tile 1, quarters 0 and 1
+            const float t10 = __shfl(dx[1][0], l16, 64), t11 = __shfl(dx[1][1], l16, 64);
+            const float t12 = __shfl(dx[1][2], l16, 64), t13 = __shfl(dx[1][3], l16, 64);
+            const float t20 = __shfl(dx[1][0], l16 + 16, 64), t21 = __shfl(dx[1][1], l16 + 16, 64);
+            pdwx = t10; pdwy = t11; pdwz = t12; pdox = t13; pdoy = t20; pdoz = t21;
+            if (valid) {
+                float* R = a.rows;
+                for (int k = q; k < kPsiIn; k += 4) R[(size_t)(kPsiRows.x + k) * n + g] = xin(k);
+                store_rows(R, kPsiRows.h1, q, g, n, h[0]);
+                store_rows(R, kPsiRows.h2, q, g, n, h[1]);
+                store_rows(R, kPsiRows.h3, q, g, n, h[2]);
+                if (q == 0) {
+                    R[(size_t)kPsiRows.dz4 * n + g] = d40;
+                    R[(size_t)(kPsiRows.dz4 + 1) * n + g] = d41;
+                    R[(size_t)(kPsiRows.dz4 + 2) * n + g] = d42;
+                }
+            }
+        }
+        // ---- features: Phi row r + 1 and Psi row r of dx feed feat r
+        {
+            const float up0 = __shfl(phi_dx0[0], l16 + 16 * ((q + 1) & 3), 64);
+            const float up1 = __shfl(phi_dx1[0], l16, 64);
+            const float nxt = q < 3 ? up0 : up1;
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float pf = i < 3 ? phi_dx0[i + 1] : nxt;
+                    a.g.feat[(size_t)(4 * q + i) * n + g] += pf + psi_dx0[i];
+                }
+            }
+        }
+        // ---- Lambertian, half vector, frames and directions
+        const float alb0 = sc.albedo[g], alb1 = sc.albedo[n + g], alb2 = sc.albedo[2 * n + g];
+        const float dfd = fmaf(dc0, alb0, fmaf(dc1, alb1, dc2 * alb2));
+        float dhsx = 0.f, dhsy = 0.f, dhsz = 0.f;
+        if (hok) {
+            const float dd = dhx * hx + dhy * hy + dhz * hz;
+            dhsx = (dhx - dd * hx) * rh;
+            dhsy = (dhy - dd * hy) * rh;
+            dhsz = (dhz - dd * hz) * rh;
+        }
+        const float dlix = dhsx, dliy = dhsy, dliz = dhsz + dfd * fd_norm * delu;
+        const float dlox = dhsx, dloy = dhsy, dloz = dhsz;
+        const float dR[9] = {dlix * wix + dlox * wox, dlix * wiy + dlox * woy, dlix * wiz + dlox * woz,
+                             dliy * wix + dloy * wox, dliy * wiy + dloy * woy, dliy * wiz + dloy * woz,
+                             dliz * wix + dloz * wox, dliz * wiy + dloz * woy, dliz * wiz + dloz * woz};
+        float dq[4];
+        quat_grad(qw, qx, qy, qz, qn, dR, dq);
+        // world directions: R^T dl plus Psi's direct inputs
+        const float dwx = R00 * dlix + R10 * dliy + R20 * dliz + pdwx;
+        const float dwy = R01 * dlix + R11 * dliy + R21 * dliz + pdwy;
+        const float dwz = R02 * dlix + R12 * dliy + R22 * dliz + pdwz;
+        const float dox = R00 * dlox + R10 * dloy + R20 * dloz + pdox;
+        const float doy = R01 * dlox + R11 * dloy + R21 * dloz + pdoy;
+        const float doz = R02 * dlox + R12 * dloy + R22 * dloz + pdoz;
+        // w = (p - mu)/|p - mu|: dmu = -(dw - (dw.w) w) / |p - mu|
+        const float wd = dwx * wix + dwy * wiy + dwz * wiz;
+        const float od = dox * wox + doy * woy + doz * woz;
+        const float dmx = -(dwx - wd * wix) * ri - (dox - od * wox) * ro;
+        const float dmy = -(dwy - wd * wiy) * ri - (doy - od * woy) * ro;
+        const float dmz = -(dwz - wd * wiz) * ri - (doz - od * woz) * ro;
+        if (valid && q == 0) {
+            a.g.albedo[g] += dc0 * fd;
+            a.g.albedo[n + g] += dc1 * fd;
+            a.g.albedo[2 * n + g] += dc2 * fd;
+            a.g.shade_rot[g] += dq[0];
+            a.g.shade_rot[n + g] += dq[1];
+            a.g.shade_rot[2 * n + g] += dq[2];
+            a.g.shade_rot[3 * n + g] += dq[3];
+            a.g.mean[g] += dmx;
+            a.g.mean[n + g] += dmy;
+            a.g.mean[2 * n + g] += dmz;
+            a.dT[g] = dTg;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// MLP weight gradients: dW_l = sum_g dz_l[:, g] in_l[:, g]^T and
+// db_l = sum_g dz_l[:, g] over all Gaussians, as split-K partial sums (one
+// workgroup per (chunk of Gaussians, layer)) and one reduction.
+
+constexpr int kWgChunk = kWgChunkHost;
+
+struct WgProblem {
+    int dz_row, in_row, O, J, off;   // scratch rows, output/input widths, offset in the flat vector
+    float* dW;                       // [O][J] +=
+    float* db;                       // [O] +=
+};
+struct WgArgs {
+    WgProblem p[8];
+    int count, total;                // problems, flat parameter count
+    const float* rows;
+    int n;
+    float* partial;                  // [chunks][total]
+};
+
+__global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
+    __shared__ float sD[64][33];
+    __shared__ float sH[64][33];
+    const WgProblem P = a.p[blockIdx.y];
+    const int n = a.n;
+    const int k0 = blockIdx.x * kWgChunk, k1 = min(n, k0 + kWgChunk);
+    const float* D = a.rows + (size_t)P.dz_row * n;
+    const float* H = a.rows + (size_t)P.in_row * n;
+    const int t = threadIdx.x;
+    const int o0 = 4 * (t >> 4), j0 = 4 * (t & 15);
+    float acc[4][4] = {{0.f}};
+    float bacc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int kb = k0; kb < k1; kb += 32) {
+        for (int idx = t; idx < 64 * 32; idx += 256) {
+            const int r = idx >> 5, c = idx & 31, gg = kb + c;
+            sD[r][c] = (r < P.O && gg < k1) ? D[(size_t)r * n + gg] : 0.f;
+            sH[r][c] = (r < P.J && gg < k1) ? H[(size_t)r * n + gg] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 32; ++kk) {
+            float av[4], bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                av[r] = sD[o0 + r][kk];
+                bv[r] = sH[j0 + r][kk];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                bacc[r] += av[r];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(av[r], bv[c], acc[r][c]);
+            }
+        }
+        __syncthreads();
+    }
+    float* part = a.partial + (size_t)blockIdx.x * a.total + P.off;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = o0 + r;
+        if (o >= P.O) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (j0 + c < P.J) part[o * P.J + j0 + c] = acc[r][c];
+        if (j0 == 0) part[P.O * P.J + o] = bacc[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(WgArgs a, int chunks) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.total) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += a.partial[(size_t)c * a.total + p];
+    for (int i = 0; i < a.count; ++i) {
+        const WgProblem& P = a.p[i];
+        const int rel = p - P.off;
+        if (rel >= 0 && rel < P.O * P.J) {
+            P.dW[rel] += s;
+            return;
+        }
+        if (rel >= P.O * P.J && rel < P.O * P.J + P.O) {
+            P.db[rel - P.O * P.J] += s;
+            return;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Projection adjoint (both views), in double like the forward projection.
+
+struct ProjBwdArgs {
+    SceneDev sc;
+    ViewParams v[2];          // camera, light
+    const float* gs[2];       // [6][n] {u, v, A, B, C, opacity} per view
+    gs3_consts kc;
+    GradDev g;
+};
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = a.sc.n;
+    if (i >= n) return;
+    const SceneDev& sc = a.sc;
+    const double mx = sc.mean[i], my = sc.mean[n + i], mz = sc.mean[2 * n + i];
+    const double s[3] = {exp((double)sc.log_scale[i]), exp((double)sc.log_scale[n + i]),
+                         exp((double)sc.log_scale[2 * n + i])};
+    double qw = sc.rot[i], qx = sc.rot[n + i], qy = sc.rot[2 * n + i], qz = sc.rot[3 * n + i];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                         2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                         2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = R[3 * r + c] * s[c];
+    double gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = 0.0;
+    for (int vi = 0; vi < 2; ++vi) {
+        const float* G = a.gs[vi];
+        const double gu = G[i], gv = G[(size_t)n + i], gA = G[(size_t)2 * n + i], gB = G[(size_t)3 * n + i],
+                     gC = G[(size_t)4 * n + i];
+        gop += G[(size_t)5 * n + i];
+        if (gu == 0.0 && gv == 0.0 && gA == 0.0 && gB == 0.0 && gC == 0.0) continue;
+        const ViewParams& vp = a.v[vi];
+        const double dx = mx - vp.eye[0], dy = my - vp.eye[1], dz = mz - vp.eye[2];
+        const double tx = vp.R[0] * dx + vp.R[1] * dy + vp.R[2] * dz;
+        const double ty = vp.R[3] * dx + vp.R[4] * dy + vp.R[5] * dz;
+        const double tz = vp.R[6] * dx + vp.R[7] * dy + vp.R[8] * dz;
+        if (!(tz > (double)a.kc.near_plane)) continue;
+        const double f = vp.focal;
+        const double xs = tx / tz, ys = ty / tz;
+        const bool cx_ = xs < -vp.lim_x || xs > vp.lim_x, cy_ = ys < -vp.lim_y || ys > vp.lim_y;
+        const double xr = fmin(fmax(xs, -vp.lim_x), vp.lim_x);
+        const double yr = fmin(fmax(ys, -vp.lim_y), vp.lim_y);
+        const double j0 = f / tz, j2x = -f * xr / tz, j2y = -f * yr / tz;
+        double A[6];
+        for (int c = 0; c < 3; ++c) {
+            A[c] = j0 * vp.R[c] + j2x * vp.R[6 + c];
+            A[3 + c] = j0 * vp.R[3 + c] + j2y * vp.R[6 + c];
+        }
+        double B[6];
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k)
+                B[3 * r + k] = A[3 * r] * M[k] + A[3 * r + 1] * M[3 + k] + A[3 * r + 2] * M[6 + k];
+        const double ca = B[0] * B[0] + B[1] * B[1] + B[2] * B[2] + (double)a.kc.dilation;
+        const double cb = B[0] * B[3] + B[1] * B[4] + B[2] * B[5];
+        const double cc = B[3] * B[3] + B[4] * B[4] + B[5] * B[5] + (double)a.kc.dilation;
+        const double det = ca * cc - cb * cb;
+        if (!(det > 0.0)) continue;
+        // (A, B, C) of the kernels -> conic (a, b, c) -> Sigma' entries
+        const double ga = gA * (-0.5 * (double)kLog2eF), gb = gB * (-(double)kLog2eF), gc = gC * (-0.5 * (double)kLog2eF);
+        const double id = 1.0 / det, id2 = id * id;
+        const double gca = ga * (-cc * cc) * id2 + gb * (cb * cc) * id2 + gc * (id - ca * cc * id2);
+        const double gcc = ga * (id - cc * ca * id2) + gb * (cb * ca) * id2 + gc * (-ca * ca) * id2;
+        const double gcb = ga * (2.0 * cc * cb) * id2 + gb * (-id - 2.0 * cb * cb * id2) + gc * (2.0 * ca * cb) * id2;
+        double gB_[6];
+        for (int k = 0; k < 3; ++k) {
+            gB_[k] = 2.0 * gca * B[k] + gcb * B[3 + k];
+            gB_[3 + k] = gcb * B[k] + 2.0 * gcc * B[3 + k];
+        }
+        double gA_[6];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c)
+                gA_[3 * r + c] = gB_[3 * r] * M[3 * c] + gB_[3 * r + 1] * M[3 * c + 1] + gB_[3 * r + 2] * M[3 * c + 2];
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) gM[3 * c + k] += A[c] * gB_[k] + A[3 + c] * gB_[3 + k];
+        double gj0 = 0.0, gj2x = 0.0, gj2y = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            gj0 += gA_[c] * vp.R[c] + gA_[3 + c] * vp.R[3 + c];
+            gj2x += gA_[c] * vp.R[6 + c];
+            gj2y += gA_[3 + c] * vp.R[6 + c];
+        }
+        double gtx = 0.0, gty = 0.0, gtz = 0.0;
+        gtz += gj0 * (-f / (tz * tz));
+        if (cx_) {
+            gtz += gj2x * (f * xr / (tz * tz));
+        } else {
+            gtx += gj2x * (-f / (tz * tz));
+            gtz += gj2x * (2.0 * f * tx / (tz * tz * tz));
+        }
+        if (cy_) {
+            gtz += gj2y * (f * yr / (tz * tz));
+        } else {
+            gty += gj2y * (-f / (tz * tz));
+            gtz += gj2y * (2.0 * f * ty / (tz * tz * tz));
+        }
+        gtx += gu * f / tz;
+        gtz += -gu * f * tx / (tz * tz);
+        gty += gv * f / tz;
+        gtz += -gv * f * ty / (tz * tz);
+        for (int c = 0; c < 3; ++c) gmean[c] += vp.R[c] * gtx + vp.R[3 + c] * gty + vp.R[6 + c] * gtz;
+    }
+    // M = R diag(s)
+    double gR[9], gls[3] = {0, 0, 0};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            gR[3 * r + c] = gM[3 * r + c] * s[c];
+            gls[c] += gM[3 * r + c] * R[3 * r + c] * s[c];
+        }
+    const double dw = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+    const double dxq = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - qw * gR[5] + qz * gR[6] +
+                              qw * gR[7] - 2.0 * qx * gR[8]);
+    const double dyq = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] - qw * gR[6] +
+                              qz * gR[7] - 2.0 * qy * gR[8]);
+    const double dzq = 2.0 * (-2.0 * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.0 * qz * gR[4] +
+                              qy * gR[5] + qx * gR[6] + qy * gR[7]);
+    const double dot = dw * qw + dxq * qx + dyq * qy + dzq * qz;
+    const double logit = sc.opacity_logit[i];
+    const double op = 1.0 / (1.0 + exp(-logit));
+    a.g.mean[i] += (float)gmean[0];
+    a.g.mean[n + i] += (float)gmean[1];
+    a.g.mean[2 * n + i] += (float)gmean[2];
+    a.g.log_scale[i] += (float)gls[0];
+    a.g.log_scale[n + i] += (float)gls[1];
+    a.g.log_scale[2 * n + i] += (float)gls[2];
+    a.g.rot[i] += (float)((dw - dot * qw) / qn);
+    a.g.rot[n + i] += (float)((dxq - dot * qx) / qn);
+    a.g.rot[2 * n + i] += (float)((dyq - dot * qy) / qn);
+    a.g.rot[3 * n + i] += (float)((dzq - dot * qz) / qn);
+    a.g.opacity_logit[i] += (float)(gop * op * (1.0 - op));
+}
+
+// --------------------------------------------------------------------------
+
+int wgrad_total_params(bool phi, bool psi) {
+    int t = 0;
+    if (phi) t += 64 * kPhiIn + 64 + 2 * (64 * 64 + 64) + 64 + 1;
+    if (psi) t += 64 * kPsiIn + 64 + 2 * (64 * 64 + 64) + 3 * 64 + 3;
+    return t;
+}
+
+hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                            const gs3_mlp* psi, const float* gcol, float* dT, const GradDev& g, float* rows,
+                            float* partial, const gs3_grads* gr, hipStream_t st) {
+    if (sc.n == 0) return hipSuccess;
+    ShadeBwdArgs a;
+    a.sc = sc;
+    for (int i = 0; i < 3; ++i) {
+        a.light[i] = sp.light[i];
+        a.eye[i] = sp.eye[i];
+    }
+    a.use_phi = phi != nullptr;
+    a.use_psi = psi != nullptr;
+    a.T = T;
+    for (int i = 0; i < 4; ++i) {
+        a.phi.w[i] = phi ? phi->w[i] : nullptr;
+        a.phi.b[i] = phi ? phi->b[i] : nullptr;
+        a.psi.w[i] = psi ? psi->w[i] : nullptr;
+        a.psi.b[i] = psi ? psi->b[i] : nullptr;
+    }
+    a.gcol = gcol;
+    a.dT = dT;
+    a.g = g;
+    a.rows = rows;
+    // 161 KB of LDS: one workgroup per CU, so 4 waves with the full register file
+    const int per_block = 4 * 16;
+    int grid = (int)((sc.n + per_block - 1) / per_block);
+    if (grid > 512) grid = 512;
+    hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || (!phi && !psi)) return e;
+    // weight gradients
+    WgArgs w;
+    w.count = 0;
+    int off = 0;
+    auto add = [&](int dz_row, int in_row, int O, int J, float* dW, float* db) {
+        WgProblem& P = w.p[w.count++];
+        P.dz_row = dz_row; P.in_row = in_row; P.O = O; P.J = J; P.off = off; P.dW = dW; P.db = db;
+        off += O * J + O;
+    };
+    if (phi) {
+        add(kPhiRows.dz1, kPhiRows.x, 64, kPhiIn, gr->phi_w[0], gr->phi_b[0]);
+        add(kPhiRows.dz2, kPhiRows.h1, 64, 64, gr->phi_w[1], gr->phi_b[1]);
+        add(kPhiRows.dz3, kPhiRows.h2, 64, 64, gr->phi_w[2], gr->phi_b[2]);
+        add(kPhiRows.dz4, kPhiRows.h3, 1, 64, gr->phi_w[3], gr->phi_b[3]);
+    }
+    if (psi) {
+        add(kPsiRows.dz1, kPsiRows.x, 64, kPsiIn, gr->psi_w[0], gr->psi_b[0]);
+        add(kPsiRows.dz2, kPsiRows.h1, 64, 64, gr->psi_w[1], gr->psi_b[1]);
+        add(kPsiRows.dz3, kPsiRows.h2, 64, 64, gr->psi_w[2], gr->psi_b[2]);
+        add(kPsiRows.dz4, kPsiRows.h3, 3, 64, gr->psi_w[3], gr->psi_b[3]);
+    }
+    w.total = off;
+    w.rows = rows;
+    w.n = sc.n;
+    w.partial = partial;
+    const int chunks = (sc.n + kWgChunk - 1) / kWgChunk;
+    hipLaunchKernelGGL(k_wgrad, dim3(chunks, w.count), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 255) / 256), dim3(256), 0, st, w, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const ViewParams& light,
+                              const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
+                              hipStream_t st) {
+    if (sc.n == 0) return hipSuccess;
+    ProjBwdArgs a;
+    a.sc = sc;
+    a.v[0] = cam;
+    a.v[1] = light;
+    a.gs[0] = gcam;
+    a.gs[1] = glight;
+    a.kc = k;
+    a.g = g;
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((sc.n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace gs3

@@ -1,0 +1,546 @@
+// Adjoints of the two per-tile splats: the camera splat (Sec. 3 Eq. 2-3,
+// Fig. 2) and the shadow splat (Sec. 4.2, Fig. 3). Nothing per (pixel,
+// splat) pair is stored by the forward: each kernel walks the same tile
+// lists again with the same float32 arithmetic, so every hit, alpha,
+// transmittance and stop decision is the forward's.
+//
+// Per-splat gradients are kept in the kernels' own parametrisation:
+//   q = A dx^2 + B dx dy + C dy^2  (= power * log2 e),  dx = px - u,
+// so the outputs are dL/du, dL/dv, dL/dA, dL/dB, dL/dC and dL/dopacity;
+// the projection adjoint converts (A, B, C) to the conic (a, b, c).
+#include "splat_common.h"
+
+namespace gs3 {
+
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kBwdEps = 9.5367431640625e-07f;   // 2^-20, the forward numerator's dark-ray bound
+
+// Gradient of q with respect to the splat parameters at offset (dx, dy),
+// scaled by dq: {u, v, A, B, C}.
+struct QGrad {
+    float u, v, A, B, C;
+};
+__device__ inline QGrad q_grad(float dq, float dx, float dy, float A, float B, float C) {
+    QGrad g;
+    g.u = -dq * fmaf(2.f * A, dx, B * dy);
+    g.v = -dq * fmaf(B, dx, 2.f * C * dy);
+    g.A = dq * dx * dx;
+    g.B = dq * dx * dy;
+    g.C = dq * dy * dy;
+    return g;
+}
+
+// --------------------------------------------------------------------------
+// Camera splat adjoint.
+//
+// Per pixel the forward composites 7 channels f_j = (c_j, T'_j, r_j):
+// F = sum_j f_j alpha_j T_j. With C_j the value composited through hit j,
+//   dF/df_j     = alpha_j T_j
+//   dF/dalpha_j = T_j f_j - (F - C_j) / (1 - alpha_j)
+// F is the forward's stored image; the walk recomputes C_j with the
+// forward's operations in the forward's order, so F - C_j is the exact
+// remainder up to rounding. The upstream gradient of the 7 channels follows
+// from final = S * Sh + R.
+
+struct RenderBwdArgs {
+    const int2* ranges;
+    const uint32_t* order;
+    const uint32_t* list;
+    const float4* rec0;
+    const float4* rec1;
+    const float4* col0;
+    const float4* col1;
+    uint32_t n;
+    int width, height, tiles_x;
+    float cutoff, alpha_min, alpha_max, t_min;
+    const float* S;      // [3][H][W]
+    const float* Sh;     // [H][W]
+    const float* R;      // [3][H][W]
+    const float* dF;     // dL/dfinal [3][H][W]
+    float* gsplat;       // [6][n] += {u, v, A, B, C, opacity}
+    float* gcol;         // [7][n] += {c.rgb, T', r.rgb}
+};
+
+constexpr int kCamGrads = 13;
+
+__global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
+    __shared__ Staged s_rec[256];
+    __shared__ float4 s_c0[256];
+    __shared__ float4 s_c1[256];
+    __shared__ uint32_t s_mask[256];
+    __shared__ uint32_t s_id[256];
+    __shared__ float s_g[kCamGrads][256];
+    const int tile = (int)a.order[blockIdx.x];
+    const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    const bool inside = px < a.width && py < a.height;
+    const float pxc = lx + 0.5f, pyc = ly + 0.5f;
+    const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
+    const uint32_t wbit = 1u << w;
+    const int2 rg = a.ranges[tile];
+    const int s = rg.x, e = rg.y;
+    // stored forward values and upstream gradient of the 7 channels
+    float F[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float G[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (inside) {
+        const int64_t hw = (int64_t)a.width * a.height;
+        const int64_t p = (int64_t)py * a.width + px;
+        F[0] = a.S[p]; F[1] = a.S[hw + p]; F[2] = a.S[2 * hw + p];
+        F[3] = a.Sh[p];
+        F[4] = a.R[p]; F[5] = a.R[hw + p]; F[6] = a.R[2 * hw + p];
+        const float d0 = a.dF[p], d1 = a.dF[hw + p], d2 = a.dF[2 * hw + p];
+        G[0] = d0 * F[3]; G[1] = d1 * F[3]; G[2] = d2 * F[3];
+        G[3] = fmaf(d0, F[0], fmaf(d1, F[1], d2 * F[2]));
+        G[4] = d0; G[5] = d1; G[6] = d2;
+    }
+    float T = 1.f;
+    float Cc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool done = !inside;
+    for (int i = tid; i < kCamGrads * 256; i += 256) (&s_g[0][0])[i] = 0.f;
+    for (int b = s; b < e; b += 256) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int m = min(256, e - b);
+        if (tid < m) {
+            const uint32_t id = safe_id(a.list[b + tid], a.n);
+            uint32_t mk;
+            s_rec[tid] = stage_splat(id, a.rec0, a.rec1, nullptr, tile_x0, tile_y0, a.cutoff, a.alpha_min, &mk);
+            s_mask[tid] = mk;
+            s_id[tid] = id;
+            s_c0[tid] = a.col0[id];
+            s_c1[tid] = a.col1[id];
+        }
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            if (!(s_mask[j] & wbit)) continue;
+            if (__ballot(!done) == 0) break;
+            const Staged sj = s_rec[j];
+            const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
+            const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
+            bool hit = !done && q >= sj.g1.y;
+            const float beta = fast_exp2(q);
+            const float ob = sj.g1.z * beta;
+            const float al = fminf(a.alpha_max, ob);
+            const float tn = T * (1.f - al);
+            if (hit && tn < a.t_min) {
+                done = true;
+                hit = false;
+            }
+            float gv[kCamGrads];
+#pragma unroll
+            for (int c = 0; c < kCamGrads; ++c) gv[c] = 0.f;
+            if (hit) {
+                const float wgt = al * T;
+                const float4 c0 = s_c0[j];
+                const float4 c1 = s_c1[j];
+                const float f[7] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
+                // the forward's blend, in its order
+                Cc[0] = fmaf(wgt, f[0], Cc[0]);
+                Cc[1] = fmaf(wgt, f[1], Cc[1]);
+                Cc[2] = fmaf(wgt, f[2], Cc[2]);
+                Cc[3] = fmaf(wgt, f[3], Cc[3]);
+                Cc[4] = fmaf(wgt, f[4], Cc[4]);
+                Cc[5] = fmaf(wgt, f[5], Cc[5]);
+                Cc[6] = fmaf(wgt, f[6], Cc[6]);
+                const float inv = 1.f / (1.f - al);
+                float dal = 0.f;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    gv[6 + c] = G[c] * wgt;
+                    dal = fmaf(G[c], fmaf(T, f[c], -(F[c] - Cc[c]) * inv), dal);
+                }
+                if (ob < a.alpha_max) {
+                    const float dq = dal * al * kLn2;
+                    const QGrad g = q_grad(dq, dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
+                    gv[0] = g.u; gv[1] = g.v; gv[2] = g.A; gv[3] = g.B; gv[4] = g.C;
+                    gv[5] = dal * beta;
+                }
+                T = tn;
+            }
+            if (__ballot(hit)) {
+#pragma unroll
+                for (int c = 0; c < kCamGrads; ++c) {
+                    const float sum = wave_sum_lane63(gv[c]);
+                    if (lane == 63 && sum != 0.f) atomicAdd(&s_g[c][j], sum);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < m) {
+            const uint32_t id = s_id[tid];
+#pragma unroll
+            for (int c = 0; c < kCamGrads; ++c) {
+                const float v = s_g[c][tid];
+                if (v != 0.f) {
+                    float* dst = c < 6 ? a.gsplat + (size_t)c * a.n : a.gcol + (size_t)(c - 6) * a.n;
+                    atomicAdd(dst + id, v);
+                    s_g[c][tid] = 0.f;
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Shadow splat adjoint.
+//
+// T_j = num_j / den_j gives dL/dnum_j = g_j / den_j and
+// dL/dden_j = -g_j T_j / den_j (g_j = dL/dT_j; both 0 where den_j = 0).
+//  - den_j = sum_m beta_jm: k_shadow_den_bwd, one wave per Gaussian over its
+//    footprint, like k_shadow_den.
+//  - num_j = sum_m beta_jm T_m(j): for a ray m let w_jm = dL/dnum_j beta_jm
+//    T_m(j) and G_m = sum_j w_jm. Occluder k enters T_m(j) for exactly the
+//    leads j from the point where the forward's trailing pointer multiplies
+//    it in, so dL/dalpha_km = -(G_m - P_m) / (1 - alpha_km), P_m being the
+//    sum of w over the leads before that point. k_shadow_bwd<0> computes G_m
+//    (same walk as the forward numerator), k_shadow_bwd<1> repeats the walk
+//    with the running P_m. Terms the forward numerator drops (ray
+//    transmittance below 2^-20) are dropped here too.
+
+struct ShadowBwdArgs {
+    const int2* ranges;
+    const uint32_t* order;
+    const uint32_t* list;
+    const float4* rec0;
+    const float4* rec1;
+    const float* depth;
+    const int4* ext;
+    uint32_t n;
+    int width, height, tiles_x;
+    float cutoff, alpha_min, alpha_max, bias;
+    const float* T;        // [n] forward shadow values
+    const float* num_den;  // [2][n]
+    const float* dT;       // [n] dL/dT
+    float* dnum;           // [n] dL/dnum (written by the den kernel)
+    float* gray;           // [H][W] G_m per light pixel
+    float* gsplat;         // [6][n] {u, v, A, B, C, opacity}
+};
+
+// den part: writes gsplat (=, the numerator sweeps then add) and dnum.
+__global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const int lx = lane & 15, ly = lane >> 4;
+    const int n = (int)a.n;
+    const int tiles_y = (a.height + kTile - 1) / kTile;
+    for (int g = blockIdx.x * 4 + w; g < n; g += gridDim.x * 4) {
+        const float den = a.num_den[n + g];
+        const float dTg = a.dT[g];
+        const float dden = den > 0.f ? -dTg * a.T[g] / den : 0.f;
+        const int4 ex = a.ext[g];
+        float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        int x0, x1, y0, y1;
+        if (dden != 0.f && tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
+            const float4 r0 = a.rec0[g];
+            const float4 r1 = a.rec1[g];
+            float A, B, C, thr;
+            const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
+            float hx = 3.0e38f, hy = 3.0e38f;
+            if (!isinf(p)) {
+                const float det = r1.x * r1.z - r1.y * r1.y;
+                hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
+                hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+            }
+            if (p > 0.f) {
+                for (int ty = y0; ty <= y1; ++ty) {
+                    const float oy = (float)(ty * kTile);
+                    const float v = rel_centre(r0.y, r0.w, oy);
+                    for (int tx = x0; tx <= x1; ++tx) {
+                        const float ox = (float)(tx * kTile);
+                        const float u = rel_centre(r0.x, r0.z, ox);
+                        if (u + hx < 0.5f || u - hx > 15.5f) continue;
+                        const float dx = (float)lx + 0.5f - u;
+                        const bool in_x = tx * kTile + lx < a.width;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float yb = (float)(4 * r);
+                            if (v + hy < yb + 0.5f || v - hy > yb + 3.5f) continue;
+                            const float dy = (float)(4 * r + ly) + 0.5f - v;
+                            const float q = quad_q(dx, dy, A, B, C);
+                            const bool hit = in_x && (ty * kTile + 4 * r + ly < a.height) && q >= thr;
+                            if (hit) {
+                                const float dq = dden * fast_exp2(q) * kLn2;
+                                const QGrad gq = q_grad(dq, dx, dy, A, B, C);
+                                acc[0] += gq.u; acc[1] += gq.v; acc[2] += gq.A; acc[3] += gq.B; acc[4] += gq.C;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const float sum = wave_sum_lane63(acc[c]);
+            if (lane == 63) a.gsplat[(size_t)c * n + g] = sum;
+        }
+        if (lane == 63) {
+            a.gsplat[(size_t)5 * n + g] = 0.f;
+            a.dnum[g] = den > 0.f ? dTg / den : 0.f;
+        }
+    }
+}
+
+struct Bits128b {
+    unsigned long long lo, hi;
+};
+__device__ inline Bits128b range_bits_b(int lo, int hi) {
+    auto upto = [](int k) -> unsigned long long { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); };
+    Bits128b b;
+    b.lo = upto(min(hi, 64)) & ~upto(min(lo, 64));
+    b.hi = upto(max(hi - 64, 0)) & ~upto(max(lo - 64, 0));
+    return b;
+}
+__device__ inline int first_bit_b(const Bits128b& b) {
+    return b.lo ? __builtin_ctzll(b.lo) : 64 + __builtin_ctzll(b.hi);
+}
+__device__ inline void clear_bit_b(Bits128b& b, int k) {
+    if (k < 64) b.lo &= ~(1ull << k); else b.hi &= ~(1ull << (k - 64));
+}
+
+constexpr int kBwdBatch = 128;
+constexpr int kBwdRingMask = 2 * kBwdBatch - 1;
+
+// The forward numerator's walk (one wave per (tile, 8x8 quadrant), LDS ring
+// of two 128-entry batches, quadrant-masked lead and trailing pointers),
+// carrying the adjoint. PASS 0: G_m per pixel. PASS 1: per-splat gradients.
+template <int PASS>
+__global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
+    __shared__ Staged s_rec[2 * kBwdBatch];
+    __shared__ uint32_t s_id[2 * kBwdBatch];
+    const int tile = (int)a.order[blockIdx.x >> 2];
+    const int qd = blockIdx.x & 3;
+    const int2 rg = a.ranges[tile];
+    const int s = rg.x, e = rg.y;
+    const int lane = __lane_id();
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int lx = (qd & 1) * 8 + (lane & 7), ly = (qd >> 1) * 8 + (lane >> 3);
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    const float pxc = lx + 0.5f, pyc = ly + 0.5f;
+    const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
+    const bool inside = px < a.width && py < a.height;
+    const int64_t pix = (int64_t)py * a.width + px;
+    bool alive = inside;
+    float gm = 0.f;                  // PASS 0: G_m; PASS 1: G_m - P_m
+    if (PASS == 1 && inside) gm = a.gray[pix];
+    const uint32_t qbit = 1u << qd;
+    float tt = 1.f;
+    Bits128b cur{0ull, 0ull}, prv{0ull, 0ull};
+    int trail = s;
+    bool finished = e <= s || !__ballot(alive);
+    // occluder k: T *= (1 - alpha); PASS 1 also its gradient
+    auto occlude = [&](const Staged& k, uint32_t kid) {
+        const float dx = pxc - k.g0.x, dy = pyc - k.g0.y;
+        const float q = quad_q(dx, dy, k.g0.z, k.g0.w, k.g1.x);
+        const bool hit = alive && q >= k.g1.y;
+        const float beta = fast_exp2(q);
+        const float ob = k.g1.z * beta;
+        const float al = fminf(a.alpha_max, ob);
+        if (PASS == 1) {
+            float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (hit && gm != 0.f && ob < a.alpha_max) {
+                const float dal = -gm / (1.f - al);
+                const QGrad gq = q_grad(dal * al * kLn2, dx, dy, k.g0.z, k.g0.w, k.g1.x);
+                g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
+                g[5] = dal * beta;
+            }
+            if (__ballot(g[5] != 0.f)) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const float sum = wave_sum_lane63(g[c]);
+                    if (lane == 63) atomicAdd(&a.gsplat[(size_t)c * a.n + kid], sum);
+                }
+            }
+        }
+        if (hit) tt *= 1.f - al;
+    };
+    for (int b = s; b < e && !finished; b += kBwdBatch) {
+        const int m = min(kBwdBatch, e - b);
+        const int base = (b - s) & kBwdRingMask;
+        bool qm[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            qm[h] = false;
+            if (jj < m) {
+                uint32_t mk;
+                const uint32_t id = safe_id(a.list[b + jj], a.n);
+                s_rec[base + jj] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                               a.alpha_min, &mk);
+                s_id[base + jj] = id;
+                qm[h] = (mk & qbit) != 0u;
+            }
+        }
+        cur.lo = __ballot(qm[0]);
+        cur.hi = __ballot(qm[1]);
+        __syncthreads();
+        const int lo_pos = max(s, b - kBwdBatch);
+        int Lh[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            Lh[h] = b + min(jj, m);
+            if (jj < m) {
+                const float thr = s_rec[base + jj].g1.w - a.bias;
+                if (lo_pos > s && !(s_rec[(lo_pos - s) & kBwdRingMask].g1.w < thr)) {
+                    Lh[h] = -1;
+                } else {
+                    int lo = lo_pos, hi = b + jj;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_rec[(mid - s) & kBwdRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
+                    }
+                    Lh[h] = lo;
+                }
+            }
+        }
+        Bits128b todo = cur;
+        while (todo.lo | todo.hi) {
+            const int j = first_bit_b(todo);
+            clear_bit_b(todo, j);
+            const Staged sj = s_rec[base + j];
+            const int L0 = __builtin_amdgcn_readlane(Lh[0], j & 63);
+            const int L1 = __builtin_amdgcn_readlane(Lh[1], j & 63);
+            const int Lj = j < 64 ? L0 : L1;
+            const float thr_d = sj.g1.w - a.bias;
+            const int stop = Lj >= 0 ? Lj : b + j;
+            while (trail < stop) {
+                if (trail < lo_pos) {
+                    uint32_t mk;
+                    const uint32_t kid = safe_id(a.list[trail], a.n);
+                    const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                                  a.alpha_min, &mk);
+                    if (Lj < 0 && !(tk.g1.w < thr_d)) break;
+                    if (mk & qbit) occlude(tk, kid);
+                    ++trail;
+                    continue;
+                }
+                const bool in_cur = trail >= b;
+                const int bstart = in_cur ? b : b - kBwdBatch;
+                const int lo = trail - bstart, hi = min(stop - bstart, kBwdBatch);
+                Bits128b rel = range_bits_b(lo, hi);
+                const Bits128b msk = in_cur ? cur : prv;
+                rel.lo &= msk.lo;
+                rel.hi &= msk.hi;
+                bool stopped = false;
+                while (rel.lo | rel.hi) {
+                    const int k = first_bit_b(rel);
+                    clear_bit_b(rel, k);
+                    const int slot = (bstart + k - s) & kBwdRingMask;
+                    const Staged tk = s_rec[slot];
+                    if (Lj < 0 && !(tk.g1.w < thr_d)) {
+                        trail = bstart + k;
+                        stopped = true;
+                        break;
+                    }
+                    occlude(tk, s_id[slot]);
+                }
+                if (stopped) break;
+                trail = bstart + hi;
+            }
+            alive = alive && tt >= kBwdEps;
+            if (!__ballot(alive)) {
+                finished = true;
+                break;
+            }
+            const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
+            const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
+            const bool hit = alive && q >= sj.g1.y;
+            if (__ballot(hit)) {
+                const uint32_t idj = s_id[base + j];
+                const float dn = a.dnum[idj];
+                const float beta = fast_exp2(q);
+                const float wv = hit ? dn * beta * tt : 0.f;
+                if (PASS == 0) {
+                    gm += wv;
+                } else {
+                    float g[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (hit && dn != 0.f) {
+                        const QGrad gq = q_grad(wv * kLn2, dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
+                        g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
+                    }
+                    if (dn != 0.f) {
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) {
+                            const float sum = wave_sum_lane63(g[c]);
+                            if (lane == 63) atomicAdd(&a.gsplat[(size_t)c * a.n + idj], sum);
+                        }
+                    }
+                    gm -= wv;
+                }
+            }
+        }
+        prv = cur;
+        __syncthreads();
+    }
+    if (PASS == 0 && inside) a.gray[pix] = gm;
+}
+
+// --------------------------------------------------------------------------
+
+hipError_t launch_render_bwd(const gs3_consts& k, const Layout& L, const void* ws, const gs3_images& fwd,
+                             const float* dF, float* gsplat, float* gcol, hipStream_t st) {
+    if (L.n == 0 || L.n_tiles == 0) return hipSuccess;
+    RenderBwdArgs a;
+    a.ranges = at<int2>(ws, L.ranges);
+    a.order = at<uint32_t>(ws, L.order);
+    a.list = at<uint32_t>(ws, L.pv_a);
+    a.rec0 = at<float4>(ws, L.rec0);
+    a.rec1 = at<float4>(ws, L.rec1);
+    a.col0 = at<float4>(ws, L.col0);
+    a.col1 = at<float4>(ws, L.col1);
+    a.n = (uint32_t)L.n;
+    a.width = L.width;
+    a.height = L.height;
+    a.tiles_x = L.tiles_x;
+    a.cutoff = k.cutoff;
+    a.alpha_min = k.alpha_min;
+    a.alpha_max = k.alpha_max;
+    a.t_min = k.t_min;
+    a.S = fwd.shading;
+    a.Sh = fwd.shadow;
+    a.R = fwd.residual;
+    a.dF = dF;
+    a.gsplat = gsplat;
+    a.gcol = gcol;
+    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)L.n_tiles), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* ws, const float* T,
+                             const float* num_den, const float* dT, float* dnum, float* gray, float* gsplat,
+                             hipStream_t st) {
+    if (L.n == 0) return hipSuccess;
+    ShadowBwdArgs a;
+    a.ranges = at<int2>(ws, L.ranges);
+    a.order = at<uint32_t>(ws, L.order);
+    a.list = at<uint32_t>(ws, L.pv_a);
+    a.rec0 = at<float4>(ws, L.rec0);
+    a.rec1 = at<float4>(ws, L.rec1);
+    a.depth = at<float>(ws, L.depth);
+    a.ext = at<int4>(ws, L.ext);
+    a.n = (uint32_t)L.n;
+    a.width = L.width;
+    a.height = L.height;
+    a.tiles_x = L.tiles_x;
+    a.cutoff = k.cutoff;
+    a.alpha_min = k.alpha_min;
+    a.alpha_max = k.alpha_max;
+    a.bias = k.shadow_bias;
+    a.T = T;
+    a.num_den = num_den;
+    a.dT = dT;
+    a.dnum = dnum;
+    a.gray = gray;
+    a.gsplat = gsplat;
+    int grid = (int)((L.n + 3) / 4);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_shadow_den_bwd, dim3(grid), dim3(256), 0, st, a);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(gray), 0u, (int64_t)L.width * L.height, st);
+    if (e != hipSuccess) return e;
+    if (L.n_tiles == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_shadow_bwd<0>, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_bwd<1>, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace gs3

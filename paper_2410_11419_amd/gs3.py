@@ -37,6 +37,7 @@ EXPORTED = [
     "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
+    "gs3_backward_workspace_size", "gs3_render_backward",
 ]
 
 
@@ -73,6 +74,13 @@ class gs3_images(C.Structure):
                 ("colour", C.c_void_p)]
 
 
+class gs3_grads(C.Structure):
+    _fields_ = [(nm, C.c_void_p) for nm in ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo",
+                                             "lobe_axis", "lobe_log_sharp", "lobe_amp", "feat")] + \
+               [("phi_w", C.c_void_p * 4), ("phi_b", C.c_void_p * 4), ("psi_w", C.c_void_p * 4),
+                ("psi_b", C.c_void_p * 4)]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2410_11419_amd.build`")
@@ -96,6 +104,11 @@ def _load():
         "gs3_shadow_den": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_num": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_resolve": (C.c_int, [P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
+        "gs3_backward_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, P(C.c_size_t)]),
+        "gs3_render_backward": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
+                                          C.c_void_p, P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_viewbuf),
+                                          P(gs3_images), C.c_void_p, P(gs3_grads), C.c_void_p, C.c_size_t,
+                                          C.c_void_p]),
         "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
                                  P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
     }
@@ -319,6 +332,61 @@ def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.
                            C.byref(cam_vb.vb), C.byref(im), _stream()), "gs3_render")
 
 
+class DeviceGrads:
+    """Gradient tensors shaped like a DeviceScene's (zeroed), for gs3_render_backward."""
+
+    def __init__(self, scene: DeviceScene, use_mlps: bool = True):
+        self.t = {nm: torch.zeros_like(v) for nm, v in scene.t.items()}
+
+        def mlp(m):
+            if m is None or not use_mlps:
+                return None
+            return [(torch.zeros_like(w), torch.zeros_like(b)) for w, b in m]
+        self.phi = mlp(scene.phi)
+        self.psi = mlp(scene.psi)
+
+    def c_struct(self) -> gs3_grads:
+        g = gs3_grads()
+        for nm, v in self.t.items():
+            setattr(g, nm, _ptr(v).value)
+        for mlp, wn, bn in ((self.phi, "phi_w", "phi_b"), (self.psi, "psi_w", "psi_b")):
+            if mlp is not None:
+                for i, (w, b) in enumerate(mlp):
+                    getattr(g, wn)[i] = _ptr(w).value
+                    getattr(g, bn)[i] = _ptr(b).value
+        return g
+
+
+def backward_workspace(n: int, light_width: int, light_height: int, device="cuda") -> torch.Tensor:
+    size = C.c_size_t()
+    _check(_lib.gs3_backward_workspace_size(n, light_width, light_height, C.byref(size)),
+           "gs3_backward_workspace_size")
+    return torch.empty(size.value + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned(buf: torch.Tensor):
+    base = buf.data_ptr()
+    off = (-base) % 256
+    return C.c_void_p(base + off), buf.numel() - off
+
+
+def gs3_render_backward(scene: DeviceScene, cam, light, consts: gs3_consts, T: torch.Tensor,
+                        num_den: torch.Tensor, light_vb: ViewBuffer, cam_vb: ViewBuffer,
+                        images: Dict[str, torch.Tensor], dL_dfinal: torch.Tensor, grads: DeviceGrads,
+                        ws: torch.Tensor, use_mlps: bool = True):
+    cv, lv = make_view(cam), make_view(light)
+    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
+    g = grads.c_struct()
+    wsp, wsb = _aligned(ws)
+    _check(_lib.gs3_render_backward(C.byref(scene.c_struct()), C.byref(cv), C.byref(lv), C.byref(consts), _ptr(T),
+                                    _ptr(num_den), C.byref(phi) if phi is not None else None,
+                                    C.byref(psi) if psi is not None else None, C.byref(light_vb.vb),
+                                    C.byref(cam_vb.vb), C.byref(im), _ptr(dL_dfinal), C.byref(g), wsp, wsb,
+                                    _stream()), "gs3_render_backward")
+
+
 # ------------------------------------------------------------- renderer
 
 class Renderer:
@@ -338,6 +406,7 @@ class Renderer:
         self.num_den = torch.empty(2, max(n, 1), device=self.dev)
         self.T = torch.empty(max(n, 1), device=self.dev)
         self.images: Dict[tuple, Dict[str, torch.Tensor]] = {}
+        self.bwd_ws: Optional[torch.Tensor] = None
 
     def _vb(self, role: str, w: int, h: int, capacity: int) -> ViewBuffer:
         key = (role, w, h)
@@ -392,6 +461,29 @@ class Renderer:
         out["num_den"] = self.num_den
         return out
 
+    def backward(self, cam, light, dL_dfinal: torch.Tensor, grads: Optional["DeviceGrads"] = None) -> "DeviceGrads":
+        """Adjoint of the last ``render(cam, light)`` of this renderer (its
+        buffers must not have been reused since): adds dL/d(parameters) for
+        the given dL/dfinal [3, H, W] into ``grads`` (new zeros if None)."""
+        if tuple(dL_dfinal.shape) != (3, cam.height, cam.width) or dL_dfinal.dtype != torch.float32:
+            raise ValueError(f"dL_dfinal must be float32 [3, {cam.height}, {cam.width}], got "
+                             f"{dL_dfinal.dtype} {tuple(dL_dfinal.shape)}")
+        if grads is None:
+            grads = DeviceGrads(self.scene, self.use_mlps)
+        if self.bwd_ws is None:
+            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev)
+        need = C.c_size_t()
+        _check(_lib.gs3_backward_workspace_size(self.scene.n, light.width, light.height, C.byref(need)),
+               "gs3_backward_workspace_size")
+        if self.bwd_ws.numel() < need.value + 256:
+            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev)
+        lvb = self.vbs[("light", light.width, light.height)]
+        cvb = self.vbs[("cam", cam.width, cam.height)]
+        gs3_render_backward(self.scene, cam, light, self.consts, self.T, self.num_den, lvb, cvb,
+                            self._images(cam.width, cam.height), dL_dfinal.contiguous(), grads, self.bwd_ws,
+                            self.use_mlps)
+        return grads
+
     def overflowed(self) -> bool:
         """True if any view's last binning exceeded its capacity (syncs)."""
         for vb in self.vbs.values():
@@ -402,3 +494,53 @@ class Renderer:
                     return True
                 raise
         return False
+
+
+# ------------------------------------------------------------ autograd
+
+SCENE_FIELDS = ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo", "lobe_axis",
+                "lobe_log_sharp", "lobe_amp", "feat")
+
+
+def scene_parameters(scene: DeviceScene) -> list:
+    """The tensors a RelitRender call differentiates: the scene's raw
+    parameters, then Phi's and Psi's (W, b) per layer."""
+    ps = [scene.t[nm] for nm in SCENE_FIELDS]
+    for m in (scene.phi, scene.psi):
+        if m is not None:
+            for w, b in m:
+                ps += [w, b]
+    return ps
+
+
+class RelitRender(torch.autograd.Function):
+    """final = render(scene, cam, light) with the hand-written adjoint
+    (gs3_render_backward) as its backward. ``renderer`` holds the forward
+    state until the backward runs, so use one Renderer per pending call
+    (e.g. one per element of a batch)."""
+
+    @staticmethod
+    def forward(ctx, renderer: "Renderer", cam, light, *params):
+        out = renderer.render(cam, light, check=True)
+        ctx.renderer, ctx.cam, ctx.light = renderer, cam, light
+        return out["final"].clone()
+
+    @staticmethod
+    def backward(ctx, dfinal):
+        r = ctx.renderer
+        g = r.backward(ctx.cam, ctx.light, dfinal)
+        outs = [g.t[nm] for nm in SCENE_FIELDS]
+        for gm, sm in ((g.phi, r.scene.phi), (g.psi, r.scene.psi)):
+            if sm is None:
+                continue
+            if gm is None:
+                outs += [None] * (2 * len(sm))
+            else:
+                for w, b in gm:
+                    outs += [w, b]
+        return (None, None, None, *outs)
+
+
+def relit_render(renderer: "Renderer", cam, light) -> torch.Tensor:
+    """Differentiable relit frame [3, H, W] (see RelitRender)."""
+    return RelitRender.apply(renderer, cam, light, *scene_parameters(renderer.scene))
