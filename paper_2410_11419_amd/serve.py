@@ -1,0 +1,221 @@
+"""Continuous-batching relight server over the gs3 library.
+
+Requests (camera view, point light, resolution) arrive over time; the scene
+stays resident in device memory. A request is admitted as soon as it has
+arrived and a buffer set for its resolution is free, or can be allocated
+without exceeding the memory cap; its whole pipeline (light preprocess,
+shadow splat, camera preprocess, shading + MLPs + camera splat) is enqueued
+on its own HIP stream, so requests that arrive while others are on the GPU
+run alongside them and the device overlaps their kernels. Completion is
+detected with events, without blocking the host; a finished request frees
+its buffer set for the next one. The plain baseline runs the same library
+calls one request at a time, first come first served, and waits for each.
+
+Latency of a request = completion time - arrival time (queueing included).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import gs3, synth
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    cam: synth.View
+    light: synth.View
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    start: float
+    done: float
+    final: Optional[torch.Tensor] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def make_requests(count: int, qps: float, seed: int = 3, resolutions=(256, 512, 800, 1024),
+                  light_res: int = 1024, fov: float = 40.0, radius: float = 4.0) -> List[Request]:
+    """Poisson arrivals at rate qps; camera and light uniform on the sphere
+    of the given radius; camera resolution uniform over `resolutions`."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, count) if qps > 0 else np.zeros(count)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(count):
+        r = int(resolutions[rng.integers(0, len(resolutions))])
+        cam = synth.make_view(rng.standard_normal(3), radius, r, r, fov)
+        light = synth.make_view(rng.standard_normal(3), radius, light_res, light_res, fov)
+        out.append(Request(i, float(t[i]), cam, light))
+    return out
+
+
+class BufferSet:
+    """Everything one in-flight request needs: a Renderer (view buffers, T,
+    num/den, images) bound to one camera resolution, and its own stream."""
+
+    def __init__(self, scene: gs3.DeviceScene, consts, res: int, light_res: int, capacity: int):
+        self.res = res
+        self.stream = torch.cuda.Stream()
+        self.renderer = gs3.Renderer(scene, consts, pair_capacity=capacity)
+        self.event = torch.cuda.Event()
+        with torch.cuda.stream(self.stream):
+            # allocate the buffers now, so admission accounting is exact
+            self.renderer._vb("light", light_res, light_res, capacity)
+            self.renderer._vb("cam", res, res, capacity)
+            self.renderer._images(res, res)
+        self.bytes = sum(vb.storage.numel() for vb in self.renderer.vbs.values()) + \
+            sum(t.numel() * t.element_size() for im in self.renderer.images.values() for t in im.values())
+
+
+class Server:
+    """Admission by a memory cap over per-resolution pools of buffer sets."""
+
+    def __init__(self, scene: gs3.DeviceScene, mem_cap_bytes: int, consts=None, light_res: int = 1024,
+                 capacity: Optional[int] = None, max_inflight: int = 8):
+        self.scene = scene
+        self.consts = consts if consts is not None else gs3.default_consts()
+        self.cap = int(mem_cap_bytes)
+        self.light_res = light_res
+        self.capacity = capacity or max(1 << 16, 32 * scene.n)
+        self.max_inflight = max_inflight
+        self.free: Dict[int, List[BufferSet]] = {}
+        self.allocated = 0
+        self.sets: List[BufferSet] = []
+
+    def _acquire(self, res: int) -> Optional[BufferSet]:
+        pool = self.free.setdefault(res, [])
+        if pool:
+            return pool.pop()
+        # estimate before allocating: one set per resolution is always allowed
+        probe = self.sets[0].bytes if self.sets else 0
+        if self.sets and self.allocated + probe > self.cap:
+            # try to reclaim an idle set of another resolution
+            for r, p in self.free.items():
+                if p:
+                    bs = p.pop()
+                    self.allocated -= bs.bytes
+                    self.sets.remove(bs)
+                    del bs
+                    break
+            else:
+                return None
+            if self.allocated + probe > self.cap:
+                return None
+        bs = BufferSet(self.scene, self.consts, res, self.light_res, self.capacity)
+        self.allocated += bs.bytes
+        self.sets.append(bs)
+        return bs
+
+    def _launch(self, req: Request, bs: BufferSet, keep: bool):
+        with torch.cuda.stream(bs.stream):
+            out = bs.renderer.render(req.cam, req.light, check=False)
+            final = out["final"].clone() if keep else None
+            bs.event.record(bs.stream)
+        return final
+
+    def _check_done(self, bs: BufferSet, req: Request, keep: bool) -> Optional[torch.Tensor]:
+        """After completion: a binning that overflowed its pair capacity is
+        rerun with a larger buffer (rare; synchronous)."""
+        with torch.cuda.stream(bs.stream):
+            # the request's own stream has finished, so this read waits for nothing
+            if not bs.renderer.overflowed():
+                return None
+            out = bs.renderer.render(req.cam, req.light, check=True)
+            final = out["final"].clone() if keep else None
+        bs.stream.synchronize()
+        return final
+
+    def run(self, requests: List[Request], keep_results: bool = False) -> List[Result]:
+        """Serve `requests` (sorted by arrival) in real time; returns one
+        Result per request in request order."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: deque = deque()
+        inflight: List[tuple] = []
+        results: Dict[int, Result] = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while pending or waiting or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            progressed = False
+            # completions
+            still = []
+            for req, bs, start, final in inflight:
+                if bs.event.query():
+                    redo = self._check_done(bs, req, keep_results)
+                    done = time.perf_counter() - t0
+                    results[req.rid] = Result(req.rid, req.arrival, start, done,
+                                              redo if redo is not None else final)
+                    self.free.setdefault(bs.res, []).append(bs)
+                    progressed = True
+                else:
+                    still.append((req, bs, start, final))
+            inflight = still
+            # admissions (first come first served; a request that cannot get
+            # memory waits, and so do the ones behind it)
+            while waiting and len(inflight) < self.max_inflight:
+                req = waiting[0]
+                bs = self._acquire(req.cam.width)
+                if bs is None:
+                    break
+                waiting.popleft()
+                start = time.perf_counter() - t0
+                final = self._launch(req, bs, keep_results)
+                inflight.append((req, bs, start, final))
+                progressed = True
+            if not progressed:
+                if inflight:
+                    time.sleep(20e-6)
+                elif pending:
+                    time.sleep(max(0.0, min(1e-3, pending[0].arrival - (time.perf_counter() - t0))))
+        return [results[r.rid] for r in requests]
+
+
+def run_plain(scene: gs3.DeviceScene, requests: List[Request], consts=None, light_res: int = 1024,
+              capacity: Optional[int] = None, keep_results: bool = False) -> List[Result]:
+    """One request at a time, first come first served, on one stream; the
+    host waits for each frame before starting the next."""
+    consts = consts if consts is not None else gs3.default_consts()
+    cap = capacity or max(1 << 16, 32 * scene.n)
+    rnd = gs3.Renderer(scene, consts, pair_capacity=cap)
+    out: Dict[int, Result] = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for req in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        start = time.perf_counter() - t0
+        o = rnd.render(req.cam, req.light, check=False)
+        final = o["final"].clone() if keep_results else None
+        torch.cuda.current_stream().synchronize()
+        if rnd.overflowed():
+            o = rnd.render(req.cam, req.light, check=True)
+            final = o["final"].clone() if keep_results else None
+            torch.cuda.current_stream().synchronize()
+        out[req.rid] = Result(req.rid, req.arrival, start, time.perf_counter() - t0, final)
+    return [out[r.rid] for r in requests]
+
+
+def summarize(results: List[Result]) -> Dict[str, float]:
+    lat = np.array([r.latency for r in results]) * 1e3
+    span = max(r.done for r in results) - min(r.arrival for r in results)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "frames_per_s": len(results) / span if span > 0 else math.inf,
+            "requests": len(results)}
