@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many frames (for rocprofv3), no JSON")
+    ap.add_argument("--train-steps", type=int, default=5, help="timed fwd+bwd steps (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=2000, help="requests per serving run (0: skip)")
+    ap.add_argument("--serving-loads", type=str, default="0.5,0.9",
+                    help="offered loads as fractions of the plain renderer's saturation rate")
+    ap.add_argument("--profile-train", action="store_true",
+                    help="only run two fwd+bwd steps (for rocprofv3), no JSON")
     return ap.parse_args()
 
 
@@ -107,6 +113,111 @@ def profiled_traffic():
         return int(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def train_step_bench(ds, sc, steps, warmup, profile=False):
+    """fwd+bwd steps/s: each step renders a batch of 4 (camera 800x800, light
+    1024x1024) pairs, takes the L1 loss against targets rendered from the
+    scene with means perturbed by N(0, 0.01) and colours by N(0, 0.05), and
+    runs the hand-written backward into one gradient buffer."""
+    import numpy as np
+    import torch
+    from paper_2410_11419_amd import gs3, synth
+    rng = np.random.default_rng(4)
+    pairs = [(synth.make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0),
+              synth.make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0)) for _ in range(8)]
+    tgt_scene = gs3.DeviceScene.from_host(synth.perturb_scene(sc, seed=5))
+    trnd = gs3.Renderer(tgt_scene)
+    targets = [trnd.render(c, l)["final"].clone() for c, l in pairs]
+    del trnd, tgt_scene
+    rnd = gs3.Renderer(ds)
+    grads = gs3.DeviceGrads(ds)
+    batch = 4
+    inv = 1.0 / (batch * 3 * 800 * 800)
+    stream = torch.cuda.current_stream()
+
+    def step(i, evs=None):
+        for t in grads.t.values():
+            t.zero_()
+        for m in (grads.phi, grads.psi):
+            for w, b in m:
+                w.zero_()
+                b.zero_()
+        for j in range(batch):
+            k = (i * batch + j) % len(pairs)
+            cam, light = pairs[k]
+            if evs is not None:
+                evs[j][0].record(stream)
+            out = rnd.render(cam, light, check=False)
+            dF = torch.sign(out["final"] - targets[k]) * inv
+            if evs is not None:
+                evs[j][1].record(stream)
+            rnd.backward(cam, light, dF, grads)
+            if evs is not None:
+                evs[j][2].record(stream)
+
+    for i in range(max(1, warmup)):
+        for j in range(batch):
+            cam, light = pairs[(i * batch + j) % len(pairs)]
+            rnd.render(cam, light, check=True)
+        step(i)
+    torch.cuda.synchronize()
+    if profile:
+        for i in range(2):
+            step(i)
+        torch.cuda.synchronize()
+        print("profiled 2 fwd+bwd steps")
+        return None
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(batch)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if rnd.overflowed():
+        raise RuntimeError("a binning exceeded its pair capacity inside the timed train steps")
+    fwd = sum(e[0].elapsed_time(e[1]) for st in evs for e in st) / steps
+    bwd = sum(e[1].elapsed_time(e[2]) for st in evs for e in st) / steps
+    return {"metric": "fwd+bwd steps/s", "value": round(steps / wall, 3), "unit": "steps/s",
+            "ms_per_step": round(1e3 * wall / steps, 3), "steps": steps, "batch": batch,
+            "workload": "300,000 Gaussians, batch of 4 (camera 800x800, light 1024x1024) pairs, L1 loss against "
+                        "targets from the scene with means + N(0,0.01) and colours + N(0,0.05)",
+            "stages_ms_per_step": {"forward_and_loss": round(fwd, 3), "backward": round(bwd, 3)}}
+
+
+def serving_bench(ds, requests, loads):
+    """Continuous-batching server vs the plain one-request-at-a-time renderer
+    on the same GPU: saturation throughput and p50/p99 latency at offered
+    loads given as fractions of the plain renderer's saturation rate."""
+    import torch
+    from paper_2410_11419_amd import serve
+    warm = serve.make_requests(16, qps=1e6, seed=9)
+    serve.run_plain(ds, warm)
+    srv = serve.Server(ds, mem_cap_bytes=24 << 30)
+    srv.run(warm)
+    burst = serve.make_requests(requests, qps=1e6, seed=3)
+    plain_sat = serve.summarize(serve.run_plain(ds, burst))
+    server_sat = serve.summarize(srv.run(burst))
+    out = {"requests": requests,
+           "workload": "300,000 Gaussians resident; camera and light uniform on the radius-4 sphere; camera "
+                       "resolution uniform over 256^2, 512^2, 800^2, 1024^2; light 1024^2 at 40 deg; Poisson arrivals",
+           "mem_cap_GB": 24, "buffer_sets": None,
+           "saturation_frames_per_s": {"plain": round(plain_sat["frames_per_s"], 1),
+                                       "server": round(server_sat["frames_per_s"], 1)},
+           "loads": []}
+    for f in loads:
+        qps = f * plain_sat["frames_per_s"]
+        rq = serve.make_requests(requests, qps=qps, seed=3)
+        a = serve.summarize(serve.run_plain(ds, rq))
+        b = serve.summarize(srv.run(rq))
+        out["loads"].append({"load": f, "qps": round(qps, 1),
+                             "plain": {k: round(v, 3) for k, v in a.items() if k != "requests"},
+                             "server": {k: round(v, 3) for k, v in b.items() if k != "requests"}})
+    out["buffer_sets"] = len(srv.sets)
+    del srv
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(n):
@@ -170,6 +281,9 @@ def main():
     sc, _, _ = synth.scene_full(n=args.n)
     ds = gs3.DeviceScene.from_host(sc, dev)
     pairs = views()
+    if args.profile_train:
+        train_step_bench(ds, sc, 0, 1, profile=True)
+        return
     rnd = gs3.Renderer(ds)
     # warm-up: sizes every view buffer (host sync allowed here)
     for i in range(max(args.warmup, len(pairs))):
@@ -273,6 +387,12 @@ def main():
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),
                       "frac_of_8TBs": round(frame_gbs / HBM_PEAK_GBS, 4)},
     }
+    if args.train_steps > 0:
+        out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
+    if args.serving_requests > 0:
+        del rnd
+        out["serving"] = serving_bench(ds, args.serving_requests,
+                                       [float(x) for x in args.serving_loads.split(",") if x])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))
