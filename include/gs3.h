@@ -288,6 +288,23 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam,
                const gs3_viewbuf* cam_vb, const gs3_images* out,
                gs3_stream_t stream);
 
+/* The two halves of gs3_render, callable apart so that the part that does
+ * not depend on the shadow values can run before (or alongside) the shadow
+ * splat; gs3_render is exactly gs3_shade then gs3_render_shaded.
+ *   gs3_shade          Sec. 4.1 (Eq. 4-7) and Sec. 4.3: per-Gaussian colour
+ *                      c and residual r (Psi, r = 0 if psi is NULL) into
+ *                      `cam_vb` and colour rows 0-2 and 4-7.
+ *   gs3_render_shaded  Sec. 4.2 (Eq. 8): T' = Phi(T) (T' = T if phi is
+ *                      NULL) into cam_vb and colour row 3, then the camera
+ *                      splat of Fig. 2 and final = S * Sh + R. Needs the
+ *                      gs3_shade of the same camera and light first.
+ * Arguments, layouts and errors as in gs3_render. */
+int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+              const gs3_mlp* psi, const gs3_viewbuf* cam_vb, float* colour, gs3_stream_t stream);
+int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+                      const gs3_consts* consts, const float* T, const gs3_mlp* phi,
+                      const gs3_viewbuf* cam_vb, const gs3_images* out, gs3_stream_t stream);
+
 /* Bytes of device workspace gs3_render_backward needs for n Gaussians and
  * a light image of light_width x light_height: per-Gaussian splat and
  * colour gradients, per-light-pixel sums, and the MLP activations kept for

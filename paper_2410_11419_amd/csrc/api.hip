@@ -47,7 +47,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.tiles_y = (height + kTile - 1) / kTile;
     l.n_tiles = (int64_t)l.tiles_x * l.tiles_y;
     l.capacity = capacity;
-    l.nblk_n = (n + kSortItems - 1) / kSortItems;
+    l.nblk_n = (n + kSortItemsN - 1) / kSortItemsN;
     l.nblk_p = (capacity + kSortItems - 1) / kSortItems;
     const int64_t nblk = l.nblk_n > l.nblk_p ? l.nblk_n : l.nblk_p;
     l.table_len = nblk * kRadixBins;
@@ -354,24 +354,21 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float*
     return GS3_OK;
 }
 
-int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_consts* consts,
-               const float* T, const gs3_mlp* phi, const gs3_mlp* psi, const gs3_viewbuf* cam_vb,
-               const gs3_images* out, gs3_stream_t stream) {
-    Layout L;
+static int render_args(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+                       const gs3_consts* consts, const gs3_viewbuf* cam_vb, Layout* L) {
     int st;
-    if ((st = check_vb(cam_vb, &L)) != GS3_OK) return st;
+    if ((st = check_vb(cam_vb, L)) != GS3_OK) return st;
     if ((st = check_scene(scene, true)) != GS3_OK) return st;
-    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if (consts && (st = check_consts(consts)) != GS3_OK) return st;
     if (scene->n != cam_vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbuf.n");
-    if (!cam || cam->width != L.width || cam->height != L.height)
+    if (!cam || cam->width != L->width || cam->height != L->height)
         return fail(GS3_INVALID_ARG, "camera view missing or its size differs from the view buffer");
     if (!light_pos) return fail(GS3_INVALID_ARG, "light_pos is NULL");
-    if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
-        !out->n_contrib || !out->colour)
-        return fail(GS3_INVALID_ARG, "an output pointer is NULL");
-    if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
-    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
-    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    return GS3_OK;
+}
+
+static ShadeParams shade_params(const gs3_view* cam, const double* light_pos, const gs3_mlp* phi,
+                                const gs3_mlp* psi) {
     ShadeParams sp;
     for (int i = 0; i < 3; ++i) {
         sp.light[i] = (float)light_pos[i];
@@ -379,8 +376,57 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_
     }
     sp.use_phi = phi != nullptr;
     sp.use_psi = psi != nullptr;
+    return sp;
+}
+
+int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_consts* consts,
+               const float* T, const gs3_mlp* phi, const gs3_mlp* psi, const gs3_viewbuf* cam_vb,
+               const gs3_images* out, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = render_args(scene, cam, light_pos, consts, cam_vb, &L)) != GS3_OK) return st;
+    if (!consts) return fail(GS3_INVALID_ARG, "consts is NULL");
+    if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
+        !out->n_contrib || !out->colour)
+        return fail(GS3_INVALID_ARG, "an output pointer is NULL");
+    if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
+    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
+    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    const ShadeParams sp = shade_params(cam, light_pos, phi, psi);
     hipStream_t s = (hipStream_t)stream;
-    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, cam_vb->ws, out->colour, s));
+    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, cam_vb->ws, out->colour, 3, s));
+    GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
+    return GS3_OK;
+}
+
+int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_mlp* psi,
+              const gs3_viewbuf* cam_vb, float* colour, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = render_args(scene, cam, light_pos, nullptr, cam_vb, &L)) != GS3_OK) return st;
+    if (!colour) return fail(GS3_INVALID_ARG, "colour is NULL");
+    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    const ShadeParams sp = shade_params(cam, light_pos, nullptr, psi);
+    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, nullptr, nullptr, psi, L, cam_vb->ws, colour, 1,
+                                   (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+                      const gs3_consts* consts, const float* T, const gs3_mlp* phi, const gs3_viewbuf* cam_vb,
+                      const gs3_images* out, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = render_args(scene, cam, light_pos, consts, cam_vb, &L)) != GS3_OK) return st;
+    if (!consts) return fail(GS3_INVALID_ARG, "consts is NULL");
+    if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
+        !out->n_contrib || !out->colour)
+        return fail(GS3_INVALID_ARG, "an output pointer is NULL");
+    if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
+    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
+    const ShadeParams sp = shade_params(cam, light_pos, phi, nullptr);
+    hipStream_t s = (hipStream_t)stream;
+    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, nullptr, L, cam_vb->ws, out->colour, 2, s));
     GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
     return GS3_OK;
 }

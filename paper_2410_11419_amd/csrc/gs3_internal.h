@@ -14,7 +14,8 @@ constexpr int kTile = 16;          // tile edge in pixels
 constexpr int kBlock = 256;        // threads per tile workgroup (4 wave64)
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kSortItems = 4096;   // items per radix / scan workgroup
+constexpr int kSortItems = 4096;   // items per radix (pair sort) / scan workgroup
+constexpr int kSortItemsN = 1024;  // items per radix workgroup of the depth sort of the N splats
 constexpr int kFeat = 16;          // per-Gaussian MLP feature size
 constexpr int kHidden = 64;        // MLP hidden width
 constexpr int kMaxLobes = 16;
@@ -97,9 +98,10 @@ struct ShadeParams {
     float eye[3];
     int32_t use_phi, use_psi;
 };
+// parts: 1 = shading c and Psi's r, 2 = Phi's T', 3 = both
 hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T,
                             const gs3_mlp* phi, const gs3_mlp* psi, const Layout& L,
-                            void* ws, float* colour_out, hipStream_t st);
+                            void* ws, float* colour_out, int parts, hipStream_t st);
 hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws,
                          const gs3_images& out, hipStream_t st);
 // Device pointers of the scene gradients (+=), mirror of SceneDev.

@@ -10,11 +10,16 @@
 
 namespace gs3 {
 
+// Which parts a launch computes: the shading c and Psi's residual r (they do
+// not depend on the shadow values) and/or Phi's refined shadow T'.
+enum ShadeParts { kShadePsi = 1, kShadePhi = 2 };
+
 struct ShadeArgs {
     SceneDev sc;
     float light[3];
     float eye[3];
     int use_phi, use_psi;
+    int parts;
     const float* T;
     MlpArgs phi, psi;
     float4* col0;
@@ -37,12 +42,15 @@ __global__ __launch_bounds__(512) void k_shade_mlp(ShadeArgs a) {
         const int g_raw = base + (lane & 15);
         const bool valid = g_raw < n;
         const int g = valid ? g_raw : n - 1;
+        float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+        float wix = 0.f, wiy = 0.f, wiz = 0.f, wox = 0.f, woy = 0.f, woz = 0.f;
+        if (a.parts & kShadePsi) {
         // ---- shading (Eq. 4-7)
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
-        float wix = a.light[0] - mx, wiy = a.light[1] - my, wiz = a.light[2] - mz;
+        wix = a.light[0] - mx; wiy = a.light[1] - my; wiz = a.light[2] - mz;
         float r = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
         wix *= r; wiy *= r; wiz *= r;
-        float wox = a.eye[0] - mx, woy = a.eye[1] - my, woz = a.eye[2] - mz;
+        wox = a.eye[0] - mx; woy = a.eye[1] - my; woz = a.eye[2] - mz;
         r = rsqrtf(wox * wox + woy * woy + woz * woz);
         wox *= r; woy *= r; woz *= r;
         float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
@@ -91,13 +99,15 @@ __global__ __launch_bounds__(512) void k_shade_mlp(ShadeArgs a) {
         sp0 += __shfl_xor(sp0, 16, 64); sp0 += __shfl_xor(sp0, 32, 64);
         sp1 += __shfl_xor(sp1, 16, 64); sp1 += __shfl_xor(sp1, 32, 64);
         sp2 += __shfl_xor(sp2, 16, 64); sp2 += __shfl_xor(sp2, 32, 64);
-        const float c0 = fmaf(sc.albedo[g], fd, sp0);
-        const float c1 = fmaf(sc.albedo[n + g], fd, sp1);
-        const float c2 = fmaf(sc.albedo[2 * n + g], fd, sp2);
+        c0 = fmaf(sc.albedo[g], fd, sp0);
+        c1 = fmaf(sc.albedo[n + g], fd, sp1);
+        c2 = fmaf(sc.albedo[2 * n + g], fd, sp2);
+        }
         // ---- shadow refinement Phi([T, feat]) (Eq. 8)
-        const float Tg = a.T[g];
-        float tp = Tg;
-        if (a.use_phi) {
+        float tp = 0.f;
+        if (a.parts & kShadePhi) tp = a.T[g];
+        if ((a.parts & kShadePhi) && a.use_phi) {
+            const float Tg = tp;
             floatx4 h[4];
             auto xin = [&](int k) -> float {
                 if (k == 0) return Tg;
@@ -109,7 +119,7 @@ __global__ __launch_bounds__(512) void k_shade_mlp(ShadeArgs a) {
         }
         // ---- residual Psi([feat, w_i, w_o]) (Sec. 4.3)
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-        if (a.use_psi) {
+        if ((a.parts & kShadePsi) && a.use_psi) {
             floatx4 h[4];
             auto xin = [&](int k) -> float {
                 if (k < kFeat) return sc.feat[(size_t)k * n + g];
@@ -129,23 +139,42 @@ __global__ __launch_bounds__(512) void k_shade_mlp(ShadeArgs a) {
             r2 = mlp_out(sm, kPsiS, lane, h, 2);
         }
         if (valid) {
-            if (q == 0) {
-                a.col0[g] = make_float4(c0, c1, c2, tp);
-                a.col1[g] = make_float4(r0, r1, r2, 0.f);
+            float* c0p = reinterpret_cast<float*>(a.col0 + g);
+            if (a.parts == (kShadePsi | kShadePhi)) {
+                if (q == 0) {
+                    a.col0[g] = make_float4(c0, c1, c2, tp);
+                    a.col1[g] = make_float4(r0, r1, r2, 0.f);
+                }
+                const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
+                const float v1 = q == 0 ? c1 : (q == 1 ? tp : (q == 2 ? r1 : 0.f));
+                a.colour[(size_t)(2 * q) * n + g] = v0;
+                a.colour[(size_t)(2 * q + 1) * n + g] = v1;
+            } else if (a.parts == kShadePsi) {
+                // colour rows 0..2 (c), 4..6 (r), 7 (0); col0.w is Phi's
+                if (q == 0) {
+                    c0p[0] = c0;
+                    c0p[1] = c1;
+                    c0p[2] = c2;
+                    a.col1[g] = make_float4(r0, r1, r2, 0.f);
+                }
+                const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
+                a.colour[(size_t)(2 * q) * n + g] = v0;
+                if (q != 1) a.colour[(size_t)(2 * q + 1) * n + g] = q == 0 ? c1 : (q == 2 ? r1 : 0.f);
+            } else if (q == 0) {
+                c0p[3] = tp;
+                a.colour[(size_t)3 * n + g] = tp;
             }
-            const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
-            const float v1 = q == 0 ? c1 : (q == 1 ? tp : (q == 2 ? r1 : 0.f));
-            a.colour[(size_t)(2 * q) * n + g] = v0;
-            a.colour[(size_t)(2 * q + 1) * n + g] = v1;
         }
     }
 }
 
 hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
-                            const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, hipStream_t st) {
+                            const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, int parts,
+                            hipStream_t st) {
     if (sc.n == 0) return hipSuccess;
     ShadeArgs a;
     a.sc = sc;
+    a.parts = parts;
     for (int i = 0; i < 3; ++i) {
         a.light[i] = sp.light[i];
         a.eye[i] = sp.eye[i];

@@ -122,8 +122,9 @@ static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t len,
 
 // ---------------------------------------------------------------- radix
 
-// Per-block digit histogram of keys[base .. base+4096), written digit-major
+// Per-block digit histogram of keys[base .. base+ITEMS), written digit-major
 // into table[digit * nblk + block]. n is read from *n_dev when given.
+template <int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                      uint32_t n_host, int shift, uint32_t* __restrict__ table, int nblk) {
     __shared__ uint32_t h[4][kRadixBins];
@@ -131,10 +132,10 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&h[0][0])[i] = 0u;
     __syncthreads();
     const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint32_t base = blockIdx.x * (uint32_t)kSortItems;
+    const uint32_t base = blockIdx.x * (uint32_t)ITEMS;
     if (base < n) {
 #pragma unroll 4
-        for (int r = 0; r < kSortItems / 256; ++r) {
+        for (int r = 0; r < ITEMS / 256; ++r) {
             const uint32_t idx = base + r * 256 + tid;
             if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
         }
@@ -143,16 +144,17 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int d = tid; d < kRadixBins; d += 256) table[d * nblk + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// Stable scatter: each block ranks its 4096 items by digit (ties keep input
+// Stable scatter: each block ranks its ITEMS items by digit (ties keep input
 // order), stages them digit-sorted in LDS, and writes each digit run to its
 // global offset (table holds the exclusive scan of the digit-major
 // histogram).
+template <int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                         const uint32_t* __restrict__ table, int nblk) {
-    __shared__ uint32_t s_key[kSortItems];
-    __shared__ uint32_t s_val[kSortItems];
+    __shared__ uint32_t s_key[ITEMS];
+    __shared__ uint32_t s_val[ITEMS];
     __shared__ uint32_t s_cnt[4][kRadixBins];
     __shared__ uint32_t s_run[kRadixBins];
     __shared__ uint32_t s_lstart[kRadixBins];
@@ -160,16 +162,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     __shared__ uint32_t s_wave[4];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint32_t base = blockIdx.x * (uint32_t)kSortItems;
+    const uint32_t base = blockIdx.x * (uint32_t)ITEMS;
     if (base >= n) return;   // whole block beyond the data: uniform exit
-    const uint32_t count = (n - base) < (uint32_t)kSortItems ? (n - base) : (uint32_t)kSortItems;
+    const uint32_t count = (n - base) < (uint32_t)ITEMS ? (n - base) : (uint32_t)ITEMS;
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
     for (int d = tid; d < kRadixBins; d += 256) {
         s_run[d] = 0u;
         s_gstart[d] = table[d * nblk + blockIdx.x];
     }
     __syncthreads();
-    constexpr int R = kSortItems / 256;
+    constexpr int R = ITEMS / 256;
     uint32_t key[R], val[R], rank[R];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < R; ++r) {
@@ -225,15 +227,18 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     }
 }
 
+// One stable LSD pass over 8 bits. ITEMS per workgroup: the table has
+// ceil(max_items / ITEMS) * 256 entries (the layout sizes it for both sorts).
+template <int ITEMS>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
                              uint32_t* table, uint32_t* sums, hipStream_t st) {
-    const int nblk = (int)((max_items + kSortItems - 1) / kSortItems);
+    const int nblk = (int)((max_items + ITEMS - 1) / ITEMS);
     if (nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
+    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
     hipError_t e = exclusive_scan(table, table, (int64_t)nblk * kRadixBins, sums, nullptr, 0, nullptr, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev, n_host,
+    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev, n_host,
                        shift, table, nblk);
     return hipGetLastError();
 }
@@ -360,10 +365,12 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     uint32_t* offs = at<uint32_t>(ws, L.offs);
     const uint32_t n = (uint32_t)L.n;
     hipError_t e;
-    // 1. depth order: 4 stable 8-bit passes over the 32-bit depth keys
+    // 1. depth order: 4 stable 8-bit passes over the 32-bit depth keys, 1024
+    //    keys per workgroup (N is small next to the pair count: more, shorter
+    //    workgroups)
     for (int pass = 0; pass < 4; ++pass) {
         const bool even = (pass & 1) == 0;
-        e = radix_pass(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
+        e = radix_pass<kSortItemsN>(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
                        even ? vals_b : vals_a, nullptr, n, L.n, pass * 8, table, sums, st);
         if (e != hipSuccess) return e;
     }
@@ -392,7 +399,7 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     const uint32_t* n_dev = &hdr->n_pairs;
     for (int pass = 0; pass < tile_passes; ++pass) {
         const bool from_b = ((pass & 1) == 0) == start_b;
-        e = radix_pass(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b, from_b ? pv_a : pv_b,
+        e = radix_pass<kSortItems>(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b, from_b ? pv_a : pv_b,
                        n_dev, 0u, L.capacity, pass * kRadixBits, table, sums, st);
         if (e != hipSuccess) return e;
     }

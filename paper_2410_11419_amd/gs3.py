@@ -37,7 +37,7 @@ EXPORTED = [
     "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
-    "gs3_backward_workspace_size", "gs3_render_backward",
+    "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
 ]
 
 
@@ -104,6 +104,10 @@ def _load():
         "gs3_shadow_den": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_num": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_resolve": (C.c_int, [P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
+        "gs3_shade": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_mlp), P(gs3_viewbuf),
+                                C.c_void_p, C.c_void_p]),
+        "gs3_render_shaded": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
+                                        P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
         "gs3_backward_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, P(C.c_size_t)]),
         "gs3_render_backward": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                           C.c_void_p, P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_viewbuf),
@@ -332,6 +336,26 @@ def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.
                            C.byref(cam_vb.vb), C.byref(im), _stream()), "gs3_render")
 
 
+def gs3_shade(scene: DeviceScene, cam, light_pos, cam_vb: ViewBuffer, colour: torch.Tensor, use_mlps: bool = True):
+    v = make_view(cam)
+    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    _check(_lib.gs3_shade(C.byref(scene.c_struct()), C.byref(v), C.byref(lp),
+                          C.byref(psi) if psi is not None else None, C.byref(cam_vb.vb), _ptr(colour), _stream()),
+           "gs3_shade")
+
+
+def gs3_render_shaded(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
+                      images: Dict[str, torch.Tensor], use_mlps: bool = True):
+    v = make_view(cam)
+    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
+    im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
+    _check(_lib.gs3_render_shaded(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
+                                  C.byref(phi) if phi is not None else None, C.byref(cam_vb.vb), C.byref(im),
+                                  _stream()), "gs3_render_shaded")
+
+
 class DeviceGrads:
     """Gradient tensors shaped like a DeviceScene's (zeroed), for gs3_render_backward."""
 
@@ -407,6 +431,7 @@ class Renderer:
         self.T = torch.empty(max(n, 1), device=self.dev)
         self.images: Dict[tuple, Dict[str, torch.Tensor]] = {}
         self.bwd_ws: Optional[torch.Tensor] = None
+        self.side = None
 
     def _vb(self, role: str, w: int, h: int, capacity: int) -> ViewBuffer:
         key = (role, w, h)
@@ -447,13 +472,62 @@ class Renderer:
             self.images[key] = im
         return im
 
-    def render(self, cam, light, check: bool = True) -> Dict[str, torch.Tensor]:
+    def render(self, cam, light, check: bool = True, overlap: bool = True,
+               events: Optional[Dict[str, torch.cuda.Event]] = None) -> Dict[str, torch.Tensor]:
         """Relit frame for camera view ``cam`` and the point light of view
         ``light`` (its eye is the light position). ``check`` verifies (with a
-        host sync) that no binning overflowed its pair capacity."""
-        lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
-        gs3_shadow_splat(self.consts, lvb, self.num_den, self.T)
-        cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
+        host sync) that no binning overflowed its pair capacity.
+
+        With ``overlap`` the independent parts of the frame run on two side
+        streams (default priority) joined by events: the camera preprocess
+        from the start of the frame, the shadow denominator once the light
+        lists exist, while the caller's stream runs the light preprocess and
+        the shadow numerator, then the resolve and the camera pass; the
+        shading and Psi (independent of the shadow values) run on the camera
+        side stream, only Phi waits for the resolve. The
+        numerator's tail occupies few CUs, which the other two fill. Results
+        are the same as with ``overlap=False`` (one stream, in order).
+        ``events`` (optional) gets "num0"/"num1" recorded around the shadow
+        numerator on the caller's stream."""
+        main = torch.cuda.current_stream()
+        if not overlap or check:
+            lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
+            gs3_shadow_den(self.consts, lvb, self.num_den)
+            if events is not None:
+                events["num0"].record(main)
+            gs3_shadow_num(self.consts, lvb, self.num_den)
+            if events is not None:
+                events["num1"].record(main)
+            gs3_shadow_resolve(lvb, self.num_den, self.T)
+            cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
+        else:
+            if self.side is None:
+                self.side = (torch.cuda.Stream(), torch.cuda.Stream())
+            s_den, s_cam = self.side
+            # both side streams start after everything already on the caller's
+            # stream (the previous frame still reads these buffers)
+            im = self._images(cam.width, cam.height)
+            s_cam.wait_stream(main)
+            with torch.cuda.stream(s_cam):
+                cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
+                gs3_shade(self.scene, cam, light.eye, cvb, im["colour"], self.use_mlps)
+            lvb = self._preprocess("light", light, GS3_DEPTH_DIST, False)
+            s_den.wait_stream(main)
+            with torch.cuda.stream(s_den):
+                gs3_shadow_den(self.consts, lvb, self.num_den)
+            if events is not None:
+                events["num0"].record(main)
+            gs3_shadow_num(self.consts, lvb, self.num_den)
+            if events is not None:
+                events["num1"].record(main)
+            main.wait_stream(s_den)
+            gs3_shadow_resolve(lvb, self.num_den, self.T)
+            main.wait_stream(s_cam)
+            gs3_render_shaded(self.scene, cam, light.eye, self.consts, self.T, cvb, im, self.use_mlps)
+            out = dict(im)
+            out["T"] = self.T
+            out["num_den"] = self.num_den
+            return out
         im = self._images(cam.width, cam.height)
         gs3_render(self.scene, cam, light.eye, self.consts, self.T, cvb, im, self.use_mlps)
         out = dict(im)

@@ -86,13 +86,14 @@ class Server:
     """Admission by a memory cap over per-resolution pools of buffer sets."""
 
     def __init__(self, scene: gs3.DeviceScene, mem_cap_bytes: int, consts=None, light_res: int = 1024,
-                 capacity: Optional[int] = None, max_inflight: int = 8):
+                 capacity: Optional[int] = None, max_inflight: int = 8, overlap: bool = False):
         self.scene = scene
         self.consts = consts if consts is not None else gs3.default_consts()
         self.cap = int(mem_cap_bytes)
         self.light_res = light_res
         self.capacity = capacity or max(1 << 16, 32 * scene.n)
         self.max_inflight = max_inflight
+        self.overlap = overlap          # also overlap the stages inside each request
         self.free: Dict[int, List[BufferSet]] = {}
         self.allocated = 0
         self.sets: List[BufferSet] = []
@@ -123,7 +124,7 @@ class Server:
 
     def _launch(self, req: Request, bs: BufferSet, keep: bool):
         with torch.cuda.stream(bs.stream):
-            out = bs.renderer.render(req.cam, req.light, check=False)
+            out = bs.renderer.render(req.cam, req.light, check=False, overlap=self.overlap)
             final = out["final"].clone() if keep else None
             bs.event.record(bs.stream)
         return final
@@ -188,9 +189,10 @@ class Server:
 
 
 def run_plain(scene: gs3.DeviceScene, requests: List[Request], consts=None, light_res: int = 1024,
-              capacity: Optional[int] = None, keep_results: bool = False) -> List[Result]:
-    """One request at a time, first come first served, on one stream; the
-    host waits for each frame before starting the next."""
+              capacity: Optional[int] = None, keep_results: bool = False, overlap: bool = True) -> List[Result]:
+    """One request at a time, first come first served; the host waits for
+    each frame before starting the next. Each frame uses the renderer's own
+    stage overlap (``overlap``)."""
     consts = consts if consts is not None else gs3.default_consts()
     cap = capacity or max(1 << 16, 32 * scene.n)
     rnd = gs3.Renderer(scene, consts, pair_capacity=cap)
@@ -202,9 +204,9 @@ def run_plain(scene: gs3.DeviceScene, requests: List[Request], consts=None, ligh
         if req.arrival > now:
             time.sleep(req.arrival - now)
         start = time.perf_counter() - t0
-        o = rnd.render(req.cam, req.light, check=False)
+        o = rnd.render(req.cam, req.light, check=False, overlap=overlap)
         final = o["final"].clone() if keep_results else None
-        torch.cuda.current_stream().synchronize()
+        torch.cuda.synchronize()
         if rnd.overflowed():
             o = rnd.render(req.cam, req.light, check=True)
             final = o["final"].clone() if keep_results else None

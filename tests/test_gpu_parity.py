@@ -225,3 +225,26 @@ def test_render_edge_cases(gs3):
     sub = synth.subset(sc, np.arange(500))
     _compare_render(gs3, sub, tiny, small_light, O.Consts(), gs3.default_consts(), False, "tiny",
                     nonempty=False)
+
+
+def test_render_overlapped_streams_match_serial(gs3):
+    # Renderer.render(overlap=True) runs the camera preprocess and the shadow
+    # denominator on side streams; over consecutive frames of different views
+    # it must give the serial result (the numerator's float atomics may add
+    # in another order: 1e-6 tolerance)
+    sc = synth.make_scene(20000, 8, seed=8, means="shell", mlps=True)
+    ds = gs3.DeviceScene.from_host(sc)
+    views = [(synth.make_view(np.random.default_rng(s).standard_normal(3), 4.0, 160, 120, 40.0),
+              synth.make_view(np.random.default_rng(s + 50).standard_normal(3), 4.0, 192, 192, 40.0))
+             for s in range(3)]
+    a = gs3.Renderer(ds)
+    b = gs3.Renderer(ds)
+    for cam, light in views:       # size buffers, check capacity
+        a.render(cam, light, check=True)
+        b.render(cam, light, check=True)
+    for cam, light in views * 2:
+        ra = {k: v.clone() for k, v in a.render(cam, light, check=False, overlap=True).items()}
+        rb = b.render(cam, light, check=False, overlap=False)
+        torch.cuda.synchronize()
+        for key in ("final", "S", "Sh", "R", "T_final", "T"):
+            assert float((ra[key] - rb[key]).abs().max()) <= 1e-6, key
