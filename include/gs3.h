@@ -211,8 +211,14 @@ int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx,
             const int32_t* ry, const float* depth, const gs3_viewbuf* vb,
             gs3_stream_t stream);
 
-/* gs3_project followed by binning of the projected splats (steps a1+a2 for
- * the light view, a7+a8 for the camera view). */
+/* Sec. 3 (steps a2 / a8): bin and sort the splats the last gs3_project
+ * stored in `vb`, exactly as gs3_preprocess does after projecting. Split
+ * out so that work that needs only the projected splats (the shadow
+ * denominator) can run while the binning does. Errors as gs3_bin. */
+int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream);
+
+/* gs3_project followed by gs3_sort (steps a1+a2 for the light view, a7+a8
+ * for the camera view). */
 int gs3_preprocess(const gs3_scene* scene, const gs3_view* view,
                    const gs3_consts* consts, int32_t depth_mode,
                    const gs3_viewbuf* vb, gs3_stream_t stream);

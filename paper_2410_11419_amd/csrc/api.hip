@@ -257,14 +257,19 @@ int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx, const int32
     return GS3_OK;
 }
 
+int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream) {
+    Layout L;
+    int st;
+    if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
+    return GS3_OK;
+}
+
 int gs3_preprocess(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
                    const gs3_viewbuf* vb, gs3_stream_t stream) {
     int st = gs3_project(scene, view, consts, depth_mode, vb, stream);
     if (st != GS3_OK) return st;
-    Layout L;
-    make_layout(vb->n, vb->width, vb->height, vb->pair_capacity, &L);
-    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
-    return GS3_OK;
+    return gs3_sort(vb, stream);
 }
 
 int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t stream) {

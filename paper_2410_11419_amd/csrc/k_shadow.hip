@@ -46,6 +46,15 @@ struct ShadowArgs {
 };
 
 // 128-bit set of batch entries (two 64-bit halves).
+// The lists, pointers and distances a wave walks are the same in every
+// lane; reading such a value through readfirstlane tells the compiler so,
+// which keeps the pointer arithmetic and loop control in scalar registers
+// and scalar branches.
+__device__ inline float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
 struct Bits128 {
     unsigned long long lo, hi;
 };
@@ -76,6 +85,7 @@ __device__ inline void clear_bit(Bits128& b, int k) {
 __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
     __shared__ Staged s_rec[2 * kShadowBatch];
     __shared__ uint32_t s_id[2 * kShadowBatch];
+    __shared__ float s_sum[kShadowBatch];        // lead sums of the current batch
     const int tile = (int)a.order[blockIdx.x >> 2];
     const int qd = blockIdx.x & 3;
     const int2 rg = a.ranges[tile];
@@ -97,6 +107,20 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
         const float q = splat_q(k, pxc, pyc);
         if (alive && q >= k.g1.y) tt *= 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
     };
+    // A global atomic without a returned value still counts as an
+    // outstanding vector memory operation, so the next wait for a load would
+    // wait for it too: the lead sums of a batch collect in LDS and go out
+    // in one burst of atomics when the batch ends.
+    auto flush = [&](int base, int m) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            if (jj < m) {
+                const float v = s_sum[jj];
+                if (v != 0.f) atomicAdd(&a.num[s_id[base + jj]], v);
+            }
+        }
+    };
     for (int b = s; b < e; b += kShadowBatch) {
         const int m = min(kShadowBatch, e - b);
         const int base = (b - s) & kRingMask;          // ring slot of entry b
@@ -113,6 +137,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                 s_id[base + jj] = id;
                 qm[h] = (mk & qbit) != 0u;
             }
+            s_sum[jj] = 0.f;
         }
         cur.lo = __ballot(qm[0]);
         cur.hi = __ballot(qm[1]);
@@ -148,7 +173,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             const int L0 = __builtin_amdgcn_readlane(Lh[0], j & 63);
             const int L1 = __builtin_amdgcn_readlane(Lh[1], j & 63);
             const int Lj = j < 64 ? L0 : L1;
-            const float thr_d = sj.g1.w - a.bias;
+            const float thr_d = uniform_f(sj.g1.w) - a.bias;
             const int stop = Lj >= 0 ? Lj : b + j;
             while (trail < stop) {
                 if (trail < lo_pos) {
@@ -156,8 +181,8 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                     uint32_t mk;
                     const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
                                                   tile_y0, a.cutoff, a.alpha_min, &mk);
-                    if (Lj < 0 && !(tk.g1.w < thr_d)) break;
-                    if (mk & qbit) occlude(tk);
+                    if (Lj < 0 && !(uniform_f(tk.g1.w) < thr_d)) break;
+                    if (uniform_u(mk) & qbit) occlude(tk);
                     ++trail;
                     continue;
                 }
@@ -174,7 +199,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                     const int k = first_bit(rel);
                     clear_bit(rel, k);
                     const Staged tk = s_rec[(bstart + k - s) & kRingMask];
-                    if (Lj < 0 && !(tk.g1.w < thr_d)) {
+                    if (Lj < 0 && !(uniform_f(tk.g1.w) < thr_d)) {
                         trail = bstart + k;
                         stopped = true;
                         break;
@@ -185,15 +210,19 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                 trail = bstart + hi;
             }
             alive = alive && tt >= kShadowEps;
-            if (!__ballot(alive)) return;          // every pixel of the quadrant is dark
+            if (!__ballot(alive)) {                // every pixel of the quadrant is dark
+                flush(base, m);
+                return;
+            }
             const float q = splat_q(sj, pxc, pyc);
             const bool hit = alive && q >= sj.g1.y;
             if (__ballot(hit)) {
                 const float v = hit ? fast_exp2(q) * tt : 0.f;
                 const float sn = wave_sum_lane63(v);
-                if (lane == 63) atomicAdd(&a.num[s_id[base + j]], sn);
+                if (lane == 63) s_sum[j] = sn;
             }
         }
+        flush(base, m);
         prv = cur;
         __syncthreads();
     }

@@ -37,7 +37,7 @@ EXPORTED = [
     "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
-    "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
+    "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
 ]
 
 
@@ -104,6 +104,7 @@ def _load():
         "gs3_shadow_den": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_num": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_resolve": (C.c_int, [P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
+        "gs3_sort": (C.c_int, [P(gs3_viewbuf), C.c_void_p]),
         "gs3_shade": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_mlp), P(gs3_viewbuf),
                                 C.c_void_p, C.c_void_p]),
         "gs3_render_shaded": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
@@ -259,6 +260,10 @@ def gs3_preprocess(scene: DeviceScene, view, consts: gs3_consts, depth_mode: int
     v = make_view(view)
     _check(_lib.gs3_preprocess(C.byref(scene.c_struct()), C.byref(v), C.byref(consts), depth_mode,
                                C.byref(vb.vb), _stream()), "gs3_preprocess")
+
+
+def gs3_sort(vb: ViewBuffer):
+    _check(_lib.gs3_sort(C.byref(vb.vb), _stream()), "gs3_sort")
 
 
 def gs3_view_pair_count(vb: ViewBuffer) -> int:
