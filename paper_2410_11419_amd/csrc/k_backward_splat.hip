@@ -307,6 +307,10 @@ template <int PASS>
 __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     __shared__ Staged s_rec[2 * kBwdBatch];
     __shared__ uint32_t s_id[2 * kBwdBatch];
+    // PASS 1: gradients of the ring's entries collect here and go out in
+    // bursts of atomics (a global atomic still counts as an outstanding
+    // memory operation that the next load would wait for)
+    __shared__ float s_acc[6][2 * kBwdBatch];
     const int tile = (int)a.order[blockIdx.x >> 2];
     const int qd = blockIdx.x & 3;
     const int2 rg = a.ranges[tile];
@@ -327,8 +331,38 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     Bits128b cur{0ull, 0ull}, prv{0ull, 0ull};
     int trail = s;
     bool finished = e <= s || !__ballot(alive);
-    // occluder k: T *= (1 - alpha); PASS 1 also its gradient
-    auto occlude = [&](const Staged& k, uint32_t kid) {
+    if (PASS == 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            s_acc[c][lane] = 0.f;
+            s_acc[c][lane + 64] = 0.f;
+            s_acc[c][lane + 128] = 0.f;
+            s_acc[c][lane + 192] = 0.f;
+        }
+    }
+    // add the gradients of the 128 ring slots from `first` to global memory
+    // and clear them (PASS 1)
+    auto flush = [&](int first, int count) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = lane + 64 * h;
+            if (jj < count) {
+                const int slot = (first + jj) & kBwdRingMask;
+                const uint32_t id = s_id[slot];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const float v = s_acc[c][slot];
+                    if (v != 0.f) {
+                        atomicAdd(&a.gsplat[(size_t)c * a.n + id], v);
+                        s_acc[c][slot] = 0.f;
+                    }
+                }
+            }
+        }
+    };
+    // occluder k: T *= (1 - alpha); PASS 1 also its gradient, into ring slot
+    // `slot`, or straight to global memory when k is older than the ring (-1)
+    auto occlude = [&](const Staged& k, uint32_t kid, int slot) {
         const float dx = pxc - k.g0.x, dy = pyc - k.g0.y;
         const float q = quad_q(dx, dy, k.g0.z, k.g0.w, k.g1.x);
         const bool hit = alive && q >= k.g1.y;
@@ -347,15 +381,21 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     const float sum = wave_sum_lane63(g[c]);
-                    if (lane == 63) atomicAdd(&a.gsplat[(size_t)c * a.n + kid], sum);
+                    if (lane == 63) {
+                        if (slot >= 0) s_acc[c][slot] += sum;
+                        else atomicAdd(&a.gsplat[(size_t)c * a.n + kid], sum);
+                    }
                 }
             }
         }
         if (hit) tt *= 1.f - al;
     };
+    int last_b = -1, last_m = 0;
     for (int b = s; b < e && !finished; b += kBwdBatch) {
         const int m = min(kBwdBatch, e - b);
         const int base = (b - s) & kBwdRingMask;
+        last_b = b;
+        last_m = m;
         bool qm[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -410,7 +450,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                     const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
                                                   a.alpha_min, &mk);
                     if (Lj < 0 && !(tk.g1.w < thr_d)) break;
-                    if (mk & qbit) occlude(tk, kid);
+                    if (mk & qbit) occlude(tk, kid, -1);
                     ++trail;
                     continue;
                 }
@@ -432,7 +472,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                         stopped = true;
                         break;
                     }
-                    occlude(tk, s_id[slot]);
+                    occlude(tk, s_id[slot], slot);
                 }
                 if (stopped) break;
                 trail = bstart + hi;
@@ -462,16 +502,19 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
 #pragma unroll
                         for (int c = 0; c < 5; ++c) {
                             const float sum = wave_sum_lane63(g[c]);
-                            if (lane == 63) atomicAdd(&a.gsplat[(size_t)c * a.n + idj], sum);
+                            if (lane == 63) s_acc[c][base + j] += sum;
                         }
                     }
                     gm -= wv;
                 }
             }
         }
+        // the previous batch leaves the ring: its gradients are final
+        if (PASS == 1 && b - kBwdBatch >= s) flush(b - kBwdBatch - s, kBwdBatch);
         prv = cur;
         __syncthreads();
     }
+    if (PASS == 1 && last_b >= s) flush(last_b - s, last_m);
     if (PASS == 0 && inside) a.gray[pix] = gm;
 }
 
