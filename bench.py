@@ -41,10 +41,12 @@ KERNEL_SOURCES = ("paper_2410_11419_amd/csrc/k_shadow.hip", "paper_2410_11419_am
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="frames in flight (double/quad buffering, one stream each)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many frames (for rocprofv3), no JSON")
     ap.add_argument("--train-steps", type=int, default=5, help="timed fwd+bwd steps (0: skip)")
@@ -282,7 +284,8 @@ def main():
     ds = gs3.DeviceScene.from_host(sc, dev)
     pairs = views()
     if args.profile_train:
-        train_step_bench(ds, sc, 0, 1, profile=True)
+        with torch.cuda.stream(torch.cuda.Stream()):
+            train_step_bench(ds, sc, 0, 1, profile=True)
         return
     rnd = gs3.Renderer(ds)
     # warm-up: sizes every view buffer (host sync allowed here)
@@ -291,9 +294,12 @@ def main():
         rnd.render(cam, light, check=True)
     torch.cuda.synchronize()
     if args.profile_steps:
+        fp = gs3.FramePipeline(ds, depth=args.inflight)
+        for cam, light in pairs:
+            fp.warm(cam, light)
         for i in range(args.profile_steps):
-            cam, light = pairs[i % len(pairs)]
-            rnd.render(cam, light, check=False)
+            fp.render(*pairs[i % len(pairs)], overlap=False)
+        torch.cuda.synchronize()
         # a plain copy of known size, to calibrate the HBM byte counters
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -316,29 +322,49 @@ def main():
         hits_c = int(gs3.gs3_view_count_hits(k, cvb, True).item())
         stats.append((p_l, p_c, hits_l, hits_c))
 
-    # one step = one relit frame through Renderer.render (camera preprocess
-    # and shadow denominator overlapped with the light pass on side streams);
-    # the library launches on torch's current stream, where the frame and
-    # numerator events are recorded
-    stream = torch.cuda.current_stream()
+    # one step = one relit frame, the whole hot path. Frames are pipelined
+    # `inflight` deep: frame i runs on renderer i % inflight (its own
+    # buffers) and its own stream, so consecutive frames overlap on the
+    # device as a renderer producing a stream of frames would run them. The
+    # library launches on that stream, where the frame and numerator events
+    # are recorded.
+    fp = gs3.FramePipeline(ds, depth=args.inflight)
+    for cam, light in pairs:
+        fp.warm(cam, light)
+    for i in range(args.warmup):
+        fp.render(*pairs[i % len(pairs)], overlap=False)
+    torch.cuda.synchronize()
     evs = [{k: torch.cuda.Event(enable_timing=True) for k in ("f0", "num0", "num1", "f1")}
            for _ in range(args.steps)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         cam, light = pairs[i % len(pairs)]
         e = evs[i]
-        e["f0"].record(stream)
-        rnd.render(cam, light, check=False, overlap=True, events=e)
-        e["f1"].record(stream)
+        st = fp.streams[i % args.inflight]
+        e["f0"].record(st)
+        fp.render(cam, light, events=e, overlap=False)
+        e["f1"].record(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if rnd.overflowed():
+    if fp.overflowed():
         raise RuntimeError("a binning exceeded its pair capacity inside the timed region")
     wall = t1 - t0
     fps = args.steps / wall
     num_ms = sum(e["num0"].elapsed_time(e["num1"]) for e in evs) / args.steps
     frame_ms = sum(e["f0"].elapsed_time(e["f1"]) for e in evs) / args.steps
+    # one frame at a time (no pipelining; stages overlapped inside the frame)
+    single = gs3.FramePipeline(ds, depth=1)
+    single.renderers[0] = rnd
+    for i in range(4):
+        single.render(*pairs[i % len(pairs)])
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    n_single = max(8, args.steps // 2)
+    for i in range(n_single):
+        single.render(*pairs[i % len(pairs)])
+    torch.cuda.synchronize()
+    single_fps = n_single / (time.perf_counter() - ts)
+    stream = torch.cuda.current_stream()
     # per-stage breakdown from a short serial pass (one stream, in order)
     n_ser = min(8, args.steps)
     ser = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(n_ser)]
@@ -393,7 +419,9 @@ def main():
                      "traffic": traffic,
                      "per_unit": f"{SHADOW_NUM_FLOPS_PER_HIT} flop per light-view hit",
                      "units_per_launch": int(h_l), "avg_launch_ms": round(num_ms, 4)},
+        "frames_in_flight": args.inflight,
         "frame_ms_events": round(frame_ms, 4),
+        "single_frame_fps": round(single_fps, 3),
         "stages_ms_serial": {"light_preprocess": round(stage[0], 4), "shadow_den": round(stage[1], 4),
                              "shadow_num": round(stage[2], 4), "shadow_resolve": round(stage[3], 4),
                              "camera_preprocess": round(stage[4], 4), "shade_mlp_render": round(stage[5], 4)},
@@ -402,12 +430,15 @@ def main():
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),
                       "frac_of_8TBs": round(frame_gbs / HBM_PEAK_GBS, 4)},
     }
+    side = torch.cuda.Stream()      # the default stream would serialize the side streams
     if args.train_steps > 0:
-        out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
+        with torch.cuda.stream(side):
+            out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
     if args.serving_requests > 0:
-        del rnd
-        out["serving"] = serving_bench(ds, args.serving_requests,
-                                       [float(x) for x in args.serving_loads.split(",") if x])
+        del rnd, fp, single
+        with torch.cuda.stream(side):
+            out["serving"] = serving_bench(ds, args.serving_requests,
+                                           [float(x) for x in args.serving_loads.split(",") if x])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

@@ -623,3 +623,35 @@ class RelitRender(torch.autograd.Function):
 def relit_render(renderer: "Renderer", cam, light) -> torch.Tensor:
     """Differentiable relit frame [3, H, W] (see RelitRender)."""
     return RelitRender.apply(renderer, cam, light, *scene_parameters(renderer.scene))
+
+
+class FramePipeline:
+    """A stream of relit frames with `depth` frames in flight: frame i runs
+    on renderer i % depth (its own buffers) and its own stream, so the next
+    frame's light pass fills the device while the previous frame's shadow
+    numerator tails off and its camera pass runs. Each frame is the same
+    computation as Renderer.render; a renderer's buffers are reused `depth`
+    frames later, after its previous frame on the same stream."""
+
+    def __init__(self, scene: DeviceScene, depth: int = 2, consts: Optional[gs3_consts] = None,
+                 use_mlps: bool = True, pair_capacity: Optional[int] = None):
+        self.renderers = [Renderer(scene, consts, use_mlps, pair_capacity) for _ in range(depth)]
+        self.streams = [torch.cuda.Stream() for _ in range(depth)]
+        self.i = 0
+
+    def warm(self, cam, light):
+        """Size every renderer's buffers for this view pair (host syncs)."""
+        for r, s in zip(self.renderers, self.streams):
+            with torch.cuda.stream(s):
+                r.render(cam, light, check=True)
+        torch.cuda.synchronize()
+
+    def render(self, cam, light, events: Optional[Dict[str, torch.cuda.Event]] = None,
+               overlap: bool = True) -> Dict[str, torch.Tensor]:
+        k = self.i % len(self.renderers)
+        self.i += 1
+        with torch.cuda.stream(self.streams[k]):
+            return self.renderers[k].render(cam, light, check=False, overlap=overlap, events=events)
+
+    def overflowed(self) -> bool:
+        return any(r.overflowed() for r in self.renderers)
