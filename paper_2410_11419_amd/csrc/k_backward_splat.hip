@@ -297,11 +297,13 @@ __device__ inline void clear_bit_b(Bits128b& b, int k) {
     if (k < 64) b.lo &= ~(1ull << k); else b.hi &= ~(1ull << (k - 64));
 }
 
-constexpr int kBwdBatch = 128;
+// list entries staged at a time; 64 (about 7.5 KB of LDS per wave) lets
+// twice as many waves share a CU as 128 would
+constexpr int kBwdBatch = 64;
 constexpr int kBwdRingMask = 2 * kBwdBatch - 1;
 
 // The forward numerator's walk (one wave per (tile, 8x8 quadrant), LDS ring
-// of two 128-entry batches, quadrant-masked lead and trailing pointers),
+// of two batches, quadrant-masked lead and trailing pointers),
 // carrying the adjoint. PASS 0: G_m per pixel. PASS 1: per-splat gradients.
 template <int PASS>
 __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
@@ -333,14 +335,11 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     bool finished = e <= s || !__ballot(alive);
     if (PASS == 1) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            s_acc[c][lane] = 0.f;
-            s_acc[c][lane + 64] = 0.f;
-            s_acc[c][lane + 128] = 0.f;
-            s_acc[c][lane + 192] = 0.f;
-        }
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int i = lane; i < 2 * kBwdBatch; i += 64) s_acc[c][i] = 0.f;
     }
-    // add the gradients of the 128 ring slots from `first` to global memory
+    // add the gradients of `count` ring slots from `first` to global memory
     // and clear them (PASS 1)
     auto flush = [&](int first, int count) {
 #pragma unroll

@@ -132,7 +132,7 @@ def test_backward_small_scene_no_mlps(gs3):
 
 
 def test_backward_ragged_multibatch(gs3):
-    # lists longer than one 128-entry batch, ragged image edges, both MLPs
+    # lists longer than one staged batch, ragged image edges, both MLPs
     sc = synth.make_scene(6000, 8, seed=7, means="shell", mlps=True, log_scale_mu=(-3.4,) * 3)
     rng = np.random.default_rng(3)
     cam = synth.make_view(rng.standard_normal(3), 4.0, 120, 88, 40.0)
