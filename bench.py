@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many frames (for rocprofv3), no JSON")
     ap.add_argument("--train-steps", type=int, default=10, help="timed fwd+bwd steps (0: skip)")
+    ap.add_argument("--fluffy-steps", type=int, default=3,
+                    help="timed fwd+bwd steps of the dense 1.5M-Gaussian scene (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=2000, help="requests per serving run (0: skip)")
     ap.add_argument("--serving-loads", type=str, default="0.5,0.9",
                     help="offered loads as fractions of the plain renderer's saturation rate")
@@ -117,29 +119,34 @@ def profiled_traffic():
         return None
 
 
-def train_step_bench(ds, sc, steps, warmup, profile=False):
-    """fwd+bwd steps/s: each step renders a batch of 4 (camera 800x800, light
-    1024x1024) pairs, takes the L1 loss against targets rendered from the
-    scene with means perturbed by N(0, 0.01) and colours by N(0, 0.05), and
-    runs the hand-written backward. The four views of a step are independent
-    until their gradients are summed, so each runs on its own renderer,
-    stream and gradient buffers (the backward adds into its buffers without
-    atomics), and the four gradient sets are added at the end of the step."""
+def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, lanes=4,
+                     workload=None):
+    """fwd+bwd steps/s: each step renders a batch of (camera, light) pairs,
+    takes the L1 loss against targets rendered from the scene with means
+    perturbed by N(0, 0.01) and colours by N(0, 0.05), and runs the
+    hand-written backward. Views are independent until their gradients are
+    summed, so the batch is spread over ``lanes`` concurrent lanes, each with
+    its own renderer, stream and gradient buffers (the backward adds into a
+    lane's buffers without atomics; a lane's views run one after another);
+    the lanes' gradients are added at the end of the step.
+    Default pairs: camera 800x800 and light 1024x1024, both at 40 deg."""
     import numpy as np
     import torch
     from paper_2410_11419_amd import gs3, synth
-    rng = np.random.default_rng(4)
-    pairs = [(synth.make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0),
-              synth.make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0)) for _ in range(8)]
+    if pairs is None:
+        rng = np.random.default_rng(4)
+        pairs = [(synth.make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0),
+                  synth.make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0)) for _ in range(8)]
     tgt_scene = gs3.DeviceScene.from_host(synth.perturb_scene(sc, seed=5))
     trnd = gs3.Renderer(tgt_scene)
     targets = [trnd.render(c, l)["final"].clone() for c, l in pairs]
     del trnd, tgt_scene
-    batch = 4
-    rnds = [gs3.Renderer(ds) for _ in range(batch)]
-    grads = [gs3.DeviceGrads(ds) for _ in range(batch)]
-    streams = [torch.cuda.Stream() for _ in range(batch)]
-    inv = 1.0 / (batch * 3 * 800 * 800)
+    lanes = min(lanes, batch)
+    rnds = [gs3.Renderer(ds) for _ in range(lanes)]
+    grads = [gs3.DeviceGrads(ds) for _ in range(lanes)]
+    streams = [torch.cuda.Stream() for _ in range(lanes)]
+    cam0 = pairs[0][0]
+    inv = 1.0 / (batch * 3 * cam0.width * cam0.height)
     main = torch.cuda.current_stream()
 
     def tensors(g):
@@ -152,31 +159,33 @@ def train_step_bench(ds, sc, steps, warmup, profile=False):
     def step(i, evs=None):
         if evs is not None:
             evs[0].record(main)
-        for j in range(batch):
-            k = (i * batch + j) % len(pairs)
-            cam, light = pairs[k]
+        for j in range(lanes):
             streams[j].wait_stream(main)
             with torch.cuda.stream(streams[j]):
                 for t in tensors(grads[j]):
                     t.zero_()
-                out = rnds[j].render(cam, light, check=False, overlap=False)
-                dF = torch.sign(out["final"] - targets[k]) * inv
-                rnds[j].backward(cam, light, dF, grads[j])
-        for j in range(batch):
+                for v in range(j, batch, lanes):
+                    k = (i * batch + v) % len(pairs)
+                    cam, light = pairs[k]
+                    out = rnds[j].render(cam, light, check=False, overlap=False)
+                    dF = torch.sign(out["final"] - targets[k]) * inv
+                    rnds[j].backward(cam, light, dF, grads[j])
+        for j in range(lanes):
             main.wait_stream(streams[j])
-        # gradient of the batch = sum over its views
+        # gradient of the batch = sum over its lanes
         for dst, *srcs in zip(*[tensors(g) for g in grads]):
             for src in srcs:
                 dst.add_(src)
         if evs is not None:
             evs[1].record(main)
 
-    for i in range(max(1, warmup)):
-        for j in range(batch):
-            cam, light = pairs[(i * batch + j) % len(pairs)]
-            with torch.cuda.stream(streams[j]):
+    # size every lane's buffers for every pair it can see (host syncs allowed)
+    for j in range(lanes):
+        with torch.cuda.stream(streams[j]):
+            for cam, light in pairs:
                 rnds[j].render(cam, light, check=True)
-        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    for i in range(max(1, warmup)):
         step(i)
     torch.cuda.synchronize()
     if profile:
@@ -195,12 +204,44 @@ def train_step_bench(ds, sc, steps, warmup, profile=False):
     if any(r.overflowed() for r in rnds):
         raise RuntimeError("a binning exceeded its pair capacity inside the timed train steps")
     per = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    light0 = pairs[0][1]
     return {"metric": "fwd+bwd steps/s", "value": round(steps / wall, 3), "unit": "steps/s",
             "ms_per_step": round(1e3 * wall / steps, 3), "steps": steps, "batch": batch,
-            "workload": "300,000 Gaussians, batch of 4 (camera 800x800, light 1024x1024) pairs, L1 loss against "
-                        "targets from the scene with means + N(0,0.01) and colours + N(0,0.05)",
-            "views": "the 4 views of a step run concurrently, one stream each; their gradients are summed",
+            "workload": workload or (f"{sc.n:,} Gaussians, batch of {batch} (camera {cam0.width}x{cam0.height}, "
+                                     f"light {light0.width}x{light0.height}) pairs, L1 loss against targets "
+                                     f"from the scene with means + N(0,0.01) and colours + N(0,0.05)"),
+            "views": f"the {batch} views of a step run on {lanes} concurrent lanes (renderer, stream and "
+                     f"gradient buffers each); the lanes' gradients are summed",
             "step_ms_events": round(per, 3)}
+
+
+def fluffy_train_bench(steps):
+    """The dense scene's training step: 1.5M Gaussians (70 % low-opacity
+    needles in the cube, 30 % shell), batch of 8 (camera 1024x1024 at 40 deg,
+    light 2048x2048 at 60 deg) pairs, L1 loss, 4 concurrent lanes. Also
+    reports the pair and hit counts of the first pair."""
+    import torch
+    from paper_2410_11419_amd import gs3, synth
+    sc = synth.scene_fluffy()
+    ds = gs3.DeviceScene.from_host(sc)
+    pairs = synth.fluffy_pairs(8)
+    res = train_step_bench(ds, sc, steps, 1, pairs=pairs, batch=8, lanes=4,
+                           workload="1,500,000 Gaussians (70 % low-opacity needles in [-1,1]^3, 30 % shell), "
+                                    "batch of 8 (camera 1024x1024 at 40 deg, light 2048x2048 at 60 deg) pairs, "
+                                    "L1 loss against targets from the scene with means + N(0,0.01) and "
+                                    "colours + N(0,0.05)")
+    rnd = gs3.Renderer(ds)
+    cam, light = pairs[0]
+    rnd.render(cam, light, check=True)
+    lvb, cvb = rnd.vbs[("light", 2048, 2048)], rnd.vbs[("cam", 1024, 1024)]
+    k = rnd.consts
+    res["work_first_pair"] = {
+        "pairs_light": int(gs3.gs3_view_pair_count(lvb)), "pairs_camera": int(gs3.gs3_view_pair_count(cvb)),
+        "hits_light": int(gs3.gs3_view_count_hits(k, lvb, False).item()),
+        "hits_camera_blended": int(gs3.gs3_view_count_hits(k, cvb, True).item())}
+    del rnd, ds
+    torch.cuda.synchronize()
+    return res
 
 
 def serving_bench(ds, requests, loads):
@@ -450,6 +491,9 @@ def main():
     if args.train_steps > 0:
         with torch.cuda.stream(side):
             out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
+    if args.fluffy_steps > 0:
+        with torch.cuda.stream(side):
+            out["train_step_fluffy"] = fluffy_train_bench(args.fluffy_steps)
     if args.serving_requests > 0:
         del rnd, fp, single
         with torch.cuda.stream(side):

@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "View", "Mlp", "make_scene", "make_view", "random_views",
-    "scene_small", "scene_full", "scene_fluffy", "scene_gradcheck",
+    "scene_small", "scene_full", "scene_fluffy", "fluffy_pairs", "scene_gradcheck",
     "perturb_scene", "subset",
 ]
 
@@ -212,6 +212,15 @@ def scene_full(seed: int = 0, n: int = 300_000):
 def scene_fluffy(seed: int = 0, n: int = 1_500_000):
     """1.5M Gaussians: 70 % fluffy volume, 30 % shell as in ``scene_full``."""
     return make_scene(n, 8, seed, means="shell", mlps=True, fluffy_fraction=0.7)
+
+
+def fluffy_pairs(count: int, seed: int = 6):
+    """(camera, light) pairs of the dense scene's training step: camera
+    1024^2 at 40 deg and light splat 2048^2 at 60 deg, both at radius 4 in
+    uniformly random directions."""
+    rng = np.random.default_rng(seed)
+    return [(make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0),
+             make_view(rng.standard_normal(3), 4.0, 2048, 2048, 60.0)) for _ in range(count)]
 
 
 def scene_gradcheck(seed: int = 0, n: int = 256, k: int = 4, mlps: bool = True):

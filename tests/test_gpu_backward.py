@@ -140,6 +140,17 @@ def test_backward_ragged_multibatch(gs3):
     _compare_grads(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "ragged")
 
 
+def test_backward_fluffy(gs3):
+    # the dense scene's distributions (70 % low-opacity needles in the cube,
+    # 30 % shell) at a size the oracle's autograd finishes: long lists, rays
+    # that stay lit through many splats, light splat at 60 deg
+    sc = synth.make_scene(8000, 8, seed=13, means="shell", mlps=True, fluffy_fraction=0.7)
+    rng = np.random.default_rng(13)
+    cam = synth.make_view(rng.standard_normal(3), 4.0, 96, 72, 40.0)
+    light = synth.make_view(rng.standard_normal(3), 4.0, 128, 128, 60.0)
+    _compare_grads(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "fluffy")
+
+
 def test_backward_accumulates(gs3):
     # two backward calls into one gradient buffer add up
     sc, cam, light = synth.scene_gradcheck(seed=5, n=128)
