@@ -49,7 +49,6 @@ struct ShadowArgs {
     float* den;
 };
 
-// 128-bit set of batch entries (two 64-bit halves).
 // The lists, pointers and distances a wave walks are the same in every
 // lane; reading such a value through readfirstlane tells the compiler so,
 // which keeps the pointer arithmetic and loop control in scalar registers
@@ -59,37 +58,59 @@ __device__ inline float uniform_f(float x) {
 }
 __device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 
-struct Bits128 {
-    unsigned long long lo, hi;
-};
-__device__ inline Bits128 range_bits(int lo, int hi) {   // entries lo .. hi-1, 0 <= lo <= hi <= 128
-    auto upto = [](int k) -> unsigned long long { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); };
-    Bits128 b;
-    b.lo = upto(min(hi, 64)) & ~upto(min(lo, 64));
-    b.hi = upto(max(hi - 64, 0)) & ~upto(max(lo - 64, 0));
-    return b;
+// Bits lo .. hi-1 of a 64-bit set (lo and hi clamped to [0, 64]).
+__device__ inline unsigned long long range_mask64(int lo, int hi) {
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > 64 ? 64 : hi;
+    if (hi <= lo) return 0ull;
+    const unsigned long long up = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return up & ~((1ull << lo) - 1ull);
 }
-__device__ inline int first_bit(const Bits128& b) {
-    return b.lo ? __builtin_ctzll(b.lo) : 64 + __builtin_ctzll(b.hi);
+
+// A lane's 64-bit value as seen by lane j (j wave-uniform).
+__device__ inline unsigned long long readlane64(unsigned long long x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((unsigned long long)hi << 32) | lo;
 }
-__device__ inline void clear_bit(Bits128& b, int k) {
-    if (k < 64) b.lo &= ~(1ull << k); else b.hi &= ~(1ull << (k - 64));
+
+// Sum of x over each 16-lane row, in every lane of the row (DPP butterfly in
+// quads, then half-row and row mirrors).
+__device__ inline float row_sum16(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, true));  // row_half_mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, true));  // row_mirror
+    return x;
 }
+
+static_assert(kShadowBatch == 64, "the walk stages one list entry per lane per batch");
 
 // One wave per (tile, 8x8 quadrant): the four quadrants of a light tile run
 // as independent single-wave workgroups, one pixel per lane. The wave stages
-// its tile's list a batch at a time into an LDS ring that also keeps the
-// previous batch for the trailing pointer; a ballot marks the entries whose
-// hit ellipse can reach the quadrant, and both pointers visit only those, so
-// the wave's sequential chain is as short as its quadrant allows. For each
-// lead entry j, L(j) (the first list position not more than `bias` closer to
-// the light) comes from a binary search over the ring's distances; when it
-// lies before the ring the trailing pointer walks and compares instead. The
-// wave exits when all its pixels are dark.
+// its tile's list 64 entries at a time (one per lane) into an LDS ring that
+// also keeps the previous batch; a ballot marks the entries whose hit
+// ellipse can reach the quadrant, and only those are visited.
+//
+// For lead entry j, L(j) = the first list position whose distance is not
+// below dist_j - bias; T_m(j) is the product of (1 - alpha) over the marked
+// entries before L(j). L is non-decreasing along the list (distances are
+// sorted), so the occluders that enter between two consecutive leads form
+// the segment [L(previous lead), L(j)) of the list. Each lane finds L for
+// its entry by a binary search over the ring's distances and turns its
+// segment into two 64-bit sets (previous batch, current batch); the walk
+// then reads the lead's two sets and multiplies in their entries, with no
+// per-lead position arithmetic. Leads whose L lies before the ring (always
+// the first leads of a batch) walk older entries from global memory
+// instead, comparing distances; entries before the ring that precede every
+// remaining lead are walked once. The lead's beta T_m(j) is summed per
+// 16-lane row (DPP) into four partial sums per entry, which go to num_j in
+// one burst of atomics per batch. The wave exits when all its pixels are
+// dark.
 __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
     __shared__ Staged s_rec[2 * kShadowBatch];
     __shared__ uint32_t s_id[2 * kShadowBatch];
-    __shared__ float s_sum[kShadowBatch];        // lead sums of the current batch
+    __shared__ float s_sum[4][kShadowBatch];     // lead sums of the current batch, per 16-lane row
     const int tile = (int)a.order[blockIdx.x >> 2];
     const int qd = blockIdx.x & 3;
     const int2 rg = a.ranges[tile];
@@ -103,128 +124,144 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
     bool alive = (tx * kTile + lx < a.width) && (ty * kTile + ly < a.height);
     if (!__ballot(alive)) return;
     const uint32_t qbit = 1u << qd;
+    // 1 - min(alpha_max, x) == max(1 - alpha_max, 1 - x) exactly: rounding
+    // of 1 - x is monotone in x
+    const float keep_min = 1.f - a.alpha_max;
     float tt = 1.f;
-    Bits128 cur{0ull, 0ull}, prv{0ull, 0ull};
+    unsigned long long prv = 0ull;
     int trail = s;
     // multiply (1 - alpha) of occluder k into tt where it hits
     auto occlude = [&](const Staged& k) {
         const float q = splat_q(k, pxc, pyc);
-        if (alive && q >= k.g1.y) tt *= 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
+        const bool hit = alive && q >= k.g1.y;
+        if (__ballot(hit)) {
+            const float f = fmaxf(keep_min, 1.f - k.g1.z * fast_exp2(q));
+            tt = hit ? tt * f : tt;
+        }
     };
     // A global atomic without a returned value still counts as an
     // outstanding vector memory operation, so the next wait for a load would
     // wait for it too: the lead sums of a batch collect in LDS and go out
     // in one burst of atomics when the batch ends.
     auto flush = [&](int base, int m) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            if (jj < m) {
-                const float v = s_sum[jj];
-                if (v != 0.f) atomicAdd(&a.num[s_id[base + jj]], v);
-            }
+        if (lane < m) {
+            const float v = (s_sum[0][lane] + s_sum[1][lane]) + (s_sum[2][lane] + s_sum[3][lane]);
+            if (v != 0.f) atomicAdd(&a.num[s_id[base + lane]], v);
         }
     };
     for (int b = s; b < e; b += kShadowBatch) {
         const int m = min(kShadowBatch, e - b);
         const int base = (b - s) & kRingMask;          // ring slot of entry b
-        bool qm[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            qm[h] = false;
-            if (jj < m) {
-                uint32_t mk;
-                const uint32_t id = safe_id(a.list[b + jj], a.n);
-                s_rec[base + jj] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                               a.alpha_min, &mk);
-                s_id[base + jj] = id;
-                qm[h] = (mk & qbit) != 0u;
-            }
-            if (jj < kShadowBatch) s_sum[jj] = 0.f;
+        const int pbase = base ^ kShadowBatch;         // ring slot of entry b - 64
+        bool qm = false;
+        if (lane < m) {
+            uint32_t mk;
+            const uint32_t id = safe_id(a.list[b + lane], a.n);
+            s_rec[base + lane] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff, a.alpha_min,
+                                             &mk);
+            s_id[base + lane] = id;
+            qm = (mk & qbit) != 0u;
         }
-        cur.lo = __ballot(qm[0]);
-        cur.hi = __ballot(qm[1]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_sum[r][lane] = 0.f;
+        const unsigned long long cur = __ballot(qm);
         __syncthreads();
-        // L(j) for the lane's two entries: the first position in
-        // [lo_pos, b + j) whose distance is not below dist_j - bias (b + j
-        // if none); -1 when it lies before the ring
+        // L for the lane's entry: the first position in [lo_pos, b + lane)
+        // whose distance is not below dist - bias (b + lane if none); -1 when
+        // it lies before the ring
         const int lo_pos = max(s, b - kShadowBatch);
-        int Lh[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            Lh[h] = b + min(jj, m);
-            if (jj < m) {
-                const float thr = s_rec[base + jj].g1.w - a.bias;
-                if (lo_pos > s && !(s_rec[(lo_pos - s) & kRingMask].g1.w < thr)) {
-                    Lh[h] = -1;
-                } else {
-                    int lo = lo_pos, hi = b + jj;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_rec[(mid - s) & kRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
-                    }
-                    Lh[h] = lo;
+        int L = b + min(lane, m);
+        if (lane < m) {
+            const float thr = s_rec[base + lane].g1.w - a.bias;
+            if (lo_pos > s && !(s_rec[(lo_pos - s) & kRingMask].g1.w < thr)) {
+                L = -1;
+            } else {
+                int lo = lo_pos, hi = b + lane;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_rec[(mid - s) & kRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
                 }
+                L = lo;
             }
         }
-        Bits128 todo = cur;
-        while (todo.lo | todo.hi) {
-            const int j = first_bit(todo);
-            clear_bit(todo, j);
-            const Staged sj = s_rec[base + j];
-            const int L0 = __builtin_amdgcn_readlane(Lh[0], j & 63);
-            const int L1 = __builtin_amdgcn_readlane(Lh[1], j & 63);
-            const int Lj = j < 64 ? L0 : L1;
-            const float thr_d = uniform_f(sj.g1.w) - a.bias;
-            const int stop = Lj >= 0 ? Lj : b + j;
-            while (trail < stop) {
-                if (trail < lo_pos) {
-                    // older than the ring: re-stage from global memory
-                    uint32_t mk;
-                    const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
-                                                  tile_y0, a.cutoff, a.alpha_min, &mk);
-                    if (Lj < 0 && !(uniform_f(tk.g1.w) < thr_d)) break;
-                    if (uniform_u(mk) & qbit) occlude(tk);
-                    ++trail;
-                    continue;
-                }
-                // ring entries of one batch, only those that reach the quadrant
-                const bool in_cur = trail >= b;
-                const int bstart = in_cur ? b : b - kShadowBatch;
-                const int lo = trail - bstart, hi = min(stop - bstart, kShadowBatch);
-                Bits128 rel = range_bits(lo, hi);
-                const Bits128 msk = in_cur ? cur : prv;
-                rel.lo &= msk.lo;
-                rel.hi &= msk.hi;
-                bool stopped = false;
-                while (rel.lo | rel.hi) {
-                    const int k = first_bit(rel);
-                    clear_bit(rel, k);
-                    const Staged tk = s_rec[(bstart + k - s) & kRingMask];
-                    if (Lj < 0 && !(uniform_f(tk.g1.w) < thr_d)) {
-                        trail = bstart + k;
-                        stopped = true;
-                        break;
-                    }
-                    occlude(tk);
-                }
-                if (stopped) break;
-                trail = bstart + hi;
-            }
+        const unsigned long long before = __ballot(L < 0);
+        auto lead_eval = [&](int j) {
             alive = alive && tt >= kShadowEps;
-            if (!__ballot(alive)) {                // every pixel of the quadrant is dark
-                flush(base, m);
-                return;
-            }
+            if (!__ballot(alive)) return false;
+            const Staged sj = s_rec[base + j];
             const float q = splat_q(sj, pxc, pyc);
             const bool hit = alive && q >= sj.g1.y;
             if (__ballot(hit)) {
-                const float v = hit ? fast_exp2(q) * tt : 0.f;
-                const float sn = wave_sum_lane63(v);
-                if (lane == 63) s_sum[j] = sn;
+                const float v = row_sum16(hit ? fast_exp2(q) * tt : 0.f);
+                if ((lane & 15) == 15) s_sum[lane >> 4][j] = v;
             }
+            return true;
+        };
+        // leads whose L lies before the ring: walk older entries from global
+        // memory up to L, comparing distances
+        unsigned long long todo = cur & before;
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const float thr_d = uniform_f(s_rec[base + j].g1.w) - a.bias;
+            while (trail < lo_pos) {
+                uint32_t mk;
+                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
+                                              tile_y0, a.cutoff, a.alpha_min, &mk);
+                if (!(uniform_f(tk.g1.w) < thr_d)) break;
+                if (uniform_u(mk) & qbit) occlude(tk);
+                ++trail;
+            }
+            if (!lead_eval(j)) {
+                flush(base, m);
+                return;
+            }
+        }
+        todo = cur & ~before;
+        if (todo) {
+            // entries before the ring precede every remaining lead's L
+            while (trail < lo_pos) {
+                uint32_t mk;
+                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
+                                              tile_y0, a.cutoff, a.alpha_min, &mk);
+                if (uniform_u(mk) & qbit) occlude(tk);
+                ++trail;
+            }
+            // the lane's segment [max(trail, L(previous lead)), L) as sets of
+            // ring entries: previous batch (positions b-64 ..) and current
+            // batch (positions b ..)
+            const unsigned long long below = todo & ((1ull << lane) - 1ull);
+            const int prev = below ? 63 - __builtin_clzll(below) : 0;
+            const int Lprev = __builtin_amdgcn_ds_bpermute(prev << 2, L);
+            const int lo_abs = below ? max(Lprev, trail) : trail;
+            const int W0 = b - kShadowBatch;
+            unsigned long long mp = 0ull, mc = 0ull;
+            if ((todo >> lane) & 1ull) {
+                mp = range_mask64(lo_abs - W0, L - W0) & prv;
+                mc = range_mask64(lo_abs - b, L - b) & cur;
+            }
+            const int last = 63 - __builtin_clzll(todo);
+            while (todo) {
+                const int j = __builtin_ctzll(todo);
+                todo &= todo - 1ull;
+                unsigned long long op = readlane64(mp, j);
+                while (op) {
+                    const int k = __builtin_ctzll(op);
+                    op &= op - 1ull;
+                    occlude(s_rec[pbase + k]);
+                }
+                unsigned long long oc = readlane64(mc, j);
+                while (oc) {
+                    const int k = __builtin_ctzll(oc);
+                    oc &= oc - 1ull;
+                    occlude(s_rec[base + k]);
+                }
+                if (!lead_eval(j)) {
+                    flush(base, m);
+                    return;
+                }
+            }
+            trail = __builtin_amdgcn_readlane(L, last);
         }
         flush(base, m);
         prv = cur;
