@@ -280,39 +280,23 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
     }
 }
 
-struct Bits128b {
-    unsigned long long lo, hi;
-};
-__device__ inline Bits128b range_bits_b(int lo, int hi) {
-    auto upto = [](int k) -> unsigned long long { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); };
-    Bits128b b;
-    b.lo = upto(min(hi, 64)) & ~upto(min(lo, 64));
-    b.hi = upto(max(hi - 64, 0)) & ~upto(max(lo - 64, 0));
-    return b;
-}
-__device__ inline int first_bit_b(const Bits128b& b) {
-    return b.lo ? __builtin_ctzll(b.lo) : 64 + __builtin_ctzll(b.hi);
-}
-__device__ inline void clear_bit_b(Bits128b& b, int k) {
-    if (k < 64) b.lo &= ~(1ull << k); else b.hi &= ~(1ull << (k - 64));
-}
-
-// list entries staged at a time; 64 (about 7.5 KB of LDS per wave) lets
-// twice as many waves share a CU as 128 would
-constexpr int kBwdBatch = 64;
+constexpr int kBwdBatch = 64;                    // list entries staged at a time: one per lane
 constexpr int kBwdRingMask = 2 * kBwdBatch - 1;
 
-// The forward numerator's walk (one wave per (tile, 8x8 quadrant), LDS ring
-// of two batches, quadrant-masked lead and trailing pointers),
-// carrying the adjoint. PASS 0: G_m per pixel. PASS 1: per-splat gradients.
+// The forward numerator's walk (one wave per (tile, 8x8 quadrant), an LDS
+// ring of two 64-entry batches, quadrant-masked leads, per-lead occluder
+// segments [L(previous lead), L(j)) as sets of ring entries, older entries
+// walked from global memory), carrying the adjoint. PASS 0: G_m per pixel.
+// PASS 1: per-splat gradients.
 template <int PASS>
 __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     __shared__ Staged s_rec[2 * kBwdBatch];
     __shared__ uint32_t s_id[2 * kBwdBatch];
+    __shared__ float s_dn[kBwdBatch];               // dL/dnum of the current batch's entries
     // PASS 1: gradients of the ring's entries collect here and go out in
     // bursts of atomics (a global atomic still counts as an outstanding
     // memory operation that the next load would wait for)
-    __shared__ float s_acc[6][2 * kBwdBatch];
+    __shared__ float s_acc[PASS == 1 ? 6 : 1][2 * kBwdBatch];
     const int tile = (int)a.order[blockIdx.x >> 2];
     const int qd = blockIdx.x & 3;
     const int2 rg = a.ranges[tile];
@@ -330,31 +314,28 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     if (PASS == 1 && inside) gm = a.gray[pix];
     const uint32_t qbit = 1u << qd;
     float tt = 1.f;
-    Bits128b cur{0ull, 0ull}, prv{0ull, 0ull};
+    unsigned long long prv = 0ull;
     int trail = s;
     bool finished = e <= s || !__ballot(alive);
     if (PASS == 1) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
-#pragma unroll
-            for (int i = lane; i < 2 * kBwdBatch; i += 64) s_acc[c][i] = 0.f;
+        for (int c = 0; c < 6; ++c) {
+            s_acc[c][lane] = 0.f;
+            s_acc[c][lane + 64] = 0.f;
+        }
     }
-    // add the gradients of `count` ring slots from `first` to global memory
-    // and clear them (PASS 1)
+    // add the gradients of the `count` ring entries from slot `first` to
+    // global memory and clear them (PASS 1)
     auto flush = [&](int first, int count) {
+        if (lane < count) {
+            const int slot = first + lane;
+            const uint32_t id = s_id[slot];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            if (jj < count) {
-                const int slot = (first + jj) & kBwdRingMask;
-                const uint32_t id = s_id[slot];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const float v = s_acc[c][slot];
-                    if (v != 0.f) {
-                        atomicAdd(&a.gsplat[(size_t)c * a.n + id], v);
-                        s_acc[c][slot] = 0.f;
-                    }
+            for (int c = 0; c < 6; ++c) {
+                const float v = s_acc[c][slot];
+                if (v != 0.f) {
+                    atomicAdd(&a.gsplat[(size_t)c * a.n + id], v);
+                    s_acc[c][slot] = 0.f;
                 }
             }
         }
@@ -365,6 +346,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         const float dx = pxc - k.g0.x, dy = pyc - k.g0.y;
         const float q = quad_q(dx, dy, k.g0.z, k.g0.w, k.g1.x);
         const bool hit = alive && q >= k.g1.y;
+        if (!__ballot(hit)) return;
         const float beta = fast_exp2(q);
         const float ob = k.g1.z * beta;
         const float al = fminf(a.alpha_max, ob);
@@ -389,115 +371,62 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         }
         if (hit) tt *= 1.f - al;
     };
-    int last_b = -1, last_m = 0;
+    int last_base = 0, last_m = 0;
     for (int b = s; b < e && !finished; b += kBwdBatch) {
         const int m = min(kBwdBatch, e - b);
         const int base = (b - s) & kBwdRingMask;
-        last_b = b;
+        const int pbase = base ^ kBwdBatch;
+        last_base = base;
         last_m = m;
-        bool qm[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            qm[h] = false;
-            if (jj < m) {
-                uint32_t mk;
-                const uint32_t id = safe_id(a.list[b + jj], a.n);
-                s_rec[base + jj] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                               a.alpha_min, &mk);
-                s_id[base + jj] = id;
-                qm[h] = (mk & qbit) != 0u;
-            }
+        bool qm = false;
+        if (lane < m) {
+            uint32_t mk;
+            const uint32_t id = safe_id(a.list[b + lane], a.n);
+            s_rec[base + lane] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                             a.alpha_min, &mk);
+            s_id[base + lane] = id;
+            s_dn[lane] = a.dnum[id];
+            qm = (mk & qbit) != 0u;
         }
-        cur.lo = __ballot(qm[0]);
-        cur.hi = __ballot(qm[1]);
+        const unsigned long long cur = __ballot(qm);
         __syncthreads();
         const int lo_pos = max(s, b - kBwdBatch);
-        int Lh[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int jj = lane + 64 * h;
-            Lh[h] = b + min(jj, m);
-            if (jj < m) {
-                const float thr = s_rec[base + jj].g1.w - a.bias;
-                if (lo_pos > s && !(s_rec[(lo_pos - s) & kBwdRingMask].g1.w < thr)) {
-                    Lh[h] = -1;
-                } else {
-                    int lo = lo_pos, hi = b + jj;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_rec[(mid - s) & kBwdRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
-                    }
-                    Lh[h] = lo;
+        int L = b + min(lane, m);
+        if (lane < m) {
+            const float thr = s_rec[base + lane].g1.w - a.bias;
+            if (lo_pos > s && !(s_rec[(lo_pos - s) & kBwdRingMask].g1.w < thr)) {
+                L = -1;
+            } else {
+                int lo = lo_pos, hi = b + lane;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_rec[(mid - s) & kBwdRingMask].g1.w < thr) lo = mid + 1; else hi = mid;
                 }
+                L = lo;
             }
         }
-        Bits128b todo = cur;
-        while (todo.lo | todo.hi) {
-            const int j = first_bit_b(todo);
-            clear_bit_b(todo, j);
-            const Staged sj = s_rec[base + j];
-            const int L0 = __builtin_amdgcn_readlane(Lh[0], j & 63);
-            const int L1 = __builtin_amdgcn_readlane(Lh[1], j & 63);
-            const int Lj = j < 64 ? L0 : L1;
-            const float thr_d = sj.g1.w - a.bias;
-            const int stop = Lj >= 0 ? Lj : b + j;
-            while (trail < stop) {
-                if (trail < lo_pos) {
-                    uint32_t mk;
-                    const uint32_t kid = safe_id(a.list[trail], a.n);
-                    const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                                  a.alpha_min, &mk);
-                    if (Lj < 0 && !(tk.g1.w < thr_d)) break;
-                    if (mk & qbit) occlude(tk, kid, -1);
-                    ++trail;
-                    continue;
-                }
-                const bool in_cur = trail >= b;
-                const int bstart = in_cur ? b : b - kBwdBatch;
-                const int lo = trail - bstart, hi = min(stop - bstart, kBwdBatch);
-                Bits128b rel = range_bits_b(lo, hi);
-                const Bits128b msk = in_cur ? cur : prv;
-                rel.lo &= msk.lo;
-                rel.hi &= msk.hi;
-                bool stopped = false;
-                while (rel.lo | rel.hi) {
-                    const int k = first_bit_b(rel);
-                    clear_bit_b(rel, k);
-                    const int slot = (bstart + k - s) & kBwdRingMask;
-                    const Staged tk = s_rec[slot];
-                    if (Lj < 0 && !(tk.g1.w < thr_d)) {
-                        trail = bstart + k;
-                        stopped = true;
-                        break;
-                    }
-                    occlude(tk, s_id[slot], slot);
-                }
-                if (stopped) break;
-                trail = bstart + hi;
-            }
+        const unsigned long long before = __ballot(L < 0);
+        // lead j: false when every pixel of the quadrant is dark
+        auto lead_eval = [&](int j) {
             alive = alive && tt >= kBwdEps;
-            if (!__ballot(alive)) {
-                finished = true;
-                break;
-            }
+            if (!__ballot(alive)) return false;
+            const Staged sj = s_rec[base + j];
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
             const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
             const bool hit = alive && q >= sj.g1.y;
             if (__ballot(hit)) {
-                const uint32_t idj = s_id[base + j];
-                const float dn = a.dnum[idj];
+                const float dn = s_dn[j];
                 const float beta = fast_exp2(q);
                 const float wv = hit ? dn * beta * tt : 0.f;
                 if (PASS == 0) {
                     gm += wv;
                 } else {
-                    float g[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-                    if (hit && dn != 0.f) {
-                        const QGrad gq = q_grad(wv * kLn2, dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
-                        g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
-                    }
                     if (dn != 0.f) {
+                        float g[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                        if (hit) {
+                            const QGrad gq = q_grad(wv * kLn2, dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
+                            g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
+                        }
 #pragma unroll
                         for (int c = 0; c < 5; ++c) {
                             const float sum = wave_sum_lane63(g[c]);
@@ -507,13 +436,80 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                     gm -= wv;
                 }
             }
+            return true;
+        };
+        // leads whose L lies before the ring: walk older entries from global
+        // memory up to L, comparing distances
+        unsigned long long todo = cur & before;
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const float thr_d = uniform_f(s_rec[base + j].g1.w) - a.bias;
+            while (trail < lo_pos) {
+                uint32_t mk;
+                const uint32_t kid = safe_id(a.list[trail], a.n);
+                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                              a.alpha_min, &mk);
+                if (!(uniform_f(tk.g1.w) < thr_d)) break;
+                if (uniform_u(mk) & qbit) occlude(tk, uniform_u(kid), -1);
+                ++trail;
+            }
+            if (!lead_eval(j)) {
+                finished = true;
+                break;
+            }
+        }
+        todo = cur & ~before;
+        if (!finished && todo) {
+            // entries before the ring precede every remaining lead's L
+            while (trail < lo_pos) {
+                uint32_t mk;
+                const uint32_t kid = safe_id(a.list[trail], a.n);
+                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                              a.alpha_min, &mk);
+                if (uniform_u(mk) & qbit) occlude(tk, uniform_u(kid), -1);
+                ++trail;
+            }
+            // the lane's segment [max(trail, L(previous lead)), L) as sets of
+            // ring entries of the previous and the current batch
+            const unsigned long long below = todo & ((1ull << lane) - 1ull);
+            const int prev = below ? 63 - __builtin_clzll(below) : 0;
+            const int Lprev = __builtin_amdgcn_ds_bpermute(prev << 2, L);
+            const int lo_abs = below ? max(Lprev, trail) : trail;
+            unsigned long long mp = 0ull, mc = 0ull;
+            if ((todo >> lane) & 1ull) {
+                mp = range_mask64(lo_abs - (b - kBwdBatch), L - (b - kBwdBatch)) & prv;
+                mc = range_mask64(lo_abs - b, L - b) & cur;
+            }
+            const int last = 63 - __builtin_clzll(todo);
+            while (todo) {
+                const int j = __builtin_ctzll(todo);
+                todo &= todo - 1ull;
+                unsigned long long op = readlane64(mp, j);
+                while (op) {
+                    const int k = __builtin_ctzll(op);
+                    op &= op - 1ull;
+                    occlude(s_rec[pbase + k], 0u, pbase + k);
+                }
+                unsigned long long oc = readlane64(mc, j);
+                while (oc) {
+                    const int k = __builtin_ctzll(oc);
+                    oc &= oc - 1ull;
+                    occlude(s_rec[base + k], 0u, base + k);
+                }
+                if (!lead_eval(j)) {
+                    finished = true;
+                    break;
+                }
+            }
+            trail = __builtin_amdgcn_readlane(L, last);
         }
         // the previous batch leaves the ring: its gradients are final
-        if (PASS == 1 && b - kBwdBatch >= s) flush(b - kBwdBatch - s, kBwdBatch);
+        if (PASS == 1 && b - kBwdBatch >= s) flush(pbase, kBwdBatch);
         prv = cur;
         __syncthreads();
     }
-    if (PASS == 1 && last_b >= s) flush(last_b - s, last_m);
+    if (PASS == 1 && last_m > 0) flush(last_base, last_m);
     if (PASS == 0 && inside) a.gray[pix] = gm;
 }
 

@@ -164,6 +164,41 @@ __device__ inline float wave_sum_lane63(float x) {
     return x;
 }
 
+// The lists, pointers and distances a wave walks are the same in every
+// lane; reading such a value through readfirstlane tells the compiler so,
+// which keeps the pointer arithmetic and loop control in scalar registers
+// and scalar branches.
+__device__ inline float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// Bits lo .. hi-1 of a 64-bit set (lo and hi clamped to [0, 64]).
+__device__ inline unsigned long long range_mask64(int lo, int hi) {
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > 64 ? 64 : hi;
+    if (hi <= lo) return 0ull;
+    const unsigned long long up = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return up & ~((1ull << lo) - 1ull);
+}
+
+// A lane's 64-bit value as seen by lane j (j wave-uniform).
+__device__ inline unsigned long long readlane64(unsigned long long x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum of x over each 16-lane row, in every lane of the row (DPP butterfly in
+// quads, then half-row and row mirrors).
+__device__ inline float row_sum16(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, true));  // row_half_mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, true));  // row_mirror
+    return x;
+}
+
 __device__ inline float wave_sum(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(x)), 63));
 }
