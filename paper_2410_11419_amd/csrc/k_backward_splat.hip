@@ -382,11 +382,12 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         if (lane < m) {
             uint32_t mk;
             const uint32_t id = safe_id(a.list[b + lane], a.n);
-            s_rec[base + lane] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                             a.alpha_min, &mk);
+            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
+                                           a.alpha_min, &mk);
+            s_rec[base + lane] = rec;
             s_id[base + lane] = id;
             s_dn[lane] = a.dnum[id];
-            qm = (mk & qbit) != 0u;
+            qm = (mk & qbit) != 0u && quad_reach(rec, qd);
         }
         const unsigned long long cur = __ballot(qm);
         __syncthreads();

@@ -122,10 +122,11 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
         if (lane < m) {
             uint32_t mk;
             const uint32_t id = safe_id(a.list[b + lane], a.n);
-            s_rec[base + lane] = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff, a.alpha_min,
-                                             &mk);
+            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff, a.alpha_min,
+                                           &mk);
+            s_rec[base + lane] = rec;
             s_id[base + lane] = id;
-            qm = (mk & qbit) != 0u;
+            qm = (mk & qbit) != 0u && quad_reach(rec, qd);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_sum[r][lane] = 0.f;

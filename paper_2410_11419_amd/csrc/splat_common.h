@@ -103,6 +103,29 @@ __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec
     return s;
 }
 
+// Whether the hit region q >= thr of staged splat s can reach a pixel centre
+// of the 8x8 quadrant qd of its tile: the maximum of the concave quadratic q
+// over the rectangle spanned by the quadrant's pixel centres (the value at
+// the splat centre when that lies inside, else the best point of each edge,
+// a one-dimensional concave maximum clamped to the edge), compared with thr
+// less a slack that covers the float32 rounding of the per-pixel test. False
+// only when no pixel centre of the quadrant is hit, so skipping the splat
+// there changes no result.
+__device__ inline bool quad_reach(const Staged& s, int qd) {
+    const float A = s.g0.z, B = s.g0.w, C = s.g1.x, thr = s.g1.y;
+    if (!(A < 0.f && C < 0.f)) return true;
+    const float x0 = (8.f * (qd & 1) + 0.5f) - s.g0.x, x1 = x0 + 7.f;     // dx over the quadrant
+    const float y0 = (8.f * (qd >> 1) + 0.5f) - s.g0.y, y1 = y0 + 7.f;    // dy over the quadrant
+    if (x0 <= 0.f && 0.f <= x1 && y0 <= 0.f && 0.f <= y1) return true;
+    const float kx = -0.5f * B / A, ky = -0.5f * B / C;   // argmax of q in dx for fixed dy, in dy for fixed dx
+    auto on_x_edge = [&](float dx) { return quad_q(dx, fminf(fmaxf(ky * dx, y0), y1), A, B, C); };
+    auto on_y_edge = [&](float dy) { return quad_q(fminf(fmaxf(kx * dy, x0), x1), dy, A, B, C); };
+    const float best = fmaxf(fmaxf(on_x_edge(x0), on_x_edge(x1)), fmaxf(on_y_edge(y0), on_y_edge(y1)));
+    const float mx = fmaxf(fabsf(x0), fabsf(x1)), my = fmaxf(fabsf(y0), fabsf(y1));
+    const float mag = (-A * mx) * mx + (fabsf(B) * mx) * my + (-C * my) * my;
+    return best >= thr - (1e-5f * mag + 1e-3f * fabsf(thr) + 1e-6f);
+}
+
 // Row-group mask of a staged splat: bit r set when the hit ellipse's
 // bounding box (padded like stage_splat's) reaches tile rows 4r .. 4r+3.
 __device__ inline uint32_t rowgroup_mask(const float4 r1, float v, float p) {
