@@ -241,18 +241,25 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
 // the hit ellipse's bounding box. The centre is formed relative to each
 // tile's origin exactly as in stage_splat, so every pixel test is
 // bit-identical to the one k_shadow makes.
+// Everything but the pixel is the same in all lanes of the wave; the
+// readfirstlane reads say so, which keeps the loops and the block culls in
+// scalar registers and scalar branches.
 __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
-    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = __lane_id();
     const int lx = lane & 15, ly = lane >> 4;
     const int n = (int)a.n;
     const int tiles_y = (a.height + kTile - 1) / kTile;
+    auto uf4 = [](float4 x) { return make_float4(uniform_f(x.x), uniform_f(x.y), uniform_f(x.z), uniform_f(x.w)); };
     for (int g = blockIdx.x * 4 + w; g < n; g += gridDim.x * 4) {
-        const int4 ex = a.ext[g];
+        const int4 exv = a.ext[g];
+        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(exv.x), __builtin_amdgcn_readfirstlane(exv.y),
+                                  __builtin_amdgcn_readfirstlane(exv.z), __builtin_amdgcn_readfirstlane(exv.w));
         float acc = 0.f;
         int x0, x1, y0, y1;
         if (tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
-            const float4 r0 = a.rec0[g];
-            const float4 r1 = a.rec1[g];
+            const float4 r0 = uf4(a.rec0[g]);
+            const float4 r1 = uf4(a.rec1[g]);
             float A, B, C, thr;
             const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
             float hx = 3.0e38f, hy = 3.0e38f;
