@@ -23,7 +23,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgs3.so")
 ARCH = "gfx950"
 
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# - no packed fp32 instructions (plain float code only);
+# - no atomic optimizer: the kernels reduce a value across the wave (or a
+#   16-lane row) before one lane adds it, and the optimizer would wrap each
+#   such single-lane atomic in a scan loop over the active lanes.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def hipcc() -> str:

@@ -112,8 +112,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
             s_c1[tid] = a.col1[id];
         }
         __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            if (!(s_mask[j] & wbit)) continue;
+        // the forward's sets of entries that can hit this wave's quadrant
+        unsigned long long set[4] = {0ull, 0ull, 0ull, 0ull};
+        if (__ballot(!done)) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int jj = 64 * h + lane;
+                set[h] = __ballot(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          unsigned long long todo = set[h];
+          while (todo) {
+            const int j = 64 * h + __builtin_ctzll(todo);
+            todo &= todo - 1ull;
             if (__ballot(!done) == 0) break;
             const Staged sj = s_rec[j];
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
@@ -159,12 +172,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
                 T = tn;
             }
             if (__ballot(hit)) {
+                // per-row sums, added into the entry by one lane of each row
+                row_sums16<kCamGrads>(gv);
+                if ((lane & 15) == 15) {
 #pragma unroll
-                for (int c = 0; c < kCamGrads; ++c) {
-                    const float sum = wave_sum_lane63(gv[c]);
-                    if (lane == 63 && sum != 0.f) atomicAdd(&s_g[c][j], sum);
+                    for (int c = 0; c < kCamGrads; ++c)
+                        if (gv[c] != 0.f) atomicAdd(&s_g[c][j], gv[c]);
                 }
             }
+          }
         }
         __syncthreads();
         if (tid < m) {
@@ -359,12 +375,18 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                 g[5] = dal * beta;
             }
             if (__ballot(g[5] != 0.f)) {
+                if (slot >= 0) {
+                    // per-row sums, added into the slot by one lane of each row
+                    row_sums16<6>(g);
+                    if ((lane & 15) == 15) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const float sum = wave_sum_lane63(g[c]);
-                    if (lane == 63) {
-                        if (slot >= 0) s_acc[c][slot] += sum;
-                        else atomicAdd(&a.gsplat[(size_t)c * a.n + kid], sum);
+                        for (int c = 0; c < 6; ++c) atomicAdd(&s_acc[c][slot], g[c]);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        const float sum = wave_sum_lane63(g[c]);
+                        if (lane == 63) atomicAdd(&a.gsplat[(size_t)c * a.n + kid], sum);
                     }
                 }
             }
@@ -428,10 +450,10 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                             const QGrad gq = q_grad(wv * kLn2, dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
                             g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
                         }
+                        row_sums16<5>(g);
+                        if ((lane & 15) == 15) {
 #pragma unroll
-                        for (int c = 0; c < 5; ++c) {
-                            const float sum = wave_sum_lane63(g[c]);
-                            if (lane == 63) s_acc[c][base + j] += sum;
+                            for (int c = 0; c < 5; ++c) atomicAdd(&s_acc[c][base + j], g[c]);
                         }
                     }
                     gm -= wv;

@@ -57,8 +57,22 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
             s_c1[tid] = a.col1[id];
         }
         __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            if (!(s_mask[j] & wbit)) continue;
+        // the entries that can hit a pixel centre of this wave's quadrant, as
+        // four 64-bit sets (bounding box, then the hit ellipse itself)
+        unsigned long long set[4] = {0ull, 0ull, 0ull, 0ull};
+        if (__ballot(!done)) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int jj = 64 * h + lane;
+                set[h] = __ballot(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          unsigned long long todo = set[h];
+          while (todo) {
+            const int j = 64 * h + __builtin_ctzll(todo);
+            todo &= todo - 1ull;
             if (__ballot(!done) == 0) break;
             const Staged sj = s_rec[j];
             const float q = splat_q(sj, pxc, pyc);
@@ -83,6 +97,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
                 T = tn;
                 last = b + j - s + 1;
             }
+          }
         }
         __syncthreads();
     }

@@ -251,15 +251,30 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     const int n = (int)a.n;
     const int tiles_y = (a.height + kTile - 1) / kTile;
     auto uf4 = [](float4 x) { return make_float4(uniform_f(x.x), uniform_f(x.y), uniform_f(x.z), uniform_f(x.w)); };
-    for (int g = blockIdx.x * 4 + w; g < n; g += gridDim.x * 4) {
-        const int4 exv = a.ext[g];
-        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(exv.x), __builtin_amdgcn_readfirstlane(exv.y),
-                                  __builtin_amdgcn_readfirstlane(exv.z), __builtin_amdgcn_readfirstlane(exv.w));
+    const int stride = gridDim.x * 4;
+    int g = blockIdx.x * 4 + w;
+    // the next Gaussian's extent and records are loaded while the current
+    // one is evaluated
+    int4 nx_ex = make_int4(0, 0, 0, 0);
+    float4 nx_r0 = make_float4(0.f, 0.f, 0.f, 0.f), nx_r1 = nx_r0;
+    if (g < n) {
+        nx_ex = a.ext[g];
+        nx_r0 = a.rec0[g];
+        nx_r1 = a.rec1[g];
+    }
+    for (; g < n; g += stride) {
+        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(nx_ex.x), __builtin_amdgcn_readfirstlane(nx_ex.y),
+                                  __builtin_amdgcn_readfirstlane(nx_ex.z), __builtin_amdgcn_readfirstlane(nx_ex.w));
+        const float4 r0 = uf4(nx_r0);
+        const float4 r1 = uf4(nx_r1);
+        if (g + stride < n) {
+            nx_ex = a.ext[g + stride];
+            nx_r0 = a.rec0[g + stride];
+            nx_r1 = a.rec1[g + stride];
+        }
         float acc = 0.f;
         int x0, x1, y0, y1;
         if (tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
-            const float4 r0 = uf4(a.rec0[g]);
-            const float4 r1 = uf4(a.rec1[g]);
             float A, B, C, thr;
             const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
             float hx = 3.0e38f, hy = 3.0e38f;

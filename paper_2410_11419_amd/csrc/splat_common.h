@@ -222,6 +222,20 @@ __device__ inline float row_sum16(float x) {
     return x;
 }
 
+// Row sums (as row_sum16) of N values at once, the DPP steps interleaved
+// across the values so that no step waits on the one before it.
+template <int N>
+__device__ inline void row_sums16(float (&x)[N]) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[c]), 0xB1, 0xF, 0xF, true));
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[c]), 0x4E, 0xF, 0xF, true));
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[c]), 0x141, 0xF, 0xF, true));
+#pragma unroll
+    for (int c = 0; c < N; ++c) x[c] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[c]), 0x140, 0xF, 0xF, true));
+}
+
 __device__ inline float wave_sum(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(x)), 63));
 }
