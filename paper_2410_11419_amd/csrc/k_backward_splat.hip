@@ -114,11 +114,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
         __syncthreads();
         // the forward's sets of entries that can hit this wave's quadrant
         unsigned long long set[4] = {0ull, 0ull, 0ull, 0ull};
-        if (__ballot(!done)) {
+        if (__builtin_amdgcn_ballot_w64(!done)) {
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int jj = 64 * h + lane;
-                set[h] = __ballot(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
+                set[h] = __builtin_amdgcn_ballot_w64(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
             }
         }
 #pragma unroll
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
           while (todo) {
             const int j = 64 * h + __builtin_ctzll(todo);
             todo &= todo - 1ull;
-            if (__ballot(!done) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
             const Staged sj = s_rec[j];
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
             const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
                 }
                 T = tn;
             }
-            if (__ballot(hit)) {
+            if (__builtin_amdgcn_ballot_w64(hit)) {
                 // per-row sums, added into the entry by one lane of each row
                 row_sums16<kCamGrads>(gv);
                 if ((lane & 15) == 15) {
@@ -235,36 +235,59 @@ struct ShadowBwdArgs {
 
 // den part: writes gsplat (=, the numerator sweeps then add) and dnum.
 __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
-    const int w = threadIdx.x >> 6, lane = __lane_id();
+    // the Gaussian and its records are wave-uniform (scalar loop control)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = __lane_id();
     const int lx = lane & 15, ly = lane >> 4;
     const int n = (int)a.n;
     const int tiles_y = (a.height + kTile - 1) / kTile;
+    auto uf4 = [](float4 x) { return make_float4(uniform_f(x.x), uniform_f(x.y), uniform_f(x.z), uniform_f(x.w)); };
     for (int g = blockIdx.x * 4 + w; g < n; g += gridDim.x * 4) {
-        const float den = a.num_den[n + g];
-        const float dTg = a.dT[g];
-        const float dden = den > 0.f ? -dTg * a.T[g] / den : 0.f;
-        const int4 ex = a.ext[g];
+        const float den = uniform_f(a.num_den[n + g]);
+        const float dTg = uniform_f(a.dT[g]);
+        const float dden = den > 0.f ? -dTg * uniform_f(a.T[g]) / den : 0.f;
+        const int4 exv = a.ext[g];
+        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(exv.x), __builtin_amdgcn_readfirstlane(exv.y),
+                                  __builtin_amdgcn_readfirstlane(exv.z), __builtin_amdgcn_readfirstlane(exv.w));
         float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         int x0, x1, y0, y1;
         if (dden != 0.f && tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
-            const float4 r0 = a.rec0[g];
-            const float4 r1 = a.rec1[g];
+            const float4 r0 = uf4(a.rec0[g]);
+            const float4 r1 = uf4(a.rec1[g]);
             float A, B, C, thr;
             const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
             float hx = 3.0e38f, hy = 3.0e38f;
+            bool banded = false;
             if (!isinf(p)) {
                 const float det = r1.x * r1.z - r1.y * r1.y;
                 hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
                 hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+                // large elongated splats (16 tiles or more, bounding box
+                // over 2.5x the ellipse): narrow the tile columns per tile
+                // row to the ellipse's own x-extent there
+                banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
+            }
+            RowExtent rows;
+            if (banded) {
+                rows = row_extent(A, B, C, thr);
+                banded = rows.valid;
             }
             if (p > 0.f) {
                 for (int ty = y0; ty <= y1; ++ty) {
                     const float oy = (float)(ty * kTile);
                     const float v = rel_centre(r0.y, r0.w, oy);
+                    // the ellipse's x-range within this tile row's pixel rows
+                    float lo = -hx, hi = hx;
+                    if (banded) {
+                        float bl, bh;
+                        if (!band_x_range(rows, 0.5f - v, 15.5f - v, &bl, &bh)) continue;
+                        lo = fmaxf(lo, bl);
+                        hi = fminf(hi, bh);
+                    }
                     for (int tx = x0; tx <= x1; ++tx) {
                         const float ox = (float)(tx * kTile);
                         const float u = rel_centre(r0.x, r0.z, ox);
-                        if (u + hx < 0.5f || u - hx > 15.5f) continue;
+                        if (u + hi < 0.5f || u + lo > 15.5f) continue;
                         const float dx = (float)lx + 0.5f - u;
                         const bool in_x = tx * kTile + lx < a.width;
 #pragma unroll
@@ -332,7 +355,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     float tt = 1.f;
     unsigned long long prv = 0ull;
     int trail = s;
-    bool finished = e <= s || !__ballot(alive);
+    bool finished = e <= s || !__builtin_amdgcn_ballot_w64(alive);
     if (PASS == 1) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -362,7 +385,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         const float dx = pxc - k.g0.x, dy = pyc - k.g0.y;
         const float q = quad_q(dx, dy, k.g0.z, k.g0.w, k.g1.x);
         const bool hit = alive && q >= k.g1.y;
-        if (!__ballot(hit)) return;
+        if (!__builtin_amdgcn_ballot_w64(hit)) return;
         const float beta = fast_exp2(q);
         const float ob = k.g1.z * beta;
         const float al = fminf(a.alpha_max, ob);
@@ -374,7 +397,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                 g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
                 g[5] = dal * beta;
             }
-            if (__ballot(g[5] != 0.f)) {
+            if (__builtin_amdgcn_ballot_w64(g[5] != 0.f)) {
                 if (slot >= 0) {
                     // per-row sums, added into the slot by one lane of each row
                     row_sums16<6>(g);
@@ -411,7 +434,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             s_dn[lane] = a.dnum[id];
             qm = (mk & qbit) != 0u && quad_reach(rec, qd);
         }
-        const unsigned long long cur = __ballot(qm);
+        const unsigned long long cur = __builtin_amdgcn_ballot_w64(qm);
         __syncthreads();
         const int lo_pos = max(s, b - kBwdBatch);
         int L = b + min(lane, m);
@@ -428,16 +451,16 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                 L = lo;
             }
         }
-        const unsigned long long before = __ballot(L < 0);
+        const unsigned long long before = __builtin_amdgcn_ballot_w64(L < 0);
         // lead j: false when every pixel of the quadrant is dark
         auto lead_eval = [&](int j) {
             alive = alive && tt >= kBwdEps;
-            if (!__ballot(alive)) return false;
+            if (!__builtin_amdgcn_ballot_w64(alive)) return false;
             const Staged sj = s_rec[base + j];
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
             const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
             const bool hit = alive && q >= sj.g1.y;
-            if (__ballot(hit)) {
+            if (__builtin_amdgcn_ballot_w64(hit)) {
                 const float dn = s_dn[j];
                 const float beta = fast_exp2(q);
                 const float wv = hit ? dn * beta * tt : 0.f;

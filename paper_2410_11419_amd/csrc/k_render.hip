@@ -60,11 +60,11 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
         // the entries that can hit a pixel centre of this wave's quadrant, as
         // four 64-bit sets (bounding box, then the hit ellipse itself)
         unsigned long long set[4] = {0ull, 0ull, 0ull, 0ull};
-        if (__ballot(!done)) {
+        if (__builtin_amdgcn_ballot_w64(!done)) {
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int jj = 64 * h + lane;
-                set[h] = __ballot(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
+                set[h] = __builtin_amdgcn_ballot_w64(jj < m && (s_mask[jj] & wbit) && quad_reach(s_rec[jj], w));
             }
         }
 #pragma unroll
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
           while (todo) {
             const int j = 64 * h + __builtin_ctzll(todo);
             todo &= todo - 1ull;
-            if (__ballot(!done) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
             const Staged sj = s_rec[j];
             const float q = splat_q(sj, pxc, pyc);
             bool hit = !done && q >= sj.g1.y;

@@ -87,20 +87,19 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
     const float pxc = lx + 0.5f, pyc = ly + 0.5f;
     const float tile_x0 = (float)(tx * kTile), tile_y0 = (float)(ty * kTile);
     bool alive = (tx * kTile + lx < a.width) && (ty * kTile + ly < a.height);
-    if (!__ballot(alive)) return;
+    if (!__builtin_amdgcn_ballot_w64(alive)) return;
     const uint32_t qbit = 1u << qd;
-    // 1 - min(alpha_max, x) == max(1 - alpha_max, 1 - x) exactly: rounding
-    // of 1 - x is monotone in x
-    const float keep_min = 1.f - a.alpha_max;
     float tt = 1.f;
     unsigned long long prv = 0ull;
     int trail = s;
-    // multiply (1 - alpha) of occluder k into tt where it hits
+    // multiply (1 - alpha) of occluder k into tt where it hits (the same
+    // rounding as the adjoint's replay: the fminf keeps 1 - alpha from being
+    // fused with the product)
     auto occlude = [&](const Staged& k) {
         const float q = splat_q(k, pxc, pyc);
         const bool hit = alive && q >= k.g1.y;
-        if (__ballot(hit)) {
-            const float f = fmaxf(keep_min, 1.f - k.g1.z * fast_exp2(q));
+        if (__builtin_amdgcn_ballot_w64(hit)) {
+            const float f = 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
             tt = hit ? tt * f : tt;
         }
     };
@@ -130,7 +129,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) s_sum[r][lane] = 0.f;
-        const unsigned long long cur = __ballot(qm);
+        const unsigned long long cur = __builtin_amdgcn_ballot_w64(qm);
         __syncthreads();
         // L for the lane's entry: the first position in [lo_pos, b + lane)
         // whose distance is not below dist - bias (b + lane if none); -1 when
@@ -150,14 +149,14 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                 L = lo;
             }
         }
-        const unsigned long long before = __ballot(L < 0);
+        const unsigned long long before = __builtin_amdgcn_ballot_w64(L < 0);
         auto lead_eval = [&](int j) {
             alive = alive && tt >= kShadowEps;
-            if (!__ballot(alive)) return false;
+            if (!__builtin_amdgcn_ballot_w64(alive)) return false;
             const Staged sj = s_rec[base + j];
             const float q = splat_q(sj, pxc, pyc);
             const bool hit = alive && q >= sj.g1.y;
-            if (__ballot(hit)) {
+            if (__builtin_amdgcn_ballot_w64(hit)) {
                 const float v = row_sum16(hit ? fast_exp2(q) * tt : 0.f);
                 if ((lane & 15) == 15) s_sum[lane >> 4][j] = v;
             }
@@ -278,19 +277,37 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
             float A, B, C, thr;
             const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
             float hx = 3.0e38f, hy = 3.0e38f;
+            bool banded = false;
             if (!isinf(p)) {
                 const float det = r1.x * r1.z - r1.y * r1.y;
                 hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
                 hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+                // large elongated splats (16 tiles or more, bounding box
+                // over 2.5x the ellipse): narrow the tile columns per tile
+                // row to the ellipse's own x-extent there
+                banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
+            }
+            RowExtent rows;
+            if (banded) {
+                rows = row_extent(A, B, C, thr);
+                banded = rows.valid;
             }
             if (p > 0.f) {
                 for (int ty = y0; ty <= y1; ++ty) {
                     const float oy = (float)(ty * kTile);
                     const float v = rel_centre(r0.y, r0.w, oy);
+                    // the ellipse's x-range within this tile row's pixel rows
+                    float lo = -hx, hi = hx;
+                    if (banded) {
+                        float bl, bh;
+                        if (!band_x_range(rows, 0.5f - v, 15.5f - v, &bl, &bh)) continue;
+                        lo = fmaxf(lo, bl);
+                        hi = fminf(hi, bh);
+                    }
                     for (int tx = x0; tx <= x1; ++tx) {
                         const float ox = (float)(tx * kTile);
                         const float u = rel_centre(r0.x, r0.z, ox);
-                        if (u + hx < 0.5f || u - hx > 15.5f) continue;
+                        if (u + hi < 0.5f || u + lo > 15.5f) continue;
                         const float dx = (float)lx + 0.5f - u;
                         const bool in_x = tx * kTile + lx < a.width;
 #pragma unroll

@@ -126,6 +126,51 @@ __device__ inline bool quad_reach(const Staged& s, int qd) {
     return best >= thr - (1e-5f * mag + 1e-3f * fabsf(thr) + 1e-6f);
 }
 
+// x-extent of the hit region q >= thr per band of rows. For fixed dy the
+// region is the interval xc(dy) -+ w(dy), xc = -B dy / (2A),
+// w = sqrt(4A thr - K dy^2) / (2|A|), K = 4AC - B^2 > 0. Its left end is
+// smallest at the ellipse's leftmost point, which lies at dy = B xmax / (2C)
+// (xmax^2 = 4C thr / K); when that row is outside a band, the convex left
+// end is smallest at a band edge. The right end likewise.
+struct RowExtent {
+    float A, B, K, fourAthr, ymax, xmax, inv2a, yl;
+    bool valid;
+};
+__device__ inline RowExtent row_extent(float A, float B, float C, float thr) {
+    RowExtent e;
+    e.A = A;
+    e.B = B;
+    e.K = 4.f * A * C - B * B;
+    e.valid = A < 0.f && C < 0.f && e.K > 0.f && thr < 0.f && !isinf(thr);
+    // hardware reciprocal and square root (about 1 ulp): the result is
+    // padded by far more than their error
+    const float rK = __builtin_amdgcn_rcpf(e.K);
+    e.fourAthr = 4.f * A * thr;
+    e.ymax = __builtin_amdgcn_sqrtf(e.fourAthr * rK) * 1.01f + 0.02f;
+    e.xmax = __builtin_amdgcn_sqrtf(4.f * C * thr * rK);
+    e.inv2a = 0.5f * __builtin_amdgcn_rcpf(A);  // negative
+    e.yl = 0.5f * B * e.xmax * __builtin_amdgcn_rcpf(C);   // row of the leftmost point; the rightmost is at -yl
+    return e;
+}
+// Range [lo, hi] of dx (offset from the splat centre) that the hit region
+// covers within the band of rows dy0 <= dy <= dy1 (e.valid required); false
+// when the band misses it. Widened by 1 % of xmax + 0.02 px for float32
+// rounding, so it contains every pixel offset the per-pixel test can hit.
+__device__ inline bool band_x_range(const RowExtent& e, float dy0, float dy1, float* lo, float* hi) {
+    dy0 = fmaxf(dy0, -e.ymax);
+    dy1 = fminf(dy1, e.ymax);
+    if (dy0 > dy1) return false;
+    auto w = [&](float dy) { return __builtin_amdgcn_sqrtf(fmaxf(e.fourAthr - e.K * dy * dy, 0.f)) * (-e.inv2a); };
+    const float w0 = w(dy0), w1 = w(dy1);
+    const float c0 = -e.B * dy0 * e.inv2a, c1 = -e.B * dy1 * e.inv2a;
+    const float l = (e.yl >= dy0 && e.yl <= dy1) ? -e.xmax : fminf(c0 - w0, c1 - w1);
+    const float h = (-e.yl >= dy0 && -e.yl <= dy1) ? e.xmax : fmaxf(c0 + w0, c1 + w1);
+    const float pad = 0.01f * e.xmax + 0.02f;
+    *lo = l - pad;
+    *hi = h + pad;
+    return true;
+}
+
 // Row-group mask of a staged splat: bit r set when the hit ellipse's
 // bounding box (padded like stage_splat's) reaches tile rows 4r .. 4r+3.
 __device__ inline uint32_t rowgroup_mask(const float4 r1, float v, float p) {
