@@ -32,9 +32,12 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # numerator pass: offset (2), conic quadratic (5), cut-off test (1), exp (1),
 # alpha = min(alpha_max, o * beta) (2), T_m update (2), num += beta * T_m (2)
 SHADOW_NUM_FLOPS_PER_HIT = 15
-# counter summary of the numerator kernel (HBM bytes per launch), valid while
-# the kernel's sources hash to the value recorded in it
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_shadow_num_300k_light1024.md")
+# flops the definition spends on one hit in the denominator pass: offset (2),
+# conic quadratic (5), cut-off test (1), exp (1), den += beta (1)
+SHADOW_DEN_FLOPS_PER_HIT = 10
+# counter summary of the two shadow-splat kernels (HBM bytes per launch),
+# valid while their sources hash to the value recorded in it
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "shadow_splat_300k_light1024.md")
 KERNEL_SOURCES = ("paper_2410_11419_amd/csrc/k_shadow.hip", "paper_2410_11419_amd/csrc/splat_common.h")
 
 
@@ -57,6 +60,9 @@ def parse():
                     help="offered loads as fractions of the plain renderer's saturation rate")
     ap.add_argument("--profile-train", action="store_true",
                     help="only run two fwd+bwd steps (for rocprofv3), no JSON")
+    ap.add_argument("--profile-fluffy", action="store_true",
+                    help="only run two fwd+bwd steps of the dense scene (for rocprofv3), no JSON")
+    ap.add_argument("--lanes", type=int, default=4, help="concurrent lanes of the dense scene's step")
     return ap.parse_args()
 
 
@@ -99,9 +105,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the numerator kernel from the committed
-    counter summary, or None when the kernel changed since it was taken."""
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` (k_shadow or k_shadow_den) from the
+    committed counter summary, or None when the kernels changed since it was
+    taken."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -114,7 +121,7 @@ def profiled_traffic():
     if vals.get("source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return int(vals["hbm_bytes_per_launch"])
+        return int(vals[f"hbm_bytes_per_launch {kernel}"])
     except (KeyError, ValueError):
         return None
 
@@ -215,7 +222,7 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
             "step_ms_events": round(per, 3)}
 
 
-def fluffy_train_bench(steps):
+def fluffy_train_bench(steps, profile=False, lanes=4):
     """The dense scene's training step: 1.5M Gaussians (70 % low-opacity
     needles in the cube, 30 % shell), batch of 8 (camera 1024x1024 at 40 deg,
     light 2048x2048 at 60 deg) pairs, L1 loss, 4 concurrent lanes. Also
@@ -225,11 +232,13 @@ def fluffy_train_bench(steps):
     sc = synth.scene_fluffy()
     ds = gs3.DeviceScene.from_host(sc)
     pairs = synth.fluffy_pairs(8)
-    res = train_step_bench(ds, sc, steps, 1, pairs=pairs, batch=8, lanes=4,
+    res = train_step_bench(ds, sc, steps, 1, profile=profile, pairs=pairs, batch=8, lanes=lanes,
                            workload="1,500,000 Gaussians (70 % low-opacity needles in [-1,1]^3, 30 % shell), "
                                     "batch of 8 (camera 1024x1024 at 40 deg, light 2048x2048 at 60 deg) pairs, "
                                     "L1 loss against targets from the scene with means + N(0,0.01) and "
                                     "colours + N(0,0.05)")
+    if profile:
+        return None
     rnd = gs3.Renderer(ds)
     cam, light = pairs[0]
     rnd.render(cam, light, check=True)
@@ -339,6 +348,10 @@ def main():
     sc, _, _ = synth.scene_full(n=args.n)
     ds = gs3.DeviceScene.from_host(sc, dev)
     pairs = views()
+    if args.profile_fluffy:
+        with torch.cuda.stream(torch.cuda.Stream()):
+            fluffy_train_bench(0, profile=True, lanes=args.lanes)
+        return
     if args.profile_train:
         with torch.cuda.stream(torch.cuda.Stream()):
             train_step_bench(ds, sc, 0, 1, profile=True)
@@ -392,7 +405,7 @@ def main():
     for i in range(args.warmup):
         fp.render(*pairs[i % len(pairs)], overlap=False)
     torch.cuda.synchronize()
-    evs = [{k: torch.cuda.Event(enable_timing=True) for k in ("f0", "num0", "num1", "f1")}
+    evs = [{k: torch.cuda.Event(enable_timing=True) for k in ("f0", "den0", "den1", "num0", "num1", "f1")}
            for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -409,6 +422,7 @@ def main():
     wall = t1 - t0
     fps = args.steps / wall
     num_ms = sum(e["num0"].elapsed_time(e["num1"]) for e in evs) / args.steps
+    den_ms = sum(e["den0"].elapsed_time(e["den1"]) for e in evs) / args.steps
     frame_ms = sum(e["f0"].elapsed_time(e["f1"]) for e in evs) / args.steps
     # one frame at a time (no pipelining; stages overlapped inside the frame)
     single = gs3.FramePipeline(ds, depth=1)
@@ -450,9 +464,20 @@ def main():
     stage /= n_ser
     used = [stats[i % len(pairs)] for i in range(args.steps)]
     p_l, p_c, h_l, h_c = [float(np.mean([u[j] for u in used])) for j in range(4)]
-    t_num = num_ms / 1e3
-    num_tflops = h_l * SHADOW_NUM_FLOPS_PER_HIT / t_num / 1e12
-    traffic = profiled_traffic()
+    # one roofline entry per shadow-splat kernel (both VALU-bound; the same
+    # hits, counted by gs3_view_count_hits); `roofline` is the longer one
+    kernels = []
+    for name, label, per_hit, ms in (
+            ("k_shadow", "k_shadow (shadow splat numerator, gs3_shadow_num)", SHADOW_NUM_FLOPS_PER_HIT, num_ms),
+            ("k_shadow_den", "k_shadow_den (shadow splat denominator, gs3_shadow_den)", SHADOW_DEN_FLOPS_PER_HIT,
+             den_ms)):
+        tflops = h_l * per_hit / (ms / 1e3) / 1e12
+        kernels.append({"bound": "alu", "kernel": label, "achieved": round(tflops, 3),
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": profiled_traffic(name),
+                        "per_unit": f"{per_hit} flop per light-view hit", "units_per_launch": int(h_l),
+                        "avg_launch_ms": round(ms, 4)})
+    dominant = max(kernels, key=lambda r: r["avg_launch_ms"])
     fb = frame_bytes(sc.n, sc.k, p_l, p_c, 800 * 800)
     frame_gbs = fb / (wall / args.steps) / 1e9
     out = {
@@ -471,12 +496,8 @@ def main():
         "config": {"workload": "full relit forward: 300,000 Gaussians, 8 lobes, Phi and Psi 3x64, "
                                "camera 800x800, light 1024x1024, 40 deg fov, 4 view pairs",
                    "n_gaussians": sc.n, "camera": [800, 800], "light": [1024, 1024]},
-        "roofline": {"bound": "alu", "kernel": "k_shadow (shadow splat numerator, gs3_shadow_num)",
-                     "achieved": round(num_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(num_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": traffic,
-                     "per_unit": f"{SHADOW_NUM_FLOPS_PER_HIT} flop per light-view hit",
-                     "units_per_launch": int(h_l), "avg_launch_ms": round(num_ms, 4)},
+        "roofline": dominant,
+        "roofline_kernels": kernels,
         "frames_in_flight": args.inflight,
         "single_frame_fps": round(single_fps, 3),
         "stages_ms_serial": {"light_preprocess": round(stage[0], 4), "shadow_den": round(stage[1], 4),
@@ -493,7 +514,7 @@ def main():
             out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
     if args.fluffy_steps > 0:
         with torch.cuda.stream(side):
-            out["train_step_fluffy"] = fluffy_train_bench(args.fluffy_steps)
+            out["train_step_fluffy"] = fluffy_train_bench(args.fluffy_steps, lanes=args.lanes)
     if args.serving_requests > 0:
         del rnd, fp, single
         with torch.cuda.stream(side):

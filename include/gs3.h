@@ -67,7 +67,11 @@ enum {
  *                      transmittance below t_min
  *   shadow_bias 0.015  Gaussian k shadows j only if dist_k < dist_j - bias
  * cutoff = +inf, alpha_min = 0, alpha_max = 1, t_min = 0, dilation = 0 and
- * shadow_bias = 0 give the threshold-free ("smooth") variant. */
+ * shadow_bias = 0 give the threshold-free ("smooth") variant.
+ * near_plane, clamp_frac, dilation, cutoff and alpha_min act at projection
+ * (gs3_project / gs3_preprocess), which stores the resulting per-splat hit
+ * threshold with the view; later calls on the view take it from there and
+ * use only alpha_max, t_min and shadow_bias of their own `consts`. */
 typedef struct {
     float near_plane;
     float clamp_frac;
@@ -194,6 +198,9 @@ int gs3_view_workspace_size(int64_t n, int32_t width, int32_t height,
  * per-axis pixel extent of the hit ellipse) in `ws`. The extent of a splat
  * is rx = ceil(sqrt(2 p Sigma'_xx)), ry = ceil(sqrt(2 p Sigma'_yy)) with
  * p = min(cutoff, ln(opacity / alpha_min)); culled splats get rx = ry = -1.
+ * The float32 hit threshold of each splat (q >= thr with q = power log2 e)
+ * and its padded bounding box are stored too: every splatting kernel that
+ * tests pixels of this view reads them, so all take the same decisions.
  * vb->n must equal scene->n and vb's size the view's. */
 int gs3_project(const gs3_scene* scene, const gs3_view* view,
                 const gs3_consts* consts, int32_t depth_mode,

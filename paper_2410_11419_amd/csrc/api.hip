@@ -62,6 +62,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.hdr = take(sizeof(ViewHeader));
     l.rec0 = take(sizeof(float4) * n);
     l.rec1 = take(sizeof(float4) * n);
+    l.rec2 = take(sizeof(float4) * n);
     l.depth = take(sizeof(float) * n);
     l.ext = take(sizeof(int4) * n);
     l.cnt = take(sizeof(uint32_t) * n);

@@ -32,6 +32,9 @@ struct ViewHeader {
 //   rec0 = {floor(u), floor(v), u - floor(u), v - floor(v)}  (pixel centre,
 //          split so a tile-relative centre can be formed without rounding)
 //   rec1 = {a, b, c, opacity}  conic (inverse 2D covariance) and sigmoid opacity
+//   rec2 = {thr, hx, hy, p}    hit threshold of q (float32, the one every kernel
+//                              tests), padded bounding-box half-widths of the hit
+//                              ellipse and the power threshold p (p <= 0: no hits)
 // Culled Gaussians have ext.z = ext.w = -1 and zero records.
 struct Layout {
     int64_t n = 0;
@@ -39,7 +42,7 @@ struct Layout {
     int64_t n_tiles = 0;
     int64_t capacity = 0;
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
-    size_t hdr = 0, rec0 = 0, rec1 = 0, depth = 0, ext = 0, cnt = 0, col0 = 0, col1 = 0;
+    size_t hdr = 0, rec0 = 0, rec1 = 0, rec2 = 0, depth = 0, ext = 0, cnt = 0, col0 = 0, col1 = 0;
     size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
     size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0, order = 0;
     size_t total = 0;

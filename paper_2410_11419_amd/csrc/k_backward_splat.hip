@@ -48,11 +48,12 @@ struct RenderBwdArgs {
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
+    const float4* rec2;   // {thr, hx, hy, p}
     const float4* col0;
     const float4* col1;
     uint32_t n;
     int width, height, tiles_x;
-    float cutoff, alpha_min, alpha_max, t_min;
+    float alpha_max, t_min;
     const float* S;      // [3][H][W]
     const float* Sh;     // [H][W]
     const float* R;      // [3][H][W]
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
         if (tid < m) {
             const uint32_t id = safe_id(a.list[b + tid], a.n);
             uint32_t mk;
-            s_rec[tid] = stage_splat(id, a.rec0, a.rec1, nullptr, tile_x0, tile_y0, a.cutoff, a.alpha_min, &mk);
+            s_rec[tid] = stage_splat(id, a.rec0, a.rec1, a.rec2, nullptr, tile_x0, tile_y0, &mk);
             s_mask[tid] = mk;
             s_id[tid] = id;
             s_c0[tid] = a.col0[id];
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
                 Cc[4] = fmaf(wgt, f[4], Cc[4]);
                 Cc[5] = fmaf(wgt, f[5], Cc[5]);
                 Cc[6] = fmaf(wgt, f[6], Cc[6]);
-                const float inv = 1.f / (1.f - al);
+                const float inv = __builtin_amdgcn_rcpf(1.f - al);   // about 1 ulp
                 float dal = 0.f;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) {
@@ -220,11 +221,12 @@ struct ShadowBwdArgs {
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
+    const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
     const int4* ext;
     uint32_t n;
     int width, height, tiles_x;
-    float cutoff, alpha_min, alpha_max, bias;
+    float alpha_max, bias;
     const float* T;        // [n] forward shadow values
     const float* num_den;  // [2][n]
     const float* dT;       // [n] dL/dT
@@ -254,14 +256,13 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
         if (dden != 0.f && tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
             const float4 r0 = uf4(a.rec0[g]);
             const float4 r1 = uf4(a.rec1[g]);
-            float A, B, C, thr;
-            const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
-            float hx = 3.0e38f, hy = 3.0e38f;
+            const float4 r2 = uf4(a.rec2[g]);
+            float A, B, C;
+            scaled_conic(r1, &A, &B, &C);
+            const float thr = r2.x, hx = r2.y, hy = r2.z, p = r2.w;
             bool banded = false;
             if (!isinf(p)) {
                 const float det = r1.x * r1.z - r1.y * r1.y;
-                hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
-                hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
                 // large elongated splats (16 tiles or more, bounding box
                 // over 2.5x the ellipse): narrow the tile columns per tile
                 // row to the ellipse's own x-extent there
@@ -392,7 +393,8 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         if (PASS == 1) {
             float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (hit && gm != 0.f && ob < a.alpha_max) {
-                const float dal = -gm / (1.f - al);
+                // hardware reciprocal (about 1 ulp) instead of a division
+                const float dal = -gm * __builtin_amdgcn_rcpf(1.f - al);
                 const QGrad gq = q_grad(dal * al * kLn2, dx, dy, k.g0.z, k.g0.w, k.g1.x);
                 g[0] = gq.u; g[1] = gq.v; g[2] = gq.A; g[3] = gq.B; g[4] = gq.C;
                 g[5] = dal * beta;
@@ -427,8 +429,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         if (lane < m) {
             uint32_t mk;
             const uint32_t id = safe_id(a.list[b + lane], a.n);
-            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                           a.alpha_min, &mk);
+            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
             s_rec[base + lane] = rec;
             s_id[base + lane] = id;
             s_dn[lane] = a.dnum[id];
@@ -494,8 +495,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             while (trail < lo_pos) {
                 uint32_t mk;
                 const uint32_t kid = safe_id(a.list[trail], a.n);
-                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                              a.alpha_min, &mk);
+                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
                 if (!(uniform_f(tk.g1.w) < thr_d)) break;
                 if (uniform_u(mk) & qbit) occlude(tk, uniform_u(kid), -1);
                 ++trail;
@@ -511,8 +511,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             while (trail < lo_pos) {
                 uint32_t mk;
                 const uint32_t kid = safe_id(a.list[trail], a.n);
-                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff,
-                                              a.alpha_min, &mk);
+                const Staged tk = stage_splat(kid, a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
                 if (uniform_u(mk) & qbit) occlude(tk, uniform_u(kid), -1);
                 ++trail;
             }
@@ -570,14 +569,13 @@ hipError_t launch_render_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);
+    a.rec2 = at<float4>(ws, L.rec2);
     a.col0 = at<float4>(ws, L.col0);
     a.col1 = at<float4>(ws, L.col1);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
-    a.cutoff = k.cutoff;
-    a.alpha_min = k.alpha_min;
     a.alpha_max = k.alpha_max;
     a.t_min = k.t_min;
     a.S = fwd.shading;
@@ -600,14 +598,13 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);
+    a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
     a.ext = at<int4>(ws, L.ext);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
-    a.cutoff = k.cutoff;
-    a.alpha_min = k.alpha_min;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.T = T;

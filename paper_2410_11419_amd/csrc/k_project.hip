@@ -7,7 +7,7 @@
 // below a float32 ulp of the pixel coordinate, so the float32 per-pixel
 // threshold decisions downstream agree with an exact evaluation except on a
 // vanishing set of pixels.
-#include "gs3_internal.h"
+#include "splat_common.h"
 
 namespace gs3 {
 
@@ -35,7 +35,7 @@ __device__ inline bool tile_rect(int64_t ix, int64_t iy, int64_t rx, int64_t ry,
 
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3_consts kc,
                                                   float4* __restrict__ rec0, float4* __restrict__ rec1,
-                                                  float* __restrict__ depth_out, int4* __restrict__ ext,
+                                                  float4* __restrict__ rec2, float* __restrict__ depth_out, int4* __restrict__ ext,
                                                   uint32_t* __restrict__ cnt, uint32_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,7 +106,10 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
         const double id = 1.0 / det;
         const double fu = floor(u), fv = floor(v);
         rec0[i] = make_float4((float)fu, (float)fv, (float)(u - fu), (float)(v - fv));
-        rec1[i] = make_float4((float)(cc * id), (float)(-cb * id), (float)(ca * id), (float)opac);
+        const float4 r1 = make_float4((float)(cc * id), (float)(-cb * id), (float)(ca * id), (float)opac);
+        rec1[i] = r1;
+        // the float32 hit threshold and bounding box every splat kernel uses
+        rec2[i] = splat_bounds(r1, kc.cutoff, kc.alpha_min);
         ext[i] = make_int4((int)ix, (int)iy, (int)rx, (int)ry);
         const float d32 = (float)dep;
         depth_out[i] = d32;
@@ -115,6 +118,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
     } else {
         rec0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec1[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec2[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         ext[i] = make_int4((int)floor_clamped(u), (int)floor_clamped(v), -1, -1);
         depth_out[i] = (float)dep;
         cnt[i] = 0u;
@@ -146,7 +150,7 @@ hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_co
     if (sc.n == 0) return hipSuccess;
     const int grid = (sc.n + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, st, sc, vp, k, at<float4>(ws, L.rec0),
-                       at<float4>(ws, L.rec1), at<float>(ws, L.depth), at<int4>(ws, L.ext),
+                       at<float4>(ws, L.rec1), at<float4>(ws, L.rec2), at<float>(ws, L.depth), at<int4>(ws, L.ext),
                        at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.keys_a), at<uint32_t>(ws, L.vals_a));
     return hipGetLastError();
 }
@@ -162,6 +166,7 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
     // records are unused by the explicit binning path; zero them for readers
     hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.rec0), 0u, 4 * L.n, st);
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec1), 0u, 4 * L.n, st);
+    if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec2), 0u, 4 * L.n, st);
     return e != hipSuccess ? e : hipGetLastError();
 }
 

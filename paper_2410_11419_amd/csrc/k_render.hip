@@ -17,11 +17,12 @@ struct RenderArgs {
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
+    const float4* rec2;   // {thr, hx, hy, p}
     const float4* col0;   // {c.r, c.g, c.b, T'}
     const float4* col1;   // {r.r, r.g, r.b, 0}
     uint32_t n;
     int width, height, tiles_x;
-    float cutoff, alpha_min, alpha_max, t_min;
+    float alpha_max, t_min;
     gs3_images out;
 };
 
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
         if (tid < m) {
             const uint32_t id = safe_id(a.list[b + tid], a.n);
             uint32_t mk;
-            s_rec[tid] = stage_splat(id, a.rec0, a.rec1, nullptr, tile_x0, tile_y0, a.cutoff, a.alpha_min, &mk);
+            s_rec[tid] = stage_splat(id, a.rec0, a.rec1, a.rec2, nullptr, tile_x0, tile_y0, &mk);
             s_mask[tid] = mk;
             s_c0[tid] = a.col0[id];
             s_c1[tid] = a.col1[id];
@@ -127,14 +128,13 @@ hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, c
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);
+    a.rec2 = at<float4>(ws, L.rec2);
     a.col0 = at<float4>(ws, L.col0);
     a.col1 = at<float4>(ws, L.col1);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
-    a.cutoff = k.cutoff;
-    a.alpha_min = k.alpha_min;
     a.alpha_max = k.alpha_max;
     a.t_min = k.t_min;
     a.out = out;

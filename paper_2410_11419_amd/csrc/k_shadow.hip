@@ -20,8 +20,9 @@
 //    kShadowEps; a wave whose 64 pixels are all there stops, and so does the
 //    workgroup. In an opaque scene this leaves only the splats near the
 //    lit surface to evaluate.
-// Both kernels test pixels with the same float32 arithmetic (stage_coeffs,
-// rel_centre, quad_q), so num and den see exactly the same hits.
+// Both kernels test pixels with the same per-splat float32 threshold (the
+// view's rec2, written by the projection) and the same float32 arithmetic
+// (rel_centre, quad_q), so num and den see exactly the same hits.
 #include "splat_common.h"
 
 namespace gs3 {
@@ -40,11 +41,12 @@ struct ShadowArgs {
     const uint32_t* list;
     const float4* rec0;
     const float4* rec1;
+    const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
     const int4* ext;
     uint32_t n;
     int width, height, tiles_x;
-    float cutoff, alpha_min, alpha_max, bias;
+    float alpha_max, bias;
     float* num;
     float* den;
 };
@@ -121,8 +123,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
         if (lane < m) {
             uint32_t mk;
             const uint32_t id = safe_id(a.list[b + lane], a.n);
-            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.depth, tile_x0, tile_y0, a.cutoff, a.alpha_min,
-                                           &mk);
+            const Staged rec = stage_splat(id, a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
             s_rec[base + lane] = rec;
             s_id[base + lane] = id;
             qm = (mk & qbit) != 0u && quad_reach(rec, qd);
@@ -171,8 +172,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             const float thr_d = uniform_f(s_rec[base + j].g1.w) - a.bias;
             while (trail < lo_pos) {
                 uint32_t mk;
-                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
-                                              tile_y0, a.cutoff, a.alpha_min, &mk);
+                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
                 if (!(uniform_f(tk.g1.w) < thr_d)) break;
                 if (uniform_u(mk) & qbit) occlude(tk);
                 ++trail;
@@ -187,8 +187,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             // entries before the ring precede every remaining lead's L
             while (trail < lo_pos) {
                 uint32_t mk;
-                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.depth, tile_x0,
-                                              tile_y0, a.cutoff, a.alpha_min, &mk);
+                const Staged tk = stage_splat(safe_id(a.list[trail], a.n), a.rec0, a.rec1, a.rec2, a.depth, tile_x0, tile_y0, &mk);
                 if (uniform_u(mk) & qbit) occlude(tk);
                 ++trail;
             }
@@ -255,33 +254,34 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     // the next Gaussian's extent and records are loaded while the current
     // one is evaluated
     int4 nx_ex = make_int4(0, 0, 0, 0);
-    float4 nx_r0 = make_float4(0.f, 0.f, 0.f, 0.f), nx_r1 = nx_r0;
+    float4 nx_r0 = make_float4(0.f, 0.f, 0.f, 0.f), nx_r1 = nx_r0, nx_r2 = nx_r0;
     if (g < n) {
         nx_ex = a.ext[g];
         nx_r0 = a.rec0[g];
         nx_r1 = a.rec1[g];
+        nx_r2 = a.rec2[g];
     }
     for (; g < n; g += stride) {
         const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(nx_ex.x), __builtin_amdgcn_readfirstlane(nx_ex.y),
                                   __builtin_amdgcn_readfirstlane(nx_ex.z), __builtin_amdgcn_readfirstlane(nx_ex.w));
         const float4 r0 = uf4(nx_r0);
         const float4 r1 = uf4(nx_r1);
+        const float4 r2 = uf4(nx_r2);
         if (g + stride < n) {
             nx_ex = a.ext[g + stride];
             nx_r0 = a.rec0[g + stride];
             nx_r1 = a.rec1[g + stride];
+            nx_r2 = a.rec2[g + stride];
         }
         float acc = 0.f;
         int x0, x1, y0, y1;
         if (tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
-            float A, B, C, thr;
-            const float p = stage_coeffs(r1, a.cutoff, a.alpha_min, &A, &B, &C, &thr);
-            float hx = 3.0e38f, hy = 3.0e38f;
+            float A, B, C;
+            scaled_conic(r1, &A, &B, &C);
+            const float thr = r2.x, hx = r2.y, hy = r2.z, p = r2.w;
             bool banded = false;
             if (!isinf(p)) {
                 const float det = r1.x * r1.z - r1.y * r1.y;
-                hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
-                hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
                 // large elongated splats (16 tiles or more, bounding box
                 // over 2.5x the ellipse): narrow the tile columns per tile
                 // row to the ellipse's own x-extent there
@@ -341,14 +341,13 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
     a.list = at<uint32_t>(ws, L.pv_a);
     a.rec0 = at<float4>(ws, L.rec0);
     a.rec1 = at<float4>(ws, L.rec1);
+    a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
     a.ext = at<int4>(ws, L.ext);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
-    a.cutoff = k.cutoff;
-    a.alpha_min = k.alpha_min;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.num = num_den;

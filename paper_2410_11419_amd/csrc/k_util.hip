@@ -82,8 +82,8 @@ namespace gs3 {
 // below t_min) and only the hits that are blended are counted.
 __global__ __launch_bounds__(256) void k_count_hits(const int2* __restrict__ ranges, const uint32_t* __restrict__ list,
                                                      const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                                                     uint32_t n, int width, int height, int tiles_x, float cutoff,
-                                                     float alpha_min, float alpha_max, float t_min, int stop_early,
+                                                     const float4* __restrict__ rec2, uint32_t n, int width,
+                                                     int height, int tiles_x, float alpha_max, float t_min, int stop_early,
                                                      unsigned long long* __restrict__ out) {
     const int tile = blockIdx.x;
     const int2 rg = ranges[tile];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_count_hits(const int2* __restrict__ ran
     bool done = !inside;
     for (int i = rg.x; i < rg.y; ++i) {
         uint32_t mk;
-        const Staged s = stage_splat(safe_id(list[i], n), rec0, rec1, nullptr, tile_x0, tile_y0, cutoff, alpha_min, &mk);
+        const Staged s = stage_splat(safe_id(list[i], n), rec0, rec1, rec2, nullptr, tile_x0, tile_y0, &mk);
         const float q = splat_q(s, pxc, pyc);
         if (!done && q >= s.g1.y) {
             if (stop_early) {
@@ -122,8 +122,9 @@ hipError_t launch_count_hits(const gs3_consts& k, const Layout& L, const void* w
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 2, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_count_hits, dim3((unsigned)L.n_tiles), dim3(256), 0, st, at<int2>(ws, L.ranges),
-                       at<uint32_t>(ws, L.pv_a), at<float4>(ws, L.rec0), at<float4>(ws, L.rec1), (uint32_t)L.n,
-                       L.width, L.height, L.tiles_x, k.cutoff, k.alpha_min, k.alpha_max, k.t_min, stop_early, out);
+                       at<uint32_t>(ws, L.pv_a), at<float4>(ws, L.rec0), at<float4>(ws, L.rec1),
+                       at<float4>(ws, L.rec2), (uint32_t)L.n, L.width, L.height, L.tiles_x, k.alpha_max, k.t_min,
+                       stop_early, out);
     return hipGetLastError();
 }
 

@@ -54,6 +54,31 @@ __device__ inline float stage_coeffs(const float4 r1, float cutoff, float alpha_
     return p;
 }
 
+// Per-splat constants of the hit test from record r1 = {conic a, b, c,
+// opacity}, computed once per view by the projection and stored as rec2:
+// {thr, hx, hy, p} with thr and p as stage_coeffs gives them, and hx, hy the
+// half-widths sqrt(2 p Sigma'_xx), sqrt(2 p Sigma'_yy) of the hit ellipse's
+// bounding box (Sigma' = conic^-1), padded so that the box is conservative
+// with respect to the per-pixel float32 test (3e38 when p is infinite).
+__device__ inline float4 splat_bounds(const float4 r1, float cutoff, float alpha_min) {
+    float A, B, C, thr;
+    const float p = stage_coeffs(r1, cutoff, alpha_min, &A, &B, &C, &thr);
+    float hx = 3.0e38f, hy = 3.0e38f;
+    if (p > 0.f && !isinf(p)) {
+        const float det = r1.x * r1.z - r1.y * r1.y;
+        hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
+        hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+    }
+    return make_float4(thr, hx, hy, p);
+}
+
+// The conic scaled by -log2(e)/2 (see Staged), from record r1.
+__device__ inline void scaled_conic(const float4 r1, float* A, float* B, float* C) {
+    *A = -0.5f * kLog2e * r1.x;
+    *B = -kLog2e * r1.y;
+    *C = -0.5f * kLog2e * r1.z;
+}
+
 // q = power * log2(e) for offset (dx, dy) from the splat centre; written with
 // explicit fmaf so that every kernel rounds it the same way.
 __device__ inline float quad_q(float dx, float dy, float A, float B, float C) {
@@ -67,29 +92,27 @@ __device__ inline float rel_centre(float hi, float lo, float origin) { return (h
 // hit ellipse's bounding box reaches wave w's 8x8 quadrant (quadrant w
 // covers tile pixels x in [8 (w & 1), +8), y in [8 (w >> 1), +8)).
 __device__ inline Staged stage_splat(uint32_t id, const float4* __restrict__ rec0,
-                                     const float4* __restrict__ rec1, const float* __restrict__ depth,
-                                     float tile_x0, float tile_y0, float cutoff, float alpha_min,
+                                     const float4* __restrict__ rec1, const float4* __restrict__ rec2,
+                                     const float* __restrict__ depth, float tile_x0, float tile_y0,
                                      uint32_t* mask) {
     const float4 r0 = rec0[id];
     const float4 r1 = rec1[id];
+    const float4 r2 = rec2[id];
     Staged s;
     const float u = rel_centre(r0.x, r0.z, tile_x0);
     const float v = rel_centre(r0.y, r0.w, tile_y0);
-    float A, B, C, thr;
-    const float p = stage_coeffs(r1, cutoff, alpha_min, &A, &B, &C, &thr);
+    float A, B, C;
+    scaled_conic(r1, &A, &B, &C);
+    const float p = r2.w;
     s.g0 = make_float4(u, v, A, B);
-    s.g1 = make_float4(C, thr, r1.w, depth ? depth[id] : 0.f);
-    // bounding box of the ellipse power >= -p: half-widths sqrt(2 p Sigma'_xx),
-    // sqrt(2 p Sigma'_yy) with Sigma' = conic^-1; padded so the cull is
-    // conservative with respect to the per-pixel float32 test.
+    s.g1 = make_float4(C, r2.x, r1.w, depth ? depth[id] : 0.f);
+    // the hit ellipse's bounding box (rec2) against each quadrant
     uint32_t m = 0u;
     if (p > 0.f) {
         if (isinf(p)) {
             m = 0xFu;
         } else {
-            const float det = r1.x * r1.z - r1.y * r1.y;
-            const float hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
-            const float hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+            const float hx = r2.y, hy = r2.z;
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 const float qx = 8.f * (w & 1), qy = 8.f * (w >> 1);
@@ -173,11 +196,11 @@ __device__ inline bool band_x_range(const RowExtent& e, float dy0, float dy1, fl
 
 // Row-group mask of a staged splat: bit r set when the hit ellipse's
 // bounding box (padded like stage_splat's) reaches tile rows 4r .. 4r+3.
-__device__ inline uint32_t rowgroup_mask(const float4 r1, float v, float p) {
+__device__ inline uint32_t rowgroup_mask(const float4 r2, float v) {
+    const float p = r2.w;
     if (!(p > 0.f)) return 0u;
     if (isinf(p)) return 0xFu;
-    const float det = r1.x * r1.z - r1.y * r1.y;
-    const float hy = sqrtf(fmaxf(2.f * p * r1.x / det, 0.f)) * 1.01f + 0.01f;
+    const float hy = r2.z;
     uint32_t m = 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -191,21 +214,21 @@ __device__ inline uint32_t rowgroup_mask(const float4 r1, float v, float p) {
 // and its row-group mask (bit r: the splat can hit tile rows 4r..4r+3; 0 if
 // its bounding box misses the tile's columns).
 __device__ inline Staged stage_rows(uint32_t id, const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                                    const float* __restrict__ depth, float tile_x0, float tile_y0, float cutoff,
-                                    float alpha_min, uint32_t* mask) {
+                                    const float4* __restrict__ rec2, const float* __restrict__ depth, float tile_x0,
+                                    float tile_y0, uint32_t* mask) {
     const float4 r0 = rec0[id];
     const float4 r1 = rec1[id];
+    const float4 r2 = rec2[id];
     Staged s;
     const float u = rel_centre(r0.x, r0.z, tile_x0);
     const float v = rel_centre(r0.y, r0.w, tile_y0);
-    float A, B, C, thr;
-    const float p = stage_coeffs(r1, cutoff, alpha_min, &A, &B, &C, &thr);
+    float A, B, C;
+    scaled_conic(r1, &A, &B, &C);
     s.g0 = make_float4(u, v, A, B);
-    s.g1 = make_float4(C, thr, r1.w, depth ? depth[id] : 0.f);
-    uint32_t m = rowgroup_mask(r1, v, p);
-    if (m && !isinf(p)) {
-        const float det = r1.x * r1.z - r1.y * r1.y;
-        const float hx = sqrtf(fmaxf(2.f * p * r1.z / det, 0.f)) * 1.01f + 0.01f;
+    s.g1 = make_float4(C, r2.x, r1.w, depth ? depth[id] : 0.f);
+    uint32_t m = rowgroup_mask(r2, v);
+    if (m && !isinf(r2.w)) {
+        const float hx = r2.y;
         if (u + hx < 0.5f || u - hx > 15.5f) m = 0u;
     }
     *mask = m;

@@ -493,11 +493,16 @@ class Renderer:
         numerator's tail occupies few CUs, which the other two fill. Results
         are the same as with ``overlap=False`` (one stream, in order).
         ``events`` (optional) gets "num0"/"num1" recorded around the shadow
-        numerator on the caller's stream."""
+        numerator on the caller's stream, and "den0"/"den1" (when present)
+        around the denominator on the stream it runs on."""
         main = torch.cuda.current_stream()
         if not overlap or check:
             lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
+            if events is not None and "den0" in events:
+                events["den0"].record(main)
             gs3_shadow_den(self.consts, lvb, self.num_den)
+            if events is not None and "den1" in events:
+                events["den1"].record(main)
             if events is not None:
                 events["num0"].record(main)
             gs3_shadow_num(self.consts, lvb, self.num_den)
@@ -519,7 +524,11 @@ class Renderer:
             lvb = self._preprocess("light", light, GS3_DEPTH_DIST, False)
             s_den.wait_stream(main)
             with torch.cuda.stream(s_den):
+                if events is not None and "den0" in events:
+                    events["den0"].record(s_den)
                 gs3_shadow_den(self.consts, lvb, self.num_den)
+                if events is not None and "den1" in events:
+                    events["den1"].record(s_den)
             if events is not None:
                 events["num0"].record(main)
             gs3_shadow_num(self.consts, lvb, self.num_den)
