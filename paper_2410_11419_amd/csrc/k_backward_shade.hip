@@ -351,52 +351,76 @@ struct WgArgs {
     float* partial;                  // [chunks][total]
 };
 
+// One workgroup per (chunk of Gaussians, layer): C[O x J] = D[O x chunk] .
+// H[J x chunk]^T on mfma_f32_16x16x4f32, the Gaussians being the
+// contraction. The chunk goes through LDS 32 Gaussians at a time (zero
+// padded to 64 x 64); wave w owns output rows 16w .. 16w + 15 and all four
+// 16-column blocks. A-operand lane l: D[16w + l % 16][4s + l / 16]; B-operand
+// lane l: H[16c + l % 16][4s + l / 16]; the result lane l holds rows
+// 16w + 4 (l / 16) + i, column 16c + l % 16. Bias sums come from the same D
+// tile.
 __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
-    __shared__ float sD[64][33];
-    __shared__ float sH[64][33];
+    constexpr int KB = 32;
+    __shared__ float sD[64][KB + 1];
+    __shared__ float sH[64][KB + 1];
     const WgProblem P = a.p[blockIdx.y];
     const int n = a.n;
     const int k0 = blockIdx.x * kWgChunk, k1 = min(n, k0 + kWgChunk);
     const float* D = a.rows + (size_t)P.dz_row * n;
     const float* H = a.rows + (size_t)P.in_row * n;
-    const int t = threadIdx.x;
-    const int o0 = 4 * (t >> 4), j0 = 4 * (t & 15);
-    float acc[4][4] = {{0.f}};
-    float bacc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int kb = k0; kb < k1; kb += 32) {
-        for (int idx = t; idx < 64 * 32; idx += 256) {
-            const int r = idx >> 5, c = idx & 31, gg = kb + c;
-            sD[r][c] = (r < P.O && gg < k1) ? D[(size_t)r * n + gg] : 0.f;
-            sH[r][c] = (r < P.J && gg < k1) ? H[(size_t)r * n + gg] : 0.f;
+    const int t = threadIdx.x, lane = __lane_id();
+    const int w = t >> 6, r16 = lane & 15, kq = lane >> 4;
+    floatx4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    // the next tile's loads are in flight while the current one is multiplied
+    constexpr int kPer = 64 * KB / 256;
+    float pd[kPer], ph[kPer];
+    auto fetch = [&](int kb) {
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const int idx = t + 256 * m, r = idx / KB, gg = kb + idx % KB;
+            pd[m] = (r < P.O && gg < k1) ? D[(size_t)r * n + gg] : 0.f;
+            ph[m] = (r < P.J && gg < k1) ? H[(size_t)r * n + gg] : 0.f;
+        }
+    };
+    if (k0 < k1) fetch(k0);
+    for (int kb = k0; kb < k1; kb += KB) {
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const int idx = t + 256 * m;
+            sD[idx / KB][idx % KB] = pd[m];
+            sH[idx / KB][idx % KB] = ph[m];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 32; ++kk) {
-            float av[4], bv[4];
+        if (kb + KB < k1) fetch(kb + KB);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                av[r] = sD[o0 + r][kk];
-                bv[r] = sH[j0 + r][kk];
-            }
+        for (int s4 = 0; s4 < KB / 4; ++s4) {
+            const float av = sD[16 * w + r16][4 * s4 + kq];
+            bacc += av;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                bacc[r] += av[r];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(av[r], bv[c], acc[r][c]);
+            for (int c = 0; c < 4; ++c) {
+                const float bv = sH[16 * c + r16][4 * s4 + kq];
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[c], 0, 0, 0);
             }
         }
         __syncthreads();
     }
+    // bias: lanes r16, r16 + 16, r16 + 32, r16 + 48 hold row 16w + r16
+    bacc += __shfl_xor(bacc, 16, 64);
+    bacc += __shfl_xor(bacc, 32, 64);
     float* part = a.partial + (size_t)blockIdx.x * a.total + P.off;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int o = o0 + r;
-        if (o >= P.O) continue;
+    for (int c = 0; c < 4; ++c) {
+        const int j = 16 * c + r16;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (j0 + c < P.J) part[o * P.J + j0 + c] = acc[r][c];
-        if (j0 == 0) part[P.O * P.J + o] = bacc[r];
+        for (int i = 0; i < 4; ++i) {
+            const int o = 16 * w + 4 * kq + i;
+            if (o < P.O && j < P.J) part[o * P.J + j] = acc[c][i];
+        }
     }
+    if (kq == 0 && 16 * w + r16 < P.O) part[P.O * P.J + 16 * w + r16] = bacc;
 }
 
 __global__ __launch_bounds__(256) void k_wgrad_reduce(WgArgs a, int chunks) {
