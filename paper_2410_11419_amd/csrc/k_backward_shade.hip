@@ -71,7 +71,7 @@ __device__ inline void store_rows(float* rows, int row0, int q, int g, int n, co
         for (int i = 0; i < 4; ++i) p[(size_t)(16 * m + i) * n] = v[m][i];
 }
 
-__global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
+__global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
     __shared__ float sm[kShadeBwdSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
@@ -187,6 +187,16 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
             };
             mlp_hidden_all<kPhiK1>(sm, kPhiS, lane, xin, h);
             const float tp = mlp_out(sm, kPhiS, lane, h[2], 0);
+            // the layer inputs go to the scratch now; the adjoint needs only
+            // the ReLU patterns of h (fewer live registers)
+            if (valid) {
+                float* R = a.rows;
+                for (int k = q; k < kPhiIn; k += 4) R[(size_t)(kPhiRows.x + k) * n + g] = xin(k);
+                store_rows(R, kPhiRows.h1, q, g, n, h[0]);
+                store_rows(R, kPhiRows.h2, q, g, n, h[1]);
+                store_rows(R, kPhiRows.h3, q, g, n, h[2]);
+            }
+            const uint32_t hmask[3] = {relu_mask(h[0]), relu_mask(h[1]), relu_mask(h[2])};
             const float d4 = dtp * tp * (1.f - tp);
             floatx4 dh3[4];
 #pragma unroll
@@ -198,20 +208,13 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
                 if (!valid) return;
                 store_rows(a.rows, l == 0 ? kPhiRows.dz1 : (l == 1 ? kPhiRows.dz2 : kPhiRows.dz3), q, g, n, dz);
             };
-            mlp_backward(sm, kPhiT, lane, h, dh3, store_dz, dx);
+            mlp_backward_masked(sm, kPhiT, lane, hmask, dh3, store_dz, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 phi_dx0[i] = dx[0][i];
                 phi_dx1[i] = dx[1][i];
             }
-            if (valid) {
-                float* R = a.rows;
-                for (int k = q; k < kPhiIn; k += 4) R[(size_t)(kPhiRows.x + k) * n + g] = xin(k);
-                store_rows(R, kPhiRows.h1, q, g, n, h[0]);
-                store_rows(R, kPhiRows.h2, q, g, n, h[1]);
-                store_rows(R, kPhiRows.h3, q, g, n, h[2]);
-                if (q == 0) R[(size_t)kPhiRows.dz4 * n + g] = d4;
-            }
+            if (valid && q == 0) a.rows[(size_t)kPhiRows.dz4 * n + g] = d4;
             // dL/dT = dx row 0 (tile 0, quarter 0, i = 0)
             dTg = __shfl(phi_dx0[0], l16, 64);
         }
@@ -236,6 +239,14 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
             const float r0 = mlp_out(sm, kPsiS, lane, h[2], 0);
             const float r1 = mlp_out(sm, kPsiS, lane, h[2], 1);
             const float r2 = mlp_out(sm, kPsiS, lane, h[2], 2);
+            if (valid) {
+                float* R = a.rows;
+                for (int k = q; k < kPsiIn; k += 4) R[(size_t)(kPsiRows.x + k) * n + g] = xin(k);
+                store_rows(R, kPsiRows.h1, q, g, n, h[0]);
+                store_rows(R, kPsiRows.h2, q, g, n, h[1]);
+                store_rows(R, kPsiRows.h3, q, g, n, h[2]);
+            }
+            const uint32_t hmask[3] = {relu_mask(h[0]), relu_mask(h[1]), relu_mask(h[2])};
             const float d40 = dr0 * r0 * (1.f - r0), d41 = dr1 * r1 * (1.f - r1), d42 = dr2 * r2 * (1.f - r2);
             floatx4 dh3[4];
 #pragma unroll
@@ -251,7 +262,7 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
                 if (!valid) return;
                 store_rows(a.rows, l == 0 ? kPsiRows.dz1 : (l == 1 ? kPsiRows.dz2 : kPsiRows.dz3), q, g, n, dz);
             };
-            mlp_backward(sm, kPsiT, lane, h, dh3, store_dz, dx);
+            mlp_backward_masked(sm, kPsiT, lane, hmask, dh3, store_dz, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) psi_dx0[i] = dx[0][i];
             // rows 16..21 = w_i, w_o live in tile 1, quarters 0 and 1
@@ -261,10 +272,6 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs a) {
             pdwx = t10; pdwy = t11; pdwz = t12; pdox = t13; pdoy = t20; pdoz = t21;
             if (valid) {
                 float* R = a.rows;
-                for (int k = q; k < kPsiIn; k += 4) R[(size_t)(kPsiRows.x + k) * n + g] = xin(k);
-                store_rows(R, kPsiRows.h1, q, g, n, h[0]);
-                store_rows(R, kPsiRows.h2, q, g, n, h[1]);
-                store_rows(R, kPsiRows.h3, q, g, n, h[2]);
                 if (q == 0) {
                     R[(size_t)kPsiRows.dz4 * n + g] = d40;
                     R[(size_t)(kPsiRows.dz4 + 1) * n + g] = d41;
@@ -608,11 +615,12 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     a.dT = dT;
     a.g = g;
     a.rows = rows;
-    // 161 KB of LDS: one workgroup per CU, so 4 waves with the full register file
-    const int per_block = 4 * 16;
+    // 161 KB of LDS: one workgroup per CU; 512 threads (two waves per SIMD,
+    // 256 registers each) share the weights
+    const int per_block = 8 * 16;
     int grid = (int)((sc.n + per_block - 1) / per_block);
     if (grid > 512) grid = 512;
-    hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(512), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!phi && !psi)) return e;
     // weight gradients

@@ -251,4 +251,38 @@ __device__ inline void mlp_backward(const float* sm, const MlpTSmem& T, int lane
     mlp_back_layer<2>(sm, T.t1, lane, dz, dx);
 }
 
+// ReLU pattern of a 64-wide activation in D layout: bit 4 m + i set when
+// h[m][i] > 0 (the lane's 16 values).
+__device__ inline uint32_t relu_mask(const floatx4 h[4]) {
+    uint32_t b = 0u;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b |= (h[m][i] > 0.f ? 1u : 0u) << (4 * m + i);
+    return b;
+}
+
+// mlp_backward with the forward's activations given only by their ReLU
+// patterns (relu_mask of h1, h2, h3), which is all the adjoint reads of them.
+template <typename StoreFn>
+__device__ inline void mlp_backward_masked(const float* sm, const MlpTSmem& T, int lane, const uint32_t mask[3],
+                                           const floatx4 dh3[4], StoreFn store, floatx4 dx[2]) {
+    floatx4 dz[4], d[4];
+    auto gate = [&](uint32_t mk, const floatx4 in[4]) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dz[m][i] = ((mk >> (4 * m + i)) & 1u) ? in[m][i] : 0.f;
+    };
+    gate(mask[2], dh3);
+    store(2, dz);
+    mlp_back_layer<4>(sm, T.t3, lane, dz, d);
+    gate(mask[1], d);
+    store(1, dz);
+    mlp_back_layer<4>(sm, T.t2, lane, dz, d);
+    gate(mask[0], d);
+    store(0, dz);
+    mlp_back_layer<2>(sm, T.t1, lane, dz, dx);
+}
+
 }  // namespace gs3
