@@ -27,7 +27,7 @@ struct ShadeArgs {
     float* colour;   // [8][n]
 };
 
-__global__ __launch_bounds__(512) void k_shade_mlp(ShadeArgs a) {
+__global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
     __shared__ float sm[kShadeSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
