@@ -225,7 +225,7 @@ struct ShadowBwdArgs {
     const float* depth;
     const int4* ext;
     uint32_t n;
-    int width, height, tiles_x;
+    int width, height, tiles_x, n_tiles;
     float alpha_max, bias;
     const float* T;        // [n] forward shadow values
     const float* num_den;  // [2][n]
@@ -337,8 +337,9 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     // bursts of atomics (a global atomic still counts as an outstanding
     // memory operation that the next load would wait for)
     __shared__ float s_acc[PASS == 1 ? 6 : 1][2 * kBwdBatch];
-    const int tile = (int)a.order[blockIdx.x >> 2];
-    const int qd = blockIdx.x & 3;
+    int slot, qd;
+    if (!xcd_tile_quadrant(a.n_tiles, &slot, &qd)) return;
+    const int tile = (int)a.order[slot];
     const int2 rg = a.ranges[tile];
     const int s = rg.x, e = rg.y;
     const int lane = __lane_id();
@@ -605,6 +606,7 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
+    a.n_tiles = (int)L.n_tiles;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.T = T;
@@ -619,8 +621,8 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(gray), 0u, (int64_t)L.width * L.height, st);
     if (e != hipSuccess) return e;
     if (L.n_tiles == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_shadow_bwd<0>, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(k_shadow_bwd<1>, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_bwd<0>, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_bwd<1>, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ struct ShadowArgs {
     const float* depth;
     const int4* ext;
     uint32_t n;
-    int width, height, tiles_x;
+    int width, height, tiles_x, n_tiles;
     float alpha_max, bias;
     float* num;
     float* den;
@@ -78,8 +78,9 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
     __shared__ Staged s_rec[2 * kShadowBatch];
     __shared__ uint32_t s_id[2 * kShadowBatch];
     __shared__ float s_sum[4][kShadowBatch];     // lead sums of the current batch, per 16-lane row
-    const int tile = (int)a.order[blockIdx.x >> 2];
-    const int qd = blockIdx.x & 3;
+    int slot, qd;
+    if (!xcd_tile_quadrant(a.n_tiles, &slot, &qd)) return;
+    const int tile = (int)a.order[slot];
     const int2 rg = a.ranges[tile];
     const int s = rg.x, e = rg.y;
     if (e <= s) return;
@@ -348,6 +349,7 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
+    a.n_tiles = (int)L.n_tiles;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.num = num_den;
@@ -368,7 +370,7 @@ hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* w
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(num_den), 0u, L.n, st);
     if (e != hipSuccess) return e;
     if (L.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shadow, dim3((unsigned)(4 * L.n_tiles)), dim3(64), 0, st, shadow_args(k, L, ws, num_den));
+    hipLaunchKernelGGL(k_shadow, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, shadow_args(k, L, ws, num_den));
     return hipGetLastError();
 }
 

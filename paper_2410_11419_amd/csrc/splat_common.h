@@ -304,6 +304,19 @@ __device__ inline void row_sums16(float (&x)[N]) {
     for (int c = 0; c < N; ++c) x[c] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x[c]), 0x140, 0xF, 0xF, true));
 }
 
+// Launch slot of the per-(tile, quadrant) waves. Consecutive workgroups go
+// to the 8 XCDs in turn, each with its own L2, so workgroup 32k + 8q + x
+// takes quadrant q of tile slot 8k + x: the four waves that stage the same
+// tile list run on one XCD and share its L2. The grid is 32 ceil(tiles / 8);
+// false for the slots past the last tile.
+__device__ inline bool xcd_tile_quadrant(int n_tiles, int* slot, int* qd) {
+    const int b = (int)blockIdx.x;
+    *slot = 8 * (b >> 5) + (b & 7);
+    *qd = (b >> 3) & 3;
+    return *slot < n_tiles;
+}
+inline unsigned quadrant_grid(int64_t n_tiles) { return (unsigned)(32 * ((n_tiles + 7) / 8)); }
+
 __device__ inline float wave_sum(float x) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(x)), 63));
 }
