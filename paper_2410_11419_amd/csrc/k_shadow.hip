@@ -305,20 +305,32 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                         lo = fmaxf(lo, bl);
                         hi = fminf(hi, bh);
                     }
-                    for (int tx = x0; tx <= x1; ++tx) {
+                    // the tile columns and 4-row groups the box reaches in
+                    // this tile row, as integer ranges (scalar compares in the
+                    // loops); 0.05 px of slack on top of the box's padding
+                    const float U = r0.x + r0.z;
+                    auto clampi = [](float x) { return (int)fminf(fmaxf(x, -1.0e6f), 1.0e6f); };
+                    const int t_lo = max(x0, __builtin_amdgcn_readfirstlane(
+                                                 clampi(ceilf((U + lo - 15.55f) * (1.f / kTile)))));
+                    const int t_hi = min(x1, __builtin_amdgcn_readfirstlane(
+                                                 clampi(floorf((U + hi - 0.45f) * (1.f / kTile)))));
+                    const int r_lo = max(0, __builtin_amdgcn_readfirstlane(clampi(ceilf((v - hy - 3.55f) * 0.25f))));
+                    const int r_hi = min(3, __builtin_amdgcn_readfirstlane(clampi(floorf((v + hy - 0.45f) * 0.25f))));
+                    for (int tx = t_lo; tx <= t_hi; ++tx) {
                         const float ox = (float)(tx * kTile);
                         const float u = rel_centre(r0.x, r0.z, ox);
-                        if (u + hi < 0.5f || u + lo > 15.5f) continue;
                         const float dx = (float)lx + 0.5f - u;
                         const bool in_x = tx * kTile + lx < a.width;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const float yb = (float)(4 * r);
-                            if (v + hy < yb + 0.5f || v - hy > yb + 3.5f) continue;
+                            if (r < r_lo || r > r_hi) continue;
                             const float dy = (float)(4 * r + ly) + 0.5f - v;
                             const float q = quad_q(dx, dy, A, B, C);
-                            const bool hit = in_x && (ty * kTile + 4 * r + ly < a.height) && q >= thr;
-                            acc += hit ? fast_exp2(q) : 0.f;
+                            // evaluated in every lane (no branch around it)
+                            float e = fast_exp2(q);
+                            asm volatile("" : "+v"(e));
+                            const bool hit = (q >= thr) & in_x & (ty * kTile + 4 * r + ly < a.height);
+                            acc += hit ? e : 0.f;
                         }
                     }
                 }
