@@ -419,6 +419,23 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         }
         if (hit) tt *= 1.f - al;
     };
+    // the occluders of one set of ring entries in order, each record read
+    // from LDS while the previous one is being applied
+    auto occlude_set = [&](unsigned long long m, int slot0) {
+        if (!m) return;
+        int k = slot0 + __builtin_ctzll(m);
+        Staged cur_rec = s_rec[k];
+        m &= m - 1ull;
+        while (m) {
+            const int k2 = slot0 + __builtin_ctzll(m);
+            const Staged nxt = s_rec[k2];
+            m &= m - 1ull;
+            occlude(cur_rec, 0u, k);
+            cur_rec = nxt;
+            k = k2;
+        }
+        occlude(cur_rec, 0u, k);
+    };
     int last_base = 0, last_m = 0;
     for (int b = s; b < e && !finished; b += kBwdBatch) {
         const int m = min(kBwdBatch, e - b);
@@ -531,18 +548,8 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1ull;
-                unsigned long long op = readlane64(mp, j);
-                while (op) {
-                    const int k = __builtin_ctzll(op);
-                    op &= op - 1ull;
-                    occlude(s_rec[pbase + k], 0u, pbase + k);
-                }
-                unsigned long long oc = readlane64(mc, j);
-                while (oc) {
-                    const int k = __builtin_ctzll(oc);
-                    oc &= oc - 1ull;
-                    occlude(s_rec[base + k], 0u, base + k);
-                }
+                occlude_set(readlane64(mp, j), pbase);
+                occlude_set(readlane64(mc, j), base);
                 if (!lead_eval(j)) {
                     finished = true;
                     break;

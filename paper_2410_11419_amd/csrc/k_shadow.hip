@@ -106,6 +106,20 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             tt = hit ? tt * f : tt;
         }
     };
+    // the occluders of one set in order, each record read from LDS while
+    // the previous one is being applied
+    auto occlude_set = [&](unsigned long long m, int slot0) {
+        if (!m) return;
+        Staged cur_rec = s_rec[slot0 + __builtin_ctzll(m)];
+        m &= m - 1ull;
+        while (m) {
+            const Staged nxt = s_rec[slot0 + __builtin_ctzll(m)];
+            m &= m - 1ull;
+            occlude(cur_rec);
+            cur_rec = nxt;
+        }
+        occlude(cur_rec);
+    };
     // A global atomic without a returned value still counts as an
     // outstanding vector memory operation, so the next wait for a load would
     // wait for it too: the lead sums of a batch collect in LDS and go out
@@ -209,18 +223,8 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1ull;
-                unsigned long long op = readlane64(mp, j);
-                while (op) {
-                    const int k = __builtin_ctzll(op);
-                    op &= op - 1ull;
-                    occlude(s_rec[pbase + k]);
-                }
-                unsigned long long oc = readlane64(mc, j);
-                while (oc) {
-                    const int k = __builtin_ctzll(oc);
-                    oc &= oc - 1ull;
-                    occlude(s_rec[base + k]);
-                }
+                occlude_set(readlane64(mp, j), pbase);
+                occlude_set(readlane64(mc, j), base);
                 if (!lead_eval(j)) {
                     flush(base, m);
                     return;
