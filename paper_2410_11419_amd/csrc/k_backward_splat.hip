@@ -472,10 +472,9 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         }
         const unsigned long long before = __builtin_amdgcn_ballot_w64(L < 0);
         // lead j: false when every pixel of the quadrant is dark
-        auto lead_eval = [&](int j) {
+        auto lead_eval = [&](int j, const Staged& sj) {
             alive = alive && tt >= kBwdEps;
             if (!__builtin_amdgcn_ballot_w64(alive)) return false;
-            const Staged sj = s_rec[base + j];
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
             const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
             const bool hit = alive && q >= sj.g1.y;
@@ -518,7 +517,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
                 if (uniform_u(mk) & qbit) occlude(tk, uniform_u(kid), -1);
                 ++trail;
             }
-            if (!lead_eval(j)) {
+            if (!lead_eval(j, s_rec[base + j])) {
                 finished = true;
                 break;
             }
@@ -548,9 +547,11 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1ull;
+                // the lead's record is read while its occluders are applied
+                const Staged sj = s_rec[base + j];
                 occlude_set(readlane64(mp, j), pbase);
                 occlude_set(readlane64(mc, j), base);
-                if (!lead_eval(j)) {
+                if (!lead_eval(j, sj)) {
                     finished = true;
                     break;
                 }

@@ -166,10 +166,9 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             }
         }
         const unsigned long long before = __builtin_amdgcn_ballot_w64(L < 0);
-        auto lead_eval = [&](int j) {
+        auto lead_eval = [&](int j, const Staged& sj) {
             alive = alive && tt >= kShadowEps;
             if (!__builtin_amdgcn_ballot_w64(alive)) return false;
-            const Staged sj = s_rec[base + j];
             const float q = splat_q(sj, pxc, pyc);
             const bool hit = alive && q >= sj.g1.y;
             if (__builtin_amdgcn_ballot_w64(hit)) {
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
                 if (uniform_u(mk) & qbit) occlude(tk);
                 ++trail;
             }
-            if (!lead_eval(j)) {
+            if (!lead_eval(j, s_rec[base + j])) {
                 flush(base, m);
                 return;
             }
@@ -223,9 +222,11 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1ull;
+                // the lead's record is read while its occluders are applied
+                const Staged sj = s_rec[base + j];
                 occlude_set(readlane64(mp, j), pbase);
                 occlude_set(readlane64(mc, j), base);
-                if (!lead_eval(j)) {
+                if (!lead_eval(j, sj)) {
                     flush(base, m);
                     return;
                 }
