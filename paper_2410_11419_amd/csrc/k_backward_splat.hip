@@ -624,7 +624,7 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.gray = gray;
     a.gsplat = gsplat;
     int grid = (int)((L.n + 3) / 4);
-    if (grid > 8192) grid = 8192;
+    if (grid > 32768) grid = 32768;
     hipLaunchKernelGGL(k_shadow_den_bwd, dim3(grid), dim3(256), 0, st, a);
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(gray), 0u, (int64_t)L.width * L.height, st);
     if (e != hipSuccess) return e;

@@ -377,7 +377,7 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
 hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
     int grid = (int)((L.n + 3) / 4);
-    if (grid > 8192) grid = 8192;
+    if (grid > 32768) grid = 32768;
     hipLaunchKernelGGL(k_shadow_den, dim3(grid), dim3(256), 0, st, shadow_args(k, L, ws, num_den));
     return hipGetLastError();
 }
