@@ -144,19 +144,25 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int d = tid; d < kRadixBins; d += 256) table[d * nblk + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// Stable scatter: each block ranks its ITEMS items by digit (ties keep input
-// order), stages them digit-sorted in LDS, and writes each digit run to its
-// global offset (table holds the exclusive scan of the digit-major
-// histogram).
+// Stable scatter. Wave w of the block owns the contiguous items
+// [w ITEMS/4, (w + 1) ITEMS/4) and ranks them 64 at a time against its own
+// running per-digit counts (ballot multisplit; no barrier between rounds).
+// After one barrier the per-digit totals give each wave's offset within its
+// digit and the block's digit starts; items are staged digit-sorted in LDS
+// and each digit run goes to its global offset (table holds the exclusive
+// scan of the digit-major histogram). An item's rank counts exactly the
+// earlier items of its block with the same digit, so ties keep input order.
 template <int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                         const uint32_t* __restrict__ table, int nblk) {
+    constexpr int PER_WAVE = ITEMS / 4;
+    constexpr int R = PER_WAVE / 64;
+    static_assert(R * 64 * 4 == ITEMS, "ITEMS must be a multiple of 256");
     __shared__ uint32_t s_key[ITEMS];
     __shared__ uint32_t s_val[ITEMS];
-    __shared__ uint32_t s_cnt[4][kRadixBins];
-    __shared__ uint32_t s_run[kRadixBins];
+    __shared__ uint32_t s_cnt[4][kRadixBins];   // per-wave digit counts, then each wave's offset in its digit
     __shared__ uint32_t s_lstart[kRadixBins];
     __shared__ uint32_t s_gstart[kRadixBins];
     __shared__ uint32_t s_wave[4];
@@ -166,16 +172,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     if (base >= n) return;   // whole block beyond the data: uniform exit
     const uint32_t count = (n - base) < (uint32_t)ITEMS ? (n - base) : (uint32_t)ITEMS;
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
-    for (int d = tid; d < kRadixBins; d += 256) {
-        s_run[d] = 0u;
-        s_gstart[d] = table[d * nblk + blockIdx.x];
-    }
+    for (int d = tid; d < kRadixBins; d += 256) s_gstart[d] = table[d * nblk + blockIdx.x];
     __syncthreads();
-    constexpr int R = ITEMS / 256;
     uint32_t key[R], val[R], rank[R];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t idx = r * 256 + tid;
+        const uint32_t idx = (uint32_t)(w * PER_WAVE + r * 64 + lane);
         const bool valid = idx < count;
         key[r] = valid ? kin[base + idx] : 0u;
         val[r] = valid ? vin[base + idx] : 0u;
@@ -188,31 +191,33 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
             peers &= bit ? bb : ~bb;
         }
         const uint32_t before = (uint32_t)__popcll(peers & lt);
-        if (valid && before == 0) s_cnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t pre = s_run[d];
-        for (int ww = 0; ww < w; ++ww) pre += s_cnt[ww][d];
-        rank[r] = pre + before;
-        __syncthreads();
-        for (int dd = tid; dd < kRadixBins; dd += 256) {
-            s_run[dd] += s_cnt[0][dd] + s_cnt[1][dd] + s_cnt[2][dd] + s_cnt[3][dd];
-            s_cnt[0][dd] = s_cnt[1][dd] = s_cnt[2][dd] = s_cnt[3][dd] = 0u;
-        }
-        __syncthreads();
-    }
-    // local digit starts = exclusive scan of the per-digit totals
-    {
-        const uint32_t v = tid < kRadixBins ? s_run[tid] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan_256(v, &tot, s_wave);
-        if (tid < kRadixBins) s_lstart[tid] = ex;
+        // every lane reads its digit's count before the first lane of each
+        // digit group advances it (program order within the wave)
+        const uint32_t run = valid ? s_cnt[w][d] : 0u;
+        rank[r] = run + before;
+        if (valid && before == 0) s_cnt[w][d] = run + (uint32_t)__popcll(peers);
     }
     __syncthreads();
+    // per digit: each wave's offset within the digit, and the block's digit
+    // starts (exclusive scan of the totals)
+    {
+        const int d = tid;   // 256 threads, 256 digits
+        const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
+        s_cnt[0][d] = 0u;
+        s_cnt[1][d] = c0;
+        s_cnt[2][d] = c0 + c1;
+        s_cnt[3][d] = c0 + c1 + c2;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_256(c0 + c1 + c2 + c3, &tot, s_wave);
+        s_lstart[d] = ex;
+    }
+    __syncthreads();
+#pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t idx = r * 256 + tid;
+        const uint32_t idx = (uint32_t)(w * PER_WAVE + r * 64 + lane);
         if (idx < count) {
             const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
-            const uint32_t p = s_lstart[d] + rank[r];
+            const uint32_t p = s_lstart[d] + s_cnt[w][d] + rank[r];
             s_key[p] = key[r];
             s_val[p] = val[r];
         }
