@@ -86,14 +86,17 @@ class Server:
     """Admission by a memory cap over per-resolution pools of buffer sets."""
 
     def __init__(self, scene: gs3.DeviceScene, mem_cap_bytes: int, consts=None, light_res: int = 1024,
-                 capacity: Optional[int] = None, max_inflight: int = 8, overlap: bool = False):
+                 capacity: Optional[int] = None, max_inflight: int = 8, overlap="auto"):
         self.scene = scene
         self.consts = consts if consts is not None else gs3.default_consts()
         self.cap = int(mem_cap_bytes)
         self.light_res = light_res
         self.capacity = capacity or max(1 << 16, 32 * scene.n)
         self.max_inflight = max_inflight
-        self.overlap = overlap          # also overlap the stages inside each request
+        # overlap the stages inside a request too: True, False, or "auto" (only
+        # when it is admitted with fewer than two requests in flight: alone it
+        # finishes sooner, while several requests already fill the device)
+        self.overlap = overlap
         self.free: Dict[int, List[BufferSet]] = {}
         self.allocated = 0
         self.sets: List[BufferSet] = []
@@ -122,9 +125,10 @@ class Server:
         self.sets.append(bs)
         return bs
 
-    def _launch(self, req: Request, bs: BufferSet, keep: bool):
+    def _launch(self, req: Request, bs: BufferSet, keep: bool, n_inflight: int = 0):
+        overlap = (n_inflight < 2) if self.overlap == "auto" else bool(self.overlap)
         with torch.cuda.stream(bs.stream):
-            out = bs.renderer.render(req.cam, req.light, check=False, overlap=self.overlap)
+            out = bs.renderer.render(req.cam, req.light, check=False, overlap=overlap)
             final = out["final"].clone() if keep else None
             bs.event.record(bs.stream)
         return final
@@ -177,7 +181,7 @@ class Server:
                     break
                 waiting.popleft()
                 start = time.perf_counter() - t0
-                final = self._launch(req, bs, keep_results)
+                final = self._launch(req, bs, keep_results, len(inflight))
                 inflight.append((req, bs, start, final))
                 progressed = True
             if not progressed:
