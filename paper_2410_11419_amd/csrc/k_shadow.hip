@@ -299,28 +299,35 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                 banded = rows.valid;
             }
             if (p > 0.f) {
+                // the bounding box's 4-row groups (absolute index 4 ty + r)
+                // and tile columns, as integer ranges computed once; 0.05 px
+                // of slack on top of the box's padding covers the rounding of
+                // the absolute centre
+                const float U = r0.x + r0.z, V = r0.y + r0.w;
+                auto clampi = [](float x) { return (int)fminf(fmaxf(x, -1.0e6f), 1.0e6f); };
+                auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
+                    *t_lo = max(x0, __builtin_amdgcn_readfirstlane(clampi(ceilf((U + lo - 15.55f) * (1.f / kTile)))));
+                    *t_hi = min(x1, __builtin_amdgcn_readfirstlane(clampi(floorf((U + hi - 0.45f) * (1.f / kTile)))));
+                };
+                const int g_lo = __builtin_amdgcn_readfirstlane(clampi(ceilf((V - hy - 3.55f) * 0.25f)));
+                const int g_hi = __builtin_amdgcn_readfirstlane(clampi(floorf((V + hy - 0.45f) * 0.25f)));
+                int box_lo, box_hi;
+                col_range(-hx, hx, &box_lo, &box_hi);
                 for (int ty = y0; ty <= y1; ++ty) {
+                    const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
+                    if (r_lo > r_hi) continue;
                     const float oy = (float)(ty * kTile);
                     const float v = rel_centre(r0.y, r0.w, oy);
-                    // the ellipse's x-range within this tile row's pixel rows
-                    float lo = -hx, hi = hx;
+                    int t_lo = box_lo, t_hi = box_hi;
                     if (banded) {
+                        // the ellipse's x-range within this tile row's pixel rows
                         float bl, bh;
                         if (!band_x_range(rows, 0.5f - v, 15.5f - v, &bl, &bh)) continue;
-                        lo = fmaxf(lo, bl);
-                        hi = fminf(hi, bh);
+                        int b_lo, b_hi;
+                        col_range(fmaxf(-hx, bl), fminf(hx, bh), &b_lo, &b_hi);
+                        t_lo = max(t_lo, b_lo);
+                        t_hi = min(t_hi, b_hi);
                     }
-                    // the tile columns and 4-row groups the box reaches in
-                    // this tile row, as integer ranges (scalar compares in the
-                    // loops); 0.05 px of slack on top of the box's padding
-                    const float U = r0.x + r0.z;
-                    auto clampi = [](float x) { return (int)fminf(fmaxf(x, -1.0e6f), 1.0e6f); };
-                    const int t_lo = max(x0, __builtin_amdgcn_readfirstlane(
-                                                 clampi(ceilf((U + lo - 15.55f) * (1.f / kTile)))));
-                    const int t_hi = min(x1, __builtin_amdgcn_readfirstlane(
-                                                 clampi(floorf((U + hi - 0.45f) * (1.f / kTile)))));
-                    const int r_lo = max(0, __builtin_amdgcn_readfirstlane(clampi(ceilf((v - hy - 3.55f) * 0.25f))));
-                    const int r_hi = min(3, __builtin_amdgcn_readfirstlane(clampi(floorf((v + hy - 0.45f) * 0.25f))));
                     for (int tx = t_lo; tx <= t_hi; ++tx) {
                         const float ox = (float)(tx * kTile);
                         const float u = rel_centre(r0.x, r0.z, ox);
