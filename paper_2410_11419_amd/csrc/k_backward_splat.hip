@@ -274,27 +274,41 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
                 banded = rows.valid;
             }
             if (p > 0.f) {
+                // the same integer row-group and tile-column ranges as the
+                // forward denominator (computed once per Gaussian)
+                const float U = r0.x + r0.z, V = r0.y + r0.w;
+                auto clampi = [](float x) { return (int)fminf(fmaxf(x, -1.0e6f), 1.0e6f); };
+                auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
+                    *t_lo = max(x0, __builtin_amdgcn_readfirstlane(clampi(ceilf((U + lo - 15.55f) * (1.f / kTile)))));
+                    *t_hi = min(x1, __builtin_amdgcn_readfirstlane(clampi(floorf((U + hi - 0.45f) * (1.f / kTile)))));
+                };
+                const int g_lo = __builtin_amdgcn_readfirstlane(clampi(ceilf((V - hy - 3.55f) * 0.25f)));
+                const int g_hi = __builtin_amdgcn_readfirstlane(clampi(floorf((V + hy - 0.45f) * 0.25f)));
+                int box_lo, box_hi;
+                col_range(-hx, hx, &box_lo, &box_hi);
                 for (int ty = y0; ty <= y1; ++ty) {
+                    const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
+                    if (r_lo > r_hi) continue;
                     const float oy = (float)(ty * kTile);
                     const float v = rel_centre(r0.y, r0.w, oy);
-                    // the ellipse's x-range within this tile row's pixel rows
-                    float lo = -hx, hi = hx;
+                    int t_lo = box_lo, t_hi = box_hi;
                     if (banded) {
+                        // the ellipse's x-range within this tile row's pixel rows
                         float bl, bh;
                         if (!band_x_range(rows, 0.5f - v, 15.5f - v, &bl, &bh)) continue;
-                        lo = fmaxf(lo, bl);
-                        hi = fminf(hi, bh);
+                        int b_lo, b_hi;
+                        col_range(fmaxf(-hx, bl), fminf(hx, bh), &b_lo, &b_hi);
+                        t_lo = max(t_lo, b_lo);
+                        t_hi = min(t_hi, b_hi);
                     }
-                    for (int tx = x0; tx <= x1; ++tx) {
+                    for (int tx = t_lo; tx <= t_hi; ++tx) {
                         const float ox = (float)(tx * kTile);
                         const float u = rel_centre(r0.x, r0.z, ox);
-                        if (u + hi < 0.5f || u + lo > 15.5f) continue;
                         const float dx = (float)lx + 0.5f - u;
                         const bool in_x = tx * kTile + lx < a.width;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const float yb = (float)(4 * r);
-                            if (v + hy < yb + 0.5f || v - hy > yb + 3.5f) continue;
+                            if (r < r_lo || r > r_hi) continue;
                             const float dy = (float)(4 * r + ly) + 0.5f - v;
                             const float q = quad_q(dx, dy, A, B, C);
                             const bool hit = in_x && (ty * kTile + 4 * r + ly < a.height) && q >= thr;
