@@ -53,6 +53,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.table_len = nblk * kRadixBins;
     const int64_t longest = l.table_len > n + 1 ? l.table_len : n + 1;
     l.scan_sums = (longest + kSortItems - 1) / kSortItems + 1;
+    if (l.scan_sums < kRadixBins) l.scan_sums = kRadixBins;   // also the radix passes' digit totals
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;

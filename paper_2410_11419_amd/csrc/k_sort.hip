@@ -44,15 +44,16 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint
 
 // ---------------------------------------------------------------- scan
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t len,
-                                                      uint32_t* __restrict__ sums) {
+// With gather given, element i of the scanned sequence is in[gather[i]].
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
+                                                      int64_t len, uint32_t* __restrict__ sums) {
     __shared__ uint32_t s_wave[4];
     const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int64_t i = base + j;
-        acc += (i < len) ? in[i] : 0u;
+        acc += (i < len) ? in[gather ? gather[i] : i] : 0u;
     }
     uint32_t tot;
     block_excl_scan_256(acc, &tot, s_wave);
@@ -85,8 +86,9 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, i
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, int64_t len,
-                                                    const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
+                                                    int64_t len, const uint32_t* __restrict__ sums,
+                                                    uint32_t* __restrict__ out) {
     __shared__ uint32_t s_wave[4];
     const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
     uint32_t vals[16];
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int64_t i = base + j;
-        vals[j] = (i < len) ? in[i] : 0u;
+        vals[j] = (i < len) ? in[gather ? gather[i] : i] : 0u;
         acc += vals[j];
     }
     uint32_t tot;
@@ -107,16 +109,17 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
     }
 }
 
-static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t len, uint32_t* sums,
-                                 ViewHeader* hdr, int64_t capacity, uint32_t* tail_out, hipStream_t st) {
+static hipError_t exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t len,
+                                 uint32_t* sums, ViewHeader* hdr, int64_t capacity, uint32_t* tail_out,
+                                 hipStream_t st) {
     const int64_t nb = (len + kSortItems - 1) / kSortItems;
     if (nb == 0) {
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, (int64_t)0, hdr, capacity, tail_out);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, len, sums);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, gather, len, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, nb, hdr, capacity, tail_out);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, st, in, len, sums, out);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, st, in, gather, len, sums, out);
     return hipGetLastError();
 }
 
@@ -144,6 +147,34 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     for (int d = tid; d < kRadixBins; d += 256) table[d * nblk + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
+// Exclusive scan of each digit's row of the digit-major table, in place:
+// workgroup d scans table[d nblk, (d + 1) nblk) and writes the row total
+// (the digit's count over all blocks) to totals[d].
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ table, int nblk,
+                                                        uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_wave[4];
+    uint32_t* row = table + (size_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblk; base += 256 * 4) {
+        const int i0 = base + threadIdx.x * 4;
+        uint32_t v[4], acc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (i0 + j < nblk) ? row[i0 + j] : 0u;
+            acc += v[j];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_excl_scan_256(acc, &tot, s_wave);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < nblk) row[i0 + j] = run;
+            run += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 // Stable scatter. Wave w of the block owns the contiguous items
 // [w ITEMS/4, (w + 1) ITEMS/4) and ranks them 64 at a time against its own
 // running per-digit counts (ballot multisplit; no barrier between rounds).
@@ -156,7 +187,8 @@ template <int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                        const uint32_t* __restrict__ table, int nblk) {
+                                                        const uint32_t* __restrict__ table,
+                                                        const uint32_t* __restrict__ totals, int nblk) {
     constexpr int PER_WAVE = ITEMS / 4;
     constexpr int R = PER_WAVE / 64;
     static_assert(R * 64 * 4 == ITEMS, "ITEMS must be a multiple of 256");
@@ -172,7 +204,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     if (base >= n) return;   // whole block beyond the data: uniform exit
     const uint32_t count = (n - base) < (uint32_t)ITEMS ? (n - base) : (uint32_t)ITEMS;
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
-    for (int d = tid; d < kRadixBins; d += 256) s_gstart[d] = table[d * nblk + blockIdx.x];
+    {
+        const int d = tid;   // 256 threads, 256 digits
+        uint32_t all;
+        const uint32_t dstart = block_excl_scan_256(totals[d], &all, s_wave);
+        s_gstart[d] = dstart + table[d * nblk + blockIdx.x];
+    }
     __syncthreads();
     uint32_t key[R], val[R], rank[R];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -232,8 +269,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     }
 }
 
-// One stable LSD pass over 8 bits. ITEMS per workgroup: the table has
-// ceil(max_items / ITEMS) * 256 entries (the layout sizes it for both sorts).
+// One stable LSD pass over 8 bits: block histograms, row scan, scatter.
+// ITEMS per workgroup: the table has ceil(max_items / ITEMS) * 256 entries
+// (the layout sizes it for both sorts); sums holds the 256 digit totals.
 template <int ITEMS>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
@@ -241,29 +279,26 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
     const int nblk = (int)((max_items + ITEMS - 1) / ITEMS);
     if (nblk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
-    hipError_t e = exclusive_scan(table, table, (int64_t)nblk * kRadixBins, sums, nullptr, 0, nullptr, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixBins), dim3(256), 0, st, table, nblk, sums);
     hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev, n_host,
-                       shift, table, nblk);
+                       shift, table, sums, nblk);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- emit
 
-__global__ __launch_bounds__(256) void k_gather_cnt(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ cnt,
-                                                     uint32_t* __restrict__ out, int n) {
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s < n) out[s] = cnt[ids[s]];
-}
-
 // Pairs of 256 depth-sorted splats per workgroup, one pair slot per lane.
+// The grid also clears the per-tile ranges (k_ranges fills in the tiles
+// that have pairs once they are sorted).
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ offs,
                                                const int4* __restrict__ ext, int n, int tiles_x, uint32_t capacity,
-                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
+                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
+                                               int2* __restrict__ ranges, int n_tiles) {
     __shared__ uint32_t s_lo[257];
     __shared__ int s_x0[256], s_y0[256], s_w[256];
     __shared__ uint32_t s_id[256];
     const int tid = threadIdx.x;
+    for (int t = blockIdx.x * 256 + tid; t < n_tiles; t += gridDim.x * 256) ranges[t] = make_int2(0, 0);
     const int s0 = blockIdx.x * 256;
     const int m = min(256, n - s0);
     const uint32_t base = offs[s0];
@@ -306,13 +341,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk, const ViewHeader* __restrict__ hdr,
                                                  int2* __restrict__ ranges, uint32_t n_tiles) {
-    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     const uint32_t n = hdr->n_pairs;
-    if (p >= n || hdr->overflow) return;   // an overflowed binning leaves every tile empty
-    const uint32_t t = pk[p];
-    if (t >= n_tiles) return;
-    if (p == 0 || pk[p - 1] != t) ranges[t].x = (int)p;
-    if (p == n - 1 || pk[p + 1] != t) ranges[t].y = (int)(p + 1);
+    if (hdr->overflow) return;   // an overflowed binning leaves every tile empty
+    for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+        const uint32_t t = pk[p];
+        if (t >= n_tiles) continue;
+        if (p == 0 || pk[p - 1] != t) ranges[t].x = (int)p;
+        if (p == n - 1 || pk[p + 1] != t) ranges[t].y = (int)(p + 1);
+    }
 }
 
 // Launch order of the tiles: longest list first (lengths bucketed by 8), so
@@ -379,12 +415,8 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
                        even ? vals_b : vals_a, nullptr, n, L.n, pass * 8, table, sums, st);
         if (e != hipSuccess) return e;
     }
-    // 2. pair offsets in depth order (keys_b reused for the sorted counts)
-    if (n > 0) {
-        hipLaunchKernelGGL(k_gather_cnt, dim3((n + 255) / 256), dim3(256), 0, st, vals_a,
-                           at<uint32_t>(ws, L.cnt), keys_b, (int)n);
-    }
-    e = exclusive_scan(keys_b, offs, L.n, sums, hdr, L.capacity, offs + L.n, st);
+    // 2. pair offsets in depth order (the counts gathered through the order)
+    e = exclusive_scan(at<uint32_t>(ws, L.cnt), vals_a, offs, L.n, sums, hdr, L.capacity, offs + L.n, st);
     if (e != hipSuccess) return e;
     // 3. emit (tile, id) pairs; the number of tile passes decides which
     // buffer they start in so that the sorted result lands in pk_a / pv_a
@@ -396,9 +428,11 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     uint32_t* pk_b = at<uint32_t>(ws, L.pk_b);
     uint32_t* pv_b = at<uint32_t>(ws, L.pv_b);
     const bool start_b = (tile_passes & 1) == 1;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext),
-                           (int)n, L.tiles_x, (uint32_t)L.capacity, start_b ? pk_b : pk_a, start_b ? pv_b : pv_a);
+    {
+        const unsigned emit_grid = n > 0 ? (n + 255) / 256 : 1u;
+        hipLaunchKernelGGL(k_emit, dim3(emit_grid), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext), (int)n,
+                           L.tiles_x, (uint32_t)L.capacity, start_b ? pk_b : pk_a, start_b ? pv_b : pv_a,
+                           at<int2>(ws, L.ranges), (int)L.n_tiles);
     }
     // 4. stable passes by tile index
     const uint32_t* n_dev = &hdr->n_pairs;
@@ -409,11 +443,11 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     // 5. per-tile [start, end)
-    e = launch_fill_u32(at<uint32_t>(ws, L.ranges), 0u, 2 * L.n_tiles, st);
-    if (e != hipSuccess) return e;
     if (L.capacity > 0) {
-        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0, st, pk_a, hdr,
-                           at<int2>(ws, L.ranges), (uint32_t)L.n_tiles);
+        int64_t grid = (L.capacity + 255) / 256;
+        if (grid > 1024) grid = 1024;
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, st, pk_a, hdr, at<int2>(ws, L.ranges),
+                           (uint32_t)L.n_tiles);
     }
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles,
                        at<uint32_t>(ws, L.order));
