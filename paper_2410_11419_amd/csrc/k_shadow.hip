@@ -24,6 +24,7 @@
 // view's rec2, written by the projection) and the same float32 arithmetic
 // (rel_centre, quad_q), so num and den see exactly the same hits.
 #include "splat_common.h"
+#include <type_traits>
 
 namespace gs3 {
 
@@ -254,6 +255,18 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     const int lx = lane & 15, ly = lane >> 4;
     const int n = (int)a.n;
     const int tiles_y = (a.height + kTile - 1) / kTile;
+    // pixel-centre offsets of the lane, and the partial last tile column /
+    // row (when the image size is not a multiple of 16) as lane masks
+    const float cx = (float)lx + 0.5f;
+    float cy[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cy[r] = (float)(4 * r + ly) + 0.5f;
+    const int last_tx = (a.width & (kTile - 1)) ? a.tiles_x - 1 : -1;
+    const int last_ty = (a.height & (kTile - 1)) ? tiles_y - 1 : -1;
+    const bool lane_x_last = lx < (a.width & (kTile - 1));
+    bool lane_y_last[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lane_y_last[r] = 4 * r + ly < (a.height & (kTile - 1));
     auto uf4 = [](float4 x) { return make_float4(uniform_f(x.x), uniform_f(x.y), uniform_f(x.z), uniform_f(x.w)); };
     const int stride = gridDim.x * 4;
     int g = blockIdx.x * 4 + w;
@@ -304,20 +317,24 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                 // of slack on top of the box's padding covers the rounding of
                 // the absolute centre
                 const float U = r0.x + r0.z, V = r0.y + r0.w;
-                auto clampi = [](float x) { return (int)fminf(fmaxf(x, -1.0e6f), 1.0e6f); };
+                // integer ranges, loop bounds and centre offsets in scalar
+                // registers
+                auto toi = [](float x) { return sgpr_i((int)fminf(fmaxf(x, -16777216.f), 16777216.f)); };
                 auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
-                    *t_lo = max(x0, __builtin_amdgcn_readfirstlane(clampi(ceilf((U + lo - 15.55f) * (1.f / kTile)))));
-                    *t_hi = min(x1, __builtin_amdgcn_readfirstlane(clampi(floorf((U + hi - 0.45f) * (1.f / kTile)))));
+                    *t_lo = max(x0, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
+                    *t_hi = min(x1, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
                 };
-                const int g_lo = __builtin_amdgcn_readfirstlane(clampi(ceilf((V - hy - 3.55f) * 0.25f)));
-                const int g_hi = __builtin_amdgcn_readfirstlane(clampi(floorf((V + hy - 0.45f) * 0.25f)));
+                const int g_lo = toi(ceilf((V - hy - 3.55f) * 0.25f));
+                const int g_hi = toi(floorf((V + hy - 0.45f) * 0.25f));
                 int box_lo, box_hi;
                 col_range(-hx, hx, &box_lo, &box_hi);
+                // the centre's integer part (rec0.x, rec0.y hold floor(u),
+                // floor(v)); (float)(iu - ox) equals rec0.x - ox exactly
+                const int iu = toi(r0.x), iv = toi(r0.y);
                 for (int ty = y0; ty <= y1; ++ty) {
                     const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
                     if (r_lo > r_hi) continue;
-                    const float oy = (float)(ty * kTile);
-                    const float v = rel_centre(r0.y, r0.w, oy);
+                    const float v = (float)(iv - ty * kTile) + r0.w;
                     int t_lo = box_lo, t_hi = box_hi;
                     if (banded) {
                         // the ellipse's x-range within this tile row's pixel rows
@@ -328,20 +345,48 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                         t_lo = max(t_lo, b_lo);
                         t_hi = min(t_hi, b_hi);
                     }
+                    const bool row_full = ty != last_ty;
+                    if (row_full && t_hi != last_tx) {
+                        // no partial image edge in this tile row: row groups
+                        // r_lo..r_hi of every column with the compare feeding
+                        // the select directly (no masks, no per-block skips)
+                        auto rows_of = [&](auto nr_c) {
+                            constexpr int NR = decltype(nr_c)::value;
+                            float dyv[NR];
+#pragma unroll
+                            for (int j = 0; j < NR; ++j) dyv[j] = (cy[0] + (float)(4 * (r_lo + j))) - v;
+                            for (int k = iu - t_lo * kTile; k >= iu - t_hi * kTile; k -= kTile) {
+                                const float dx = cx - ((float)k + r0.z);
+#pragma unroll
+                                for (int j = 0; j < NR; ++j) {
+                                    const float q = quad_q(dx, dyv[j], A, B, C);
+                                    float e = fast_exp2(q);
+                                    asm volatile("" : "+v"(e));
+                                    acc += q >= thr ? e : 0.f;
+                                }
+                            }
+                        };
+                        switch (r_hi - r_lo) {
+                            case 3: rows_of(std::integral_constant<int, 4>{}); break;
+                            case 2: rows_of(std::integral_constant<int, 3>{}); break;
+                            case 1: rows_of(std::integral_constant<int, 2>{}); break;
+                            default: rows_of(std::integral_constant<int, 1>{}); break;
+                        }
+                        continue;
+                    }
                     for (int tx = t_lo; tx <= t_hi; ++tx) {
-                        const float ox = (float)(tx * kTile);
-                        const float u = rel_centre(r0.x, r0.z, ox);
-                        const float dx = (float)lx + 0.5f - u;
-                        const bool in_x = tx * kTile + lx < a.width;
+                        const float u = (float)(iu - tx * kTile) + r0.z;
+                        const float dx = cx - u;
+                        const bool in_x = (tx != last_tx) | lane_x_last;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             if (r < r_lo || r > r_hi) continue;
-                            const float dy = (float)(4 * r + ly) + 0.5f - v;
+                            const float dy = cy[r] - v;
                             const float q = quad_q(dx, dy, A, B, C);
                             // evaluated in every lane (no branch around it)
                             float e = fast_exp2(q);
                             asm volatile("" : "+v"(e));
-                            const bool hit = (q >= thr) & in_x & (ty * kTile + 4 * r + ly < a.height);
+                            const bool hit = (q >= thr) & in_x & (row_full | lane_y_last[r]);
                             acc += hit ? e : 0.f;
                         }
                     }

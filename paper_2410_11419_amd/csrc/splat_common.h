@@ -263,6 +263,16 @@ __device__ inline float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 __device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+// A wave-uniform int pinned to a scalar register. The builtin above is
+// dropped when the compiler already knows the value is uniform, and a
+// float-to-int conversion (a vector instruction) then leaves the loop bounds
+// and indices derived from it in vector registers, compared and stepped with
+// vector instructions.
+__device__ inline int sgpr_i(int x) {
+    int s;
+    asm("v_readfirstlane_b32 %0, %1" : "=s"(s) : "v"(x));
+    return s;
+}
 
 // Bits lo .. hi-1 of a 64-bit set (lo and hi clamped to [0, 64]).
 __device__ inline unsigned long long range_mask64(int lo, int hi) {
