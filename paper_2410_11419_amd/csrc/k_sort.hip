@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ ta
 // and each digit run goes to its global offset (table holds the exclusive
 // scan of the digit-major histogram). An item's rank counts exactly the
 // earlier items of its block with the same digit, so ties keep input order.
-template <int ITEMS>
+template <int ITEMS, bool VALS>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     constexpr int R = PER_WAVE / 64;
     static_assert(R * 64 * 4 == ITEMS, "ITEMS must be a multiple of 256");
     __shared__ uint32_t s_key[ITEMS];
-    __shared__ uint32_t s_val[ITEMS];
+    __shared__ uint32_t s_val[VALS ? ITEMS : 1];
     __shared__ uint32_t s_cnt[4][kRadixBins];   // per-wave digit counts, then each wave's offset in its digit
     __shared__ uint32_t s_lstart[kRadixBins];
     __shared__ uint32_t s_gstart[kRadixBins];
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         const uint32_t idx = (uint32_t)(w * PER_WAVE + r * 64 + lane);
         const bool valid = idx < count;
         key[r] = valid ? kin[base + idx] : 0u;
-        val[r] = valid ? vin[base + idx] : 0u;
+        val[r] = (VALS && valid) ? vin[base + idx] : 0u;
         const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
             const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
             const uint32_t p = s_lstart[d] + s_cnt[w][d] + rank[r];
             s_key[p] = key[r];
-            s_val[p] = val[r];
+            if (VALS) s_val[p] = val[r];
         }
     }
     __syncthreads();
@@ -265,14 +265,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         const uint32_t d = (k >> shift) & (kRadixBins - 1);
         const uint32_t g = s_gstart[d] + (p - s_lstart[d]);
         kout[g] = k;
-        vout[g] = s_val[p];
+        if (VALS) vout[g] = s_val[p];
     }
 }
 
 // One stable LSD pass over 8 bits: block histograms, row scan, scatter.
 // ITEMS per workgroup: the table has ceil(max_items / ITEMS) * 256 entries
 // (the layout sizes it for both sorts); sums holds the 256 digit totals.
-template <int ITEMS>
+// Without VALS only the keys move (values packed into their low bits).
+template <int ITEMS, bool VALS>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
                              uint32_t* table, uint32_t* sums, hipStream_t st) {
@@ -280,20 +281,22 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
     if (nblk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixBins), dim3(256), 0, st, table, nblk, sums);
-    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev, n_host,
-                       shift, table, sums, nblk);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, VALS>), dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev,
+                       n_host, shift, table, sums, nblk);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- emit
 
 // Pairs of 256 depth-sorted splats per workgroup, one pair slot per lane.
-// The grid also clears the per-tile ranges (k_ranges fills in the tiles
-// that have pairs once they are sorted).
+// With id_bits > 0 a pair is one word, (tile << id_bits) | id, and pv is
+// unused; otherwise the tile goes to pk and the id to pv. The grid also
+// clears the per-tile ranges (k_ranges fills in the tiles that have pairs
+// once they are sorted).
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ offs,
                                                const int4* __restrict__ ext, int n, int tiles_x, uint32_t capacity,
                                                uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
-                                               int2* __restrict__ ranges, int n_tiles) {
+                                               int2* __restrict__ ranges, int n_tiles, int id_bits) {
     __shared__ uint32_t s_lo[257];
     __shared__ int s_x0[256], s_y0[256], s_w[256];
     __shared__ uint32_t s_id[256];
@@ -334,20 +337,31 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
         const uint32_t k = j - s_lo[lo];
         const int w = s_w[lo];
         const uint32_t tile = (uint32_t)(s_y0[lo] + (int)(k / w)) * (uint32_t)tiles_x + (uint32_t)(s_x0[lo] + (int)(k % w));
-        pk[base + j] = tile;
-        pv[base + j] = s_id[lo];
+        if (id_bits > 0) {
+            pk[base + j] = (tile << id_bits) | s_id[lo];   // packed: tile above the id
+        } else {
+            pk[base + j] = tile;
+            pv[base + j] = s_id[lo];
+        }
     }
 }
 
+// Per-tile [start, end) of the sorted pairs. With packed pairs
+// (id_bits > 0) the tile is the word's high part, and the ids are written
+// to ids for the splatting kernels.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk, const ViewHeader* __restrict__ hdr,
-                                                 int2* __restrict__ ranges, uint32_t n_tiles) {
+                                                 int2* __restrict__ ranges, uint32_t n_tiles, int id_bits,
+                                                 uint32_t* __restrict__ ids) {
     const uint32_t n = hdr->n_pairs;
     if (hdr->overflow) return;   // an overflowed binning leaves every tile empty
+    const uint32_t id_mask = id_bits > 0 ? (1u << id_bits) - 1u : 0u;
     for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
-        const uint32_t t = pk[p];
+        const uint32_t w = pk[p];
+        const uint32_t t = w >> id_bits;
+        if (id_bits > 0) ids[p] = w & id_mask;
         if (t >= n_tiles) continue;
-        if (p == 0 || pk[p - 1] != t) ranges[t].x = (int)p;
-        if (p == n - 1 || pk[p + 1] != t) ranges[t].y = (int)(p + 1);
+        if (p == 0 || (pk[p - 1] >> id_bits) != t) ranges[t].x = (int)p;
+        if (p == n - 1 || (pk[p + 1] >> id_bits) != t) ranges[t].y = (int)(p + 1);
     }
 }
 
@@ -411,15 +425,17 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     //    workgroups)
     for (int pass = 0; pass < 4; ++pass) {
         const bool even = (pass & 1) == 0;
-        e = radix_pass<kSortItemsN>(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
+        e = radix_pass<kSortItemsN, true>(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
                        even ? vals_b : vals_a, nullptr, n, L.n, pass * 8, table, sums, st);
         if (e != hipSuccess) return e;
     }
     // 2. pair offsets in depth order (the counts gathered through the order)
     e = exclusive_scan(at<uint32_t>(ws, L.cnt), vals_a, offs, L.n, sums, hdr, L.capacity, offs + L.n, st);
     if (e != hipSuccess) return e;
-    // 3. emit (tile, id) pairs; the number of tile passes decides which
-    // buffer they start in so that the sorted result lands in pk_a / pv_a
+    // 3. emit (tile, id) pairs, packed into one word when tile and id bits
+    // fit in 32 (only the keys then move through the tile passes); the
+    // number of tile passes decides which buffer they start in so that the
+    // sorted result lands in pk_a / pv_a
     int tile_bits = 0;
     while ((1ll << tile_bits) < L.n_tiles) ++tile_bits;
     const int tile_passes = tile_bits == 0 ? 0 : (tile_bits + kRadixBits - 1) / kRadixBits;
@@ -432,14 +448,20 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
         const unsigned emit_grid = n > 0 ? (n + 255) / 256 : 1u;
         hipLaunchKernelGGL(k_emit, dim3(emit_grid), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext), (int)n,
                            L.tiles_x, (uint32_t)L.capacity, start_b ? pk_b : pk_a, start_b ? pv_b : pv_a,
-                           at<int2>(ws, L.ranges), (int)L.n_tiles);
+                           at<int2>(ws, L.ranges), (int)L.n_tiles, L.id_bits);
     }
     // 4. stable passes by tile index
     const uint32_t* n_dev = &hdr->n_pairs;
     for (int pass = 0; pass < tile_passes; ++pass) {
         const bool from_b = ((pass & 1) == 0) == start_b;
-        e = radix_pass<kSortItems>(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b, from_b ? pv_a : pv_b,
-                       n_dev, 0u, L.capacity, pass * kRadixBits, table, sums, st);
+        const int shift = L.id_bits + pass * kRadixBits;
+        if (L.id_bits > 0) {
+            e = radix_pass<kSortItems, false>(from_b ? pk_b : pk_a, nullptr, from_b ? pk_a : pk_b, nullptr, n_dev, 0u,
+                                              L.capacity, shift, table, sums, st);
+        } else {
+            e = radix_pass<kSortItems, true>(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b,
+                                             from_b ? pv_a : pv_b, n_dev, 0u, L.capacity, shift, table, sums, st);
+        }
         if (e != hipSuccess) return e;
     }
     // 5. per-tile [start, end)
@@ -447,7 +469,7 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
         int64_t grid = (L.capacity + 255) / 256;
         if (grid > 1024) grid = 1024;
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, st, pk_a, hdr, at<int2>(ws, L.ranges),
-                           (uint32_t)L.n_tiles);
+                           (uint32_t)L.n_tiles, L.id_bits, pv_a);
     }
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles,
                        at<uint32_t>(ws, L.order));

@@ -15,12 +15,14 @@ __global__ __launch_bounds__(256) void k_export_ranges(const int2* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_export_pairs(const uint32_t* __restrict__ pk, const uint32_t* __restrict__ pv,
                                                        const float* __restrict__ depth, const ViewHeader* __restrict__ hdr,
-                                                       uint32_t n, int32_t* __restrict__ ids, uint64_t* __restrict__ keys) {
+                                                       uint32_t n, int id_bits, int32_t* __restrict__ ids,
+                                                       uint64_t* __restrict__ keys) {
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     if (p >= hdr->n_pairs) return;
     const uint32_t id = pv[p];
     if (ids) ids[p] = (int32_t)id;
-    if (keys) keys[p] = ((uint64_t)pk[p] << 32) | (uint64_t)__float_as_uint(depth[id < n ? id : 0u]);
+    const uint32_t tile = pk[p] >> id_bits;   // packed pairs keep the tile above the id
+    if (keys) keys[p] = ((uint64_t)tile << 32) | (uint64_t)__float_as_uint(depth[id < n ? id : 0u]);
 }
 
 __global__ __launch_bounds__(256) void k_export_splats(const float4* __restrict__ rec0, const float4* __restrict__ rec1,
@@ -59,7 +61,7 @@ hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, 
     if ((ids || keys) && L.capacity > 0)
         hipLaunchKernelGGL(k_export_pairs, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0, st,
                            at<uint32_t>(ws, L.pk_a), at<uint32_t>(ws, L.pv_a), at<float>(ws, L.depth),
-                           at<ViewHeader>(ws, L.hdr), (uint32_t)L.n, ids, keys);
+                           at<ViewHeader>(ws, L.hdr), (uint32_t)L.n, (int)L.id_bits, ids, keys);
     return hipGetLastError();
 }
 

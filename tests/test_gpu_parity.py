@@ -193,6 +193,16 @@ def test_render_parity_with_mlps_ragged(gs3):
     _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "mlp")
 
 
+def test_render_parity_ragged_light(gs3):
+    # a light view whose size is not a multiple of the 16-px tile in either
+    # direction: the shadow kernels' partial last tile column and row (lane
+    # masks in the denominator, bounds checks in the numerator)
+    sc, cam, _ = synth.scene_small(seed=2)
+    rng = np.random.default_rng(21)
+    light = synth.make_view(rng.standard_normal(3), 4.0, 184, 136, 50.0)
+    _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), False, "ragged_light")
+
+
 def test_render_parity_bias_and_stop_variants(gs3):
     sc, cam, light = synth.scene_small(seed=3)
     ko = O.Consts(shadow_bias=0.05, t_min=0.01, alpha_max=0.9)
