@@ -72,15 +72,15 @@ __device__ inline void store_rows(float* rows, int row0, int q, int g, int n, co
 }
 
 __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
-    __shared__ float sm[kShadeBwdSmem];
+    __shared__ __align__(16) float sm[kShadeBwdSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
     if (a.use_phi) {
-        load_mlp(sm, kPhiS, kPhiK1, kPhiIn, 1, a.phi);
+        load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
         load_mlp_t(sm, kPhiT, kPhiIn, a.phi);
     }
     if (a.use_psi) {
-        load_mlp(sm, kPsiS, kPsiK1, kPsiIn, 3, a.psi);
+        load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
         load_mlp_t(sm, kPsiT, kPsiIn, a.psi);
     }
     __syncthreads();
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                 if (k <= kFeat) return sc.feat[(size_t)(k - 1) * n + g];
                 return 0.f;
             };
-            mlp_hidden_all<kPhiK1>(sm, kPhiS, lane, xin, h);
+            mlp_hidden_all<kPhiKR>(sm, kPhiS, lane, xin, h);
             const float tp = mlp_out(sm, kPhiS, lane, h[2], 0);
             // the layer inputs go to the scratch now; the adjoint needs only
             // the ReLU patterns of h (fewer live registers)
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                     default: return 0.f;
                 }
             };
-            mlp_hidden_all<kPsiK1>(sm, kPsiS, lane, xin, h);
+            mlp_hidden_all<kPsiKR>(sm, kPsiS, lane, xin, h);
             const float r0 = mlp_out(sm, kPsiS, lane, h[2], 0);
             const float r1 = mlp_out(sm, kPsiS, lane, h[2], 1);
             const float r2 = mlp_out(sm, kPsiS, lane, h[2], 2);

@@ -28,11 +28,11 @@ struct ShadeArgs {
 };
 
 __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
-    __shared__ float sm[kShadeSmem];
+    __shared__ __align__(16) float sm[kShadeSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
-    if (a.use_phi) load_mlp(sm, kPhiS, kPhiK1, kPhiIn, 1, a.phi);
-    if (a.use_psi) load_mlp(sm, kPsiS, kPsiK1, kPsiIn, 3, a.psi);
+    if (a.use_phi) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
+    if (a.use_psi) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
     __syncthreads();
     const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4;
     const int waves = blockDim.x >> 6;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
                 if (k <= kFeat) return sc.feat[(size_t)(k - 1) * n + g];
                 return 0.f;
             };
-            mlp_hidden<kPhiK1>(sm, kPhiS, lane, xin, h);
+            mlp_hidden<kPhiKR>(sm, kPhiS, lane, xin, h);
             tp = mlp_out(sm, kPhiS, lane, h, 0);
         }
         // ---- residual Psi([feat, w_i, w_o]) (Sec. 4.3)
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
                     default: return 0.f;
                 }
             };
-            mlp_hidden<kPsiK1>(sm, kPsiS, lane, xin, h);
+            mlp_hidden<kPsiKR>(sm, kPsiS, lane, xin, h);
             r0 = mlp_out(sm, kPsiS, lane, h, 0);
             r1 = mlp_out(sm, kPsiS, lane, h, 1);
             r2 = mlp_out(sm, kPsiS, lane, h, 2);

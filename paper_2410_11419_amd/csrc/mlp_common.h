@@ -3,16 +3,23 @@
 // each n_in -> 64 -> 64 -> 64 -> n_out with ReLU and a sigmoid output.
 //
 // A wave evaluates 16 Gaussians, four lanes per Gaussian (lane l: Gaussian
-// l % 16, quarter q = l / 16), transposed, H^T = W X^T, on
-// v_mfma_f32_16x16x4_f32, so Gaussians are the N dimension:
-//   B operand of k-step kk: lane l supplies X[g = l%16][4 kk + l/16]
-//   A operand: W[16 mt + l%16][4 kk + l/16]
-//   D: lane l holds H^T[16 mt + 4 (l/16) + i][l%16], i = 0..3.
-// Because the contraction order over the hidden index is free, the D
-// registers of one layer are fed directly as the B operand of the next
-// (k-step (m, i) <-> hidden 16 m + 4 (l/16) + i) and the weights are packed
-// in LDS in that permuted order, so no transposes are needed between layers.
-// The adjoint runs the same scheme with W^T packed the same way.
+// l % 16, quarter q = l / 16), transposed, H^T = W X^T, so Gaussians are the
+// N dimension. The hidden layers run on v_mfma_f32_16x16x16_f16 with every
+// float32 operand split into two halves, x = hi + lo / 2048 (hi = x rounded
+// to half, lo = the remainder scaled by 2048 so that it stays a normal
+// half): W X = Wh Xh + (Wh Xl + Wl Xh) / 2048, the dropped Wl Xl / 2048^2
+// term and the halves' rounding leave a relative error near 2^-22 per
+// product, below the float32 accumulation's own. Three half-precision
+// products cost far less than the four float32 ones (16x16x4) they replace.
+// Operand layout of one 16x16x16 product (k-block kb, output tile mt):
+//   A: lane l supplies W[16 mt + l%16][16 kb + 4 (l/16) + i], i = 0..3
+//   B: lane l supplies X[g = l%16][16 kb + 4 (l/16) + i]
+//   D: lane l holds H^T[16 mt + 4 (l/16) + i][l%16], i = 0..3,
+// so the D registers of output tile m are exactly the B operand of k-block m
+// of the next layer, with no transposes between layers. Activations above
+// the half range (65504) are outside this scheme's domain.
+// The adjoint recomputes the forward activations with the same routine (so
+// its ReLU masks are the forward's) and runs its own products in float32.
 #pragma once
 
 #include "gs3_internal.h"
@@ -20,30 +27,39 @@
 namespace gs3 {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kPhiIn = 1 + kFeat;        // [T, feat]
-constexpr int kPsiIn = kFeat + 6;        // [feat, w_i, w_o]
-constexpr int kPhiK1 = (kPhiIn + 3) / 4; // k-steps of the input layer
-constexpr int kPsiK1 = (kPsiIn + 3) / 4;
-// LDS layout (floats) of one packed MLP
-constexpr int kLH = 4 * 16 * 64;          // a 64x64 hidden layer
+constexpr int kPhiIn = 1 + kFeat;          // [T, feat]
+constexpr int kPsiIn = kFeat + 6;          // [feat, w_i, w_o]
+// The input layer's first 16 inputs form one split 16-wide k-block; the
+// remaining ones run as float32 16x16x4 steps (padding them to a second
+// 16-wide block would not fit the adjoint's LDS).
+constexpr int kPhiKR = (kPhiIn - 16 + 3) / 4;   // float32 k-steps of the input layer
+constexpr int kPsiKR = (kPsiIn - 16 + 3) / 4;
+static_assert(kPhiIn >= 16 && kPsiIn >= 16, "the input layer's first k-block is full");
+// LDS layout (floats) of one packed MLP: per (output tile, k-block, lane)
+// four floats holding the A operand's hi and lo halves; the input layer's
+// float32 remainder per (output tile, k-step, lane) one float
+constexpr int kLH = 4 * 4 * 64 * 4;          // a 64x64 hidden layer
 struct MlpSmem {
-    int l1, l2, l3, w4, b1, b2, b3, b4, size;
+    int l1, l1r, l2, l3, w4, b1, b2, b3, b4, size;
 };
-__host__ __device__ constexpr MlpSmem mlp_smem(int base, int k1, int n_out) {
+__host__ __device__ constexpr MlpSmem mlp_smem(int base, int kr, int n_out) {
     return MlpSmem{base,
-                   base + 4 * k1 * 64,
-                   base + 4 * k1 * 64 + kLH,
-                   base + 4 * k1 * 64 + 2 * kLH,
-                   base + 4 * k1 * 64 + 2 * kLH + n_out * 64,
-                   base + 4 * k1 * 64 + 2 * kLH + n_out * 64 + 64,
-                   base + 4 * k1 * 64 + 2 * kLH + n_out * 64 + 128,
-                   base + 4 * k1 * 64 + 2 * kLH + n_out * 64 + 192,
-                   4 * k1 * 64 + 2 * kLH + n_out * 64 + 192 + 4};
+                   base + 4 * 64 * 4,
+                   base + 4 * 64 * 4 + 4 * kr * 64,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + kLH,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + 2 * kLH,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + 2 * kLH + n_out * 64,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + 2 * kLH + n_out * 64 + 64,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + 2 * kLH + n_out * 64 + 128,
+                   base + 4 * 64 * 4 + 4 * kr * 64 + 2 * kLH + n_out * 64 + 192,
+                   (4 * 64 * 4 + 4 * kr * 64 + 2 * kLH + n_out * 64 + 192 + 4 + 3) / 4 * 4};
 }
-constexpr MlpSmem kPhiS = mlp_smem(0, kPhiK1, 1);
-constexpr MlpSmem kPsiS = mlp_smem(kPhiS.size, kPsiK1, 3);
+constexpr MlpSmem kPhiS = mlp_smem(0, kPhiKR, 1);
+constexpr MlpSmem kPsiS = mlp_smem(kPhiS.size, kPsiKR, 3);
 constexpr int kShadeSmem = kPhiS.size + kPsiS.size;
+static_assert(kPhiS.size % 4 == 0 && kPsiS.l1 % 4 == 0, "packed operands are read as 16-byte vectors");
 
 struct MlpArgs {
     const float* w[4];
@@ -52,19 +68,41 @@ struct MlpArgs {
 
 
 
-// Copy one MLP into LDS in the permuted A-operand order.
-__device__ inline void load_mlp(float* sm, const MlpSmem& S, int k1, int n_in, int n_out, const MlpArgs& m) {
+// x = hi + lo / 2048 with both parts half precision.
+__device__ inline void split_half(float x, _Float16* hi, _Float16* lo) {
+    const _Float16 h = (_Float16)x;
+    *hi = h;
+    *lo = (_Float16)((x - (float)h) * 2048.f);
+}
+
+// Copy one MLP into LDS: hidden-layer and input-layer weights as split A
+// operands, the output layer and biases as float32.
+__device__ inline void load_mlp(float* sm, const MlpSmem& S, int kr, int n_in, int n_out, const MlpArgs& m) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int idx = tid; idx < 4 * k1 * 64; idx += nt) {
-        const int mt = idx / (k1 * 64), rem = idx % (k1 * 64), kk = rem / 64, l = rem % 64;
-        const int row = 16 * mt + (l & 15), col = 4 * kk + (l >> 4);
-        sm[S.l1 + idx] = col < n_in ? m.w[0][row * n_in + col] : 0.f;
+    auto put = [&](int off, const float* W, int ld, int row, int col0, int ncol) {
+        _Float16 hv[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int col = col0 + i;
+            split_half(col < ncol ? W[row * ld + col] : 0.f, &hv[i], &hv[4 + i]);
+        }
+        float4 v;
+        __builtin_memcpy(&v, hv, sizeof v);
+        *reinterpret_cast<float4*>(sm + off) = v;
+    };
+    for (int idx = tid; idx < 4 * 64; idx += nt) {
+        const int mt = idx / 64, l = idx % 64;
+        put(S.l1 + 4 * idx, m.w[0], n_in, 16 * mt + (l & 15), 4 * (l >> 4), n_in);
     }
-    for (int idx = tid; idx < kLH; idx += nt) {
-        const int mt = idx / 1024, rem = idx % 1024, ks = rem / 64, l = rem % 64;
-        const int row = 16 * mt + (l & 15), col = 16 * (ks >> 2) + 4 * (l >> 4) + (ks & 3);
-        sm[S.l2 + idx] = m.w[1][row * kHidden + col];
-        sm[S.l3 + idx] = m.w[2][row * kHidden + col];
+    for (int idx = tid; idx < 4 * kr * 64; idx += nt) {
+        const int mt = idx / (kr * 64), rem = idx % (kr * 64), kk = rem / 64, l = rem % 64;
+        const int row = 16 * mt + (l & 15), col = 16 + 4 * kk + (l >> 4);
+        sm[S.l1r + idx] = col < n_in ? m.w[0][row * n_in + col] : 0.f;
+    }
+    for (int idx = tid; idx < 4 * 4 * 64; idx += nt) {
+        const int mt = idx / 256, rem = idx % 256, kb = rem / 64, l = rem % 64;
+        put(S.l2 + 4 * idx, m.w[1], kHidden, 16 * mt + (l & 15), 16 * kb + 4 * (l >> 4), kHidden);
+        put(S.l3 + 4 * idx, m.w[2], kHidden, 16 * mt + (l & 15), 16 * kb + 4 * (l >> 4), kHidden);
     }
     for (int idx = tid; idx < n_out * 64; idx += nt) sm[S.w4 + idx] = m.w[3][idx];
     for (int idx = tid; idx < 64; idx += nt) {
@@ -75,51 +113,96 @@ __device__ inline void load_mlp(float* sm, const MlpSmem& S, int k1, int n_in, i
     for (int idx = tid; idx < n_out; idx += nt) sm[S.b4 + idx] = m.b[3][idx];
 }
 
+// One split product step: D += A B over a 16-wide k-block, with the A
+// operand's halves read from LDS and B given as hi/lo halves.
+__device__ inline void mfma_split(const float* sm, int off, halfx4 bh, halfx4 bl, floatx4* d, floatx4* dc) {
+    const float4 v = *reinterpret_cast<const float4*>(sm + off);
+    halfx4 ah, al;
+    __builtin_memcpy(&ah, &v.x, sizeof ah);
+    __builtin_memcpy(&al, &v.z, sizeof al);
+    *d = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, *d, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, *dc, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, *dc, 0, 0, 0);
+}
+
+__device__ inline void split_b(const float x[4], halfx4* bh, halfx4* bl) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        _Float16 h, l;
+        split_half(x[i], &h, &l);
+        (*bh)[i] = h;
+        (*bl)[i] = l;
+    }
+}
+
 __device__ inline float relu(float x) { return fmaxf(x, 0.f); }
 
-// Three hidden layers on MFMA; returns the last hidden activations in D
-// layout (h[m][i] = hidden 16 m + 4 q + i of Gaussian l % 16).
-template <int K1, typename InFn>
-__device__ inline void mlp_hidden(const float* sm, const MlpSmem& S, int lane, InFn x_of_k, floatx4 h[4]) {
+// The three hidden layers of the forward; h[l][m][i] = layer l + 1, hidden
+// unit 16 m + 4 q + i of Gaussian lane % 16 (D layout). Only the last layer
+// is kept when ALL is false.
+template <int KR, bool ALL, typename InFn>
+__device__ inline void mlp_layers(const float* sm, const MlpSmem& S, int lane, InFn x_of_k,
+                                  floatx4 (*h)[4]) {
     const int q = lane >> 4;
-    floatx4 acc[4];
+    floatx4 acc[4], cor[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = cor[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    {
+        float xv[4];
 #pragma unroll
-    for (int kk = 0; kk < K1; ++kk) {
-        const float bx = x_of_k(4 * kk + q);
+        for (int i = 0; i < 4; ++i) xv[i] = x_of_k(4 * q + i);
+        halfx4 bh, bl;
+        split_b(xv, &bh, &bl);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) mfma_split(sm, S.l1 + 4 * (mt * 64 + lane), bh, bl, &acc[mt], &cor[mt]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+        const float bx = x_of_k(16 + 4 * kk + q);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[S.l1 + (mt * K1 + kk) * 64 + lane], bx, acc[mt], 0, 0, 0);
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[S.l1r + (mt * KR + kk) * 64 + lane], bx, acc[mt], 0, 0, 0);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[mt][i] = relu(acc[mt][i] + sm[S.b1 + 16 * mt + 4 * q + i]);
+        for (int i = 0; i < 4; ++i)
+            acc[mt][i] = relu(fmaf(cor[mt][i], 1.f / 2048.f, acc[mt][i]) + sm[S.b1 + 16 * mt + 4 * q + i]);
+    if (ALL) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h[0][mt] = acc[mt];
+    }
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
         const int wl = layer == 0 ? S.l2 : S.l3;
         const int bl = layer == 0 ? S.b2 : S.b3;
-        floatx4 nxt[4];
+        floatx4 nxt[4], ncor[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) nxt[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 4; ++mt) nxt[mt] = ncor[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int kb = 0; kb < 4; ++kb) {
+            const float xv[4] = {acc[kb][0], acc[kb][1], acc[kb][2], acc[kb][3]};
+            halfx4 bh, bq;
+            split_b(xv, &bh, &bq);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ks = 4 * m + i;
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-                    nxt[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[wl + (mt * 16 + ks) * 64 + lane], acc[m][i],
-                                                                   nxt[mt], 0, 0, 0);
-            }
+            for (int mt = 0; mt < 4; ++mt) mfma_split(sm, wl + 4 * ((mt * 4 + kb) * 64 + lane), bh, bq, &nxt[mt], &ncor[mt]);
+        }
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[mt][i] = relu(nxt[mt][i] + sm[bl + 16 * mt + 4 * q + i]);
-    }
+            for (int i = 0; i < 4; ++i)
+                acc[mt][i] = relu(fmaf(ncor[mt][i], 1.f / 2048.f, nxt[mt][i]) + sm[bl + 16 * mt + 4 * q + i]);
+        if (ALL || layer == 1) {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) h[mt] = acc[mt];
+            for (int mt = 0; mt < 4; ++mt) h[ALL ? layer + 1 : 0][mt] = acc[mt];
+        }
+    }
+}
+
+// Three hidden layers; returns the last hidden activations in D layout.
+template <int KR, typename InFn>
+__device__ inline void mlp_hidden(const float* sm, const MlpSmem& S, int lane, InFn x_of_k, floatx4 h[4]) {
+    mlp_layers<KR, false>(sm, S, lane, x_of_k, reinterpret_cast<floatx4(*)[4]>(h));
 }
 
 // Output unit o: sigmoid(w4[o] . h + b4[o]), summed over the lane quarters.
@@ -139,43 +222,9 @@ __device__ inline float mlp_out(const float* sm, const MlpSmem& S, int lane, con
 
 // All three hidden layers of the forward, in D layout (h[l][m][i] = layer
 // l + 1, hidden unit 16 m + 4 q + i of Gaussian lane % 16), for the adjoint.
-template <int K1, typename InFn>
+template <int KR, typename InFn>
 __device__ inline void mlp_hidden_all(const float* sm, const MlpSmem& S, int lane, InFn x_of_k, floatx4 h[3][4]) {
-    const int q = lane >> 4;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) h[0][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < K1; ++kk) {
-        const float bx = x_of_k(4 * kk + q);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            h[0][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[S.l1 + (mt * K1 + kk) * 64 + lane], bx, h[0][mt], 0, 0, 0);
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h[0][mt][i] = relu(h[0][mt][i] + sm[S.b1 + 16 * mt + 4 * q + i]);
-#pragma unroll
-    for (int layer = 1; layer < 3; ++layer) {
-        const int wl = layer == 1 ? S.l2 : S.l3;
-        const int bl = layer == 1 ? S.b2 : S.b3;
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) h[layer][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ks = 4 * m + i;
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-                    h[layer][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[wl + (mt * 16 + ks) * 64 + lane],
-                                                                        h[layer - 1][m][i], h[layer][mt], 0, 0, 0);
-            }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[layer][mt][i] = relu(h[layer][mt][i] + sm[bl + 16 * mt + 4 * q + i]);
-    }
+    mlp_layers<KR, true>(sm, S, lane, x_of_k, h);
 }
 
 // LDS layout (floats) of one MLP's transposed weights for the adjoint:
