@@ -9,6 +9,7 @@
 // bits) then leaves each tile's pairs in depth order. Same lists, far fewer
 // bytes moved per pair than sorting 64-bit keys.
 #include "gs3_internal.h"
+#include <climits>
 
 namespace gs3 {
 
@@ -183,12 +184,13 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ ta
 // and each digit run goes to its global offset (table holds the exclusive
 // scan of the digit-major histogram). An item's rank counts exactly the
 // earlier items of its block with the same digit, so ties keep input order.
-template <int ITEMS, bool VALS>
+template <int ITEMS, bool VALS, bool FINAL>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                         const uint32_t* __restrict__ table,
-                                                        const uint32_t* __restrict__ totals, int nblk) {
+                                                        const uint32_t* __restrict__ totals, int nblk, int id_bits,
+                                                        int* __restrict__ ranges) {
     constexpr int PER_WAVE = ITEMS / 4;
     constexpr int R = PER_WAVE / 64;
     static_assert(R * 64 * 4 == ITEMS, "ITEMS must be a multiple of 256");
@@ -264,25 +266,38 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         const uint32_t k = s_key[p];
         const uint32_t d = (k >> shift) & (kRadixBins - 1);
         const uint32_t g = s_gstart[d] + (p - s_lstart[d]);
-        kout[g] = k;
-        if (VALS) vout[g] = s_val[p];
+        if (FINAL) {
+            // last pass over packed pairs: the block's staged keys are in
+            // final order, so a run of one tile is contiguous here and in
+            // the output; its ends widen the tile's range (atomics across
+            // the blocks holding parts of the tile), and only the id is kept
+            const uint32_t t = k >> id_bits;
+            kout[g] = k & ((1u << id_bits) - 1u);
+            if (p == 0 || (s_key[p - 1] >> id_bits) != t) atomicMin(&ranges[2 * t], (int)g);
+            if (p == count - 1 || (s_key[p + 1] >> id_bits) != t) atomicMax(&ranges[2 * t + 1], (int)(g + 1));
+        } else {
+            kout[g] = k;
+            if (VALS) vout[g] = s_val[p];
+        }
     }
 }
 
 // One stable LSD pass over 8 bits: block histograms, row scan, scatter.
 // ITEMS per workgroup: the table has ceil(max_items / ITEMS) * 256 entries
 // (the layout sizes it for both sorts); sums holds the 256 digit totals.
-// Without VALS only the keys move (values packed into their low bits).
-template <int ITEMS, bool VALS>
+// Without VALS only the keys move (values packed into their low bits);
+// FINAL (last pass over packed pairs) writes the ids and the tile ranges.
+template <int ITEMS, bool VALS, bool FINAL = false>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
-                             uint32_t* table, uint32_t* sums, hipStream_t st) {
+                             uint32_t* table, uint32_t* sums, hipStream_t st, int id_bits = 0,
+                             int2* ranges = nullptr) {
     const int nblk = (int)((max_items + ITEMS - 1) / ITEMS);
     if (nblk == 0) return hipSuccess;
     hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixBins), dim3(256), 0, st, table, nblk, sums);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, VALS>), dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout, n_dev,
-                       n_host, shift, table, sums, nblk);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, VALS, FINAL>), dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout,
+                       n_dev, n_host, shift, table, sums, nblk, id_bits, reinterpret_cast<int*>(ranges));
     return hipGetLastError();
 }
 
@@ -291,8 +306,9 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 // Pairs of 256 depth-sorted splats per workgroup, one pair slot per lane.
 // With id_bits > 0 a pair is one word, (tile << id_bits) | id, and pv is
 // unused; otherwise the tile goes to pk and the id to pv. The grid also
-// clears the per-tile ranges (k_ranges fills in the tiles that have pairs
-// once they are sorted).
+// resets the per-tile ranges to (INT_MAX, 0): the range pass (or the last
+// tile pass) fills in the tiles that have pairs, and k_tile_order turns the
+// untouched ones into empty (0, 0) ranges.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ offs,
                                                const int4* __restrict__ ext, int n, int tiles_x, uint32_t capacity,
                                                uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
@@ -301,7 +317,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
     __shared__ int s_x0[256], s_y0[256], s_w[256];
     __shared__ uint32_t s_id[256];
     const int tid = threadIdx.x;
-    for (int t = blockIdx.x * 256 + tid; t < n_tiles; t += gridDim.x * 256) ranges[t] = make_int2(0, 0);
+    for (int t = blockIdx.x * 256 + tid; t < n_tiles; t += gridDim.x * 256) ranges[t] = make_int2(INT_MAX, 0);
     const int s0 = blockIdx.x * 256;
     const int m = min(256, n - s0);
     const uint32_t base = offs[s0];
@@ -365,15 +381,25 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk,
     }
 }
 
-// Launch order of the tiles: longest list first (lengths bucketed by 8), so
+// Final per-tile ranges, then the launch order of the tiles: longest list
+// first (lengths bucketed by 8), so
 // the few long tiles start early instead of forming the tail of the
 // splatting kernels. Only the schedule depends on it, not any result.
-__global__ __launch_bounds__(1024) void k_tile_order(const int2* __restrict__ ranges, int n_tiles,
+__global__ __launch_bounds__(1024) void k_tile_order(int2* __restrict__ ranges, int n_tiles,
+                                                      const ViewHeader* __restrict__ hdr,
                                                       uint32_t* __restrict__ order) {
     __shared__ uint32_t hist[1024];
     __shared__ uint32_t s_wave[16];
     const int tid = threadIdx.x;
     hist[tid] = 0u;
+    // tiles without pairs (still (INT_MAX, 0)) and every tile of an
+    // overflowed binning become empty ranges; each thread later reads back
+    // only the tiles it wrote here
+    const bool overflow = hdr->overflow != 0u;
+    for (int t = tid; t < n_tiles; t += 1024) {
+        const int2 r = ranges[t];
+        if (overflow || r.x >= r.y) ranges[t] = make_int2(0, 0);
+    }
     __syncthreads();
     auto bucket = [&](int t) -> int {
         const int2 r = ranges[t];
@@ -443,7 +469,11 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     uint32_t* pv_a = at<uint32_t>(ws, L.pv_a);
     uint32_t* pk_b = at<uint32_t>(ws, L.pk_b);
     uint32_t* pv_b = at<uint32_t>(ws, L.pv_b);
-    const bool start_b = (tile_passes & 1) == 1;
+    const bool packed = L.id_bits > 0;
+    // packed pairs start in pk_a and alternate with pk_b; the last pass
+    // writes the ids to pv_a. Unpacked pairs start where the sorted result
+    // lands in pk_a / pv_a.
+    const bool start_b = !packed && (tile_passes & 1) == 1;
     {
         const unsigned emit_grid = n > 0 ? (n + 255) / 256 : 1u;
         hipLaunchKernelGGL(k_emit, dim3(emit_grid), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext), (int)n,
@@ -455,7 +485,11 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
     for (int pass = 0; pass < tile_passes; ++pass) {
         const bool from_b = ((pass & 1) == 0) == start_b;
         const int shift = L.id_bits + pass * kRadixBits;
-        if (L.id_bits > 0) {
+        if (packed && pass == tile_passes - 1) {
+            e = radix_pass<kSortItems, false, true>(from_b ? pk_b : pk_a, nullptr, pv_a, nullptr, n_dev, 0u,
+                                                    L.capacity, shift, table, sums, st, L.id_bits,
+                                                    at<int2>(ws, L.ranges));
+        } else if (packed) {
             e = radix_pass<kSortItems, false>(from_b ? pk_b : pk_a, nullptr, from_b ? pk_a : pk_b, nullptr, n_dev, 0u,
                                               L.capacity, shift, table, sums, st);
         } else {
@@ -464,14 +498,15 @@ hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
         }
         if (e != hipSuccess) return e;
     }
-    // 5. per-tile [start, end)
-    if (L.capacity > 0) {
+    // 5. per-tile [start, end) (already done by the last pass over packed
+    //    pairs)
+    if (L.capacity > 0 && !(packed && tile_passes > 0)) {
         int64_t grid = (L.capacity + 255) / 256;
         if (grid > 1024) grid = 1024;
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, st, pk_a, hdr, at<int2>(ws, L.ranges),
                            (uint32_t)L.n_tiles, L.id_bits, pv_a);
     }
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles,
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles, hdr,
                        at<uint32_t>(ws, L.order));
     return hipGetLastError();
 }

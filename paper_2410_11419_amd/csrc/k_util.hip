@@ -15,14 +15,28 @@ __global__ __launch_bounds__(256) void k_export_ranges(const int2* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_export_pairs(const uint32_t* __restrict__ pk, const uint32_t* __restrict__ pv,
                                                        const float* __restrict__ depth, const ViewHeader* __restrict__ hdr,
-                                                       uint32_t n, int id_bits, int32_t* __restrict__ ids,
+                                                       uint32_t n, int32_t* __restrict__ ids,
                                                        uint64_t* __restrict__ keys) {
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     if (p >= hdr->n_pairs) return;
     const uint32_t id = pv[p];
     if (ids) ids[p] = (int32_t)id;
-    const uint32_t tile = pk[p] >> id_bits;   // packed pairs keep the tile above the id
-    if (keys) keys[p] = ((uint64_t)tile << 32) | (uint64_t)__float_as_uint(depth[id < n ? id : 0u]);
+    if (keys) keys[p] = ((uint64_t)pk[p] << 32) | (uint64_t)__float_as_uint(depth[id < n ? id : 0u]);
+}
+
+// Keys of packed binnings, where the sorted tile indices are not kept: one
+// thread per tile writes its range's keys.
+__global__ __launch_bounds__(256) void k_export_tile_keys(const int2* __restrict__ rg, int64_t tiles,
+                                                           const uint32_t* __restrict__ pv,
+                                                           const float* __restrict__ depth, uint32_t n,
+                                                           uint64_t* __restrict__ keys) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= tiles) return;
+    const int2 r = rg[t];
+    for (int p = r.x; p < r.y; ++p) {
+        const uint32_t id = pv[p];
+        keys[p] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(depth[id < n ? id : 0u]);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_export_splats(const float4* __restrict__ rec0, const float4* __restrict__ rec1,
@@ -58,10 +72,15 @@ hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, 
     if ((start || end) && L.n_tiles > 0)
         hipLaunchKernelGGL(k_export_ranges, dim3((unsigned)((L.n_tiles + 255) / 256)), dim3(256), 0, st,
                            at<int2>(ws, L.ranges), L.n_tiles, start, end);
-    if ((ids || keys) && L.capacity > 0)
+    const bool packed = L.id_bits > 0;
+    if ((ids || (keys && !packed)) && L.capacity > 0)
         hipLaunchKernelGGL(k_export_pairs, dim3((unsigned)((L.capacity + 255) / 256)), dim3(256), 0, st,
                            at<uint32_t>(ws, L.pk_a), at<uint32_t>(ws, L.pv_a), at<float>(ws, L.depth),
-                           at<ViewHeader>(ws, L.hdr), (uint32_t)L.n, (int)L.id_bits, ids, keys);
+                           at<ViewHeader>(ws, L.hdr), (uint32_t)L.n, ids, packed ? nullptr : keys);
+    if (keys && packed && L.n_tiles > 0)
+        hipLaunchKernelGGL(k_export_tile_keys, dim3((unsigned)((L.n_tiles + 255) / 256)), dim3(256), 0, st,
+                           at<int2>(ws, L.ranges), L.n_tiles, at<uint32_t>(ws, L.pv_a), at<float>(ws, L.depth),
+                           (uint32_t)L.n, keys);
     return hipGetLastError();
 }
 
