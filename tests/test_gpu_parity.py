@@ -65,6 +65,8 @@ def _bin_gpu(g, ix, iy, rx, ry, depth, W, H, capacity):
     dict(n=5000, W=10, H=7, seed=3, max_r=4),      # one tile: no tile pass
     dict(n=4097, W=300, H=200, seed=4, cull_frac=1.0),   # everything culled
     dict(n=1, W=64, H=64, seed=5),
+    # 21 id bits + 12 tile bits do not pack into one word: the two-array sort
+    dict(n=(1 << 20) + 5, W=1024, H=768, seed=6, max_r=3),
 ])
 def test_binning_bit_exact(gs3, case):
     rng = np.random.default_rng(case["seed"])
