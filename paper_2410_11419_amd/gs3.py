@@ -489,8 +489,10 @@ class Renderer:
         lists exist, while the caller's stream runs the light preprocess and
         the shadow numerator, then the resolve and the camera pass; the
         shading and Psi (independent of the shadow values) run on the camera
-        side stream, only Phi waits for the resolve. The
-        numerator's tail occupies few CUs, which the other two fill. Results
+        side stream, only Phi waits for the resolve. The light path is
+        issued first: one frame at a time the host's launches would
+        otherwise delay it. The numerator's tail occupies few CUs, which
+        the other two fill. Results
         are the same as with ``overlap=False`` (one stream, in order).
         ``events`` (optional) gets "num0"/"num1" recorded around the shadow
         numerator on the caller's stream, and "den0"/"den1" (when present)
@@ -513,16 +515,18 @@ class Renderer:
         else:
             if self.side is None:
                 self.side = (torch.cuda.Stream(), torch.cuda.Stream())
+                self.side_events = (torch.cuda.Event(), torch.cuda.Event())
             s_den, s_cam = self.side
-            # both side streams start after everything already on the caller's
-            # stream (the previous frame still reads these buffers)
+            ev_start, ev_light = self.side_events
             im = self._images(cam.width, cam.height)
-            s_cam.wait_stream(main)
-            with torch.cuda.stream(s_cam):
-                cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
-                gs3_shade(self.scene, cam, light.eye, cvb, im["colour"], self.use_mlps)
+            # the light path (preprocess, numerator, resolve) is the frame's
+            # critical path, so it is issued first; the side streams start
+            # after everything already on the caller's stream (the previous
+            # frame still reads these buffers), not after this frame's work
+            ev_start.record(main)
             lvb = self._preprocess("light", light, GS3_DEPTH_DIST, False)
-            s_den.wait_stream(main)
+            ev_light.record(main)
+            s_den.wait_event(ev_light)
             with torch.cuda.stream(s_den):
                 if events is not None and "den0" in events:
                     events["den0"].record(s_den)
@@ -534,6 +538,10 @@ class Renderer:
             gs3_shadow_num(self.consts, lvb, self.num_den)
             if events is not None:
                 events["num1"].record(main)
+            s_cam.wait_event(ev_start)
+            with torch.cuda.stream(s_cam):
+                cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
+                gs3_shade(self.scene, cam, light.eye, cvb, im["colour"], self.use_mlps)
             main.wait_stream(s_den)
             gs3_shadow_resolve(lvb, self.num_den, self.T)
             main.wait_stream(s_cam)
