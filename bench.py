@@ -156,21 +156,13 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
     inv = 1.0 / (batch * 3 * cam0.width * cam0.height)
     main = torch.cuda.current_stream()
 
-    def tensors(g):
-        out = list(g.t.values())
-        for m in (g.phi, g.psi):
-            for w, b in m:
-                out += [w, b]
-        return out
-
     def step(i, evs=None):
         if evs is not None:
             evs[0].record(main)
         for j in range(lanes):
             streams[j].wait_stream(main)
             with torch.cuda.stream(streams[j]):
-                for t in tensors(grads[j]):
-                    t.zero_()
+                grads[j].zero_()
                 for v in range(j, batch, lanes):
                     k = (i * batch + v) % len(pairs)
                     cam, light = pairs[k]
@@ -180,9 +172,8 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
         for j in range(lanes):
             main.wait_stream(streams[j])
         # gradient of the batch = sum over its lanes
-        for dst, *srcs in zip(*[tensors(g) for g in grads]):
-            for src in srcs:
-                dst.add_(src)
+        for g in grads[1:]:
+            grads[0].add_(g)
         if evs is not None:
             evs[1].record(main)
 

@@ -362,17 +362,34 @@ def gs3_render_shaded(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T:
 
 
 class DeviceGrads:
-    """Gradient tensors shaped like a DeviceScene's (zeroed), for gs3_render_backward."""
+    """Gradient tensors shaped like a DeviceScene's (zeroed), for
+    gs3_render_backward. They are views of one flat buffer (each slice
+    256-byte aligned), so clearing or summing a whole set is one kernel."""
 
     def __init__(self, scene: DeviceScene, use_mlps: bool = True):
-        self.t = {nm: torch.zeros_like(v) for nm, v in scene.t.items()}
+        like = list(scene.t.values())
+        mlps = [m if (m is not None and use_mlps) else None for m in (scene.phi, scene.psi)]
+        for m in mlps:
+            if m is not None:
+                for w, b in m:
+                    like += [w, b]
+        offs, total = [], 0
+        for v in like:
+            offs.append(total)
+            total += (v.numel() + 63) // 64 * 64
+        self.flat = torch.zeros(max(total, 1), dtype=torch.float32, device=like[0].device)
+        views = iter(self.flat[o:o + v.numel()].view(v.shape) for o, v in zip(offs, like))
+        self.t = {nm: next(views) for nm in scene.t}
+        self.phi, self.psi = [None if m is None else [(next(views), next(views)) for _ in m] for m in mlps]
 
-        def mlp(m):
-            if m is None or not use_mlps:
-                return None
-            return [(torch.zeros_like(w), torch.zeros_like(b)) for w, b in m]
-        self.phi = mlp(scene.phi)
-        self.psi = mlp(scene.psi)
+    def zero_(self) -> "DeviceGrads":
+        self.flat.zero_()
+        return self
+
+    def add_(self, other: "DeviceGrads") -> "DeviceGrads":
+        """Adds another set of the same scene and MLP configuration."""
+        self.flat.add_(other.flat)
+        return self
 
     def c_struct(self) -> gs3_grads:
         g = gs3_grads()
