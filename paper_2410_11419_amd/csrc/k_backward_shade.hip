@@ -430,11 +430,31 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     if (kq == 0 && 16 * w + r16 < P.O) part[P.O * P.J + 16 * w + r16] = bacc;
 }
 
+// Sum of the per-chunk partials of 64 consecutive parameters per
+// workgroup: each of the four waves takes every fourth chunk with eight
+// loads in flight, then one wave adds the four wave sums (fixed order, so
+// the result is deterministic).
 __global__ __launch_bounds__(256) void k_wgrad_reduce(WgArgs a, int chunks) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.total) return;
+    __shared__ float s_part[4][64];
+    const int lp = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lp;
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += a.partial[(size_t)c * a.total + p];
+    if (p < a.total) {
+        const float* src = a.partial + p;
+        const size_t ld = (size_t)a.total;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int c = grp;
+        for (; c + 28 < chunks; c += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += src[(size_t)(c + 4 * u) * ld];
+        }
+        for (; c < chunks; c += 4) acc[0] += src[(size_t)c * ld];
+        s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    }
+    s_part[grp][lp] = s;
+    __syncthreads();
+    if (grp != 0 || p >= a.total) return;
+    s = (s_part[0][lp] + s_part[1][lp]) + (s_part[2][lp] + s_part[3][lp]);
     for (int i = 0; i < a.count; ++i) {
         const WgProblem& P = a.p[i];
         const int rel = p - P.off;
@@ -650,7 +670,7 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     w.partial = partial;
     const int chunks = (sc.n + kWgChunk - 1) / kWgChunk;
     hipLaunchKernelGGL(k_wgrad, dim3(chunks, w.count), dim3(256), 0, st, w);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 255) / 256), dim3(256), 0, st, w, chunks);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 63) / 64), dim3(256), 0, st, w, chunks);
     return hipGetLastError();
 }
 
