@@ -294,7 +294,10 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float*
  * NULL), then splat c, T' and r toward the camera front to back and write
  * final = S * Sh + R. `cam_vb` holds `cam` preprocessed with GS3_DEPTH_Z.
  * MLP weight pointers may be in any device memory; n_in/n_out must be
- * 17/1 (phi) and 22/3 (psi). */
+ * 17/1 (phi) and 22/3 (psi). The MLP arithmetic is float32; its hidden
+ * layers run as split half-precision products (each operand hi + lo/2048,
+ * about 2^-22 relative per product), which assumes hidden activations and
+ * weights below the half range (65504). */
 int gs3_render(const gs3_scene* scene, const gs3_view* cam,
                const double* light_pos, const gs3_consts* consts,
                const float* T, const gs3_mlp* phi, const gs3_mlp* psi,
