@@ -195,6 +195,26 @@ def test_render_parity_with_mlps_ragged(gs3):
     _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "mlp")
 
 
+@pytest.mark.parametrize("scale", [1e-3, 1e3])
+def test_render_parity_mlp_activation_scale(gs3, scale):
+    # The MLP hidden layers run as split half-precision products. Scaling the
+    # first layer's weights and every hidden bias by s and the output layer's
+    # weights by 1/s leaves the network's function unchanged (ReLU is
+    # positively homogeneous) while the hidden activations become s times
+    # their usual size: the split must hold its accuracy over that range.
+    sc = synth.make_scene(4096, 4, seed=11, means="shell", mlps=True, log_scale_mu=(-3.6,) * 3)
+    for mlp in (sc.phi, sc.psi):
+        L = mlp.layers
+        L[0] = ((L[0][0] * scale).astype(np.float32), (L[0][1] * scale).astype(np.float32))
+        L[1] = (L[1][0], (L[1][1] * scale).astype(np.float32))
+        L[2] = (L[2][0], (L[2][1] * scale).astype(np.float32))
+        L[3] = ((L[3][0] / scale).astype(np.float32), L[3][1])
+    rng = np.random.default_rng(2)
+    cam = synth.make_view(rng.standard_normal(3), 4.0, 128, 128, 40.0)
+    light = synth.make_view(rng.standard_normal(3), 4.0, 128, 128, 60.0)
+    _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, f"mlp_scale_{scale:g}")
+
+
 def test_render_parity_ragged_light(gs3):
     # a light view whose size is not a multiple of the 16-px tile in either
     # direction: the shadow kernels' partial last tile column and row (lane
