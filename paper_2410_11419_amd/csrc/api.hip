@@ -72,6 +72,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.rec2 = take(sizeof(float4) * n);
     l.depth = take(sizeof(float) * n);
     l.ext = take(sizeof(int4) * n);
+    l.drec = take(sizeof(int4) * n);
     l.cnt = take(sizeof(uint32_t) * n);
     l.col0 = take(sizeof(float4) * n);
     l.col1 = take(sizeof(float4) * n);

@@ -43,7 +43,7 @@ struct Layout {
     int64_t capacity = 0;
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
     int32_t id_bits = 0;   // > 0: pairs are packed (tile << id_bits) | id while sorting
-    size_t hdr = 0, rec0 = 0, rec1 = 0, rec2 = 0, depth = 0, ext = 0, cnt = 0, col0 = 0, col1 = 0;
+    size_t hdr = 0, rec0 = 0, rec1 = 0, rec2 = 0, depth = 0, ext = 0, drec = 0, cnt = 0, col0 = 0, col1 = 0;
     size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
     size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0, order = 0;
     size_t total = 0;

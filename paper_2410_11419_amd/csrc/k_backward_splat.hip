@@ -224,6 +224,7 @@ struct ShadowBwdArgs {
     const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
     const int4* ext;
+    const int4* drec;      // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
     float alpha_max, bias;
@@ -259,44 +260,34 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
         const float den = uniform_f(a.num_den[n + g]);
         const float dTg = uniform_f(a.dT[g]);
         const float dden = den > 0.f ? -dTg * uniform_f(a.T[g]) / den : 0.f;
-        const int4 exv = a.ext[g];
-        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(exv.x), __builtin_amdgcn_readfirstlane(exv.y),
-                                  __builtin_amdgcn_readfirstlane(exv.z), __builtin_amdgcn_readfirstlane(exv.w));
+        const int4 drv = a.drec[g];
+        const int4 dr = make_int4(__builtin_amdgcn_readfirstlane(drv.x), __builtin_amdgcn_readfirstlane(drv.y),
+                                  __builtin_amdgcn_readfirstlane(drv.z), __builtin_amdgcn_readfirstlane(drv.w));
         float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        int x0, x1, y0, y1;
-        if (dden != 0.f && tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
+        // the forward denominator's culls (den_ranges, from the projection)
+        const int box_lo = dr.x & 0xFFFF, box_hi = (dr.x >> 16) & 0x7FFF;
+        const int y0 = dr.y & 0xFFFF, y1 = (dr.y >> 16) & 0xFFFF;
+        if (dden != 0.f && box_lo <= box_hi && y0 <= y1) {
             const float4 r0 = uf4(a.rec0[g]);
             const float4 r1 = uf4(a.rec1[g]);
             const float4 r2 = uf4(a.rec2[g]);
             float A, B, C;
             scaled_conic(r1, &A, &B, &C);
-            const float thr = r2.x, hx = r2.y, hy = r2.z, p = r2.w;
-            bool banded = false;
-            if (!isinf(p)) {
-                const float det = r1.x * r1.z - r1.y * r1.y;
-                // large elongated splats (16 tiles or more, bounding box
-                // over 2.5x the ellipse): narrow the tile columns per tile
-                // row to the ellipse's own x-extent there
-                banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
-            }
+            const float thr = r2.x, hx = r2.y;
+            bool banded = dr.x < 0;
             RowExtent rows;
             if (banded) {
                 rows = row_extent(A, B, C, thr);
                 banded = rows.valid;
             }
-            if (p > 0.f) {
-                // the same integer row-group and tile-column ranges as the
-                // forward denominator (computed once per Gaussian)
-                const float U = r0.x + r0.z, V = r0.y + r0.w;
+            {
+                const int g_lo = dr.z, g_hi = dr.w;
+                const float U = r0.x + r0.z;
                 auto toi = [](float x) { return sgpr_i((int)fminf(fmaxf(x, -16777216.f), 16777216.f)); };
                 auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
-                    *t_lo = max(x0, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
-                    *t_hi = min(x1, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
+                    *t_lo = max(box_lo, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
+                    *t_hi = min(box_hi, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
                 };
-                const int g_lo = toi(ceilf((V - hy - 3.55f) * 0.25f));
-                const int g_hi = toi(floorf((V + hy - 0.45f) * 0.25f));
-                int box_lo, box_hi;
-                col_range(-hx, hx, &box_lo, &box_hi);
                 const int iu = toi(r0.x), iv = toi(r0.y);
                 for (int ty = y0; ty <= y1; ++ty) {
                     const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
@@ -635,6 +626,7 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
     a.ext = at<int4>(ws, L.ext);
+    a.drec = at<int4>(ws, L.drec);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;

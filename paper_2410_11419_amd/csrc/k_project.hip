@@ -36,6 +36,7 @@ __device__ inline bool tile_rect(int64_t ix, int64_t iy, int64_t rx, int64_t ry,
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3_consts kc,
                                                   float4* __restrict__ rec0, float4* __restrict__ rec1,
                                                   float4* __restrict__ rec2, float* __restrict__ depth_out, int4* __restrict__ ext,
+                                                  int4* __restrict__ drec,
                                                   uint32_t* __restrict__ cnt, uint32_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -109,7 +110,10 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
         const float4 r1 = make_float4((float)(cc * id), (float)(-cb * id), (float)(ca * id), (float)opac);
         rec1[i] = r1;
         // the float32 hit threshold and bounding box every splat kernel uses
-        rec2[i] = splat_bounds(r1, kc.cutoff, kc.alpha_min);
+        const float4 r2 = splat_bounds(r1, kc.cutoff, kc.alpha_min);
+        rec2[i] = r2;
+        drec[i] = den_ranges(make_float4((float)fu, (float)fv, (float)(u - fu), (float)(v - fv)), r1, r2, x0, x1, y0,
+                             y1);
         ext[i] = make_int4((int)ix, (int)iy, (int)rx, (int)ry);
         const float d32 = (float)dep;
         depth_out[i] = d32;
@@ -119,6 +123,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
         rec0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec1[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec2[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        drec[i] = make_int4(1, 1, 0, 0);
         ext[i] = make_int4((int)floor_clamped(u), (int)floor_clamped(v), -1, -1);
         depth_out[i] = (float)dep;
         cnt[i] = 0u;
@@ -151,7 +156,8 @@ hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_co
     const int grid = (sc.n + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, st, sc, vp, k, at<float4>(ws, L.rec0),
                        at<float4>(ws, L.rec1), at<float4>(ws, L.rec2), at<float>(ws, L.depth), at<int4>(ws, L.ext),
-                       at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.keys_a), at<uint32_t>(ws, L.vals_a));
+                       at<int4>(ws, L.drec), at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.keys_a),
+                       at<uint32_t>(ws, L.vals_a));
     return hipGetLastError();
 }
 
@@ -167,6 +173,8 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
     hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.rec0), 0u, 4 * L.n, st);
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec1), 0u, 4 * L.n, st);
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec2), 0u, 4 * L.n, st);
+    // no denominator work: the empty range {1, 1, 0, 0} in every word pair
+    if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.drec), 1u, 4 * L.n, st);
     return e != hipSuccess ? e : hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct ShadowArgs {
     const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
     const int4* ext;
+    const int4* drec;   // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
     float alpha_max, bias;
@@ -270,64 +271,51 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     auto uf4 = [](float4 x) { return make_float4(uniform_f(x.x), uniform_f(x.y), uniform_f(x.z), uniform_f(x.w)); };
     const int stride = gridDim.x * 4;
     int g = blockIdx.x * 4 + w;
-    // the next Gaussian's extent and records are loaded while the current
+    // the next Gaussian's ranges and records are loaded while the current
     // one is evaluated
-    int4 nx_ex = make_int4(0, 0, 0, 0);
+    int4 nx_dr = make_int4(1, 1, 0, 0);
     float4 nx_r0 = make_float4(0.f, 0.f, 0.f, 0.f), nx_r1 = nx_r0, nx_r2 = nx_r0;
     if (g < n) {
-        nx_ex = a.ext[g];
+        nx_dr = a.drec[g];
         nx_r0 = a.rec0[g];
         nx_r1 = a.rec1[g];
         nx_r2 = a.rec2[g];
     }
     for (; g < n; g += stride) {
-        const int4 ex = make_int4(__builtin_amdgcn_readfirstlane(nx_ex.x), __builtin_amdgcn_readfirstlane(nx_ex.y),
-                                  __builtin_amdgcn_readfirstlane(nx_ex.z), __builtin_amdgcn_readfirstlane(nx_ex.w));
+        const int4 dr = make_int4(__builtin_amdgcn_readfirstlane(nx_dr.x), __builtin_amdgcn_readfirstlane(nx_dr.y),
+                                  __builtin_amdgcn_readfirstlane(nx_dr.z), __builtin_amdgcn_readfirstlane(nx_dr.w));
         const float4 r0 = uf4(nx_r0);
         const float4 r1 = uf4(nx_r1);
         const float4 r2 = uf4(nx_r2);
         if (g + stride < n) {
-            nx_ex = a.ext[g + stride];
+            nx_dr = a.drec[g + stride];
             nx_r0 = a.rec0[g + stride];
             nx_r1 = a.rec1[g + stride];
             nx_r2 = a.rec2[g + stride];
         }
         float acc = 0.f;
-        int x0, x1, y0, y1;
-        if (tile_rect_i(ex.x, ex.y, ex.z, ex.w, a.tiles_x, tiles_y, &x0, &x1, &y0, &y1)) {
+        // the culls computed by the projection (den_ranges)
+        const int box_lo = dr.x & 0xFFFF, box_hi = (dr.x >> 16) & 0x7FFF;
+        const int y0 = dr.y & 0xFFFF, y1 = (dr.y >> 16) & 0xFFFF;
+        if (box_lo <= box_hi && y0 <= y1) {
             float A, B, C;
             scaled_conic(r1, &A, &B, &C);
-            const float thr = r2.x, hx = r2.y, hy = r2.z, p = r2.w;
-            bool banded = false;
-            if (!isinf(p)) {
-                const float det = r1.x * r1.z - r1.y * r1.y;
-                // large elongated splats (16 tiles or more, bounding box
-                // over 2.5x the ellipse): narrow the tile columns per tile
-                // row to the ellipse's own x-extent there
-                banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
-            }
+            const float thr = r2.x, hx = r2.y;
+            bool banded = dr.x < 0;
             RowExtent rows;
             if (banded) {
                 rows = row_extent(A, B, C, thr);
                 banded = rows.valid;
             }
-            if (p > 0.f) {
-                // the bounding box's 4-row groups (absolute index 4 ty + r)
-                // and tile columns, as integer ranges computed once; 0.05 px
-                // of slack on top of the box's padding covers the rounding of
-                // the absolute centre
-                const float U = r0.x + r0.z, V = r0.y + r0.w;
-                // integer ranges, loop bounds and centre offsets in scalar
-                // registers
+            {
+                const int g_lo = dr.z, g_hi = dr.w;
+                const float U = r0.x + r0.z;
+                // integer loop bounds and centre offsets in scalar registers
                 auto toi = [](float x) { return sgpr_i((int)fminf(fmaxf(x, -16777216.f), 16777216.f)); };
                 auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
-                    *t_lo = max(x0, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
-                    *t_hi = min(x1, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
+                    *t_lo = max(box_lo, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
+                    *t_hi = min(box_hi, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
                 };
-                const int g_lo = toi(ceilf((V - hy - 3.55f) * 0.25f));
-                const int g_hi = toi(floorf((V + hy - 0.45f) * 0.25f));
-                int box_lo, box_hi;
-                col_range(-hx, hx, &box_lo, &box_hi);
                 // the centre's integer part (rec0.x, rec0.y hold floor(u),
                 // floor(v)); (float)(iu - ox) equals rec0.x - ox exactly
                 const int iu = toi(r0.x), iv = toi(r0.y);
@@ -414,6 +402,7 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
     a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
     a.ext = at<int4>(ws, L.ext);
+    a.drec = at<int4>(ws, L.drec);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;

@@ -263,6 +263,38 @@ __device__ inline float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 __device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+// The shadow denominator's per-Gaussian culls, computed once per view by the
+// projection (one lane per Gaussian) instead of by a whole wave per Gaussian
+// in every denominator pass. From the stored records: the bounding box's tile
+// columns [x_lo, x_hi] and tile rows [y_lo, y_hi], clipped to the splat's
+// tile rectangle [x0, x1] x [y0, y1], and its 4-row groups [g_lo, g_hi]
+// (absolute index 4 ty + r), with 0.05 px of slack on top of the box's
+// padding for the rounding of the absolute centre; bit 31 of .x flags a
+// large elongated splat whose columns are narrowed per tile row (16 tiles or
+// more, bounding box over 2.5x the ellipse). Packed as
+//   {x_lo | x_hi << 16 | banded << 31, y_lo | y_hi << 16, g_lo, g_hi};
+// an empty range (no denominator work) is {1, 1, 0, 0}.
+__device__ inline int4 den_ranges(float4 r0, float4 r1, float4 r2, int x0, int x1, int y0, int y1) {
+    const int4 empty = make_int4(1, 1, 0, 0);
+    const float hx = r2.y, hy = r2.z, p = r2.w;
+    if (!(p > 0.f)) return empty;
+    const float U = r0.x + r0.z, V = r0.y + r0.w;
+    auto toi = [](float x) { return (int)fminf(fmaxf(x, -16777216.f), 16777216.f); };
+    const int x_lo = max(x0, toi(ceilf((U - hx - 15.55f) * (1.f / kTile))));
+    const int x_hi = min(x1, toi(floorf((U + hx - 0.45f) * (1.f / kTile))));
+    const int g_lo = toi(ceilf((V - hy - 3.55f) * 0.25f));
+    const int g_hi = toi(floorf((V + hy - 0.45f) * 0.25f));
+    // tile rows with a row group in [g_lo, g_hi]: 4 ty + 3 >= g_lo, 4 ty <= g_hi
+    const int y_lo = max(y0, -((3 - g_lo) >> 2)), y_hi = min(y1, g_hi >> 2);
+    if (x_lo > x_hi || y_lo > y_hi) return empty;
+    bool banded = false;
+    if (!isinf(p)) {
+        const float det = r1.x * r1.z - r1.y * r1.y;
+        banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
+    }
+    return make_int4(x_lo | (x_hi << 16) | (banded ? (int)0x80000000u : 0), y_lo | (y_hi << 16), g_lo, g_hi);
+}
+
 // A wave-uniform int pinned to a scalar register. The builtin above is
 // dropped when the compiler already knows the value is uniform, and a
 // float-to-int conversion (a vector instruction) then leaves the loop bounds
