@@ -266,8 +266,9 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
         float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         // the forward denominator's culls (den_ranges, from the projection)
         const int box_lo = dr.x & 0xFFFF, box_hi = (dr.x >> 16) & 0x7FFF;
-        const int y0 = dr.y & 0xFFFF, y1 = (dr.y >> 16) & 0xFFFF;
-        if (dden != 0.f && box_lo <= box_hi && y0 <= y1) {
+        const int g_lo = dr.y & 0xFFFF, g_hi = (dr.y >> 16) & 0xFFFF;
+        const int y0 = -((3 - g_lo) >> 2), y1 = g_hi >> 2;   // rows with a group in [g_lo, g_hi]
+        if (dden != 0.f && box_lo <= box_hi) {
             const float4 r0 = uf4(a.rec0[g]);
             const float4 r1 = uf4(a.rec1[g]);
             const float4 r2 = uf4(a.rec2[g]);
@@ -281,14 +282,13 @@ __global__ __launch_bounds__(256) void k_shadow_den_bwd(ShadowBwdArgs a) {
                 banded = rows.valid;
             }
             {
-                const int g_lo = dr.z, g_hi = dr.w;
                 const float U = r0.x + r0.z;
                 auto toi = [](float x) { return sgpr_i((int)fminf(fmaxf(x, -16777216.f), 16777216.f)); };
                 auto col_range = [&](float lo, float hi, int* t_lo, int* t_hi) {
                     *t_lo = max(box_lo, toi(ceilf((U + lo - 15.55f) * (1.f / kTile))));
                     *t_hi = min(box_hi, toi(floorf((U + hi - 0.45f) * (1.f / kTile))));
                 };
-                const int iu = toi(r0.x), iv = toi(r0.y);
+                const int iu = dr.z, iv = dr.w;
                 for (int ty = y0; ty <= y1; ++ty) {
                     const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
                     if (r_lo > r_hi) continue;

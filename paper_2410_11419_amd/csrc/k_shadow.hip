@@ -296,8 +296,9 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
         float acc = 0.f;
         // the culls computed by the projection (den_ranges)
         const int box_lo = dr.x & 0xFFFF, box_hi = (dr.x >> 16) & 0x7FFF;
-        const int y0 = dr.y & 0xFFFF, y1 = (dr.y >> 16) & 0xFFFF;
-        if (box_lo <= box_hi && y0 <= y1) {
+        const int g_lo = dr.y & 0xFFFF, g_hi = (dr.y >> 16) & 0xFFFF;
+        const int y0 = -((3 - g_lo) >> 2), y1 = g_hi >> 2;   // rows with a group in [g_lo, g_hi]
+        if (box_lo <= box_hi) {
             float A, B, C;
             scaled_conic(r1, &A, &B, &C);
             const float thr = r2.x, hx = r2.y;
@@ -308,7 +309,6 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                 banded = rows.valid;
             }
             {
-                const int g_lo = dr.z, g_hi = dr.w;
                 const float U = r0.x + r0.z;
                 // integer loop bounds and centre offsets in scalar registers
                 auto toi = [](float x) { return sgpr_i((int)fminf(fmaxf(x, -16777216.f), 16777216.f)); };
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                 };
                 // the centre's integer part (rec0.x, rec0.y hold floor(u),
                 // floor(v)); (float)(iu - ox) equals rec0.x - ox exactly
-                const int iu = toi(r0.x), iv = toi(r0.y);
+                const int iu = dr.z, iv = dr.w;
                 for (int ty = y0; ty <= y1; ++ty) {
                     const int r_lo = max(0, g_lo - 4 * ty), r_hi = min(3, g_hi - 4 * ty);
                     if (r_lo > r_hi) continue;

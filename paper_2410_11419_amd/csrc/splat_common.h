@@ -266,14 +266,16 @@ __device__ inline uint32_t uniform_u(uint32_t x) { return (uint32_t)__builtin_am
 // The shadow denominator's per-Gaussian culls, computed once per view by the
 // projection (one lane per Gaussian) instead of by a whole wave per Gaussian
 // in every denominator pass. From the stored records: the bounding box's tile
-// columns [x_lo, x_hi] and tile rows [y_lo, y_hi], clipped to the splat's
-// tile rectangle [x0, x1] x [y0, y1], and its 4-row groups [g_lo, g_hi]
-// (absolute index 4 ty + r), with 0.05 px of slack on top of the box's
+// columns [x_lo, x_hi] clipped to the splat's tile rectangle [x0, x1] x
+// [y0, y1], and its 4-row groups [g_lo, g_hi] (absolute index 4 ty + r)
+// clipped to the rectangle's rows, with 0.05 px of slack on top of the box's
 // padding for the rounding of the absolute centre; bit 31 of .x flags a
 // large elongated splat whose columns are narrowed per tile row (16 tiles or
-// more, bounding box over 2.5x the ellipse). Packed as
-//   {x_lo | x_hi << 16 | banded << 31, y_lo | y_hi << 16, g_lo, g_hi};
-// an empty range (no denominator work) is {1, 1, 0, 0}.
+// more, bounding box over 2.5x the ellipse); iu, iv = (int) of rec0.x,
+// rec0.y (floor of the centre, exact below 2^24). Packed as
+//   {x_lo | x_hi << 16 | banded << 31, g_lo | g_hi << 16, iu, iv};
+// an empty range (no denominator work) has x_lo > x_hi, as {1, 1, 0, 0}.
+// The tile rows to visit are ceil((g_lo - 3) / 4) .. floor(g_hi / 4).
 __device__ inline int4 den_ranges(float4 r0, float4 r1, float4 r2, int x0, int x1, int y0, int y1) {
     const int4 empty = make_int4(1, 1, 0, 0);
     const float hx = r2.y, hy = r2.z, p = r2.w;
@@ -282,17 +284,18 @@ __device__ inline int4 den_ranges(float4 r0, float4 r1, float4 r2, int x0, int x
     auto toi = [](float x) { return (int)fminf(fmaxf(x, -16777216.f), 16777216.f); };
     const int x_lo = max(x0, toi(ceilf((U - hx - 15.55f) * (1.f / kTile))));
     const int x_hi = min(x1, toi(floorf((U + hx - 0.45f) * (1.f / kTile))));
-    const int g_lo = toi(ceilf((V - hy - 3.55f) * 0.25f));
-    const int g_hi = toi(floorf((V + hy - 0.45f) * 0.25f));
-    // tile rows with a row group in [g_lo, g_hi]: 4 ty + 3 >= g_lo, 4 ty <= g_hi
-    const int y_lo = max(y0, -((3 - g_lo) >> 2)), y_hi = min(y1, g_hi >> 2);
-    if (x_lo > x_hi || y_lo > y_hi) return empty;
+    // clipping the row groups to the rectangle's rows changes no tile row's
+    // [max(0, g_lo - 4 ty), min(3, g_hi - 4 ty)] inside the rectangle
+    const int g_lo = max(4 * y0, toi(ceilf((V - hy - 3.55f) * 0.25f)));
+    const int g_hi = min(4 * y1 + 3, toi(floorf((V + hy - 0.45f) * 0.25f)));
+    if (x_lo > x_hi || g_lo > g_hi) return empty;
     bool banded = false;
     if (!isinf(p)) {
         const float det = r1.x * r1.z - r1.y * r1.y;
         banded = (x1 - x0 + 1) * (y1 - y0 + 1) >= 16 && r1.x * r1.z > 4.f * det;
     }
-    return make_int4(x_lo | (x_hi << 16) | (banded ? (int)0x80000000u : 0), y_lo | (y_hi << 16), g_lo, g_hi);
+    return make_int4(x_lo | (x_hi << 16) | (banded ? (int)0x80000000u : 0), g_lo | (g_hi << 16), toi(r0.x),
+                     toi(r0.y));
 }
 
 // A wave-uniform int pinned to a scalar register. The builtin above is
