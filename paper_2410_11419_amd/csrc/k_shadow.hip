@@ -340,9 +340,12 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                         // the select directly (no masks, no per-block skips)
                         auto rows_of = [&](auto nr_c) {
                             constexpr int NR = decltype(nr_c)::value;
+                            // cy[0] + 4 (r_lo + j) is exact, and is cy[j] when
+                            // all four groups are taken (r_lo = 0)
                             float dyv[NR];
+                            const float base = NR == 4 ? cy[0] : cy[0] + (float)(4 * r_lo);
 #pragma unroll
-                            for (int j = 0; j < NR; ++j) dyv[j] = (cy[0] + (float)(4 * (r_lo + j))) - v;
+                            for (int j = 0; j < NR; ++j) dyv[j] = (NR == 4 ? cy[j] : base + (float)(4 * j)) - v;
                             for (int k = iu - t_lo * kTile; k >= iu - t_hi * kTile; k -= kTile) {
                                 const float dx = cx - ((float)k + r0.z);
 #pragma unroll
