@@ -181,9 +181,11 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ ta
 // running per-digit counts (ballot multisplit; no barrier between rounds).
 // After one barrier the per-digit totals give each wave's offset within its
 // digit and the block's digit starts; items are staged digit-sorted in LDS
-// and each digit run goes to its global offset (table holds the exclusive
-// scan of the digit-major histogram). An item's rank counts exactly the
-// earlier items of its block with the same digit, so ties keep input order.
+// and each digit run goes to its global offset: the digit's start (the
+// exclusive scan of the 256 digit totals, done here) plus the digit's count
+// in earlier blocks (the row-scanned table). An item's rank counts exactly
+// the earlier items of its block with the same digit, so ties keep input
+// order.
 template <int ITEMS, bool VALS, bool FINAL>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -382,9 +384,9 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk,
 }
 
 // Final per-tile ranges, then the launch order of the tiles: longest list
-// first (lengths bucketed by 8), so
-// the few long tiles start early instead of forming the tail of the
-// splatting kernels. Only the schedule depends on it, not any result.
+// first (lengths bucketed by 8), so the few long tiles start early instead
+// of forming the tail of the splatting kernels. Only the schedule depends on
+// the order, not any result.
 __global__ __launch_bounds__(1024) void k_tile_order(int2* __restrict__ ranges, int n_tiles,
                                                       const ViewHeader* __restrict__ hdr,
                                                       uint32_t* __restrict__ order) {
