@@ -244,9 +244,10 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
 // den_j = sum of beta over the pixels of the light image Gaussian j hits.
 // One wave per Gaussian walks the 16x4 pixel blocks of the tiles it is
 // binned to (the same pixels the tile kernel tests), skipping blocks outside
-// the hit ellipse's bounding box. The centre is formed relative to each
-// tile's origin exactly as in stage_splat, so every pixel test is
-// bit-identical to the one k_shadow makes.
+// the hit ellipse's bounding box; those culls come precomputed from the
+// projection (den_ranges). The centre is formed relative to each tile's
+// origin exactly as in stage_splat, so every pixel test is bit-identical to
+// the one k_shadow makes.
 // Everything but the pixel is the same in all lanes of the wave; the
 // readfirstlane reads say so, which keeps the loops and the block culls in
 // scalar registers and scalar branches.
