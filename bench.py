@@ -327,8 +327,8 @@ def cpu_baseline(n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path has no "
-              f"multi-GPU component in this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: every kernel of the "
+              f"path runs on a single GPU", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
