@@ -223,7 +223,6 @@ struct ShadowBwdArgs {
     const float4* rec1;
     const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
-    const int4* ext;
     const int4* drec;      // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
@@ -625,7 +624,6 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.rec1 = at<float4>(ws, L.rec1);
     a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
-    a.ext = at<int4>(ws, L.ext);
     a.drec = at<int4>(ws, L.drec);
     a.n = (uint32_t)L.n;
     a.width = L.width;

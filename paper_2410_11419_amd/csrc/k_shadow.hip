@@ -44,7 +44,6 @@ struct ShadowArgs {
     const float4* rec1;
     const float4* rec2;   // {thr, hx, hy, p}
     const float* depth;
-    const int4* ext;
     const int4* drec;   // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
@@ -405,7 +404,6 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
     a.rec1 = at<float4>(ws, L.rec1);
     a.rec2 = at<float4>(ws, L.rec2);
     a.depth = at<float>(ws, L.depth);
-    a.ext = at<int4>(ws, L.ext);
     a.drec = at<int4>(ws, L.drec);
     a.n = (uint32_t)L.n;
     a.width = L.width;

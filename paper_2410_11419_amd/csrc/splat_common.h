@@ -19,23 +19,6 @@ struct Staged {
     float4 g1;  // {C, thr, opacity, depth}
 };
 
-// Tiles a splat with extent (ix, iy, rx, ry) is binned to: those covering
-// pixel columns ix-rx..ix+rx and rows iy-ry..iy+ry (the binning rule).
-__device__ inline bool tile_rect_i(int ix, int iy, int rx, int ry, int tiles_x, int tiles_y, int* x0, int* x1,
-                                   int* y0, int* y1) {
-    if (rx <= 0 || ry <= 0) return false;
-    auto fdiv = [](long long v) -> long long { return v >= 0 ? v / kTile : -((-v + kTile - 1) / kTile); };
-    long long a0 = fdiv((long long)ix - rx), a1 = fdiv((long long)ix + rx);
-    long long b0 = fdiv((long long)iy - ry), b1 = fdiv((long long)iy + ry);
-    a0 = a0 < 0 ? 0 : a0;
-    b0 = b0 < 0 ? 0 : b0;
-    a1 = a1 > tiles_x - 1 ? tiles_x - 1 : a1;
-    b1 = b1 > tiles_y - 1 ? tiles_y - 1 : b1;
-    if (a0 > a1 || b0 > b1) return false;
-    *x0 = (int)a0; *x1 = (int)a1; *y0 = (int)b0; *y1 = (int)b1;
-    return true;
-}
-
 // Ids come from the view's own binning and are < n; the clamp only keeps a
 // corrupted list (never produced by a successful binning) inside the arrays.
 __device__ inline uint32_t safe_id(uint32_t id, uint32_t n) { return id < n ? id : 0u; }
@@ -194,47 +177,6 @@ __device__ inline bool band_x_range(const RowExtent& e, float dy0, float dy1, fl
     return true;
 }
 
-// Row-group mask of a staged splat: bit r set when the hit ellipse's
-// bounding box (padded like stage_splat's) reaches tile rows 4r .. 4r+3.
-__device__ inline uint32_t rowgroup_mask(const float4 r2, float v) {
-    const float p = r2.w;
-    if (!(p > 0.f)) return 0u;
-    if (isinf(p)) return 0xFu;
-    const float hy = r2.z;
-    uint32_t m = 0u;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float y0 = 4.f * r;
-        if (v + hy >= y0 + 0.5f && v - hy <= y0 + 3.5f) m |= 1u << r;
-    }
-    return m;
-}
-
-// Stage splat `id` for the tile with origin (tile_x0, tile_y0): the record
-// and its row-group mask (bit r: the splat can hit tile rows 4r..4r+3; 0 if
-// its bounding box misses the tile's columns).
-__device__ inline Staged stage_rows(uint32_t id, const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                                    const float4* __restrict__ rec2, const float* __restrict__ depth, float tile_x0,
-                                    float tile_y0, uint32_t* mask) {
-    const float4 r0 = rec0[id];
-    const float4 r1 = rec1[id];
-    const float4 r2 = rec2[id];
-    Staged s;
-    const float u = rel_centre(r0.x, r0.z, tile_x0);
-    const float v = rel_centre(r0.y, r0.w, tile_y0);
-    float A, B, C;
-    scaled_conic(r1, &A, &B, &C);
-    s.g0 = make_float4(u, v, A, B);
-    s.g1 = make_float4(C, r2.x, r1.w, depth ? depth[id] : 0.f);
-    uint32_t m = rowgroup_mask(r2, v);
-    if (m && !isinf(r2.w)) {
-        const float hx = r2.y;
-        if (u + hx < 0.5f || u - hx > 15.5f) m = 0u;
-    }
-    *mask = m;
-    return s;
-}
-
 // q = power * log2(e) at tile-relative pixel centre (px, py)
 __device__ inline float splat_q(const Staged& s, float px, float py) {
     return quad_q(px - s.g0.x, py - s.g0.y, s.g0.z, s.g0.w, s.g1.x);
@@ -361,9 +303,5 @@ __device__ inline bool xcd_tile_quadrant(int n_tiles, int* slot, int* qd) {
     return *slot < n_tiles;
 }
 inline unsigned quadrant_grid(int64_t n_tiles) { return (unsigned)(32 * ((n_tiles + 7) / 8)); }
-
-__device__ inline float wave_sum(float x) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(x)), 63));
-}
 
 }  // namespace gs3
