@@ -353,7 +353,25 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
                                     const float q = quad_q(dx, dyv[j], A, B, C);
                                     float e = fast_exp2(q);
                                     asm volatile("" : "+v"(e));
-                                    acc += q >= thr ? e : 0.f;
+                                    // acc += e where q >= thr, as a compare that
+                                    // narrows the lane mask and a masked add: one
+                                    // vector instruction fewer per block than
+                                    // compare, select and add. The scalar moves
+                                    // that save and restore the mask issue beside
+                                    // other waves' vector work. thr is
+                                    // wave-uniform; a NaN q fails both forms.
+                                    float sum = acc;
+                                    const float th = thr;
+                                    unsigned long long saved;
+                                    asm volatile(
+                                        "s_mov_b64 %1, exec\n\t"
+                                        "v_cmpx_le_f32_e32 vcc, %3, %2\n\t"
+                                        "v_add_f32_e32 %0, %0, %4\n\t"
+                                        "s_mov_b64 exec, %1"
+                                        : "+v"(sum), "=&s"(saved)
+                                        : "v"(q), "s"(th), "v"(e)
+                                        : "vcc");
+                                    acc = sum;
                                 }
                             }
                         };
