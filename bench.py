@@ -155,6 +155,12 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
     cam0 = pairs[0][0]
     inv = 1.0 / (batch * 3 * cam0.width * cam0.height)
     main = torch.cuda.current_stream()
+    # per view of a step: the L1 loss value and its gradient dL/dfinal, both
+    # from gs3_l1_loss (scale 1 / (batch 3 H W): the batch mean)
+    px = 3 * cam0.width * cam0.height
+    dFs = [torch.empty(3, cam0.height, cam0.width, device=ds.t["mean"].device) for _ in range(lanes)]
+    losses = torch.empty(batch, device=ds.t["mean"].device)
+    loss_ws = [gs3.l1_workspace(px) for _ in range(lanes)]
 
     def step(i, evs=None):
         if evs is not None:
@@ -167,8 +173,8 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
                     k = (i * batch + v) % len(pairs)
                     cam, light = pairs[k]
                     out = rnds[j].render(cam, light, check=False, overlap=False)
-                    dF = torch.sign(out["final"] - targets[k]) * inv
-                    rnds[j].backward(cam, light, dF, grads[j])
+                    gs3.gs3_l1_loss(out["final"], targets[k], inv, losses[v:v + 1], dFs[j], loss_ws[j])
+                    rnds[j].backward(cam, light, dFs[j], grads[j])
         for j in range(lanes):
             main.wait_stream(streams[j])
         # gradient of the batch = sum over its lanes
@@ -203,7 +209,9 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
         raise RuntimeError("a binning exceeded its pair capacity inside the timed train steps")
     per = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
     light0 = pairs[0][1]
+    loss_last = float(losses.sum().item())
     return {"metric": "fwd+bwd steps/s", "value": round(steps / wall, 3), "unit": "steps/s",
+            "loss_last_step": round(loss_last, 6),
             "ms_per_step": round(1e3 * wall / steps, 3), "steps": steps, "batch": batch,
             "workload": workload or (f"{sc.n:,} Gaussians, batch of {batch} (camera {cam0.width}x{cam0.height}, "
                                      f"light {light0.width}x{light0.height}) pairs, L1 loss against targets "

@@ -26,7 +26,8 @@
  *    library allocates no device memory on any path.
  *  - All work is enqueued asynchronously on the caller's HIP stream
  *    (`stream`, NULL = the default stream); no call synchronises the host
- *    except gs3_view_pair_count.
+ *    except gs3_view_pair_count (a workspace's status block, see
+ *    gs3_viewbuf, reports the same without a synchronisation).
  *  - Per-Gaussian arrays are float32 structure-of-arrays with the Gaussian
  *    index fastest ([C][n]); images are planar float32 [C][H][W], row-major.
  *  - Calls that share a workspace must be ordered on one stream; distinct
@@ -48,7 +49,9 @@ enum {
     GS3_OK = 0,
     GS3_INVALID_ARG = -1,          /* null pointer, bad size, misaligned buffer */
     GS3_WORKSPACE_TOO_SMALL = -2,  /* ws_bytes below gs3_view_workspace_size */
-    GS3_PAIR_CAPACITY_EXCEEDED = -3, /* reported by gs3_view_pair_count */
+    GS3_PAIR_CAPACITY_EXCEEDED = -3, /* a binning needed more pairs than its capacity:
+                                        reported by gs3_view_pair_count, and by the
+                                        next call on a workspace with a status block */
     GS3_HIP_ERROR = -4,            /* a HIP runtime call or launch failed */
     GS3_UNSUPPORTED = -5           /* parameter combination not implemented */
 };
@@ -138,6 +141,23 @@ typedef struct {
     int32_t width;          /* image size in pixels, 1..16384 */
     int32_t height;
     int64_t pair_capacity;  /* max (tile, Gaussian) pairs, 0..2^31-1 */
+    /* Optional (NULL = none) binning status block: two int64 of HOST-PINNED
+     * memory (hipHostMalloc / torch pin_memory) owned by the caller and
+     * zeroed by it before the first binning. It reports a pair-capacity
+     * overflow without synchronising the stream:
+     *   status[0]  binning generation, incremented on the host by every
+     *              gs3_bin / gs3_sort / gs3_preprocess into this workspace
+     *              when it is enqueued;
+     *   status[1]  written by the device once that binning's pair count is
+     *              known: (generation mod 2^24) << 40 | overflow << 39 |
+     *              required pair count (39 bits).
+     * gs3_view_poll decodes it. Every call that reads the workspace's lists
+     * (gs3_shadow_*, gs3_render*, gs3_render_backward, gs3_view_lists,
+     * gs3_view_count_hits) first reads the block on the host and returns
+     * GS3_PAIR_CAPACITY_EXCEEDED, enqueueing nothing, when the latest
+     * binning has completed with an overflow. A binning call rejects with
+     * GS3_INVALID_ARG a block the device cannot address. */
+    int64_t* status;
 } gs3_viewbuf;
 
 /* Depth key of a view: view-space z (camera) or distance to the eye
@@ -232,9 +252,20 @@ int gs3_preprocess(const gs3_scene* scene, const gs3_view* view,
 
 /* Number of (tile, Gaussian) pairs of the last binning in `vb` (host
  * value; synchronises `stream`). Returns GS3_PAIR_CAPACITY_EXCEEDED (and
- * the required count) if it exceeded the capacity: the lists are then
- * truncated and every later result from this workspace is invalid. */
+ * the required count) if it exceeded the capacity. An overflowed binning
+ * leaves every tile list of the workspace empty; the calls that consume it
+ * then write NaN sentinels instead of plausible values: T of
+ * gs3_shadow_splat / gs3_shadow_resolve and every image of gs3_render /
+ * gs3_render_shaded are NaN. Rebin with a larger capacity. */
 int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t stream);
+
+/* Status of the latest binning of `vb` from its status block (vb->status),
+ * without touching the device or the stream: *state = 0 while that binning
+ * has not completed on the device yet, 1 when it completed within the
+ * capacity, 2 when it overflowed; *required_pairs = its unclamped pair count
+ * once completed (else -1). GS3_INVALID_ARG when vb->status is NULL. */
+enum { GS3_VIEW_PENDING = 0, GS3_VIEW_OK = 1, GS3_VIEW_OVERFLOW = 2 };
+int gs3_view_poll(const gs3_viewbuf* vb, int32_t* state, int64_t* required_pairs);
 
 /* Copy the binning of `vb` out: tile_start/tile_end [tiles] (list of tile t
  * is ids[tile_start[t] .. tile_end[t]) ), ids [pair count] Gaussian indices,
@@ -350,6 +381,30 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
                         const gs3_viewbuf* light_vb, const gs3_viewbuf* cam_vb,
                         const gs3_images* fwd, const float* dL_dfinal,
                         const gs3_grads* grads, void* ws, size_t ws_bytes, gs3_stream_t stream);
+
+/* Sec. 4.4, Eq. 9 (the L1 term of the training loss): for `count` float32
+ * elements, *loss = scale * sum_i |pred_i - target_i| (one float of device
+ * memory) and, unless dL_dpred is NULL, dL_dpred[i] = scale *
+ * sign(pred_i - target_i) (0 where the two are equal: the subgradient the
+ * oracle uses). scale = 1 / count gives the mean. The sum is formed in a
+ * fixed order, float64 partial sums of consecutive 8192-element chunks
+ * added in chunk order, so the value is the same on every run. `ws` (256-
+ * byte aligned, gs3_l1_loss_workspace_size bytes) holds the partial sums.
+ * Errors: GS3_INVALID_ARG (NULL pred/target/loss with count > 0, count < 0,
+ * misaligned ws), GS3_WORKSPACE_TOO_SMALL. */
+int gs3_l1_loss_workspace_size(int64_t count, size_t* bytes);
+int gs3_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
+                float* dL_dpred, void* ws, size_t ws_bytes, gs3_stream_t stream);
+
+/* Gradient-set upkeep of a training step (Sec. 4.4): gs3_render_backward
+ * adds into its gradients, so a step clears them first, and views whose
+ * gradients were accumulated in separate sets (to run concurrently) are
+ * summed afterwards. Both act on `count` float32 of device memory:
+ *   gs3_grads_clear       g[i] = 0
+ *   gs3_grads_accumulate  dst[i] += src[i]   (dst and src must not overlap)
+ * Errors: GS3_INVALID_ARG for count < 0 or a NULL pointer with count > 0. */
+int gs3_grads_clear(float* g, int64_t count, gs3_stream_t stream);
+int gs3_grads_accumulate(float* dst, const float* src, int64_t count, gs3_stream_t stream);
 
 #ifdef __cplusplus
 }

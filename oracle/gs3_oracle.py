@@ -36,7 +36,7 @@ __all__ = [
     "focal", "project", "tile_rects", "bin_tiles", "pixel_entries",
     "shadow_pass", "shadow_accumulate", "shadow_values", "splat_extent", "diffuse", "angular_gaussian",
     "lobe_frame", "shade", "mlp_forward", "camera_pass", "render",
-    "render_images", "sigmoid",
+    "render_images", "sigmoid", "l1_loss",
 ]
 
 DT = torch.float64
@@ -676,6 +676,17 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
             "T": T, "num": num, "den": den, "Tp": tp, "c": sh["c"], "r": r,
             "amb_T": amb_T, "amb_px": amb_px, "proj_l": proj_l, "proj_c": proj_c,
             "opacity": opacity}
+
+
+# --------------------------------------------------------------- training
+
+def l1_loss(pred, target, scale: float):
+    """The L1 term of the training loss (Sec. 4.4, Eq. 9): scale * sum
+    |pred - target| over all elements, in float64, and its subgradient
+    scale * sign(pred - target), taken as 0 where the two are equal.
+    Returns (value, gradient array)."""
+    d = np.asarray(pred, np.float64) - np.asarray(target, np.float64)
+    return float(scale * np.abs(d).sum()), scale * np.sign(d)
 
 
 def render_images(out: Dict, view) -> Dict[str, np.ndarray]:

@@ -106,6 +106,64 @@ static int check_vb(const gs3_viewbuf* vb, Layout* L) {
     return GS3_OK;
 }
 
+// Binning status block (gs3_viewbuf.status): the host-side generation in
+// status[0], the device-written packed outcome in status[1].
+constexpr int kGenBits = 24;
+constexpr unsigned long long kGenMask = (1ull << kGenBits) - 1ull;
+
+static void read_status(const gs3_viewbuf* vb, int32_t* state, int64_t* required) {
+    const volatile int64_t* st = vb->status;
+    const unsigned long long gen = (unsigned long long)st[0];
+    const unsigned long long word = (unsigned long long)__atomic_load_n(&vb->status[1], __ATOMIC_ACQUIRE);
+    if (gen == 0 || (word >> 40) != (gen & kGenMask)) {
+        *state = GS3_VIEW_PENDING;
+        *required = -1;
+        return;
+    }
+    *required = (int64_t)(word & ((1ull << 39) - 1ull));
+    *state = (word >> 39) & 1ull ? GS3_VIEW_OVERFLOW : GS3_VIEW_OK;
+}
+
+// Calls that read a workspace's lists: refuse, enqueueing nothing, once the
+// latest binning is known (from the status block) to have overflowed.
+static int check_lists(const gs3_viewbuf* vb) {
+    if (!vb->status) return GS3_OK;
+    int32_t state;
+    int64_t req;
+    read_status(vb, &state, &req);
+    if (state == GS3_VIEW_OVERFLOW)
+        return fail(GS3_PAIR_CAPACITY_EXCEEDED, "the last binning of this workspace needed %lld pairs, capacity is %lld",
+                    (long long)req, (long long)vb->pair_capacity);
+    return GS3_OK;
+}
+
+// A binning into `vb`: the device address of the status block (NULL when
+// there is none), checked before anything is enqueued.
+static int status_target(const gs3_viewbuf* vb, int64_t** dev) {
+    *dev = nullptr;
+    if (!vb->status) return GS3_OK;
+    if ((reinterpret_cast<uintptr_t>(vb->status) & 7) != 0)
+        return fail(GS3_INVALID_ARG, "viewbuf.status is not 8-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, vb->status) != hipSuccess || attr.devicePointer == nullptr) {
+        (void)hipGetLastError();
+        return fail(GS3_INVALID_ARG, "viewbuf.status is not host-pinned memory the device can write");
+    }
+    *dev = reinterpret_cast<int64_t*>(attr.devicePointer);
+    return GS3_OK;
+}
+
+// After a binning has been enqueued: the next generation, and the kernel
+// that reports it.
+static int post_status(const gs3_viewbuf* vb, const Layout& L, int64_t* dev, hipStream_t st) {
+    if (!dev) return GS3_OK;
+    volatile int64_t* gen = vb->status;
+    const long long g = (long long)gen[0] + 1;
+    gen[0] = g;
+    GS3_CHECK_HIP(launch_write_status(L, vb->ws, g, dev + 1, st));
+    return GS3_OK;
+}
+
 static int check_consts(const gs3_consts* k) {
     if (!k) return fail(GS3_INVALID_ARG, "consts is NULL");
     if (!(k->near_plane > 0.f) || !(k->clamp_frac > 0.f) || !(k->dilation >= 0.f) || !(k->cutoff > 0.f) ||
@@ -261,17 +319,21 @@ int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx, const int32
     int st;
     if ((st = check_vb(vb, &L)) != GS3_OK) return st;
     if (L.n > 0 && (!ix || !iy || !rx || !ry || !depth)) return fail(GS3_INVALID_ARG, "extent/depth pointer is NULL");
+    int64_t* sdev;
+    if ((st = status_target(vb, &sdev)) != GS3_OK) return st;
     GS3_CHECK_HIP(launch_extent_keys(ix, iy, rx, ry, depth, L, vb->ws, (hipStream_t)stream));
     GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
-    return GS3_OK;
+    return post_status(vb, L, sdev, (hipStream_t)stream);
 }
 
 int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream) {
     Layout L;
     int st;
     if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    int64_t* sdev;
+    if ((st = status_target(vb, &sdev)) != GS3_OK) return st;
     GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
-    return GS3_OK;
+    return post_status(vb, L, sdev, (hipStream_t)stream);
 }
 
 int gs3_preprocess(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
@@ -297,11 +359,19 @@ int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t st
     return GS3_OK;
 }
 
+int gs3_view_poll(const gs3_viewbuf* vb, int32_t* state, int64_t* required_pairs) {
+    if (!vb || !vb->status) return fail(GS3_INVALID_ARG, "viewbuf or its status block is NULL");
+    if (!state || !required_pairs) return fail(GS3_INVALID_ARG, "state / required_pairs is NULL");
+    read_status(vb, state, required_pairs);
+    return GS3_OK;
+}
+
 int gs3_view_lists(const gs3_viewbuf* vb, int32_t* tile_start, int32_t* tile_end, int32_t* ids, uint64_t* keys,
                    gs3_stream_t stream) {
     Layout L;
     int st;
     if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(vb)) != GS3_OK) return st;
     GS3_CHECK_HIP(launch_export_lists(L, vb->ws, tile_start, tile_end, ids, keys, (hipStream_t)stream));
     return GS3_OK;
 }
@@ -320,6 +390,7 @@ int gs3_view_count_hits(const gs3_consts* consts, const gs3_viewbuf* vb, int32_t
     Layout L;
     int st;
     if ((st = check_vb(vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(vb)) != GS3_OK) return st;
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (!hits) return fail(GS3_INVALID_ARG, "hits is NULL");
     if ((reinterpret_cast<uintptr_t>(hits) & 7) != 0) return fail(GS3_INVALID_ARG, "hits not 8-byte aligned");
@@ -333,6 +404,7 @@ int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb, floa
     Layout L;
     int st;
     if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(light_vb)) != GS3_OK) return st;
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (L.n > 0 && (!num_den || !T)) return fail(GS3_INVALID_ARG, "num_den / T is NULL");
     GS3_CHECK_HIP(launch_shadow(*consts, L, light_vb->ws, num_den, T, (hipStream_t)stream));
@@ -343,6 +415,7 @@ int gs3_shadow_den(const gs3_consts* consts, const gs3_viewbuf* light_vb, float*
     Layout L;
     int st;
     if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(light_vb)) != GS3_OK) return st;
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (L.n > 0 && !num_den) return fail(GS3_INVALID_ARG, "num_den is NULL");
     GS3_CHECK_HIP(launch_shadow_den(*consts, L, light_vb->ws, num_den, (hipStream_t)stream));
@@ -353,6 +426,7 @@ int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float*
     Layout L;
     int st;
     if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(light_vb)) != GS3_OK) return st;
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (L.n > 0 && !num_den) return fail(GS3_INVALID_ARG, "num_den is NULL");
     GS3_CHECK_HIP(launch_shadow_num(*consts, L, light_vb->ws, num_den, (hipStream_t)stream));
@@ -363,8 +437,9 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float*
     Layout L;
     int st;
     if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
+    if ((st = check_lists(light_vb)) != GS3_OK) return st;
     if (L.n > 0 && (!num_den || !T)) return fail(GS3_INVALID_ARG, "num_den / T is NULL");
-    GS3_CHECK_HIP(launch_shadow_resolve(L, num_den, T, (hipStream_t)stream));
+    GS3_CHECK_HIP(launch_shadow_resolve(L, light_vb->ws, num_den, T, (hipStream_t)stream));
     return GS3_OK;
 }
 
@@ -372,6 +447,7 @@ static int render_args(const gs3_scene* scene, const gs3_view* cam, const double
                        const gs3_consts* consts, const gs3_viewbuf* cam_vb, Layout* L) {
     int st;
     if ((st = check_vb(cam_vb, L)) != GS3_OK) return st;
+    if ((st = check_lists(cam_vb)) != GS3_OK) return st;
     if ((st = check_scene(scene, true)) != GS3_OK) return st;
     if (consts && (st = check_consts(consts)) != GS3_OK) return st;
     if (scene->n != cam_vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbuf.n");
@@ -499,6 +575,8 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     int st;
     if ((st = check_vb(cam_vb, &Lc)) != GS3_OK) return st;
     if ((st = check_vb(light_vb, &Ll)) != GS3_OK) return st;
+    if ((st = check_lists(cam_vb)) != GS3_OK) return st;
+    if ((st = check_lists(light_vb)) != GS3_OK) return st;
     if ((st = check_scene(scene, true)) != GS3_OK) return st;
     if ((st = check_consts(consts)) != GS3_OK) return st;
     if (scene->n != cam_vb->n || scene->n != light_vb->n)
@@ -561,6 +639,40 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     GS3_CHECK_HIP(launch_shade_bwd(sd, sp, T, phi, psi, gcol, dT, g, rows, partial, grads, s));
     GS3_CHECK_HIP(launch_shadow_bwd(*consts, Ll, light_vb->ws, T, num_den, dT, dnum, gray, glight, s));
     GS3_CHECK_HIP(launch_project_bwd(sd, vpc, vpl, *consts, gcam, glight, g, s));
+    return GS3_OK;
+}
+
+int gs3_l1_loss_workspace_size(int64_t count, size_t* bytes) {
+    if (!bytes) return fail(GS3_INVALID_ARG, "bytes is NULL");
+    if (count < 0) return fail(GS3_INVALID_ARG, "count < 0");
+    const int64_t chunks = l1_chunks(count);
+    *bytes = align256(sizeof(double) * (size_t)(chunks > 0 ? chunks : 1));
+    return GS3_OK;
+}
+
+int gs3_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss, float* dL_dpred,
+                void* ws, size_t ws_bytes, gs3_stream_t stream) {
+    if (count < 0) return fail(GS3_INVALID_ARG, "count < 0");
+    if (!loss || (count > 0 && (!pred || !target))) return fail(GS3_INVALID_ARG, "pred / target / loss is NULL");
+    if (!ws) return fail(GS3_INVALID_ARG, "ws is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GS3_INVALID_ARG, "ws not 256-byte aligned");
+    size_t need;
+    gs3_l1_loss_workspace_size(count, &need);
+    if (ws_bytes < need) return fail(GS3_WORKSPACE_TOO_SMALL, "loss workspace has %zu bytes, needs %zu", ws_bytes, need);
+    GS3_CHECK_HIP(launch_l1_loss(pred, target, count, scale, loss, dL_dpred, static_cast<double*>(ws),
+                                 (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_grads_clear(float* g, int64_t count, gs3_stream_t stream) {
+    if (count < 0 || (count > 0 && !g)) return fail(GS3_INVALID_ARG, "bad gradient buffer");
+    GS3_CHECK_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g), 0u, count, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_grads_accumulate(float* dst, const float* src, int64_t count, gs3_stream_t stream) {
+    if (count < 0 || (count > 0 && (!dst || !src))) return fail(GS3_INVALID_ARG, "bad gradient buffers");
+    GS3_CHECK_HIP(launch_accumulate(dst, src, count, (hipStream_t)stream));
     return GS3_OK;
 }
 

@@ -96,7 +96,7 @@ hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws,
                          float* num_den, float* T, hipStream_t st);
 hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
 hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
-hipError_t launch_shadow_resolve(const Layout& L, const float* num_den, float* T, hipStream_t st);
+hipError_t launch_shadow_resolve(const Layout& L, const void* ws, const float* num_den, float* T, hipStream_t st);
 struct ShadeParams {
     float light[3];
     float eye[3];
@@ -136,6 +136,12 @@ hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const V
                               const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
                               hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
+hipError_t launch_write_status(const Layout& L, const void* ws, long long generation, int64_t* status_dev,
+                               hipStream_t st);
+int64_t l1_chunks(int64_t count);
+hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
+                          float* grad, double* partial, hipStream_t st);
+hipError_t launch_accumulate(float* dst, const float* src, int64_t count, hipStream_t st);
 hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, int32_t* end, int32_t* ids,
                                uint64_t* keys, hipStream_t st);
 hipError_t launch_count_hits(const gs3_consts& k, const Layout& L, const void* ws, int stop_early,

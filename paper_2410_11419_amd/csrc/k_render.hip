@@ -20,6 +20,7 @@ struct RenderArgs {
     const float4* rec2;   // {thr, hx, hy, p}
     const float4* col0;   // {c.r, c.g, c.b, T'}
     const float4* col1;   // {r.r, r.g, r.b, 0}
+    const ViewHeader* hdr;
     uint32_t n;
     int width, height, tiles_x;
     float alpha_max, t_min;
@@ -102,6 +103,12 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
         }
         __syncthreads();
     }
+    if (a.hdr->overflow) {
+        // the binning overflowed its pair capacity and left every list
+        // empty: mark the pixels instead of writing an empty-scene image
+        const float nan = __builtin_nanf("");
+        S0 = S1 = S2 = Sh = R0 = R1 = R2 = T = nan;
+    }
     if (inside) {
         const int64_t hw = (int64_t)a.width * a.height;
         const int64_t p = (int64_t)py * a.width + px;
@@ -131,6 +138,7 @@ hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, c
     a.rec2 = at<float4>(ws, L.rec2);
     a.col0 = at<float4>(ws, L.col0);
     a.col1 = at<float4>(ws, L.col1);
+    a.hdr = at<ViewHeader>(ws, L.hdr);
     a.n = (uint32_t)L.n;
     a.width = L.width;
     a.height = L.height;

@@ -407,10 +407,16 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     }
 }
 
+// T = num / den (1 where den = 0). A binning that overflowed its pair
+// capacity left the tile lists empty, so num is missing every term: T is
+// then NaN, not a plausible value.
 __global__ __launch_bounds__(256) void k_shadow_finish(const float* __restrict__ num, const float* __restrict__ den,
-                                                        float* __restrict__ T, int n) {
+                                                        const ViewHeader* __restrict__ hdr, float* __restrict__ T,
+                                                        int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) T[i] = den[i] > 0.f ? num[i] / den[i] : 1.f;
+    if (i >= n) return;
+    const float t = den[i] > 0.f ? num[i] / den[i] : 1.f;
+    T[i] = hdr->overflow ? __builtin_nanf("") : t;
 }
 
 static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* ws, float* num_den) {
@@ -452,10 +458,10 @@ hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* w
     return hipGetLastError();
 }
 
-hipError_t launch_shadow_resolve(const Layout& L, const float* num_den, float* T, hipStream_t st) {
+hipError_t launch_shadow_resolve(const Layout& L, const void* ws, const float* num_den, float* T, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, num_den,
-                       num_den + L.n, T, (int)L.n);
+                       num_den + L.n, at<ViewHeader>(ws, L.hdr), T, (int)L.n);
     return hipGetLastError();
 }
 
@@ -463,7 +469,7 @@ hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws, f
                          hipStream_t st) {
     hipError_t e = launch_shadow_den(k, L, ws, num_den, st);
     if (e == hipSuccess) e = launch_shadow_num(k, L, ws, num_den, st);
-    if (e == hipSuccess) e = launch_shadow_resolve(L, num_den, T, st);
+    if (e == hipSuccess) e = launch_shadow_resolve(L, ws, num_den, T, st);
     return e;
 }
 

@@ -428,6 +428,27 @@ __global__ __launch_bounds__(1024) void k_tile_order(int2* __restrict__ ranges, 
     for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
 }
 
+// The binning's outcome into the caller's host-pinned status word (see
+// gs3_viewbuf.status): (generation mod 2^24) << 40 | overflow << 39 |
+// required pairs, one 64-bit store, made visible to the host at once.
+__global__ __launch_bounds__(64) void k_write_status(const ViewHeader* __restrict__ hdr, long long generation,
+                                                      unsigned long long* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long req = hdr->required_pairs;
+    const unsigned long long req39 = req < (1ull << 39) ? req : (1ull << 39) - 1ull;
+    const unsigned long long v = ((unsigned long long)(generation & 0xFFFFFF) << 40) |
+                                 ((unsigned long long)(hdr->overflow ? 1u : 0u) << 39) | req39;
+    __hip_atomic_store(status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
+hipError_t launch_write_status(const Layout& L, const void* ws, long long generation, int64_t* status_dev,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_write_status, dim3(1), dim3(64), 0, st, at<ViewHeader>(ws, L.hdr), generation,
+                       reinterpret_cast<unsigned long long*>(status_dev));
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, value, count);

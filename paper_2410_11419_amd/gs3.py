@@ -38,7 +38,9 @@ EXPORTED = [
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
+    "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
 ]
+GS3_VIEW_PENDING, GS3_VIEW_OK, GS3_VIEW_OVERFLOW = 0, 1, 2
 
 
 class gs3_consts(C.Structure):
@@ -65,7 +67,7 @@ class gs3_mlp(C.Structure):
 
 class gs3_viewbuf(C.Structure):
     _fields_ = [("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("n", C.c_int64), ("width", C.c_int32),
-                ("height", C.c_int32), ("pair_capacity", C.c_int64)]
+                ("height", C.c_int32), ("pair_capacity", C.c_int64), ("status", C.c_void_p)]
 
 
 class gs3_images(C.Structure):
@@ -116,6 +118,12 @@ def _load():
                                           C.c_void_p]),
         "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
                                  P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
+        "gs3_view_poll": (C.c_int, [P(gs3_viewbuf), P(C.c_int32), P(C.c_int64)]),
+        "gs3_l1_loss_workspace_size": (C.c_int, [C.c_int64, P(C.c_size_t)]),
+        "gs3_l1_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+        "gs3_grads_clear": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+        "gs3_grads_accumulate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -228,16 +236,21 @@ class DeviceScene:
 
 
 class ViewBuffer:
-    """Device workspace of one view (projected splats, sort buffers, lists)."""
+    """Device workspace of one view (projected splats, sort buffers, lists)
+    and its host-pinned binning status block (see gs3_viewbuf.status), which
+    reports a pair-capacity overflow without a stream synchronisation."""
 
-    def __init__(self, n: int, width: int, height: int, pair_capacity: int, device="cuda"):
+    def __init__(self, n: int, width: int, height: int, pair_capacity: int, device="cuda",
+                 status: bool = True):
         size = C.c_size_t()
         _check(_lib.gs3_view_workspace_size(n, width, height, pair_capacity, C.byref(size)),
                "gs3_view_workspace_size")
         self.storage = torch.empty(size.value + 256, dtype=torch.uint8, device=device)
         base = self.storage.data_ptr()
         off = (-base) % 256
-        self.vb = gs3_viewbuf(C.c_void_p(base + off), size.value, n, width, height, pair_capacity)
+        self.status = torch.zeros(2, dtype=torch.int64, pin_memory=True) if status else None
+        self.vb = gs3_viewbuf(C.c_void_p(base + off), size.value, n, width, height, pair_capacity,
+                              C.c_void_p(self.status.data_ptr()) if status else None)
         self.n, self.width, self.height, self.capacity = n, width, height, pair_capacity
         self.tiles_x = (width + 15) // 16
         self.tiles_y = (height + 15) // 16
@@ -277,6 +290,15 @@ def gs3_view_pair_count(vb: ViewBuffer) -> int:
         raise e
     _check(st, "gs3_view_pair_count")
     return int(n.value)
+
+
+def gs3_view_poll(vb: ViewBuffer):
+    """(state, required pairs) of the latest binning from the status block,
+    without touching the stream: state is GS3_VIEW_PENDING (not finished on
+    the device yet; required = -1), GS3_VIEW_OK or GS3_VIEW_OVERFLOW."""
+    st, req = C.c_int32(), C.c_int64()
+    _check(_lib.gs3_view_poll(C.byref(vb.vb), C.byref(st), C.byref(req)), "gs3_view_poll")
+    return int(st.value), int(req.value)
 
 
 def gs3_view_lists(vb: ViewBuffer):
@@ -361,6 +383,39 @@ def gs3_render_shaded(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T:
                                   _stream()), "gs3_render_shaded")
 
 
+def l1_workspace(count: int, device="cuda") -> torch.Tensor:
+    size = C.c_size_t()
+    _check(_lib.gs3_l1_loss_workspace_size(int(count), C.byref(size)), "gs3_l1_loss_workspace_size")
+    return torch.empty(size.value + 256, dtype=torch.uint8, device=device)
+
+
+def gs3_l1_loss(pred: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor,
+                grad: Optional[torch.Tensor], ws: torch.Tensor):
+    """loss[0] = scale * sum |pred - target|; grad = scale * sign(pred - target)
+    (if given). All float32 device tensors with pred's element count."""
+    count = pred.numel()
+    if target.numel() != count or (grad is not None and grad.numel() != count):
+        raise ValueError("pred, target and grad must have the same number of elements")
+    for t in (pred, target, loss) + ((grad,) if grad is not None else ()):
+        if t.dtype != torch.float32:
+            raise ValueError("gs3_l1_loss takes float32 tensors")
+    wsp, wsb = _aligned(ws)
+    _check(_lib.gs3_l1_loss(_ptr(pred), _ptr(target), count, float(scale), _ptr(loss), _ptr(grad), wsp, wsb,
+                            _stream()), "gs3_l1_loss")
+
+
+def gs3_grads_clear(g: torch.Tensor):
+    if g.dtype != torch.float32:
+        raise ValueError("gradients are float32")
+    _check(_lib.gs3_grads_clear(_ptr(g), g.numel(), _stream()), "gs3_grads_clear")
+
+
+def gs3_grads_accumulate(dst: torch.Tensor, src: torch.Tensor):
+    if dst.dtype != torch.float32 or src.dtype != torch.float32 or dst.numel() != src.numel():
+        raise ValueError("gradient sets must be float32 of one size")
+    _check(_lib.gs3_grads_accumulate(_ptr(dst), _ptr(src), dst.numel(), _stream()), "gs3_grads_accumulate")
+
+
 class DeviceGrads:
     """Gradient tensors shaped like a DeviceScene's (zeroed), for
     gs3_render_backward. They are views of one flat buffer (each slice
@@ -377,18 +432,19 @@ class DeviceGrads:
         for v in like:
             offs.append(total)
             total += (v.numel() + 63) // 64 * 64
-        self.flat = torch.zeros(max(total, 1), dtype=torch.float32, device=like[0].device)
+        self.flat = torch.empty(max(total, 1), dtype=torch.float32, device=like[0].device)
+        gs3_grads_clear(self.flat)
         views = iter(self.flat[o:o + v.numel()].view(v.shape) for o, v in zip(offs, like))
         self.t = {nm: next(views) for nm in scene.t}
         self.phi, self.psi = [None if m is None else [(next(views), next(views)) for _ in m] for m in mlps]
 
     def zero_(self) -> "DeviceGrads":
-        self.flat.zero_()
+        gs3_grads_clear(self.flat)
         return self
 
     def add_(self, other: "DeviceGrads") -> "DeviceGrads":
         """Adds another set of the same scene and MLP configuration."""
-        self.flat.add_(other.flat)
+        gs3_grads_accumulate(self.flat, other.flat)
         return self
 
     def c_struct(self) -> gs3_grads:
@@ -598,8 +654,17 @@ class Renderer:
         return grads
 
     def overflowed(self) -> bool:
-        """True if any view's last binning exceeded its capacity (syncs)."""
+        """True if any view's last binning exceeded its capacity. Read from
+        the views' status blocks without a synchronisation once their
+        binnings have finished; a binning still pending on the device is
+        waited for (gs3_view_pair_count)."""
         for vb in self.vbs.values():
+            if vb.status is not None:
+                state, _ = gs3_view_poll(vb)
+                if state == GS3_VIEW_OVERFLOW:
+                    return True
+                if state == GS3_VIEW_OK:
+                    continue
             try:
                 gs3_view_pair_count(vb)
             except Gs3Error as e:

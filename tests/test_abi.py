@@ -60,3 +60,84 @@ def test_host_only_entry_points():
     assert gs3._lib.gs3_view_pair_count(C.byref(vb), C.byref(n), None) == gs3.GS3_WORKSPACE_TOO_SMALL
     vb = gs3.gs3_viewbuf(C.c_void_p(257), 1 << 30, 100, 64, 64, 1000)  # misaligned
     assert gs3._lib.gs3_view_pair_count(C.byref(vb), C.byref(n), None) == gs3.GS3_INVALID_ARG
+
+
+def _status_block(generation, overflow, required):
+    """A status block as the device leaves it after binning `generation`."""
+    blk = (C.c_int64 * 2)()
+    blk[0] = generation
+    blk[1] = ((generation & 0xFFFFFF) << 40) | ((1 if overflow else 0) << 39) | required
+    return blk
+
+
+def test_status_block_reports_overflow_without_the_device():
+    """A workspace whose status block records a completed, overflowed binning
+    is refused by every call that would read its lists, before anything is
+    enqueued (these calls run here without a GPU); a binning still pending
+    (generation ahead of the device's word) or one within capacity is not."""
+    from paper_2410_11419_amd import gs3
+    size = C.c_size_t()
+    assert gs3._lib.gs3_view_workspace_size(100, 64, 64, 1000, C.byref(size)) == 0
+    k = gs3.default_consts()
+    blk = _status_block(3, True, 12345)
+    vb = gs3.gs3_viewbuf(C.c_void_p(256), size.value, 100, 64, 64, 1000, C.cast(blk, C.c_void_p))
+    st, req = C.c_int32(), C.c_int64()
+    assert gs3._lib.gs3_view_poll(C.byref(vb), C.byref(st), C.byref(req)) == 0
+    assert (st.value, req.value) == (gs3.GS3_VIEW_OVERFLOW, 12345)
+    fake = C.c_void_p(512)
+    calls = {
+        "gs3_shadow_splat": lambda: gs3._lib.gs3_shadow_splat(C.byref(k), C.byref(vb), fake, fake, None),
+        "gs3_shadow_den": lambda: gs3._lib.gs3_shadow_den(C.byref(k), C.byref(vb), fake, None),
+        "gs3_shadow_num": lambda: gs3._lib.gs3_shadow_num(C.byref(k), C.byref(vb), fake, None),
+        "gs3_shadow_resolve": lambda: gs3._lib.gs3_shadow_resolve(C.byref(vb), fake, fake, None),
+        "gs3_view_lists": lambda: gs3._lib.gs3_view_lists(C.byref(vb), None, None, None, None, None),
+        "gs3_view_count_hits": lambda: gs3._lib.gs3_view_count_hits(C.byref(k), C.byref(vb), 0, C.c_void_p(1024),
+                                                                     None),
+    }
+    for name, call in calls.items():
+        assert call() == gs3.GS3_PAIR_CAPACITY_EXCEEDED, name
+        assert b"12345" in gs3._lib.gs3_last_error(), name
+    # the camera side: gs3_render is refused the same way
+    cam = gs3.gs3_view()
+    cam.eye[0], cam.width, cam.height, cam.fov = 4.0, 64, 64, 0.7
+    scene = gs3.gs3_scene()
+    scene.n, scene.k = 100, 0
+    for nm in ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo", "feat"):
+        setattr(scene, nm, 512)
+    lp = (C.c_double * 3)(0.0, 4.0, 0.0)
+    im = gs3.gs3_images(*([512] * 7))
+    assert gs3._lib.gs3_render(C.byref(scene), C.byref(cam), C.byref(lp), C.byref(k), fake, None, None, C.byref(vb),
+                               C.byref(im), None) == gs3.GS3_PAIR_CAPACITY_EXCEEDED
+    # a newer binning that has not finished yet: nothing is known, nothing refused
+    blk[0] = 4
+    assert gs3._lib.gs3_view_poll(C.byref(vb), C.byref(st), C.byref(req)) == 0
+    assert (st.value, req.value) == (gs3.GS3_VIEW_PENDING, -1)
+    # a binning within capacity
+    ok = _status_block(7, False, 999)
+    vb.status = C.cast(ok, C.c_void_p)
+    assert gs3._lib.gs3_view_poll(C.byref(vb), C.byref(st), C.byref(req)) == 0
+    assert (st.value, req.value) == (gs3.GS3_VIEW_OK, 999)
+    # never binned
+    fresh = (C.c_int64 * 2)()
+    vb.status = C.cast(fresh, C.c_void_p)
+    assert gs3._lib.gs3_view_poll(C.byref(vb), C.byref(st), C.byref(req)) == 0
+    assert st.value == gs3.GS3_VIEW_PENDING
+    vb.status = None
+    assert gs3._lib.gs3_view_poll(C.byref(vb), C.byref(st), C.byref(req)) == gs3.GS3_INVALID_ARG
+
+
+def test_loss_and_gradient_set_argument_checks():
+    from paper_2410_11419_amd import gs3
+    size = C.c_size_t()
+    assert gs3._lib.gs3_l1_loss_workspace_size(0, C.byref(size)) == 0 and size.value >= 8
+    assert gs3._lib.gs3_l1_loss_workspace_size(3 * 800 * 800, C.byref(size)) == 0
+    assert size.value >= 8 * ((3 * 800 * 800 + 8191) // 8192) and size.value % 256 == 0
+    assert gs3._lib.gs3_l1_loss_workspace_size(-1, C.byref(size)) == gs3.GS3_INVALID_ARG
+    p = C.c_void_p(256)
+    assert gs3._lib.gs3_l1_loss(None, p, 10, 1.0, p, None, p, 1 << 20, None) == gs3.GS3_INVALID_ARG
+    assert gs3._lib.gs3_l1_loss(p, p, -1, 1.0, p, None, p, 1 << 20, None) == gs3.GS3_INVALID_ARG
+    assert gs3._lib.gs3_l1_loss(p, p, 10, 1.0, p, None, C.c_void_p(260), 1 << 20, None) == gs3.GS3_INVALID_ARG
+    assert gs3._lib.gs3_l1_loss(p, p, 1 << 24, 1.0, p, None, p, 8, None) == gs3.GS3_WORKSPACE_TOO_SMALL
+    assert gs3._lib.gs3_grads_clear(None, 5, None) == gs3.GS3_INVALID_ARG
+    assert gs3._lib.gs3_grads_clear(p, -1, None) == gs3.GS3_INVALID_ARG
+    assert gs3._lib.gs3_grads_accumulate(p, None, 5, None) == gs3.GS3_INVALID_ARG
