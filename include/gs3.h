@@ -396,6 +396,19 @@ int gs3_l1_loss_workspace_size(int64_t count, size_t* bytes);
 int gs3_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                 float* dL_dpred, void* ws, size_t ws_bytes, gs3_stream_t stream);
 
+/* gs3_l1_loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, same arguments without the workspace, same results bit
+ * for bit. The partial sums live in a 32 KiB array inside the library, one
+ * per device, held until the process ends; nothing is allocated per call.
+ * count is limited to 33,554,432 elements (4096 chunks of 8192): larger
+ * counts return GS3_INVALID_ARG. Every call on one device shares that
+ * array, so calls that overlap on a device (concurrent streams, or threads
+ * without ordering) race and must not be issued; calls ordered on one
+ * stream are safe, each fully rewriting the partial sums it reads. */
+int gs3_l1_loss_noalloc(const float* pred, const float* target, int64_t count, float scale, float* loss,
+                        float* dL_dpred, gs3_stream_t stream);
+
 /* Gradient-set upkeep of a training step (Sec. 4.4): gs3_render_backward
  * adds into its gradients, so a step clears them first, and views whose
  * gradients were accumulated in separate sets (to run concurrently) are

@@ -23,6 +23,8 @@ static int fail(int status, const char* fmt, ...) {
     return status;
 }
 
+int set_error(int status, const char* msg) { return fail(status, "%s", msg); }
+
 static int hip_fail(hipError_t e, const char* where) {
     return fail(GS3_HIP_ERROR, "%s: %s", where, hipGetErrorString(e));
 }

@@ -49,6 +49,10 @@ struct Layout {
     size_t total = 0;
 };
 
+// Records `msg` as the calling thread's last error (gs3_last_error) and
+// returns `status`.
+int set_error(int status, const char* msg);
+
 // Compute the workspace layout; returns false on invalid sizes.
 bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Layout* L);
 

@@ -8,6 +8,8 @@
 // chunk order. The same input therefore gives the same float64 sum on every
 // run and for every caller of these kernels. Bound by HBM: 8 B read and (with
 // the gradient) 4 B written per element.
+#include <mutex>
+
 #include "gs3_internal.h"
 
 namespace gs3 {
@@ -99,4 +101,53 @@ hipError_t launch_accumulate(float* dst, const float* src, int64_t count, hipStr
     return hipGetLastError();
 }
 
+// ------------------------------------------------ no-allocation variant
+//
+// gs3_l1_loss_noalloc keeps its partial sums in this file-scope array
+// instead of a caller workspace. Each device the library runs on holds its
+// own copy until the process ends. Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+constexpr int64_t kL1NoAllocChunks = 4096;   // 32 KiB: up to 4096 * 8192 = 33,554,432 elements
+static __device__ __align__(256) double scratch[kL1NoAllocChunks];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+static hipError_t scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace gs3
+
+using namespace gs3;
+
+extern "C" int gs3_l1_loss_noalloc(const float* pred, const float* target, int64_t count, float scale, float* loss,
+                                   float* dL_dpred, gs3_stream_t stream) {
+    if (count < 0) return set_error(GS3_INVALID_ARG, "count < 0");
+    if (!loss || (count > 0 && (!pred || !target))) return set_error(GS3_INVALID_ARG, "pred / target / loss is NULL");
+    if (l1_chunks(count) > kL1NoAllocChunks)
+        return set_error(GS3_INVALID_ARG,
+                         "count exceeds the no-allocation scratch (at most 33554432 elements; use gs3_l1_loss)");
+    double* partial = nullptr;
+    hipError_t e = scratch_address(&partial);
+    if (e == hipSuccess) e = launch_l1_loss(pred, target, count, scale, loss, dL_dpred, partial, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(GS3_HIP_ERROR, hipGetErrorString(e));
+    return GS3_OK;
+}

@@ -39,6 +39,7 @@ EXPORTED = [
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
     "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
+    "gs3_l1_loss_noalloc",
 ]
 GS3_VIEW_PENDING, GS3_VIEW_OK, GS3_VIEW_OVERFLOW = 0, 1, 2
 
@@ -122,6 +123,8 @@ def _load():
         "gs3_l1_loss_workspace_size": (C.c_int, [C.c_int64, P(C.c_size_t)]),
         "gs3_l1_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_size_t, C.c_void_p]),
+        "gs3_l1_loss_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
         "gs3_grads_clear": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "gs3_grads_accumulate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     }
@@ -402,6 +405,18 @@ def gs3_l1_loss(pred: torch.Tensor, target: torch.Tensor, scale: float, loss: to
     wsp, wsb = _aligned(ws)
     _check(_lib.gs3_l1_loss(_ptr(pred), _ptr(target), count, float(scale), _ptr(loss), _ptr(grad), wsp, wsb,
                             _stream()), "gs3_l1_loss")
+
+
+def gs3_l1_loss_noalloc(pred: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor,
+                        grad: Optional[torch.Tensor]):
+    """gs3_l1_loss without a workspace (the library's own per-device
+    scratch; at most 33,554,432 elements; calls on one device must not
+    overlap)."""
+    count = pred.numel()
+    if target.numel() != count or (grad is not None and grad.numel() != count):
+        raise ValueError("pred, target and grad must have the same number of elements")
+    _check(_lib.gs3_l1_loss_noalloc(_ptr(pred), _ptr(target), count, float(scale), _ptr(loss), _ptr(grad),
+                                    _stream()), "gs3_l1_loss_noalloc")
 
 
 def gs3_grads_clear(g: torch.Tensor):
