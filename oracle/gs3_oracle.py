@@ -36,7 +36,9 @@ __all__ = [
     "focal", "project", "tile_rects", "bin_tiles", "pixel_entries",
     "shadow_pass", "shadow_accumulate", "shadow_values", "splat_extent", "diffuse", "angular_gaussian",
     "lobe_frame", "shade", "mlp_forward", "camera_pass", "render",
-    "render_images", "sigmoid", "l1_loss",
+    "render_images", "sigmoid", "l1_loss", "hit_threshold", "hit_margin", "transmittance_relerr",
+    "AMB_BUDGET", "HIT_KAPPA", "pair_key", "ssim_window", "ssim_map", "dssim_loss", "adam_step",
+    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "LOSS_LAMBDA", "CANDIDATE_CUT",
 ]
 
 DT = torch.float64
@@ -278,22 +280,86 @@ def bin_tiles(ix, iy, rx, ry, depth, W: int, H: int, tile: int = 16):
 
 # -------------------------------------------------------- per-pixel entries
 
-# Error model of the float32 evaluation, used only to flag outputs whose
-# value hangs on a threshold decision (cut-off, alpha minimum, early stop)
-# that a float32 evaluation may take differently from this float64 one.
-# (Depth order and the shadow-bias test are decided on float32 keys in
-# float32 arithmetic on both sides, so they need no flag.) It assumes splat
-# centres rounded once to float32 from an exact evaluation, a pixel offset
-# formed relative to a nearby origin (error ~ 2e-7 (|d| + 32) px), and
-# per-pixel arithmetic in float32.
-_POS_REL = 2e-7          # error of a pixel offset d, per px of |d| + 32
-_POW_REL = 4e-6          # relative error of power, alpha
-_AMB_T = 2e-5            # relative margin on the early-stop test
+# Error model of a float32 evaluation, used only to flag outputs whose value
+# hangs on a threshold decision (cut-off, alpha minimum, early stop) that a
+# float32 evaluation may take differently from this float64 one. (Depth
+# order and the shadow-bias test are decided on float32 keys in float32
+# arithmetic on both sides, so they need no flag.)
+#
+# The float32 evaluation it describes: splat centre, conic and opacity
+# rounded once to float32 from an exact value; the pixel offset d formed
+# relative to an origin within 16 px of the pixel (a tile corner); the
+# quadratic power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 and the threshold
+# p = min(cutoff, ln(opacity / alpha_min)) each evaluated in a handful of
+# float32 operations. With u = 2^-24 (float32 unit roundoff):
+#   - each conic coefficient carries 2 roundings and each quadratic term up
+#     to 5 more: at most 3.5 u S, S = |a| dx^2 + 2 |b dx dy| + |c| dy^2
+#     (S, not |power|: the terms can cancel for elongated splats);
+#   - the offset error is at most u (2 |d| + 17) per axis (the centre's
+#     fractional part, the offset from the origin, the difference), times
+#     the gradient |conic d| of the power;
+#   - the threshold: the opacity ratio, a logarithm within 2 ulp and the
+#     scaling, at most u (4 + 6 p).
+# HIT_KAPPA widens the sum by half. A float32 simulation of this evaluation
+# (three operation orders, 10^7 pairs near the threshold, elongated splats
+# included) found every decision flip inside the margin and the largest
+# error at 0.73 of the unwidened sum (tests/test_oracle_pins.py).
+_U32 = 2.0 ** -24
+HIT_KAPPA = 1.5
 AMB_BUDGET = 5e-5        # an output is ambiguous when it could move this much
 
 
+def CANDIDATE_CUT(cutoff: float) -> float:
+    """Power threshold of the (pixel, splat) pairs the oracle considers:
+    1 % beyond the cut-off, far wider than the float32 error margin."""
+    return cutoff * (1 + 1e-2) + 1e-2
+
+
+def hit_threshold(opacity: torch.Tensor, consts: Consts) -> torch.Tensor:
+    """p with hit <=> power >= -p: min(cutoff, ln(opacity / alpha_min))
+    (the cut-off and the alpha >= alpha_min test of Sec. 3 in one bound)."""
+    p = torch.full_like(opacity, consts.cutoff)
+    if consts.alpha_min > 0:
+        p = torch.minimum(p, torch.log(opacity / consts.alpha_min))
+    return p
+
+
+def hit_margin(dx, dy, ca, cb, cc, p) -> torch.Tensor:
+    """Bound on how far a float32 evaluation of power + p can fall from the
+    exact value for pixel offset (dx, dy), conic (ca, cb, cc) and threshold
+    p (see the error model above); a pair whose |power + p| is within it is
+    a hit or a miss depending on rounding."""
+    S = ca.abs() * dx * dx + 2 * (cb * dx * dy).abs() + cc.abs() * dy * dy
+    gx = (ca * dx + cb * dy).abs()
+    gy = (cb * dx + cc * dy).abs()
+    pos = gx * (2 * dx.abs() + 17.0) + gy * (2 * dy.abs() + 17.0)
+    return HIT_KAPPA * _U32 * (3.5 * S + pos + 4.0 + 6.0 * p.abs())
+
+
+def transmittance_relerr(alpha_full, hit, margin, consts: Consts) -> torch.Tensor:
+    """Per hit, a bound on the relative float32 error of its factor
+    (1 - alpha) in a transmittance product, plus the product's own
+    rounding: alpha = min(alpha_max, opacity exp(power)) carries the power
+    error (margin) and a few roundings (exp, the opacity, the product),
+    which (1 - alpha) amplifies by alpha / (1 - alpha); a clamped alpha is
+    exact up to the float32 rounding of alpha_max."""
+    am32 = float(np.float32(consts.alpha_max))
+    clamped = alpha_full >= consts.alpha_max
+    one_m = (1.0 - alpha_full).clamp_min(1e-30)
+    r_free = alpha_full * (margin / HIT_KAPPA + 4 * _U32) / one_m
+    r_clamp = abs(am32 - consts.alpha_max) / one_m
+    r = torch.where(clamped, r_clamp, r_free) + 3 * _U32
+    return torch.where(hit, HIT_KAPPA * r, torch.zeros_like(r))
+
+
+def pair_key(gid, px, py, W: int, H: int):
+    """Integer name of the pair (Gaussian gid, pixel (px, py)) of a W x H
+    view: gid * W * H + py * W + px."""
+    return gid * (W * H) + py * W + px
+
+
 def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
-                  pixels: Optional[torch.Tensor] = None, rows=None):
+                  pixels: Optional[torch.Tensor] = None, rows=None, flips=None):
     """Every (pixel, Gaussian) pair whose power can reach the cut-off,
     grouped per pixel and sorted by (depth, id): a padded [P, L] layout.
 
@@ -304,7 +370,13 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
     are kept as non-hits so that threshold ambiguity can be measured.
 
     ``rows`` = (y0, y1) selects a band of full rows, else ``pixels`` is a
-    1-D tensor of flat pixel indices (y*W + x); default all pixels."""
+    1-D tensor of flat pixel indices (y*W + x); default all pixels.
+
+    ``flips`` (optional 1-D int64 tensor of pair keys, see ``pair_key``)
+    inverts the hit decision of those pairs. It is meant for pairs the
+    error model flags: their decision is a rounding matter, so a float32
+    evaluation may take it either way, and a comparison supplies the
+    decision it observed."""
     u, v, conic, cov2, depth, valid = (proj["u"], proj["v"], proj["conic"],
                                        proj["cov2"], proj["depth"], proj["valid"])
     n = u.shape[0]
@@ -323,10 +395,12 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
         pix_set = torch.full(((yhi - ylo) * (xhi - xlo),), -1, dtype=torch.int64)
         pix_set[(py_all - ylo) * (xhi - xlo) + (px_all - xlo)] = torch.arange(pixels.numel())
     with torch.no_grad():
-        # candidate rectangle: the bounding box of the ellipse power >= -cut
-        # (half-widths sqrt(2 cut Sigma'_xx), sqrt(2 cut Sigma'_yy)), with a
-        # slightly larger cut so near misses are seen.
-        cut = consts.cutoff * (1 + 1e-3) + 1e-3
+        # candidates: the pixels of the ellipse power >= -cut, found through
+        # its bounding box (half-widths sqrt(2 cut Sigma'_xx), sqrt(2 cut
+        # Sigma'_yy)); the cut is 1 % beyond the cut-off so that near misses
+        # within the float32 error margin are seen. Pairs outside that
+        # ellipse can neither hit nor be flagged and are dropped.
+        cut = CANDIDATE_CUT(consts.cutoff)
         uu, vv = u.detach(), v.detach()
         if math.isinf(cut):
             cx0 = torch.full((n,), xlo, dtype=torch.int64)
@@ -357,6 +431,13 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
             keep = pidx >= 0
             gid, px, py, pidx = gid[keep], px[keep], py[keep], pidx[keep]
             n_pix = pixels.numel()
+        if not math.isinf(cut):
+            ddx = (px.to(DT) + 0.5) - uu[gid]
+            ddy = (py.to(DT) + 0.5) - vv[gid]
+            cg = conic.detach()[gid]
+            pw0 = -0.5 * (cg[:, 0] * ddx * ddx + 2 * cg[:, 1] * ddx * ddy + cg[:, 2] * ddy * ddy)
+            keep = pw0 >= -cut
+            gid, px, py, pidx = gid[keep], px[keep], py[keep], pidx[keep]
         # sort by (pixel, depth key, id): pairs come in id order, then two
         # stable sorts. The depth key is the depth rounded to float32 (the
         # method's sort key); the order is a discrete decision, so it is
@@ -379,14 +460,18 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
     alpha_full = torch.clamp(opacity[gid] * beta, max=consts.alpha_max)
     with torch.no_grad():
         hit = (power >= -consts.cutoff) & (alpha_full >= consts.alpha_min)
-        # threshold ambiguity of this pair (power cut-off or alpha minimum)
-        gx = (ca * dx + cb * dy).abs()
-        gy = (cb * dx + cc * dy).abs()
-        pos_err = _POS_REL * (dx.abs() + dy.abs() + 32.0)
-        pmarg = _POW_REL * (1.0 + power.abs()) + pos_err * (gx + gy)
-        amb = (power + consts.cutoff).abs() <= pmarg
-        if consts.alpha_min > 0:
-            amb = amb | ((alpha_full - consts.alpha_min).abs() <= (pmarg + _POW_REL) * alpha_full)
+        key = pair_key(gid, px, py, W, H)
+        if flips is not None and len(flips):
+            hit = hit ^ torch.isin(key, torch.as_tensor(flips, dtype=torch.int64))
+        # threshold ambiguity of this pair (the cut-off or the alpha minimum,
+        # both power >= -p): within the float32 error margin of -p
+        pw, op = power.detach(), opacity.detach()[gid]
+        p_thr = hit_threshold(op, consts)
+        fin = torch.isfinite(p_thr)          # no threshold at all without a cut-off and alpha minimum
+        p_fin = torch.where(fin, p_thr, torch.zeros_like(p_thr))
+        marg = hit_margin(dx.detach(), dy.detach(), ca.detach(), cb.detach(), cc.detach(), p_fin)
+        amb = fin & ((pw + p_fin).abs() <= marg)
+        t_rel = transmittance_relerr(alpha_full.detach(), hit, marg, consts)
 
     def pad(x, fill):
         out = torch.full((n_pix, max(L, 1)), fill, dtype=x.dtype)
@@ -402,6 +487,9 @@ def pixel_entries(proj, W: int, H: int, opacity: torch.Tensor, consts: Consts,
         "alpha_full_pad": pad(alpha_full.detach(), 0.0),
         "beta_pad": pad(torch.where(hit, beta, torch.zeros_like(beta)), 0.0),
         "beta_full_pad": pad(beta.detach(), 0.0),
+        "t_relerr_pad": pad(t_rel, 0.0),
+        "key_pad": pad(key, -1),
+        "marg_pad": pad(marg, 0.0),
     }
 
 
@@ -414,7 +502,8 @@ def _excl_prefix_product(x: torch.Tensor) -> torch.Tensor:
 # ------------------------------------------------------------ shadow pass
 
 def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
-                band_rows: int = 8, pixels=None):
+                band_rows: int = 8, pixels=None, flips=None, amb_keys: Optional[list] = None,
+                pair_out: Optional[list] = None, den_err: Optional[torch.Tensor] = None):
     """Second splatting (Sec. 4.2, Fig. 3) over the light image.
 
     Every light pixel m is one shadow ray; its hits are sorted by distance to
@@ -425,7 +514,15 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
     float32, as the kernel does); then num_j += beta_jm T_m(j) and
     den_j += beta_jm. Returns num, den and the
     per-Gaussian ambiguity bound (an upper bound on how far T_j could move
-    if float32 took a threshold decision the other way)."""
+    if float32 took a threshold decision the other way). ``flips`` inverts
+    the hit decision of the given pair keys (``pixel_entries``); the keys of
+    the pairs the error model flags are appended to ``amb_keys`` when it is
+    a list, and every hit's (Gaussian, flat pixel, beta T_m(j), beta) to
+    ``pair_out`` when that is a list (its terms of num and den). When
+    ``den_err`` (a float64 tensor [n]) is given, each Gaussian's bound on the
+    float32 error of its den terms is added to it: beta times the error
+    margin of the pair's power (a float32 beta = exp(power) moves by that
+    relative amount)."""
     W, H = light_view.width, light_view.height
     n = opacity.shape[0]
     num = torch.zeros(n, dtype=DT)
@@ -439,9 +536,11 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
     for kind, arg in chunks:
         e = pixel_entries(proj_l, W, H, opacity, consts,
                           rows=arg if kind == "rows" else None,
-                          pixels=arg if kind == "pix" else None)
+                          pixels=arg if kind == "pix" else None, flips=flips)
         if e["L"] == 0:
             continue
+        if amb_keys is not None:
+            amb_keys.append(e["key_pad"][e["amb_pad"]])
         alpha, beta, dist = e["alpha_pad"], e["beta_pad"], e["depth_pad"]
         hit, gidp = e["hit_pad"], e["gid_pad"]
         prefix = _excl_prefix_product(1.0 - alpha)                  # [P, L+1]
@@ -450,6 +549,11 @@ def shadow_pass(proj_l, light_view, opacity: torch.Tensor, consts: Consts,
         thr = (dist.to(torch.float32) - torch.tensor(b, dtype=torch.float32)).to(DT)
         cnt = torch.searchsorted(dist.contiguous(), thr.contiguous(), right=False)
         Tm = torch.gather(prefix, 1, cnt)                           # T_m(j)
+        if pair_out is not None:
+            kp = e["key_pad"][hit]
+            pair_out.append((gidp[hit], kp % (W * H), (beta[hit] * Tm[hit]).detach(), beta[hit].detach()))
+        if den_err is not None:
+            den_err.index_add_(0, gidp[hit], (beta[hit] * e["marg_pad"][hit]).detach())
         dn, dd = shadow_accumulate(gidp[hit], beta[hit], Tm[hit], n)
         num = num + dn
         den = den + dd
@@ -571,14 +675,22 @@ def mlp_forward(layers, x: torch.Tensor) -> torch.Tensor:
 # ------------------------------------------------------------ camera pass
 
 def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts,
-                tprime_err=None, band_rows: int = 8, pixels=None):
+                tprime_err=None, band_rows: int = 8, pixels=None, flips=None, stop_flips=None,
+                amb_keys: Optional[list] = None, stop_keys: Optional[list] = None):
     """Third splatting (Sec. 3 Eq. 2-3; Sec. 4, Fig. 2) toward the camera.
 
     Per pixel, hits sorted by view depth; T starts at 1; a hit that would
     take T below t_min stops the pixel before it contributes; otherwise
     S += c alpha T, Sh += T' alpha T, R += r alpha T, T *= (1 - alpha).
     Final = S * Sh + R (background 0). Returns images [C, P] over the
-    requested pixels, T_final, and the per-pixel ambiguity bound."""
+    requested pixels, T_final, and the per-pixel ambiguity bound.
+
+    ``flips`` inverts hit decisions and ``stop_flips`` the stop decisions
+    taken at the given pair keys (a hit whose T (1 - alpha) sits within the
+    float32 error of t_min): both for decisions a float32 evaluation may
+    take either way. The keys the error model flags (hit decisions of pairs
+    reached before the pixel stops, and stop decisions) are appended to
+    ``amb_keys`` and ``stop_keys`` when they are lists."""
     W, H = cam_view.width, cam_view.height
     if pixels is not None:
         chunks = [("pix", torch.as_tensor(pixels, dtype=torch.int64))]
@@ -588,7 +700,7 @@ def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts
     for kind, arg in chunks:
         e = pixel_entries(proj_c, W, H, opacity, consts,
                           rows=arg if kind == "rows" else None,
-                          pixels=arg if kind == "pix" else None)
+                          pixels=arg if kind == "pix" else None, flips=flips)
         P = e["n_pix"]
         if e["L"] == 0:
             outS.append(torch.zeros(3, P, dtype=DT)); outSh.append(torch.zeros(P, dtype=DT))
@@ -598,7 +710,14 @@ def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts
         alpha, hit, gidp = e["alpha_pad"], e["hit_pad"], e["gid_pad"]
         prefix = _excl_prefix_product(1.0 - alpha)
         T_excl, T_incl = prefix[:, :-1], prefix[:, 1:]
-        inc = hit & (T_incl >= consts.t_min)
+        # the pixel stops before the first hit that would take T below
+        # t_min; nothing after it is blended
+        with torch.no_grad():
+            stop = hit & (T_incl.detach() < consts.t_min)
+            if stop_flips is not None and len(stop_flips):
+                stop = stop ^ (hit & torch.isin(e["key_pad"], torch.as_tensor(stop_flips, dtype=torch.int64)))
+            stopped = torch.cumsum(stop.to(torch.int64), 1) > 0
+        inc = hit & ~stopped
         w = torch.where(inc, alpha * T_excl, torch.zeros_like(alpha))
         g = gidp.clamp_min(0)
         cpix = colour[g]                       # [P, L, 3]
@@ -609,10 +728,22 @@ def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts
         with torch.no_grad():
             amb, af = e["amb_pad"], e["alpha_full_pad"]
             Te = T_excl.detach()
-            live = Te >= consts.t_min * (1 - _AMB_T)
+            # relative float32 error of the transmittance in front of and
+            # through each entry (products of the hits' factors)
+            R_incl = torch.cumsum(e["t_relerr_pad"], 1)
+            R_excl = R_incl - e["t_relerr_pad"]
+            live = Te >= consts.t_min * (1 - R_excl)
             w_thr = torch.where(amb & live, af * Te, torch.zeros_like(af)).sum(1)
-            near_stop = hit & ((T_incl.detach() - consts.t_min).abs() <= _AMB_T * consts.t_min)
+            Ti = T_incl.detach()
+            near_stop = hit & ((Ti - consts.t_min).abs() <= R_incl * Ti) & (consts.t_min > 0)
+            # only decisions the pixel reaches matter: hits before its stop
+            reached = ~(torch.cumsum(stop.to(torch.int64), 1) - stop.to(torch.int64) > 0)
+            near_stop = near_stop & reached
             w_stop = torch.where(near_stop, af * Te, torch.zeros_like(af)).sum(1)
+            if amb_keys is not None:
+                amb_keys.append(e["key_pad"][amb & live & reached])
+            if stop_keys is not None:
+                stop_keys.append(e["key_pad"][near_stop])
             cabs = torch.where(hit, colour.detach().abs().amax(1)[g], torch.zeros_like(af))
             cmax = cabs.amax(1).clamp_min(1.0)
             rmax = torch.where(hit, resid.detach().abs().amax(1)[g], torch.zeros_like(af)).amax(1)
@@ -630,7 +761,7 @@ def camera_pass(proj_c, cam_view, opacity, colour, tprime, resid, consts: Consts
 def render(scene, cam_view, light_view, consts: Consts = Consts(),
            params: Optional[Dict[str, torch.Tensor]] = None,
            phi=None, psi=None, band_rows: int = 8, cam_pixels=None,
-           light_pixels=None):
+           light_pixels=None, light_flips=None, cam_flips=None, cam_stop_flips=None):
     """The full relit render for one camera and one point light (Sec. 4).
 
     1. activate raw parameters (Eq. 1; sigmoid opacity);
@@ -640,14 +771,19 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
     4. camera splatting of c, T', r and final = S * Sh + R (Fig. 2).
 
     ``phi``/``psi`` are lists of (W, b) (arrays or tensors) or None.
-    ``params`` (from ``scene_tensors``) may carry requires_grad tensors."""
+    ``params`` (from ``scene_tensors``) may carry requires_grad tensors.
+    ``light_flips``, ``cam_flips`` and ``cam_stop_flips`` invert threshold
+    decisions that the float32 error model flags (see ``shadow_pass`` and
+    ``camera_pass``); the flagged pair keys are returned as
+    "amb_light_keys", "amb_cam_keys" and "amb_stop_keys"."""
     p = params if params is not None else scene_tensors(scene)
     cov = covariance(p["log_scale"], p["rot"])
     opacity = sigmoid(p["opacity_logit"])
     light_pos = as_t(light_view.eye)
     proj_l = project(p["mean"], cov, light_view, consts, "dist")
+    lk, ck, sk = [], [], []
     num, den, infl = shadow_pass(proj_l, light_view, opacity, consts,
-                                 band_rows=band_rows, pixels=light_pixels)
+                                 band_rows=band_rows, pixels=light_pixels, flips=light_flips, amb_keys=lk)
     T = shadow_values(num, den)
     with torch.no_grad():
         amb_T = torch.where(den > 0, infl / torch.where(den > 0, den, torch.ones_like(den)),
@@ -670,15 +806,32 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
     proj_c = project(p["mean"], cov, cam_view, consts, "z")
     S, Sh, R, Tfin, amb_px = camera_pass(proj_c, cam_view, opacity, sh["c"], tp, r, consts,
                                          tprime_err=amb_Tp.clamp_max(1.0),
-                                         band_rows=band_rows, pixels=cam_pixels)
+                                         band_rows=band_rows, pixels=cam_pixels, flips=cam_flips,
+                                         stop_flips=cam_stop_flips, amb_keys=ck, stop_keys=sk)
     final = S * Sh[None, :] + R
+    cat = lambda x: torch.cat(x) if x else torch.zeros(0, dtype=torch.int64)  # noqa: E731
     return {"final": final, "S": S, "Sh": Sh, "R": R, "T_final": Tfin,
             "T": T, "num": num, "den": den, "Tp": tp, "c": sh["c"], "r": r,
             "amb_T": amb_T, "amb_px": amb_px, "proj_l": proj_l, "proj_c": proj_c,
-            "opacity": opacity}
+            "opacity": opacity, "amb_light_keys": cat(lk), "amb_cam_keys": cat(ck),
+            "amb_stop_keys": cat(sk)}
 
 
 # --------------------------------------------------------------- training
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-15):
+    """One Adam update (Kingma and Ba 2015; the optimiser of Sec. 4.4, with
+    momentum beta1 = 0.9), float64: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2)
+    g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t = step
+    (1 for the first update). Returns (param, m, v)."""
+    p, g = np.asarray(param, np.float64), np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
 
 def l1_loss(pred, target, scale: float):
     """The L1 term of the training loss (Sec. 4.4, Eq. 9): scale * sum
@@ -687,6 +840,54 @@ def l1_loss(pred, target, scale: float):
     Returns (value, gradient array)."""
     d = np.asarray(pred, np.float64) - np.asarray(target, np.float64)
     return float(scale * np.abs(d).sum()), scale * np.sign(d)
+
+
+# SSIM constants (Wang et al. 2004, the SSIM the loss of Sec. 4.4 refers
+# to): an 11 x 11 Gaussian window of standard deviation 1.5, C1 = (0.01 L)^2,
+# C2 = (0.03 L)^2 with dynamic range L = 1.
+SSIM_WINDOW = 11
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+LOSS_LAMBDA = 0.2        # Sec. 4.4: weight of the D-SSIM term
+
+
+def ssim_window() -> torch.Tensor:
+    """The normalised 11 x 11 Gaussian window (outer product of a normalised
+    1-D Gaussian with sigma 1.5), float64."""
+    r = SSIM_WINDOW // 2
+    x = torch.arange(-r, r + 1, dtype=DT)
+    g = torch.exp(-x * x / (2 * SSIM_SIGMA ** 2))
+    g = g / g.sum()
+    return g[:, None] * g[None, :]
+
+
+def ssim_map(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """Per-pixel SSIM of images x, y [C, H, W] (float64): local means,
+    variances and covariance from the Gaussian window centred on the pixel,
+    zero outside the image, each channel on its own:
+    s = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2))."""
+    w = ssim_window()
+    C = x.shape[0]
+    k = w[None, None].expand(C, 1, *w.shape)
+    pad = SSIM_WINDOW // 2
+    blur = lambda t: torch.nn.functional.conv2d(t[None], k, padding=pad, groups=C)[0]  # noqa: E731
+    mx, my = blur(x), blur(y)
+    sxx = blur(x * x) - mx * mx
+    syy = blur(y * y) - my * my
+    sxy = blur(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def dssim_loss(pred, target, scale: float):
+    """The D-SSIM term of the training loss (Sec. 4.4, Eq. 9; the D-SSIM of
+    the Gaussian-splatting loss the paper adopts): scale * sum over channels
+    and pixels of (1 - SSIM). Returns (value, gradient array) in float64;
+    scale = lambda / (C H W) gives lambda times the mean D-SSIM."""
+    x = as_t(pred).clone().requires_grad_(True)
+    val = scale * (1.0 - ssim_map(x, as_t(target))).sum()
+    val.backward()
+    return float(val.detach()), x.grad.numpy()
 
 
 def render_images(out: Dict, view) -> Dict[str, np.ndarray]:

@@ -64,6 +64,13 @@ def make_requests(count: int, qps: float, seed: int = 3, resolutions=(256, 512, 
     return out
 
 
+def _ws_bytes(n: int, w: int, h: int, capacity: int) -> int:
+    import ctypes as C
+    size = C.c_size_t()
+    gs3._check(gs3._lib.gs3_view_workspace_size(n, w, h, capacity, C.byref(size)), "gs3_view_workspace_size")
+    return size.value + 256
+
+
 class BufferSet:
     """Everything one in-flight request needs: a Renderer (view buffers, T,
     num/den, images) bound to one camera resolution, and its own stream."""
@@ -78,8 +85,22 @@ class BufferSet:
             self.renderer._vb("light", light_res, light_res, capacity)
             self.renderer._vb("cam", res, res, capacity)
             self.renderer._images(res, res)
-        self.bytes = sum(vb.storage.numel() for vb in self.renderer.vbs.values()) + \
-            sum(t.numel() * t.element_size() for im in self.renderer.images.values() for t in im.values())
+        self.bytes = self.measure()
+
+    def measure(self) -> int:
+        """Device bytes this set holds now (view workspaces, images, shadow
+        state)."""
+        r = self.renderer
+        return sum(vb.storage.numel() for vb in r.vbs.values()) + \
+            sum(t.numel() * t.element_size() for im in r.images.values() for t in im.values()) + \
+            (r.num_den.numel() + r.T.numel()) * 4
+
+    @staticmethod
+    def estimate(n: int, res: int, light_res: int, capacity: int) -> int:
+        """Device bytes a new set for camera resolution `res` will hold."""
+        images = 12 * res * res * 4 + 8 * max(n, 1) * 4
+        return _ws_bytes(n, light_res, light_res, capacity) + _ws_bytes(n, res, res, capacity) + images + \
+            3 * max(n, 1) * 4
 
 
 class Server:
@@ -105,19 +126,20 @@ class Server:
         pool = self.free.setdefault(res, [])
         if pool:
             return pool.pop()
-        # estimate before allocating: one set per resolution is always allowed
-        probe = self.sets[0].bytes if self.sets else 0
+        # size the new set before allocating it (the first set is always
+        # allowed, so that every request can be served)
+        probe = BufferSet.estimate(self.scene.n, res, self.light_res, self.capacity)
         if self.sets and self.allocated + probe > self.cap:
-            # try to reclaim an idle set of another resolution
-            for r, p in self.free.items():
-                if p:
+            # reclaim idle sets of other resolutions until the new one fits
+            idle = [bs for p in self.free.values() for bs in p]
+            if sum(bs.bytes for bs in idle) < self.allocated + probe - self.cap:
+                return None          # not enough even then: wait for a request to finish
+            for p in self.free.values():
+                while p and self.allocated + probe > self.cap:
                     bs = p.pop()
                     self.allocated -= bs.bytes
                     self.sets.remove(bs)
                     del bs
-                    break
-            else:
-                return None
             if self.allocated + probe > self.cap:
                 return None
         bs = BufferSet(self.scene, self.consts, res, self.light_res, self.capacity)
@@ -137,12 +159,17 @@ class Server:
         """After completion: a binning that overflowed its pair capacity is
         rerun with a larger buffer (rare; synchronous)."""
         with torch.cuda.stream(bs.stream):
-            # the request's own stream has finished, so this read waits for nothing
+            # the request's own stream has finished, so the views' status
+            # blocks are final and this read waits for nothing
             if not bs.renderer.overflowed():
                 return None
             out = bs.renderer.render(req.cam, req.light, check=True)
             final = out["final"].clone() if keep else None
         bs.stream.synchronize()
+        # the rerun may have grown the view buffers: keep the accounting exact
+        grown = bs.measure()
+        self.allocated += grown - bs.bytes
+        bs.bytes = grown
         return final
 
     def run(self, requests: List[Request], keep_results: bool = False) -> List[Result]:

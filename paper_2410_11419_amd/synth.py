@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "Scene", "View", "Mlp", "make_scene", "make_view", "random_views",
     "scene_small", "scene_full", "scene_fluffy", "fluffy_pairs", "scene_gradcheck",
-    "perturb_scene", "subset",
+    "perturb_scene", "subset", "concat_scenes", "scene_needles",
 ]
 
 FEAT_DIM = 16
@@ -232,6 +232,32 @@ def scene_gradcheck(seed: int = 0, n: int = 256, k: int = 4, mlps: bool = True):
     cam = make_view(rng.standard_normal(3), 4.0, 32, 32, 40.0)
     light = make_view(rng.standard_normal(3), 4.0, 32, 32, 60.0)
     return sc, cam, light
+
+
+def concat_scenes(a: Scene, b: Scene) -> Scene:
+    """The Gaussians of a, then those of b (a's MLPs)."""
+    cat = lambda x, y, ax: np.ascontiguousarray(np.concatenate([x, y], ax))  # noqa: E731
+    return Scene(mean=cat(a.mean, b.mean, 1), log_scale=cat(a.log_scale, b.log_scale, 1),
+                 rot=cat(a.rot, b.rot, 1), opacity_logit=cat(a.opacity_logit, b.opacity_logit, 0),
+                 shade_rot=cat(a.shade_rot, b.shade_rot, 1), albedo=cat(a.albedo, b.albedo, 1),
+                 lobe_axis=cat(a.lobe_axis, b.lobe_axis, 2), lobe_log_sharp=cat(a.lobe_log_sharp, b.lobe_log_sharp, 1),
+                 lobe_amp=cat(a.lobe_amp, b.lobe_amp, 2), feat=cat(a.feat, b.feat, 1), phi=a.phi, psi=a.psi)
+
+
+def scene_needles(seed: int = 0, n_needles: int = 60, n_blobs: int = 340, mlps: bool = True):
+    """Long thin needles (log-scales N(-1.2, 0.2), N(-4.5, 0.3), N(-4.5, 0.3)
+    in [-1,1]^3) among small blobs (log-scales N(-3, 0.3)): in a 256^2 light
+    view at 60 deg many needles span 16 tiles or more with a bounding box
+    several times their ellipse (the banded shadow-denominator path).
+    Camera 128^2 at 40 deg; both views at radius 4."""
+    nd = make_scene(n_needles, 4, seed, means="cube", log_scale_mu=(-1.2, -4.5, -4.5),
+                    log_scale_sd=(0.2, 0.3, 0.3), mlps=mlps)
+    bl = make_scene(n_blobs, 4, seed + 1000, means="cube", log_scale_mu=(-3.0, -3.0, -3.0),
+                    log_scale_sd=(0.3, 0.3, 0.3))
+    rng = np.random.default_rng(seed + 1)
+    cam = make_view(rng.standard_normal(3), 4.0, 128, 128, 40.0)
+    light = make_view(rng.standard_normal(3), 4.0, 256, 256, 60.0)
+    return concat_scenes(nd, bl), cam, light
 
 
 def perturb_scene(sc: Scene, seed: int, mean_sd: float = 0.01,

@@ -54,3 +54,53 @@ def test_plain_baseline_and_memory_cap(env):
         assert float((a.final - b.final).abs().max()) <= 1e-4
     s = serve.summarize(got)
     assert s["requests"] == 12 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_served_equals_alone_at_serving_workload(env):
+    """The serving workload's own scene and sizes: 300,000 Gaussians,
+    camera 256^2 / 512^2 / 800^2 / 1024^2, light 1024^2; 16 requests arriving
+    at once, up to 8 in flight, each result equal to the request rendered
+    alone."""
+    gs3, serve, _ = env
+    sc, _, _ = synth.scene_full()
+    ds = gs3.DeviceScene.from_host(sc)
+    reqs = serve.make_requests(16, qps=1e6, seed=8)
+    assert {r.cam.width for r in reqs} == {256, 512, 800, 1024}
+    srv = serve.Server(ds, mem_cap_bytes=24 << 30, max_inflight=8)
+    got = srv.run(reqs, keep_results=True)
+    spans = sorted((r.start, r.done) for r in got)
+    overlap = max(sum(1 for s, d in spans if s <= t < d) for t, _ in spans)
+    rnd = gs3.Renderer(ds)
+    worst = 0.0
+    for req, res in zip(reqs, got):
+        alone = rnd.render(req.cam, req.light)["final"]
+        assert res.final.shape == alone.shape
+        worst = max(worst, float((res.final - alone).abs().max()))
+    print(f"300K scene: max requests in flight together {overlap}, max |served - alone| = {worst:.2e}")
+    assert overlap >= 2
+    assert worst <= 1e-4
+
+
+def test_memory_cap_with_mixed_resolutions(env):
+    """Requests of 64^2 and 256^2 under a cap that holds one small and one
+    large set at most: the server never allocates past the cap, and frees
+    idle sets of the other resolution to make room."""
+    gs3, serve, ds = env
+    cap_small = serve.BufferSet.estimate(ds.n, 64, 128, max(1 << 16, 32 * ds.n))
+    cap_large = serve.BufferSet.estimate(ds.n, 256, 128, max(1 << 16, 32 * ds.n))
+    cap = cap_small + cap_large + 1
+    reqs = serve.make_requests(20, qps=3000.0, seed=7, resolutions=(64, 256), light_res=128)
+    srv = serve.Server(ds, mem_cap_bytes=cap, light_res=128, max_inflight=4)
+    peak = 0
+    orig = srv._acquire
+
+    def watch(res):
+        nonlocal peak
+        bs = orig(res)
+        peak = max(peak, srv.allocated)
+        return bs
+    srv._acquire = watch
+    got = srv.run(reqs, keep_results=True)
+    print(f"cap {cap} bytes, peak allocated {peak}, sets {len(srv.sets)}")
+    assert peak <= cap and srv.allocated <= cap
+    assert all(r.final is not None for r in got)

@@ -219,7 +219,7 @@ def test_compositing_telescopes_without_cutoffs():
     assert (Tf.numpy() < 1).all()
 
 
-def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=None):
+def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=None, flips=(), stop_flips=()):
     """Independent pure-Python per-pixel evaluation (tiny inputs only)."""
     u, v = pr["u"].numpy(), pr["v"].numpy()
     con = pr["conic"].numpy()
@@ -238,7 +238,10 @@ def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=No
                 dx, dy = x + 0.5 - u[g], y + 0.5 - v[g]
                 pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
                 al = min(consts.alpha_max, opv[g] * math.exp(pw))
-                if pw >= -consts.cutoff and al >= consts.alpha_min:
+                is_hit = pw >= -consts.cutoff and al >= consts.alpha_min
+                if (g, x, y) in flips:
+                    is_hit = not is_hit
+                if is_hit:
                     hits.append((np.float32(dep[g]), g, al, math.exp(pw)))   # float32 depth key
             hits.sort()
             if mode == "shadow":
@@ -253,7 +256,7 @@ def _brute_pixels(pr, op, W, H, consts, mode, colour=None, tprime=None, resid=No
             else:
                 t = 1.0
                 for (d, g, al, b) in hits:
-                    if t * (1 - al) < consts.t_min:
+                    if (t * (1 - al) < consts.t_min) != ((g, x, y) in stop_flips):
                         break
                     S[:, y, x] += colour[g] * al * t
                     Sh[y, x] += tprime[g] * al * t
@@ -288,6 +291,83 @@ def test_passes_match_pure_python_brute_force(consts):
     np.testing.assert_allclose(R.numpy().reshape(3, 16, 20), bR, atol=1e-13)
     np.testing.assert_allclose(Tf.numpy().reshape(16, 20), bT, atol=1e-13)
     assert (bT < 1).sum() > 20
+
+
+def test_forced_decisions_match_brute_force():
+    """Decisions handed to the oracle as flips (hit <-> miss for near-
+    threshold pairs, stop <-> continue at a hit) give what the pure-Python
+    brute force gives with the same decisions inverted."""
+    consts = O.Consts(t_min=0.05)
+    sc = synth.make_scene(40, 2, seed=11, means="cube", log_scale_mu=(-2.3, -2.3, -2.3),
+                          log_scale_sd=(0.3, 0.3, 0.3))
+    cam = _view([1.0, -3.6, 1.2], 20, 16)
+    light = _view([3.0, -1.0, 2.5], 18, 14, 60)
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    op = O.sigmoid(p["opacity_logit"])
+    rng = np.random.default_rng(3)
+
+    def near_pairs(pr, W, H, count):
+        # pairs whose power lies within 0.3 of the threshold and inside the
+        # oracle's candidate region (power >= -4.5 - 0.055), hits and misses
+        u, v, con = pr["u"].numpy(), pr["v"].numpy(), pr["conic"].numpy()
+        pth = O.hit_threshold(op.detach(), consts).numpy()
+        out = []
+        for g in range(len(u)):
+            if not bool(pr["valid"][g]):
+                continue
+            for y in range(H):
+                for x in range(W):
+                    dx, dy = x + 0.5 - u[g], y + 0.5 - v[g]
+                    pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
+                    if abs(pw + pth[g]) < 0.3 and pw >= -4.5:
+                        out.append((g, x, y))
+        assert len(out) >= count
+        return [out[i] for i in rng.choice(len(out), count, replace=False)]
+
+    prl = O.project(p["mean"], cov, light, consts, "dist")
+    fl = near_pairs(prl, 18, 14, 6)
+    keys = [g * 18 * 14 + y * 18 + x for g, x, y in fl]
+    num, den, _ = O.shadow_pass(prl, light, op, consts, band_rows=5, flips=keys)
+    bn, bd, *_ = _brute_pixels(prl, op, 18, 14, consts, "shadow", flips=set(fl))
+    n0, d0, _ = O.shadow_pass(prl, light, op, consts, band_rows=5)
+    assert not torch.allclose(den, d0)                 # the flips change something
+    np.testing.assert_allclose(num.numpy(), bn, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(den.numpy(), bd, rtol=1e-12, atol=1e-14)
+    prc = O.project(p["mean"], cov, cam, consts, "z")
+    col, tp, rs = rng.uniform(0, 2, (40, 3)), rng.uniform(0, 1, 40), rng.uniform(0, 1, (40, 3))
+    fl = near_pairs(prc, 20, 16, 6)
+    keys = [g * 20 * 16 + y * 20 + x for g, x, y in fl]
+    # stop flips: the hit at which some pixels stop, and a hit before a stop
+    ref = _brute_pixels(prc, op, 20, 16, consts, "camera", col, tp, rs, flips=set(fl))
+    stops = []
+    u, v, con = prc["u"].numpy(), prc["v"].numpy(), prc["conic"].numpy()
+    for y in range(16):
+        for x in range(20):
+            if ref[5][y, x] < 0.2 and len(stops) < 4:
+                # the pixel's last blended hit: inverting its decision stops the pixel there
+                hits = []
+                for g in range(40):
+                    dx, dy = x + 0.5 - u[g], y + 0.5 - v[g]
+                    pw = -0.5 * (con[g, 0] * dx * dx + 2 * con[g, 1] * dx * dy + con[g, 2] * dy * dy)
+                    al = min(consts.alpha_max, float(op[g]) * math.exp(pw))
+                    h = (pw >= -consts.cutoff and al >= consts.alpha_min) != ((g, x, y) in set(fl))
+                    if h and bool(prc["valid"][g]):
+                        hits.append((np.float32(prc["depth"][g].item()), g))
+                hits.sort()
+                if hits:
+                    stops.append((hits[len(hits) // 2][1], x, y))
+    assert stops
+    skeys = [g * 20 * 16 + y * 20 + x for g, x, y in stops]
+    S, Sh, R, Tf, _ = O.camera_pass(prc, cam, op, T(col), T(tp), T(rs), consts, band_rows=3, flips=keys,
+                                    stop_flips=skeys)
+    _, _, bS, bSh, bR, bT = _brute_pixels(prc, op, 20, 16, consts, "camera", col, tp, rs, flips=set(fl),
+                                          stop_flips=set(stops))
+    np.testing.assert_allclose(S.numpy().reshape(3, 16, 20), bS, atol=1e-13)
+    np.testing.assert_allclose(Sh.numpy().reshape(16, 20), bSh, atol=1e-13)
+    np.testing.assert_allclose(R.numpy().reshape(3, 16, 20), bR, atol=1e-13)
+    np.testing.assert_allclose(Tf.numpy().reshape(16, 20), bT, atol=1e-13)
+    assert not np.allclose(bT, ref[5])
 
 
 def test_equal_depth_keys_are_ordered_by_index():
@@ -619,3 +699,240 @@ def test_ambiguity_flags_are_rare_on_small_scene():
     out = O.render(sc, cam, light, O.SMOOTH)    # no thresholds, distinct depths
     assert (out["amb_px"] > O.gs3_oracle.AMB_BUDGET).sum() == 0
     assert (out["amb_T"] > O.gs3_oracle.AMB_BUDGET).sum() == 0
+
+
+# ---------------------------------------------- float32 error-model pins
+#
+# The oracle flags a (pixel, splat) pair as threshold-ambiguous when its
+# exact power lies within O.hit_margin of the threshold -p. These tests pin
+# that margin against float32 evaluations written here in numpy (not the
+# kernels): splat centre, conic and opacity rounded once to float32, the
+# pixel offset formed relative to the pixel's 16x16 tile corner, and the
+# quadratic in three operation orders (fused multiply-adds, plain products,
+# a Horner form). Every pair whose float32 decision differs from the exact
+# one must be flagged, and the margin must stay close to the observed error
+# band.
+
+_F32 = np.float32
+_LOG2E = _F32(1.4426950408889634)
+
+
+def _fma32(a, b, c):
+    # float32 fused multiply-add: the float64 product of float32 values is
+    # exact, then one float64 sum rounded to float32
+    return _F32(a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64))
+
+
+def _near_threshold_pairs(n, rng):
+    """Random splats (sigma 0.2-40 px, a third of them needles with aspect
+    up to 300, plus the 0.3 px^2 dilation), opacities both generic and in the
+    alpha-limited range, and pixel centres placed at power = -p + eps with
+    |eps| spread over 1e-8 .. 1e-3."""
+    s1 = np.exp(rng.uniform(np.log(0.2), np.log(40.0), n))
+    needle = rng.random(n) < 0.33
+    asp = np.where(needle, np.exp(rng.uniform(0, np.log(300.0), n)), np.exp(rng.uniform(0, np.log(3.0), n)))
+    s2 = s1 / asp
+    th = rng.uniform(0, np.pi, n)
+    c, s = np.cos(th), np.sin(th)
+    a = c * c * s1 ** 2 + s * s * s2 ** 2 + 0.3
+    b = c * s * (s1 ** 2 - s2 ** 2)
+    cc = s * s * s1 ** 2 + c * c * s2 ** 2 + 0.3
+    det = a * cc - b * b
+    ca, cb, ccc = cc / det, -b / det, a / det
+    o = np.where(rng.random(n) < 0.5, 1 / (1 + np.exp(-rng.normal(0, 1, n))),
+                 np.exp(rng.uniform(np.log(1 / 255 * 1.01), np.log(0.05), n)))
+    p = np.minimum(4.5, np.log(o / (1.0 / 255.0)))
+    px = rng.integers(0, 2048, n) + 0.5
+    py = rng.integers(0, 2048, n) + 0.5
+    phi = rng.uniform(0, 2 * np.pi, n)
+    ux, uy = np.cos(phi), np.sin(phi)
+    qd = ca * ux * ux + 2 * cb * ux * uy + ccc * uy * uy
+    eps = rng.uniform(-1, 1, n) * 10 ** rng.uniform(-8, -3, n)
+    r = np.sqrt(2 * (p + eps) / qd)
+    return dict(ca=ca, cb=cb, cc=ccc, o=o, p=p, px=px, py=py, u=px - r * ux, v=py - r * uy)
+
+
+def _float32_decision_value(S, order):
+    """(q - thr) / log2(e) of a float32 evaluation: >= 0 means a hit."""
+    hu, hv = np.floor(S["u"]), np.floor(S["v"])
+    lu, lv = _F32(S["u"] - hu), _F32(S["v"] - hv)
+    a, b, c, o = _F32(S["ca"]), _F32(S["cb"]), _F32(S["cc"]), _F32(S["o"])
+    p = np.minimum(_F32(4.5), np.log(_F32(o / _F32(1.0 / 255.0))).astype(np.float32))
+    thr = _F32(-p * _LOG2E)
+    ox, oy = 16.0 * np.floor(S["px"] / 16.0), 16.0 * np.floor(S["py"] / 16.0)
+    ur, vr = _F32(_F32(hu - ox) + lu), _F32(_F32(hv - oy) + lv)
+    dx, dy = _F32(_F32(S["px"] - ox) - ur), _F32(_F32(S["py"] - oy) - vr)
+    K = _F32(-0.5 * _LOG2E)
+    A, B, C = _F32(K * a), _F32(_F32(-_LOG2E) * b), _F32(K * c)
+    if order == "fma":
+        q = _fma32(dx, _fma32(B, dy, _F32(A * dx)), _F32(_F32(C * dy) * dy))
+    elif order == "plain":
+        q = _F32(_F32(_F32(A * dx) * dx) + _F32(_F32(_F32(B * dx) * dy) + _F32(_F32(C * dy) * dy)))
+    else:
+        q = _F32(_F32(dx * _F32(_F32(A * dx) + _F32(B * dy))) + _F32(C * _F32(dy * dy)))
+    return (q.astype(np.float64) - thr.astype(np.float64)) / float(_LOG2E)
+
+
+def test_hit_margin_covers_every_float32_flip():
+    rng = np.random.default_rng(11)
+    worst, flips, total = 0.0, 0, 0
+    for _ in range(3):
+        S = _near_threshold_pairs(1_200_000, rng)
+        dx, dy = S["px"] - S["u"], S["py"] - S["v"]
+        exact = -0.5 * (S["ca"] * dx * dx + 2 * S["cb"] * dx * dy + S["cc"] * dy * dy) + S["p"]
+        marg = O.hit_margin(*(T(x) for x in (dx, dy, S["ca"], S["cb"], S["cc"], S["p"]))).numpy()
+        for order in ("fma", "plain", "horner"):
+            v32 = _float32_decision_value(S, order)
+            flip = (v32 >= 0) != (exact >= 0)
+            assert (np.abs(exact[flip]) <= marg[flip]).all(), order
+            worst = max(worst, float((np.abs(v32 - exact) / marg).max()))
+            flips += int(flip.sum())
+            total += flip.size
+    assert total >= 10_000_000 and flips > 100_000
+    # every float32 error within the margin, and the margin not needlessly
+    # wide: the worst error reaches a third of it (it is the unwidened bound
+    # times HIT_KAPPA = 1.5; the simulation's worst is about 0.73 of that
+    # bound)
+    assert worst <= 1.0 and worst >= 1.0 / 3.0, worst
+
+
+def test_hit_margin_threshold_pins():
+    """A 3 px round splat: a pixel at power = -4.5 +- 1e-7 is flagged, one at
+    -4.5 +- 1e-3 is not; the alpha-limited threshold likewise."""
+    sig2 = 9.3
+    ca, cb, cc = T([1 / sig2]), T([0.0]), T([1 / sig2])
+    for p0, op in ((4.5, 0.9), (math.log(0.02 * 255), 0.02)):
+        p = O.hit_threshold(T([op]), O.Consts())
+        assert abs(float(p) - p0) < 1e-12
+        for eps, flagged in ((1e-7, True), (-1e-7, True), (1e-3, False), (-1e-3, False)):
+            r = math.sqrt(2 * (p0 + eps) * sig2)
+            dx, dy = T([r * 0.6]), T([r * 0.8])
+            power = -0.5 * (ca * dx * dx + cc * dy * dy)
+            m = O.hit_margin(dx, dy, ca, cb, cc, p)
+            assert bool((power + p).abs() <= m) == flagged, (p0, eps)
+
+
+def test_transmittance_error_bound_covers_float32_products():
+    """Front-to-back products of (1 - alpha) along random chains of up to
+    300 hits, alpha from a float32 evaluation (opacity times 2^q, clamped at
+    float32(0.99)), against float64: the relative error stays inside the
+    cumulative bound of O.transmittance_relerr at every entry, so a stop
+    decision (T * (1 - alpha) < t_min) outside the bound is the same in both
+    precisions."""
+    rng = np.random.default_rng(12)
+    k = O.Consts()
+    S = _near_threshold_pairs(400_000, rng)
+    # move the pixels inward so that alphas span the whole range: power
+    # between -p and 0
+    frac = rng.uniform(0.0, 1.0, S["p"].size) ** 2
+    S["u"] = S["px"] - (S["px"] - S["u"]) * np.sqrt(frac)
+    S["v"] = S["py"] - (S["py"] - S["v"]) * np.sqrt(frac)
+    S["o"] = np.where(rng.random(S["o"].size) < 0.3, rng.uniform(0.9, 1.0, S["o"].size), S["o"])
+    S["p"] = np.minimum(4.5, np.log(S["o"] / (1.0 / 255.0)))
+    dx, dy = S["px"] - S["u"], S["py"] - S["v"]
+    power = -0.5 * (S["ca"] * dx * dx + 2 * S["cb"] * dx * dy + S["cc"] * dy * dy)
+    a64 = np.minimum(k.alpha_max, S["o"] * np.exp(power))
+    v32 = _float32_decision_value(S, "fma")            # (q - thr) / log2 e
+    thr32 = -np.minimum(_F32(4.5), np.log(_F32(_F32(S["o"]) / _F32(1 / 255))).astype(np.float32)) * _LOG2E
+    q32 = _F32(v32 * float(_LOG2E) + thr32.astype(np.float64))
+    a32 = np.minimum(_F32(k.alpha_max), _F32(_F32(S["o"]) * np.exp2(q32).astype(np.float32)))
+    hit = torch.ones(a64.size, dtype=torch.bool)
+    marg = O.hit_margin(*(T(x) for x in (dx, dy, S["ca"], S["cb"], S["cc"], S["p"])))
+    r = O.transmittance_relerr(T(a64), hit, marg, k).numpy()
+    pos = 0
+    while pos + 300 <= a64.size:
+        L = int(rng.integers(1, 300))
+        sl = slice(pos, pos + L)
+        pos += L
+        t64 = np.cumprod(1.0 - a64[sl])
+        t32 = np.ones(L, np.float32)
+        acc = _F32(1.0)
+        for i, al in enumerate(a32[sl]):
+            acc = _F32(acc * _F32(_F32(1.0) - al))
+            t32[i] = acc
+        bound = np.cumsum(r[sl]) * t64
+        ok = t64 > 1e-30
+        assert (np.abs(t32.astype(np.float64) - t64)[ok] <= bound[ok] + 1e-37).all()
+
+
+# ------------------------------------------------------- training-loss pins
+
+def _ssim_brute(x, y, i, j):
+    """SSIM at pixel (i, j) of one channel from explicit window sums (pure
+    Python): the window's weights are w(a, b) = g(a) g(b), g the normalised
+    1-D Gaussian of sigma 1.5 over -5..5; pixels outside the image are 0."""
+    g = [math.exp(-(t * t) / (2 * 1.5 ** 2)) for t in range(-5, 6)]
+    gs = sum(g)
+    g = [t / gs for t in g]
+    H, W = x.shape
+    mx = my = exx = eyy = exy = 0.0
+    for a in range(-5, 6):
+        for b in range(-5, 6):
+            ii, jj = i + a, j + b
+            if 0 <= ii < H and 0 <= jj < W:
+                wgt = g[a + 5] * g[b + 5]
+                xv, yv = float(x[ii, jj]), float(y[ii, jj])
+                mx += wgt * xv
+                my += wgt * yv
+                exx += wgt * xv * xv
+                eyy += wgt * yv * yv
+                exy += wgt * xv * yv
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    sx, sy, sxy = exx - mx * mx, eyy - my * my, exy - mx * my
+    return ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sx + sy + c2))
+
+
+def test_ssim_map_matches_window_sums():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, 1, (2, 9, 13))
+    y = np.clip(x + rng.normal(0, 0.1, x.shape), 0, 1)
+    s = O.ssim_map(T(x), T(y)).numpy()
+    for c, i, j in ((0, 0, 0), (0, 4, 6), (1, 8, 12), (1, 2, 11), (0, 7, 1)):
+        assert abs(s[c, i, j] - _ssim_brute(x[c], y[c], i, j)) < 1e-12
+
+
+def test_ssim_closed_forms():
+    # identical images: SSIM 1 everywhere, D-SSIM 0
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 1, (3, 24, 20))
+    assert np.allclose(O.ssim_map(T(x), T(x)).numpy(), 1.0, atol=1e-14)
+    assert abs(O.dssim_loss(x, x, 1.0)[0]) < 1e-10
+    # constant images a, b: away from the border (window inside the image)
+    # the variances vanish and SSIM = (2ab + C1) / (a^2 + b^2 + C1)
+    a, b = 0.3, 0.7
+    s = O.ssim_map(T(np.full((1, 30, 30), a)), T(np.full((1, 30, 30), b))).numpy()
+    want = (2 * a * b + O.SSIM_C1) / (a * a + b * b + O.SSIM_C1)
+    assert abs(s[0, 15, 15] - want) < 1e-12
+    # the window is normalised and has the stated width
+    w = O.ssim_window().numpy()
+    assert abs(w.sum() - 1) < 1e-15 and w.shape == (11, 11)
+    assert abs(w[5, 6] / w[5, 5] - math.exp(-1 / (2 * 1.5 ** 2))) < 1e-14
+
+
+def test_dssim_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, (2, 8, 9))
+    y = rng.uniform(0, 1, (2, 8, 9))
+    val, g = O.dssim_loss(x, y, 0.7)
+    h = 1e-6
+    for idx in ((0, 0, 0), (1, 4, 5), (0, 7, 8), (1, 3, 0)):
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (O.dssim_loss(xp, y, 0.7)[0] - O.dssim_loss(xm, y, 0.7)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_adam_step_matches_torch_optim():
+    rng = np.random.default_rng(4)
+    p0 = rng.normal(size=50)
+    grads = [rng.normal(size=50) for _ in range(4)]
+    tp = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=0.01, betas=(0.9, 0.999), eps=1e-15)
+    p, m, v = p0, np.zeros(50), np.zeros(50)
+    for t, g in enumerate(grads, 1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = O.adam_step(p, g, m, v, t, 0.01)
+    assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-14)
