@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--fluffy-steps", type=int, default=3,
                     help="timed fwd+bwd steps of the dense 1.5M-Gaussian scene (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=2000, help="requests per serving run (0: skip)")
-    ap.add_argument("--serving-loads", type=str, default="0.5,0.9",
+    ap.add_argument("--serving-loads", type=str, default="0.25,0.5,0.75,0.9",
                     help="offered loads as fractions of the plain renderer's saturation rate")
     ap.add_argument("--profile-train", action="store_true",
                     help="only run two fwd+bwd steps (for rocprofv3), no JSON")
@@ -94,6 +94,41 @@ def frame_bytes(n, k, p_light, p_cam, cam_px):
     per_g = n * 40
     image = cam_px * 12
     return params + records + emit + sort + lists + per_g + image
+
+
+GEOM_BYTES = 4 * (3 + 3 + 4 + 1)      # mean, log-scale, rotation, opacity logit
+
+
+def appearance_bytes(k):
+    """Per-Gaussian appearance and feature reads of the shading: shading
+    rotation, albedo, K lobes (axis, log-sharpness, RGB amplitude), the
+    16 features and the centre."""
+    return 4 * (4 + 3 + 7 * k + 16 + 3)
+
+
+def preprocess_bytes(n, pairs):
+    """Algorithmic HBM bytes of one view's projection + binning: geometry
+    read (44 B), projected record written (36 B: centre, conic, opacity,
+    depth) per Gaussian; per (tile, Gaussian) pair the emission (12 B) and
+    one read + write of the sort (24 B)."""
+    return n * (GEOM_BYTES + 36) + pairs * 36
+
+
+def shade_bytes(n, k):
+    """Algorithmic bytes of the per-Gaussian shading + Psi (gs3_shade):
+    appearance reads, colour and residual written (c, r and their copies
+    for the caller: 32 + 32 B)."""
+    return n * (appearance_bytes(k) + 64)
+
+
+def backward_bytes(n, k, p_light, p_cam, cam_px):
+    """Algorithmic bytes of one view's adjoint: parameters read again
+    (geometry for both views, appearance), both views' records and lists,
+    the saved per-Gaussian state (T, num, den, c, T', r), the camera images
+    it reads (dL/dfinal, S, Sh, R: 10 floats per pixel) and one read +
+    write of the 90 gradient floats per Gaussian it accumulates into."""
+    params = n * (2 * GEOM_BYTES + appearance_bytes(k))
+    return params + 2 * n * 36 + 4 * (p_light + p_cam) + n * 4 * 10 + cam_px * 40 + 2 * n * 90 * 4
 
 
 def kernel_source_hash():
@@ -210,8 +245,22 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
     per = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
     light0 = pairs[0][1]
     loss_last = float(losses.sum().item())
+    # algorithmic HBM bytes of a step: per view the forward frame and its
+    # adjoint (pairs and hits counted on the step's first views)
+    per_view = []
+    for cam, light in pairs[:batch]:
+        rnds[0].render(cam, light, check=True)
+        lvb = rnds[0].vbs[("light", light.width, light.height)]
+        cvb = rnds[0].vbs[("cam", cam.width, cam.height)]
+        pl, pc = gs3.gs3_view_pair_count(lvb), gs3.gs3_view_pair_count(cvb)
+        per_view.append(frame_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height) +
+                        backward_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height))
+    step_bytes = float(np.mean(per_view)) * batch
+    step_gbs = step_bytes / (wall / steps) / 1e9
     return {"metric": "fwd+bwd steps/s", "value": round(steps / wall, 3), "unit": "steps/s",
             "loss_last_step": round(loss_last, 6),
+            "hbm": {"algorithmic_bytes": int(step_bytes), "achieved_GBs": round(step_gbs, 1),
+                    "frac_of_8TBs": round(step_gbs / HBM_PEAK_GBS, 4)},
             "ms_per_step": round(1e3 * wall / steps, 3), "steps": steps, "batch": batch,
             "workload": workload or (f"{sc.n:,} Gaussians, batch of {batch} (camera {cam0.width}x{cam0.height}, "
                                      f"light {light0.width}x{light0.height}) pairs, L1 loss against targets "
@@ -286,6 +335,44 @@ def serving_bench(ds, requests, loads):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_train(seconds=15.0):
+    """The FP64 oracle's forward + backward (torch float64 autograd of its
+    render, L = sum(dF * final)) at the gradient-check scale: 256 Gaussians,
+    camera and light 32x32, both MLPs. Runs steps for about `seconds`."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_2410_11419_amd import synth
+    sc, cam, light = synth.scene_gradcheck(seed=0)
+    dF = torch.as_tensor(np.random.default_rng(0).standard_normal((3, cam.height * cam.width)))
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds or steps < 2:
+        p = O.scene_tensors(sc, requires_grad=True)
+        phi = [(torch.tensor(w, dtype=torch.float64, requires_grad=True),
+                torch.tensor(b, dtype=torch.float64, requires_grad=True)) for w, b in sc.phi.layers]
+        psi = [(torch.tensor(w, dtype=torch.float64, requires_grad=True),
+                torch.tensor(b, dtype=torch.float64, requires_grad=True)) for w, b in sc.psi.layers]
+        ref = O.render(sc, cam, light, O.Consts(), params=p, phi=phi, psi=psi)
+        (ref["final"] * dF).sum().backward()
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(steps / dt, 4), "unit": "steps/s", "cores": torch.get_num_threads(),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"FP64 oracle forward + autograd backward, 256 Gaussians, 32x32 camera and light, both "
+                      f"MLPs: {steps} steps in {dt:.1f} s (the gradient-check scale; a full 300K step is "
+                      f"beyond the oracle)"}
+
+
 def cpu_baseline(n):
     """The FP64 oracle, as it is, on a bounded sample of the same frame:
     projection of both views and shading + both MLPs for all Gaussians, plus
@@ -325,6 +412,7 @@ def cpu_baseline(n):
         t_cam += time.perf_counter() - t0
     frame = t_pg + t_light * light.height / (3 * band) + t_cam * cam.height / (3 * band)
     return {"value": round(1.0 / frame, 6), "unit": "frames/s", "cores": torch.get_num_threads(),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
             "kind": "oracle",
             "sample": (f"FP64 oracle: projection + shading + both MLPs for all {sc.n} Gaussians "
                        f"({t_pg:.1f} s), light pass on 3x{band} of {light.height} rows ({t_light:.1f} s), "
@@ -436,12 +524,20 @@ def main():
     torch.cuda.synchronize()
     single_fps = n_single / (time.perf_counter() - ts)
     stream = torch.cuda.current_stream()
-    # per-stage breakdown from a short serial pass (one stream, in order)
-    n_ser = min(8, args.steps)
-    ser = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(n_ser)]
+    # per-stage breakdown from a serial pass (one stream, in order, nothing
+    # else on the device): each stage's events bracket only its own
+    # launches, so the shadow denominator and numerator brackets are the
+    # kernels k_shadow_den and k_shadow alone. This pass is the last use of
+    # those kernels in the frame benchmark; the roofline takes their
+    # durations from it (a profile of the same command shows them as the
+    # last dispatches of each).
+    n_ser = max(8, min(16, args.steps))
+    torch.cuda.synchronize()
+    ser = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(n_ser)]
     for i in range(n_ser):
         cam, light = pairs[i % len(pairs)]
         e = ser[i]
+        im = rnd._images(cam.width, cam.height)
         e[0].record(stream)
         lvb = rnd._preprocess("light", light, gs3.GS3_DEPTH_DIST, False)
         e[1].record(stream)
@@ -453,32 +549,53 @@ def main():
         e[4].record(stream)
         cvb = rnd._preprocess("cam", cam, gs3.GS3_DEPTH_Z, False)
         e[5].record(stream)
-        gs3.gs3_render(ds, cam, light.eye, k, rnd.T, cvb, rnd._images(cam.width, cam.height), True)
+        gs3.gs3_shade(ds, cam, light.eye, cvb, im["colour"], True)
         e[6].record(stream)
+        gs3.gs3_render_shaded(ds, cam, light.eye, k, rnd.T, cvb, im, True)
+        e[7].record(stream)
     torch.cuda.synchronize()
-    stage = np.zeros(6)
+    stage = np.zeros(7)
     for e in ser:
-        for j in range(6):
+        for j in range(7):
             stage[j] += e[j].elapsed_time(e[j + 1])
     stage /= n_ser
     used = [stats[i % len(pairs)] for i in range(args.steps)]
     p_l, p_c, h_l, h_c = [float(np.mean([u[j] for u in used])) for j in range(4)]
+    ser_used = [stats[i % len(pairs)] for i in range(n_ser)]
+    sp_l, sp_c, sh_l = [float(np.mean([u[j] for u in ser_used])) for j in range(3)]
     # one roofline entry per shadow-splat kernel (both VALU-bound; the same
-    # hits, counted by gs3_view_count_hits); `roofline` is the longer one
+    # hits, counted by gs3_view_count_hits); `roofline` is the longer one.
+    # avg_launch_ms is the kernel alone (serial pass); the pipelined timed
+    # region's average, where other frames share the device, is beside it.
     kernels = []
-    for name, label, per_hit, ms in (
-            ("k_shadow", "k_shadow (shadow splat numerator, gs3_shadow_num)", SHADOW_NUM_FLOPS_PER_HIT, num_ms),
+    for name, label, per_hit, ms, ms_live in (
+            ("k_shadow", "k_shadow (shadow splat numerator, gs3_shadow_num)", SHADOW_NUM_FLOPS_PER_HIT,
+             stage[2], num_ms),
             ("k_shadow_den", "k_shadow_den (shadow splat denominator, gs3_shadow_den)", SHADOW_DEN_FLOPS_PER_HIT,
-             den_ms)):
-        tflops = h_l * per_hit / (ms / 1e3) / 1e12
+             stage[1], den_ms)):
+        tflops = sh_l * per_hit / (ms / 1e3) / 1e12
         kernels.append({"bound": "alu", "kernel": label, "achieved": round(tflops, 3),
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": profiled_traffic(name),
-                        "per_unit": f"{per_hit} flop per light-view hit", "units_per_launch": int(h_l),
-                        "avg_launch_ms": round(ms, 4)})
+                        "per_unit": f"{per_hit} flop per light-view hit", "units_per_launch": int(sh_l),
+                        "avg_launch_ms": round(float(ms), 4), "launches": n_ser,
+                        "avg_launch_ms_pipelined": round(float(ms_live), 4)})
     dominant = max(kernels, key=lambda r: r["avg_launch_ms"])
     fb = frame_bytes(sc.n, sc.k, p_l, p_c, 800 * 800)
     frame_gbs = fb / (wall / args.steps) / 1e9
+
+    def hbm(bytes_, ms):
+        gbs = bytes_ / (ms / 1e3) / 1e9
+        return {"bound": "hbm", "algorithmic_bytes": int(bytes_), "ms": round(float(ms), 4),
+                "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    stages_roofline = {
+        "light_preprocess": hbm(preprocess_bytes(sc.n, sp_l), stage[0]),
+        "camera_preprocess": hbm(preprocess_bytes(sc.n, sp_c), stage[4]),
+        "shade_psi": hbm(shade_bytes(sc.n, sc.k), stage[5]),
+        "shadow_den": {"bound": "alu", "frac": kernels[1]["frac"]},
+        "shadow_num": {"bound": "alu", "frac": kernels[0]["frac"]},
+    }
     out = {
         "metric": "relit frames/s @300k Gaussians 800^2 (1024^2 light splat)",
         "value": round(fps, 3),
@@ -491,17 +608,22 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_notes": "float32 throughout; the MLP hidden layers are float32 products formed from split "
+                       "half-precision MFMA operands (x = hi + lo/2048, three f16 products per block, about "
+                       "2^-22 relative; valid for |activations| < 65504)",
         "data": "synthetic (seeded scene and views; no trained weights exist for this workload)",
         "config": {"workload": "full relit forward: 300,000 Gaussians, 8 lobes, Phi and Psi 3x64, "
                                "camera 800x800, light 1024x1024, 40 deg fov, 4 view pairs",
                    "n_gaussians": sc.n, "camera": [800, 800], "light": [1024, 1024]},
         "roofline": dominant,
         "roofline_kernels": kernels,
+        "stages_roofline": stages_roofline,
         "frames_in_flight": args.inflight,
         "single_frame_fps": round(single_fps, 3),
         "stages_ms_serial": {"light_preprocess": round(stage[0], 4), "shadow_den": round(stage[1], 4),
                              "shadow_num": round(stage[2], 4), "shadow_resolve": round(stage[3], 4),
-                             "camera_preprocess": round(stage[4], 4), "shade_mlp_render": round(stage[5], 4)},
+                             "camera_preprocess": round(stage[4], 4), "shade_psi": round(stage[5], 4),
+                             "phi_camera_splat": round(stage[6], 4)},
         "work": {"pairs_light": int(p_l), "pairs_camera": int(p_c), "hits_light": int(h_l),
                  "hits_camera_blended": int(h_c)},
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),
@@ -521,6 +643,8 @@ def main():
                                            [float(x) for x in args.serving_loads.split(",") if x])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
+        if "train_step" in out:
+            out["train_step"]["cpu_baseline"] = cpu_baseline_train()
     print(json.dumps(out))
 
 

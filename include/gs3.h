@@ -305,18 +305,25 @@ int gs3_shadow_splat(const gs3_consts* consts, const gs3_viewbuf* light_vb,
  * that each can be timed or overlapped on its own; gs3_shadow_splat is
  * exactly gs3_shadow_den, gs3_shadow_num, gs3_shadow_resolve in that order.
  *   gs3_shadow_den      writes den_j = sum_m beta_jm into num_den[n .. 2n).
- *   gs3_shadow_num      writes num_j = sum_m beta_jm T_m(j) into
- *                       num_den[0 .. n); terms of a pixel whose transmittance
- *                       in front of j is below 2^-20 are left out, which
- *                       moves num_j / den_j by less than 2^-20.
- *   gs3_shadow_resolve  T[j] = num_j / den_j, or 1 where den_j = 0.
- * Same arguments, layout and errors as gs3_shadow_splat (T is not used by
- * the first two and num_den is only read by the third). */
+ *   gs3_shadow_num      accumulates num_j = sum_m beta_jm T_m(j) in the
+ *                       view workspace (one kernel; num_den is not touched);
+ *                       terms of a pixel whose transmittance in front of j
+ *                       is below 2^-20 are left out, which moves
+ *                       num_j / den_j by less than 2^-20. The accumulator
+ *                       starts at zero after gs3_project and after
+ *                       gs3_shadow_resolve, so each gs3_shadow_num must be
+ *                       followed by gs3_shadow_resolve before the next one
+ *                       on the same workspace.
+ *   gs3_shadow_resolve  writes num_j into num_den[0 .. n), T[j] = num_j /
+ *                       den_j (1 where den_j = 0), and clears the
+ *                       accumulator; reads den from num_den[n .. 2n).
+ * Same arguments, layout and errors as gs3_shadow_splat (T is only used by
+ * the third). */
 int gs3_shadow_den(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den,
                    gs3_stream_t stream);
 int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float* num_den,
                    gs3_stream_t stream);
-int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float* T, gs3_stream_t stream);
+int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs3_stream_t stream);
 
 /* Sec. 4.1-4.3 and Fig. 2 (steps a4-a6, a9): shade every Gaussian for the
  * point light at light_pos[3] (host) seen from the camera `cam`
@@ -395,6 +402,35 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
 int gs3_l1_loss_workspace_size(int64_t count, size_t* bytes);
 int gs3_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                 float* dL_dpred, void* ws, size_t ws_bytes, gs3_stream_t stream);
+
+/* Sec. 4.4, Eq. 9 (the D-SSIM term; lambda = 0.2 in the paper): SSIM with
+ * an 11x11 Gaussian window (sigma 1.5, normalised, zero outside the image),
+ * C1 = 0.01^2, C2 = 0.03^2, each of `channels` planes of pred and target
+ * ([channels][height][width] float32) on its own:
+ *   *loss = scale * sum over channels and pixels of (1 - SSIM)
+ * (scale = lambda / (channels height width) gives lambda times the mean
+ * D-SSIM), and unless dL_dpred is NULL its gradient with respect to pred,
+ * written (accumulate = 0) or added (accumulate != 0) to dL_dpred, so that
+ * it can follow gs3_l1_loss into the same buffer. target is not
+ * differentiated. The sum is formed in a fixed order (float64 per-tile
+ * partial sums added in tile order). `ws` (256-byte aligned,
+ * gs3_dssim_loss_workspace_size bytes) holds three per-pixel maps and the
+ * partial sums. Errors: GS3_INVALID_ARG (NULL pointer, size out of
+ * 1..64 x 1..16384 x 1..16384, misaligned ws), GS3_WORKSPACE_TOO_SMALL. */
+int gs3_dssim_loss_workspace_size(int32_t channels, int32_t height, int32_t width, size_t* bytes);
+int gs3_dssim_loss(const float* pred, const float* target, int32_t channels, int32_t height, int32_t width,
+                   float scale, float* loss, float* dL_dpred, int32_t accumulate, void* ws, size_t ws_bytes,
+                   gs3_stream_t stream);
+
+/* Sec. 4.4 (the optimiser: Adam with momentum beta1 = 0.9): one update of
+ * `count` float32 parameters in place, step t >= 1 the update's number:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   param -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * m and v (zeroed before step 1) are the caller's moment buffers. Errors:
+ * GS3_INVALID_ARG for NULL buffers, step < 1, betas outside [0, 1), eps < 0
+ * or a non-finite lr. */
+int gs3_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, int32_t step, float lr,
+                  float beta1, float beta2, float eps, gs3_stream_t stream);
 
 /* gs3_l1_loss for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

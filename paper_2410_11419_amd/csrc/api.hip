@@ -76,6 +76,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.ext = take(sizeof(int4) * n);
     l.drec = take(sizeof(int4) * n);
     l.cnt = take(sizeof(uint32_t) * n);
+    l.num = take(sizeof(float) * n);
     l.col0 = take(sizeof(float4) * n);
     l.col1 = take(sizeof(float4) * n);
     l.keys_a = take(sizeof(uint32_t) * n);
@@ -435,7 +436,7 @@ int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float*
     return GS3_OK;
 }
 
-int gs3_shadow_resolve(const gs3_viewbuf* light_vb, const float* num_den, float* T, gs3_stream_t stream) {
+int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs3_stream_t stream) {
     Layout L;
     int st;
     if ((st = check_vb(light_vb, &L)) != GS3_OK) return st;
@@ -663,6 +664,39 @@ int gs3_l1_loss(const float* pred, const float* target, int64_t count, float sca
     if (ws_bytes < need) return fail(GS3_WORKSPACE_TOO_SMALL, "loss workspace has %zu bytes, needs %zu", ws_bytes, need);
     GS3_CHECK_HIP(launch_l1_loss(pred, target, count, scale, loss, dL_dpred, static_cast<double*>(ws),
                                  (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_dssim_loss_workspace_size(int32_t channels, int32_t height, int32_t width, size_t* bytes) {
+    if (!bytes) return fail(GS3_INVALID_ARG, "bytes is NULL");
+    if (channels <= 0 || height <= 0 || width <= 0 || channels > 64 || height > 16384 || width > 16384)
+        return fail(GS3_INVALID_ARG, "invalid image size %d x %d x %d", channels, height, width);
+    *bytes = ssim_layout(channels, height, width).total;
+    return GS3_OK;
+}
+
+int gs3_dssim_loss(const float* pred, const float* target, int32_t channels, int32_t height, int32_t width,
+                   float scale, float* loss, float* dL_dpred, int32_t accumulate, void* ws, size_t ws_bytes,
+                   gs3_stream_t stream) {
+    size_t need;
+    int st;
+    if ((st = gs3_dssim_loss_workspace_size(channels, height, width, &need)) != GS3_OK) return st;
+    if (!pred || !target || !loss) return fail(GS3_INVALID_ARG, "pred / target / loss is NULL");
+    if (!ws) return fail(GS3_INVALID_ARG, "ws is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GS3_INVALID_ARG, "ws not 256-byte aligned");
+    if (ws_bytes < need) return fail(GS3_WORKSPACE_TOO_SMALL, "D-SSIM workspace has %zu bytes, needs %zu", ws_bytes, need);
+    GS3_CHECK_HIP(launch_dssim(pred, target, channels, height, width, scale, loss, dL_dpred, accumulate ? 1 : 0, ws,
+                               (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, int32_t step, float lr,
+                  float beta1, float beta2, float eps, gs3_stream_t stream) {
+    if (count < 0 || (count > 0 && (!param || !grad || !m || !v))) return fail(GS3_INVALID_ARG, "bad Adam buffers");
+    if (step < 1) return fail(GS3_INVALID_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f) || !std::isfinite(lr))
+        return fail(GS3_INVALID_ARG, "invalid Adam hyper-parameters");
+    GS3_CHECK_HIP(launch_adam(param, grad, m, v, count, step, lr, beta1, beta2, eps, (hipStream_t)stream));
     return GS3_OK;
 }
 

@@ -44,6 +44,7 @@ struct Layout {
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
     int32_t id_bits = 0;   // > 0: pairs are packed (tile << id_bits) | id while sorting
     size_t hdr = 0, rec0 = 0, rec1 = 0, rec2 = 0, depth = 0, ext = 0, drec = 0, cnt = 0, col0 = 0, col1 = 0;
+    size_t num = 0;   // shadow numerator accumulator [n]: cleared by the projection and by the resolve
     size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
     size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0, order = 0;
     size_t total = 0;
@@ -96,11 +97,11 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
                               const int32_t* ry, const float* depth, const Layout& L,
                               void* ws, hipStream_t st);
 hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st);
-hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws,
+hipError_t launch_shadow(const gs3_consts& k, const Layout& L, void* ws,
                          float* num_den, float* T, hipStream_t st);
-hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
-hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st);
-hipError_t launch_shadow_resolve(const Layout& L, const void* ws, const float* num_den, float* T, hipStream_t st);
+hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st);
+hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st);
+hipError_t launch_shadow_resolve(const Layout& L, void* ws, float* num_den, float* T, hipStream_t st);
 struct ShadeParams {
     float light[3];
     float eye[3];
@@ -146,6 +147,16 @@ int64_t l1_chunks(int64_t count);
 hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                           float* grad, double* partial, hipStream_t st);
 hipError_t launch_accumulate(float* dst, const float* src, int64_t count, hipStream_t st);
+// D-SSIM workspace: the adjoint maps a, b, c and the per-tile partial sums.
+struct SsimLayout {
+    int tiles_x = 0, tiles_y = 0;
+    size_t amap = 0, bmap = 0, cmap = 0, partial = 0, total = 0;
+};
+SsimLayout ssim_layout(int channels, int height, int width);
+hipError_t launch_dssim(const float* pred, const float* target, int channels, int height, int width, float scale,
+                        float* loss, float* grad, int accumulate, void* ws, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
 hipError_t launch_export_lists(const Layout& L, const void* ws, int32_t* start, int32_t* end, int32_t* ids,
                                uint64_t* keys, hipStream_t st);
 hipError_t launch_count_hits(const gs3_consts& k, const Layout& L, const void* ws, int stop_early,

@@ -38,10 +38,11 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
                                                   float4* __restrict__ rec2, float* __restrict__ depth_out, int4* __restrict__ ext,
                                                   int4* __restrict__ drec,
                                                   uint32_t* __restrict__ cnt, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals) {
+                                                  uint32_t* __restrict__ vals, float* __restrict__ num) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = sc.n;
     if (i >= n) return;
+    num[i] = 0.f;   // the shadow numerator's accumulator starts empty for every projection
     const double mx = sc.mean[i], my = sc.mean[n + i], mz = sc.mean[2 * n + i];
     const double s0 = exp((double)sc.log_scale[i]);
     const double s1 = exp((double)sc.log_scale[n + i]);
@@ -157,7 +158,7 @@ hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_co
     hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, st, sc, vp, k, at<float4>(ws, L.rec0),
                        at<float4>(ws, L.rec1), at<float4>(ws, L.rec2), at<float>(ws, L.depth), at<int4>(ws, L.ext),
                        at<int4>(ws, L.drec), at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.keys_a),
-                       at<uint32_t>(ws, L.vals_a));
+                       at<uint32_t>(ws, L.vals_a), at<float>(ws, L.num));
     return hipGetLastError();
 }
 
@@ -175,6 +176,7 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec2), 0u, 4 * L.n, st);
     // no denominator work: the empty range {1, 1, 0, 0} in every word pair
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.drec), 1u, 4 * L.n, st);
+    if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.num), 0u, L.n, st);
     return e != hipSuccess ? e : hipGetLastError();
 }
 

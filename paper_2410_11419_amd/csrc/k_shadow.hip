@@ -407,19 +407,25 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
     }
 }
 
-// T = num / den (1 where den = 0). A binning that overflowed its pair
-// capacity left the tile lists empty, so num is missing every term: T is
-// then NaN, not a plausible value.
-__global__ __launch_bounds__(256) void k_shadow_finish(const float* __restrict__ num, const float* __restrict__ den,
+// T = num / den (1 where den = 0), with num taken from the view's
+// accumulator, which is handed to the caller's num_den and cleared for the
+// next numerator pass. A binning that overflowed its pair capacity left the
+// tile lists empty, so num is missing every term: T is then NaN, not a
+// plausible value.
+__global__ __launch_bounds__(256) void k_shadow_finish(float* __restrict__ acc, float* __restrict__ num,
+                                                        const float* __restrict__ den,
                                                         const ViewHeader* __restrict__ hdr, float* __restrict__ T,
                                                         int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const float t = den[i] > 0.f ? num[i] / den[i] : 1.f;
+    const float nu = acc[i];
+    acc[i] = 0.f;
+    num[i] = nu;
+    const float t = den[i] > 0.f ? nu / den[i] : 1.f;
     T[i] = hdr->overflow ? __builtin_nanf("") : t;
 }
 
-static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* ws, float* num_den) {
+static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, void* ws, float* num_den) {
     ShadowArgs a;
     a.ranges = at<int2>(ws, L.ranges);
     a.order = at<uint32_t>(ws, L.order);
@@ -436,12 +442,12 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, const void* 
     a.n_tiles = (int)L.n_tiles;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
-    a.num = num_den;
+    a.num = at<float>(ws, L.num);   // the view's accumulator
     a.den = num_den + L.n;
     return a;
 }
 
-hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st) {
+hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
     int grid = (int)((L.n + 3) / 4);
     if (grid > 32768) grid = 32768;
@@ -449,23 +455,21 @@ hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, const void* w
     return hipGetLastError();
 }
 
-hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, hipStream_t st) {
-    if (L.n == 0) return hipSuccess;
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(num_den), 0u, L.n, st);
-    if (e != hipSuccess) return e;
-    if (L.n_tiles == 0) return hipSuccess;
+hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st) {
+    if (L.n == 0 || L.n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_shadow, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, shadow_args(k, L, ws, num_den));
     return hipGetLastError();
 }
 
-hipError_t launch_shadow_resolve(const Layout& L, const void* ws, const float* num_den, float* T, hipStream_t st) {
+hipError_t launch_shadow_resolve(const Layout& L, void* ws, float* num_den, float* T, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, num_den,
-                       num_den + L.n, at<ViewHeader>(ws, L.hdr), T, (int)L.n);
+    hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st,
+                       at<float>(ws, L.num), num_den, num_den + L.n,
+                       at<ViewHeader>(ws, L.hdr), T, (int)L.n);
     return hipGetLastError();
 }
 
-hipError_t launch_shadow(const gs3_consts& k, const Layout& L, const void* ws, float* num_den, float* T,
+hipError_t launch_shadow(const gs3_consts& k, const Layout& L, void* ws, float* num_den, float* T,
                          hipStream_t st) {
     hipError_t e = launch_shadow_den(k, L, ws, num_den, st);
     if (e == hipSuccess) e = launch_shadow_num(k, L, ws, num_den, st);

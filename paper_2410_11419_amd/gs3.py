@@ -39,7 +39,7 @@ EXPORTED = [
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
     "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
-    "gs3_l1_loss_noalloc",
+    "gs3_l1_loss_noalloc", "gs3_dssim_loss_workspace_size", "gs3_dssim_loss", "gs3_adam_step",
 ]
 GS3_VIEW_PENDING, GS3_VIEW_OK, GS3_VIEW_OVERFLOW = 0, 1, 2
 
@@ -125,6 +125,11 @@ def _load():
                                   C.c_void_p, C.c_size_t, C.c_void_p]),
         "gs3_l1_loss_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
                                           C.c_void_p]),
+        "gs3_dssim_loss_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P(C.c_size_t)]),
+        "gs3_dssim_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+        "gs3_adam_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
         "gs3_grads_clear": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "gs3_grads_accumulate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     }
@@ -417,6 +422,34 @@ def gs3_l1_loss_noalloc(pred: torch.Tensor, target: torch.Tensor, scale: float, 
         raise ValueError("pred, target and grad must have the same number of elements")
     _check(_lib.gs3_l1_loss_noalloc(_ptr(pred), _ptr(target), count, float(scale), _ptr(loss), _ptr(grad),
                                     _stream()), "gs3_l1_loss_noalloc")
+
+
+def dssim_workspace(channels: int, height: int, width: int, device="cuda") -> torch.Tensor:
+    size = C.c_size_t()
+    _check(_lib.gs3_dssim_loss_workspace_size(channels, height, width, C.byref(size)),
+           "gs3_dssim_loss_workspace_size")
+    return torch.empty(size.value + 256, dtype=torch.uint8, device=device)
+
+
+def gs3_dssim_loss(pred: torch.Tensor, target: torch.Tensor, scale: float, loss: torch.Tensor,
+                   grad: Optional[torch.Tensor], ws: torch.Tensor, accumulate: bool = False):
+    """loss[0] = scale * sum (1 - SSIM) over the [C, H, W] images; grad (if
+    given) gets (or, with accumulate, adds) its gradient."""
+    if pred.dim() != 3 or pred.shape != target.shape or (grad is not None and grad.shape != pred.shape):
+        raise ValueError("pred, target and grad must be [C, H, W] of one shape")
+    c, h, w = pred.shape
+    wsp, wsb = _aligned(ws)
+    _check(_lib.gs3_dssim_loss(_ptr(pred), _ptr(target), c, h, w, float(scale), _ptr(loss), _ptr(grad),
+                               int(bool(accumulate)), wsp, wsb, _stream()), "gs3_dssim_loss")
+
+
+def gs3_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+                  lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15):
+    n = param.numel()
+    if not (grad.numel() == m.numel() == v.numel() == n):
+        raise ValueError("param, grad, m and v must have one size")
+    _check(_lib.gs3_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n, int(step), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream()), "gs3_adam_step")
 
 
 def gs3_grads_clear(g: torch.Tensor):
