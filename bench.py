@@ -41,6 +41,14 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "shadow_splat_300k_light1024.md
 KERNEL_SOURCES = ("paper_2410_11419_amd/csrc/k_shadow.hip", "paper_2410_11419_amd/csrc/splat_common.h")
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg: str):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +331,7 @@ def serving_bench(ds, requests, loads):
            "loads": []}
     for f in loads:
         qps = f * plain_sat["frames_per_s"]
+        log(f"serving at {f} of plain saturation ({qps:.0f} requests/s)")
         rq = serve.make_requests(requests, qps=qps, seed=3)
         a = serve.summarize(serve.run_plain(ds, rq))
         b = serve.summarize(srv.run(rq))
@@ -465,6 +474,7 @@ def main():
         print(f"profiled {args.profile_steps} frames and one {src.numel() * 4 >> 20} MiB copy")
         return
 
+    log("scene resident; counting pairs and hits")
     # work units of each pair: pairs and hits of both views
     stats = []
     k = rnd.consts
@@ -492,6 +502,7 @@ def main():
     for i in range(args.warmup):
         fp.render(*pairs[i % len(pairs)], overlap=False)
     torch.cuda.synchronize()
+    log(f"timing {args.steps} frames, {args.inflight} in flight")
     evs = [{k: torch.cuda.Event(enable_timing=True) for k in ("f0", "den0", "den1", "num0", "num1", "f1")}
            for _ in range(args.steps)]
     t0 = time.perf_counter()
@@ -629,19 +640,24 @@ def main():
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),
                       "frac_of_8TBs": round(frame_gbs / HBM_PEAK_GBS, 4)},
     }
+    log(f"frames: {fps:.1f} frames/s; single frame {single_fps:.1f} frames/s")
     side = torch.cuda.Stream()      # the default stream would serialize the side streams
     if args.train_steps > 0:
+        log("train step (300K, batch 4)")
         with torch.cuda.stream(side):
             out["train_step"] = train_step_bench(ds, sc, args.train_steps, 1)
     if args.fluffy_steps > 0:
+        log("train step (dense 1.5M, batch 8)")
         with torch.cuda.stream(side):
             out["train_step_fluffy"] = fluffy_train_bench(args.fluffy_steps, lanes=args.lanes)
     if args.serving_requests > 0:
+        log("serving")
         del rnd, fp, single
         with torch.cuda.stream(side):
             out["serving"] = serving_bench(ds, args.serving_requests,
                                            [float(x) for x in args.serving_loads.split(",") if x])
     if not args.no_cpu_baseline:
+        log("CPU baseline (the oracle)")
         out["cpu_baseline"] = cpu_baseline(args.n)
         if "train_step" in out:
             out["train_step"]["cpu_baseline"] = cpu_baseline_train()
