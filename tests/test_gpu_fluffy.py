@@ -240,12 +240,12 @@ def test_fluffy_banded_denominator(run):
     # shadow values of the thinnest banded needles
     pth_all = O.hit_threshold(op, k).numpy()
     ell = np.pi * 2 * pth_all / np.sqrt(np.maximum(det, 1e-30))
-    # lit needles (shadow values well inside (0, 1)), so the check has
-    # occluders to get right
+    # the most lit thin needles (few rays in this dense volume stay lit), so
+    # the check has occluders to get right and a value to get
     T_g = res["T"][:n]
-    cand = np.nonzero(banded & (ell > 60) & (ell < 400) & (res["num_den"][1, :n] > 0) &
-                      (T_g > 0.2) & (T_g < 0.95))[0]
-    needles = cand[np.argsort(ell[cand])[:4]]
+    cand = np.nonzero(banded & (ell > 60) & (ell < 800) & (res["num_den"][1, :n] > 0) &
+                      (T_g > 1e-3) & (T_g < 0.999))[0]
+    needles = cand[np.argsort(-T_g[cand])[:4]]
     worst = 0.0
     for j in needles:
         # the light pixels the needle hits, or may hit by rounding
