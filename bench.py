@@ -340,6 +340,23 @@ def serving_bench(ds, requests, loads):
                              "server": {k: round(v, 3) for k, v in b.items() if k != "requests"}})
     out["buffer_sets"] = len(srv.sets)
     del srv
+    # light sharing: requests under a set of 8 point lights (a light stage's
+    # OLAT set) share one shadow pass per light
+    shared = serve.make_requests(requests, qps=1e6, seed=3, n_lights=8)
+    log("serving with 8 shared lights")
+    a = serve.summarize(serve.run_plain(ds, shared))
+    srv_s = serve.Server(ds, mem_cap_bytes=24 << 30, share_lights=True)
+    srv_s.run(serve.make_requests(16, qps=1e6, seed=9, n_lights=8))
+    b = serve.summarize(srv_s.run(shared))
+    srv_n = serve.Server(ds, mem_cap_bytes=24 << 30)
+    srv_n.run(warm)
+    c = serve.summarize(srv_n.run(shared))
+    out["light_sharing"] = {"lights": 8, "requests": requests,
+                            "saturation_frames_per_s": {"plain": round(a["frames_per_s"], 1),
+                                                        "server": round(c["frames_per_s"], 1),
+                                                        "server_shared_lights": round(b["frames_per_s"], 1)},
+                            "shadow_passes_shared": srv_s.light_passes}
+    del srv_s, srv_n
     torch.cuda.synchronize()
     return out
 

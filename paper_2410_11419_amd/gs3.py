@@ -598,6 +598,19 @@ class Renderer:
             self.images[key] = im
         return im
 
+    def render_shadowed(self, cam, light, T: torch.Tensor, check: bool = True) -> Dict[str, torch.Tensor]:
+        """Relit frame for camera ``cam`` under the point light of view
+        ``light`` whose shadow values ``T`` [n] were already computed (by a
+        render of the same light view): only the camera path runs (camera
+        preprocess, shading + MLPs, camera splat). Used to share one shadow
+        splat among requests with the same light."""
+        cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
+        im = self._images(cam.width, cam.height)
+        gs3_render(self.scene, cam, light.eye, self.consts, T, cvb, im, self.use_mlps)
+        out = dict(im)
+        out["T"] = T
+        return out
+
     def render(self, cam, light, check: bool = True, overlap: bool = True,
                events: Optional[Dict[str, torch.cuda.Event]] = None) -> Dict[str, torch.Tensor]:
         """Relit frame for camera view ``cam`` and the point light of view

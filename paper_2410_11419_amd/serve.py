@@ -11,6 +11,14 @@ detected with events, without blocking the host; a finished request frees
 its buffer set for the next one. The plain baseline runs the same library
 calls one request at a time, first come first served, and waits for each.
 
+With ``share_lights`` the server also shares shadow splats: requests whose
+light view is the same (position, target, resolution, field of view) reuse
+one shadow pass (light preprocess, shadow splat, per-Gaussian T; Sec. 4.2
+computes T per light, independent of the camera). The first such request
+runs it and keeps a copy of T; later ones wait for that copy on the device
+(a stream wait on its event) and run only their camera path. Copies are
+kept for the most recently used lights, within the memory cap.
+
 Latency of a request = completion time - arrival time (queueing included).
 """
 from __future__ import annotations
@@ -18,7 +26,7 @@ from __future__ import annotations
 import dataclasses
 import math
 import time
-from collections import deque
+from collections import OrderedDict, deque
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -49,17 +57,29 @@ class Result:
 
 
 def make_requests(count: int, qps: float, seed: int = 3, resolutions=(256, 512, 800, 1024),
-                  light_res: int = 1024, fov: float = 40.0, radius: float = 4.0) -> List[Request]:
+                  light_res: int = 1024, fov: float = 40.0, radius: float = 4.0,
+                  n_lights: Optional[int] = None) -> List[Request]:
     """Poisson arrivals at rate qps; camera and light uniform on the sphere
-    of the given radius; camera resolution uniform over `resolutions`."""
+    of the given radius; camera resolution uniform over `resolutions`. With
+    `n_lights`, each request's light is drawn from a fixed set of that many
+    lights (a light stage's set of point lights) instead."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / qps, count) if qps > 0 else np.zeros(count)
     t = np.cumsum(gaps) - gaps[0]
+    light_set = None
+    if n_lights:
+        lrng = np.random.default_rng(seed + 1000)
+        light_set = [synth.make_view(lrng.standard_normal(3), radius, light_res, light_res, fov)
+                     for _ in range(n_lights)]
     out = []
     for i in range(count):
         r = int(resolutions[rng.integers(0, len(resolutions))])
         cam = synth.make_view(rng.standard_normal(3), radius, r, r, fov)
-        light = synth.make_view(rng.standard_normal(3), radius, light_res, light_res, fov)
+        d = rng.standard_normal(3)
+        if light_set is not None:
+            light = light_set[int(rng.integers(0, n_lights))]
+        else:
+            light = synth.make_view(d, radius, light_res, light_res, fov)
         out.append(Request(i, float(t[i]), cam, light))
     return out
 
@@ -103,11 +123,25 @@ class BufferSet:
             3 * max(n, 1) * 4
 
 
+@dataclasses.dataclass
+class LightEntry:
+    """A shared shadow pass: T of one light view, valid once `event` has
+    completed on the device."""
+    T: torch.Tensor
+    event: torch.cuda.Event
+
+
+def light_key(light: synth.View) -> tuple:
+    return (tuple(float(x) for x in light.eye), tuple(float(x) for x in light.target), light.width,
+            light.height, float(light.fov))
+
+
 class Server:
     """Admission by a memory cap over per-resolution pools of buffer sets."""
 
     def __init__(self, scene: gs3.DeviceScene, mem_cap_bytes: int, consts=None, light_res: int = 1024,
-                 capacity: Optional[int] = None, max_inflight: int = 8, overlap="auto"):
+                 capacity: Optional[int] = None, max_inflight: int = 8, overlap="auto",
+                 share_lights: bool = False, max_lights: int = 256):
         self.scene = scene
         self.consts = consts if consts is not None else gs3.default_consts()
         self.cap = int(mem_cap_bytes)
@@ -121,6 +155,10 @@ class Server:
         self.free: Dict[int, List[BufferSet]] = {}
         self.allocated = 0
         self.sets: List[BufferSet] = []
+        self.share_lights = share_lights
+        self.max_lights = max_lights
+        self.lights: "OrderedDict[tuple, LightEntry]" = OrderedDict()
+        self.light_passes = 0          # shadow passes run (not shared)
 
     def _acquire(self, res: int) -> Optional[BufferSet]:
         pool = self.free.setdefault(res, [])
@@ -149,11 +187,39 @@ class Server:
 
     def _launch(self, req: Request, bs: BufferSet, keep: bool, n_inflight: int = 0):
         overlap = (n_inflight < 2) if self.overlap == "auto" else bool(self.overlap)
+        key = light_key(req.light) if self.share_lights else None
+        entry = self.lights.get(key) if key is not None else None
         with torch.cuda.stream(bs.stream):
-            out = bs.renderer.render(req.cam, req.light, check=False, overlap=overlap)
+            if entry is not None:
+                # the light's shadow values exist (or are being computed):
+                # wait for them on the device, run only the camera path
+                self.lights.move_to_end(key)
+                bs.stream.wait_event(entry.event)
+                entry.T.record_stream(bs.stream)     # not reused while this stream reads it
+                out = bs.renderer.render_shadowed(req.cam, req.light, entry.T, check=False)
+            else:
+                out = bs.renderer.render(req.cam, req.light, check=False, overlap=overlap)
+                self.light_passes += 1
+                if key is not None:
+                    self._keep_light(key, out["T"], bs.stream)
             final = out["final"].clone() if keep else None
             bs.event.record(bs.stream)
         return final
+
+    def _keep_light(self, key, T: torch.Tensor, stream):
+        """Keep a copy of a light's shadow values for later requests (LRU;
+        the oldest copies go when the count or the memory cap is reached)."""
+        nbytes = T.numel() * T.element_size()
+        while self.lights and (len(self.lights) >= self.max_lights or self.allocated + nbytes > self.cap):
+            _, old = self.lights.popitem(last=False)
+            self.allocated -= old.T.numel() * old.T.element_size()
+        if self.allocated + nbytes > self.cap:
+            return
+        ev = torch.cuda.Event()
+        copy = T.clone()           # on `stream`, after the shadow splat that wrote T
+        ev.record(stream)
+        self.lights[key] = LightEntry(copy, ev)
+        self.allocated += nbytes
 
     def _check_done(self, bs: BufferSet, req: Request, keep: bool) -> Optional[torch.Tensor]:
         """After completion: a binning that overflowed its pair capacity is
@@ -213,7 +279,9 @@ class Server:
                 progressed = True
             if not progressed:
                 if inflight:
-                    time.sleep(20e-6)
+                    # poll again at once: a sleep would add its granularity
+                    # (tens of microseconds) to every completion
+                    pass
                 elif pending:
                     time.sleep(max(0.0, min(1e-3, pending[0].arrival - (time.perf_counter() - t0))))
         return [results[r.rid] for r in requests]

@@ -104,3 +104,22 @@ def test_memory_cap_with_mixed_resolutions(env):
     print(f"cap {cap} bytes, peak allocated {peak}, sets {len(srv.sets)}")
     assert peak <= cap and srv.allocated <= cap
     assert all(r.final is not None for r in got)
+
+
+def test_shared_lights_equal_alone(env):
+    """Light sharing: 24 requests of mixed resolution under 3 distinct
+    lights run 3 shadow passes, and every result equals the request
+    rendered alone."""
+    gs3, serve, ds = env
+    reqs = serve.make_requests(24, qps=1e6, seed=12, resolutions=(96, 160, 256), light_res=256, n_lights=3)
+    assert len({serve.light_key(r.light) for r in reqs}) == 3
+    srv = serve.Server(ds, mem_cap_bytes=4 << 30, light_res=256, max_inflight=6, share_lights=True)
+    got = srv.run(reqs, keep_results=True)
+    rnd = gs3.Renderer(ds)
+    worst = 0.0
+    for req, res in zip(reqs, got):
+        alone = rnd.render(req.cam, req.light)["final"]
+        worst = max(worst, float((res.final - alone).abs().max()))
+    print(f"shadow passes {srv.light_passes} for 24 requests, max |served - alone| = {worst:.2e}")
+    assert srv.light_passes == 3
+    assert worst <= 1e-4
