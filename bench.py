@@ -577,9 +577,9 @@ def main():
         e[4].record(stream)
         cvb = rnd._preprocess("cam", cam, gs3.GS3_DEPTH_Z, False)
         e[5].record(stream)
-        gs3.gs3_shade(ds, cam, light.eye, cvb, im["colour"], True)
+        gs3.gs3_shade(ds, cam, light, cvb, im["colour"], True)
         e[6].record(stream)
-        gs3.gs3_render_shaded(ds, cam, light.eye, k, rnd.T, cvb, im, True)
+        gs3.gs3_render_shaded(ds, cam, light, k, rnd.T, cvb, im, True)
         e[7].record(stream)
     torch.cuda.synchronize()
     stage = np.zeros(7)

@@ -86,18 +86,30 @@ typedef struct {
     float shadow_bias;
 } gs3_consts;
 
-/* A pinhole view looking from `eye` at `target` (host values). Camera axes:
- * x right, y down, z forward; world up +z (+y when the view direction is
- * within acos(0.99) of +-z). Focal length (width/2)/tan(fov/2) in pixels,
- * square pixels, principal point (width/2, height/2), pixel (i, j) centred
- * at (i + 0.5, j + 0.5). A point light is a view whose eye is the light
- * (Sec. 4.2: a perspective camera centred at the light). */
+/* A view looking from `eye` at `target` (host values). Camera axes: x
+ * right, y down, z forward; world up +z (+y when the view direction is
+ * within acos(0.99) of +-z); square pixels, principal point (width/2,
+ * height/2), pixel (i, j) centred at (i + 0.5, j + 0.5).
+ *   GS3_PERSPECTIVE   pinhole, focal length (width/2)/tan(fov/2) pixels. A
+ *                     point light is such a view whose eye is the light
+ *                     (Sec. 4.2: a perspective camera centred at the light).
+ *   GS3_ORTHOGRAPHIC  parallel projection, width/ortho_width pixels per world
+ *                     unit; x_pixel = scale * x_view + width/2. A directional
+ *                     light is such a view (Sec. 4.5: the shadow splat switches
+ *                     to an orthographic projection); it shines along
+ *                     target - eye, and its distance key is the view-space z
+ *                     (depth along the light direction from the eye's plane),
+ *                     so the eye must lie outside the scene, on the lit side.
+ * The near plane culls Gaussians with view-space z <= near_plane in both. */
+enum { GS3_PERSPECTIVE = 0, GS3_ORTHOGRAPHIC = 1 };
 typedef struct {
     double eye[3];
     double target[3];
     int32_t width;
     int32_t height;
-    double fov; /* horizontal field of view, radians, in (0, pi) */
+    double fov;          /* perspective: horizontal field of view, radians, in (0, pi) */
+    int32_t projection;  /* GS3_PERSPECTIVE or GS3_ORTHOGRAPHIC */
+    double ortho_width;  /* orthographic: world units across the image width, > 0 */
 } gs3_view;
 
 /* Raw (pre-activation) per-Gaussian parameters, device float32 SoA.
@@ -326,7 +338,10 @@ int gs3_shadow_num(const gs3_consts* consts, const gs3_viewbuf* light_vb, float*
 int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs3_stream_t stream);
 
 /* Sec. 4.1-4.3 and Fig. 2 (steps a4-a6, a9): shade every Gaussian for the
- * point light at light_pos[3] (host) seen from the camera `cam`
+ * light of view `light` (a perspective view: a point light at light->eye,
+ * w_i the unit vector from the Gaussian to it; an orthographic view: a
+ * directional light, w_i = (eye - target) / |eye - target| for every
+ * Gaussian; Sec. 4.5) seen from the camera `cam`
  * (c = rho_d f_d + sum_k amp_k G_k, Eq. 4-7, isotropic lobes, unit light),
  * refine T with Phi (T' = T if phi is NULL), evaluate Psi (r = 0 if psi is
  * NULL), then splat c, T' and r toward the camera front to back and write
@@ -337,7 +352,7 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs
  * about 2^-22 relative per product), which assumes hidden activations and
  * weights below the half range (65504). */
 int gs3_render(const gs3_scene* scene, const gs3_view* cam,
-               const double* light_pos, const gs3_consts* consts,
+               const gs3_view* light, const gs3_consts* consts,
                const float* T, const gs3_mlp* phi, const gs3_mlp* psi,
                const gs3_viewbuf* cam_vb, const gs3_images* out,
                gs3_stream_t stream);
@@ -353,9 +368,9 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam,
  *                      splat of Fig. 2 and final = S * Sh + R. Needs the
  *                      gs3_shade of the same camera and light first.
  * Arguments, layouts and errors as in gs3_render. */
-int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
               const gs3_mlp* psi, const gs3_viewbuf* cam_vb, float* colour, gs3_stream_t stream);
-int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
                       const gs3_consts* consts, const float* T, const gs3_mlp* phi,
                       const gs3_viewbuf* cam_vb, const gs3_images* out, gs3_stream_t stream);
 
@@ -444,6 +459,13 @@ int gs3_adam_step(float* param, const float* grad, float* m, float* v, int64_t c
  * stream are safe, each fully rewriting the partial sums it reads. */
 int gs3_l1_loss_noalloc(const float* pred, const float* target, int64_t count, float scale, float* loss,
                         float* dL_dpred, gs3_stream_t stream);
+
+/* Sec. 4.5 (environment lighting as a linear combination of the renders
+ * under sampled directional lights): dst[i] += weight * src[i] over `count`
+ * float32 of device memory (dst and src must not overlap). Errors:
+ * GS3_INVALID_ARG for count < 0, a NULL pointer with count > 0 or a
+ * non-finite weight. */
+int gs3_image_accumulate(float* dst, const float* src, float weight, int64_t count, gs3_stream_t stream);
 
 /* Gradient-set upkeep of a training step (Sec. 4.4): gs3_render_backward
  * adds into its gradients, so a step clears them first, and views whose

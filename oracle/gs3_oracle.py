@@ -38,7 +38,8 @@ __all__ = [
     "lobe_frame", "shade", "mlp_forward", "camera_pass", "render",
     "render_images", "sigmoid", "l1_loss", "hit_threshold", "hit_margin", "transmittance_relerr",
     "AMB_BUDGET", "HIT_KAPPA", "pair_key", "ssim_window", "ssim_map", "dssim_loss", "adam_step",
-    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "LOSS_LAMBDA", "CANDIDATE_CUT",
+    "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "LOSS_LAMBDA", "CANDIDATE_CUT", "is_ortho",
+    "render_env",
 ]
 
 DT = torch.float64
@@ -157,6 +158,11 @@ def focal(view) -> float:
     return (view.width / 2.0) / math.tan(view.fov / 2.0)
 
 
+def is_ortho(view) -> bool:
+    """An orthographic view (a directional light, Sec. 4.5)."""
+    return getattr(view, "projection", "perspective") == "orthographic"
+
+
 def project(mean: torch.Tensor, cov: torch.Tensor, view, consts: Consts,
             depth_mode: str) -> Dict[str, torch.Tensor]:
     """Project 3D Gaussians to 2D splats (Sec. 3; EWA splatting as in GS).
@@ -165,23 +171,35 @@ def project(mean: torch.Tensor, cov: torch.Tensor, view, consts: Consts,
     with x/z, y/z clamped to +-clamp_frac*tan(half fov); Sigma' = J R_v Sigma
     R_v^T J^T + dilation*I; cull det <= 0; conic = Sigma'^-1; centre
     (f t_x/t_z + W/2, f t_y/t_z + H/2). The depth key is t_z for the camera
-    ("z") and |mu - eye| toward the light ("dist", Sec. 4.2)."""
+    ("z") and |mu - eye| toward the light ("dist", Sec. 4.2).
+
+    An orthographic view (a directional light: Sec. 4.5 switches the shadow
+    splat to an orthographic projection) maps t to (s t_x + W/2, s t_y +
+    H/2) with s = W / ortho_width pixels per world unit, so J = [[s, 0, 0],
+    [0, s, 0]]; its distance key is t_z, the depth along the light
+    direction."""
     W, H = view.width, view.height
-    f = focal(view)
     Rv = look_at(view.eye, view.target)
     eye = as_t(view.eye)
     t = (mean - eye) @ Rv.T
     tz = t[:, 2]
     valid = tz > consts.near
     tzs = torch.where(valid, tz, torch.ones_like(tz))
-    lim_x = consts.clamp_frac * (W / 2.0) / f
-    lim_y = consts.clamp_frac * (H / 2.0) / f
-    xr = torch.clamp(t[:, 0] / tzs, -lim_x, lim_x)
-    yr = torch.clamp(t[:, 1] / tzs, -lim_y, lim_y)
     zero = torch.zeros_like(tz)
-    J = torch.stack([
-        torch.stack([f / tzs, zero, -f * xr / tzs], -1),
-        torch.stack([zero, f / tzs, -f * yr / tzs], -1)], 1)        # [N,2,3]
+    ortho = is_ortho(view)
+    if ortho:
+        f = W / view.ortho_width
+        sv = torch.full_like(tz, f)
+        J = torch.stack([torch.stack([sv, zero, zero], -1), torch.stack([zero, sv, zero], -1)], 1)
+    else:
+        f = focal(view)
+        lim_x = consts.clamp_frac * (W / 2.0) / f
+        lim_y = consts.clamp_frac * (H / 2.0) / f
+        xr = torch.clamp(t[:, 0] / tzs, -lim_x, lim_x)
+        yr = torch.clamp(t[:, 1] / tzs, -lim_y, lim_y)
+        J = torch.stack([
+            torch.stack([f / tzs, zero, -f * xr / tzs], -1),
+            torch.stack([zero, f / tzs, -f * yr / tzs], -1)], 1)        # [N,2,3]
     cov_cam = Rv @ cov @ Rv.T
     cov2 = J @ cov_cam @ J.transpose(1, 2)
     a = cov2[:, 0, 0] + consts.dilation
@@ -191,9 +209,13 @@ def project(mean: torch.Tensor, cov: torch.Tensor, view, consts: Consts,
     valid = valid & (det > 0)
     dets = torch.where(valid, det, torch.ones_like(det))
     conic = torch.stack([c / dets, -b / dets, a / dets], -1)
-    u = f * t[:, 0] / tzs + W / 2.0
-    v = f * t[:, 1] / tzs + H / 2.0
-    if depth_mode == "z":
+    if ortho:
+        u = f * t[:, 0] + W / 2.0
+        v = f * t[:, 1] + H / 2.0
+    else:
+        u = f * t[:, 0] / tzs + W / 2.0
+        v = f * t[:, 1] / tzs + H / 2.0
+    if depth_mode == "z" or (depth_mode == "dist" and ortho):
         depth = tz
     elif depth_mode == "dist":
         depth = torch.linalg.norm(mean - eye, dim=-1)
@@ -628,7 +650,7 @@ def angular_gaussian(h, x, y, z, sx, sy, sz):
     return torch.exp(-0.5 * (theta * aniso / sz) ** 2) / sz
 
 
-def shade(p: Dict[str, torch.Tensor], light_pos, eye) -> Dict[str, torch.Tensor]:
+def shade(p: Dict[str, torch.Tensor], light_pos, eye, light_dir=None) -> Dict[str, torch.Tensor]:
     """First splatting (Sec. 4.1, Eq. 4): per-Gaussian colour
     c = rho_d f_d(w_i') + sum_k amp_k G_k(h') in the Gaussian's shading frame.
 
@@ -637,10 +659,16 @@ def shade(p: Dict[str, torch.Tensor], light_pos, eye) -> Dict[str, torch.Tensor]
     quaternion; n' = +z. Lobes are isotropic (sigma_x = sigma_y = 1) with
     sigma_z = exp(-log_sharp) and axis normalised in the shading frame;
     amp_k is the lobe's RGB weight (alpha_j rho_s of Eq. 4/6). Unit light
-    intensity, no distance fall-off."""
+    intensity, no distance fall-off. With ``light_dir`` (a directional
+    light, Sec. 4.5) w_i is that unit direction toward the light for every
+    Gaussian."""
     mu = p["mean"]
-    wi = as_t(light_pos) - mu
-    wi = wi / torch.linalg.norm(wi, dim=-1, keepdim=True)
+    if light_dir is not None:
+        d = as_t(light_dir)
+        wi = (d / torch.linalg.norm(d)).expand_as(mu)
+    else:
+        wi = as_t(light_pos) - mu
+        wi = wi / torch.linalg.norm(wi, dim=-1, keepdim=True)
     wo = as_t(eye) - mu
     wo = wo / torch.linalg.norm(wo, dim=-1, keepdim=True)
     Rsh = quat_to_rotmat(p["shade_rot"])
@@ -788,7 +816,10 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
     with torch.no_grad():
         amb_T = torch.where(den > 0, infl / torch.where(den > 0, den, torch.ones_like(den)),
                             torch.where(infl > 0, torch.ones_like(infl), torch.zeros_like(infl)))
-    sh = shade(p, light_pos, cam_view.eye)
+    if is_ortho(light_view):
+        sh = shade(p, None, cam_view.eye, light_dir=np.asarray(light_view.eye) - np.asarray(light_view.target))
+    else:
+        sh = shade(p, light_pos, cam_view.eye)
     if phi is not None:
         tp = mlp_forward(phi, torch.cat([T[:, None], p["feat"]], 1))[:, 0]
         with torch.enable_grad():
@@ -815,6 +846,17 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
             "amb_T": amb_T, "amb_px": amb_px, "proj_l": proj_l, "proj_c": proj_c,
             "opacity": opacity, "amb_light_keys": cat(lk), "amb_cam_keys": cat(ck),
             "amb_stop_keys": cat(sk)}
+
+
+def render_env(scene, cam_view, light_views, weights, consts: Consts = Consts(), **kw) -> torch.Tensor:
+    """Environment lighting (Sec. 4.5): the linear combination
+    sum_k w_k final_k of the renders under directional lights (orthographic
+    light views) sampled from the environment. Returns final [3, P]."""
+    out = None
+    for lv, w in zip(light_views, weights):
+        f = render(scene, cam_view, lv, consts, **kw)["final"] * float(w)
+        out = f if out is None else out + f
+    return out
 
 
 # --------------------------------------------------------------- training

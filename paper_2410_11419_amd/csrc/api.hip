@@ -211,7 +211,12 @@ static int view_params(const gs3_view* v, const Layout& L, int depth_mode, ViewP
     if (v->width != L.width || v->height != L.height)
         return fail(GS3_INVALID_ARG, "view size %dx%d does not match the view buffer %dx%d", v->width, v->height,
                     L.width, L.height);
-    if (!(v->fov > 0.0 && v->fov < M_PI)) return fail(GS3_INVALID_ARG, "fov must be in (0, pi)");
+    if (v->projection != GS3_PERSPECTIVE && v->projection != GS3_ORTHOGRAPHIC)
+        return fail(GS3_INVALID_ARG, "bad projection");
+    const bool ortho = v->projection == GS3_ORTHOGRAPHIC;
+    if (ortho && !(v->ortho_width > 0.0 && std::isfinite(v->ortho_width)))
+        return fail(GS3_INVALID_ARG, "ortho_width must be positive");
+    if (!ortho && !(v->fov > 0.0 && v->fov < M_PI)) return fail(GS3_INVALID_ARG, "fov must be in (0, pi)");
     if (depth_mode != GS3_DEPTH_Z && depth_mode != GS3_DEPTH_DIST) return fail(GS3_INVALID_ARG, "bad depth_mode");
     double f[3] = {v->target[0] - v->eye[0], v->target[1] - v->eye[1], v->target[2] - v->eye[2]};
     const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
@@ -228,7 +233,9 @@ static int view_params(const gs3_view* v, const Layout& L, int depth_mode, ViewP
         vp->R[6 + i] = f[i];
         vp->eye[i] = v->eye[i];
     }
-    vp->focal = (v->width / 2.0) / std::tan(v->fov / 2.0);
+    vp->ortho = ortho ? 1 : 0;
+    vp->scale = ortho ? v->width / v->ortho_width : 0.0;
+    vp->focal = ortho ? vp->scale : (v->width / 2.0) / std::tan(v->fov / 2.0);
     vp->cx = v->width / 2.0;
     vp->cy = v->height / 2.0;
     vp->width = L.width;
@@ -446,7 +453,7 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs
     return GS3_OK;
 }
 
-static int render_args(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+static int render_args(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
                        const gs3_consts* consts, const gs3_viewbuf* cam_vb, Layout* L) {
     int st;
     if ((st = check_vb(cam_vb, L)) != GS3_OK) return st;
@@ -456,28 +463,49 @@ static int render_args(const gs3_scene* scene, const gs3_view* cam, const double
     if (scene->n != cam_vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbuf.n");
     if (!cam || cam->width != L->width || cam->height != L->height)
         return fail(GS3_INVALID_ARG, "camera view missing or its size differs from the view buffer");
-    if (!light_pos) return fail(GS3_INVALID_ARG, "light_pos is NULL");
+    if (!light) return fail(GS3_INVALID_ARG, "light view is NULL");
+    if (light->projection == GS3_ORTHOGRAPHIC) {
+        const double d[3] = {light->eye[0] - light->target[0], light->eye[1] - light->target[1],
+                             light->eye[2] - light->target[2]};
+        if (!(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0.0)) return fail(GS3_INVALID_ARG, "light eye and target coincide");
+    } else if (light->projection != GS3_PERSPECTIVE) {
+        return fail(GS3_INVALID_ARG, "bad light projection");
+    }
     return GS3_OK;
 }
 
-static ShadeParams shade_params(const gs3_view* cam, const double* light_pos, const gs3_mlp* phi,
+// The light of the shading: a point light at the eye of a perspective light
+// view, or (orthographic light view) a directional light whose unit
+// direction toward the light is stored instead (Sec. 4.5).
+static void shade_light(const gs3_view* light, ShadeParams* sp) {
+    if (light->projection == GS3_ORTHOGRAPHIC) {
+        double d[3] = {light->eye[0] - light->target[0], light->eye[1] - light->target[1],
+                       light->eye[2] - light->target[2]};
+        const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int i = 0; i < 3; ++i) sp->light[i] = (float)(d[i] / dn);
+        sp->light_dir = 1;
+    } else {
+        for (int i = 0; i < 3; ++i) sp->light[i] = (float)light->eye[i];
+        sp->light_dir = 0;
+    }
+}
+
+static ShadeParams shade_params(const gs3_view* cam, const gs3_view* light, const gs3_mlp* phi,
                                 const gs3_mlp* psi) {
     ShadeParams sp;
-    for (int i = 0; i < 3; ++i) {
-        sp.light[i] = (float)light_pos[i];
-        sp.eye[i] = (float)cam->eye[i];
-    }
+    shade_light(light, &sp);
+    for (int i = 0; i < 3; ++i) sp.eye[i] = (float)cam->eye[i];
     sp.use_phi = phi != nullptr;
     sp.use_psi = psi != nullptr;
     return sp;
 }
 
-int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_consts* consts,
+int gs3_render(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light, const gs3_consts* consts,
                const float* T, const gs3_mlp* phi, const gs3_mlp* psi, const gs3_viewbuf* cam_vb,
                const gs3_images* out, gs3_stream_t stream) {
     Layout L;
     int st;
-    if ((st = render_args(scene, cam, light_pos, consts, cam_vb, &L)) != GS3_OK) return st;
+    if ((st = render_args(scene, cam, light, consts, cam_vb, &L)) != GS3_OK) return st;
     if (!consts) return fail(GS3_INVALID_ARG, "consts is NULL");
     if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
         !out->n_contrib || !out->colour)
@@ -485,39 +513,39 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam, const double* light_
     if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
     if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
     if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
-    const ShadeParams sp = shade_params(cam, light_pos, phi, psi);
+    const ShadeParams sp = shade_params(cam, light, phi, psi);
     hipStream_t s = (hipStream_t)stream;
     GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, cam_vb->ws, out->colour, 3, s));
     GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
     return GS3_OK;
 }
 
-int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const double* light_pos, const gs3_mlp* psi,
+int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light, const gs3_mlp* psi,
               const gs3_viewbuf* cam_vb, float* colour, gs3_stream_t stream) {
     Layout L;
     int st;
-    if ((st = render_args(scene, cam, light_pos, nullptr, cam_vb, &L)) != GS3_OK) return st;
+    if ((st = render_args(scene, cam, light, nullptr, cam_vb, &L)) != GS3_OK) return st;
     if (!colour) return fail(GS3_INVALID_ARG, "colour is NULL");
     if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
-    const ShadeParams sp = shade_params(cam, light_pos, nullptr, psi);
+    const ShadeParams sp = shade_params(cam, light, nullptr, psi);
     GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, nullptr, nullptr, psi, L, cam_vb->ws, colour, 1,
                                    (hipStream_t)stream));
     return GS3_OK;
 }
 
-int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const double* light_pos,
+int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light,
                       const gs3_consts* consts, const float* T, const gs3_mlp* phi, const gs3_viewbuf* cam_vb,
                       const gs3_images* out, gs3_stream_t stream) {
     Layout L;
     int st;
-    if ((st = render_args(scene, cam, light_pos, consts, cam_vb, &L)) != GS3_OK) return st;
+    if ((st = render_args(scene, cam, light, consts, cam_vb, &L)) != GS3_OK) return st;
     if (!consts) return fail(GS3_INVALID_ARG, "consts is NULL");
     if (!out || !out->final_rgb || !out->shading || !out->shadow || !out->residual || !out->t_final ||
         !out->n_contrib || !out->colour)
         return fail(GS3_INVALID_ARG, "an output pointer is NULL");
     if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
     if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
-    const ShadeParams sp = shade_params(cam, light_pos, phi, nullptr);
+    const ShadeParams sp = shade_params(cam, light, phi, nullptr);
     hipStream_t s = (hipStream_t)stream;
     GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, nullptr, L, cam_vb->ws, out->colour, 2, s));
     GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
@@ -631,10 +659,8 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     g.lobe_amp = grads->lobe_amp;
     g.feat = grads->feat;
     ShadeParams sp;
-    for (int i = 0; i < 3; ++i) {
-        sp.light[i] = (float)light->eye[i];
-        sp.eye[i] = (float)cam->eye[i];
-    }
+    shade_light(light, &sp);
+    for (int i = 0; i < 3; ++i) sp.eye[i] = (float)cam->eye[i];
     sp.use_phi = phi != nullptr;
     sp.use_psi = psi != nullptr;
     const SceneDev sd = scene_dev(scene);
@@ -697,6 +723,13 @@ int gs3_adam_step(float* param, const float* grad, float* m, float* v, int64_t c
     if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f) || !std::isfinite(lr))
         return fail(GS3_INVALID_ARG, "invalid Adam hyper-parameters");
     GS3_CHECK_HIP(launch_adam(param, grad, m, v, count, step, lr, beta1, beta2, eps, (hipStream_t)stream));
+    return GS3_OK;
+}
+
+int gs3_image_accumulate(float* dst, const float* src, float weight, int64_t count, gs3_stream_t stream) {
+    if (count < 0 || (count > 0 && (!dst || !src))) return fail(GS3_INVALID_ARG, "bad image buffers");
+    if (!std::isfinite(weight)) return fail(GS3_INVALID_ARG, "weight is not finite");
+    GS3_CHECK_HIP(launch_accumulate_scaled(dst, src, weight, count, (hipStream_t)stream));
     return GS3_OK;
 }
 

@@ -73,6 +73,8 @@ struct ViewParams {
     double lim_x, lim_y;  // clamp of x/z, y/z in the Jacobian
     int32_t width, height, tiles_x, tiles_y;
     int32_t depth_mode;
+    int32_t ortho;      // 1: orthographic (x_pixel = scale x_view + cx), 0: pinhole
+    double scale;       // orthographic: pixels per world unit
 };
 
 struct SceneDev {
@@ -103,9 +105,10 @@ hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, void* ws, flo
 hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st);
 hipError_t launch_shadow_resolve(const Layout& L, void* ws, float* num_den, float* T, hipStream_t st);
 struct ShadeParams {
-    float light[3];
+    float light[3];     // point light position, or (light_dir) unit direction toward the light
     float eye[3];
     int32_t use_phi, use_psi;
+    int32_t light_dir;  // 1: directional light (w_i = light for every Gaussian)
 };
 // parts: 1 = shading c and Psi's r, 2 = Phi's T', 3 = both
 hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T,
@@ -147,6 +150,7 @@ int64_t l1_chunks(int64_t count);
 hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                           float* grad, double* partial, hipStream_t st);
 hipError_t launch_accumulate(float* dst, const float* src, int64_t count, hipStream_t st);
+hipError_t launch_accumulate_scaled(float* dst, const float* src, float w, int64_t count, hipStream_t st);
 // D-SSIM workspace: the adjoint maps a, b, c and the per-tile partial sums.
 struct SsimLayout {
     int tiles_x = 0, tiles_y = 0;

@@ -29,9 +29,10 @@ static_assert(kShadeBwdSmem * 4 <= 160 * 1024, "shading adjoint LDS exceeds 160 
 
 struct ShadeBwdArgs {
     SceneDev sc;
-    float light[3];
+    float light[3];      // point light, or (light_dir) unit direction toward the light
     float eye[3];
     int use_phi, use_psi;
+    int light_dir;
     const float* T;
     MlpArgs phi, psi;
     const float* gcol;   // [7][n] dL/d{c.rgb, T', r.rgb}
@@ -97,7 +98,9 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         const int g = valid ? g_raw : n - 1;
         // ---- forward recompute of the shading inputs
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
-        float wix = a.light[0] - mx, wiy = a.light[1] - my, wiz = a.light[2] - mz;
+        // w_i: toward a point light, or a directional light's fixed direction
+        const float lm = a.light_dir ? 0.f : 1.f;
+        float wix = a.light[0] - lm * mx, wiy = a.light[1] - lm * my, wiz = a.light[2] - lm * mz;
         const float ri = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
         wix *= ri; wiy *= ri; wiz *= ri;
         float wox = a.eye[0] - mx, woy = a.eye[1] - my, woz = a.eye[2] - mz;
@@ -316,12 +319,14 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         const float dox = R00 * dlox + R10 * dloy + R20 * dloz + pdox;
         const float doy = R01 * dlox + R11 * dloy + R21 * dloz + pdoy;
         const float doz = R02 * dlox + R12 * dloy + R22 * dloz + pdoz;
-        // w = (p - mu)/|p - mu|: dmu = -(dw - (dw.w) w) / |p - mu|
+        // w = (p - mu)/|p - mu|: dmu = -(dw - (dw.w) w) / |p - mu|; a
+        // directional light's w_i does not depend on mu
         const float wd = dwx * wix + dwy * wiy + dwz * wiz;
         const float od = dox * wox + doy * woy + doz * woz;
-        const float dmx = -(dwx - wd * wix) * ri - (dox - od * wox) * ro;
-        const float dmy = -(dwy - wd * wiy) * ri - (doy - od * woy) * ro;
-        const float dmz = -(dwz - wd * wiz) * ri - (doz - od * woz) * ro;
+        const float rim = lm * ri;
+        const float dmx = -(dwx - wd * wix) * rim - (dox - od * wox) * ro;
+        const float dmy = -(dwy - wd * wiy) * rim - (doy - od * woy) * ro;
+        const float dmz = -(dwz - wd * wiz) * rim - (doz - od * woz) * ro;
         if (valid && q == 0) {
             a.g.albedo[g] += dc0 * fd;
             a.g.albedo[n + g] += dc1 * fd;
@@ -511,11 +516,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         const double tz = vp.R[6] * dx + vp.R[7] * dy + vp.R[8] * dz;
         if (!(tz > (double)a.kc.near_plane)) continue;
         const double f = vp.focal;
+        const bool ortho = vp.ortho != 0;
         const double xs = tx / tz, ys = ty / tz;
         const bool cx_ = xs < -vp.lim_x || xs > vp.lim_x, cy_ = ys < -vp.lim_y || ys > vp.lim_y;
         const double xr = fmin(fmax(xs, -vp.lim_x), vp.lim_x);
         const double yr = fmin(fmax(ys, -vp.lim_y), vp.lim_y);
-        const double j0 = f / tz, j2x = -f * xr / tz, j2y = -f * yr / tz;
+        // J of the forward projection: pinhole, or the constant scale of a
+        // parallel projection (no dependence on the position)
+        const double j0 = ortho ? vp.scale : f / tz;
+        const double j2x = ortho ? 0.0 : -f * xr / tz, j2y = ortho ? 0.0 : -f * yr / tz;
         double A[6];
         for (int c = 0; c < 3; ++c) {
             A[c] = j0 * vp.R[c] + j2x * vp.R[6 + c];
@@ -554,6 +563,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
             gj2y += gA_[3 + c] * vp.R[6 + c];
         }
         double gtx = 0.0, gty = 0.0, gtz = 0.0;
+        if (ortho) {
+            // u = s t_x + cx, v = s t_y + cy; J constant
+            gtx = gu * vp.scale;
+            gty = gv * vp.scale;
+            for (int c = 0; c < 3; ++c) gmean[c] += vp.R[c] * gtx + vp.R[3 + c] * gty;
+            continue;
+        }
         gtz += gj0 * (-f / (tz * tz));
         if (cx_) {
             gtz += gj2x * (f * xr / (tz * tz));
@@ -624,6 +640,7 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     }
     a.use_phi = phi != nullptr;
     a.use_psi = psi != nullptr;
+    a.light_dir = sp.light_dir;
     a.T = T;
     for (int i = 0; i < 4; ++i) {
         a.phi.w[i] = phi ? phi->w[i] : nullptr;

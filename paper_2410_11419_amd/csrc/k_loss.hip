@@ -101,6 +101,21 @@ hipError_t launch_accumulate(float* dst, const float* src, int64_t count, hipStr
     return hipGetLastError();
 }
 
+// dst += w * src (the weighted sum of an environment light's renders).
+__global__ __launch_bounds__(256) void k_accumulate_scaled(float* __restrict__ dst, const float* __restrict__ src,
+                                                            float w, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) dst[i] = fmaf(w, src[i], dst[i]);
+}
+
+hipError_t launch_accumulate_scaled(float* dst, const float* src, float w, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t grid = (count + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_accumulate_scaled, dim3((unsigned)grid), dim3(256), 0, st, dst, src, w, count);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------ no-allocation variant
 //
 // gs3_l1_loss_noalloc keeps its partial sums in this file-scope array

@@ -62,15 +62,19 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
     const double tx = vp.R[0] * dx + vp.R[1] * dy + vp.R[2] * dz;
     const double ty = vp.R[3] * dx + vp.R[4] * dy + vp.R[5] * dz;
     const double tz = vp.R[6] * dx + vp.R[7] * dy + vp.R[8] * dz;
-    const double dep = vp.depth_mode == GS3_DEPTH_DIST ? sqrt(dx * dx + dy * dy + dz * dz) : tz;
+    // distance key: to the light's position (perspective), or along the
+    // light's direction (orthographic: a directional light, Sec. 4.5)
+    const double dep = vp.depth_mode == GS3_DEPTH_DIST && !vp.ortho ? sqrt(dx * dx + dy * dy + dz * dz) : tz;
 
     bool ok = tz > (double)kc.near_plane;
     const double tzs = ok ? tz : 1.0;
     const double f = vp.focal;
     const double xr = fmin(fmax(tx / tzs, -vp.lim_x), vp.lim_x);
     const double yr = fmin(fmax(ty / tzs, -vp.lim_y), vp.lim_y);
-    // A = J R_v (2x3) with J = [[f/z, 0, -f xr/z], [0, f/z, -f yr/z]]
-    const double j0 = f / tzs, j2x = -f * xr / tzs, j2y = -f * yr / tzs;
+    // A = J R_v (2x3) with J = [[f/z, 0, -f xr/z], [0, f/z, -f yr/z]], or
+    // for a parallel projection J = [[s, 0, 0], [0, s, 0]]
+    const double j0 = vp.ortho ? vp.scale : f / tzs;
+    const double j2x = vp.ortho ? 0.0 : -f * xr / tzs, j2y = vp.ortho ? 0.0 : -f * yr / tzs;
     const double A00 = j0 * vp.R[0] + j2x * vp.R[6], A01 = j0 * vp.R[1] + j2x * vp.R[7], A02 = j0 * vp.R[2] + j2x * vp.R[8];
     const double A10 = j0 * vp.R[3] + j2y * vp.R[6], A11 = j0 * vp.R[4] + j2y * vp.R[7], A12 = j0 * vp.R[5] + j2y * vp.R[8];
     // B = A M (2x3); Sigma' = B B^T
@@ -85,8 +89,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3
     const double cc = B10 * B10 + B11 * B11 + B12 * B12 + (double)kc.dilation;
     const double det = ca * cc - cb * cb;
     ok = ok && det > 0.0;
-    const double u = f * tx / tzs + vp.cx;
-    const double v = f * ty / tzs + vp.cy;
+    const double u = (vp.ortho ? vp.scale * tx : f * tx / tzs) + vp.cx;
+    const double v = (vp.ortho ? vp.scale * ty : f * ty / tzs) + vp.cy;
     const double logit = sc.opacity_logit[i];
     const double opac = 1.0 / (1.0 + exp(-logit));
     // hit ellipse: power >= -p with p = min(cutoff, ln(opacity / alpha_min))

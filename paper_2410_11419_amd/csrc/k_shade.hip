@@ -16,9 +16,10 @@ enum ShadeParts { kShadePsi = 1, kShadePhi = 2 };
 
 struct ShadeArgs {
     SceneDev sc;
-    float light[3];
+    float light[3];      // point light, or (light_dir) unit direction toward the light
     float eye[3];
     int use_phi, use_psi;
+    int light_dir;
     int parts;
     const float* T;
     MlpArgs phi, psi;
@@ -47,7 +48,9 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
         if (a.parts & kShadePsi) {
         // ---- shading (Eq. 4-7)
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
-        wix = a.light[0] - mx; wiy = a.light[1] - my; wiz = a.light[2] - mz;
+        // w_i: toward a point light, or a directional light's fixed direction
+        const float lm = a.light_dir ? 0.f : 1.f;
+        wix = a.light[0] - lm * mx; wiy = a.light[1] - lm * my; wiz = a.light[2] - lm * mz;
         float r = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
         wix *= r; wiy *= r; wiz *= r;
         wox = a.eye[0] - mx; woy = a.eye[1] - my; woz = a.eye[2] - mz;
@@ -181,6 +184,7 @@ hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const flo
     }
     a.use_phi = phi != nullptr;
     a.use_psi = psi != nullptr;
+    a.light_dir = sp.light_dir;
     a.T = T;
     for (int i = 0; i < 4; ++i) {
         a.phi.w[i] = phi ? phi->w[i] : nullptr;

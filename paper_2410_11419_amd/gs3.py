@@ -40,6 +40,7 @@ EXPORTED = [
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
     "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
     "gs3_l1_loss_noalloc", "gs3_dssim_loss_workspace_size", "gs3_dssim_loss", "gs3_adam_step",
+    "gs3_image_accumulate",
 ]
 GS3_VIEW_PENDING, GS3_VIEW_OK, GS3_VIEW_OVERFLOW = 0, 1, 2
 
@@ -50,9 +51,13 @@ class gs3_consts(C.Structure):
                 ("t_min", C.c_float), ("shadow_bias", C.c_float)]
 
 
+GS3_PERSPECTIVE, GS3_ORTHOGRAPHIC = 0, 1
+
+
 class gs3_view(C.Structure):
     _fields_ = [("eye", C.c_double * 3), ("target", C.c_double * 3), ("width", C.c_int32),
-                ("height", C.c_int32), ("fov", C.c_double)]
+                ("height", C.c_int32), ("fov", C.c_double), ("projection", C.c_int32),
+                ("ortho_width", C.c_double)]
 
 
 class gs3_scene(C.Structure):
@@ -108,17 +113,18 @@ def _load():
         "gs3_shadow_num": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_void_p, C.c_void_p]),
         "gs3_shadow_resolve": (C.c_int, [P(gs3_viewbuf), C.c_void_p, C.c_void_p, C.c_void_p]),
         "gs3_sort": (C.c_int, [P(gs3_viewbuf), C.c_void_p]),
-        "gs3_shade": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_mlp), P(gs3_viewbuf),
+        "gs3_shade": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_mlp), P(gs3_viewbuf),
                                 C.c_void_p, C.c_void_p]),
-        "gs3_render_shaded": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
+        "gs3_render_shaded": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                         P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
         "gs3_backward_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, P(C.c_size_t)]),
         "gs3_render_backward": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                           C.c_void_p, P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_viewbuf),
                                           P(gs3_images), C.c_void_p, P(gs3_grads), C.c_void_p, C.c_size_t,
                                           C.c_void_p]),
-        "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_double * 3), P(gs3_consts), C.c_void_p,
+        "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                  P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
+        "gs3_image_accumulate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_float, C.c_int64, C.c_void_p]),
         "gs3_view_poll": (C.c_int, [P(gs3_viewbuf), P(C.c_int32), P(C.c_int64)]),
         "gs3_l1_loss_workspace_size": (C.c_int, [C.c_int64, P(C.c_size_t)]),
         "gs3_l1_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
@@ -183,7 +189,8 @@ def make_consts(**kw) -> gs3_consts:
 
 
 def make_view(view) -> gs3_view:
-    """``view`` has eye, target, width, height, fov (radians)."""
+    """``view`` has eye, target, width, height, fov (radians) and optionally
+    projection ("perspective" / "orthographic") and ortho_width."""
     v = gs3_view()
     for i in range(3):
         v.eye[i] = float(view.eye[i])
@@ -191,6 +198,9 @@ def make_view(view) -> gs3_view:
     v.width = int(view.width)
     v.height = int(view.height)
     v.fov = float(view.fov)
+    ortho = getattr(view, "projection", "perspective") == "orthographic"
+    v.projection = GS3_ORTHOGRAPHIC if ortho else GS3_PERSPECTIVE
+    v.ortho_width = float(getattr(view, "ortho_width", 0.0))
     return v
 
 
@@ -358,10 +368,12 @@ def gs3_shadow_resolve(light_vb: ViewBuffer, num_den: torch.Tensor, T: torch.Ten
     _check(_lib.gs3_shadow_resolve(C.byref(light_vb.vb), _ptr(num_den), _ptr(T), _stream()), "gs3_shadow_resolve")
 
 
-def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
+def gs3_render(scene: DeviceScene, cam, light, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
                images: Dict[str, torch.Tensor], use_mlps: bool = True):
+    """``light`` is the light's view: perspective for a point light at its
+    eye, orthographic for a directional light."""
     v = make_view(cam)
-    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    lp = make_view(light)
     phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
     psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
     im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
@@ -371,19 +383,19 @@ def gs3_render(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.
                            C.byref(cam_vb.vb), C.byref(im), _stream()), "gs3_render")
 
 
-def gs3_shade(scene: DeviceScene, cam, light_pos, cam_vb: ViewBuffer, colour: torch.Tensor, use_mlps: bool = True):
+def gs3_shade(scene: DeviceScene, cam, light, cam_vb: ViewBuffer, colour: torch.Tensor, use_mlps: bool = True):
     v = make_view(cam)
-    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    lp = make_view(light)
     psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
     _check(_lib.gs3_shade(C.byref(scene.c_struct()), C.byref(v), C.byref(lp),
                           C.byref(psi) if psi is not None else None, C.byref(cam_vb.vb), _ptr(colour), _stream()),
            "gs3_shade")
 
 
-def gs3_render_shaded(scene: DeviceScene, cam, light_pos, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
+def gs3_render_shaded(scene: DeviceScene, cam, light, consts: gs3_consts, T: torch.Tensor, cam_vb: ViewBuffer,
                       images: Dict[str, torch.Tensor], use_mlps: bool = True):
     v = make_view(cam)
-    lp = (C.c_double * 3)(*[float(x) for x in light_pos])
+    lp = make_view(light)
     phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
     im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
     _check(_lib.gs3_render_shaded(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
@@ -450,6 +462,14 @@ def gs3_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: t
         raise ValueError("param, grad, m and v must have one size")
     _check(_lib.gs3_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), n, int(step), float(lr), float(beta1),
                               float(beta2), float(eps), _stream()), "gs3_adam_step")
+
+
+def gs3_image_accumulate(dst: torch.Tensor, src: torch.Tensor, weight: float):
+    """dst += weight * src (float32 device tensors of one size)."""
+    if dst.dtype != torch.float32 or src.dtype != torch.float32 or dst.numel() != src.numel():
+        raise ValueError("images must be float32 of one size")
+    _check(_lib.gs3_image_accumulate(_ptr(dst), _ptr(src), float(weight), dst.numel(), _stream()),
+           "gs3_image_accumulate")
 
 
 def gs3_grads_clear(g: torch.Tensor):
@@ -606,7 +626,7 @@ class Renderer:
         splat among requests with the same light."""
         cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
         im = self._images(cam.width, cam.height)
-        gs3_render(self.scene, cam, light.eye, self.consts, T, cvb, im, self.use_mlps)
+        gs3_render(self.scene, cam, light, self.consts, T, cvb, im, self.use_mlps)
         out = dict(im)
         out["T"] = T
         return out
@@ -675,21 +695,44 @@ class Renderer:
             s_cam.wait_event(ev_start)
             with torch.cuda.stream(s_cam):
                 cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
-                gs3_shade(self.scene, cam, light.eye, cvb, im["colour"], self.use_mlps)
+                gs3_shade(self.scene, cam, light, cvb, im["colour"], self.use_mlps)
             main.wait_stream(s_den)
             gs3_shadow_resolve(lvb, self.num_den, self.T)
             main.wait_stream(s_cam)
-            gs3_render_shaded(self.scene, cam, light.eye, self.consts, self.T, cvb, im, self.use_mlps)
+            gs3_render_shaded(self.scene, cam, light, self.consts, self.T, cvb, im, self.use_mlps)
             out = dict(im)
             out["T"] = self.T
             out["num_den"] = self.num_den
             return out
         im = self._images(cam.width, cam.height)
-        gs3_render(self.scene, cam, light.eye, self.consts, self.T, cvb, im, self.use_mlps)
+        gs3_render(self.scene, cam, light, self.consts, self.T, cvb, im, self.use_mlps)
         out = dict(im)
         out["T"] = self.T
         out["num_den"] = self.num_den
         return out
+
+    def render_env(self, cam, lights: Sequence, weights: Sequence[float], check: bool = True) -> torch.Tensor:
+        """Environment lighting (Sec. 4.5): the weighted sum of the relit
+        frames of ``cam`` under each light of ``lights`` (directional lights:
+        orthographic light views, synth.environment_lights) with
+        ``weights``. The camera preprocess runs once; each light runs its
+        own light preprocess, shadow splat, shading and camera splat, and
+        its frame is added into the result with gs3_image_accumulate.
+        Returns a new [3, H, W] tensor."""
+        if len(lights) != len(weights) or not len(lights):
+            raise ValueError("one weight per light, at least one light")
+        cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, check)
+        im = self._images(cam.width, cam.height)
+        env = torch.empty(3, cam.height, cam.width, device=self.dev)
+        gs3_grads_clear(env)
+        for light, w in zip(lights, weights):
+            lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
+            gs3_shadow_den(self.consts, lvb, self.num_den)
+            gs3_shadow_num(self.consts, lvb, self.num_den)
+            gs3_shadow_resolve(lvb, self.num_den, self.T)
+            gs3_render(self.scene, cam, light, self.consts, self.T, cvb, im, self.use_mlps)
+            gs3_image_accumulate(env, im["final"], float(w))
+        return env
 
     def backward(self, cam, light, dL_dfinal: torch.Tensor, grads: Optional["DeviceGrads"] = None) -> "DeviceGrads":
         """Adjoint of the last ``render(cam, light)`` of this renderer (its

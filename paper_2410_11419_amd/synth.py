@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "Scene", "View", "Mlp", "make_scene", "make_view", "random_views",
     "scene_small", "scene_full", "scene_fluffy", "fluffy_pairs", "scene_gradcheck",
-    "perturb_scene", "subset", "concat_scenes", "scene_needles",
+    "perturb_scene", "subset", "concat_scenes", "scene_needles", "make_directional", "environment_lights",
 ]
 
 FEAT_DIM = 16
@@ -80,12 +80,16 @@ class Scene:
 
 @dataclasses.dataclass
 class View:
-    """Pinhole view looking at ``target``; ``fov`` is horizontal, radians."""
+    """View looking at ``target``: a pinhole (``fov`` horizontal, radians)
+    or, with projection "orthographic", a parallel projection whose image
+    spans ``ortho_width`` world units across (a directional light)."""
     eye: np.ndarray      # [3] float64
     target: np.ndarray   # [3] float64
     width: int
     height: int
     fov: float
+    projection: str = "perspective"
+    ortho_width: float = 0.0
 
 
 def _unit_rows(v: np.ndarray) -> np.ndarray:
@@ -179,6 +183,38 @@ def make_view(direction, radius: float, width: int, height: int, fov_deg: float,
     d = d / np.linalg.norm(d)
     return View(eye=d * radius, target=np.asarray(target, np.float64),
                 width=int(width), height=int(height), fov=math.radians(fov_deg))
+
+
+def make_directional(direction, width: int, height: int, ortho_width: float, radius: float = 4.0) -> View:
+    """A directional light shining from `direction` toward the origin: an
+    orthographic view whose eye sits at `radius` along the direction."""
+    d = np.asarray(direction, np.float64)
+    d = d / np.linalg.norm(d)
+    return View(eye=d * radius, target=np.zeros(3), width=int(width), height=int(height), fov=0.0,
+                projection="orthographic", ortho_width=float(ortho_width))
+
+
+def environment_lights(count: int, seed: int, width: int, height: int, ortho_width: float):
+    """`count` directional lights on a Fibonacci sphere (a seeded random
+    rotation of it) with weights from a synthetic sky: w proportional to
+    0.2 + max(0, d_z)^2 (a bright zenith), normalised to sum to 1. Stands in
+    for the directions and weights sampled from an environment map."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(count) + 0.5
+    z = 1 - 2 * i / count
+    phi = np.pi * (1 + 5 ** 0.5) * i
+    r = np.sqrt(1 - z * z)
+    dirs = np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w_, x, y, zq = q
+    R = np.array([[1 - 2 * (y * y + zq * zq), 2 * (x * y - w_ * zq), 2 * (x * zq + w_ * y)],
+                  [2 * (x * y + w_ * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w_ * x)],
+                  [2 * (x * zq - w_ * y), 2 * (y * zq + w_ * x), 1 - 2 * (x * x + y * y)]])
+    dirs = dirs @ R.T
+    w = 0.2 + np.maximum(dirs[:, 2], 0.0) ** 2
+    w = w / w.sum()
+    return [make_directional(d, width, height, ortho_width) for d in dirs], w
 
 
 def random_views(count: int, seed: int, radius: float, width: int, height: int,

@@ -104,7 +104,8 @@ def test_status_block_reports_overflow_without_the_device():
     scene.n, scene.k = 100, 0
     for nm in ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo", "feat"):
         setattr(scene, nm, 512)
-    lp = (C.c_double * 3)(0.0, 4.0, 0.0)
+    lp = gs3.gs3_view()
+    lp.eye[1], lp.width, lp.height, lp.fov = 4.0, 64, 64, 0.7
     im = gs3.gs3_images(*([512] * 7))
     assert gs3._lib.gs3_render(C.byref(scene), C.byref(cam), C.byref(lp), C.byref(k), fake, None, None, C.byref(vb),
                                C.byref(im), None) == gs3.GS3_PAIR_CAPACITY_EXCEEDED
@@ -141,3 +142,24 @@ def test_loss_and_gradient_set_argument_checks():
     assert gs3._lib.gs3_grads_clear(None, 5, None) == gs3.GS3_INVALID_ARG
     assert gs3._lib.gs3_grads_clear(p, -1, None) == gs3.GS3_INVALID_ARG
     assert gs3._lib.gs3_grads_accumulate(p, None, 5, None) == gs3.GS3_INVALID_ARG
+
+
+def test_view_projection_checks():
+    """Orthographic views need a positive width; unknown projections are
+    refused (before any device work)."""
+    from paper_2410_11419_amd import gs3
+    size = C.c_size_t()
+    assert gs3._lib.gs3_view_workspace_size(10, 64, 64, 1000, C.byref(size)) == 0
+    vb = gs3.gs3_viewbuf(C.c_void_p(256), size.value, 10, 64, 64, 1000, None)
+    scene = gs3.gs3_scene()
+    scene.n, scene.k = 10, 0
+    for nm in ("mean", "log_scale", "rot", "opacity_logit"):
+        setattr(scene, nm, 512)
+    k = gs3.default_consts()
+    v = gs3.gs3_view()
+    v.eye[2], v.width, v.height = 4.0, 64, 64
+    v.projection, v.ortho_width = gs3.GS3_ORTHOGRAPHIC, 0.0
+    assert gs3._lib.gs3_project(C.byref(scene), C.byref(v), C.byref(k), 1, C.byref(vb), None) == gs3.GS3_INVALID_ARG
+    assert b"ortho_width" in gs3._lib.gs3_last_error()
+    v.projection = 7
+    assert gs3._lib.gs3_project(C.byref(scene), C.byref(v), C.byref(k), 1, C.byref(vb), None) == gs3.GS3_INVALID_ARG

@@ -135,7 +135,7 @@ def test_overflow_without_status_block_gives_nan(gs3):
           "T_final": torch.zeros(cam.height, cam.width, device="cuda"),
           "n_contrib": torch.zeros(cam.height, cam.width, dtype=torch.int32, device="cuda"),
           "colour": torch.zeros(8, sc.n, device="cuda")}
-    gs3.gs3_render(ds, cam, light.eye, k, torch.ones(sc.n, device="cuda"), cvb, im, use_mlps=False)
+    gs3.gs3_render(ds, cam, light, k, torch.ones(sc.n, device="cuda"), cvb, im, use_mlps=False)
     torch.cuda.synchronize()
     for key in ("final", "S", "Sh", "R", "T_final"):
         assert torch.isnan(im[key]).all(), key

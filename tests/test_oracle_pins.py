@@ -936,3 +936,108 @@ def test_adam_step_matches_torch_optim():
         opt.step()
         p, m, v = O.adam_step(p, g, m, v, t, 0.01)
     assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-14)
+
+
+
+# ------------------------------------------ directional and environment light
+
+def _ortho(direction, w=64, h=64, width_world=2.0, radius=4.0):
+    return synth.make_directional(direction, w, h, width_world, radius)
+
+
+def test_orthographic_projection_closed_form():
+    """A directional light's view (Sec. 4.5: orthographic shadow splat): an
+    isotropic Gaussian of std sigma projects to Sigma' = (s sigma)^2 I + 0.3 I
+    with s = W / ortho_width, centred at s t + (W/2, H/2) for any depth; the
+    distance key is the depth along the light direction."""
+    lv = _ortho([0.3, -0.9, 0.4], 80, 60, 2.5)
+    sigma = sig32(0.05)
+    pts = [[0.0, 0.0, 0.0], [0.4, -0.2, 0.3], [-0.5, 0.1, -0.6]]
+    sc = _one_gaussian_scene(pts, math.log(0.05))
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    pr = O.project(p["mean"], cov, lv, O.Consts(), "dist")
+    s = 80 / 2.5
+    Rv = O.look_at(lv.eye, lv.target).numpy()
+    for i, m in enumerate(pts):
+        t = Rv @ (f32(np.array(m)) - lv.eye)
+        assert abs(pr["u"][i].item() - (s * t[0] + 40)) < 1e-12
+        assert abs(pr["v"][i].item() - (s * t[1] + 30)) < 1e-12
+        assert abs(pr["depth"][i].item() - t[2]) < 1e-12
+        c2 = pr["cov2"][i].numpy()
+        assert np.allclose(c2, [(s * sigma) ** 2 + 0.3, 0.0, (s * sigma) ** 2 + 0.3], atol=1e-10)
+
+
+def test_orthographic_is_the_far_perspective_limit():
+    """A perspective light moved far away along its direction, with the fov
+    that keeps the same image width at the origin, converges to the
+    orthographic projection."""
+    d = np.array([0.2, 0.7, -0.5])
+    d /= np.linalg.norm(d)
+    lo = _ortho(d, 64, 48, 2.2)
+    sc = synth.make_scene(50, 1, seed=3, means="cube", log_scale_mu=(-3.0,) * 3)
+    p = O.scene_tensors(sc)
+    cov = O.covariance(p["log_scale"], p["rot"])
+    po = O.project(p["mean"], cov, lo, O.Consts(), "dist")
+    D = 1e7
+    lp = synth.View(eye=d * D, target=np.zeros(3), width=64, height=48, fov=2 * math.atan(1.1 / D))
+    pp = O.project(p["mean"], cov, lp, O.Consts(clamp_frac=1e9), "z")
+    assert torch.allclose(po["u"], pp["u"], atol=1e-5) and torch.allclose(po["v"], pp["v"], atol=1e-5)
+    assert torch.allclose(po["cov2"], pp["cov2"], rtol=1e-5, atol=1e-7)
+
+
+def test_directional_shadow_bias_and_shading():
+    """Two Gaussians on one line along the light direction: the far one is
+    shadowed by the near one when their depths differ by more than the bias
+    (0.016), not when by less (0.014); a Lambertian sphere under a
+    directional light has c = rho f_d(n . w) with w the light direction."""
+    d = np.array([0.0, -1.0, 0.0])
+    lv = _ortho(-d, 32, 32, 0.6)     # light shines along d: from +y toward the origin
+    for gap, shadowed in ((0.016, True), (0.014, False)):
+        sc = _one_gaussian_scene([[0.0, 0.0, 0.0], [0.0, -gap, 0.0]], math.log(0.03), opacity_logit=3.0)
+        p = O.scene_tensors(sc)
+        cov = O.covariance(p["log_scale"], p["rot"])
+        op = O.sigmoid(p["opacity_logit"])
+        pr = O.project(p["mean"], cov, lv, O.Consts(), "dist")
+        num, den, _ = O.shadow_pass(pr, lv, op, O.Consts())
+        tv = O.shadow_values(num, den).numpy()
+        assert abs(tv[0] - 1.0) < 1e-12
+        # shadowed: the near splat covers the far one's footprint (T well
+        # below 1, above 1 - o); else nothing lies in front
+        assert (0.3 < tv[1] < 0.8) if shadowed else abs(tv[1] - 1.0) < 1e-12
+    # Lambertian sphere, lobes off, shading frames with +z along the normal
+    rng = np.random.default_rng(7)
+    nrm = rng.standard_normal((64, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    sc = _one_gaussian_scene(nrm * 0.5, math.log(0.02))
+    # shading quaternion rotating the world normal onto +z
+    qs = []
+    for nv in nrm:
+        r, _ = Rotation.align_vectors([nv], [[0.0, 0.0, 1.0]])
+        x, y, z, w = r.inv().as_quat()
+        qs.append([w, x, y, z])
+    sc.shade_rot = np.ascontiguousarray(np.array(qs).T, np.float32)
+    p = O.scene_tensors(sc)
+    ldir = np.array([0.3, 0.5, 0.8])
+    sh = O.shade(p, None, [0.0, 0.0, 6.0], light_dir=ldir)
+    wdir = ldir / np.linalg.norm(ldir)
+    cos = T(nrm @ wdir)
+    want = sc.albedo.T.astype(np.float64) * O.diffuse(cos).numpy()[:, None]
+    assert np.allclose(sh["c"].detach().numpy(), want, atol=1e-6)
+
+
+def test_environment_light_is_the_weighted_sum():
+    """Sec. 4.5: the environment render is the linear combination of the
+    directional renders; one light of weight 1 is that light's render, and
+    the weights act linearly."""
+    sc = synth.make_scene(300, 2, seed=9, means="cube", log_scale_mu=(-2.6,) * 3)
+    rng = np.random.default_rng(9)
+    cam = synth.make_view(rng.standard_normal(3), 4.0, 24, 20, 40.0)
+    lights, w = synth.environment_lights(3, seed=9, width=24, height=24, ortho_width=3.6)
+    assert abs(w.sum() - 1) < 1e-12 and (w > 0).all()
+    one = O.render(sc, cam, lights[0])["final"]
+    assert torch.equal(O.render_env(sc, cam, lights[:1], [1.0]), one)
+    env = O.render_env(sc, cam, lights, w)
+    parts = [O.render(sc, cam, lv)["final"] for lv in lights]
+    assert torch.allclose(env, sum(float(wi) * f for wi, f in zip(w, parts)), atol=1e-14)
+    assert torch.allclose(O.render_env(sc, cam, lights, 2 * w), 2 * env, atol=1e-14)
