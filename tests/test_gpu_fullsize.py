@@ -12,7 +12,11 @@ can compute piece by piece:
     inside one of a few 64x64 light patches (its T is then a function of
     those pixels only);
   - three 16x16 patches of the camera images (S, Sh, R, final), given the
-    GPU's T.
+    GPU's T;
+  - the adjoint for an upstream gradient on one 16x16 camera patch: every
+    appearance gradient (albedo, lobes, shading rotation, features) of every
+    Gaussian and every MLP weight gradient, against FP64 autograd of the
+    oracle's patch given the GPU's T.
 Tolerance 1e-4 max abs over every checked output; the threshold decisions
 the oracle flags as float32-ambiguous follow the GPU's
 (tests/parity_resolve.py)."""
@@ -64,7 +68,8 @@ def run():
     k = O.Consts()
     prl = O.project(p["mean"], cov, light, k, "dist")
     prc = O.project(p["mean"], cov, cam, k, "z")
-    return dict(sc=sc, cam=cam, light=light, res=res, lists=lists, p=p, op=op, prl=prl, prc=prc, k=k)
+    return dict(sc=sc, cam=cam, light=light, res=res, lists=lists, p=p, op=op, prl=prl, prc=prc, k=k,
+                rnd=rnd, gs3=gs3)
 
 
 @pytest.mark.parametrize("role", ["light", "cam"])
@@ -187,3 +192,84 @@ def test_fullsize_camera_patches(run):
     assert covered > 100
     for name, e in worst.items():
         assert e <= TOL, (name, e)
+
+
+APPEARANCE = ("shade_rot", "albedo", "lobe_axis", "lobe_log_sharp", "lobe_amp", "feat")
+_TO_LIB = {"shade_rot": lambda x: x.T, "albedo": lambda x: x.T, "lobe_axis": lambda x: x.permute(1, 2, 0),
+           "lobe_log_sharp": lambda x: x.T, "lobe_amp": lambda x: x.permute(1, 2, 0), "feat": lambda x: x.T}
+
+
+def test_fullsize_backward_patch(run):
+    """The adjoint at full size, in the benchmark's launch configuration:
+    dL/dfinal is a seeded random field on one 16x16 camera patch and zero
+    elsewhere. Given the GPU's shadow values T, the appearance parameters
+    and both MLPs reach the loss only through that patch's pixels (Sec. 4.1,
+    4.2 Eq. 8, 4.3), so FP64 autograd of the oracle's patch (the camera
+    pass over the Gaussians that reach it, flagged decisions following the
+    GPU's) gives their exact gradients: every Gaussian's appearance
+    gradients (zero for the Gaussians off the patch) and every MLP weight
+    gradient, 1e-4 * max(1, max |ref|) per tensor. The geometry gradients
+    also carry the shadow splat's adjoint over the whole light image and are
+    checked at small sizes (test_gpu_backward)."""
+    sc, res, cam, prc, op, k = run["sc"], run["res"], run["cam"], run["prc"], run["op"], run["k"]
+    gs3, rnd = run["gs3"], run["rnd"]
+    n = sc.n
+    x0, y0, w = 392, 392, 16
+    rng = np.random.default_rng(40)
+    dF = np.zeros((3, cam.height, cam.width), np.float32)
+    dF[:, y0:y0 + w, x0:x0 + w] = rng.standard_normal((3, w, w)).astype(np.float32) / w
+    g = rnd.backward(cam, run["light"], torch.as_tensor(dF).cuda())
+    torch.cuda.synchronize()
+    got = {nm: g.t[nm].cpu().numpy() for nm in APPEARANCE}
+    for tag, m in (("phi", g.phi), ("psi", g.psi)):
+        for i, (gw, gb) in enumerate(m):
+            got[f"{tag}_w{i}"], got[f"{tag}_b{i}"] = gw.cpu().numpy(), gb.cpu().numpy()
+    # oracle: the patch given the GPU's T
+    ys, xs = np.meshgrid(np.arange(y0, y0 + w), np.arange(x0, x0 + w), indexing="ij")
+    pix = torch.as_tensor((ys * cam.width + xs).ravel())
+    ids, sub, sop = restrict(prc, op, pix, cam.width, k)
+    p = O.scene_tensors(synth.subset(sc, ids.numpy()), requires_grad=True)
+    phi = [(torch.tensor(a, dtype=torch.float64, requires_grad=True),
+            torch.tensor(b, dtype=torch.float64, requires_grad=True)) for a, b in sc.phi.layers]
+    psi = [(torch.tensor(a, dtype=torch.float64, requires_grad=True),
+            torch.tensor(b, dtype=torch.float64, requires_grad=True)) for a, b in sc.psi.layers]
+    T = torch.as_tensor(res["T"][:n].astype(np.float64))[ids]
+    sh = O.shade(p, run["light"].eye, cam.eye)
+    tp = O.mlp_forward(phi, torch.cat([T[:, None], p["feat"]], 1))[:, 0]
+    r = O.mlp_forward(psi, torch.cat([p["feat"], sh["wi"], sh["wo"]], 1))
+    gpu = {"S": res["S"][:, ys, xs].reshape(3, -1), "Sh": res["Sh"][ys, xs].reshape(-1),
+           "R": res["R"][:, ys, xs].reshape(3, -1), "final": res["final"][:, ys, xs].reshape(3, -1),
+           "T_final": res["T_final"][ys, xs].reshape(-1)}
+    hk, sk = [], []
+    with torch.no_grad():
+        O.camera_pass(sub, cam, sop, sh["c"], tp, r, k, pixels=pix, amb_keys=hk, stop_keys=sk)
+    hk = torch.cat(hk) if hk else torch.zeros(0, dtype=torch.int64)
+    sk = torch.cat(sk) if sk else torch.zeros(0, dtype=torch.int64)
+    cf, sf, unresolved = resolve_camera(sub, cam, sop, sh["c"].detach(), tp.detach(), r.detach(), k, hk, sk,
+                                        gpu, pix.tolist())
+    assert not unresolved.any()
+    S, Sh, R, _, _ = O.camera_pass(sub, cam, sop, sh["c"], tp, r, k, pixels=pix, flips=cf, stop_flips=sf)
+    final = S * Sh[None, :] + R
+    loss = (final * torch.as_tensor(dF[:, ys, xs].reshape(3, -1), dtype=torch.float64)).sum()
+    loss.backward()
+    idn = ids.numpy()
+    worst = {}
+    for nm in APPEARANCE:
+        ref = np.zeros_like(got[nm], dtype=np.float64)
+        sel = (slice(None),) * (ref.ndim - 1) + (idn,)
+        ref[sel] = _TO_LIB[nm](p[nm].grad).numpy()
+        scale = max(1.0, float(np.abs(ref).max()))
+        worst[nm] = (float(np.abs(got[nm] - ref).max()) / scale, scale)
+    for tag, m in (("phi", phi), ("psi", psi)):
+        for i, (a, b) in enumerate(m):
+            for nm, t in ((f"{tag}_w{i}", a), (f"{tag}_b{i}", b)):
+                ref = t.grad.numpy()
+                scale = max(1.0, float(np.abs(ref).max()))
+                worst[nm] = (float(np.abs(got[nm] - ref).max()) / scale, scale)
+    print(f"full-size backward patch: {len(idn)} Gaussians reach it, flagged camera decisions "
+          f"{int(torch.unique(hk).numel() + torch.unique(sk).numel())}, flipped {len(cf) + len(sf)}; error / scale: "
+          + ", ".join(f"{nm} {e:.1e}/{s:.1e}" for nm, (e, s) in worst.items()))
+    assert len(idn) > 50
+    assert np.abs(got["albedo"]).max() > 0
+    for nm, (e, s) in worst.items():
+        assert e <= TOL, (nm, e, s)
