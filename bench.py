@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--env-lights", type=int, default=16,
                     help="directional lights of the environment-light leg (0: skip)")
     ap.add_argument("--env-steps", type=int, default=5, help="timed environment frames")
+    ap.add_argument("--batch-views", type=int, default=0,
+                    help="1: each frame preprocesses its light and camera views in one launch sequence")
     return ap.parse_args()
 
 
@@ -543,7 +545,7 @@ def main():
     # queues or stages split over more streams measured slower). The library
     # launches on the frame's stream, where the frame and numerator events
     # are recorded.
-    fp = gs3.FramePipeline(ds, depth=args.inflight)
+    fp = gs3.FramePipeline(ds, depth=args.inflight, batch_views=bool(args.batch_views))
     for cam, light in pairs:
         fp.warm(cam, light)
     for i in range(args.warmup):
@@ -571,6 +573,7 @@ def main():
     frame_ms = sum(e["f0"].elapsed_time(e["f1"]) for e in evs) / args.steps
     # one frame at a time (no pipelining; stages overlapped inside the frame)
     single = gs3.FramePipeline(ds, depth=1)
+    rnd.batch_views = bool(args.batch_views)
     single.renderers[0] = rnd
     for i in range(4):
         single.render(*pairs[i % len(pairs)])
@@ -617,6 +620,15 @@ def main():
         for j in range(7):
             stage[j] += e[j].elapsed_time(e[j + 1])
     stage /= n_ser
+    # both views' preprocess in one launch sequence (gs3_preprocess_views)
+    pb = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_ser)]
+    for i in range(n_ser):
+        cam, light = pairs[i % len(pairs)]
+        pb[i][0].record(stream)
+        rnd._preprocess_pair(light, cam, False)
+        pb[i][1].record(stream)
+    torch.cuda.synchronize()
+    pre_batched = sum(a.elapsed_time(b) for a, b in pb) / n_ser
     used = [stats[i % len(pairs)] for i in range(args.steps)]
     p_l, p_c, h_l, h_c = [float(np.mean([u[j] for u in used])) for j in range(4)]
     ser_used = [stats[i % len(pairs)] for i in range(n_ser)]
@@ -681,7 +693,9 @@ def main():
         "stages_ms_serial": {"light_preprocess": round(stage[0], 4), "shadow_den": round(stage[1], 4),
                              "shadow_num": round(stage[2], 4), "shadow_resolve": round(stage[3], 4),
                              "camera_preprocess": round(stage[4], 4), "shade_psi": round(stage[5], 4),
-                             "phi_camera_splat": round(stage[6], 4)},
+                             "phi_camera_splat": round(stage[6], 4),
+                             "light_and_camera_preprocess_batched": round(pre_batched, 4)},
+        "batch_views": bool(args.batch_views),
         "work": {"pairs_light": int(p_l), "pairs_camera": int(p_c), "hits_light": int(h_l),
                  "hits_camera_blended": int(h_c)},
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),

@@ -262,6 +262,24 @@ int gs3_preprocess(const gs3_scene* scene, const gs3_view* view,
                    const gs3_consts* consts, int32_t depth_mode,
                    const gs3_viewbuf* vb, gs3_stream_t stream);
 
+/* Steps a1+a2 / a7+a8 for n_views >= 1 views of one scene in one launch
+ * sequence (Sec. 3 projection and sorting; Sec. 4.2 light views sorted by
+ * distance): views[v] is projected with depth_modes[v] into vbs[v] and
+ * binned there, with the same results as gs3_preprocess on each view alone.
+ * The kernels of all views share each launch, so a frame's light and
+ * camera views, or the views of many requests, fill the device together
+ * and pay the launch sequence once. `views`, `depth_modes` and `vbs` are
+ * host arrays of n_views entries; every vbs[v].n equals scene->n, the
+ * workspaces must not overlap, and each may have its own size and
+ * capacity. Every argument is checked before anything is enqueued
+ * (GS3_INVALID_ARG / GS3_WORKSPACE_TOO_SMALL name the offending view);
+ * status blocks, overflow and capacity behave per view as for
+ * gs3_preprocess. */
+int gs3_preprocess_views(const gs3_scene* scene, const gs3_view* views,
+                         const int32_t* depth_modes, int32_t n_views,
+                         const gs3_consts* consts, const gs3_viewbuf* vbs,
+                         gs3_stream_t stream);
+
 /* Number of (tile, Gaussian) pairs of the last binning in `vb` (host
  * value; synchronises `stream`). Returns GS3_PAIR_CAPACITY_EXCEEDED (and
  * the required count) if it exceeded the capacity. An overflowed binning

@@ -1,5 +1,6 @@
 // Host side of the C-ABI (include/gs3.h): argument checks, workspace
 // layout, view set-up in double precision, kernel launch order.
+#include <vector>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -163,7 +164,8 @@ static int post_status(const gs3_viewbuf* vb, const Layout& L, int64_t* dev, hip
     volatile int64_t* gen = vb->status;
     const long long g = (long long)gen[0] + 1;
     gen[0] = g;
-    GS3_CHECK_HIP(launch_write_status(L, vb->ws, g, dev + 1, st));
+    StatusReq r{&L, vb->ws, g, dev + 1};
+    GS3_CHECK_HIP(launch_write_status(&r, 1, st));
     return GS3_OK;
 }
 
@@ -348,9 +350,55 @@ int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream) {
 
 int gs3_preprocess(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
                    const gs3_viewbuf* vb, gs3_stream_t stream) {
-    int st = gs3_project(scene, view, consts, depth_mode, vb, stream);
-    if (st != GS3_OK) return st;
-    return gs3_sort(vb, stream);
+    return gs3_preprocess_views(scene, view, &depth_mode, 1, consts, vb, stream);
+}
+
+int gs3_preprocess_views(const gs3_scene* scene, const gs3_view* views, const int32_t* depth_modes,
+                         int32_t n_views, const gs3_consts* consts, const gs3_viewbuf* vbs, gs3_stream_t stream) {
+    if (n_views < 1) return fail(GS3_INVALID_ARG, "n_views must be at least 1");
+    if (!views || !depth_modes || !vbs) return fail(GS3_INVALID_ARG, "views, depth_modes or viewbufs is NULL");
+    int st;
+    if ((st = check_scene(scene, false)) != GS3_OK) return st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    std::vector<Layout> L(n_views);
+    std::vector<ViewParams> vp(n_views);
+    std::vector<int64_t*> sdev(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const gs3_viewbuf* vb = &vbs[v];
+        if ((st = check_vb(vb, &L[v])) != GS3_OK) return st;
+        if (scene->n != vb->n) return fail(GS3_INVALID_ARG, "scene.n != viewbufs[%d].n", v);
+        if ((st = view_params(&views[v], L[v], depth_modes[v], &vp[v])) != GS3_OK) return st;
+        const double tx = (views[v].width / 2.0) / vp[v].focal, ty = (views[v].height / 2.0) / vp[v].focal;
+        vp[v].lim_x = consts->clamp_frac * tx;
+        vp[v].lim_y = consts->clamp_frac * ty;
+        if ((st = status_target(vb, &sdev[v])) != GS3_OK) return st;
+        // views of one call share a launch: their workspaces must not overlap
+        const char* a0 = static_cast<const char*>(vb->ws);
+        for (int u = 0; u < v; ++u) {
+            const char* b0 = static_cast<const char*>(vbs[u].ws);
+            if (a0 < b0 + L[u].total && b0 < a0 + L[v].total)
+                return fail(GS3_INVALID_ARG, "viewbufs[%d] and viewbufs[%d] share workspace memory", u, v);
+        }
+    }
+    std::vector<const Layout*> Lp(n_views);
+    std::vector<void*> ws(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        Lp[v] = &L[v];
+        ws[v] = vbs[v].ws;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    GS3_CHECK_HIP(launch_project_batch(scene_dev(scene), vp.data(), *consts, Lp.data(), ws.data(), n_views, s));
+    GS3_CHECK_HIP(launch_bin_batch(Lp.data(), ws.data(), n_views, s));
+    std::vector<StatusReq> req;
+    for (int v = 0; v < n_views; ++v) {
+        if (!sdev[v]) continue;
+        volatile int64_t* gen = vbs[v].status;
+        const long long g = (long long)gen[0] + 1;
+        gen[0] = g;
+        req.push_back(StatusReq{Lp[v], vbs[v].ws, g, sdev[v] + 1});
+    }
+    if (!req.empty()) GS3_CHECK_HIP(launch_write_status(req.data(), (int)req.size(), s));
+    return GS3_OK;
 }
 
 int gs3_view_pair_count(const gs3_viewbuf* vb, int64_t* n_pairs, gs3_stream_t stream) {

@@ -19,6 +19,7 @@ constexpr int kSortItemsN = 1024;  // items per radix workgroup of the depth sor
 constexpr int kFeat = 16;          // per-Gaussian MLP feature size
 constexpr int kHidden = 64;        // MLP hidden width
 constexpr int kMaxLobes = 16;
+constexpr int kMaxBatch = 8;       // views per batched launch (longer batches run in chunks)
 
 // Device-side counters at the head of every view workspace.
 struct ViewHeader {
@@ -99,6 +100,12 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
                               const int32_t* ry, const float* depth, const Layout& L,
                               void* ws, hipStream_t st);
 hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st);
+// One launch sequence bins all nv views (any nv; chunks of kMaxBatch).
+hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st);
+// Projection of one scene into nv views (ViewParams vps[v], workspace
+// wss[v] with layout Ls[v]); chunks of kMaxBatch views per launch.
+hipError_t launch_project_batch(const SceneDev& sc, const ViewParams* vps, const gs3_consts& k,
+                                const Layout* const* Ls, void* const* wss, int nv, hipStream_t st);
 hipError_t launch_shadow(const gs3_consts& k, const Layout& L, void* ws,
                          float* num_den, float* T, hipStream_t st);
 hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st);
@@ -144,8 +151,14 @@ hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const V
                               const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
                               hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
-hipError_t launch_write_status(const Layout& L, const void* ws, long long generation, int64_t* status_dev,
-                               hipStream_t st);
+// A binning outcome to report into a host-pinned status block.
+struct StatusReq {
+    const Layout* L;
+    const void* ws;
+    long long generation;
+    int64_t* status_dev;   // device address of the block's word 1
+};
+hipError_t launch_write_status(const StatusReq* req, int count, hipStream_t st);
 int64_t l1_chunks(int64_t count);
 hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                           float* grad, double* partial, hipStream_t st);

@@ -33,16 +33,46 @@ __device__ inline bool tile_rect(int64_t ix, int64_t iy, int64_t rx, int64_t ry,
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_project(SceneDev sc, ViewParams vp, gs3_consts kc,
-                                                  float4* __restrict__ rec0, float4* __restrict__ rec1,
-                                                  float4* __restrict__ rec2, float* __restrict__ depth_out, int4* __restrict__ ext,
-                                                  int4* __restrict__ drec,
-                                                  uint32_t* __restrict__ cnt, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals, float* __restrict__ num) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Output buffers of one view's projection (in its workspace).
+struct ProjDesc {
+    ViewParams vp;
+    float4* rec0;
+    float4* rec1;
+    float4* rec2;
+    float* depth_out;
+    int4* ext;
+    int4* drec;
+    uint32_t* cnt;
+    uint32_t* keys;
+    uint32_t* vals;
+    float* num;
+};
+struct ProjBatch {
+    int32_t nv;
+    uint32_t blocks_per_view;
+    ProjDesc d[kMaxBatch];
+};
+static_assert(sizeof(ProjBatch) <= 3072, "projection batch exceeds the kernel argument budget");
+
+// One lane per (view, Gaussian): the views of the batch share the scene,
+// block b projects Gaussians of view b / blocks_per_view.
+__global__ __launch_bounds__(256) void k_project(SceneDev sc, gs3_consts kc, ProjBatch B) {
+    const int view = (int)(blockIdx.x / B.blocks_per_view);
+    const ProjDesc& D = B.d[view];
+    const ViewParams& vp = D.vp;
+    float4* __restrict__ rec0 = D.rec0;
+    float4* __restrict__ rec1 = D.rec1;
+    float4* __restrict__ rec2 = D.rec2;
+    float* __restrict__ depth_out = D.depth_out;
+    int4* __restrict__ ext = D.ext;
+    int4* __restrict__ drec = D.drec;
+    uint32_t* __restrict__ cnt = D.cnt;
+    uint32_t* __restrict__ keys = D.keys;
+    uint32_t* __restrict__ vals = D.vals;
+    const int i = (int)(blockIdx.x - view * B.blocks_per_view) * blockDim.x + threadIdx.x;
     const int n = sc.n;
     if (i >= n) return;
-    num[i] = 0.f;   // the shadow numerator's accumulator starts empty for every projection
+    D.num[i] = 0.f;   // the shadow numerator's accumulator starts empty for every projection
     const double mx = sc.mean[i], my = sc.mean[n + i], mz = sc.mean[2 * n + i];
     const double s0 = exp((double)sc.log_scale[i]);
     const double s1 = exp((double)sc.log_scale[n + i]);
@@ -155,15 +185,39 @@ __global__ __launch_bounds__(256) void k_extent_keys(const int32_t* __restrict__
     depth_out[i] = depth[i];
 }
 
+hipError_t launch_project_batch(const SceneDev& sc, const ViewParams* vps, const gs3_consts& k,
+                                const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
+    if (sc.n == 0 || nv <= 0) return hipSuccess;
+    const uint32_t per = (uint32_t)((sc.n + 255) / 256);
+    for (int c0 = 0; c0 < nv; c0 += kMaxBatch) {
+        ProjBatch B;
+        B.nv = 0;
+        B.blocks_per_view = per;
+        for (int v = c0; v < nv && v < c0 + kMaxBatch; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            ProjDesc& d = B.d[B.nv++];
+            d.vp = vps[v];
+            d.rec0 = at<float4>(ws, L.rec0);
+            d.rec1 = at<float4>(ws, L.rec1);
+            d.rec2 = at<float4>(ws, L.rec2);
+            d.depth_out = at<float>(ws, L.depth);
+            d.ext = at<int4>(ws, L.ext);
+            d.drec = at<int4>(ws, L.drec);
+            d.cnt = at<uint32_t>(ws, L.cnt);
+            d.keys = at<uint32_t>(ws, L.keys_a);
+            d.vals = at<uint32_t>(ws, L.vals_a);
+            d.num = at<float>(ws, L.num);
+        }
+        hipLaunchKernelGGL(k_project, dim3(per * (uint32_t)B.nv), dim3(256), 0, st, sc, k, B);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_consts& k,
                           const Layout& L, void* ws, hipStream_t st) {
-    if (sc.n == 0) return hipSuccess;
-    const int grid = (sc.n + 255) / 256;
-    hipLaunchKernelGGL(k_project, dim3(grid), dim3(256), 0, st, sc, vp, k, at<float4>(ws, L.rec0),
-                       at<float4>(ws, L.rec1), at<float4>(ws, L.rec2), at<float>(ws, L.depth), at<int4>(ws, L.ext),
-                       at<int4>(ws, L.drec), at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.keys_a),
-                       at<uint32_t>(ws, L.vals_a), at<float>(ws, L.num));
-    return hipGetLastError();
+    const Layout* Lp = &L;
+    return launch_project_batch(sc, &vp, k, &Lp, &ws, 1, st);
 }
 
 hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_t* rx,

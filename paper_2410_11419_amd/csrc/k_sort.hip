@@ -43,118 +43,179 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint
     if (i < count) p[i] = value;
 }
 
+// ---------------------------------------------------------------- batches
+//
+// Every kernel below runs over a batch of up to kMaxBatch views in one
+// launch: the grid is the concatenation of each view's own grid, block b
+// belongs to view v with blk0[v] <= b < blk0[v + 1], and each view's
+// descriptor carries its own buffers and sizes. A single view is a batch of
+// one. Views with an empty grid take no blocks.
+
+__device__ inline int batch_view(const uint32_t* blk0, int nv, uint32_t b) {
+    int v = 0;
+    while (v + 1 < nv && b >= blk0[v + 1]) ++v;
+    return v;
+}
+
+__device__ inline uint32_t digit_of(uint32_t k, int shift) {
+    return shift < 32 ? (k >> shift) & (kRadixBins - 1) : 0u;
+}
+
+template <class D>
+struct Batch {
+    int32_t nv = 0;
+    uint32_t blk0[kMaxBatch + 1] = {};
+    D d[kMaxBatch];
+};
+
+// Appends view descriptor `d` with `blocks` workgroups; returns the grid.
+template <class D>
+static void batch_add(Batch<D>& b, const D& d, uint32_t blocks) {
+    b.d[b.nv] = d;
+    b.blk0[b.nv + 1] = b.blk0[b.nv] + blocks;
+    ++b.nv;
+}
+
 // ---------------------------------------------------------------- scan
 
-// With gather given, element i of the scanned sequence is in[gather[i]].
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
-                                                      int64_t len, uint32_t* __restrict__ sums) {
+// Exclusive scan of len u32 counts per view; with gather given, element i of
+// the scanned sequence is in[gather[i]]. The grand total goes to the view
+// header (required pairs, clamped count, overflow flag) and to tail_out.
+struct ScanDesc {
+    const uint32_t* in;
+    const uint32_t* gather;
+    uint32_t* out;
+    uint32_t* sums;
+    ViewHeader* hdr;
+    uint32_t* tail_out;
+    int64_t len;
+    int64_t capacity;
+    int64_t nb;
+};
+
+__global__ __launch_bounds__(256) void k_scan_reduce(Batch<ScanDesc> B) {
     __shared__ uint32_t s_wave[4];
-    const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const ScanDesc& D = B.d[v];
+    const uint32_t blk = blockIdx.x - B.blk0[v];
+    const int64_t base = (int64_t)blk * kSortItems + threadIdx.x * 16;
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int64_t i = base + j;
-        acc += (i < len) ? in[gather ? gather[i] : i] : 0u;
+        acc += (i < D.len) ? D.in[D.gather ? D.gather[i] : i] : 0u;
     }
     uint32_t tot;
     block_excl_scan_256(acc, &tot, s_wave);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+    if (threadIdx.x == 0) D.sums[blk] = tot;
 }
 
-// single workgroup: exclusive scan of m block sums in place; the grand
-// total (64-bit) optionally goes to the view header.
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int64_t m,
-                                                   ViewHeader* __restrict__ hdr, int64_t capacity,
-                                                   uint32_t* __restrict__ tail_out) {
+// one workgroup per view: exclusive scan of the view's nb block sums in
+// place, then the grand total (64-bit) to the header and the tail
+__global__ __launch_bounds__(256) void k_scan_top(Batch<ScanDesc> B) {
     __shared__ uint32_t s_wave[4];
+    const ScanDesc& D = B.d[blockIdx.x];
     unsigned long long carry = 0;
-    for (int64_t base = 0; base < m; base += 256) {
+    for (int64_t base = 0; base < D.nb; base += 256) {
         const int64_t i = base + threadIdx.x;
-        const uint32_t v = i < m ? sums[i] : 0u;
+        const uint32_t v = i < D.nb ? D.sums[i] : 0u;
         uint32_t tot;
         const uint32_t ex = block_excl_scan_256(v, &tot, s_wave);
-        if (i < m) sums[i] = (uint32_t)(carry + ex);
+        if (i < D.nb) D.sums[i] = (uint32_t)(carry + ex);
         carry += tot;
     }
     if (threadIdx.x == 0) {
-        if (hdr) {
-            hdr->required_pairs = carry;
-            const unsigned long long cap = (unsigned long long)capacity;
-            hdr->n_pairs = (uint32_t)(carry < cap ? carry : cap);
-            hdr->overflow = carry > cap ? 1u : 0u;
-        }
-        if (tail_out) *tail_out = (uint32_t)carry;
+        ViewHeader* hdr = D.hdr;
+        hdr->required_pairs = carry;
+        const unsigned long long cap = (unsigned long long)D.capacity;
+        hdr->n_pairs = (uint32_t)(carry < cap ? carry : cap);
+        hdr->overflow = carry > cap ? 1u : 0u;
+        *D.tail_out = (uint32_t)carry;
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, const uint32_t* __restrict__ gather,
-                                                    int64_t len, const uint32_t* __restrict__ sums,
-                                                    uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_scan_down(Batch<ScanDesc> B) {
     __shared__ uint32_t s_wave[4];
-    const int64_t base = (int64_t)blockIdx.x * kSortItems + threadIdx.x * 16;
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const ScanDesc& D = B.d[v];
+    const uint32_t blk = blockIdx.x - B.blk0[v];
+    const int64_t base = (int64_t)blk * kSortItems + threadIdx.x * 16;
     uint32_t vals[16];
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int64_t i = base + j;
-        vals[j] = (i < len) ? in[gather ? gather[i] : i] : 0u;
+        vals[j] = (i < D.len) ? D.in[D.gather ? D.gather[i] : i] : 0u;
         acc += vals[j];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan_256(acc, &tot, s_wave) + sums[blockIdx.x];
+    uint32_t run = block_excl_scan_256(acc, &tot, s_wave) + D.sums[blk];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int64_t i = base + j;
-        if (i < len) out[i] = run;
+        if (i < D.len) D.out[i] = run;
         run += vals[j];
     }
 }
 
-static hipError_t exclusive_scan(const uint32_t* in, const uint32_t* gather, uint32_t* out, int64_t len,
-                                 uint32_t* sums, ViewHeader* hdr, int64_t capacity, uint32_t* tail_out,
-                                 hipStream_t st) {
-    const int64_t nb = (len + kSortItems - 1) / kSortItems;
-    if (nb == 0) {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, (int64_t)0, hdr, capacity, tail_out);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, gather, len, sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, sums, nb, hdr, capacity, tail_out);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, st, in, gather, len, sums, out);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- radix
 
-// Per-block digit histogram of keys[base .. base+ITEMS), written digit-major
-// into table[digit * nblk + block]. n is read from *n_dev when given.
+// One stable LSD pass of a view: kin (+ vin) -> kout (+ vout) by the 8-bit
+// digit at `shift` (digits at or above bit 32 are 0). n items, read from
+// *n_dev when given; nblk workgroups of ITEMS items; table holds the
+// digit-major per-block counts, totals the 256 digit totals. FINAL (last
+// pass over packed pairs) writes ids to kout and the tile ranges.
+struct RadixDesc {
+    const uint32_t* kin;
+    const uint32_t* vin;
+    uint32_t* kout;
+    uint32_t* vout;
+    const uint32_t* n_dev;
+    uint32_t* table;
+    uint32_t* totals;
+    int* ranges;
+    uint32_t n_host;
+    int32_t shift;
+    int32_t nblk;
+    int32_t id_bits;
+};
+
+// Per-block digit histogram of the block's keys, written digit-major into
+// table[digit * nblk + block].
 template <int ITEMS>
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                                                     uint32_t n_host, int shift, uint32_t* __restrict__ table, int nblk) {
+__global__ __launch_bounds__(256) void k_radix_hist(Batch<RadixDesc> B) {
     __shared__ uint32_t h[4][kRadixBins];
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const RadixDesc& D = B.d[v];
+    const uint32_t blk = blockIdx.x - B.blk0[v];
     const int tid = threadIdx.x, w = tid >> 6;
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&h[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint32_t base = blockIdx.x * (uint32_t)ITEMS;
+    const uint32_t n = D.n_dev ? *D.n_dev : D.n_host;
+    const uint32_t base = blk * (uint32_t)ITEMS;
+    const uint32_t* keys = D.kin;
+    const int shift = D.shift;
     if (base < n) {
 #pragma unroll 4
         for (int r = 0; r < ITEMS / 256; ++r) {
             const uint32_t idx = base + r * 256 + tid;
-            if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & (kRadixBins - 1)], 1u);
+            if (idx < n) atomicAdd(&h[w][digit_of(keys[idx], shift)], 1u);
         }
     }
     __syncthreads();
-    for (int d = tid; d < kRadixBins; d += 256) table[d * nblk + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+    for (int d = tid; d < kRadixBins; d += 256)
+        D.table[d * D.nblk + blk] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// Exclusive scan of each digit's row of the digit-major table, in place:
-// workgroup d scans table[d nblk, (d + 1) nblk) and writes the row total
+// Exclusive scan of each digit's row of a view's digit-major table, in
+// place: workgroup (v, d) scans view v's row d and writes the row total
 // (the digit's count over all blocks) to totals[d].
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ table, int nblk,
-                                                        uint32_t* __restrict__ totals) {
+__global__ __launch_bounds__(256) void k_radix_rowscan(Batch<RadixDesc> B) {
     __shared__ uint32_t s_wave[4];
-    uint32_t* row = table + (size_t)blockIdx.x * nblk;
+    const RadixDesc& D = B.d[blockIdx.x / kRadixBins];
+    const int digit = blockIdx.x % kRadixBins;
+    const int nblk = D.nblk;
+    uint32_t* row = D.table + (size_t)digit * nblk;
     uint32_t carry = 0;
     for (int base = 0; base < nblk; base += 256 * 4) {
         const int i0 = base + threadIdx.x * 4;
@@ -173,7 +234,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ ta
         }
         carry += tot;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) D.totals[digit] = carry;
 }
 
 // Stable scatter. Wave w of the block owns the contiguous items
@@ -187,12 +248,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ ta
 // the earlier items of its block with the same digit, so ties keep input
 // order.
 template <int ITEMS, bool VALS, bool FINAL>
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                        const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                        const uint32_t* __restrict__ table,
-                                                        const uint32_t* __restrict__ totals, int nblk, int id_bits,
-                                                        int* __restrict__ ranges) {
+__global__ __launch_bounds__(256) void k_radix_scatter(Batch<RadixDesc> B) {
     constexpr int PER_WAVE = ITEMS / 4;
     constexpr int R = PER_WAVE / 64;
     static_assert(R * 64 * 4 == ITEMS, "ITEMS must be a multiple of 256");
@@ -202,17 +258,22 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     __shared__ uint32_t s_lstart[kRadixBins];
     __shared__ uint32_t s_gstart[kRadixBins];
     __shared__ uint32_t s_wave[4];
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const RadixDesc& D = B.d[v];
+    const uint32_t blk = blockIdx.x - B.blk0[v];
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-    const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint32_t base = blockIdx.x * (uint32_t)ITEMS;
+    const uint32_t n = D.n_dev ? *D.n_dev : D.n_host;
+    const uint32_t base = blk * (uint32_t)ITEMS;
     if (base >= n) return;   // whole block beyond the data: uniform exit
+    const int shift = D.shift;
+    const int nblk = D.nblk;
     const uint32_t count = (n - base) < (uint32_t)ITEMS ? (n - base) : (uint32_t)ITEMS;
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
     {
         const int d = tid;   // 256 threads, 256 digits
         uint32_t all;
-        const uint32_t dstart = block_excl_scan_256(totals[d], &all, s_wave);
-        s_gstart[d] = dstart + table[d * nblk + blockIdx.x];
+        const uint32_t dstart = block_excl_scan_256(D.totals[d], &all, s_wave);
+        s_gstart[d] = dstart + D.table[d * nblk + blk];
     }
     __syncthreads();
     uint32_t key[R], val[R], rank[R];
@@ -221,9 +282,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     for (int r = 0; r < R; ++r) {
         const uint32_t idx = (uint32_t)(w * PER_WAVE + r * 64 + lane);
         const bool valid = idx < count;
-        key[r] = valid ? kin[base + idx] : 0u;
-        val[r] = (VALS && valid) ? vin[base + idx] : 0u;
-        const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+        key[r] = valid ? D.kin[base + idx] : 0u;
+        val[r] = (VALS && valid) ? D.vin[base + idx] : 0u;
+        const uint32_t d = digit_of(key[r], shift);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -257,49 +318,45 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
     for (int r = 0; r < R; ++r) {
         const uint32_t idx = (uint32_t)(w * PER_WAVE + r * 64 + lane);
         if (idx < count) {
-            const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+            const uint32_t d = digit_of(key[r], shift);
             const uint32_t p = s_lstart[d] + s_cnt[w][d] + rank[r];
             s_key[p] = key[r];
             if (VALS) s_val[p] = val[r];
         }
     }
     __syncthreads();
+    uint32_t* kout = D.kout;
     for (uint32_t p = tid; p < count; p += 256) {
         const uint32_t k = s_key[p];
-        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        const uint32_t d = digit_of(k, shift);
         const uint32_t g = s_gstart[d] + (p - s_lstart[d]);
         if (FINAL) {
             // last pass over packed pairs: the block's staged keys are in
             // final order, so a run of one tile is contiguous here and in
             // the output; its ends widen the tile's range (atomics across
             // the blocks holding parts of the tile), and only the id is kept
+            const int id_bits = D.id_bits;
             const uint32_t t = k >> id_bits;
             kout[g] = k & ((1u << id_bits) - 1u);
-            if (p == 0 || (s_key[p - 1] >> id_bits) != t) atomicMin(&ranges[2 * t], (int)g);
-            if (p == count - 1 || (s_key[p + 1] >> id_bits) != t) atomicMax(&ranges[2 * t + 1], (int)(g + 1));
+            if (p == 0 || (s_key[p - 1] >> id_bits) != t) atomicMin(&D.ranges[2 * t], (int)g);
+            if (p == count - 1 || (s_key[p + 1] >> id_bits) != t) atomicMax(&D.ranges[2 * t + 1], (int)(g + 1));
         } else {
             kout[g] = k;
-            if (VALS) vout[g] = s_val[p];
+            if (VALS) D.vout[g] = s_val[p];
         }
     }
 }
 
-// One stable LSD pass over 8 bits: block histograms, row scan, scatter.
-// ITEMS per workgroup: the table has ceil(max_items / ITEMS) * 256 entries
-// (the layout sizes it for both sorts); sums holds the 256 digit totals.
-// Without VALS only the keys move (values packed into their low bits);
-// FINAL (last pass over packed pairs) writes the ids and the tile ranges.
+// One stable LSD pass over 8 bits for every view of the batch: block
+// histograms, row scans, scatter. Each view's table has nblk * 256 entries
+// (the layout sizes it for both sorts); totals holds its 256 digit totals.
 template <int ITEMS, bool VALS, bool FINAL = false>
-static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                             const uint32_t* n_dev, uint32_t n_host, int64_t max_items, int shift,
-                             uint32_t* table, uint32_t* sums, hipStream_t st, int id_bits = 0,
-                             int2* ranges = nullptr) {
-    const int nblk = (int)((max_items + ITEMS - 1) / ITEMS);
-    if (nblk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblk), dim3(256), 0, st, kin, n_dev, n_host, shift, table, nblk);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixBins), dim3(256), 0, st, table, nblk, sums);
-    hipLaunchKernelGGL((k_radix_scatter<ITEMS, VALS, FINAL>), dim3(nblk), dim3(256), 0, st, kin, vin, kout, vout,
-                       n_dev, n_host, shift, table, sums, nblk, id_bits, reinterpret_cast<int*>(ranges));
+static hipError_t radix_pass(const Batch<RadixDesc>& B, hipStream_t st) {
+    const uint32_t grid = B.blk0[B.nv];
+    if (B.nv == 0 || grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)(kRadixBins * B.nv)), dim3(256), 0, st, B);
+    hipLaunchKernelGGL((k_radix_scatter<ITEMS, VALS, FINAL>), dim3(grid), dim3(256), 0, st, B);
     return hipGetLastError();
 }
 
@@ -307,27 +364,43 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 
 // Pairs of 256 depth-sorted splats per workgroup, one pair slot per lane.
 // With id_bits > 0 a pair is one word, (tile << id_bits) | id, and pv is
-// unused; otherwise the tile goes to pk and the id to pv. The grid also
-// resets the per-tile ranges to (INT_MAX, 0): the range pass (or the last
-// tile pass) fills in the tiles that have pairs, and k_tile_order turns the
-// untouched ones into empty (0, 0) ranges.
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ offs,
-                                               const int4* __restrict__ ext, int n, int tiles_x, uint32_t capacity,
-                                               uint32_t* __restrict__ pk, uint32_t* __restrict__ pv,
-                                               int2* __restrict__ ranges, int n_tiles, int id_bits) {
+// unused; otherwise the tile goes to pk and the id to pv. The view's blocks
+// also reset its per-tile ranges to (INT_MAX, 0): the range pass (or the
+// last tile pass) fills in the tiles that have pairs, and k_tile_order turns
+// the untouched ones into empty (0, 0) ranges.
+struct EmitDesc {
+    const uint32_t* ids;
+    const uint32_t* offs;
+    const int4* ext;
+    uint32_t* pk;
+    uint32_t* pv;
+    int2* ranges;
+    int32_t n;
+    int32_t tiles_x;
+    uint32_t capacity;
+    int32_t n_tiles;
+    int32_t id_bits;
+    int32_t nblk;
+};
+
+__global__ __launch_bounds__(256) void k_emit(Batch<EmitDesc> B) {
     __shared__ uint32_t s_lo[257];
     __shared__ int s_x0[256], s_y0[256], s_w[256];
     __shared__ uint32_t s_id[256];
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const EmitDesc& D = B.d[v];
+    const int blk = (int)(blockIdx.x - B.blk0[v]);
     const int tid = threadIdx.x;
-    for (int t = blockIdx.x * 256 + tid; t < n_tiles; t += gridDim.x * 256) ranges[t] = make_int2(INT_MAX, 0);
-    const int s0 = blockIdx.x * 256;
+    const int n = D.n, tiles_x = D.tiles_x, id_bits = D.id_bits;
+    for (int t = blk * 256 + tid; t < D.n_tiles; t += D.nblk * 256) D.ranges[t] = make_int2(INT_MAX, 0);
+    const int s0 = blk * 256;
     const int m = min(256, n - s0);
-    const uint32_t base = offs[s0];
+    const uint32_t base = D.offs[s0];
     if (tid < m) {
-        const uint32_t g = ids[s0 + tid];
+        const uint32_t g = D.ids[s0 + tid];
         s_id[tid] = g;
-        s_lo[tid] = offs[s0 + tid] - base;
-        const int4 e = ext[g];
+        s_lo[tid] = D.offs[s0 + tid] - base;
+        const int4 e = D.ext[g];
         int x0 = 0, y0 = 0, w = 1;
         if (e.z > 0 && e.w > 0) {
             auto fdiv = [](int a) -> int { return a >= 0 ? a / kTile : -((-a + kTile - 1) / kTile); };
@@ -339,11 +412,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
         }
         s_x0[tid] = x0; s_y0[tid] = y0; s_w[tid] = w;
     }
-    if (tid == 0) s_lo[m] = offs[s0 + m] - base;
+    if (tid == 0) s_lo[m > 0 ? m : 0] = D.offs[s0 + (m > 0 ? m : 0)] - base;
     __syncthreads();
-    const uint32_t total = s_lo[m];
-    if (base >= capacity) return;
-    const uint32_t room = capacity - base;              // slots left in the pair arrays
+    const uint32_t total = s_lo[m > 0 ? m : 0];
+    if (base >= D.capacity) return;
+    const uint32_t room = D.capacity - base;              // slots left in the pair arrays
     const uint32_t lim = total < room ? total : room;
     for (uint32_t j = tid; j < lim; j += 256) {
         // last i with s_lo[i] <= j (s_lo is non-decreasing, s_lo[0] = 0)
@@ -356,10 +429,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
         const int w = s_w[lo];
         const uint32_t tile = (uint32_t)(s_y0[lo] + (int)(k / w)) * (uint32_t)tiles_x + (uint32_t)(s_x0[lo] + (int)(k % w));
         if (id_bits > 0) {
-            pk[base + j] = (tile << id_bits) | s_id[lo];   // packed: tile above the id
+            D.pk[base + j] = (tile << id_bits) | s_id[lo];   // packed: tile above the id
         } else {
-            pk[base + j] = tile;
-            pv[base + j] = s_id[lo];
+            D.pk[base + j] = tile;
+            D.pv[base + j] = s_id[lo];
         }
     }
 }
@@ -367,37 +440,58 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ids, 
 // Per-tile [start, end) of the sorted pairs. With packed pairs
 // (id_bits > 0) the tile is the word's high part, and the ids are written
 // to ids for the splatting kernels.
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ pk, const ViewHeader* __restrict__ hdr,
-                                                 int2* __restrict__ ranges, uint32_t n_tiles, int id_bits,
-                                                 uint32_t* __restrict__ ids) {
-    const uint32_t n = hdr->n_pairs;
-    if (hdr->overflow) return;   // an overflowed binning leaves every tile empty
+struct RangesDesc {
+    const uint32_t* pk;
+    const ViewHeader* hdr;
+    int2* ranges;
+    uint32_t* ids;
+    uint32_t n_tiles;
+    int32_t id_bits;
+    int32_t nblk;
+};
+
+__global__ __launch_bounds__(256) void k_ranges(Batch<RangesDesc> B) {
+    const int v = batch_view(B.blk0, B.nv, blockIdx.x);
+    const RangesDesc& D = B.d[v];
+    const uint32_t blk = blockIdx.x - B.blk0[v];
+    const uint32_t n = D.hdr->n_pairs;
+    if (D.hdr->overflow) return;   // an overflowed binning leaves every tile empty
+    const int id_bits = D.id_bits;
     const uint32_t id_mask = id_bits > 0 ? (1u << id_bits) - 1u : 0u;
-    for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+    const uint32_t* pk = D.pk;
+    for (uint32_t p = blk * 256 + threadIdx.x; p < n; p += (uint32_t)D.nblk * 256) {
         const uint32_t w = pk[p];
         const uint32_t t = w >> id_bits;
-        if (id_bits > 0) ids[p] = w & id_mask;
-        if (t >= n_tiles) continue;
-        if (p == 0 || (pk[p - 1] >> id_bits) != t) ranges[t].x = (int)p;
-        if (p == n - 1 || (pk[p + 1] >> id_bits) != t) ranges[t].y = (int)(p + 1);
+        if (id_bits > 0) D.ids[p] = w & id_mask;
+        if (t >= D.n_tiles) continue;
+        if (p == 0 || (pk[p - 1] >> id_bits) != t) D.ranges[t].x = (int)p;
+        if (p == n - 1 || (pk[p + 1] >> id_bits) != t) D.ranges[t].y = (int)(p + 1);
     }
 }
 
 // Final per-tile ranges, then the launch order of the tiles: longest list
 // first (lengths bucketed by 8), so the few long tiles start early instead
 // of forming the tail of the splatting kernels. Only the schedule depends on
-// the order, not any result.
-__global__ __launch_bounds__(1024) void k_tile_order(int2* __restrict__ ranges, int n_tiles,
-                                                      const ViewHeader* __restrict__ hdr,
-                                                      uint32_t* __restrict__ order) {
+// the order, not any result. One workgroup per view.
+struct OrderDesc {
+    int2* ranges;
+    const ViewHeader* hdr;
+    uint32_t* order;
+    int32_t n_tiles;
+};
+
+__global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
     __shared__ uint32_t hist[1024];
     __shared__ uint32_t s_wave[16];
+    const OrderDesc& D = B.d[blockIdx.x];
+    int2* ranges = D.ranges;
+    const int n_tiles = D.n_tiles;
     const int tid = threadIdx.x;
     hist[tid] = 0u;
     // tiles without pairs (still (INT_MAX, 0)) and every tile of an
     // overflowed binning become empty ranges; each thread later reads back
     // only the tiles it wrote here
-    const bool overflow = hdr->overflow != 0u;
+    const bool overflow = D.hdr->overflow != 0u;
     for (int t = tid; t < n_tiles; t += 1024) {
         const int2 r = ranges[t];
         if (overflow || r.x >= r.y) ranges[t] = make_int2(0, 0);
@@ -425,27 +519,42 @@ __global__ __launch_bounds__(1024) void k_tile_order(int2* __restrict__ ranges, 
     __syncthreads();
     hist[tid] = pre + x - v;
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
+    for (int t = tid; t < n_tiles; t += 1024) D.order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
 }
 
 // The binning's outcome into the caller's host-pinned status word (see
 // gs3_viewbuf.status): (generation mod 2^24) << 40 | overflow << 39 |
-// required pairs, one 64-bit store, made visible to the host at once.
-__global__ __launch_bounds__(64) void k_write_status(const ViewHeader* __restrict__ hdr, long long generation,
-                                                      unsigned long long* __restrict__ status) {
+// required pairs, one 64-bit store, made visible to the host at once. One
+// wave per view.
+struct StatusDesc {
+    const ViewHeader* hdr;
+    unsigned long long* status;
+    long long generation;
+};
+
+__global__ __launch_bounds__(64) void k_write_status(Batch<StatusDesc> B) {
     if (threadIdx.x != 0) return;
-    const unsigned long long req = hdr->required_pairs;
+    const StatusDesc& D = B.d[blockIdx.x];
+    const unsigned long long req = D.hdr->required_pairs;
     const unsigned long long req39 = req < (1ull << 39) ? req : (1ull << 39) - 1ull;
-    const unsigned long long v = ((unsigned long long)(generation & 0xFFFFFF) << 40) |
-                                 ((unsigned long long)(hdr->overflow ? 1u : 0u) << 39) | req39;
-    __hip_atomic_store(status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned long long v = ((unsigned long long)(D.generation & 0xFFFFFF) << 40) |
+                                 ((unsigned long long)(D.hdr->overflow ? 1u : 0u) << 39) | req39;
+    __hip_atomic_store(D.status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
 }
 
-hipError_t launch_write_status(const Layout& L, const void* ws, long long generation, int64_t* status_dev,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_write_status, dim3(1), dim3(64), 0, st, at<ViewHeader>(ws, L.hdr), generation,
-                       reinterpret_cast<unsigned long long*>(status_dev));
+hipError_t launch_write_status(const StatusReq* req, int count, hipStream_t st) {
+    for (int c0 = 0; c0 < count; c0 += kMaxBatch) {
+        Batch<StatusDesc> B;
+        for (int i = c0; i < count && i < c0 + kMaxBatch; ++i) {
+            StatusDesc d;
+            d.hdr = at<ViewHeader>(req[i].ws, req[i].L->hdr);
+            d.status = reinterpret_cast<unsigned long long*>(req[i].status_dev);
+            d.generation = req[i].generation;
+            batch_add(B, d, 1u);
+        }
+        hipLaunchKernelGGL(k_write_status, dim3((unsigned)B.nv), dim3(64), 0, st, B);
+    }
     return hipGetLastError();
 }
 
@@ -455,83 +564,190 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
-// Depth sort of the splats, pair emission in depth order, stable sort of
-// the pairs by tile, per-tile ranges. Inputs: keys_a/vals_a (depth bits /
-// index), cnt, ext from the projection (or the explicit extents).
-hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
-    ViewHeader* hdr = at<ViewHeader>(ws, L.hdr);
-    uint32_t* keys_a = at<uint32_t>(ws, L.keys_a);
-    uint32_t* vals_a = at<uint32_t>(ws, L.vals_a);
-    uint32_t* keys_b = at<uint32_t>(ws, L.keys_b);
-    uint32_t* vals_b = at<uint32_t>(ws, L.vals_b);
-    uint32_t* table = at<uint32_t>(ws, L.table);
-    uint32_t* sums = at<uint32_t>(ws, L.sums);
-    uint32_t* offs = at<uint32_t>(ws, L.offs);
-    const uint32_t n = (uint32_t)L.n;
+static int tile_passes_of(const Layout& L) {
+    int tile_bits = 0;
+    while ((1ll << tile_bits) < L.n_tiles) ++tile_bits;
+    return tile_bits == 0 ? 0 : (tile_bits + kRadixBits - 1) / kRadixBits;
+}
+
+// Binning of up to kMaxBatch views in one launch sequence: depth order of
+// the splats, pair offsets, pair emission in depth order, stable passes by
+// tile index, per-tile ranges and the tile launch order. Inputs of each
+// view: keys_a / vals_a (depth bits / index), cnt and ext from the
+// projection (or the explicit extents). Views with packed pairs and views
+// without run their tile passes as two sub-batches; within one, every view
+// takes the largest pass count (a pass over digits that are all 0 keeps the
+// order), so the sorted result lands where the view's readers expect it.
+static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
     hipError_t e;
     // 1. depth order: 4 stable 8-bit passes over the 32-bit depth keys, 1024
     //    keys per workgroup (N is small next to the pair count: more, shorter
     //    workgroups)
     for (int pass = 0; pass < 4; ++pass) {
         const bool even = (pass & 1) == 0;
-        e = radix_pass<kSortItemsN, true>(even ? keys_a : keys_b, even ? vals_a : vals_b, even ? keys_b : keys_a,
-                       even ? vals_b : vals_a, nullptr, n, L.n, pass * 8, table, sums, st);
-        if (e != hipSuccess) return e;
+        Batch<RadixDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            RadixDesc d{};
+            d.kin = at<uint32_t>(ws, even ? L.keys_a : L.keys_b);
+            d.vin = at<uint32_t>(ws, even ? L.vals_a : L.vals_b);
+            d.kout = at<uint32_t>(ws, even ? L.keys_b : L.keys_a);
+            d.vout = at<uint32_t>(ws, even ? L.vals_b : L.vals_a);
+            d.n_dev = nullptr;
+            d.n_host = (uint32_t)L.n;
+            d.shift = pass * 8;
+            d.table = at<uint32_t>(ws, L.table);
+            d.totals = at<uint32_t>(ws, L.sums);
+            d.nblk = (int32_t)L.nblk_n;
+            batch_add(B, d, (uint32_t)L.nblk_n);
+        }
+        if ((e = radix_pass<kSortItemsN, true>(B, st)) != hipSuccess) return e;
     }
     // 2. pair offsets in depth order (the counts gathered through the order)
-    e = exclusive_scan(at<uint32_t>(ws, L.cnt), vals_a, offs, L.n, sums, hdr, L.capacity, offs + L.n, st);
-    if (e != hipSuccess) return e;
-    // 3. emit (tile, id) pairs, packed into one word when tile and id bits
-    // fit in 32 (only the keys then move through the tile passes); the
-    // number of tile passes decides which buffer they start in so that the
-    // sorted result lands in pk_a / pv_a
-    int tile_bits = 0;
-    while ((1ll << tile_bits) < L.n_tiles) ++tile_bits;
-    const int tile_passes = tile_bits == 0 ? 0 : (tile_bits + kRadixBits - 1) / kRadixBits;
-    uint32_t* pk_a = at<uint32_t>(ws, L.pk_a);
-    uint32_t* pv_a = at<uint32_t>(ws, L.pv_a);
-    uint32_t* pk_b = at<uint32_t>(ws, L.pk_b);
-    uint32_t* pv_b = at<uint32_t>(ws, L.pv_b);
-    const bool packed = L.id_bits > 0;
-    // packed pairs start in pk_a and alternate with pk_b; the last pass
-    // writes the ids to pv_a. Unpacked pairs start where the sorted result
-    // lands in pk_a / pv_a.
-    const bool start_b = !packed && (tile_passes & 1) == 1;
     {
-        const unsigned emit_grid = n > 0 ? (n + 255) / 256 : 1u;
-        hipLaunchKernelGGL(k_emit, dim3(emit_grid), dim3(256), 0, st, vals_a, offs, at<int4>(ws, L.ext), (int)n,
-                           L.tiles_x, (uint32_t)L.capacity, start_b ? pk_b : pk_a, start_b ? pv_b : pv_a,
-                           at<int2>(ws, L.ranges), (int)L.n_tiles, L.id_bits);
-    }
-    // 4. stable passes by tile index
-    const uint32_t* n_dev = &hdr->n_pairs;
-    for (int pass = 0; pass < tile_passes; ++pass) {
-        const bool from_b = ((pass & 1) == 0) == start_b;
-        const int shift = L.id_bits + pass * kRadixBits;
-        if (packed && pass == tile_passes - 1) {
-            e = radix_pass<kSortItems, false, true>(from_b ? pk_b : pk_a, nullptr, pv_a, nullptr, n_dev, 0u,
-                                                    L.capacity, shift, table, sums, st, L.id_bits,
-                                                    at<int2>(ws, L.ranges));
-        } else if (packed) {
-            e = radix_pass<kSortItems, false>(from_b ? pk_b : pk_a, nullptr, from_b ? pk_a : pk_b, nullptr, n_dev, 0u,
-                                              L.capacity, shift, table, sums, st);
-        } else {
-            e = radix_pass<kSortItems, true>(from_b ? pk_b : pk_a, from_b ? pv_b : pv_a, from_b ? pk_a : pk_b,
-                                             from_b ? pv_a : pv_b, n_dev, 0u, L.capacity, shift, table, sums, st);
+        Batch<ScanDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            ScanDesc d{};
+            d.in = at<uint32_t>(ws, L.cnt);
+            d.gather = at<uint32_t>(ws, L.vals_a);
+            d.out = at<uint32_t>(ws, L.offs);
+            d.sums = at<uint32_t>(ws, L.sums);
+            d.hdr = at<ViewHeader>(ws, L.hdr);
+            d.tail_out = at<uint32_t>(ws, L.offs) + L.n;
+            d.len = L.n;
+            d.capacity = L.capacity;
+            d.nb = (L.n + kSortItems - 1) / kSortItems;
+            batch_add(B, d, (uint32_t)d.nb);
         }
+        const uint32_t grid = B.blk0[B.nv];
+        if (grid > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(256), 0, st, B);
+        hipLaunchKernelGGL(k_scan_top, dim3((unsigned)nv), dim3(256), 0, st, B);
+        if (grid > 0) hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(256), 0, st, B);
+    }
+    // tile pass counts of the two sub-batches
+    int passes[2] = {0, 0};   // [unpacked, packed]
+    for (int v = 0; v < nv; ++v) {
+        const int p = tile_passes_of(*Ls[v]);
+        const int g = Ls[v]->id_bits > 0 ? 1 : 0;
+        if (p > passes[g]) passes[g] = p;
+    }
+    // 3. emit (tile, id) pairs, packed into one word when tile and id bits
+    //    fit in 32 (only the keys then move through the tile passes). Packed
+    //    pairs start in pk_a and alternate with pk_b, the last pass writing
+    //    the ids to pv_a; unpacked pairs start where an odd or even number
+    //    of passes leaves the result in pk_a / pv_a.
+    {
+        Batch<EmitDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            const bool packed = L.id_bits > 0;
+            const bool start_b = !packed && (passes[0] & 1) == 1;
+            EmitDesc d{};
+            d.ids = at<uint32_t>(ws, L.vals_a);
+            d.offs = at<uint32_t>(ws, L.offs);
+            d.ext = at<int4>(ws, L.ext);
+            d.pk = at<uint32_t>(ws, start_b ? L.pk_b : L.pk_a);
+            d.pv = at<uint32_t>(ws, start_b ? L.pv_b : L.pv_a);
+            d.ranges = at<int2>(ws, L.ranges);
+            d.n = (int32_t)L.n;
+            d.tiles_x = L.tiles_x;
+            d.capacity = (uint32_t)L.capacity;
+            d.n_tiles = (int32_t)L.n_tiles;
+            d.id_bits = L.id_bits;
+            d.nblk = L.n > 0 ? (int32_t)((L.n + 255) / 256) : 1;
+            batch_add(B, d, (uint32_t)d.nblk);
+        }
+        hipLaunchKernelGGL(k_emit, dim3(B.blk0[B.nv]), dim3(256), 0, st, B);
+    }
+    // 4. stable passes by tile index, per sub-batch
+    for (int g = 0; g < 2; ++g) {
+        const bool packed = g == 1;
+        const int P = passes[g];
+        const bool start_b = !packed && (P & 1) == 1;
+        for (int pass = 0; pass < P; ++pass) {
+            const bool from_b = ((pass & 1) == 0) == start_b;
+            const bool final_pass = packed && pass == P - 1;
+            Batch<RadixDesc> B;
+            for (int v = 0; v < nv; ++v) {
+                const Layout& L = *Ls[v];
+                if ((L.id_bits > 0) != packed) continue;
+                void* ws = wss[v];
+                RadixDesc d{};
+                d.kin = at<uint32_t>(ws, from_b ? L.pk_b : L.pk_a);
+                d.vin = packed ? nullptr : at<uint32_t>(ws, from_b ? L.pv_b : L.pv_a);
+                d.kout = at<uint32_t>(ws, final_pass ? L.pv_a : (from_b ? L.pk_a : L.pk_b));
+                d.vout = packed ? nullptr : at<uint32_t>(ws, from_b ? L.pv_a : L.pv_b);
+                d.n_dev = &at<ViewHeader>(ws, L.hdr)->n_pairs;
+                d.n_host = 0u;
+                d.shift = L.id_bits + pass * kRadixBits;
+                d.table = at<uint32_t>(ws, L.table);
+                d.totals = at<uint32_t>(ws, L.sums);
+                d.ranges = reinterpret_cast<int*>(at<int2>(ws, L.ranges));
+                d.nblk = (int32_t)L.nblk_p;
+                d.id_bits = L.id_bits;
+                batch_add(B, d, (uint32_t)L.nblk_p);
+            }
+            if (final_pass) e = radix_pass<kSortItems, false, true>(B, st);
+            else if (packed) e = radix_pass<kSortItems, false>(B, st);
+            else e = radix_pass<kSortItems, true>(B, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    // 5. per-tile [start, end), unless the last pass over packed pairs
+    //    already wrote them
+    {
+        Batch<RangesDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            const bool packed = L.id_bits > 0;
+            if (L.capacity == 0 || (packed && passes[1] > 0)) continue;
+            void* ws = wss[v];
+            RangesDesc d{};
+            d.pk = at<uint32_t>(ws, L.pk_a);
+            d.hdr = at<ViewHeader>(ws, L.hdr);
+            d.ranges = at<int2>(ws, L.ranges);
+            d.ids = at<uint32_t>(ws, L.pv_a);
+            d.n_tiles = (uint32_t)L.n_tiles;
+            d.id_bits = L.id_bits;
+            int64_t grid = (L.capacity + 255) / 256;
+            d.nblk = (int32_t)(grid > 1024 ? 1024 : grid);
+            batch_add(B, d, (uint32_t)d.nblk);
+        }
+        if (B.nv > 0) hipLaunchKernelGGL(k_ranges, dim3(B.blk0[B.nv]), dim3(256), 0, st, B);
+    }
+    {
+        Batch<OrderDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            OrderDesc d{};
+            d.ranges = at<int2>(ws, L.ranges);
+            d.hdr = at<ViewHeader>(ws, L.hdr);
+            d.order = at<uint32_t>(ws, L.order);
+            d.n_tiles = (int32_t)L.n_tiles;
+            batch_add(B, d, 1u);
+        }
+        hipLaunchKernelGGL(k_tile_order, dim3((unsigned)nv), dim3(1024), 0, st, B);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
+    for (int c0 = 0; c0 < nv; c0 += kMaxBatch) {
+        const int m = nv - c0 < kMaxBatch ? nv - c0 : kMaxBatch;
+        const hipError_t e = bin_chunk(Ls + c0, wss + c0, m, st);
         if (e != hipSuccess) return e;
     }
-    // 5. per-tile [start, end) (already done by the last pass over packed
-    //    pairs)
-    if (L.capacity > 0 && !(packed && tile_passes > 0)) {
-        int64_t grid = (L.capacity + 255) / 256;
-        if (grid > 1024) grid = 1024;
-        hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, st, pk_a, hdr, at<int2>(ws, L.ranges),
-                           (uint32_t)L.n_tiles, L.id_bits, pv_a);
-    }
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, at<int2>(ws, L.ranges), (int)L.n_tiles, hdr,
-                       at<uint32_t>(ws, L.order));
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
+    const Layout* Lp = &L;
+    return launch_bin_batch(&Lp, &ws, 1, st);
 }
 
 }  // namespace gs3

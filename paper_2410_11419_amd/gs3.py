@@ -34,7 +34,7 @@ GS3_DEPTH_DIST = 1
 
 EXPORTED = [
     "gs3_consts_default", "gs3_status_string", "gs3_last_error", "gs3_device_ok",
-    "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess",
+    "gs3_view_workspace_size", "gs3_project", "gs3_bin", "gs3_preprocess", "gs3_preprocess_views",
     "gs3_view_pair_count", "gs3_view_lists", "gs3_view_splats", "gs3_view_count_hits", "gs3_shadow_splat",
     "gs3_shadow_den", "gs3_shadow_num", "gs3_shadow_resolve", "gs3_render",
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
@@ -102,6 +102,8 @@ def _load():
         "gs3_view_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int64, P(C.c_size_t)]),
         "gs3_project": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_consts), C.c_int32, P(gs3_viewbuf), C.c_void_p]),
         "gs3_bin": (C.c_int, [C.c_void_p] * 5 + [P(gs3_viewbuf), C.c_void_p]),
+        "gs3_preprocess_views": (C.c_int, [P(gs3_scene), P(gs3_view), P(C.c_int32), C.c_int32, P(gs3_consts),
+                                           P(gs3_viewbuf), C.c_void_p]),
         "gs3_preprocess": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_consts), C.c_int32, P(gs3_viewbuf),
                                      C.c_void_p]),
         "gs3_view_pair_count": (C.c_int, [P(gs3_viewbuf), P(C.c_int64), C.c_void_p]),
@@ -291,6 +293,19 @@ def gs3_preprocess(scene: DeviceScene, view, consts: gs3_consts, depth_mode: int
     v = make_view(view)
     _check(_lib.gs3_preprocess(C.byref(scene.c_struct()), C.byref(v), C.byref(consts), depth_mode,
                                C.byref(vb.vb), _stream()), "gs3_preprocess")
+
+
+def gs3_preprocess_views(scene: DeviceScene, views: Sequence, depth_modes: Sequence[int], consts: gs3_consts,
+                         vbs: Sequence[ViewBuffer]):
+    """Projection and binning of several views in one launch sequence."""
+    n = len(views)
+    if n < 1 or len(depth_modes) != n or len(vbs) != n:
+        raise ValueError("one depth mode and one view buffer per view, at least one view")
+    va = (gs3_view * n)(*[make_view(v) for v in views])
+    ma = (C.c_int32 * n)(*depth_modes)
+    ba = (gs3_viewbuf * n)(*[vb.vb for vb in vbs])
+    _check(_lib.gs3_preprocess_views(C.byref(scene.c_struct()), va, ma, n, C.byref(consts), ba, _stream()),
+           "gs3_preprocess_views")
 
 
 def gs3_sort(vb: ViewBuffer):
@@ -565,8 +580,9 @@ class Renderer:
     first use and grown when a binning needs more pairs."""
 
     def __init__(self, scene: DeviceScene, consts: Optional[gs3_consts] = None, use_mlps: bool = True,
-                 pair_capacity: Optional[int] = None):
+                 pair_capacity: Optional[int] = None, batch_views: bool = False):
         self.scene = scene
+        self.batch_views = batch_views
         self.consts = consts if consts is not None else default_consts()
         self.use_mlps = use_mlps and scene.phi is not None
         self.capacity_hint = pair_capacity
@@ -605,6 +621,30 @@ class Renderer:
                 gs3_view_pair_count(vb)
         return vb
 
+    def _preprocess_pair(self, light, cam, check: bool):
+        """Light (distance keys) and camera (z keys) preprocess in one
+        launch sequence (gs3_preprocess_views); with ``check``, a view whose
+        binning overflowed is grown and preprocessed again on its own."""
+        vbs = []
+        for role, view in (("light", light), ("cam", cam)):
+            vb = self.vbs.get((role, view.width, view.height))
+            if vb is None:
+                cap = self.capacity_hint or max(1 << 16, 32 * self.scene.n)
+                vb = self._vb(role, view.width, view.height, cap)
+            vbs.append(vb)
+        gs3_preprocess_views(self.scene, [light, cam], [GS3_DEPTH_DIST, GS3_DEPTH_Z], self.consts, vbs)
+        if check:
+            for i, (role, view, mode) in enumerate((("light", light, GS3_DEPTH_DIST), ("cam", cam, GS3_DEPTH_Z))):
+                try:
+                    gs3_view_pair_count(vbs[i])
+                except Gs3Error as e:
+                    if e.status != GS3_PAIR_CAPACITY_EXCEEDED:
+                        raise
+                    vbs[i] = self._vb(role, view.width, view.height, int(e.required * 1.25) + 4096)
+                    gs3_preprocess(self.scene, view, self.consts, mode, vbs[i])
+                    gs3_view_pair_count(vbs[i])
+        return vbs[0], vbs[1]
+
     def _images(self, w: int, h: int):
         key = (w, h)
         im = self.images.get(key)
@@ -632,7 +672,8 @@ class Renderer:
         return out
 
     def render(self, cam, light, check: bool = True, overlap: bool = True,
-               events: Optional[Dict[str, torch.cuda.Event]] = None) -> Dict[str, torch.Tensor]:
+               events: Optional[Dict[str, torch.cuda.Event]] = None,
+               batch: Optional[bool] = None) -> Dict[str, torch.Tensor]:
         """Relit frame for camera view ``cam`` and the point light of view
         ``light`` (its eye is the light position). ``check`` verifies (with a
         host sync) that no binning overflowed its pair capacity.
@@ -650,9 +691,27 @@ class Renderer:
         are the same as with ``overlap=False`` (one stream, in order).
         ``events`` (optional) gets "num0"/"num1" recorded around the shadow
         numerator on the caller's stream, and "den0"/"den1" (when present)
-        around the denominator on the stream it runs on."""
+        around the denominator on the stream it runs on. With ``batch``
+        (default: the renderer's ``batch_views``) the two views are
+        preprocessed in one launch sequence (gs3_preprocess_views); with
+        ``overlap`` as well the denominator and the shading then run on the
+        side streams after it."""
         main = torch.cuda.current_stream()
-        if not overlap or check:
+        batch = self.batch_views if batch is None else batch
+        if batch and (not overlap or check):
+            lvb, cvb = self._preprocess_pair(light, cam, check)
+            if events is not None and "den0" in events:
+                events["den0"].record(main)
+            gs3_shadow_den(self.consts, lvb, self.num_den)
+            if events is not None and "den1" in events:
+                events["den1"].record(main)
+            if events is not None:
+                events["num0"].record(main)
+            gs3_shadow_num(self.consts, lvb, self.num_den)
+            if events is not None:
+                events["num1"].record(main)
+            gs3_shadow_resolve(lvb, self.num_den, self.T)
+        elif not overlap or check:
             lvb = self._preprocess("light", light, GS3_DEPTH_DIST, check)
             if events is not None and "den0" in events:
                 events["den0"].record(main)
@@ -678,7 +737,10 @@ class Renderer:
             # after everything already on the caller's stream (the previous
             # frame still reads these buffers), not after this frame's work
             ev_start.record(main)
-            lvb = self._preprocess("light", light, GS3_DEPTH_DIST, False)
+            if batch:
+                lvb, cvb = self._preprocess_pair(light, cam, False)
+            else:
+                lvb = self._preprocess("light", light, GS3_DEPTH_DIST, False)
             ev_light.record(main)
             s_den.wait_event(ev_light)
             with torch.cuda.stream(s_den):
@@ -692,9 +754,10 @@ class Renderer:
             gs3_shadow_num(self.consts, lvb, self.num_den)
             if events is not None:
                 events["num1"].record(main)
-            s_cam.wait_event(ev_start)
+            s_cam.wait_event(ev_light if batch else ev_start)
             with torch.cuda.stream(s_cam):
-                cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
+                if not batch:
+                    cvb = self._preprocess("cam", cam, GS3_DEPTH_Z, False)
                 gs3_shade(self.scene, cam, light, cvb, im["colour"], self.use_mlps)
             main.wait_stream(s_den)
             gs3_shadow_resolve(lvb, self.num_den, self.T)
@@ -837,8 +900,8 @@ class FramePipeline:
     frames later, after its previous frame on the same stream."""
 
     def __init__(self, scene: DeviceScene, depth: int = 2, consts: Optional[gs3_consts] = None,
-                 use_mlps: bool = True, pair_capacity: Optional[int] = None):
-        self.renderers = [Renderer(scene, consts, use_mlps, pair_capacity) for _ in range(depth)]
+                 use_mlps: bool = True, pair_capacity: Optional[int] = None, batch_views: bool = False):
+        self.renderers = [Renderer(scene, consts, use_mlps, pair_capacity, batch_views) for _ in range(depth)]
         self.streams = [torch.cuda.Stream() for _ in range(depth)]
         self.i = 0
 

@@ -163,3 +163,36 @@ def test_view_projection_checks():
     assert b"ortho_width" in gs3._lib.gs3_last_error()
     v.projection = 7
     assert gs3._lib.gs3_project(C.byref(scene), C.byref(v), C.byref(k), 1, C.byref(vb), None) == gs3.GS3_INVALID_ARG
+
+
+def test_preprocess_views_checks():
+    """gs3_preprocess_views checks every view before enqueuing anything:
+    n_views >= 1, matching sizes, and workspaces that do not overlap."""
+    from paper_2410_11419_amd import gs3
+    size = C.c_size_t()
+    assert gs3._lib.gs3_view_workspace_size(10, 64, 64, 1000, C.byref(size)) == 0
+    a = gs3.gs3_viewbuf(C.c_void_p(1 << 20), size.value, 10, 64, 64, 1000, None)
+    b = gs3.gs3_viewbuf(C.c_void_p((1 << 20) + 256), size.value, 10, 64, 64, 1000, None)   # overlaps a
+    scene = gs3.gs3_scene()
+    scene.n, scene.k = 10, 0
+    for nm in ("mean", "log_scale", "rot", "opacity_logit"):
+        setattr(scene, nm, 512)
+    k = gs3.default_consts()
+    v = gs3.gs3_view()
+    v.eye[2], v.width, v.height, v.fov = 4.0, 64, 64, 0.7
+    views = (gs3.gs3_view * 2)(v, v)
+    modes = (C.c_int32 * 2)(0, 1)
+    vbs = (gs3.gs3_viewbuf * 2)(a, b)
+    f = gs3._lib.gs3_preprocess_views
+    assert f(C.byref(scene), views, modes, 0, C.byref(k), vbs, None) == gs3.GS3_INVALID_ARG
+    assert f(C.byref(scene), views, modes, 2, C.byref(k), vbs, None) == gs3.GS3_INVALID_ARG
+    assert b"share workspace" in gs3._lib.gs3_last_error()
+    v2 = gs3.gs3_view()
+    v2.eye[2], v2.width, v2.height, v2.fov = 4.0, 32, 64, 0.7
+    views2 = (gs3.gs3_view * 2)(v, v2)
+    b2 = gs3.gs3_viewbuf(C.c_void_p(1 << 30), size.value, 10, 64, 64, 1000, None)
+    vbs2 = (gs3.gs3_viewbuf * 2)(a, b2)
+    assert f(C.byref(scene), views2, modes, 2, C.byref(k), vbs2, None) == gs3.GS3_INVALID_ARG
+    assert b"does not match" in gs3._lib.gs3_last_error()
+    modes_bad = (C.c_int32 * 2)(0, 5)
+    assert f(C.byref(scene), views, modes_bad, 2, C.byref(k), vbs2, None) == gs3.GS3_INVALID_ARG

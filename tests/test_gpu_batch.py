@@ -1,0 +1,143 @@
+"""GPU tests of the batched entry points: several views in one launch
+sequence give exactly (bit for bit) the splats and tile lists of the same
+views preprocessed one at a time, across batch chunks, mixed sizes, tile
+pass counts, packed and two-array pair sorts, and a view that overflows."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2410_11419_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs3():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2410_11419_amd import gs3 as g
+    assert g.device_ok(), "libgs3 needs a gfx950 device"
+    return g
+
+
+def _views():
+    rng = np.random.default_rng(17)
+    v = []
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 128, 128, 40.0), "z"))
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 128, 128, 60.0), "dist"))
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 200, 152, 40.0), "z"))     # ragged tiles
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 1, 1, 40.0), "z"))         # one pixel
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 3, 5, 60.0), "dist"))      # one tile
+    v.append((synth.make_directional(rng.standard_normal(3), 160, 160, 3.6), "dist"))  # orthographic
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0), "dist"))  # two tile passes
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 64, 48, 40.0), "z"))
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 800, 600, 50.0), "z"))      # second chunk
+    # 1M tiles (20 bits) + 13 id bits: the two-array sort, three tile passes
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 16384, 16384, 40.0), "z"))
+    v.append((synth.make_view(rng.standard_normal(3), 4.0, 96, 256, 30.0), "dist"))
+    return v
+
+
+def _mode(g, m):
+    return g.GS3_DEPTH_Z if m == "z" else g.GS3_DEPTH_DIST
+
+
+def _single(g, ds, view, mode, consts):
+    cap = 1 << 16
+    while True:
+        vb = g.ViewBuffer(ds.n, view.width, view.height, cap)
+        g.gs3_preprocess(ds, view, consts, mode, vb)
+        try:
+            return vb, g.gs3_view_pair_count(vb)
+        except g.Gs3Error as e:
+            assert e.status == g.GS3_PAIR_CAPACITY_EXCEEDED
+            cap = e.required + 1000
+
+
+def _export(g, vb):
+    lists = [t.cpu().numpy() for t in g.gs3_view_lists(vb)]
+    splats = [t.cpu().numpy() for t in g.gs3_view_splats(vb)]
+    return lists, splats
+
+
+def test_preprocess_views_equals_single(gs3):
+    sc, _, _ = synth.scene_small(seed=6)
+    ds = gs3.DeviceScene.from_host(sc)
+    k = gs3.default_consts()
+    views = _views()
+    singles, caps = [], []
+    for view, m in views:
+        vb, p = _single(gs3, ds, view, _mode(gs3, m), k)
+        singles.append(_export(gs3, vb))
+        caps.append(p + 7)
+    packed = [vb_bits for vb_bits in (math.ceil(math.log2(max(2, ((v.width + 15) // 16) * ((v.height + 15) // 16))))
+                                      for v, _ in views)]
+    print(f"{len(views)} views, pair counts {[c - 7 for c in caps]}, tile bits {packed}")
+    vbs = [gs3.ViewBuffer(ds.n, v.width, v.height, c) for (v, _), c in zip(views, caps)]
+    gs3.gs3_preprocess_views(ds, [v for v, _ in views], [_mode(gs3, m) for _, m in views], k, vbs)
+    for i, vb in enumerate(vbs):
+        assert gs3.gs3_view_pair_count(vb) == caps[i] - 7
+        (ts, te, ids, keys), splats = _export(gs3, vb)
+        (ts0, te0, ids0, keys0), splats0 = singles[i]
+        np.testing.assert_array_equal(te - ts, te0 - ts0)
+        np.testing.assert_array_equal(ids, ids0)
+        np.testing.assert_array_equal(keys, keys0)
+        for a, b in zip(splats, splats0):
+            np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    # the oracle's brute-force binning of two of them, from the GPU's extents
+    for i in (2, 9):
+        view = views[i][0]
+        (ts, te, ids, keys), (_, _, _, depth, ext) = singles[i]
+        ext = ext.astype(np.int64)
+        counts, oids, okeys = O.bin_tiles(ext[0], ext[1], ext[2], ext[3], depth, view.width, view.height)
+        np.testing.assert_array_equal(te - ts, counts)
+        np.testing.assert_array_equal(ids, oids)
+        np.testing.assert_array_equal(keys.view(np.uint64), okeys)
+
+
+def test_preprocess_views_overflow_is_per_view(gs3):
+    sc, _, _ = synth.scene_small(seed=7)
+    ds = gs3.DeviceScene.from_host(sc)
+    k = gs3.default_consts()
+    views = _views()[:4]
+    ref = [_single(gs3, ds, v, _mode(gs3, m), k) for v, m in views]
+    caps = [p + 3 for _, p in ref]
+    caps[1] = ref[1][1] // 3          # too small: overflows
+    vbs = [gs3.ViewBuffer(ds.n, v.width, v.height, c) for (v, _), c in zip(views, caps)]
+    gs3.gs3_preprocess_views(ds, [v for v, _ in views], [_mode(gs3, m) for _, m in views], k, vbs)
+    for i, vb in enumerate(vbs):
+        if i == 1:
+            with pytest.raises(gs3.Gs3Error) as ei:
+                gs3.gs3_view_pair_count(vb)
+            assert ei.value.status == gs3.GS3_PAIR_CAPACITY_EXCEEDED and ei.value.required == ref[1][1]
+            state, req = gs3.gs3_view_poll(vb)
+            assert state == gs3.GS3_VIEW_OVERFLOW and req == ref[1][1]
+        else:
+            assert gs3.gs3_view_pair_count(vb) == ref[i][1]
+            np.testing.assert_array_equal(gs3.gs3_view_lists(vb)[2].cpu().numpy(),
+                                          gs3.gs3_view_lists(ref[i][0])[2].cpu().numpy())
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_renderer_batched_views(gs3, overlap):
+    """Renderer(batch_views=True) preprocesses the light and camera views in
+    one launch sequence; frames equal the unbatched renderer's (the shadow
+    numerator's float atomics may add in another order: 1e-6)."""
+    sc = synth.make_scene(20000, 8, seed=8, means="shell", mlps=True)
+    ds = gs3.DeviceScene.from_host(sc)
+    a = gs3.Renderer(ds)
+    b = gs3.Renderer(ds, batch_views=True)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        cam = synth.make_view(rng.standard_normal(3), 4.0, 160, 120, 40.0)
+        light = synth.make_view(rng.standard_normal(3), 4.0, 192, 192, 40.0)
+        ra = a.render(cam, light, check=True)
+        b.render(cam, light, check=True)
+        rb = b.render(cam, light, check=False, overlap=overlap)
+        torch.cuda.synchronize()
+        assert not b.overflowed()
+        for key in ("final", "T_final", "S"):
+            assert float((ra[key] - rb[key]).abs().max()) <= 1e-6, key
+        assert float((ra["T"] - rb["T"]).abs().max()) <= 1e-6
