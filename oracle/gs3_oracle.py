@@ -39,7 +39,7 @@ __all__ = [
     "render_images", "sigmoid", "l1_loss", "hit_threshold", "hit_margin", "transmittance_relerr",
     "AMB_BUDGET", "HIT_KAPPA", "pair_key", "ssim_window", "ssim_map", "dssim_loss", "adam_step",
     "SSIM_C1", "SSIM_C2", "SSIM_WINDOW", "SSIM_SIGMA", "LOSS_LAMBDA", "CANDIDATE_CUT", "is_ortho",
-    "render_env",
+    "render_env", "PE_BANDS", "LEAKY_SLOPE", "positional_encoding", "shade_basis", "basis_mlp_inputs",
 ]
 
 DT = torch.float64
@@ -47,6 +47,14 @@ DT = torch.float64
 # Sec. 4.1, Eq. 5: the ELU hyper-parameter and epsilon are both 0.01.
 ELU_ALPHA = 0.01
 EPS_D = 0.01
+
+# Sec. 4.2 / 4.3 (the paper's MLP form): 4-band positional encoding of the
+# centre and the light / view direction, leaky ReLU after each hidden layer.
+# The paper gives neither the encoding's frequencies nor the slope; the
+# readings are frequencies 2^k pi (k = 0..3) with the input itself kept, and
+# the customary slope 0.01.
+PE_BANDS = 4
+LEAKY_SLOPE = 0.01
 
 
 @dataclass(frozen=True)
@@ -113,6 +121,25 @@ def scene_tensors(scene, requires_grad: bool = False) -> Dict[str, torch.Tensor]
         "lobe_log_sharp": t(scene.lobe_log_sharp, (1, 0)),  # [N,K]
         "lobe_amp": t(scene.lobe_amp, (2, 0, 1)),        # [N,K,3]
         "feat": t(scene.feat, (1, 0)),
+        **_basis_tensors(scene, t),
+    }
+
+
+def _basis_tensors(scene, t) -> Dict[str, torch.Tensor]:
+    """The shared-basis appearance of Sec. 4.1 when the scene carries one
+    (``scene.basis``): per Gaussian rho_s [N,3], the basis weights alpha
+    [N,K] and the latent l [N,6]; shared by all Gaussians, each basis angular
+    Gaussian's frame quaternion [K,4] and log(sigma_x, sigma_y, sigma_z)
+    [K,3]."""
+    b = getattr(scene, "basis", None)
+    if b is None:
+        return {}
+    return {
+        "spec_albedo": t(b.spec_albedo, (1, 0)),
+        "basis_weight": t(b.weight, (1, 0)),
+        "latent": t(b.latent, (1, 0)),
+        "basis_rot": t(b.basis_rot),
+        "basis_log_sigma": t(b.basis_log_sigma),
     }
 
 
@@ -663,14 +690,7 @@ def shade(p: Dict[str, torch.Tensor], light_pos, eye, light_dir=None) -> Dict[st
     light, Sec. 4.5) w_i is that unit direction toward the light for every
     Gaussian."""
     mu = p["mean"]
-    if light_dir is not None:
-        d = as_t(light_dir)
-        wi = (d / torch.linalg.norm(d)).expand_as(mu)
-    else:
-        wi = as_t(light_pos) - mu
-        wi = wi / torch.linalg.norm(wi, dim=-1, keepdim=True)
-    wo = as_t(eye) - mu
-    wo = wo / torch.linalg.norm(wo, dim=-1, keepdim=True)
+    wi, wo = _directions(mu, light_pos, eye, light_dir)
     Rsh = quat_to_rotmat(p["shade_rot"])
     wi_l = (Rsh @ wi[..., None])[..., 0]
     wo_l = (Rsh @ wo[..., None])[..., 0]
@@ -689,14 +709,87 @@ def shade(p: Dict[str, torch.Tensor], light_pos, eye, light_dir=None) -> Dict[st
     return {"c": c, "wi": wi, "wo": wo, "fd": fd, "h": h, "G": G}
 
 
-def mlp_forward(layers, x: torch.Tensor) -> torch.Tensor:
-    """Dense layers, ReLU after each hidden layer, sigmoid at the output
-    (Sec. 4.2 and 4.3). ``layers`` = [(W [out,in], b [out]), ...]."""
+def _directions(mu, light_pos, eye, light_dir=None):
+    """Unit w_i (toward the light, or a directional light's fixed direction)
+    and w_o (toward the camera) per Gaussian centre."""
+    if light_dir is not None:
+        d = as_t(light_dir)
+        wi = (d / torch.linalg.norm(d)).expand_as(mu)
+    else:
+        wi = as_t(light_pos) - mu
+        wi = wi / torch.linalg.norm(wi, dim=-1, keepdim=True)
+    wo = as_t(eye) - mu
+    wo = wo / torch.linalg.norm(wo, dim=-1, keepdim=True)
+    return wi, wo
+
+
+def shade_basis(p: Dict[str, torch.Tensor], light_pos, eye, light_dir=None) -> Dict[str, torch.Tensor]:
+    """First splatting with the paper's shared basis (Sec. 4.1, Eq. 4-7 and
+    the shared-basis paragraph): c = rho_d f_d(w_i') + rho_s sum_j alpha_j
+    G_j(h'), where the K basis angular Gaussians are shared by every spatial
+    Gaussian and each spatial Gaussian has its own shading frame, rho_d,
+    rho_s (RGB) and weights alpha_j.
+
+    Basis j has a frame [x_j, y_j, z_j] in the shading frame, given by a
+    quaternion whose rotation maps shading-frame coordinates to the basis
+    frame (the rows of its matrix are x_j, y_j, z_j, the same convention as
+    the world-to-shading quaternion), and sigma_x, sigma_y, sigma_z =
+    exp(log sigma). G_j is Eq. 7, anisotropic (``angular_gaussian``).
+    w_i, w_o, h' and f_d are as in ``shade``."""
+    mu = p["mean"]
+    wi, wo = _directions(mu, light_pos, eye, light_dir)
+    Rsh = quat_to_rotmat(p["shade_rot"])
+    wi_l = (Rsh @ wi[..., None])[..., 0]
+    wo_l = (Rsh @ wo[..., None])[..., 0]
+    fd = diffuse(wi_l[:, 2])
+    hs = wi_l + wo_l
+    hn = torch.linalg.norm(hs, dim=-1, keepdim=True)
+    ok = hn > 1e-12
+    ez = torch.tensor([0.0, 0.0, 1.0], dtype=DT).expand_as(hs)
+    h = torch.where(ok, hs / torch.where(ok, hn, torch.ones_like(hn)), ez)
+    Rb = quat_to_rotmat(p["basis_rot"])                # [K,3,3], rows x, y, z
+    sig = torch.exp(p["basis_log_sigma"])             # [K,3]
+    K = Rb.shape[0]
+    hk = h[:, None, :].expand(-1, K, -1)
+    G = angular_gaussian(hk, Rb[None, :, 0, :], Rb[None, :, 1, :], Rb[None, :, 2, :],
+                         sig[None, :, 0], sig[None, :, 1], sig[None, :, 2])   # [N,K]
+    fs = (p["basis_weight"] * G).sum(1)                # Eq. 6
+    c = p["albedo"] * fd[:, None] + p["spec_albedo"] * fs[:, None]
+    return {"c": c, "wi": wi, "wo": wo, "fd": fd, "h": h, "G": G}
+
+
+def positional_encoding(x: torch.Tensor, bands: int = PE_BANDS) -> torch.Tensor:
+    """Positional encoding of Sec. 4.2 / 4.3 with `bands` frequency bands:
+    [x, sin(pi x), cos(pi x), sin(2 pi x), cos(2 pi x), ...,
+    sin(2^(bands-1) pi x), cos(2^(bands-1) pi x)], each entry a block of the
+    components of x (3 + 6 bands values for a 3-vector)."""
+    out = [x]
+    for k in range(bands):
+        out.append(torch.sin((2.0 ** k) * math.pi * x))
+        out.append(torch.cos((2.0 ** k) * math.pi * x))
+    return torch.cat(out, -1)
+
+
+def basis_mlp_inputs(p: Dict[str, torch.Tensor], T: torch.Tensor, wi: torch.Tensor, wo: torch.Tensor):
+    """Inputs of the paper's MLPs: Phi(T, w_i; mu, l) (Sec. 4.2, Eq. 8) gets
+    [T, PE(w_i), PE(mu), l] (61 values) and Psi(w_o; mu, l) (Sec. 4.3) gets
+    [PE(w_o), PE(mu), l] (60 values); w_i, w_o and mu in world space, l the
+    per-Gaussian 6-D latent shared by both."""
+    pm = positional_encoding(p["mean"])
+    phi_in = torch.cat([T[:, None], positional_encoding(wi), pm, p["latent"]], 1)
+    psi_in = torch.cat([positional_encoding(wo), pm, p["latent"]], 1)
+    return phi_in, psi_in
+
+
+def mlp_forward(layers, x: torch.Tensor, slope: float = 0.0) -> torch.Tensor:
+    """Dense layers, ReLU (slope = 0) or leaky ReLU with the given negative
+    slope after each hidden layer, sigmoid at the output (Sec. 4.2 and 4.3).
+    ``layers`` = [(W [out,in], b [out]), ...]."""
     hcur = x
     for i, (w, b) in enumerate(layers):
         hcur = hcur @ as_t(w).T + as_t(b)
         if i + 1 < len(layers):
-            hcur = torch.relu(hcur)
+            hcur = torch.where(hcur > 0, hcur, slope * hcur) if slope else torch.relu(hcur)
     return sigmoid(hcur)
 
 
@@ -816,22 +909,34 @@ def render(scene, cam_view, light_view, consts: Consts = Consts(),
     with torch.no_grad():
         amb_T = torch.where(den > 0, infl / torch.where(den > 0, den, torch.ones_like(den)),
                             torch.where(infl > 0, torch.ones_like(infl), torch.zeros_like(infl)))
+    # the paper's shared-basis appearance and MLP inputs when the scene has
+    # them, else the isotropic per-Gaussian lobes and [T, feat] / [feat, w_i, w_o]
+    basis = "basis_weight" in p
+    shade_fn = shade_basis if basis else shade
+    slope = LEAKY_SLOPE if basis else 0.0
     if is_ortho(light_view):
-        sh = shade(p, None, cam_view.eye, light_dir=np.asarray(light_view.eye) - np.asarray(light_view.target))
+        sh = shade_fn(p, None, cam_view.eye, light_dir=np.asarray(light_view.eye) - np.asarray(light_view.target))
     else:
-        sh = shade(p, light_pos, cam_view.eye)
+        sh = shade_fn(p, light_pos, cam_view.eye)
+
+    def phi_input(t, q, wi):
+        if basis:
+            return basis_mlp_inputs(q, t, wi, sh["wo"])[0]
+        return torch.cat([t[:, None], q["feat"]], 1)
     if phi is not None:
-        tp = mlp_forward(phi, torch.cat([T[:, None], p["feat"]], 1))[:, 0]
+        tp = mlp_forward(phi, phi_input(T, p, sh["wi"]), slope)[:, 0]
         with torch.enable_grad():
             tq = T.detach().clone().requires_grad_(True)
-            yq = mlp_forward(phi, torch.cat([tq[:, None], p["feat"].detach()], 1))[:, 0]
+            yq = mlp_forward(phi, phi_input(tq, {k: v.detach() for k, v in p.items()}, sh["wi"].detach()),
+                             slope)[:, 0]
             dphi = torch.autograd.grad(yq.sum(), tq)[0].abs()
         amb_Tp = 2.0 * dphi * amb_T
     else:
         tp = T
         amb_Tp = amb_T
     if psi is not None:
-        r = mlp_forward(psi, torch.cat([p["feat"], sh["wi"], sh["wo"]], 1))
+        x_psi = basis_mlp_inputs(p, T, sh["wi"], sh["wo"])[1] if basis else torch.cat([p["feat"], sh["wi"], sh["wo"]], 1)
+        r = mlp_forward(psi, x_psi, slope)
     else:
         r = torch.zeros_like(sh["c"])
     proj_c = project(p["mean"], cov, cam_view, consts, "z")

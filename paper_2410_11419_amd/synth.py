@@ -33,10 +33,19 @@ __all__ = [
     "Scene", "View", "Mlp", "make_scene", "make_view", "random_views",
     "scene_small", "scene_full", "scene_fluffy", "fluffy_pairs", "scene_gradcheck",
     "perturb_scene", "subset", "concat_scenes", "scene_needles", "make_directional", "environment_lights",
+    "BasisAppearance", "make_basis_scene", "scene_basis_small", "scene_basis_full", "scene_basis_gradcheck",
 ]
 
 FEAT_DIM = 16
 HIDDEN = 64
+# the paper's MLP form (Sec. 4.2 / 4.3): 6-D latent, 4-band positional
+# encoding of 3-vectors (3 + 2 * 4 * 3 = 27 values), Phi {32}^3, Psi {128}^3
+LATENT_DIM = 6
+PE_DIM = 27
+PHI_BASIS_IN = 1 + 2 * PE_DIM + LATENT_DIM     # [T, PE(w_i), PE(mu), l]
+PSI_BASIS_IN = 2 * PE_DIM + LATENT_DIM         # [PE(w_o), PE(mu), l]
+PHI_BASIS_HIDDEN = 32
+PSI_BASIS_HIDDEN = 128
 
 
 @dataclasses.dataclass
@@ -54,6 +63,23 @@ class Mlp:
 
 
 @dataclasses.dataclass
+class BasisAppearance:
+    """The paper's appearance parameters (Sec. 4.1 shared basis; Sec. 4.2
+    latent): per Gaussian rho_s, basis weights alpha_j and the 6-D latent;
+    shared by all Gaussians, the K basis angular Gaussians' frames and
+    log-sigmas."""
+    spec_albedo: np.ndarray      # [3, N]  rho_s
+    weight: np.ndarray           # [K, N]  alpha_j
+    latent: np.ndarray           # [6, N]  l
+    basis_rot: np.ndarray        # [K, 4]  quaternion (w, x, y, z): shading -> basis frame
+    basis_log_sigma: np.ndarray  # [K, 3]  log sigma_x, sigma_y, sigma_z
+
+    @property
+    def k(self) -> int:
+        return self.weight.shape[0]
+
+
+@dataclasses.dataclass
 class Scene:
     """Raw (pre-activation) per-Gaussian parameters, float32 SoA."""
     mean: np.ndarray            # [3, N]
@@ -68,6 +94,8 @@ class Scene:
     feat: np.ndarray            # [16, N]
     phi: Optional[Mlp] = None   # shadow refinement MLP, None = passthrough
     psi: Optional[Mlp] = None   # residual RGB MLP, None = zero residual
+    # the paper's shared-basis appearance; None = per-Gaussian isotropic lobes
+    basis: Optional[BasisAppearance] = None
 
     @property
     def n(self) -> int:
@@ -75,7 +103,8 @@ class Scene:
 
     @property
     def k(self) -> int:
-        return self.lobe_axis.shape[0]
+        """Lobes per Gaussian, or basis angular Gaussians of a basis scene."""
+        return self.basis.k if self.basis is not None else self.lobe_axis.shape[0]
 
 
 @dataclasses.dataclass
@@ -277,7 +306,10 @@ def concat_scenes(a: Scene, b: Scene) -> Scene:
                  rot=cat(a.rot, b.rot, 1), opacity_logit=cat(a.opacity_logit, b.opacity_logit, 0),
                  shade_rot=cat(a.shade_rot, b.shade_rot, 1), albedo=cat(a.albedo, b.albedo, 1),
                  lobe_axis=cat(a.lobe_axis, b.lobe_axis, 2), lobe_log_sharp=cat(a.lobe_log_sharp, b.lobe_log_sharp, 1),
-                 lobe_amp=cat(a.lobe_amp, b.lobe_amp, 2), feat=cat(a.feat, b.feat, 1), phi=a.phi, psi=a.psi)
+                 lobe_amp=cat(a.lobe_amp, b.lobe_amp, 2), feat=cat(a.feat, b.feat, 1), phi=a.phi, psi=a.psi,
+                 basis=None if a.basis is None else dataclasses.replace(
+                     a.basis, spec_albedo=cat(a.basis.spec_albedo, b.basis.spec_albedo, 1),
+                     weight=cat(a.basis.weight, b.basis.weight, 1), latent=cat(a.basis.latent, b.basis.latent, 1)))
 
 
 def scene_needles(seed: int = 0, n_needles: int = 60, n_blobs: int = 340, mlps: bool = True):
@@ -324,4 +356,70 @@ def subset(sc: Scene, idx) -> Scene:
         lobe_amp=np.ascontiguousarray(sc.lobe_amp[:, :, idx]),
         feat=np.ascontiguousarray(sc.feat[:, idx]),
         phi=sc.phi, psi=sc.psi,
+        basis=None if sc.basis is None else dataclasses.replace(
+            sc.basis, spec_albedo=np.ascontiguousarray(sc.basis.spec_albedo[:, idx]),
+            weight=np.ascontiguousarray(sc.basis.weight[:, idx]),
+            latent=np.ascontiguousarray(sc.basis.latent[:, idx])),
     )
+
+
+def make_basis_scene(n: int, seed: int = 0, k: int = 8, mlps: bool = True, **geometry) -> Scene:
+    """A scene with the paper's appearance model (Sec. 4.1 shared basis of
+    `k` anisotropic angular Gaussians; Sec. 4.2 / 4.3 MLP form).
+
+    Geometry, opacity, rho_d and shading frames are drawn exactly as
+    ``make_scene(n, 0, seed, mlps=False, **geometry)`` draws them (no
+    per-Gaussian lobes). A second generator, seeded with (seed, 7), then
+    draws in this order: rho_s U[0,1]^3, weights alpha U[0,1]^k, latent
+    N(0, 0.1)^6 per Gaussian; per basis a random unit frame quaternion,
+    sigma_x and sigma_y U[0.3, 1.0] (anisotropic; the paper initialises
+    0.5 and 1.0) and sigma_z U[0.13, 0.69] (the paper's initial range),
+    stored as logs; then, when `mlps`, Phi 61 -> 32 -> 32 -> 32 -> 1 and Psi
+    60 -> 128 -> 128 -> 128 -> 3 (Xavier-uniform weights, zero biases, layer
+    order)."""
+    sc = make_scene(n, 0, seed, mlps=False, **geometry)
+    rng = np.random.default_rng([seed, 7])
+    f = np.float32
+    spec = rng.uniform(0.0, 1.0, size=(n, 3))
+    weight = rng.uniform(0.0, 1.0, size=(n, k))
+    latent = rng.normal(0.0, 0.1, size=(n, LATENT_DIM))
+    brot = _unit_rows(rng.standard_normal((k, 4)))
+    sxy = rng.uniform(0.3, 1.0, size=(k, 2))
+    sz = rng.uniform(0.13, 0.69, size=(k, 1))
+    log_sigma = np.log(np.concatenate([sxy, sz], 1))
+    sc.basis = BasisAppearance(
+        spec_albedo=np.ascontiguousarray(spec.T, f),
+        weight=np.ascontiguousarray(weight.T, f),
+        latent=np.ascontiguousarray(latent.T, f),
+        basis_rot=np.ascontiguousarray(brot, f),
+        basis_log_sigma=np.ascontiguousarray(log_sigma, f),
+    )
+    if mlps:
+        sc.phi = _make_mlp(rng, PHI_BASIS_IN, 1, hidden=PHI_BASIS_HIDDEN)
+        sc.psi = _make_mlp(rng, PSI_BASIS_IN, 3, hidden=PSI_BASIS_HIDDEN)
+    return sc
+
+
+def scene_basis_small(seed: int = 0, n: int = 4096, mlps: bool = True):
+    """``scene_small``'s geometry and views with the paper's appearance."""
+    sc = make_basis_scene(n, seed, means="cube", mlps=mlps)
+    _, cam, light = scene_small(seed)
+    return sc, cam, light
+
+
+def scene_basis_full(seed: int = 0, n: int = 300_000):
+    """``scene_full``'s geometry and views (300K shell Gaussians, 800^2
+    camera, 1024^2 light) with the paper's appearance and MLPs."""
+    sc = make_basis_scene(n, seed, means="shell", mlps=True)
+    rng = np.random.default_rng(1)
+    cam = make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0)
+    light = make_view(rng.standard_normal(3), 4.0, 1024, 1024, 40.0)
+    return sc, cam, light
+
+
+def scene_basis_gradcheck(seed: int = 0, n: int = 256, mlps: bool = True):
+    """``scene_gradcheck``'s geometry and views with the paper's appearance."""
+    sc = make_basis_scene(n, seed, means="cube", log_scale_mu=(-2.0, -2.0, -2.0),
+                          log_scale_sd=(0.3, 0.3, 0.3), mlps=mlps)
+    _, cam, light = scene_gradcheck(seed, n=8, k=1, mlps=False)
+    return sc, cam, light
