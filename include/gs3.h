@@ -112,10 +112,29 @@ typedef struct {
     double ortho_width;  /* orthographic: world units across the image width, > 0 */
 } gs3_view;
 
+/* Appearance model of a scene (gs3_scene.appearance):
+ *   GS3_APPEARANCE_LOBES  k isotropic angular lobes per Gaussian, each with
+ *       its own axis, sharpness and RGB amplitude (Eq. 7 with sigma_x =
+ *       sigma_y), and the MLP inputs [T, feat] / [feat, w_i, w_o] with
+ *       3x64 ReLU hidden layers.
+ *   GS3_APPEARANCE_BASIS  the paper's own form: k anisotropic basis angular
+ *       Gaussians SHARED by all spatial Gaussians (Sec. 4.1, Eq. 6-7 and the
+ *       shared-basis paragraph), c = rho_d f_d + rho_s sum_j alpha_j G_j(h');
+ *       Phi(T, w_i; mu, l) (Sec. 4.2, Eq. 8) with 3x32 and Psi(w_o; mu, l)
+ *       (Sec. 4.3) with 3x128 leaky-ReLU (slope 0.01) hidden layers, inputs
+ *       [T, PE(w_i), PE(mu), l] (61) and [PE(w_o), PE(mu), l] (60), where
+ *       PE(v) = [v, sin(2^j pi v), cos(2^j pi v) for j = 0..3] (27 values
+ *       for a 3-vector, each block ordered x, y, z) and l is the per-Gaussian
+ *       6-D latent; w_i, w_o and mu in world space. */
+enum { GS3_APPEARANCE_LOBES = 0, GS3_APPEARANCE_BASIS = 1 };
+
 /* Raw (pre-activation) per-Gaussian parameters, device float32 SoA.
  * Activations applied inside the library: scale = exp(log_scale),
  * opacity = sigmoid(opacity_logit), quaternions (w,x,y,z) normalised,
- * lobe axes normalised, lobe sharpness lambda = exp(lobe_log_sharp). */
+ * lobe axes normalised, lobe sharpness lambda = exp(lobe_log_sharp),
+ * basis sigmas = exp(basis_log_sigma). The lobe and feat pointers are read
+ * only by GS3_APPEARANCE_LOBES, the fields after `appearance` only by
+ * GS3_APPEARANCE_BASIS (zero-initialise the struct for the former). */
 typedef struct {
     const float* mean;           /* [3][n] */
     const float* log_scale;      /* [3][n] */
@@ -128,13 +147,23 @@ typedef struct {
     const float* lobe_amp;       /* [k][3][n] RGB weight of each lobe */
     const float* feat;           /* [16][n] per-Gaussian MLP feature */
     int64_t n;                   /* number of Gaussians, >= 0, < 2^31 */
-    int32_t k;                   /* lobes per Gaussian, 0..16 */
+    int32_t k;                   /* lobes per Gaussian (LOBES) or basis angular
+                                    Gaussians (BASIS), 0..16 */
+    int32_t appearance;          /* GS3_APPEARANCE_LOBES or GS3_APPEARANCE_BASIS */
+    const float* spec_albedo;    /* [3][n]  rho_s */
+    const float* basis_weight;   /* [k][n]  alpha_j */
+    const float* latent;         /* [6][n]  l, input of both MLPs */
+    const float* basis_rot;      /* [k][4]  shared: quaternion mapping shading-frame
+                                    coordinates to basis j's frame [x_j, y_j, z_j] */
+    const float* basis_log_sigma;/* [k][3]  shared: log sigma_x, sigma_y, sigma_z */
 } gs3_scene;
 
-/* A dense MLP with three hidden layers of 64 ReLU units and a sigmoid
- * output: w[i] is row-major [out][in] float32, b[i] is [out].
- * Phi (shadow refinement, Eq. 8): n_in = 17 ([T, feat]), n_out = 1.
- * Psi (residual RGB, Sec. 4.3): n_in = 22 ([feat, w_i, w_o]), n_out = 3. */
+/* A dense MLP with three hidden layers and a sigmoid output: w[i] is
+ * row-major [out][in] float32, b[i] is [out]. GS3_APPEARANCE_LOBES: 64
+ * ReLU units per hidden layer, Phi (shadow refinement, Eq. 8) n_in = 17
+ * ([T, feat]), n_out = 1; Psi (residual RGB, Sec. 4.3) n_in = 22 ([feat,
+ * w_i, w_o]), n_out = 3. GS3_APPEARANCE_BASIS: leaky ReLU (slope 0.01),
+ * Phi 61 -> 32 -> 32 -> 32 -> 1, Psi 60 -> 128 -> 128 -> 128 -> 3. */
 typedef struct {
     const float* w[4];
     const float* b[4];
@@ -210,6 +239,13 @@ typedef struct gs3_grads {
     float* phi_b[4];
     float* psi_w[4];
     float* psi_b[4];
+    /* GS3_APPEARANCE_BASIS only (the lobe and feat pointers above are then
+     * not used): layouts of the gs3_scene fields of the same names */
+    float* spec_albedo;
+    float* basis_weight;
+    float* latent;
+    float* basis_rot;
+    float* basis_log_sigma;
 } gs3_grads;
 
 void gs3_consts_default(gs3_consts* out);
@@ -360,15 +396,17 @@ int gs3_shadow_resolve(const gs3_viewbuf* light_vb, float* num_den, float* T, gs
  * w_i the unit vector from the Gaussian to it; an orthographic view: a
  * directional light, w_i = (eye - target) / |eye - target| for every
  * Gaussian; Sec. 4.5) seen from the camera `cam`
- * (c = rho_d f_d + sum_k amp_k G_k, Eq. 4-7, isotropic lobes, unit light),
+ * (c = rho_d f_d + sum_k amp_k G_k, Eq. 4-7, isotropic lobes, unit light;
+ * or, for a GS3_APPEARANCE_BASIS scene, c = rho_d f_d + rho_s sum_j
+ * alpha_j G_j with the shared anisotropic basis),
  * refine T with Phi (T' = T if phi is NULL), evaluate Psi (r = 0 if psi is
  * NULL), then splat c, T' and r toward the camera front to back and write
  * final = S * Sh + R. `cam_vb` holds `cam` preprocessed with GS3_DEPTH_Z.
  * MLP weight pointers may be in any device memory; n_in/n_out must be
- * 17/1 (phi) and 22/3 (psi). The MLP arithmetic is float32; its hidden
- * layers run as split half-precision products (each operand hi + lo/2048,
- * about 2^-22 relative per product), which assumes hidden activations and
- * weights below the half range (65504). */
+ * 17/1 (phi) and 22/3 (psi), or 61/1 and 60/3 for a basis scene. The MLP
+ * arithmetic is float32; its hidden layers run as split half-precision
+ * products (each operand hi + lo/2048, about 2^-22 relative per product),
+ * which assumes layer inputs and weights below the half range (65504). */
 int gs3_render(const gs3_scene* scene, const gs3_view* cam,
                const gs3_view* light, const gs3_consts* consts,
                const float* T, const gs3_mlp* phi, const gs3_mlp* psi,
@@ -397,6 +435,11 @@ int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_vie
  * colour gradients, per-light-pixel sums, and the MLP activations kept for
  * the weight gradients (about 3.3 KB per Gaussian with both MLPs). */
 int gs3_backward_workspace_size(int64_t n, int32_t light_width, int32_t light_height, size_t* bytes);
+/* The same for a scene of appearance `appearance` (gs3_backward_workspace_size
+ * is this with GS3_APPEARANCE_LOBES). GS3_APPEARANCE_BASIS keeps about 4.4 KB
+ * per Gaussian: both MLPs' layer inputs and pre-activation gradients. */
+int gs3_backward_workspace_size_for(int32_t appearance, int64_t n, int32_t light_width, int32_t light_height,
+                                    size_t* bytes);
 
 /* Sec. 4.4 (training by gradient descent on an image loss): the adjoint of
  * gs3_shadow_splat followed by gs3_render. Given dL_dfinal [3][H][W] (the

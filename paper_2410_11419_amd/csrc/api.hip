@@ -185,7 +185,16 @@ static int check_scene(const gs3_scene* s, bool need_shading) {
     if (s->n == 0) return GS3_OK;
     if (!s->mean || !s->log_scale || !s->rot || !s->opacity_logit)
         return fail(GS3_INVALID_ARG, "scene geometry pointer is NULL");
-    if (need_shading && (!s->shade_rot || !s->albedo || !s->feat || (s->k > 0 && (!s->lobe_axis || !s->lobe_log_sharp || !s->lobe_amp))))
+    if (s->appearance != GS3_APPEARANCE_LOBES && s->appearance != GS3_APPEARANCE_BASIS)
+        return fail(GS3_INVALID_ARG, "scene.appearance must be GS3_APPEARANCE_LOBES or GS3_APPEARANCE_BASIS");
+    if (!need_shading) return GS3_OK;
+    if (s->appearance == GS3_APPEARANCE_BASIS) {
+        if (!s->shade_rot || !s->albedo || !s->spec_albedo || !s->latent ||
+            (s->k > 0 && (!s->basis_weight || !s->basis_rot || !s->basis_log_sigma)))
+            return fail(GS3_INVALID_ARG, "scene appearance pointer is NULL (basis appearance)");
+        return GS3_OK;
+    }
+    if (!s->shade_rot || !s->albedo || !s->feat || (s->k > 0 && (!s->lobe_axis || !s->lobe_log_sharp || !s->lobe_amp)))
         return fail(GS3_INVALID_ARG, "scene appearance pointer is NULL");
     return GS3_OK;
 }
@@ -204,6 +213,12 @@ static SceneDev scene_dev(const gs3_scene* s) {
     d.feat = s->feat;
     d.n = (int32_t)s->n;
     d.k = s->k;
+    d.appearance = s->appearance;
+    d.spec_albedo = s->spec_albedo;
+    d.basis_weight = s->basis_weight;
+    d.latent = s->latent;
+    d.basis_rot = s->basis_rot;
+    d.basis_log_sigma = s->basis_log_sigma;
     return d;
 }
 
@@ -251,11 +266,27 @@ static int view_params(const gs3_view* v, const Layout& L, int depth_mode, ViewP
 static int check_mlp(const gs3_mlp* m, int n_in, int n_out, const char* name) {
     if (!m) return GS3_OK;
     if (m->n_in != n_in || m->n_out != n_out)
-        return fail(GS3_INVALID_ARG, "%s must be %d -> 64 -> 64 -> 64 -> %d (got n_in=%d, n_out=%d)", name, n_in,
+        return fail(GS3_INVALID_ARG, "%s must take %d inputs and give %d outputs (got n_in=%d, n_out=%d)", name, n_in,
                     n_out, m->n_in, m->n_out);
     for (int i = 0; i < 4; ++i)
         if (!m->w[i] || !m->b[i]) return fail(GS3_INVALID_ARG, "%s weight pointer %d is NULL", name, i);
     return GS3_OK;
+}
+
+// Phi and Psi shapes of the scene's appearance model.
+static int check_mlps(const gs3_scene* scene, const gs3_mlp* phi, const gs3_mlp* psi) {
+    const bool basis = scene->appearance == GS3_APPEARANCE_BASIS;
+    int st = check_mlp(phi, basis ? kPhiBasisIn : 17, 1, "phi");
+    if (st != GS3_OK) return st;
+    return check_mlp(psi, basis ? kPsiBasisIn : 22, 3, "psi");
+}
+
+static hipError_t shade_launch(const gs3_scene* scene, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                               const gs3_mlp* psi, const Layout& L, void* ws, float* colour, int parts,
+                               hipStream_t st) {
+    if (scene->appearance == GS3_APPEARANCE_BASIS)
+        return launch_basis_shade(scene_dev(scene), sp, T, phi, psi, L, ws, colour, parts, st);
+    return launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, ws, colour, parts, st);
 }
 
 }  // namespace gs3
@@ -559,11 +590,10 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam, const gs3_view* ligh
         !out->n_contrib || !out->colour)
         return fail(GS3_INVALID_ARG, "an output pointer is NULL");
     if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
-    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
-    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    if ((st = check_mlps(scene, phi, psi)) != GS3_OK) return st;
     const ShadeParams sp = shade_params(cam, light, phi, psi);
     hipStream_t s = (hipStream_t)stream;
-    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, psi, L, cam_vb->ws, out->colour, 3, s));
+    GS3_CHECK_HIP(shade_launch(scene, sp, T, phi, psi, L, cam_vb->ws, out->colour, 3, s));
     GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
     return GS3_OK;
 }
@@ -574,10 +604,9 @@ int gs3_shade(const gs3_scene* scene, const gs3_view* cam, const gs3_view* light
     int st;
     if ((st = render_args(scene, cam, light, nullptr, cam_vb, &L)) != GS3_OK) return st;
     if (!colour) return fail(GS3_INVALID_ARG, "colour is NULL");
-    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    if ((st = check_mlps(scene, nullptr, psi)) != GS3_OK) return st;
     const ShadeParams sp = shade_params(cam, light, nullptr, psi);
-    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, nullptr, nullptr, psi, L, cam_vb->ws, colour, 1,
-                                   (hipStream_t)stream));
+    GS3_CHECK_HIP(shade_launch(scene, sp, nullptr, nullptr, psi, L, cam_vb->ws, colour, 1, (hipStream_t)stream));
     return GS3_OK;
 }
 
@@ -592,10 +621,10 @@ int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_vie
         !out->n_contrib || !out->colour)
         return fail(GS3_INVALID_ARG, "an output pointer is NULL");
     if (L.n > 0 && !T) return fail(GS3_INVALID_ARG, "T is NULL");
-    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
+    if ((st = check_mlps(scene, phi, nullptr)) != GS3_OK) return st;
     const ShadeParams sp = shade_params(cam, light, phi, nullptr);
     hipStream_t s = (hipStream_t)stream;
-    GS3_CHECK_HIP(launch_shade_mlp(scene_dev(scene), sp, T, phi, nullptr, L, cam_vb->ws, out->colour, 2, s));
+    GS3_CHECK_HIP(shade_launch(scene, sp, T, phi, nullptr, L, cam_vb->ws, out->colour, 2, s));
     GS3_CHECK_HIP(launch_render(*consts, L, cam_vb->ws, *out, s));
     return GS3_OK;
 }
@@ -606,7 +635,7 @@ int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_vie
 struct BwdLayout {
     size_t gcam, gcol, glight, dT, dnum, gray, rows, partial, total;
 };
-static bool bwd_layout(int64_t n, int32_t lw, int32_t lh, BwdLayout* B) {
+static bool bwd_layout(int32_t appearance, int64_t n, int32_t lw, int32_t lh, BwdLayout* B) {
     if (n < 0 || n >= (int64_t(1) << 31) || lw <= 0 || lh <= 0 || lw > 16384 || lh > 16384) return false;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -622,19 +651,32 @@ static bool bwd_layout(int64_t n, int32_t lw, int32_t lh, BwdLayout* B) {
     B->dT = take(4 * nn);
     B->dnum = take(4 * nn);
     B->gray = take(4 * (size_t)lw * lh);
-    B->rows = take(4 * (size_t)mlp_scratch_rows() * nn);
-    B->partial = take(4 * (size_t)chunks * wgrad_total_params(true, true));
+    if (appearance == GS3_APPEARANCE_BASIS) {
+        B->rows = take(4 * (size_t)basis_scratch_rows() * nn);
+        B->partial = take(4 * ((size_t)basis_partial_floats(kMaxLobes) +
+                               (size_t)chunks * basis_wgrad_total_params()));
+    } else {
+        B->rows = take(4 * (size_t)mlp_scratch_rows() * nn);
+        B->partial = take(4 * (size_t)chunks * wgrad_total_params(true, true));
+    }
     B->total = off;
     return true;
 }
 
-int gs3_backward_workspace_size(int64_t n, int32_t light_width, int32_t light_height, size_t* bytes) {
+int gs3_backward_workspace_size_for(int32_t appearance, int64_t n, int32_t light_width, int32_t light_height,
+                                    size_t* bytes) {
     if (!bytes) return fail(GS3_INVALID_ARG, "bytes is NULL");
+    if (appearance != GS3_APPEARANCE_LOBES && appearance != GS3_APPEARANCE_BASIS)
+        return fail(GS3_INVALID_ARG, "bad appearance");
     BwdLayout B;
-    if (!bwd_layout(n, light_width, light_height, &B))
+    if (!bwd_layout(appearance, n, light_width, light_height, &B))
         return fail(GS3_INVALID_ARG, "invalid sizes (n=%lld, light %dx%d)", (long long)n, light_width, light_height);
     *bytes = B.total;
     return GS3_OK;
+}
+
+int gs3_backward_workspace_size(int64_t n, int32_t light_width, int32_t light_height, size_t* bytes) {
+    return gs3_backward_workspace_size_for(GS3_APPEARANCE_LOBES, n, light_width, light_height, bytes);
 }
 
 static int proj_params(const gs3_view* v, const Layout& L, int depth_mode, const gs3_consts* k, ViewParams* vp) {
@@ -663,21 +705,27 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     ViewParams vpc, vpl;
     if ((st = proj_params(cam, Lc, GS3_DEPTH_Z, consts, &vpc)) != GS3_OK) return st;
     if ((st = proj_params(light, Ll, GS3_DEPTH_DIST, consts, &vpl)) != GS3_OK) return st;
-    if ((st = check_mlp(phi, 17, 1, "phi")) != GS3_OK) return st;
-    if ((st = check_mlp(psi, 22, 3, "psi")) != GS3_OK) return st;
+    if ((st = check_mlps(scene, phi, psi)) != GS3_OK) return st;
     if (!fwd || !fwd->shading || !fwd->shadow || !fwd->residual)
         return fail(GS3_INVALID_ARG, "forward images (shading, shadow, residual) missing");
     if (scene->n > 0 && (!T || !num_den)) return fail(GS3_INVALID_ARG, "T / num_den is NULL");
     if (!dL_dfinal) return fail(GS3_INVALID_ARG, "dL_dfinal is NULL");
+    const bool basis = scene->appearance == GS3_APPEARANCE_BASIS;
     if (!grads || !grads->mean || !grads->log_scale || !grads->rot || !grads->opacity_logit || !grads->shade_rot ||
-        !grads->albedo || !grads->lobe_axis || !grads->lobe_log_sharp || !grads->lobe_amp || !grads->feat)
+        !grads->albedo)
         return fail(GS3_INVALID_ARG, "a scene gradient pointer is NULL");
+    if (!basis && (!grads->lobe_axis || !grads->lobe_log_sharp || !grads->lobe_amp || !grads->feat))
+        return fail(GS3_INVALID_ARG, "a lobe or feature gradient pointer is NULL");
+    if (basis && (!grads->spec_albedo || !grads->latent ||
+                  (scene->k > 0 && (!grads->basis_weight || !grads->basis_rot || !grads->basis_log_sigma))))
+        return fail(GS3_INVALID_ARG, "a basis-appearance gradient pointer is NULL");
     for (int i = 0; i < 4; ++i) {
         if (phi && (!grads->phi_w[i] || !grads->phi_b[i])) return fail(GS3_INVALID_ARG, "phi gradient pointer is NULL");
         if (psi && (!grads->psi_w[i] || !grads->psi_b[i])) return fail(GS3_INVALID_ARG, "psi gradient pointer is NULL");
     }
     BwdLayout B;
-    if (!bwd_layout(scene->n, light->width, light->height, &B)) return fail(GS3_INVALID_ARG, "invalid sizes");
+    if (!bwd_layout(scene->appearance, scene->n, light->width, light->height, &B))
+        return fail(GS3_INVALID_ARG, "invalid sizes");
     if (!ws) return fail(GS3_INVALID_ARG, "ws is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GS3_INVALID_ARG, "ws not 256-byte aligned");
     if (ws_bytes < B.total)
@@ -706,6 +754,11 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     g.lobe_log_sharp = grads->lobe_log_sharp;
     g.lobe_amp = grads->lobe_amp;
     g.feat = grads->feat;
+    g.spec_albedo = grads->spec_albedo;
+    g.basis_weight = grads->basis_weight;
+    g.latent = grads->latent;
+    g.basis_rot = grads->basis_rot;
+    g.basis_log_sigma = grads->basis_log_sigma;
     ShadeParams sp;
     shade_light(light, &sp);
     for (int i = 0; i < 3; ++i) sp.eye[i] = (float)cam->eye[i];
@@ -713,7 +766,10 @@ int gs3_render_backward(const gs3_scene* scene, const gs3_view* cam, const gs3_v
     sp.use_psi = psi != nullptr;
     const SceneDev sd = scene_dev(scene);
     GS3_CHECK_HIP(launch_render_bwd(*consts, Lc, cam_vb->ws, *fwd, dL_dfinal, gcam, gcol, s));
-    GS3_CHECK_HIP(launch_shade_bwd(sd, sp, T, phi, psi, gcol, dT, g, rows, partial, grads, s));
+    if (basis)
+        GS3_CHECK_HIP(launch_basis_shade_bwd(sd, sp, T, phi, psi, gcol, dT, g, rows, partial, grads, s));
+    else
+        GS3_CHECK_HIP(launch_shade_bwd(sd, sp, T, phi, psi, gcol, dT, g, rows, partial, grads, s));
     GS3_CHECK_HIP(launch_shadow_bwd(*consts, Ll, light_vb->ws, T, num_den, dT, dnum, gray, glight, s));
     GS3_CHECK_HIP(launch_project_bwd(sd, vpc, vpl, *consts, gcam, glight, g, s));
     return GS3_OK;

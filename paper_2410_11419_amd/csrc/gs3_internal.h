@@ -91,6 +91,12 @@ struct SceneDev {
     const float* feat;
     int32_t n;
     int32_t k;
+    int32_t appearance;          // GS3_APPEARANCE_LOBES / GS3_APPEARANCE_BASIS
+    const float* spec_albedo;    // basis appearance (Sec. 4.1 shared basis)
+    const float* basis_weight;
+    const float* latent;
+    const float* basis_rot;
+    const float* basis_log_sigma;
 };
 
 // Launchers (return hipError_t of the launch).
@@ -135,6 +141,11 @@ struct GradDev {
     float* lobe_log_sharp;
     float* lobe_amp;
     float* feat;
+    float* spec_albedo;
+    float* basis_weight;
+    float* latent;
+    float* basis_rot;
+    float* basis_log_sigma;
 };
 int mlp_scratch_rows();
 int wgrad_total_params(bool phi, bool psi);
@@ -147,6 +158,31 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
 hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
                             const gs3_mlp* psi, const float* gcol, float* dT, const GradDev& g, float* rows,
                             float* partial, const gs3_grads* gr, hipStream_t st);
+// Shared-basis appearance (Sec. 4.1) with the paper's MLP form (Sec. 4.2,
+// 4.3): forward shading + Psi, forward Phi, and the adjoint of both.
+constexpr int kLatent = 6;
+constexpr int kPhiBasisIn = 61, kPsiBasisIn = 60;     // [T, PE(w_i), PE(mu), l] / [PE(w_o), PE(mu), l]
+constexpr int kPhiBasisHidden = 32, kPsiBasisHidden = 128;
+constexpr float kLeakySlope = 0.01f;
+hipError_t launch_basis_shade(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                              const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, int parts,
+                              hipStream_t st);
+int basis_scratch_rows();
+int basis_wgrad_total_params();
+int basis_partial_floats(int k);
+hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                                  const gs3_mlp* psi, const float* gcol, float* dT, const GradDev& g, float* rows,
+                                  float* partial, const gs3_grads* gr, hipStream_t st);
+// Weight gradients dW += sum_g dz[:, g] in[:, g]^T (and db += sum_g dz)
+// over problems of at most 64 x 64 (scratch rows [row][n]); dW has row
+// stride ldw, db may be NULL.
+struct WgSpec {
+    int dz_row, in_row, O, J, ldw;
+    float* dW;
+    float* db;
+};
+hipError_t launch_wgrad(const WgSpec* specs, int count, const float* rows, int n, float* partial, hipStream_t st);
+int wgrad_partial_floats(const WgSpec* specs, int count);
 hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const ViewParams& light,
                               const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
                               hipStream_t st);

@@ -41,26 +41,6 @@ struct ShadeBwdArgs {
     float* rows;         // [kMlpRows][n] MLP scratch
 };
 
-// Adjoint of the quaternion -> rotation map (q normalised inside): dR -> dq.
-__device__ inline void quat_grad(float qw, float qx, float qy, float qz, float qn, const float dR[9], float dq[4]) {
-    // (qw..qz) is the normalised quaternion, qn the raw norm
-    const float g00 = dR[0], g01 = dR[1], g02 = dR[2], g10 = dR[3], g11 = dR[4], g12 = dR[5], g20 = dR[6],
-                g21 = dR[7], g22 = dR[8];
-    const float dw = 2.f * (-qz * g01 + qy * g02 + qz * g10 - qx * g12 - qy * g20 + qx * g21);
-    const float dx = 2.f * (qy * g01 + qz * g02 + qy * g10 - 2.f * qx * g11 - qw * g12 + qz * g20 + qw * g21 -
-                            2.f * qx * g22);
-    const float dy = 2.f * (-2.f * qy * g00 + qx * g01 + qw * g02 + qx * g10 + qz * g12 - qw * g20 + qz * g21 -
-                            2.f * qy * g22);
-    const float dz = 2.f * (-2.f * qz * g00 - qw * g01 + qx * g02 + qw * g10 - 2.f * qz * g11 + qy * g12 +
-                            qx * g20 + qy * g21);
-    const float dot = dw * qw + dx * qx + dy * qy + dz * qz;
-    const float inv = 1.f / qn;
-    dq[0] = (dw - dot * qw) * inv;
-    dq[1] = (dx - dot * qx) * inv;
-    dq[2] = (dy - dot * qy) * inv;
-    dq[3] = (dz - dot * qz) * inv;
-}
-
 // Store a D-layout 64-vector of one Gaussian into scratch rows row0 ..
 // row0 + 63: lane (g, q) writes rows row0 + 16 m + 4 q + i. The per-lane
 // base is formed once; the row offsets (16 m + i) n are wave-uniform.
@@ -352,11 +332,13 @@ constexpr int kWgChunk = kWgChunkHost;
 
 struct WgProblem {
     int dz_row, in_row, O, J, off;   // scratch rows, output/input widths, offset in the flat vector
-    float* dW;                       // [O][J] +=
-    float* db;                       // [O] +=
+    int ldw;                         // row stride of dW
+    float* dW;                       // [O][ldw] +=
+    float* db;                       // [O] += (NULL: bias not accumulated by this problem)
 };
+constexpr int kWgMaxProblems = 16;
 struct WgArgs {
-    WgProblem p[8];
+    WgProblem p[kWgMaxProblems];
     int count, total;                // problems, flat parameter count
     const float* rows;
     int n;
@@ -464,11 +446,11 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(WgArgs a, int chunks) {
         const WgProblem& P = a.p[i];
         const int rel = p - P.off;
         if (rel >= 0 && rel < P.O * P.J) {
-            P.dW[rel] += s;
+            P.dW[(size_t)(rel / P.J) * P.ldw + rel % P.J] += s;
             return;
         }
         if (rel >= P.O * P.J && rel < P.O * P.J + P.O) {
-            P.db[rel - P.O * P.J] += s;
+            if (P.db) P.db[rel - P.O * P.J] += s;
             return;
         }
     }
@@ -661,13 +643,10 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!phi && !psi)) return e;
     // weight gradients
-    WgArgs w;
-    w.count = 0;
-    int off = 0;
+    WgSpec spec[8];
+    int count = 0;
     auto add = [&](int dz_row, int in_row, int O, int J, float* dW, float* db) {
-        WgProblem& P = w.p[w.count++];
-        P.dz_row = dz_row; P.in_row = in_row; P.O = O; P.J = J; P.off = off; P.dW = dW; P.db = db;
-        off += O * J + O;
+        spec[count++] = WgSpec{dz_row, in_row, O, J, J, dW, db};
     };
     if (phi) {
         add(kPhiRows.dz1, kPhiRows.x, 64, kPhiIn, gr->phi_w[0], gr->phi_b[0]);
@@ -681,11 +660,34 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
         add(kPsiRows.dz3, kPsiRows.h2, 64, 64, gr->psi_w[2], gr->psi_b[2]);
         add(kPsiRows.dz4, kPsiRows.h3, 3, 64, gr->psi_w[3], gr->psi_b[3]);
     }
+    return launch_wgrad(spec, count, rows, sc.n, partial, st);
+}
+
+int wgrad_partial_floats(const WgSpec* specs, int count) {
+    int t = 0;
+    for (int i = 0; i < count; ++i) t += specs[i].O * specs[i].J + specs[i].O;
+    return t;
+}
+
+hipError_t launch_wgrad(const WgSpec* specs, int count, const float* rows, int n, float* partial, hipStream_t st) {
+    if (count <= 0 || n <= 0) return hipSuccess;
+    if (count > kWgMaxProblems) return hipErrorInvalidValue;
+    WgArgs w;
+    w.count = count;
+    int off = 0;
+    for (int i = 0; i < count; ++i) {
+        const WgSpec& S = specs[i];
+        if (S.O > 64 || S.J > 64 || S.O <= 0 || S.J <= 0) return hipErrorInvalidValue;
+        WgProblem& P = w.p[i];
+        P.dz_row = S.dz_row; P.in_row = S.in_row; P.O = S.O; P.J = S.J; P.off = off;
+        P.ldw = S.ldw; P.dW = S.dW; P.db = S.db;
+        off += S.O * S.J + S.O;
+    }
     w.total = off;
     w.rows = rows;
-    w.n = sc.n;
+    w.n = n;
     w.partial = partial;
-    const int chunks = (sc.n + kWgChunk - 1) / kWgChunk;
+    const int chunks = (n + kWgChunk - 1) / kWgChunk;
     hipLaunchKernelGGL(k_wgrad, dim3(chunks, w.count), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 63) / 64), dim3(256), 0, st, w, chunks);
     return hipGetLastError();

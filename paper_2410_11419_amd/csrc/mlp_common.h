@@ -68,6 +68,26 @@ struct MlpArgs {
 
 
 
+// Adjoint of the quaternion -> rotation map (q normalised inside): dR -> dq.
+__device__ inline void quat_grad(float qw, float qx, float qy, float qz, float qn, const float dR[9], float dq[4]) {
+    // (qw..qz) is the normalised quaternion, qn the raw norm
+    const float g00 = dR[0], g01 = dR[1], g02 = dR[2], g10 = dR[3], g11 = dR[4], g12 = dR[5], g20 = dR[6],
+                g21 = dR[7], g22 = dR[8];
+    const float dw = 2.f * (-qz * g01 + qy * g02 + qz * g10 - qx * g12 - qy * g20 + qx * g21);
+    const float dx = 2.f * (qy * g01 + qz * g02 + qy * g10 - 2.f * qx * g11 - qw * g12 + qz * g20 + qw * g21 -
+                            2.f * qx * g22);
+    const float dy = 2.f * (-2.f * qy * g00 + qx * g01 + qw * g02 + qx * g10 + qz * g12 - qw * g20 + qz * g21 -
+                            2.f * qy * g22);
+    const float dz = 2.f * (-2.f * qz * g00 - qw * g01 + qx * g02 + qw * g10 - 2.f * qz * g11 + qy * g12 +
+                            qx * g20 + qy * g21);
+    const float dot = dw * qw + dx * qx + dy * qy + dz * qz;
+    const float inv = 1.f / qn;
+    dq[0] = (dw - dot * qw) * inv;
+    dq[1] = (dx - dot * qx) * inv;
+    dq[2] = (dy - dot * qy) * inv;
+    dq[3] = (dz - dot * qz) * inv;
+}
+
 // x = hi + lo / 2048 with both parts half precision.
 __device__ inline void split_half(float x, _Float16* hi, _Float16* lo) {
     const _Float16 h = (_Float16)x;

@@ -40,8 +40,10 @@ EXPORTED = [
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
     "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
     "gs3_l1_loss_noalloc", "gs3_dssim_loss_workspace_size", "gs3_dssim_loss", "gs3_adam_step",
-    "gs3_image_accumulate",
+    "gs3_image_accumulate", "gs3_backward_workspace_size_for",
 ]
+GS3_APPEARANCE_LOBES, GS3_APPEARANCE_BASIS = 0, 1
+BASIS_NAMES = ("spec_albedo", "basis_weight", "latent", "basis_rot", "basis_log_sigma")
 GS3_VIEW_PENDING, GS3_VIEW_OK, GS3_VIEW_OVERFLOW = 0, 1, 2
 
 
@@ -64,7 +66,9 @@ class gs3_scene(C.Structure):
     _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("rot", C.c_void_p),
                 ("opacity_logit", C.c_void_p), ("shade_rot", C.c_void_p), ("albedo", C.c_void_p),
                 ("lobe_axis", C.c_void_p), ("lobe_log_sharp", C.c_void_p), ("lobe_amp", C.c_void_p),
-                ("feat", C.c_void_p), ("n", C.c_int64), ("k", C.c_int32)]
+                ("feat", C.c_void_p), ("n", C.c_int64), ("k", C.c_int32), ("appearance", C.c_int32),
+                ("spec_albedo", C.c_void_p), ("basis_weight", C.c_void_p), ("latent", C.c_void_p),
+                ("basis_rot", C.c_void_p), ("basis_log_sigma", C.c_void_p)]
 
 
 class gs3_mlp(C.Structure):
@@ -86,7 +90,7 @@ class gs3_grads(C.Structure):
     _fields_ = [(nm, C.c_void_p) for nm in ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo",
                                              "lobe_axis", "lobe_log_sharp", "lobe_amp", "feat")] + \
                [("phi_w", C.c_void_p * 4), ("phi_b", C.c_void_p * 4), ("psi_w", C.c_void_p * 4),
-                ("psi_b", C.c_void_p * 4)]
+                ("psi_b", C.c_void_p * 4)] + [(nm, C.c_void_p) for nm in BASIS_NAMES]
 
 
 def _load():
@@ -120,6 +124,7 @@ def _load():
         "gs3_render_shaded": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                         P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
         "gs3_backward_workspace_size": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, P(C.c_size_t)]),
+        "gs3_backward_workspace_size_for": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, P(C.c_size_t)]),
         "gs3_render_backward": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                           C.c_void_p, P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_viewbuf),
                                           P(gs3_images), C.c_void_p, P(gs3_grads), C.c_void_p, C.c_size_t,
@@ -214,26 +219,48 @@ def device_ok() -> bool:
 
 @dataclasses.dataclass
 class DeviceScene:
-    """A scene's raw parameters as contiguous float32 device tensors."""
+    """A scene's raw parameters as contiguous float32 device tensors. A
+    scene with the paper's shared-basis appearance (``scene.basis``) holds
+    rho_s, the basis weights, the latent and the shared basis frames and
+    sigmas instead of the per-Gaussian lobes and features."""
     t: Dict[str, torch.Tensor]
     phi: Optional[list]
     psi: Optional[list]
     n: int
     k: int
+    appearance: int = GS3_APPEARANCE_LOBES
 
     @classmethod
     def from_host(cls, scene, device="cuda") -> "DeviceScene":
-        names = ["mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo", "lobe_axis",
-                 "lobe_log_sharp", "lobe_amp", "feat"]
+        names = ["mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo"]
+        basis = getattr(scene, "basis", None)
+        if basis is None:
+            names += ["lobe_axis", "lobe_log_sharp", "lobe_amp", "feat"]
         t = {nm: torch.as_tensor(np.ascontiguousarray(getattr(scene, nm), np.float32)).to(device)
              for nm in names}
+        if basis is not None:
+            src = {"spec_albedo": basis.spec_albedo, "basis_weight": basis.weight, "latent": basis.latent,
+                   "basis_rot": basis.basis_rot, "basis_log_sigma": basis.basis_log_sigma}
+            for nm in BASIS_NAMES:
+                t[nm] = torch.as_tensor(np.ascontiguousarray(src[nm], np.float32)).to(device)
 
         def mlp(m):
             if m is None:
                 return None
             return [(torch.as_tensor(np.ascontiguousarray(w, np.float32)).to(device),
                      torch.as_tensor(np.ascontiguousarray(b, np.float32)).to(device)) for w, b in m.layers]
-        return cls(t, mlp(scene.phi), mlp(scene.psi), int(scene.mean.shape[1]), int(scene.lobe_axis.shape[0]))
+        k = int(basis.weight.shape[0]) if basis is not None else int(scene.lobe_axis.shape[0])
+        return cls(t, mlp(scene.phi), mlp(scene.psi), int(scene.mean.shape[1]), k,
+                   GS3_APPEARANCE_BASIS if basis is not None else GS3_APPEARANCE_LOBES)
+
+    @property
+    def phi_io(self):
+        """(n_in, n_out) of Phi for this scene's appearance model."""
+        return (61, 1) if self.appearance == GS3_APPEARANCE_BASIS else (17, 1)
+
+    @property
+    def psi_io(self):
+        return (60, 3) if self.appearance == GS3_APPEARANCE_BASIS else (22, 3)
 
     def c_struct(self) -> gs3_scene:
         s = gs3_scene()
@@ -241,6 +268,7 @@ class DeviceScene:
             setattr(s, nm, _ptr(v))
         s.n = self.n
         s.k = self.k
+        s.appearance = self.appearance
         return s
 
     @staticmethod
@@ -389,8 +417,8 @@ def gs3_render(scene: DeviceScene, cam, light, consts: gs3_consts, T: torch.Tens
     eye, orthographic for a directional light."""
     v = make_view(cam)
     lp = make_view(light)
-    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
-    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    phi = DeviceScene.c_mlp(scene.phi, *scene.phi_io) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, *scene.psi_io) if use_mlps else None
     im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
     _check(_lib.gs3_render(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
                            C.byref(phi) if phi is not None else None,
@@ -401,7 +429,7 @@ def gs3_render(scene: DeviceScene, cam, light, consts: gs3_consts, T: torch.Tens
 def gs3_shade(scene: DeviceScene, cam, light, cam_vb: ViewBuffer, colour: torch.Tensor, use_mlps: bool = True):
     v = make_view(cam)
     lp = make_view(light)
-    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, *scene.psi_io) if use_mlps else None
     _check(_lib.gs3_shade(C.byref(scene.c_struct()), C.byref(v), C.byref(lp),
                           C.byref(psi) if psi is not None else None, C.byref(cam_vb.vb), _ptr(colour), _stream()),
            "gs3_shade")
@@ -411,7 +439,7 @@ def gs3_render_shaded(scene: DeviceScene, cam, light, consts: gs3_consts, T: tor
                       images: Dict[str, torch.Tensor], use_mlps: bool = True):
     v = make_view(cam)
     lp = make_view(light)
-    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
+    phi = DeviceScene.c_mlp(scene.phi, *scene.phi_io) if use_mlps else None
     im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
     _check(_lib.gs3_render_shaded(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
                                   C.byref(phi) if phi is not None else None, C.byref(cam_vb.vb), C.byref(im),
@@ -542,10 +570,11 @@ class DeviceGrads:
         return g
 
 
-def backward_workspace(n: int, light_width: int, light_height: int, device="cuda") -> torch.Tensor:
+def backward_workspace(n: int, light_width: int, light_height: int, device="cuda",
+                       appearance: int = GS3_APPEARANCE_LOBES) -> torch.Tensor:
     size = C.c_size_t()
-    _check(_lib.gs3_backward_workspace_size(n, light_width, light_height, C.byref(size)),
-           "gs3_backward_workspace_size")
+    _check(_lib.gs3_backward_workspace_size_for(appearance, n, light_width, light_height, C.byref(size)),
+           "gs3_backward_workspace_size_for")
     return torch.empty(size.value + 256, dtype=torch.uint8, device=device)
 
 
@@ -560,8 +589,8 @@ def gs3_render_backward(scene: DeviceScene, cam, light, consts: gs3_consts, T: t
                         images: Dict[str, torch.Tensor], dL_dfinal: torch.Tensor, grads: DeviceGrads,
                         ws: torch.Tensor, use_mlps: bool = True):
     cv, lv = make_view(cam), make_view(light)
-    phi = DeviceScene.c_mlp(scene.phi, 17, 1) if use_mlps else None
-    psi = DeviceScene.c_mlp(scene.psi, 22, 3) if use_mlps else None
+    phi = DeviceScene.c_mlp(scene.phi, *scene.phi_io) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, *scene.psi_io) if use_mlps else None
     im = gs3_images(*[_ptr(images[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib", "colour")])
     g = grads.c_struct()
     wsp, wsb = _aligned(ws)
@@ -806,13 +835,14 @@ class Renderer:
                              f"{dL_dfinal.dtype} {tuple(dL_dfinal.shape)}")
         if grads is None:
             grads = DeviceGrads(self.scene, self.use_mlps)
+        app = self.scene.appearance
         if self.bwd_ws is None:
-            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev)
+            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev, app)
         need = C.c_size_t()
-        _check(_lib.gs3_backward_workspace_size(self.scene.n, light.width, light.height, C.byref(need)),
-               "gs3_backward_workspace_size")
+        _check(_lib.gs3_backward_workspace_size_for(app, self.scene.n, light.width, light.height, C.byref(need)),
+               "gs3_backward_workspace_size_for")
         if self.bwd_ws.numel() < need.value + 256:
-            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev)
+            self.bwd_ws = backward_workspace(self.scene.n, light.width, light.height, self.dev, app)
         lvb = self.vbs[("light", light.width, light.height)]
         cvb = self.vbs[("cam", cam.width, cam.height)]
         gs3_render_backward(self.scene, cam, light, self.consts, self.T, self.num_den, lvb, cvb,
@@ -850,7 +880,7 @@ SCENE_FIELDS = ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albed
 def scene_parameters(scene: DeviceScene) -> list:
     """The tensors a RelitRender call differentiates: the scene's raw
     parameters, then Phi's and Psi's (W, b) per layer."""
-    ps = [scene.t[nm] for nm in SCENE_FIELDS]
+    ps = list(scene.t.values())
     for m in (scene.phi, scene.psi):
         if m is not None:
             for w, b in m:
@@ -874,7 +904,7 @@ class RelitRender(torch.autograd.Function):
     def backward(ctx, dfinal):
         r = ctx.renderer
         g = r.backward(ctx.cam, ctx.light, dfinal)
-        outs = [g.t[nm] for nm in SCENE_FIELDS]
+        outs = [g.t[nm] for nm in r.scene.t]
         for gm, sm in ((g.phi, r.scene.phi), (g.psi, r.scene.psi)):
             if sm is None:
                 continue
