@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--env-lights", type=int, default=16,
                     help="directional lights of the environment-light leg (0: skip)")
     ap.add_argument("--env-steps", type=int, default=5, help="timed environment frames")
+    ap.add_argument("--basis-steps", type=int, default=30,
+                    help="timed frames of the shared-basis appearance scene (0: skip)")
+    ap.add_argument("--basis-train-steps", type=int, default=5, help="its timed fwd+bwd steps (0: skip)")
     ap.add_argument("--batch-views", type=int, default=0,
                     help="1: each frame preprocesses its light and camera views in one launch sequence")
     return ap.parse_args()
@@ -91,14 +94,13 @@ def views(n_pairs=4, seed=2):
     return out
 
 
-def frame_bytes(n, k, p_light, p_cam, cam_px):
+def frame_bytes(n, k, p_light, p_cam, cam_px, basis=False):
     """Compulsory HBM bytes of one frame (each item read or written once):
     parameters (geometry twice, appearance once), projected records of both
     views (write + read), pair emission, one read + write of the sorted pairs,
     list reads, per-Gaussian shading outputs, the final image."""
     geom = 4 * (3 + 3 + 4 + 1)
-    appear = 4 * (4 + 3 + k * 7 + 16)
-    params = n * (2 * geom + appear)
+    params = n * (2 * geom + appearance_bytes(k, basis) - 12)
     records = 2 * n * 2 * 36
     pairs = p_light + p_cam
     emit = 12 * pairs
@@ -112,10 +114,13 @@ def frame_bytes(n, k, p_light, p_cam, cam_px):
 GEOM_BYTES = 4 * (3 + 3 + 4 + 1)      # mean, log-scale, rotation, opacity logit
 
 
-def appearance_bytes(k):
+def appearance_bytes(k, basis=False):
     """Per-Gaussian appearance and feature reads of the shading: shading
     rotation, albedo, K lobes (axis, log-sharpness, RGB amplitude), the
-    16 features and the centre."""
+    16 features and the centre; for the shared-basis appearance the shading
+    rotation, rho_d, rho_s, K basis weights, the 6-D latent and the centre."""
+    if basis:
+        return 4 * (4 + 3 + 3 + k + 6 + 3)
     return 4 * (4 + 3 + 7 * k + 16 + 3)
 
 
@@ -127,21 +132,22 @@ def preprocess_bytes(n, pairs):
     return n * (GEOM_BYTES + 36) + pairs * 36
 
 
-def shade_bytes(n, k):
+def shade_bytes(n, k, basis=False):
     """Algorithmic bytes of the per-Gaussian shading + Psi (gs3_shade):
     appearance reads, colour and residual written (c, r and their copies
     for the caller: 32 + 32 B)."""
-    return n * (appearance_bytes(k) + 64)
+    return n * (appearance_bytes(k, basis) + 64)
 
 
-def backward_bytes(n, k, p_light, p_cam, cam_px):
+def backward_bytes(n, k, p_light, p_cam, cam_px, basis=False):
     """Algorithmic bytes of one view's adjoint: parameters read again
     (geometry for both views, appearance), both views' records and lists,
     the saved per-Gaussian state (T, num, den, c, T', r), the camera images
     it reads (dL/dfinal, S, Sh, R: 10 floats per pixel) and one read +
     write of the 90 gradient floats per Gaussian it accumulates into."""
-    params = n * (2 * GEOM_BYTES + appearance_bytes(k))
-    return params + 2 * n * 36 + 4 * (p_light + p_cam) + n * 4 * 10 + cam_px * 40 + 2 * n * 90 * 4
+    params = n * (2 * GEOM_BYTES + appearance_bytes(k, basis))
+    grads = (11 + 7 + k + 6) if basis else 90
+    return params + 2 * n * 36 + 4 * (p_light + p_cam) + n * 4 * 10 + cam_px * 40 + 2 * n * grads * 4
 
 
 def kernel_source_hash():
@@ -266,8 +272,9 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
         lvb = rnds[0].vbs[("light", light.width, light.height)]
         cvb = rnds[0].vbs[("cam", cam.width, cam.height)]
         pl, pc = gs3.gs3_view_pair_count(lvb), gs3.gs3_view_pair_count(cvb)
-        per_view.append(frame_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height) +
-                        backward_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height))
+        basis = ds.appearance == gs3.GS3_APPEARANCE_BASIS
+        per_view.append(frame_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height, basis) +
+                        backward_bytes(ds.n, ds.k, pl, pc, cam.width * cam.height, basis))
     step_bytes = float(np.mean(per_view)) * batch
     step_gbs = step_bytes / (wall / steps) / 1e9
     return {"metric": "fwd+bwd steps/s", "value": round(steps / wall, 3), "unit": "steps/s",
@@ -324,15 +331,26 @@ def serving_bench(ds, requests, loads):
     serve.run_plain(ds, warm)
     srv = serve.Server(ds, mem_cap_bytes=24 << 30)
     srv.run(warm)
+    # batched launches: up to 8 waiting requests per launch sequence, 16 in flight
+    srv_b = serve.Server(ds, mem_cap_bytes=24 << 30, max_inflight=16, batch=8)
+    srv_b.run(warm)
     burst = serve.make_requests(requests, qps=1e6, seed=3)
     plain_sat = serve.summarize(serve.run_plain(ds, burst))
     server_sat = serve.summarize(srv.run(burst))
+    nb0 = srv_b.batches
+    batched_sat = serve.summarize(srv_b.run(burst))
     out = {"requests": requests,
            "workload": "300,000 Gaussians resident; camera and light uniform on the radius-4 sphere; camera "
                        "resolution uniform over 256^2, 512^2, 800^2, 1024^2; light 1024^2 at 40 deg; Poisson arrivals",
            "mem_cap_GB": 24, "buffer_sets": None,
+           "server": "continuous batching, one stream per in-flight request (up to 8)",
+           "server_batched": "continuous batching with batched launches: the requests waiting when there is room "
+                             "(up to 8, mixed resolutions) run as one launch sequence per stage, up to 16 requests "
+                             "in flight",
            "saturation_frames_per_s": {"plain": round(plain_sat["frames_per_s"], 1),
-                                       "server": round(server_sat["frames_per_s"], 1)},
+                                       "server": round(server_sat["frames_per_s"], 1),
+                                       "server_batched": round(batched_sat["frames_per_s"], 1)},
+           "saturation_batches": srv_b.batches - nb0,
            "loads": []}
     for f in loads:
         qps = f * plain_sat["frames_per_s"]
@@ -340,11 +358,16 @@ def serving_bench(ds, requests, loads):
         rq = serve.make_requests(requests, qps=qps, seed=3)
         a = serve.summarize(serve.run_plain(ds, rq))
         b = serve.summarize(srv.run(rq))
+        nb0 = srv_b.batches
+        c = serve.summarize(srv_b.run(rq))
         out["loads"].append({"load": f, "qps": round(qps, 1),
                              "plain": {k: round(v, 3) for k, v in a.items() if k != "requests"},
-                             "server": {k: round(v, 3) for k, v in b.items() if k != "requests"}})
+                             "server": {k: round(v, 3) for k, v in b.items() if k != "requests"},
+                             "server_batched": {**{k: round(v, 3) for k, v in c.items() if k != "requests"},
+                                                "batches": srv_b.batches - nb0}})
     out["buffer_sets"] = len(srv.sets)
-    del srv
+    out["buffer_sets_batched"] = len(srv_b.sets)
+    del srv, srv_b
     # light sharing: requests under a set of 8 point lights (a light stage's
     # OLAT set) share one shadow pass per light
     shared = serve.make_requests(requests, qps=1e6, seed=3, n_lights=8)
@@ -391,6 +414,79 @@ def env_bench(ds, n_lights, steps):
     return {"frames_per_s": round(1.0 / dt, 3), "ms_per_frame": round(1e3 * dt, 3),
             "ms_per_light": round(1e3 * dt / n_lights, 4), "lights": n_lights, "steps": steps,
             "config": "300,000 Gaussians, camera 800x800, directional lights 1024x1024 orthographic"}
+
+
+def basis_bench(steps, train_steps, inflight=6):
+    """The paper's own appearance and MLP form (shared anisotropic basis
+    angular Gaussians; Phi {32}^3 and Psi {128}^3 with encoding, latent and
+    leaky ReLU) on the 300K shell scene, camera 800x800, light 1024x1024:
+    frames/s with `inflight` frames in flight and one at a time, serial
+    times of its two shading stages, and the fwd+bwd step at batch 4."""
+    import numpy as np
+    import torch
+    from paper_2410_11419_amd import gs3, synth
+    sc, _, _ = synth.scene_basis_full()
+    ds = gs3.DeviceScene.from_host(sc)
+    pairs = views()
+    fp = gs3.FramePipeline(ds, depth=inflight)
+    for cam, light in pairs:
+        fp.warm(cam, light)
+    for i in range(inflight):
+        fp.render(*pairs[i % len(pairs)], overlap=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fp.render(*pairs[i % len(pairs)], overlap=False)
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    if fp.overflowed():
+        raise RuntimeError("a binning exceeded its pair capacity in the basis-appearance frames")
+    rnd = fp.renderers[0]
+    single = gs3.FramePipeline(ds, depth=1)
+    single.renderers[0] = rnd
+    for i in range(4):
+        single.render(*pairs[i % len(pairs)])
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    n_single = max(8, steps // 2)
+    for i in range(n_single):
+        single.render(*pairs[i % len(pairs)])
+    torch.cuda.synchronize()
+    single_fps = n_single / (time.perf_counter() - ts)
+    stream = torch.cuda.current_stream()
+    k = rnd.consts
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(8)]
+    for i in range(8):
+        cam, light = pairs[i % len(pairs)]
+        rnd.render(cam, light, check=False, overlap=False)
+        cvb = rnd.vbs[("cam", cam.width, cam.height)]
+        im = rnd._images(cam.width, cam.height)
+        evs[i][0].record(stream)
+        gs3.gs3_shade(ds, cam, light, cvb, im["colour"], True)
+        evs[i][1].record(stream)
+        gs3.gs3_render_shaded(ds, cam, light, k, rnd.T, cvb, im, True)
+        evs[i][2].record(stream)
+    torch.cuda.synchronize()
+    shade_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    phi_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    del fp, single, rnd
+    psi_flop = 2 * (60 * 128 + 2 * 128 * 128 + 128 * 3)
+    out = {"frames_per_s": round(fps, 3), "frames_in_flight": inflight, "single_frame_fps": round(single_fps, 3),
+           "stages_ms_serial": {"shade_psi": round(shade_ms, 4), "phi_camera_splat": round(phi_ms, 4)},
+           "shade_psi_mlp_tflops": round(sc.n * psi_flop / (shade_ms / 1e3) / 1e12, 2),
+           "shade_psi_hbm": {"algorithmic_bytes": shade_bytes(sc.n, sc.k, True),
+                             "achieved_GBs": round(shade_bytes(sc.n, sc.k, True) / (shade_ms / 1e3) / 1e9, 1)},
+           "steps": steps,
+           "config": "300,000 Gaussians, 8 shared anisotropic basis angular Gaussians, Phi 61-32-32-32-1 and "
+                     "Psi 60-128-128-128-3 (leaky ReLU, 4-band encoding, 6-D latent), camera 800x800, "
+                     "light 1024x1024, 40 deg"}
+    if train_steps > 0:
+        out["train_step"] = train_step_bench(
+            ds, sc, train_steps, 1,
+            workload="300,000 Gaussians with the shared-basis appearance, batch of 4 (camera 800x800, light "
+                     "1024x1024) pairs, L1 loss against targets from the scene with means + N(0,0.01) and "
+                     "albedos + N(0,0.05)")
+    return out
 
 
 def cpu_model() -> str:
@@ -715,6 +811,10 @@ def main():
         log(f"environment light ({args.env_lights} directional lights)")
         with torch.cuda.stream(side):
             out["environment_light"] = env_bench(ds, args.env_lights, args.env_steps)
+    if args.basis_steps > 0:
+        log("shared-basis appearance (the paper's MLP form)")
+        with torch.cuda.stream(side):
+            out["paper_appearance"] = basis_bench(args.basis_steps, args.basis_train_steps)
     if args.serving_requests > 0:
         log("serving")
         del rnd, fp, single

@@ -413,6 +413,26 @@ int gs3_render(const gs3_scene* scene, const gs3_view* cam,
                const gs3_viewbuf* cam_vb, const gs3_images* out,
                gs3_stream_t stream);
 
+/* Steps a3 and a4-a6 + a9 for n_views >= 1 views in one launch sequence
+ * (Sec. 4.2 shadow splatting; Sec. 4.1-4.3 and Fig. 2 shading, MLPs and
+ * camera splat): the same results as gs3_shadow_splat / gs3_render on each
+ * view alone, with the kernels of all views sharing each launch (views of
+ * different sizes included), so that the requests of a serving batch pay
+ * one launch sequence. Arrays are host arrays of n_views entries:
+ *   gs3_shadow_splat_views  light_vbs[v] (preprocessed with GS3_DEPTH_DIST,
+ *       every .n equal), num_den[v] / T[v] device outputs of view v.
+ *   gs3_render_views        cams[v] / lights[v] views, T[v] the shadow
+ *       values of lights[v], cam_vbs[v] (preprocessed with GS3_DEPTH_Z),
+ *       outs[v] the images; one scene and one pair of MLPs for all views.
+ * Workspaces must not overlap. Every argument is checked before anything is
+ * enqueued; errors as for the one-view calls (GS3_PAIR_CAPACITY_EXCEEDED
+ * when a status block reports an overflowed binning of any view). */
+int gs3_shadow_splat_views(const gs3_consts* consts, const gs3_viewbuf* light_vbs, int32_t n_views,
+                           float* const* num_den, float* const* T, gs3_stream_t stream);
+int gs3_render_views(const gs3_scene* scene, const gs3_view* cams, const gs3_view* lights, int32_t n_views,
+                     const gs3_consts* consts, const float* const* T, const gs3_mlp* phi, const gs3_mlp* psi,
+                     const gs3_viewbuf* cam_vbs, const gs3_images* outs, gs3_stream_t stream);
+
 /* The two halves of gs3_render, callable apart so that the part that does
  * not depend on the shadow values can run before (or alongside) the shadow
  * splat; gs3_render is exactly gs3_shade then gs3_render_shaded.

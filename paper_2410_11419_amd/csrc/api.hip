@@ -629,6 +629,87 @@ int gs3_render_shaded(const gs3_scene* scene, const gs3_view* cam, const gs3_vie
     return GS3_OK;
 }
 
+// Views of one batched call: each workspace valid, with lists that are not
+// from an overflowed binning, and no two sharing memory.
+static int check_batch_vbs(const gs3_viewbuf* vbs, int32_t n_views, std::vector<Layout>* L) {
+    int st;
+    L->resize(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const gs3_viewbuf* vb = &vbs[v];
+        if ((st = check_vb(vb, &(*L)[v])) != GS3_OK) return st;
+        if ((st = check_lists(vb)) != GS3_OK) return st;
+        const char* a0 = static_cast<const char*>(vb->ws);
+        for (int u = 0; u < v; ++u) {
+            const char* b0 = static_cast<const char*>(vbs[u].ws);
+            if (a0 < b0 + (*L)[u].total && b0 < a0 + (*L)[v].total)
+                return fail(GS3_INVALID_ARG, "viewbufs[%d] and viewbufs[%d] share workspace memory", u, v);
+        }
+    }
+    return GS3_OK;
+}
+
+int gs3_shadow_splat_views(const gs3_consts* consts, const gs3_viewbuf* light_vbs, int32_t n_views,
+                           float* const* num_den, float* const* T, gs3_stream_t stream) {
+    if (n_views < 1) return fail(GS3_INVALID_ARG, "n_views must be at least 1");
+    if (!light_vbs || !num_den || !T) return fail(GS3_INVALID_ARG, "light_vbs, num_den or T is NULL");
+    int st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    std::vector<Layout> L;
+    if ((st = check_batch_vbs(light_vbs, n_views, &L)) != GS3_OK) return st;
+    std::vector<const Layout*> Lp(n_views);
+    std::vector<void*> ws(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        if (L[v].n != L[0].n) return fail(GS3_INVALID_ARG, "light_vbs[%d].n differs from light_vbs[0].n", v);
+        if (L[v].n > 0 && (!num_den[v] || !T[v])) return fail(GS3_INVALID_ARG, "num_den[%d] / T[%d] is NULL", v, v);
+        Lp[v] = &L[v];
+        ws[v] = light_vbs[v].ws;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    GS3_CHECK_HIP(launch_shadow_den_batch(*consts, Lp.data(), ws.data(), num_den, n_views, s));
+    GS3_CHECK_HIP(launch_shadow_num_batch(*consts, Lp.data(), ws.data(), num_den, n_views, s));
+    GS3_CHECK_HIP(launch_shadow_resolve_batch(Lp.data(), ws.data(), num_den, T, n_views, s));
+    return GS3_OK;
+}
+
+int gs3_render_views(const gs3_scene* scene, const gs3_view* cams, const gs3_view* lights, int32_t n_views,
+                     const gs3_consts* consts, const float* const* T, const gs3_mlp* phi, const gs3_mlp* psi,
+                     const gs3_viewbuf* cam_vbs, const gs3_images* outs, gs3_stream_t stream) {
+    if (n_views < 1) return fail(GS3_INVALID_ARG, "n_views must be at least 1");
+    if (!cams || !lights || !T || !cam_vbs || !outs) return fail(GS3_INVALID_ARG, "an array argument is NULL");
+    int st;
+    if ((st = check_consts(consts)) != GS3_OK) return st;
+    if ((st = check_scene(scene, true)) != GS3_OK) return st;
+    if ((st = check_mlps(scene, phi, psi)) != GS3_OK) return st;
+    std::vector<Layout> L;
+    if ((st = check_batch_vbs(cam_vbs, n_views, &L)) != GS3_OK) return st;
+    std::vector<const Layout*> Lp(n_views);
+    std::vector<void*> ws(n_views);
+    std::vector<ShadeParams> sp(n_views);
+    std::vector<float*> colour(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        Layout Lv;
+        if ((st = render_args(scene, &cams[v], &lights[v], consts, &cam_vbs[v], &Lv)) != GS3_OK) return st;
+        const gs3_images* o = &outs[v];
+        if (!o->final_rgb || !o->shading || !o->shadow || !o->residual || !o->t_final || !o->n_contrib || !o->colour)
+            return fail(GS3_INVALID_ARG, "an output pointer of outs[%d] is NULL", v);
+        if (L[v].n > 0 && !T[v]) return fail(GS3_INVALID_ARG, "T[%d] is NULL", v);
+        Lp[v] = &L[v];
+        ws[v] = cam_vbs[v].ws;
+        sp[v] = shade_params(&cams[v], &lights[v], phi, psi);
+        colour[v] = o->colour;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    const SceneDev sd = scene_dev(scene);
+    if (scene->appearance == GS3_APPEARANCE_BASIS)
+        GS3_CHECK_HIP(launch_basis_shade_batch(sd, sp.data(), T, phi, psi, Lp.data(), ws.data(), colour.data(), 3,
+                                               n_views, s));
+    else
+        GS3_CHECK_HIP(launch_shade_mlp_batch(sd, sp.data(), T, phi, psi, Lp.data(), ws.data(), colour.data(), 3,
+                                             n_views, s));
+    GS3_CHECK_HIP(launch_render_batch(*consts, Lp.data(), ws.data(), outs, n_views, s));
+    return GS3_OK;
+}
+
 // Backward workspace: per-Gaussian splat gradients of both views, colour
 // gradients, dL/dT, dL/dnum, per-light-pixel sums, the MLP scratch rows and
 // the weight-gradient partial sums.

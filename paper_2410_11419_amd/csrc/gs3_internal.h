@@ -123,12 +123,40 @@ struct ShadeParams {
     int32_t use_phi, use_psi;
     int32_t light_dir;  // 1: directional light (w_i = light for every Gaussian)
 };
+// Per-view inputs and outputs of the per-Gaussian shading kernels (one
+// entry per view of a batched launch; blockIdx.y selects it).
+struct ShadeView {
+    float light[3];     // point light position, or (light_dir) unit direction toward the light
+    float eye[3];
+    int32_t light_dir;
+    const float* T;     // shadow values (Phi's input)
+    float4* col0;       // splat colours in the camera view's workspace
+    float4* col1;
+    float* colour;      // [8][n] caller copy
+};
 // parts: 1 = shading c and Psi's r, 2 = Phi's T', 3 = both
 hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T,
                             const gs3_mlp* phi, const gs3_mlp* psi, const Layout& L,
                             void* ws, float* colour_out, int parts, hipStream_t st);
+// The same for nv views of one scene (any nv; chunks of kMaxBatch views per
+// launch): view v has shading parameters sps[v], shadow values T[v] and the
+// camera workspace wss[v] with layout Ls[v].
+hipError_t launch_shade_mlp_batch(const SceneDev& sc, const ShadeParams* sps, const float* const* T,
+                                  const gs3_mlp* phi, const gs3_mlp* psi, const Layout* const* Ls,
+                                  void* const* wss, float* const* colour, int parts, int nv, hipStream_t st);
+hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, const float* const* T,
+                                    const gs3_mlp* phi, const gs3_mlp* psi, const Layout* const* Ls,
+                                    void* const* wss, float* const* colour, int parts, int nv, hipStream_t st);
 hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws,
                          const gs3_images& out, hipStream_t st);
+hipError_t launch_render_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                               const gs3_images* outs, int nv, hipStream_t st);
+hipError_t launch_shadow_den_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                                   float* const* num_den, int nv, hipStream_t st);
+hipError_t launch_shadow_num_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                                   float* const* num_den, int nv, hipStream_t st);
+hipError_t launch_shadow_resolve_batch(const Layout* const* Ls, void* const* wss, float* const* num_den,
+                                       float* const* T, int nv, hipStream_t st);
 // Device pointers of the scene gradients (+=), mirror of SceneDev.
 struct GradDev {
     float* mean;

@@ -89,11 +89,17 @@ __device__ inline void pack_split(float* sm, int M, int K, ElemFn elem) {
     }
 }
 
-// out = A x for the 16 Gaussians of the wave: A packed by pack_split (MT
-// output tiles, KB k-blocks), x and out in D layout. The Gaussian's column
-// is scaled by a power of two for the split and scaled back.
-template <int MT, int KB>
-__device__ inline void split_gemm(const float* sm, int lane, const floatx4* x, floatx4* out) {
+// The B operand of a split product for the 16 Gaussians of the wave (x in
+// D layout, KB k-blocks): each Gaussian's column scaled by a power of two
+// that brings its largest entry to [128, 256) and split into halves;
+// `down` undoes the scaling.
+template <int KB>
+struct SplitB {
+    halfx4 h[KB], l[KB];
+    float down;
+};
+template <int KB>
+__device__ inline void split_cols(const floatx4* x, SplitB<KB>& b) {
     float m = 0.f;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
@@ -101,24 +107,45 @@ __device__ inline void split_gemm(const float* sm, int lane, const floatx4* x, f
         for (int i = 0; i < 4; ++i) m = fmaxf(m, fabsf(x[kb][i]));
     m = fmaxf(m, __shfl_xor(m, 16, 64));
     m = fmaxf(m, __shfl_xor(m, 32, 64));
-    // scale 2^(8 - e) with m = f 2^e, f in [0.5, 1): largest entry in [128, 256)
+    // m = f 2^e with f in [0.5, 1): the scale 2^(8 - e)
     const int e = m > 0.f ? max(ilogbf(m) + 1, -100) : 0;
-    const float up = ldexpf(1.f, 8 - e), down = ldexpf(1.f, e - 8);
-    floatx4 cor[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) out[mt] = cor[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float up = ldexpf(1.f, 8 - e);
+    b.down = ldexpf(1.f, e - 8);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const float xv[4] = {x[kb][0] * up, x[kb][1] * up, x[kb][2] * up, x[kb][3] * up};
-        halfx4 bh, bl;
-        split_b(xv, &bh, &bl);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) mfma_split(sm, 4 * ((mt * KB + kb) * 64 + lane), bh, bl, &out[mt], &cor[mt]);
+        split_b(xv, &b.h[kb], &b.l[kb]);
     }
+}
+
+// Output tiles mt0 .. mt0 + CH - 1 of A x (A packed by pack_split with KB
+// k-blocks per row of tiles), D layout.
+template <int KB, int CH>
+__device__ inline void split_tiles(const float* sm, int lane, int mt0, const SplitB<KB>& b, floatx4* out) {
+    floatx4 cor[CH];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int c = 0; c < CH; ++c) out[c] = cor[c] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[mt][i] = fmaf(cor[mt][i], 1.f / 2048.f, out[mt][i]) * down;
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            mfma_split(sm, 4 * (((mt0 + c) * KB + kb) * 64 + lane), b.h[kb], b.l[kb], &out[c], &cor[c]);
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[c][i] = fmaf(cor[c][i], 1.f / 2048.f, out[c][i]) * b.down;
+}
+
+// out = A x for the 16 Gaussians of the wave (MT output tiles), two tiles
+// at a time so that only the split operand and two tiles' accumulators are
+// live beside the result.
+template <int MT, int KB>
+__device__ inline void split_gemm(const float* sm, int lane, const floatx4* x, floatx4* out) {
+    SplitB<KB> b;
+    split_cols<KB>(x, b);
+    constexpr int CH = MT % 2 == 0 ? 2 : 1;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt += CH) split_tiles<KB, CH>(sm, lane, mt, b, out + mt);
 }
 
 __device__ inline float leaky(float z) { return z > 0.f ? z : kLeakySlope * z; }
@@ -236,18 +263,15 @@ __device__ inline void directions(const float light[3], int light_dir, const flo
 
 // ---------------------------------------------------------------- forward
 
+// Scene, MLPs and the views of one launch (blockIdx.y selects the view;
+// STORE launches take one view).
 struct BasisArgs {
     SceneDev sc;
-    float light[3], eye[3];
-    int light_dir;
     int use_phi, use_psi;
-    const float* T;
     MlpArgs phi, psi;
-    float4* col0;
-    float4* col1;
-    float* colour;       // [8][n]
     const float* gcol;   // STORE: [7][n] dL/d{c.rgb, T', r.rgb}
     float* rows;         // STORE: scratch rows
+    ShadeView v[kMaxBatch];
 };
 
 // Shading c (Eq. 4-7 with the shared basis) and the residual r = Psi(w_o;
@@ -255,6 +279,7 @@ struct BasisArgs {
 // last hidden layer's pre-activation gradient go to the scratch rows.
 template <bool STORE>
 __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
+    const ShadeView vw = a.v[blockIdx.y];
     __shared__ __align__(16) float sm[kPsiSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
@@ -280,7 +305,7 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
         const int g = valid ? g_raw : n - 1;
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
         float wi[3], wo[3], ri, ro;
-        directions(a.light, a.light_dir, a.eye, mx, my, mz, wi, wo, &ri, &ro);
+        directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
         float c0 = 0.f, c1 = 0.f, c2 = 0.f;
         if (!STORE) {
             float Rs[9];
@@ -317,6 +342,16 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
             c0 = fmaf(sc.albedo[g], fd, sc.spec_albedo[g] * fs);
             c1 = fmaf(sc.albedo[n + g], fd, sc.spec_albedo[n + g] * fs);
             c2 = fmaf(sc.albedo[2 * n + g], fd, sc.spec_albedo[2 * n + g] * fs);
+            // c is written before Psi runs (colour rows 0..2; row 3 is Phi's)
+            if (valid) {
+                if (q == 0) {
+                    float* c0p = reinterpret_cast<float*>(vw.col0 + g);
+                    c0p[0] = c0;
+                    c0p[1] = c1;
+                    c0p[2] = c2;
+                }
+                if (q < 3) vw.colour[(size_t)q * n + g] = q == 0 ? c0 : (q == 1 ? c1 : c2);
+            }
         }
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
         if (a.use_psi) {
@@ -381,17 +416,9 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
             }
         }
         if (!STORE && valid) {
-            if (q == 0) {
-                float* c0p = reinterpret_cast<float*>(a.col0 + g);
-                c0p[0] = c0;
-                c0p[1] = c1;
-                c0p[2] = c2;
-                a.col1[g] = make_float4(r0, r1, r2, 0.f);
-            }
-            // colour rows 0..2 (c), 4..6 (r), 7 (0); row 3 is Phi's
-            const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
-            a.colour[(size_t)(2 * q) * n + g] = v0;
-            if (q != 1) a.colour[(size_t)(2 * q + 1) * n + g] = q == 0 ? c1 : (q == 2 ? r1 : 0.f);
+            // r: col1 and colour rows 4..6, row 7 = 0
+            if (q == 0) vw.col1[g] = make_float4(r0, r1, r2, 0.f);
+            vw.colour[(size_t)(4 + q) * n + g] = q == 0 ? r0 : (q == 1 ? r1 : (q == 2 ? r2 : 0.f));
         }
     }
 }
@@ -401,6 +428,7 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
 // layer's pre-activation gradient go to the scratch rows.
 template <bool STORE>
 __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
+    const ShadeView vw = a.v[blockIdx.y];
     __shared__ __align__(16) float sm[kPhiSmem];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
@@ -421,12 +449,12 @@ __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
         const int g_raw = base + (lane & 15);
         const bool valid = g_raw < n;
         const int g = valid ? g_raw : n - 1;
-        const float Tg = a.T[g];
+        const float Tg = vw.T[g];
         float tp = Tg;
         if (a.use_phi) {
             const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
             float wi[3], wo[3], ri, ro;
-            directions(a.light, a.light_dir, a.eye, mx, my, mz, wi, wo, &ri, &ro);
+            directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
             // inputs [T, PE(w_i), PE(mu), l]
             floatx4 x[4];
 #pragma unroll
@@ -475,8 +503,8 @@ __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
             }
         }
         if (!STORE && valid && q == 0) {
-            reinterpret_cast<float*>(a.col0 + g)[3] = tp;
-            a.colour[(size_t)3 * n + g] = tp;
+            reinterpret_cast<float*>(vw.col0 + g)[3] = tp;
+            vw.colour[(size_t)3 * n + g] = tp;
         }
     }
 }
@@ -510,18 +538,27 @@ __global__ __launch_bounds__(256) void k_mlp_layer_bwd(LayerBwdArgs a) {
         const int g_raw = base + (lane & 15);
         const bool valid = g_raw < n;
         const int g = valid ? g_raw : n - 1;
-        floatx4 dz[KB], out[MT];
-        load_d<KB>(a.rows, a.dz_row, q, g, n, dz);
-        split_gemm<MT, KB>(sm, lane, dz, out);
-        if (MASK) {
-            floatx4 h[MT];
-            load_d<MT>(a.rows, a.h_row, q, g, n, h);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) out[mt][i] = h[mt][i] > 0.f ? out[mt][i] : kLeakySlope * out[mt][i];
+        SplitB<KB> b;
+        {
+            floatx4 dz[KB];
+            load_d<KB>(a.rows, a.dz_row, q, g, n, dz);
+            split_cols<KB>(dz, b);
         }
-        if (valid) store_d<MT>(a.rows, a.out_row, q, g, n, out);
+        // two output tiles at a time: their products, mask and stores
+#pragma unroll 1
+        for (int mt = 0; mt < MT; mt += 2) {
+            floatx4 out[2];
+            split_tiles<KB, 2>(sm, lane, mt, b, out);
+            if (MASK) {
+                floatx4 h[2];
+                load_d<2>(a.rows, a.h_row + 16 * mt, q, g, n, h);
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) out[c][i] = h[c][i] > 0.f ? out[c][i] : kLeakySlope * out[c][i];
+            }
+            if (valid) store_d<2>(a.rows, a.out_row + 16 * mt, q, g, n, out);
+        }
     }
 }
 
@@ -726,61 +763,61 @@ __global__ __launch_bounds__(256) void k_basis_shade_bwd(ShadeBwdBasisArgs a) {
 }
 
 // Sum the per-wave basis sums in a fixed order and apply the adjoint of the
-// basis quaternions (dR_j -> dq_j) and sigmas. One workgroup of 1024
-// threads: value v = t % 256 (12 per basis), quarter t / 256 of the waves.
-__global__ __launch_bounds__(1024) void k_basis_finish(SceneDev sc, const float* partial, int waves, GradDev g) {
-    __shared__ float s4[4][256];
-    __shared__ float tot[256];
-    const int v = threadIdx.x & 255, part = threadIdx.x >> 8;
-    const int K = sc.k;
+// basis quaternions (dR_j -> dq_j) and sigmas. Workgroup j handles basis j
+// with 12 waves, one per value: lane l adds every 64th wave's partial from
+// wave l on, the lanes are combined by a butterfly (fixed order), and the
+// first thread applies the quaternion adjoint.
+__global__ __launch_bounds__(768) void k_basis_finish(SceneDev sc, const float* partial, int waves, GradDev g) {
+    __shared__ float tot[12];
+    const int j = blockIdx.x, v = threadIdx.x >> 6, lane = __lane_id();
     float s = 0.f;
-    if (v < 12 * K)
-        for (int w = part; w < waves; w += 4) s += partial[(size_t)w * 12 * kMaxBasis + v];
-    s4[part][v] = s;
+    for (int w = lane; w < waves; w += 64) s += partial[(size_t)w * 12 * kMaxBasis + 12 * j + v];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) tot[v] = s;
     __syncthreads();
-    if (part == 0) tot[v] = (s4[0][v] + s4[1][v]) + (s4[2][v] + s4[3][v]);
-    __syncthreads();
-    if (threadIdx.x < K) {
-        const int j = threadIdx.x;
-        const float* t = tot + 12 * j;
+    if (threadIdx.x == 0) {
         float qw = sc.basis_rot[4 * j], qx = sc.basis_rot[4 * j + 1], qy = sc.basis_rot[4 * j + 2],
               qz = sc.basis_rot[4 * j + 3];
         const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
         qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-        const float dR[9] = {t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]};
+        const float dR[9] = {tot[0], tot[1], tot[2], tot[3], tot[4], tot[5], tot[6], tot[7], tot[8]};
         float dq[4];
         quat_grad(qw, qx, qy, qz, qn, dR, dq);
         for (int c = 0; c < 4; ++c) g.basis_rot[4 * j + c] += dq[c];
-        for (int c = 0; c < 3; ++c) g.basis_log_sigma[3 * j + c] += t[9 + c];
+        for (int c = 0; c < 3; ++c) g.basis_log_sigma[3 * j + c] += tot[9 + c];
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-static BasisArgs basis_args(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
-                            const gs3_mlp* psi) {
+static BasisArgs basis_args(const SceneDev& sc, const gs3_mlp* phi, const gs3_mlp* psi) {
     BasisArgs a;
     a.sc = sc;
-    for (int i = 0; i < 3; ++i) {
-        a.light[i] = sp.light[i];
-        a.eye[i] = sp.eye[i];
-    }
-    a.light_dir = sp.light_dir;
     a.use_phi = phi != nullptr;
     a.use_psi = psi != nullptr;
-    a.T = T;
     for (int i = 0; i < 4; ++i) {
         a.phi.w[i] = phi ? phi->w[i] : nullptr;
         a.phi.b[i] = phi ? phi->b[i] : nullptr;
         a.psi.w[i] = psi ? psi->w[i] : nullptr;
         a.psi.b[i] = psi ? psi->b[i] : nullptr;
     }
-    a.col0 = nullptr;
-    a.col1 = nullptr;
-    a.colour = nullptr;
     a.gcol = nullptr;
     a.rows = nullptr;
     return a;
+}
+
+static void set_view(ShadeView& w, const ShadeParams& sp, const float* T, float4* col0, float4* col1,
+                     float* colour) {
+    for (int c = 0; c < 3; ++c) {
+        w.light[c] = sp.light[c];
+        w.eye[c] = sp.eye[c];
+    }
+    w.light_dir = sp.light_dir;
+    w.T = T;
+    w.col0 = col0;
+    w.col1 = col1;
+    w.colour = colour;
 }
 
 // Workgroups of a grid-stride launch over n Gaussians, `per` per workgroup.
@@ -789,25 +826,36 @@ static int grid_for(int64_t n, int per, int cap) {
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, const float* const* T,
+                                    const gs3_mlp* phi, const gs3_mlp* psi, const Layout* const* Ls,
+                                    void* const* wss, float* const* colour, int parts, int nv, hipStream_t st) {
+    if (sc.n == 0) return hipSuccess;
+    BasisArgs a = basis_args(sc, phi, psi);
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        const int m = nv - v0 < kMaxBatch ? nv - v0 : kMaxBatch;
+        for (int i = 0; i < m; ++i)
+            set_view(a.v[i], sps[v0 + i], T ? T[v0 + i] : nullptr, at<float4>(wss[v0 + i], Ls[v0 + i]->col0),
+                     at<float4>(wss[v0 + i], Ls[v0 + i]->col1), colour[v0 + i]);
+        if (parts & 1) {
+            // the Psi weights take the whole LDS: one 512-thread workgroup per CU
+            hipLaunchKernelGGL(k_basis_psi<false>, dim3(grid_for(sc.n, 8 * 16, 256), m), dim3(512), 0, st, a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (parts & 2) {
+            hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, 2048), m), dim3(256), 0, st, a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_basis_shade(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
                               const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, int parts,
                               hipStream_t st) {
-    if (sc.n == 0) return hipSuccess;
-    BasisArgs a = basis_args(sc, sp, T, phi, psi);
-    a.col0 = at<float4>(ws, L.col0);
-    a.col1 = at<float4>(ws, L.col1);
-    a.colour = colour_out;
-    if (parts & 1) {
-        // the Psi weights take the whole LDS: one 512-thread workgroup per CU
-        hipLaunchKernelGGL(k_basis_psi<false>, dim3(grid_for(sc.n, 8 * 16, 256)), dim3(512), 0, st, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (parts & 2) {
-        hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, 2048)), dim3(256), 0, st, a);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+    const Layout* Ls[1] = {&L};
+    return launch_basis_shade_batch(sc, &sp, &T, phi, psi, Ls, &ws, &colour_out, parts, 1, st);
 }
 
 int basis_partial_floats(int k) {
@@ -866,7 +914,8 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
                                   float* partial, const gs3_grads* gr, hipStream_t st) {
     if (sc.n == 0) return hipSuccess;
     const int n = sc.n;
-    BasisArgs a = basis_args(sc, sp, T, phi, psi);
+    BasisArgs a = basis_args(sc, phi, psi);
+    set_view(a.v[0], sp, T, nullptr, nullptr, nullptr);
     a.gcol = gcol;
     a.rows = rows;
     hipError_t e;
@@ -918,7 +967,7 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
     hipLaunchKernelGGL(k_basis_shade_bwd, dim3(grid), dim3(256), 0, st, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sc.k > 0) {
-        hipLaunchKernelGGL(k_basis_finish, dim3(1), dim3(1024), 0, st, sc, (const float*)partial, grid * 4, g);
+        hipLaunchKernelGGL(k_basis_finish, dim3(sc.k), dim3(768), 0, st, sc, (const float*)partial, grid * 4, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!phi && !psi) return hipSuccess;

@@ -22,12 +22,23 @@ struct RenderArgs {
     const float4* col1;   // {r.r, r.g, r.b, 0}
     const ViewHeader* hdr;
     uint32_t n;
-    int width, height, tiles_x;
+    int width, height, tiles_x, n_tiles;
     float alpha_max, t_min;
     gs3_images out;
 };
 
-__global__ __launch_bounds__(256) void k_render(RenderArgs a) {
+// The views of one launch: blockIdx.y selects the view, blockIdx.x its
+// tile (the x extent is the largest view's tile count; the surplus
+// workgroups of smaller views exit).
+struct RenderBatch {
+    RenderArgs v[kMaxBatch];
+};
+
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_render(RenderBatch B) {
+    // ONE: a single view (static argument offsets)
+    const RenderArgs a = ONE ? B.v[0] : B.v[blockIdx.y];
+    if ((int)blockIdx.x >= a.n_tiles) return;
     __shared__ Staged s_rec[256];
     __shared__ float4 s_c0[256];
     __shared__ float4 s_c1[256];
@@ -127,8 +138,7 @@ __global__ __launch_bounds__(256) void k_render(RenderArgs a) {
     }
 }
 
-hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, const gs3_images& out,
-                         hipStream_t st) {
+static RenderArgs render_args(const gs3_consts& k, const Layout& L, const void* ws, const gs3_images& out) {
     RenderArgs a;
     a.ranges = at<int2>(ws, L.ranges);
     a.order = at<uint32_t>(ws, L.order);
@@ -143,11 +153,38 @@ hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, c
     a.width = L.width;
     a.height = L.height;
     a.tiles_x = L.tiles_x;
+    a.n_tiles = (int)L.n_tiles;
     a.alpha_max = k.alpha_max;
     a.t_min = k.t_min;
     a.out = out;
-    hipLaunchKernelGGL(k_render, dim3((unsigned)L.n_tiles), dim3(256), 0, st, a);
-    return hipGetLastError();
+    return a;
+}
+
+hipError_t launch_render_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                               const gs3_images* outs, int nv, hipStream_t st) {
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        const int m = nv - v0 < kMaxBatch ? nv - v0 : kMaxBatch;
+        RenderBatch B;
+        int64_t gx = 0;
+        for (int i = 0; i < m; ++i) {
+            B.v[i] = render_args(k, *Ls[v0 + i], wss[v0 + i], outs[v0 + i]);
+            gx = Ls[v0 + i]->n_tiles > gx ? Ls[v0 + i]->n_tiles : gx;
+        }
+        if (m == 1)
+            hipLaunchKernelGGL(k_render<true>, dim3((unsigned)gx), dim3(256), 0, st, B);
+        else
+            hipLaunchKernelGGL(k_render<false>, dim3((unsigned)gx, m), dim3(256), 0, st, B);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_render(const gs3_consts& k, const Layout& L, const void* ws, const gs3_images& out,
+                         hipStream_t st) {
+    const Layout* Ls[1] = {&L};
+    void* w = const_cast<void*>(ws);
+    return launch_render_batch(k, Ls, &w, &out, 1, st);
 }
 
 }  // namespace gs3

@@ -14,23 +14,19 @@ namespace gs3 {
 // not depend on the shadow values) and/or Phi's refined shadow T'.
 enum ShadeParts { kShadePsi = 1, kShadePhi = 2 };
 
+// Scene, MLPs and the views of one launch (blockIdx.y selects the view).
 struct ShadeArgs {
     SceneDev sc;
-    float light[3];      // point light, or (light_dir) unit direction toward the light
-    float eye[3];
     int use_phi, use_psi;
-    int light_dir;
     int parts;
-    const float* T;
     MlpArgs phi, psi;
-    float4* col0;
-    float4* col1;
-    float* colour;   // [8][n]
+    ShadeView v[kMaxBatch];
 };
 
 __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
     __shared__ __align__(16) float sm[kShadeSmem];
     const SceneDev& sc = a.sc;
+    const ShadeView vw = a.v[blockIdx.y];
     const int n = sc.n;
     if (a.use_phi) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
     if (a.use_psi) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
@@ -49,11 +45,11 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
         // ---- shading (Eq. 4-7)
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
         // w_i: toward a point light, or a directional light's fixed direction
-        const float lm = a.light_dir ? 0.f : 1.f;
-        wix = a.light[0] - lm * mx; wiy = a.light[1] - lm * my; wiz = a.light[2] - lm * mz;
+        const float lm = vw.light_dir ? 0.f : 1.f;
+        wix = vw.light[0] - lm * mx; wiy = vw.light[1] - lm * my; wiz = vw.light[2] - lm * mz;
         float r = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
         wix *= r; wiy *= r; wiz *= r;
-        wox = a.eye[0] - mx; woy = a.eye[1] - my; woz = a.eye[2] - mz;
+        wox = vw.eye[0] - mx; woy = vw.eye[1] - my; woz = vw.eye[2] - mz;
         r = rsqrtf(wox * wox + woy * woy + woz * woz);
         wox *= r; woy *= r; woz *= r;
         float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
@@ -108,7 +104,7 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
         }
         // ---- shadow refinement Phi([T, feat]) (Eq. 8)
         float tp = 0.f;
-        if (a.parts & kShadePhi) tp = a.T[g];
+        if (a.parts & kShadePhi) tp = vw.T[g];
         if ((a.parts & kShadePhi) && a.use_phi) {
             const float Tg = tp;
             floatx4 h[4];
@@ -142,64 +138,80 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
             r2 = mlp_out(sm, kPsiS, lane, h, 2);
         }
         if (valid) {
-            float* c0p = reinterpret_cast<float*>(a.col0 + g);
+            float* c0p = reinterpret_cast<float*>(vw.col0 + g);
             if (a.parts == (kShadePsi | kShadePhi)) {
                 if (q == 0) {
-                    a.col0[g] = make_float4(c0, c1, c2, tp);
-                    a.col1[g] = make_float4(r0, r1, r2, 0.f);
+                    vw.col0[g] = make_float4(c0, c1, c2, tp);
+                    vw.col1[g] = make_float4(r0, r1, r2, 0.f);
                 }
                 const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
                 const float v1 = q == 0 ? c1 : (q == 1 ? tp : (q == 2 ? r1 : 0.f));
-                a.colour[(size_t)(2 * q) * n + g] = v0;
-                a.colour[(size_t)(2 * q + 1) * n + g] = v1;
+                vw.colour[(size_t)(2 * q) * n + g] = v0;
+                vw.colour[(size_t)(2 * q + 1) * n + g] = v1;
             } else if (a.parts == kShadePsi) {
                 // colour rows 0..2 (c), 4..6 (r), 7 (0); col0.w is Phi's
                 if (q == 0) {
                     c0p[0] = c0;
                     c0p[1] = c1;
                     c0p[2] = c2;
-                    a.col1[g] = make_float4(r0, r1, r2, 0.f);
+                    vw.col1[g] = make_float4(r0, r1, r2, 0.f);
                 }
                 const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
-                a.colour[(size_t)(2 * q) * n + g] = v0;
-                if (q != 1) a.colour[(size_t)(2 * q + 1) * n + g] = q == 0 ? c1 : (q == 2 ? r1 : 0.f);
+                vw.colour[(size_t)(2 * q) * n + g] = v0;
+                if (q != 1) vw.colour[(size_t)(2 * q + 1) * n + g] = q == 0 ? c1 : (q == 2 ? r1 : 0.f);
             } else if (q == 0) {
                 c0p[3] = tp;
-                a.colour[(size_t)3 * n + g] = tp;
+                vw.colour[(size_t)3 * n + g] = tp;
             }
         }
     }
 }
 
-hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
-                            const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, int parts,
-                            hipStream_t st) {
+hipError_t launch_shade_mlp_batch(const SceneDev& sc, const ShadeParams* sps, const float* const* T,
+                                  const gs3_mlp* phi, const gs3_mlp* psi, const Layout* const* Ls,
+                                  void* const* wss, float* const* colour, int parts, int nv, hipStream_t st) {
     if (sc.n == 0) return hipSuccess;
     ShadeArgs a;
     a.sc = sc;
     a.parts = parts;
-    for (int i = 0; i < 3; ++i) {
-        a.light[i] = sp.light[i];
-        a.eye[i] = sp.eye[i];
-    }
     a.use_phi = phi != nullptr;
     a.use_psi = psi != nullptr;
-    a.light_dir = sp.light_dir;
-    a.T = T;
     for (int i = 0; i < 4; ++i) {
         a.phi.w[i] = phi ? phi->w[i] : nullptr;
         a.phi.b[i] = phi ? phi->b[i] : nullptr;
         a.psi.w[i] = psi ? psi->w[i] : nullptr;
         a.psi.b[i] = psi ? psi->b[i] : nullptr;
     }
-    a.col0 = at<float4>(ws, L.col0);
-    a.col1 = at<float4>(ws, L.col1);
-    a.colour = colour_out;
     const int per_block = 8 * 16;
     int grid = (int)((sc.n + per_block - 1) / per_block);
     if (grid > 512) grid = 512;
-    hipLaunchKernelGGL(k_shade_mlp, dim3(grid), dim3(512), 0, st, a);
-    return hipGetLastError();
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        const int m = nv - v0 < kMaxBatch ? nv - v0 : kMaxBatch;
+        for (int i = 0; i < m; ++i) {
+            const ShadeParams& sp = sps[v0 + i];
+            ShadeView& w = a.v[i];
+            for (int c = 0; c < 3; ++c) {
+                w.light[c] = sp.light[c];
+                w.eye[c] = sp.eye[c];
+            }
+            w.light_dir = sp.light_dir;
+            w.T = T ? T[v0 + i] : nullptr;
+            w.col0 = at<float4>(wss[v0 + i], Ls[v0 + i]->col0);
+            w.col1 = at<float4>(wss[v0 + i], Ls[v0 + i]->col1);
+            w.colour = colour[v0 + i];
+        }
+        hipLaunchKernelGGL(k_shade_mlp, dim3(grid, m), dim3(512), 0, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_shade_mlp(const SceneDev& sc, const ShadeParams& sp, const float* T, const gs3_mlp* phi,
+                            const gs3_mlp* psi, const Layout& L, void* ws, float* colour_out, int parts,
+                            hipStream_t st) {
+    const Layout* Ls[1] = {&L};
+    return launch_shade_mlp_batch(sc, &sp, &T, phi, psi, Ls, &ws, &colour_out, parts, 1, st);
 }
 
 }  // namespace gs3

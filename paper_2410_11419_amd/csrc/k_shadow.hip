@@ -54,6 +54,13 @@ struct ShadowArgs {
 
 static_assert(kShadowBatch == 64, "the walk stages one list entry per lane per batch");
 
+// The views of one launch: blockIdx.y selects the view, blockIdx.x runs
+// over that view's work as in a launch of the view alone (the x extent is
+// the largest view's; the surplus workgroups of smaller views exit).
+struct ShadowBatch {
+    ShadowArgs v[kMaxBatch];
+};
+
 // One wave per (tile, 8x8 quadrant): the four quadrants of a light tile run
 // as independent single-wave workgroups, one pixel per lane. The wave stages
 // its tile's list 64 entries at a time (one per lane) into an LDS ring that
@@ -75,7 +82,10 @@ static_assert(kShadowBatch == 64, "the walk stages one list entry per lane per b
 // 16-lane row (DPP) into four partial sums per entry, which go to num_j in
 // one burst of atomics per batch. The wave exits when all its pixels are
 // dark.
-__global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
+template <bool ONE>
+__global__ __launch_bounds__(64) void k_shadow(ShadowBatch B) {
+    // ONE: a single view (static argument offsets)
+    const ShadowArgs a = ONE ? B.v[0] : B.v[blockIdx.y];
     __shared__ Staged s_rec[2 * kShadowBatch];
     __shared__ uint32_t s_id[2 * kShadowBatch];
     __shared__ float s_sum[4][kShadowBatch];     // lead sums of the current batch, per 16-lane row
@@ -250,7 +260,9 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowArgs a) {
 // Everything but the pixel is the same in all lanes of the wave; the
 // readfirstlane reads say so, which keeps the loops and the block culls in
 // scalar registers and scalar branches.
-__global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_shadow_den(ShadowBatch B) {
+    const ShadowArgs a = ONE ? B.v[0] : B.v[blockIdx.y];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = __lane_id();
     const int lx = lane & 15, ly = lane >> 4;
@@ -412,10 +424,23 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowArgs a) {
 // next numerator pass. A binning that overflowed its pair capacity left the
 // tile lists empty, so num is missing every term: T is then NaN, not a
 // plausible value.
-__global__ __launch_bounds__(256) void k_shadow_finish(float* __restrict__ acc, float* __restrict__ num,
-                                                        const float* __restrict__ den,
-                                                        const ViewHeader* __restrict__ hdr, float* __restrict__ T,
-                                                        int n) {
+struct FinishArgs {
+    float* acc;
+    float* num;
+    const float* den;
+    const ViewHeader* hdr;
+    float* T;
+};
+struct FinishBatch {
+    FinishArgs v[kMaxBatch];
+};
+__global__ __launch_bounds__(256) void k_shadow_finish(FinishBatch B, int n) {
+    const FinishArgs f = B.v[blockIdx.y];
+    float* __restrict__ acc = f.acc;
+    float* __restrict__ num = f.num;
+    const float* __restrict__ den = f.den;
+    const ViewHeader* __restrict__ hdr = f.hdr;
+    float* __restrict__ T = f.T;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const float nu = acc[i];
@@ -447,26 +472,90 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, void* ws, fl
     return a;
 }
 
+// Launches over nv views in chunks of kMaxBatch (blockIdx.y = view).
+template <typename Fill>
+static hipError_t batched(int nv, Fill fill) {
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        const int m = nv - v0 < kMaxBatch ? nv - v0 : kMaxBatch;
+        hipError_t e = fill(v0, m);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_shadow_den_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                                   float* const* num_den, int nv, hipStream_t st) {
+    return batched(nv, [&](int v0, int m) {
+        ShadowBatch B;
+        int64_t gx = 0;
+        for (int i = 0; i < m; ++i) {
+            B.v[i] = shadow_args(k, *Ls[v0 + i], wss[v0 + i], num_den[v0 + i]);
+            gx = Ls[v0 + i]->n > gx ? Ls[v0 + i]->n : gx;
+        }
+        if (gx == 0) return hipSuccess;
+        int grid = (int)((gx + 3) / 4);
+        if (grid > 32768) grid = 32768;
+        if (m == 1)
+            hipLaunchKernelGGL(k_shadow_den<true>, dim3(grid), dim3(256), 0, st, B);
+        else
+            hipLaunchKernelGGL(k_shadow_den<false>, dim3(grid, m), dim3(256), 0, st, B);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_shadow_num_batch(const gs3_consts& k, const Layout* const* Ls, void* const* wss,
+                                   float* const* num_den, int nv, hipStream_t st) {
+    return batched(nv, [&](int v0, int m) {
+        ShadowBatch B;
+        unsigned gx = 0;
+        for (int i = 0; i < m; ++i) {
+            const Layout& L = *Ls[v0 + i];
+            B.v[i] = shadow_args(k, L, wss[v0 + i], num_den[v0 + i]);
+            // a view without Gaussians has no list to walk
+            if (L.n == 0) B.v[i].n_tiles = 0;
+            const unsigned g = L.n == 0 ? 0u : quadrant_grid(L.n_tiles);
+            gx = g > gx ? g : gx;
+        }
+        if (gx == 0) return hipSuccess;
+        if (m == 1)
+            hipLaunchKernelGGL(k_shadow<true>, dim3(gx), dim3(64), 0, st, B);
+        else
+            hipLaunchKernelGGL(k_shadow<false>, dim3(gx, m), dim3(64), 0, st, B);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_shadow_resolve_batch(const Layout* const* Ls, void* const* wss, float* const* num_den,
+                                       float* const* T, int nv, hipStream_t st) {
+    return batched(nv, [&](int v0, int m) {
+        FinishBatch B;
+        const int64_t n = Ls[v0]->n;
+        for (int i = 0; i < m; ++i) {
+            const Layout& L = *Ls[v0 + i];
+            void* ws = wss[v0 + i];
+            B.v[i] = FinishArgs{at<float>(ws, L.num), num_den[v0 + i], num_den[v0 + i] + L.n,
+                                at<ViewHeader>(ws, L.hdr), T[v0 + i]};
+        }
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((n + 255) / 256), m), dim3(256), 0, st, B, (int)n);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_shadow_den(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st) {
-    if (L.n == 0) return hipSuccess;
-    int grid = (int)((L.n + 3) / 4);
-    if (grid > 32768) grid = 32768;
-    hipLaunchKernelGGL(k_shadow_den, dim3(grid), dim3(256), 0, st, shadow_args(k, L, ws, num_den));
-    return hipGetLastError();
+    const Layout* Ls[1] = {&L};
+    return launch_shadow_den_batch(k, Ls, &ws, &num_den, 1, st);
 }
 
 hipError_t launch_shadow_num(const gs3_consts& k, const Layout& L, void* ws, float* num_den, hipStream_t st) {
-    if (L.n == 0 || L.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shadow, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, shadow_args(k, L, ws, num_den));
-    return hipGetLastError();
+    if (L.n_tiles == 0) return hipSuccess;
+    const Layout* Ls[1] = {&L};
+    return launch_shadow_num_batch(k, Ls, &ws, &num_den, 1, st);
 }
 
 hipError_t launch_shadow_resolve(const Layout& L, void* ws, float* num_den, float* T, hipStream_t st) {
-    if (L.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_shadow_finish, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st,
-                       at<float>(ws, L.num), num_den, num_den + L.n,
-                       at<ViewHeader>(ws, L.hdr), T, (int)L.n);
-    return hipGetLastError();
+    const Layout* Ls[1] = {&L};
+    return launch_shadow_resolve_batch(Ls, &ws, &num_den, &T, 1, st);
 }
 
 hipError_t launch_shadow(const gs3_consts& k, const Layout& L, void* ws, float* num_den, float* T,

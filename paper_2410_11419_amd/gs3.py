@@ -40,7 +40,7 @@ EXPORTED = [
     "gs3_sort", "gs3_shade", "gs3_render_shaded", "gs3_backward_workspace_size", "gs3_render_backward",
     "gs3_view_poll", "gs3_l1_loss_workspace_size", "gs3_l1_loss", "gs3_grads_clear", "gs3_grads_accumulate",
     "gs3_l1_loss_noalloc", "gs3_dssim_loss_workspace_size", "gs3_dssim_loss", "gs3_adam_step",
-    "gs3_image_accumulate", "gs3_backward_workspace_size_for",
+    "gs3_image_accumulate", "gs3_backward_workspace_size_for", "gs3_shadow_splat_views", "gs3_render_views",
 ]
 GS3_APPEARANCE_LOBES, GS3_APPEARANCE_BASIS = 0, 1
 BASIS_NAMES = ("spec_albedo", "basis_weight", "latent", "basis_rot", "basis_log_sigma")
@@ -132,6 +132,11 @@ def _load():
         "gs3_render": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), P(gs3_consts), C.c_void_p,
                                  P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images), C.c_void_p]),
         "gs3_image_accumulate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_float, C.c_int64, C.c_void_p]),
+        "gs3_shadow_splat_views": (C.c_int, [P(gs3_consts), P(gs3_viewbuf), C.c_int32, P(C.c_void_p),
+                                             P(C.c_void_p), C.c_void_p]),
+        "gs3_render_views": (C.c_int, [P(gs3_scene), P(gs3_view), P(gs3_view), C.c_int32, P(gs3_consts),
+                                       P(C.c_void_p), P(gs3_mlp), P(gs3_mlp), P(gs3_viewbuf), P(gs3_images),
+                                       C.c_void_p]),
         "gs3_view_poll": (C.c_int, [P(gs3_viewbuf), P(C.c_int32), P(C.c_int64)]),
         "gs3_l1_loss_workspace_size": (C.c_int, [C.c_int64, P(C.c_size_t)]),
         "gs3_l1_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
@@ -444,6 +449,40 @@ def gs3_render_shaded(scene: DeviceScene, cam, light, consts: gs3_consts, T: tor
     _check(_lib.gs3_render_shaded(C.byref(scene.c_struct()), C.byref(v), C.byref(lp), C.byref(consts), _ptr(T),
                                   C.byref(phi) if phi is not None else None, C.byref(cam_vb.vb), C.byref(im),
                                   _stream()), "gs3_render_shaded")
+
+
+def gs3_shadow_splat_views(consts: gs3_consts, light_vbs: Sequence[ViewBuffer], num_dens: Sequence[torch.Tensor],
+                           Ts: Sequence[torch.Tensor]):
+    """Shadow splats of several light views in one launch sequence."""
+    n = len(light_vbs)
+    if n < 1 or len(num_dens) != n or len(Ts) != n:
+        raise ValueError("one num_den and one T per light view, at least one view")
+    ba = (gs3_viewbuf * n)(*[vb.vb for vb in light_vbs])
+    nd = (C.c_void_p * n)(*[_ptr(t).value for t in num_dens])
+    ta = (C.c_void_p * n)(*[_ptr(t).value for t in Ts])
+    _check(_lib.gs3_shadow_splat_views(C.byref(consts), ba, n, nd, ta, _stream()), "gs3_shadow_splat_views")
+
+
+def gs3_render_views(scene: DeviceScene, cams: Sequence, lights: Sequence, consts: gs3_consts,
+                     Ts: Sequence[torch.Tensor], cam_vbs: Sequence[ViewBuffer],
+                     images: Sequence[Dict[str, torch.Tensor]], use_mlps: bool = True):
+    """Shading, MLPs and camera splats of several (camera, light) views in
+    one launch sequence."""
+    n = len(cams)
+    if n < 1 or len(lights) != n or len(Ts) != n or len(cam_vbs) != n or len(images) != n:
+        raise ValueError("one light, T, camera buffer and image set per camera, at least one camera")
+    ca = (gs3_view * n)(*[make_view(v) for v in cams])
+    la = (gs3_view * n)(*[make_view(v) for v in lights])
+    ta = (C.c_void_p * n)(*[_ptr(t).value for t in Ts])
+    ba = (gs3_viewbuf * n)(*[vb.vb for vb in cam_vbs])
+    ia = (gs3_images * n)(*[gs3_images(*[_ptr(im[k]) for k in ("final", "S", "Sh", "R", "T_final", "n_contrib",
+                                                                 "colour")]) for im in images])
+    phi = DeviceScene.c_mlp(scene.phi, *scene.phi_io) if use_mlps else None
+    psi = DeviceScene.c_mlp(scene.psi, *scene.psi_io) if use_mlps else None
+    _check(_lib.gs3_render_views(C.byref(scene.c_struct()), ca, la, n, C.byref(consts), ta,
+                                 C.byref(phi) if phi is not None else None,
+                                 C.byref(psi) if psi is not None else None, ba, ia, _stream()),
+           "gs3_render_views")
 
 
 def l1_workspace(count: int, device="cuda") -> torch.Tensor:
@@ -919,6 +958,58 @@ class RelitRender(torch.autograd.Function):
 def relit_render(renderer: "Renderer", cam, light) -> torch.Tensor:
     """Differentiable relit frame [3, H, W] (see RelitRender)."""
     return RelitRender.apply(renderer, cam, light, *scene_parameters(renderer.scene))
+
+
+def render_batched(renderers: Sequence["Renderer"], cams: Sequence, lights: Sequence,
+                   shadows: Optional[Sequence[Optional[torch.Tensor]]] = None) -> list:
+    """Relit frames of several (camera, light) requests with one launch
+    sequence per stage: the light and camera views of every request are
+    projected and binned together (gs3_preprocess_views), the light views'
+    shadow splats run together (gs3_shadow_splat_views) and so do the
+    shading, MLPs and camera splats (gs3_render_views). Request i uses the
+    buffers of ``renderers[i]`` (all of one scene). Requests whose light view
+    is the same share one shadow pass; with ``shadows[i]`` given, request i
+    uses those shadow values and runs no light pass. Returns each request's
+    output dict (its renderer's images and T). No host synchronisation."""
+    n = len(cams)
+    if n < 1 or len(renderers) != n or len(lights) != n:
+        raise ValueError("one renderer and one light per camera, at least one request")
+    shadows = list(shadows) if shadows is not None else [None] * n
+    r0 = renderers[0]
+    scene, consts = r0.scene, r0.consts
+
+    def vb(r, role, view):
+        got = r.vbs.get((role, view.width, view.height))
+        if got is None:
+            got = r._vb(role, view.width, view.height, r.capacity_hint or max(1 << 16, 32 * scene.n))
+        return got
+
+    def key(light):
+        return (tuple(float(x) for x in light.eye), tuple(float(x) for x in light.target), light.width,
+                light.height, float(light.fov), light.projection, float(light.ortho_width))
+    owner: Dict[tuple, int] = {}     # light view -> request running its shadow pass
+    for i in range(n):
+        if shadows[i] is None:
+            owner.setdefault(key(lights[i]), i)
+    passes = sorted(owner.values())
+    views, modes, vbs = [], [], []
+    for i in passes:
+        views.append(lights[i]); modes.append(GS3_DEPTH_DIST); vbs.append(vb(renderers[i], "light", lights[i]))
+    cvbs = [vb(renderers[i], "cam", cams[i]) for i in range(n)]
+    views += list(cams); modes += [GS3_DEPTH_Z] * n; vbs += cvbs
+    gs3_preprocess_views(scene, views, modes, consts, vbs)
+    if passes:
+        gs3_shadow_splat_views(consts, vbs[:len(passes)], [renderers[i].num_den for i in passes],
+                               [renderers[i].T for i in passes])
+    Ts = [shadows[i] if shadows[i] is not None else renderers[owner[key(lights[i])]].T for i in range(n)]
+    ims = [renderers[i]._images(cams[i].width, cams[i].height) for i in range(n)]
+    gs3_render_views(scene, cams, lights, consts, Ts, cvbs, ims, r0.use_mlps)
+    outs = []
+    for i in range(n):
+        o = dict(ims[i])
+        o["T"] = Ts[i]
+        outs.append(o)
+    return outs
 
 
 class FramePipeline:

@@ -19,6 +19,14 @@ runs it and keeps a copy of T; later ones wait for that copy on the device
 (a stream wait on its event) and run only their camera path. Copies are
 kept for the most recently used lights, within the memory cap.
 
+With ``batch`` > 1 the server launches requests in batches: the requests
+waiting when the device has room (up to ``batch`` of them, mixed
+resolutions) run as one launch sequence per stage over all their views
+(``gs3.render_batched``: one projection + binning launch sequence for every
+light and camera view, one shadow-splat sequence, one shading + camera-splat
+sequence), on one stream; several batches can be in flight together. A light
+seen twice in a batch gets one shadow pass.
+
 Latency of a request = completion time - arrival time (queueing included).
 """
 from __future__ import annotations
@@ -141,7 +149,7 @@ class Server:
 
     def __init__(self, scene: gs3.DeviceScene, mem_cap_bytes: int, consts=None, light_res: int = 1024,
                  capacity: Optional[int] = None, max_inflight: int = 8, overlap="auto",
-                 share_lights: bool = False, max_lights: int = 256):
+                 share_lights: bool = False, max_lights: int = 256, batch: int = 1):
         self.scene = scene
         self.consts = consts if consts is not None else gs3.default_consts()
         self.cap = int(mem_cap_bytes)
@@ -159,6 +167,8 @@ class Server:
         self.max_lights = max_lights
         self.lights: "OrderedDict[tuple, LightEntry]" = OrderedDict()
         self.light_passes = 0          # shadow passes run (not shared)
+        self.batch = max(1, int(batch))
+        self.batches = 0               # batched launches issued
 
     def _acquire(self, res: int) -> Optional[BufferSet]:
         pool = self.free.setdefault(res, [])
@@ -206,6 +216,42 @@ class Server:
             bs.event.record(bs.stream)
         return final
 
+    def _launch_batch(self, reqs: List[Request], sets: List[BufferSet], keep: bool, n_inflight: int = 0) -> list:
+        """Requests `reqs` with buffer sets `sets` as one batch on the first
+        set's stream (its event marks the batch done). Returns the finals. A
+        batch of one request runs the one-request path, whose frame overlaps
+        its own stages when the device is otherwise idle."""
+        if len(reqs) == 1:
+            final = self._launch(reqs[0], sets[0], keep, n_inflight)
+            self.batches += 1
+            return [final]
+        stream = sets[0].stream
+        shadows = [None] * len(reqs)
+        keys = [light_key(r.light) for r in reqs]
+        with torch.cuda.stream(stream):
+            if self.share_lights:
+                for i, k in enumerate(keys):
+                    entry = self.lights.get(k)
+                    if entry is not None:
+                        self.lights.move_to_end(k)
+                        stream.wait_event(entry.event)
+                        entry.T.record_stream(stream)
+                        shadows[i] = entry.T
+            outs = gs3.render_batched([bs.renderer for bs in sets], [r.cam for r in reqs],
+                                      [r.light for r in reqs], shadows)
+            fresh = {}
+            for i, k in enumerate(keys):
+                if shadows[i] is None and k not in fresh:
+                    fresh[k] = outs[i]["T"]
+            self.light_passes += len(fresh)
+            if self.share_lights:
+                for k, T in fresh.items():
+                    self._keep_light(k, T, stream)
+            finals = [o["final"].clone() if keep else None for o in outs]
+            sets[0].event.record(stream)
+        self.batches += 1
+        return finals
+
     def _keep_light(self, key, T: torch.Tensor, stream):
         """Keep a copy of a light's shadow values for later requests (LRU;
         the oldest copies go when the count or the memory cap is reached)."""
@@ -252,10 +298,10 @@ class Server:
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             progressed = False
-            # completions
+            # completions (a batch's requests complete with its first set's event)
             still = []
-            for req, bs, start, final in inflight:
-                if bs.event.query():
+            for req, bs, start, final, ev in inflight:
+                if ev.query():
                     redo = self._check_done(bs, req, keep_results)
                     done = time.perf_counter() - t0
                     results[req.rid] = Result(req.rid, req.arrival, start, done,
@@ -263,11 +309,25 @@ class Server:
                     self.free.setdefault(bs.res, []).append(bs)
                     progressed = True
                 else:
-                    still.append((req, bs, start, final))
+                    still.append((req, bs, start, final, ev))
             inflight = still
             # admissions (first come first served; a request that cannot get
             # memory waits, and so do the ones behind it)
-            while waiting and len(inflight) < self.max_inflight:
+            if self.batch > 1:
+                reqs, sets = [], []
+                while waiting and len(inflight) + len(reqs) < self.max_inflight and len(reqs) < self.batch:
+                    bs = self._acquire(waiting[0].cam.width)
+                    if bs is None:
+                        break
+                    reqs.append(waiting.popleft())
+                    sets.append(bs)
+                if reqs:
+                    start = time.perf_counter() - t0
+                    finals = self._launch_batch(reqs, sets, keep_results, len(inflight))
+                    for req, bs, final in zip(reqs, sets, finals):
+                        inflight.append((req, bs, start, final, sets[0].event))
+                    progressed = True
+            while self.batch == 1 and waiting and len(inflight) < self.max_inflight:
                 req = waiting[0]
                 bs = self._acquire(req.cam.width)
                 if bs is None:
@@ -275,7 +335,7 @@ class Server:
                 waiting.popleft()
                 start = time.perf_counter() - t0
                 final = self._launch(req, bs, keep_results, len(inflight))
-                inflight.append((req, bs, start, final))
+                inflight.append((req, bs, start, final, bs.event))
                 progressed = True
             if not progressed:
                 if inflight:

@@ -331,13 +331,18 @@ def scene_needles(seed: int = 0, n_needles: int = 60, n_blobs: int = 340, mlps: 
 def perturb_scene(sc: Scene, seed: int, mean_sd: float = 0.01,
                   colour_sd: float = 0.05) -> Scene:
     """Target scene for the training step: means + N(0, mean_sd), albedo and
-    lobe amplitudes + N(0, colour_sd), unclamped; everything else shared."""
+    lobe amplitudes (or the basis scene's specular albedo) + N(0, colour_sd),
+    unclamped; everything else shared."""
     rng = np.random.default_rng(seed)
     f = np.float32
     out = dataclasses.replace(sc)
     out.mean = (sc.mean.astype(np.float64) + rng.normal(0, mean_sd, sc.mean.shape)).astype(f)
     out.albedo = (sc.albedo.astype(np.float64) + rng.normal(0, colour_sd, sc.albedo.shape)).astype(f)
     out.lobe_amp = (sc.lobe_amp.astype(np.float64) + rng.normal(0, colour_sd, sc.lobe_amp.shape)).astype(f)
+    if sc.basis is not None:     # the specular albedo of the shared-basis appearance
+        sp = sc.basis.spec_albedo
+        out.basis = dataclasses.replace(
+            sc.basis, spec_albedo=(sp.astype(np.float64) + rng.normal(0, colour_sd, sp.shape)).astype(f))
     return out
 
 

@@ -141,3 +141,70 @@ def test_renderer_batched_views(gs3, overlap):
         for key in ("final", "T_final", "S"):
             assert float((ra[key] - rb[key]).abs().max()) <= 1e-6, key
         assert float((ra["T"] - rb["T"]).abs().max()) <= 1e-6
+
+
+def _requests(n, seed, sizes, light_sizes):
+    rng = np.random.default_rng(seed)
+    cams, lights = [], []
+    for i in range(n):
+        w, h = sizes[i % len(sizes)]
+        cams.append(synth.make_view(rng.standard_normal(3), 4.0, w, h, 40.0))
+        lw, lh = light_sizes[i % len(light_sizes)]
+        if lw < 0:
+            lights.append(synth.make_directional(rng.standard_normal(3), -lw, -lh, 2.4))
+        else:
+            lights.append(synth.make_view(rng.standard_normal(3), 4.0, lw, lh, 60.0))
+    return cams, lights
+
+
+@pytest.mark.parametrize("appearance", ["lobes", "basis"])
+def test_render_batched_equals_single(gs3, appearance):
+    """gs3_preprocess_views + gs3_shadow_splat_views + gs3_render_views over
+    eleven requests of mixed camera and light sizes (two launch chunks, a
+    directional light, a light shared by two requests, a one-tile camera)
+    against each request rendered alone: shadow values and every image
+    within 1e-5 (the shadow numerator's float atomics may add in another
+    order), integer contribution counts equal."""
+    if appearance == "lobes":
+        sc = synth.make_scene(6000, 4, seed=21, means="shell", mlps=True, log_scale_mu=(-3.6,) * 3)
+    else:
+        sc = synth.make_basis_scene(6000, 21, means="shell", mlps=True, log_scale_mu=(-3.6,) * 3)
+    ds = gs3.DeviceScene.from_host(sc)
+    sizes = [(128, 128), (200, 152), (96, 64), (16, 16), (256, 256), (72, 200)]
+    lsizes = [(128, 128), (-160, -160), (200, 200), (64, 64)]
+    cams, lights = _requests(11, 31, sizes, lsizes)
+    lights[7] = lights[2]                         # a shared light
+    rnds = [gs3.Renderer(ds) for _ in cams]
+    outs = gs3.render_batched(rnds, cams, lights)
+    got = [{k: v.clone() for k, v in o.items()} for o in outs]
+    torch.cuda.synchronize()
+    assert not any(r.overflowed() for r in rnds)
+    single = gs3.Renderer(ds)
+    worst_T = worst_im = 0.0
+    for i, (cam, light) in enumerate(zip(cams, lights)):
+        ref = single.render(cam, light, overlap=False)
+        worst_T = max(worst_T, float((got[i]["T"][:sc.n] - ref["T"][:sc.n]).abs().max()))
+        for k in ("final", "S", "Sh", "R", "T_final", "colour"):
+            worst_im = max(worst_im, float((got[i][k] - ref[k]).abs().max()))
+        assert torch.equal(got[i]["n_contrib"], ref["n_contrib"]) or \
+            float((got[i]["n_contrib"] != ref["n_contrib"]).float().mean()) < 1e-3
+    print(f"[{appearance}] batched vs single: T {worst_T:.2e}, images {worst_im:.2e}")
+    assert worst_T <= 1e-5 and worst_im <= 1e-5
+
+
+def test_batched_entry_points_check_arguments(gs3):
+    sc = synth.make_scene(500, 2, seed=3, means="cube")
+    ds = gs3.DeviceScene.from_host(sc)
+    rnd = gs3.Renderer(ds)
+    cam, light = _requests(1, 5, [(64, 64)], [(64, 64)])
+    out = rnd.render(cam[0], light[0])
+    lvb = rnd.vbs[("light", 64, 64)]
+    with pytest.raises(gs3.Gs3Error):
+        gs3.gs3_shadow_splat_views(rnd.consts, [lvb, lvb], [rnd.num_den, rnd.num_den], [rnd.T, rnd.T])  # shared ws
+    cvb = rnd.vbs[("cam", 64, 64)]
+    im = rnd._images(64, 64)
+    with pytest.raises(gs3.Gs3Error):   # a light view in place of a camera buffer of the wrong size
+        gs3.gs3_render_views(ds, [cam[0]], [light[0]], rnd.consts, [rnd.T],
+                             [gs3.ViewBuffer(ds.n, 32, 32, 1 << 16)], [im])
+    gs3.gs3_render_views(ds, [cam[0]], [light[0]], rnd.consts, [out["T"]], [cvb], [im])
+    torch.cuda.synchronize()

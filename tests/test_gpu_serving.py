@@ -123,3 +123,42 @@ def test_shared_lights_equal_alone(env):
     print(f"shadow passes {srv.light_passes} for 24 requests, max |served - alone| = {worst:.2e}")
     assert srv.light_passes == 3
     assert worst <= 1e-4
+
+
+def test_batched_server_equals_alone(env):
+    """Batched launches: 24 requests arriving at once, mixed resolutions,
+    batches of up to 6 requests per launch sequence; every result equals the
+    request rendered alone, and fewer launch sequences than requests ran."""
+    gs3, serve, ds = env
+    reqs = serve.make_requests(24, qps=1e6, seed=9, resolutions=(96, 160, 256), light_res=256)
+    srv = serve.Server(ds, mem_cap_bytes=4 << 30, light_res=256, max_inflight=12, batch=6)
+    got = srv.run(reqs, keep_results=True)
+    rnd = gs3.Renderer(ds)
+    worst = 0.0
+    for req, res in zip(reqs, got):
+        alone = rnd.render(req.cam, req.light)["final"]
+        assert res.final.shape == alone.shape
+        worst = max(worst, float((res.final - alone).abs().max()))
+    print(f"batches {srv.batches} for 24 requests, max |served - alone| = {worst:.2e}")
+    assert srv.batches < 24
+    assert worst <= 1e-4
+
+
+def test_batched_server_at_serving_workload(env):
+    """The serving workload's scene and sizes (300,000 Gaussians, cameras
+    256^2 to 1024^2, light 1024^2), 16 requests at once in batches of up to
+    8, shared lights within a batch: each result equals the request alone."""
+    gs3, serve, _ = env
+    sc, _, _ = synth.scene_full()
+    ds = gs3.DeviceScene.from_host(sc)
+    reqs = serve.make_requests(16, qps=1e6, seed=8, n_lights=5)
+    srv = serve.Server(ds, mem_cap_bytes=24 << 30, max_inflight=16, batch=8, share_lights=True)
+    got = srv.run(reqs, keep_results=True)
+    rnd = gs3.Renderer(ds)
+    worst = 0.0
+    for req, res in zip(reqs, got):
+        alone = rnd.render(req.cam, req.light)["final"]
+        worst = max(worst, float((res.final - alone).abs().max()))
+    print(f"300K scene: batches {srv.batches}, shadow passes {srv.light_passes}, max |served - alone| = {worst:.2e}")
+    assert srv.batches < 16 and srv.light_passes <= 5
+    assert worst <= 1e-4
