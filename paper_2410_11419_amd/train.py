@@ -16,6 +16,10 @@ rho_s), 0.01 for the lobe axes and sharpness, decayed exponentially from
 the geometry and the MLPs take the rates of the Gaussian-splatting recipe
 the paper follows (positions 1.6e-4, log-scales 5e-3, rotations 1e-3,
 opacity logits 5e-2), features and MLP weights 1e-3, shading rotations 1e-3.
+A scene with the paper's shared-basis appearance trains rho_s and the basis
+weights at 0.01, the latent at 1e-3, and the basis frames and sigmas on the
+angular-Gaussian schedule; in the first stage (k = 0) the specular
+parameters get no gradient and no update.
 """
 from __future__ import annotations
 
@@ -31,9 +35,12 @@ STAGE1_ITERS = 15_000          # Lambertian-only iterations (Sec. 4.4)
 
 BASE_LR = {"mean": 1.6e-4, "log_scale": 5e-3, "rot": 1e-3, "opacity_logit": 5e-2, "shade_rot": 1e-3,
            "albedo": 1e-2, "lobe_axis": 1e-2, "lobe_log_sharp": 1e-2, "lobe_amp": 1e-2, "feat": 1e-3,
-           "mlp": 1e-3}
-LOBE_SHAPE = ("lobe_axis", "lobe_log_sharp")
-LOBES = ("lobe_axis", "lobe_log_sharp", "lobe_amp")
+           "mlp": 1e-3, "spec_albedo": 1e-2, "basis_weight": 1e-2, "latent": 1e-3, "basis_rot": 1e-2,
+           "basis_log_sigma": 1e-2}
+# angular-Gaussian shape parameters (the decayed schedule) and the specular
+# parameters frozen in the Lambertian stage
+LOBE_SHAPE = ("lobe_axis", "lobe_log_sharp", "basis_rot", "basis_log_sigma")
+LOBES = ("lobe_axis", "lobe_log_sharp", "lobe_amp", "spec_albedo", "basis_weight", "basis_rot", "basis_log_sigma")
 
 
 def lobe_lr(it: int) -> float:
@@ -76,7 +83,7 @@ class Trainer:
 
     @staticmethod
     def _tensors(t, phi, psi) -> List[Tuple[str, torch.Tensor]]:
-        out = [(nm, t[nm]) for nm in gs3.SCENE_FIELDS]
+        out = list(t.items())
         for m in (phi, psi):
             if m is not None:
                 for w, b in m:

@@ -306,3 +306,62 @@ def test_trainer_step_against_oracle(gs3):
         want, _, _ = O.adam_step(before[i].cpu().numpy(), g_gpu[i], 0.0, 0.0, 1, lr)
         assert float(np.abs(pa - want).max()) <= 1e-6 * max(1.0, float(np.abs(want).max())), nm
     assert tr.stage() == 2 and tr.it == 1
+
+
+def test_trainer_step_basis_appearance(gs3):
+    """One optimisation step of the full objective in the second stage for a
+    scene with the paper's shared-basis appearance: loss terms, every
+    gradient (scene, latent, shared basis, both MLPs) and one Adam update of
+    every tensor, against the oracle."""
+    from parity_resolve import resolve
+    from paper_2410_11419_amd import train
+    sc = synth.make_basis_scene(2000, 23, k=4, means="shell", mlps=True, log_scale_mu=(-3.4,) * 3)
+    rng = np.random.default_rng(23)
+    views = [(synth.make_view(rng.standard_normal(3), 4.0, 64, 56, 40.0),
+              synth.make_view(rng.standard_normal(3), 4.0, 96, 96, 40.0)) for _ in range(2)]
+    tgt = gs3.Renderer(gs3.DeviceScene.from_host(synth.perturb_scene(sc, seed=24)))
+    targets = [tgt.render(c, l)["final"].clone() for c, l in views]
+    ds = gs3.DeviceScene.from_host(sc)
+    tr = train.Trainer(ds, lanes=2, stage1_iters=0)
+    tr.check_capacity(views)
+    before = [p.detach().clone() for _, p in tr.params]
+    parts = tr.step([(c, l, t) for (c, l), t in zip(views, targets)]).cpu().numpy()
+    torch.cuda.synchronize()
+    g_gpu = [g.cpu().numpy() for _, g in tr.gtens]
+    p = O.scene_tensors(sc, requires_grad=True)
+    mlp = lambda L: [(torch.tensor(w, dtype=torch.float64, requires_grad=True),  # noqa: E731
+                      torch.tensor(b, dtype=torch.float64, requires_grad=True)) for w, b in L]
+    phi, psi = mlp(sc.phi.layers), mlp(sc.psi.layers)
+    total = 0.0
+    px_all = sum(3 * c.width * c.height for c, _ in views)
+    for j, ((cam, light), target) in enumerate(zip(views, targets)):
+        r = tr.rnds[j]
+        out = r._images(cam.width, cam.height)
+        npx = cam.width * cam.height
+        px = {k: out[k].cpu().numpy().reshape(-1, npx).squeeze(0) if out[k].dim() == 2 else
+              out[k].cpu().numpy().reshape(3, npx) for k in ("final", "S", "Sh", "R", "T_final")}
+        ref, _ = resolve(sc, cam, light, O.Consts(), phi, psi, r.T.cpu().numpy()[:sc.n], px, params=p)
+        f = ref["final"].reshape(3, cam.height, cam.width)
+        t = torch.as_tensor(target.cpu().numpy(), dtype=torch.float64)
+        l1 = (1 - O.LOSS_LAMBDA) * (f - t).abs().sum() / px_all
+        ds_ = O.LOSS_LAMBDA * (1 - O.ssim_map(f, t)).sum() / px_all
+        assert abs(parts[0, j] - float(l1)) <= 1e-5 * float(l1)
+        assert abs(parts[1, j] - float(ds_)) <= 1e-5 * float(ds_)
+        total = total + l1 + ds_
+    total.backward()
+    ref_g = [p[nm].grad for nm in ds.t] + [x.grad for m in (phi, psi) for pair in m for x in pair]
+    worst = 0.0
+    for (nm, _), a, rg in zip(tr.params, g_gpu, ref_g):
+        r_ = rg.numpy()
+        if r_.ndim == 2 and nm not in ("basis_rot", "basis_log_sigma") and r_.shape != a.shape:
+            r_ = r_.T
+        assert a.shape == r_.shape, (nm, a.shape, r_.shape)
+        scale = max(1e-12, float(np.abs(r_).max()))
+        e = float(np.abs(a - r_).max()) / scale
+        worst = max(worst, e)
+        assert e <= 1e-3, (nm, e)
+    print(f"[trainer basis] gradient error relative to each tensor's largest entry: {worst:.1e}")
+    for i, (nm, p_after) in enumerate(tr.params):
+        lr = train.lobe_lr(0) if nm in train.LOBE_SHAPE else tr.lr[nm]
+        want, _, _ = O.adam_step(before[i].cpu().numpy(), g_gpu[i], 0.0, 0.0, 1, lr)
+        assert float(np.abs(p_after.cpu().numpy() - want).max()) <= 1e-6 * max(1.0, float(np.abs(want).max())), nm
