@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--basis-train-steps", type=int, default=5, help="its timed fwd+bwd steps (0: skip)")
     ap.add_argument("--batch-views", type=int, default=0,
                     help="1: each frame preprocesses its light and camera views in one launch sequence")
+    ap.add_argument("--frame-group", type=int, default=1,
+                    help="frames per batched launch sequence in the timed region (1: one frame per sequence)")
     return ap.parse_args()
 
 
@@ -263,7 +265,7 @@ def train_step_bench(ds, sc, steps, warmup, profile=False, pairs=None, batch=4, 
         raise RuntimeError("a binning exceeded its pair capacity inside the timed train steps")
     per = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
     light0 = pairs[0][1]
-    loss_last = float(losses.sum().item())
+    loss_last = float(losses.cpu().sum())
     # algorithmic HBM bytes of a step: per view the forward frame and its
     # adjoint (pairs and hits counted on the step's first views)
     per_view = []
@@ -650,14 +652,37 @@ def main():
     log(f"timing {args.steps} frames, {args.inflight} in flight")
     evs = [{k: torch.cuda.Event(enable_timing=True) for k in ("f0", "den0", "den1", "num0", "num1", "f1")}
            for _ in range(args.steps)]
+    G = max(1, args.frame_group)
+    if G > 1:
+        if args.inflight % G:
+            raise SystemExit("--inflight must be a multiple of --frame-group")
+        for i in range(0, 2 * args.inflight, G):
+            fp.render_group(*zip(*[pairs[(i + j) % len(pairs)] for j in range(G)]))
+        torch.cuda.synchronize()
+        fp.i = 0
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        cam, light = pairs[i % len(pairs)]
-        e = evs[i]
-        st = fp.streams[i % args.inflight]
-        e["f0"].record(st)
-        fp.render(cam, light, events=e, overlap=False)
-        e["f1"].record(st)
+    if G > 1:
+        # groups of G frames, one batched launch sequence per stage each
+        for i in range(0, args.steps, G):
+            cams, lights = zip(*[pairs[(i + j) % len(pairs)] for j in range(G)])
+            st = fp.streams[fp.i % args.inflight]
+            for j in range(G):
+                if i + j < args.steps:
+                    evs[i + j]["f0"].record(st)
+            fp.render_group(list(cams), list(lights))
+            for j in range(G):
+                if i + j < args.steps:
+                    evs[i + j]["f1"].record(st)
+                    for name in ("den0", "den1", "num0", "num1"):
+                        evs[i + j][name].record(st)
+    else:
+        for i in range(args.steps):
+            cam, light = pairs[i % len(pairs)]
+            e = evs[i]
+            st = fp.streams[i % args.inflight]
+            e["f0"].record(st)
+            fp.render(cam, light, events=e, overlap=False)
+            e["f1"].record(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if fp.overflowed():
@@ -792,6 +817,7 @@ def main():
                              "phi_camera_splat": round(stage[6], 4),
                              "light_and_camera_preprocess_batched": round(pre_batched, 4)},
         "batch_views": bool(args.batch_views),
+        "frame_group": G,
         "work": {"pairs_light": int(p_l), "pairs_camera": int(p_c), "hits_light": int(h_l),
                  "hits_camera_blended": int(h_c)},
         "frame_hbm": {"algorithmic_bytes": int(fb), "achieved_GBs": round(frame_gbs, 1),

@@ -202,7 +202,7 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
                                   const gs3_mlp* psi, const float* gcol, float* dT, const GradDev& g, float* rows,
                                   float* partial, const gs3_grads* gr, hipStream_t st);
 // Weight gradients dW += sum_g dz[:, g] in[:, g]^T (and db += sum_g dz)
-// over problems of at most 64 x 64 (scratch rows [row][n]); dW has row
+// over problems of at most 128 x 128 (scratch rows [row][n]); dW has row
 // stride ldw, db may be NULL.
 struct WgSpec {
     int dz_row, in_row, O, J, ldw;

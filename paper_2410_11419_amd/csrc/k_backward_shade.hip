@@ -345,18 +345,22 @@ struct WgArgs {
     float* partial;                  // [chunks][total]
 };
 
-// One workgroup per (chunk of Gaussians, layer): C[O x J] = D[O x chunk] .
+// One workgroup per (chunk of Gaussians, problem): C[O x J] = D[O x chunk] .
 // H[J x chunk]^T on mfma_f32_16x16x4f32, the Gaussians being the
-// contraction. The chunk goes through LDS 32 Gaussians at a time (zero
-// padded to 64 x 64); wave w owns output rows 16w .. 16w + 15 and all four
-// 16-column blocks. A-operand lane l: D[16w + l % 16][4s + l / 16]; B-operand
-// lane l: H[16c + l % 16][4s + l / 16]; the result lane l holds rows
-// 16w + 4 (l / 16) + i, column 16c + l % 16. Bias sums come from the same D
-// tile.
+// contraction, for O, J <= R (R = 64 or 128). The chunk goes through LDS 32
+// Gaussians at a time (zero padded to R x R); wave w owns output rows
+// R/4 w .. R/4 w + R/4 - 1 (R/64 tiles of 16 rows) and all R/16 column
+// blocks. A-operand lane l: D[row0 + l % 16][4s + l / 16]; B-operand lane l:
+// H[16c + l % 16][4s + l / 16]; the result lane l holds rows
+// row0 + 4 (l / 16) + i, column 16c + l % 16. Bias sums come from the same
+// D tile.
+template <int R>
 __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     constexpr int KB = 32;
-    __shared__ float sD[64][KB + 1];
-    __shared__ float sH[64][KB + 1];
+    constexpr int RT = R / 64;        // row tiles per wave
+    constexpr int CB = R / 16;        // column blocks
+    __shared__ float sD[R][KB + 1];
+    __shared__ float sH[R][KB + 1];
     const WgProblem P = a.p[blockIdx.y];
     const int n = a.n;
     const int k0 = blockIdx.x * kWgChunk, k1 = min(n, k0 + kWgChunk);
@@ -364,12 +368,16 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     const float* H = a.rows + (size_t)P.in_row * n;
     const int t = threadIdx.x, lane = __lane_id();
     const int w = t >> 6, r16 = lane & 15, kq = lane >> 4;
-    floatx4 acc[4];
+    floatx4 acc[RT][CB];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[rt][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bacc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) bacc[rt] = 0.f;
     // the next tile's loads are in flight while the current one is multiplied
-    constexpr int kPer = 64 * KB / 256;
+    constexpr int kPer = R * KB / 256;
     float pd[kPer], ph[kPer];
     auto fetch = [&](int kb) {
 #pragma unroll
@@ -391,30 +399,41 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
         if (kb + KB < k1) fetch(kb + KB);
 #pragma unroll
         for (int s4 = 0; s4 < KB / 4; ++s4) {
-            const float av = sD[16 * w + r16][4 * s4 + kq];
-            bacc += av;
+            float av[RT];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int rt = 0; rt < RT; ++rt) {
+                av[rt] = sD[(R / 4) * w + 16 * rt + r16][4 * s4 + kq];
+                bacc[rt] += av[rt];
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
                 const float bv = sH[16 * c + r16][4 * s4 + kq];
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[c], 0, 0, 0);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], bv, acc[rt][c], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    // bias: lanes r16, r16 + 16, r16 + 32, r16 + 48 hold row 16w + r16
-    bacc += __shfl_xor(bacc, 16, 64);
-    bacc += __shfl_xor(bacc, 32, 64);
     float* part = a.partial + (size_t)blockIdx.x * a.total + P.off;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int j = 16 * c + r16;
+    for (int rt = 0; rt < RT; ++rt) {
+        const int row0 = (R / 4) * w + 16 * rt;
+        // bias: lanes r16, r16 + 16, r16 + 32, r16 + 48 hold row row0 + r16
+        float bs = bacc[rt];
+        bs += __shfl_xor(bs, 16, 64);
+        bs += __shfl_xor(bs, 32, 64);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = 16 * w + 4 * kq + i;
-            if (o < P.O && j < P.J) part[o * P.J + j] = acc[c][i];
+        for (int c = 0; c < CB; ++c) {
+            const int j = 16 * c + r16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = row0 + 4 * kq + i;
+                if (o < P.O && j < P.J) part[o * P.J + j] = acc[rt][c][i];
+            }
         }
+        if (kq == 0 && row0 + r16 < P.O) part[P.O * P.J + row0 + r16] = bs;
     }
-    if (kq == 0 && 16 * w + r16 < P.O) part[P.O * P.J + 16 * w + r16] = bacc;
 }
 
 // Sum of the per-chunk partials of 64 consecutive parameters per
@@ -675,9 +694,11 @@ hipError_t launch_wgrad(const WgSpec* specs, int count, const float* rows, int n
     WgArgs w;
     w.count = count;
     int off = 0;
+    int widest = 0;
     for (int i = 0; i < count; ++i) {
         const WgSpec& S = specs[i];
-        if (S.O > 64 || S.J > 64 || S.O <= 0 || S.J <= 0) return hipErrorInvalidValue;
+        if (S.O > 128 || S.J > 128 || S.O <= 0 || S.J <= 0) return hipErrorInvalidValue;
+        widest = max(widest, max(S.O, S.J));
         WgProblem& P = w.p[i];
         P.dz_row = S.dz_row; P.in_row = S.in_row; P.O = S.O; P.J = S.J; P.off = off;
         P.ldw = S.ldw; P.dW = S.dW; P.db = S.db;
@@ -688,7 +709,10 @@ hipError_t launch_wgrad(const WgSpec* specs, int count, const float* rows, int n
     w.n = n;
     w.partial = partial;
     const int chunks = (n + kWgChunk - 1) / kWgChunk;
-    hipLaunchKernelGGL(k_wgrad, dim3(chunks, w.count), dim3(256), 0, st, w);
+    if (widest > 64)
+        hipLaunchKernelGGL(k_wgrad<128>, dim3(chunks, w.count), dim3(256), 0, st, w);
+    else
+        hipLaunchKernelGGL(k_wgrad<64>, dim3(chunks, w.count), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 63) / 64), dim3(256), 0, st, w, chunks);
     return hipGetLastError();
 }

@@ -402,7 +402,9 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
         const float dx = pxc - k.g0.x, dy = pyc - k.g0.y;
         const float q = quad_q(dx, dy, k.g0.z, k.g0.w, k.g1.x);
         const bool hit = alive && q >= k.g1.y;
-        if (!__builtin_amdgcn_ballot_w64(hit)) return;
+        // the first sweep takes no branch on the ballot (its latency-bound
+        // walk loses more to the branch than the unused evaluation costs)
+        if (PASS == 1 && !__builtin_amdgcn_ballot_w64(hit)) return;
         const float beta = fast_exp2(q);
         const float ob = k.g1.z * beta;
         const float al = fminf(a.alpha_max, ob);
@@ -493,7 +495,7 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
             const float dx = pxc - sj.g0.x, dy = pyc - sj.g0.y;
             const float q = quad_q(dx, dy, sj.g0.z, sj.g0.w, sj.g1.x);
             const bool hit = alive && q >= sj.g1.y;
-            if (__builtin_amdgcn_ballot_w64(hit)) {
+            if (PASS == 0 || __builtin_amdgcn_ballot_w64(hit)) {
                 const float dn = s_dn[j];
                 const float beta = fast_exp2(q);
                 const float wv = hit ? dn * beta * tt : 0.f;

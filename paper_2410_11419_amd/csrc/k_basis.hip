@@ -883,6 +883,8 @@ static int basis_wgrad_specs(const gs3_grads* gr, bool phi, bool psi, WgSpec* sp
         const int H = kPsiBasisHidden;
         float* const* W = gr ? gr->psi_w : nullptr;
         float* const* B = gr ? gr->psi_b : nullptr;
+        // 64 x 64 problems (twice the workgroups of 128-wide ones, which
+        // measured slower for all that they read each row once)
         for (int o = 0; o < H; o += 64)
             add(kPsiB.dz1 + o, kPsiB.x, 64, kPsiBasisIn, kPsiBasisIn, ptr(W, 0, (size_t)o * kPsiBasisIn), ptr(B, 0, o));
         for (int o = 0; o < H; o += 64)
@@ -971,8 +973,7 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!phi && !psi) return hipSuccess;
-    // weight gradients: problems of at most 64 x 64, their partial sums
-    // after the per-wave basis sums
+    // weight gradients, their partial sums after the per-wave basis sums
     WgSpec spec[16];
     const int count = basis_wgrad_specs(gr, phi != nullptr, psi != nullptr, spec);
     return launch_wgrad(spec, count, rows, n, partial + basis_partial_floats(sc.k), st);

@@ -112,10 +112,10 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowBatch B) {
     auto occlude = [&](const Staged& k) {
         const float q = splat_q(k, pxc, pyc);
         const bool hit = alive && q >= k.g1.y;
-        if (__builtin_amdgcn_ballot_w64(hit)) {
-            const float f = 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
-            tt = hit ? tt * f : tt;
-        }
+        // no branch on the ballot: a latency-bound walk loses more to the
+        // branch than the unused evaluation costs
+        const float f = 1.f - fminf(a.alpha_max, k.g1.z * fast_exp2(q));
+        tt = hit ? tt * f : tt;
     };
     // the occluders of one set in order, each record read from LDS while
     // the previous one is being applied
@@ -182,10 +182,8 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowBatch B) {
             if (!__builtin_amdgcn_ballot_w64(alive)) return false;
             const float q = splat_q(sj, pxc, pyc);
             const bool hit = alive && q >= sj.g1.y;
-            if (__builtin_amdgcn_ballot_w64(hit)) {
-                const float v = row_sum16(hit ? fast_exp2(q) * tt : 0.f);
-                if ((lane & 15) == 15) s_sum[lane >> 4][j] = v;
-            }
+            const float v = row_sum16(hit ? fast_exp2(q) * tt : 0.f);
+            if ((lane & 15) == 15) s_sum[lane >> 4][j] = v;
             return true;
         };
         // leads whose L lies before the ring: walk older entries from global

@@ -1040,5 +1040,20 @@ class FramePipeline:
         with torch.cuda.stream(self.streams[k]):
             return self.renderers[k].render(cam, light, check=False, overlap=overlap, events=events)
 
+    def render_group(self, cams: Sequence, lights: Sequence) -> list:
+        """Several frames as one batch (``render_batched``): one launch
+        sequence per stage for all of them, on the stream of the group's
+        first renderer. Groups take consecutive renderers, so a renderer's
+        buffers are reused only after `depth` frames, on the same stream."""
+        g = len(cams)
+        k0 = self.i % len(self.renderers)
+        if k0 + g > len(self.renderers):
+            k0 = 0
+            self.i = 0
+        self.i += g
+        rnds = self.renderers[k0:k0 + g]
+        with torch.cuda.stream(self.streams[k0]):
+            return render_batched(rnds, cams, lights)
+
     def overflowed(self) -> bool:
         return any(r.overflowed() for r in self.renderers)
