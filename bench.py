@@ -68,6 +68,8 @@ def parse():
                     help="offered loads as fractions of the plain renderer's saturation rate")
     ap.add_argument("--profile-train", action="store_true",
                     help="only run two fwd+bwd steps (for rocprofv3), no JSON")
+    ap.add_argument("--profile-basis", action="store_true",
+                    help="profiling mode: a few frames and two train steps of the shared-basis appearance scene")
     ap.add_argument("--profile-fluffy", action="store_true",
                     help="only run two fwd+bwd steps of the dense scene (for rocprofv3), no JSON")
     ap.add_argument("--lanes", type=int, default=4, help="concurrent lanes of the dense scene's step")
@@ -598,6 +600,11 @@ def main():
     if args.profile_train:
         with torch.cuda.stream(torch.cuda.Stream()):
             train_step_bench(ds, sc, 0, 1, profile=True)
+        return
+    if args.profile_basis:
+        with torch.cuda.stream(torch.cuda.Stream()):
+            basis_bench(8, 2)
+        print("profiled the shared-basis appearance: 8 frames and 2 fwd+bwd steps after warm-up")
         return
     rnd = gs3.Renderer(ds)
     # warm-up: sizes every view buffer (host sync allowed here)

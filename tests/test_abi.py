@@ -196,3 +196,45 @@ def test_preprocess_views_checks():
     assert b"does not match" in gs3._lib.gs3_last_error()
     modes_bad = (C.c_int32 * 2)(0, 5)
     assert f(C.byref(scene), views, modes_bad, 2, C.byref(k), vbs2, None) == gs3.GS3_INVALID_ARG
+
+
+def test_view_array_and_appearance_checks():
+    """The view-array calls and the appearance model are validated on the
+    host before anything reaches the device."""
+    from paper_2410_11419_amd import gs3
+    k = gs3.default_consts()
+    L = gs3._lib
+    vb = gs3.gs3_viewbuf(C.c_void_p(256), 1 << 30, 100, 64, 64, 1000)
+    arr = (C.c_void_p * 1)(C.c_void_p(512))
+    vbs = (gs3.gs3_viewbuf * 1)(vb)
+    # no views, NULL arrays
+    assert L.gs3_shadow_splat_views(C.byref(k), vbs, 0, arr, arr, None) == gs3.GS3_INVALID_ARG
+    assert L.gs3_shadow_splat_views(C.byref(k), None, 1, arr, arr, None) == gs3.GS3_INVALID_ARG
+    # two views sharing one workspace
+    vbs2 = (gs3.gs3_viewbuf * 2)(vb, vb)
+    arr2 = (C.c_void_p * 2)(C.c_void_p(512), C.c_void_p(1024))
+    assert L.gs3_shadow_splat_views(C.byref(k), vbs2, 2, arr2, arr2, None) == gs3.GS3_INVALID_ARG
+    assert b"share workspace memory" in L.gs3_last_error()
+    # render views: a scene with an unknown appearance model is refused
+    sc = gs3.gs3_scene()
+    sc.n, sc.k, sc.appearance = 100, 2, 7
+    for name in ("mean", "log_scale", "rot", "opacity_logit", "shade_rot", "albedo"):
+        setattr(sc, name, C.c_void_p(4096))
+    cam = gs3.make_view(type("V", (), dict(eye=(0.0, 0.0, 4.0), target=(0.0, 0.0, 0.0), width=64, height=64,
+                                            fov=0.7, projection="perspective", ortho_width=0.0))())
+    cams = (gs3.gs3_view * 1)(cam)
+    ims = (gs3.gs3_images * 1)(gs3.gs3_images())
+    assert L.gs3_render_views(C.byref(sc), cams, cams, 1, C.byref(k), arr, None, None, vbs, ims,
+                              None) == gs3.GS3_INVALID_ARG
+    assert b"appearance" in L.gs3_last_error()
+    # the basis model needs its own pointers
+    sc.appearance = gs3.GS3_APPEARANCE_BASIS
+    assert L.gs3_render_views(C.byref(sc), cams, cams, 1, C.byref(k), arr, None, None, vbs, ims,
+                              None) == gs3.GS3_INVALID_ARG
+    assert b"basis" in L.gs3_last_error()
+    # backward workspace per appearance: the basis model keeps more per Gaussian
+    a, b = C.c_size_t(), C.c_size_t()
+    assert L.gs3_backward_workspace_size_for(gs3.GS3_APPEARANCE_LOBES, 300000, 1024, 1024, C.byref(a)) == 0
+    assert L.gs3_backward_workspace_size_for(gs3.GS3_APPEARANCE_BASIS, 300000, 1024, 1024, C.byref(b)) == 0
+    assert b.value > a.value > 300000 * 811 * 4
+    assert L.gs3_backward_workspace_size_for(5, 10, 8, 8, C.byref(a)) == gs3.GS3_INVALID_ARG
