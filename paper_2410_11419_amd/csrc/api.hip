@@ -57,6 +57,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     const int64_t longest = l.table_len > n + 1 ? l.table_len : n + 1;
     l.scan_sums = (longest + kSortItems - 1) / kSortItems + 1;
     if (l.scan_sums < kRadixBins) l.scan_sums = kRadixBins;   // also the radix passes' digit totals
+    if (l.scan_sums < (n + 255) / 256) l.scan_sums = (n + 255) / 256;   // 256-splat count sums
     {
         int tile_bits = 0, id_bits = 1;
         while ((int64_t(1) << tile_bits) < l.n_tiles) ++tile_bits;

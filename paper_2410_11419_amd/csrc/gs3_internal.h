@@ -16,6 +16,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortItems = 4096;   // items per radix (pair sort) / scan workgroup
 constexpr int kSortItemsN = 1024;  // items per radix workgroup of the depth sort of the N splats
+constexpr int64_t kEmitScanMaxN = 1 << 19;  // views of at most this many splats form pair offsets inside the emission
 constexpr int kFeat = 16;          // per-Gaussian MLP feature size
 constexpr int kHidden = 64;        // MLP hidden width
 constexpr int kMaxLobes = 16;

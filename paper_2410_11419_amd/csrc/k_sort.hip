@@ -81,6 +81,9 @@ static void batch_add(Batch<D>& b, const D& d, uint32_t blocks) {
 // Exclusive scan of len u32 counts per view; with gather given, element i of
 // the scanned sequence is in[gather[i]]. The grand total goes to the view
 // header (required pairs, clamped count, overflow flag) and to tail_out.
+// With per256 (gather given), k_scan_reduce alone runs, over 1024 elements
+// per workgroup: sums[c] = the sum over elements [256 c, 256 c + 256)
+// (k_emit forms the offsets from these).
 struct ScanDesc {
     const uint32_t* in;
     const uint32_t* gather;
@@ -91,6 +94,7 @@ struct ScanDesc {
     int64_t len;
     int64_t capacity;
     int64_t nb;
+    int32_t per256;
 };
 
 __global__ __launch_bounds__(256) void k_scan_reduce(Batch<ScanDesc> B) {
@@ -98,6 +102,22 @@ __global__ __launch_bounds__(256) void k_scan_reduce(Batch<ScanDesc> B) {
     const int v = batch_view(B.blk0, B.nv, blockIdx.x);
     const ScanDesc& D = B.d[v];
     const uint32_t blk = blockIdx.x - B.blk0[v];
+    if (D.per256) {
+        // 1024 elements per workgroup, 4 per thread: each wave sums one
+        // 256-element chunk
+        const int64_t c = (int64_t)blk * 4 + (threadIdx.x >> 6);
+        const int64_t i0 = c * 256 + (threadIdx.x & 63) * 4;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            acc += (i < D.len) ? D.in[D.gather[i]] : 0u;
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
+        if ((threadIdx.x & 63) == 0 && c * 256 < D.len) D.sums[c] = acc;
+        return;
+    }
     const int64_t base = (int64_t)blk * kSortItems + threadIdx.x * 16;
     uint32_t acc = 0;
 #pragma unroll
@@ -271,9 +291,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Batch<RadixDesc> B) {
     for (int i = tid; i < 4 * kRadixBins; i += 256) (&s_cnt[0][0])[i] = 0u;
     {
         const int d = tid;   // 256 threads, 256 digits
+        const uint32_t total = D.totals[d];
+        const uint32_t earlier = D.table[d * nblk + blk];
         uint32_t all;
-        const uint32_t dstart = block_excl_scan_256(D.totals[d], &all, s_wave);
-        s_gstart[d] = dstart + D.table[d * nblk + blk];
+        const uint32_t dstart = block_excl_scan_256(total, &all, s_wave);
+        s_gstart[d] = dstart + earlier;
     }
     __syncthreads();
     uint32_t key[R], val[R], rank[R];
@@ -368,9 +390,16 @@ static hipError_t radix_pass(const Batch<RadixDesc>& B, hipStream_t st) {
 // also reset its per-tile ranges to (INT_MAX, 0): the range pass (or the
 // last tile pass) fills in the tiles that have pairs, and k_tile_order turns
 // the untouched ones into empty (0, 0) ranges.
+// offs == nullptr: the offsets are formed here from the 256-element chunk
+// sums of the depth-ordered counts (sums, nb256 of them; k_scan_reduce with
+// per256), and workgroup 0 writes the view header.
 struct EmitDesc {
     const uint32_t* ids;
     const uint32_t* offs;
+    const uint32_t* cnt;
+    const uint32_t* sums;
+    ViewHeader* hdr;
+    int32_t nb256;
     const int4* ext;
     uint32_t* pk;
     uint32_t* pv;
@@ -383,10 +412,23 @@ struct EmitDesc {
     int32_t nblk;
 };
 
+// sum over the workgroup of one u64 per thread (blockDim.x == 256)
+__device__ inline unsigned long long block_sum_u64_256(unsigned long long x, unsigned long long* s_red) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) x += __shfl_xor(x, d, 64);
+    if (lane_id() == 0) s_red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    const unsigned long long t = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    __syncthreads();
+    return t;
+}
+
 __global__ __launch_bounds__(256) void k_emit(Batch<EmitDesc> B) {
     __shared__ uint32_t s_lo[257];
     __shared__ int s_x0[256], s_y0[256], s_w[256];
     __shared__ uint32_t s_id[256];
+    __shared__ uint32_t s_wave[4];
+    __shared__ unsigned long long s_red[4];
     const int v = batch_view(B.blk0, B.nv, blockIdx.x);
     const EmitDesc& D = B.d[v];
     const int blk = (int)(blockIdx.x - B.blk0[v]);
@@ -395,11 +437,44 @@ __global__ __launch_bounds__(256) void k_emit(Batch<EmitDesc> B) {
     for (int t = blk * 256 + tid; t < D.n_tiles; t += D.nblk * 256) D.ranges[t] = make_int2(INT_MAX, 0);
     const int s0 = blk * 256;
     const int m = min(256, n - s0);
-    const uint32_t base = D.offs[s0];
+    unsigned long long base64;
+    if (D.offs) {
+        base64 = D.offs[s0];
+    } else {
+        // the offset of the workgroup's first pair: the chunk sums before
+        // it (chunk c holds depth positions [256 c, 256 c + 256), so this
+        // workgroup is chunk blk); workgroup 0 also forms the grand total
+        unsigned long long pre = 0ull, all = 0ull;
+        for (int c = tid; c < D.nb256; c += 256) {
+            const uint32_t x = D.sums[c];
+            pre += c < blk ? x : 0u;
+            all += x;
+        }
+        base64 = block_sum_u64_256(pre, s_red);
+        if (blk == 0) {
+            const unsigned long long total = block_sum_u64_256(all, s_red);
+            if (tid == 0) {
+                ViewHeader* hdr = D.hdr;
+                hdr->required_pairs = total;
+                hdr->n_pairs = (uint32_t)(total < D.capacity ? total : D.capacity);
+                hdr->overflow = total > D.capacity ? 1u : 0u;
+            }
+        }
+    }
+    // offsets within the workgroup (these fit in 32 bits: at most 256
+    // splats, each over at most 2^24 tiles)
+    uint32_t lo_own = 0u;
+    if (!D.offs) {
+        const uint32_t c = tid < m ? D.cnt[D.ids[s0 + tid]] : 0u;
+        uint32_t tot;
+        lo_own = block_excl_scan_256(c, &tot, s_wave);
+        if (tid == 0) s_lo[m > 0 ? m : 0] = tot;
+    }
+    const uint32_t base = (uint32_t)base64;
     if (tid < m) {
         const uint32_t g = D.ids[s0 + tid];
         s_id[tid] = g;
-        s_lo[tid] = D.offs[s0 + tid] - base;
+        s_lo[tid] = D.offs ? D.offs[s0 + tid] - base : lo_own;
         const int4 e = D.ext[g];
         int x0 = 0, y0 = 0, w = 1;
         if (e.z > 0 && e.w > 0) {
@@ -412,10 +487,10 @@ __global__ __launch_bounds__(256) void k_emit(Batch<EmitDesc> B) {
         }
         s_x0[tid] = x0; s_y0[tid] = y0; s_w[tid] = w;
     }
-    if (tid == 0) s_lo[m > 0 ? m : 0] = D.offs[s0 + (m > 0 ? m : 0)] - base;
+    if (D.offs && tid == 0) s_lo[m > 0 ? m : 0] = D.offs[s0 + (m > 0 ? m : 0)] - base;
     __syncthreads();
     const uint32_t total = s_lo[m > 0 ? m : 0];
-    if (base >= D.capacity) return;
+    if (base64 >= D.capacity) return;
     const uint32_t room = D.capacity - base;              // slots left in the pair arrays
     const uint32_t lim = total < room ? total : room;
     for (uint32_t j = tid; j < lim; j += 256) {
@@ -580,6 +655,12 @@ static int tile_passes_of(const Layout& L) {
 // order), so the sorted result lands where the view's readers expect it.
 static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
     hipError_t e;
+    // Views of up to kEmitScanMaxN splats take the short form of step 2: the
+    // pair offsets are formed inside k_emit from 256-splat sums (two launches
+    // instead of four; every k_emit workgroup reads all nb256 sums).
+    bool short_form = true;
+    for (int v = 0; v < nv; ++v)
+        if (Ls[v]->n > kEmitScanMaxN) short_form = false;
     // 1. depth order: 4 stable 8-bit passes over the 32-bit depth keys, 1024
     //    keys per workgroup (N is small next to the pair count: more, shorter
     //    workgroups)
@@ -605,7 +686,23 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
         if ((e = radix_pass<kSortItemsN, true>(B, st)) != hipSuccess) return e;
     }
     // 2. pair offsets in depth order (the counts gathered through the order)
-    {
+    if (short_form) {
+        Batch<ScanDesc> B;
+        for (int v = 0; v < nv; ++v) {
+            const Layout& L = *Ls[v];
+            void* ws = wss[v];
+            ScanDesc d{};
+            d.in = at<uint32_t>(ws, L.cnt);
+            d.gather = at<uint32_t>(ws, L.vals_a);
+            d.sums = at<uint32_t>(ws, L.sums);
+            d.len = L.n;
+            d.per256 = 1;
+            d.nb = (L.n + 1023) / 1024;
+            batch_add(B, d, (uint32_t)d.nb);
+        }
+        const uint32_t grid = B.blk0[B.nv];
+        if (grid > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(256), 0, st, B);
+    } else {
         Batch<ScanDesc> B;
         for (int v = 0; v < nv; ++v) {
             const Layout& L = *Ls[v];
@@ -648,7 +745,11 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
             const bool start_b = !packed && (passes[0] & 1) == 1;
             EmitDesc d{};
             d.ids = at<uint32_t>(ws, L.vals_a);
-            d.offs = at<uint32_t>(ws, L.offs);
+            d.offs = short_form ? nullptr : at<uint32_t>(ws, L.offs);
+            d.cnt = at<uint32_t>(ws, L.cnt);
+            d.sums = at<uint32_t>(ws, L.sums);
+            d.hdr = at<ViewHeader>(ws, L.hdr);
+            d.nb256 = (int32_t)((L.n + 255) / 256);
             d.ext = at<int4>(ws, L.ext);
             d.pk = at<uint32_t>(ws, start_b ? L.pk_b : L.pk_a);
             d.pv = at<uint32_t>(ws, start_b ? L.pv_b : L.pv_a);

@@ -69,6 +69,10 @@ def _bin_gpu(g, ix, iy, rx, ry, depth, W, H, capacity):
     dict(n=1, W=64, H=64, seed=5),
     # 21 id bits + 12 tile bits do not pack into one word: the two-array sort
     dict(n=(1 << 20) + 5, W=1024, H=768, seed=6, max_r=3),
+    # the largest view whose pair offsets are formed inside the emission
+    # (2^19 splats), and one splat more (separate scan launches)
+    dict(n=128 * 4096, W=512, H=384, seed=7, max_r=5),
+    dict(n=128 * 4096 + 1, W=512, H=384, seed=8, max_r=5),
 ])
 def test_binning_bit_exact(gs3, case):
     rng = np.random.default_rng(case["seed"])
