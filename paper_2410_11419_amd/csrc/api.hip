@@ -158,16 +158,13 @@ static int status_target(const gs3_viewbuf* vb, int64_t** dev) {
     return GS3_OK;
 }
 
-// After a binning has been enqueued: the next generation, and the kernel
-// that reports it.
-static int post_status(const gs3_viewbuf* vb, const Layout& L, int64_t* dev, hipStream_t st) {
-    if (!dev) return GS3_OK;
+// Before a binning is enqueued: the next generation of the view's status
+// block (word 0, written by the host) and where the binning reports it.
+static StatusReq next_status(const gs3_viewbuf* vb, int64_t* dev) {
     volatile int64_t* gen = vb->status;
     const long long g = (long long)gen[0] + 1;
     gen[0] = g;
-    StatusReq r{&L, vb->ws, g, dev + 1};
-    GS3_CHECK_HIP(launch_write_status(&r, 1, st));
-    return GS3_OK;
+    return StatusReq{g, dev + 1};
 }
 
 static int check_consts(const gs3_consts* k) {
@@ -366,8 +363,10 @@ int gs3_bin(const int32_t* ix, const int32_t* iy, const int32_t* rx, const int32
     int64_t* sdev;
     if ((st = status_target(vb, &sdev)) != GS3_OK) return st;
     GS3_CHECK_HIP(launch_extent_keys(ix, iy, rx, ry, depth, L, vb->ws, (hipStream_t)stream));
-    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
-    return post_status(vb, L, sdev, (hipStream_t)stream);
+    StatusReq r{};
+    if (sdev) r = next_status(vb, sdev);
+    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream, sdev ? &r : nullptr));
+    return GS3_OK;
 }
 
 int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream) {
@@ -376,8 +375,10 @@ int gs3_sort(const gs3_viewbuf* vb, gs3_stream_t stream) {
     if ((st = check_vb(vb, &L)) != GS3_OK) return st;
     int64_t* sdev;
     if ((st = status_target(vb, &sdev)) != GS3_OK) return st;
-    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream));
-    return post_status(vb, L, sdev, (hipStream_t)stream);
+    StatusReq r{};
+    if (sdev) r = next_status(vb, sdev);
+    GS3_CHECK_HIP(launch_bin(L, vb->ws, (hipStream_t)stream, sdev ? &r : nullptr));
+    return GS3_OK;
 }
 
 int gs3_preprocess(const gs3_scene* scene, const gs3_view* view, const gs3_consts* consts, int32_t depth_mode,
@@ -420,16 +421,14 @@ int gs3_preprocess_views(const gs3_scene* scene, const gs3_view* views, const in
     }
     const hipStream_t s = (hipStream_t)stream;
     GS3_CHECK_HIP(launch_project_batch(scene_dev(scene), vp.data(), *consts, Lp.data(), ws.data(), n_views, s));
-    GS3_CHECK_HIP(launch_bin_batch(Lp.data(), ws.data(), n_views, s));
-    std::vector<StatusReq> req;
+    std::vector<StatusReq> req(n_views);
+    std::vector<const StatusReq*> reqp(n_views, nullptr);
     for (int v = 0; v < n_views; ++v) {
         if (!sdev[v]) continue;
-        volatile int64_t* gen = vbs[v].status;
-        const long long g = (long long)gen[0] + 1;
-        gen[0] = g;
-        req.push_back(StatusReq{Lp[v], vbs[v].ws, g, sdev[v] + 1});
+        req[v] = next_status(&vbs[v], sdev[v]);
+        reqp[v] = &req[v];
     }
-    if (!req.empty()) GS3_CHECK_HIP(launch_write_status(req.data(), (int)req.size(), s));
+    GS3_CHECK_HIP(launch_bin_batch(Lp.data(), ws.data(), n_views, s, reqp.data()));
     return GS3_OK;
 }
 

@@ -106,9 +106,18 @@ hipError_t launch_project(const SceneDev& sc, const ViewParams& vp, const gs3_co
 hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_t* rx,
                               const int32_t* ry, const float* depth, const Layout& L,
                               void* ws, hipStream_t st);
-hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st);
-// One launch sequence bins all nv views (any nv; chunks of kMaxBatch).
-hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st);
+// A binning outcome to report into a host-pinned status block.
+struct StatusReq {
+    long long generation;
+    int64_t* status_dev;   // device address of the block's word 1
+};
+// status (optional): where to report the outcome (the last kernel of the
+// binning writes it).
+hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st, const StatusReq* status = nullptr);
+// One launch sequence bins all nv views (any nv; chunks of kMaxBatch);
+// status (optional) holds one entry per view, nullptr for none.
+hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st,
+                            const StatusReq* const* status = nullptr);
 // Projection of one scene into nv views (ViewParams vps[v], workspace
 // wss[v] with layout Ls[v]); chunks of kMaxBatch views per launch.
 hipError_t launch_project_batch(const SceneDev& sc, const ViewParams* vps, const gs3_consts& k,
@@ -216,14 +225,6 @@ hipError_t launch_project_bwd(const SceneDev& sc, const ViewParams& cam, const V
                               const gs3_consts& k, const float* gcam, const float* glight, const GradDev& g,
                               hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
-// A binning outcome to report into a host-pinned status block.
-struct StatusReq {
-    const Layout* L;
-    const void* ws;
-    long long generation;
-    int64_t* status_dev;   // device address of the block's word 1
-};
-hipError_t launch_write_status(const StatusReq* req, int count, hipStream_t st);
 int64_t l1_chunks(int64_t count);
 hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                           float* grad, double* partial, hipStream_t st);

@@ -548,11 +548,17 @@ __global__ __launch_bounds__(256) void k_ranges(Batch<RangesDesc> B) {
 // first (lengths bucketed by 8), so the few long tiles start early instead
 // of forming the tail of the splatting kernels. Only the schedule depends on
 // the order, not any result. One workgroup per view.
+// With status given, the workgroup also reports the binning's outcome into
+// the caller's host-pinned status word (see gs3_viewbuf.status):
+// (generation mod 2^24) << 40 | overflow << 39 | required pairs, one 64-bit
+// store, made visible to the host at once.
 struct OrderDesc {
     int2* ranges;
     const ViewHeader* hdr;
     uint32_t* order;
     int32_t n_tiles;
+    unsigned long long* status;
+    long long generation;
 };
 
 __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
@@ -567,6 +573,14 @@ __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
     // overflowed binning become empty ranges; each thread later reads back
     // only the tiles it wrote here
     const bool overflow = D.hdr->overflow != 0u;
+    if (tid == 0 && D.status) {
+        const unsigned long long req = D.hdr->required_pairs;
+        const unsigned long long req39 = req < (1ull << 39) ? req : (1ull << 39) - 1ull;
+        const unsigned long long word = ((unsigned long long)(D.generation & 0xFFFFFF) << 40) |
+                                        ((unsigned long long)(overflow ? 1u : 0u) << 39) | req39;
+        __hip_atomic_store(D.status, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __threadfence_system();
+    }
     for (int t = tid; t < n_tiles; t += 1024) {
         const int2 r = ranges[t];
         if (overflow || r.x >= r.y) ranges[t] = make_int2(0, 0);
@@ -597,42 +611,6 @@ __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
     for (int t = tid; t < n_tiles; t += 1024) D.order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
 }
 
-// The binning's outcome into the caller's host-pinned status word (see
-// gs3_viewbuf.status): (generation mod 2^24) << 40 | overflow << 39 |
-// required pairs, one 64-bit store, made visible to the host at once. One
-// wave per view.
-struct StatusDesc {
-    const ViewHeader* hdr;
-    unsigned long long* status;
-    long long generation;
-};
-
-__global__ __launch_bounds__(64) void k_write_status(Batch<StatusDesc> B) {
-    if (threadIdx.x != 0) return;
-    const StatusDesc& D = B.d[blockIdx.x];
-    const unsigned long long req = D.hdr->required_pairs;
-    const unsigned long long req39 = req < (1ull << 39) ? req : (1ull << 39) - 1ull;
-    const unsigned long long v = ((unsigned long long)(D.generation & 0xFFFFFF) << 40) |
-                                 ((unsigned long long)(D.hdr->overflow ? 1u : 0u) << 39) | req39;
-    __hip_atomic_store(D.status, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __threadfence_system();
-}
-
-hipError_t launch_write_status(const StatusReq* req, int count, hipStream_t st) {
-    for (int c0 = 0; c0 < count; c0 += kMaxBatch) {
-        Batch<StatusDesc> B;
-        for (int i = c0; i < count && i < c0 + kMaxBatch; ++i) {
-            StatusDesc d;
-            d.hdr = at<ViewHeader>(req[i].ws, req[i].L->hdr);
-            d.status = reinterpret_cast<unsigned long long*>(req[i].status_dev);
-            d.generation = req[i].generation;
-            batch_add(B, d, 1u);
-        }
-        hipLaunchKernelGGL(k_write_status, dim3((unsigned)B.nv), dim3(64), 0, st, B);
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, value, count);
@@ -653,7 +631,8 @@ static int tile_passes_of(const Layout& L) {
 // without run their tile passes as two sub-batches; within one, every view
 // takes the largest pass count (a pass over digits that are all 0 keeps the
 // order), so the sorted result lands where the view's readers expect it.
-static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
+static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, const StatusReq* const* status, int nv,
+                            hipStream_t st) {
     hipError_t e;
     // Views of up to kEmitScanMaxN splats take the short form of step 2: the
     // pair offsets are formed inside k_emit from 256-splat sums (two launches
@@ -684,6 +663,13 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
             batch_add(B, d, (uint32_t)L.nblk_n);
         }
         if ((e = radix_pass<kSortItemsN, true>(B, st)) != hipSuccess) return e;
+    }
+    // tile pass counts of the two sub-batches
+    int passes[2] = {0, 0};   // [unpacked, packed]
+    for (int v = 0; v < nv; ++v) {
+        const int p = tile_passes_of(*Ls[v]);
+        const int g = Ls[v]->id_bits > 0 ? 1 : 0;
+        if (p > passes[g]) passes[g] = p;
     }
     // 2. pair offsets in depth order (the counts gathered through the order)
     if (short_form) {
@@ -723,13 +709,6 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
         if (grid > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(256), 0, st, B);
         hipLaunchKernelGGL(k_scan_top, dim3((unsigned)nv), dim3(256), 0, st, B);
         if (grid > 0) hipLaunchKernelGGL(k_scan_down, dim3(grid), dim3(256), 0, st, B);
-    }
-    // tile pass counts of the two sub-batches
-    int passes[2] = {0, 0};   // [unpacked, packed]
-    for (int v = 0; v < nv; ++v) {
-        const int p = tile_passes_of(*Ls[v]);
-        const int g = Ls[v]->id_bits > 0 ? 1 : 0;
-        if (p > passes[g]) passes[g] = p;
     }
     // 3. emit (tile, id) pairs, packed into one word when tile and id bits
     //    fit in 32 (only the keys then move through the tile passes). Packed
@@ -830,6 +809,9 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
             d.hdr = at<ViewHeader>(ws, L.hdr);
             d.order = at<uint32_t>(ws, L.order);
             d.n_tiles = (int32_t)L.n_tiles;
+            const StatusReq* r = status ? status[v] : nullptr;
+            d.status = r ? reinterpret_cast<unsigned long long*>(r->status_dev) : nullptr;
+            d.generation = r ? r->generation : 0;
             batch_add(B, d, 1u);
         }
         hipLaunchKernelGGL(k_tile_order, dim3((unsigned)nv), dim3(1024), 0, st, B);
@@ -837,18 +819,19 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, int nv, h
     return hipGetLastError();
 }
 
-hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st) {
+hipError_t launch_bin_batch(const Layout* const* Ls, void* const* wss, int nv, hipStream_t st,
+                            const StatusReq* const* status) {
     for (int c0 = 0; c0 < nv; c0 += kMaxBatch) {
         const int m = nv - c0 < kMaxBatch ? nv - c0 : kMaxBatch;
-        const hipError_t e = bin_chunk(Ls + c0, wss + c0, m, st);
+        const hipError_t e = bin_chunk(Ls + c0, wss + c0, status ? status + c0 : nullptr, m, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st) {
+hipError_t launch_bin(const Layout& L, void* ws, hipStream_t st, const StatusReq* status) {
     const Layout* Lp = &L;
-    return launch_bin_batch(&Lp, &ws, 1, st);
+    return launch_bin_batch(&Lp, &ws, 1, st, &status);
 }
 
 }  // namespace gs3
