@@ -7,15 +7,15 @@ namespace gs3 {
 
 constexpr float kLog2eF = 1.4426950408889634f;
 
-// Rows of the per-Gaussian MLP scratch ([row][n] floats): the layer inputs
-// and the pre-activation gradients the weight gradients are formed from.
+// Rows of the per-Gaussian MLP scratch ([row][n] floats): each MLP's input
+// and the gradient of its output pre-activation. The weight-gradient kernel
+// recomputes the hidden activations and the hidden pre-activation gradients
+// from these on the matrix cores, so the scratch stays small (43 rows).
 struct MlpRows {
-    int x, h1, h2, h3, dz1, dz2, dz3, dz4, size;
+    int x, dout, size;
 };
 __host__ __device__ constexpr MlpRows mlp_rows(int base, int n_in, int n_out) {
-    return MlpRows{base,           base + n_in,           base + n_in + 64,      base + n_in + 128,
-                   base + n_in + 192, base + n_in + 256, base + n_in + 320,     base + n_in + 384,
-                   n_in + 384 + n_out};
+    return MlpRows{base, base + n_in, n_in + n_out};
 }
 constexpr MlpRows kPhiRows = mlp_rows(0, kPhiIn, 1);
 constexpr MlpRows kPsiRows = mlp_rows(kPhiRows.size, kPsiIn, 3);
@@ -38,19 +38,8 @@ struct ShadeBwdArgs {
     const float* gcol;   // [7][n] dL/d{c.rgb, T', r.rgb}
     float* dT;           // [n] = dL/dT
     GradDev g;           // += scene gradients (shading part)
-    float* rows;         // [kMlpRows][n] MLP scratch
+    float* rows;         // [kMlpRows][n] MLP scratch (inputs, output-layer gradients)
 };
-
-// Store a D-layout 64-vector of one Gaussian into scratch rows row0 ..
-// row0 + 63: lane (g, q) writes rows row0 + 16 m + 4 q + i. The per-lane
-// base is formed once; the row offsets (16 m + i) n are wave-uniform.
-__device__ inline void store_rows(float* rows, int row0, int q, int g, int n, const floatx4 v[4]) {
-    float* p = rows + (size_t)(row0 + 4 * q) * n + g;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) p[(size_t)(16 * m + i) * n] = v[m][i];
-}
 
 __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
     __shared__ __align__(16) float sm[kShadeBwdSmem];
@@ -170,14 +159,11 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
             };
             mlp_hidden_all<kPhiKR>(sm, kPhiS, lane, xin, h);
             const float tp = mlp_out(sm, kPhiS, lane, h[2], 0);
-            // the layer inputs go to the scratch now; the adjoint needs only
-            // the ReLU patterns of h (fewer live registers)
+            // the input goes to the scratch now; the adjoint needs only the
+            // ReLU patterns of h (fewer live registers)
             if (valid) {
                 float* R = a.rows;
                 for (int k = q; k < kPhiIn; k += 4) R[(size_t)(kPhiRows.x + k) * n + g] = xin(k);
-                store_rows(R, kPhiRows.h1, q, g, n, h[0]);
-                store_rows(R, kPhiRows.h2, q, g, n, h[1]);
-                store_rows(R, kPhiRows.h3, q, g, n, h[2]);
             }
             const uint32_t hmask[3] = {relu_mask(h[0]), relu_mask(h[1]), relu_mask(h[2])};
             const float d4 = dtp * tp * (1.f - tp);
@@ -187,17 +173,13 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) dh3[m][i] = sm[kPhiS.w4 + 16 * m + 4 * q + i] * d4;
             floatx4 dx[2];
-            auto store_dz = [&](int l, const floatx4 dz[4]) {
-                if (!valid) return;
-                store_rows(a.rows, l == 0 ? kPhiRows.dz1 : (l == 1 ? kPhiRows.dz2 : kPhiRows.dz3), q, g, n, dz);
-            };
-            mlp_backward_masked(sm, kPhiT, lane, hmask, dh3, store_dz, dx);
+            mlp_backward_masked(sm, kPhiT, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 phi_dx0[i] = dx[0][i];
                 phi_dx1[i] = dx[1][i];
             }
-            if (valid && q == 0) a.rows[(size_t)kPhiRows.dz4 * n + g] = d4;
+            if (valid && q == 0) a.rows[(size_t)kPhiRows.dout * n + g] = d4;
             // dL/dT = dx row 0 (tile 0, quarter 0, i = 0)
             dTg = __shfl(phi_dx0[0], l16, 64);
         }
@@ -225,9 +207,6 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
             if (valid) {
                 float* R = a.rows;
                 for (int k = q; k < kPsiIn; k += 4) R[(size_t)(kPsiRows.x + k) * n + g] = xin(k);
-                store_rows(R, kPsiRows.h1, q, g, n, h[0]);
-                store_rows(R, kPsiRows.h2, q, g, n, h[1]);
-                store_rows(R, kPsiRows.h3, q, g, n, h[2]);
             }
             const uint32_t hmask[3] = {relu_mask(h[0]), relu_mask(h[1]), relu_mask(h[2])};
             const float d40 = dr0 * r0 * (1.f - r0), d41 = dr1 * r1 * (1.f - r1), d42 = dr2 * r2 * (1.f - r2);
@@ -241,11 +220,7 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                                      fmaf(sm[kPsiS.w4 + 64 + r], d41, sm[kPsiS.w4 + 128 + r] * d42));
                 }
             floatx4 dx[2];
-            auto store_dz = [&](int l, const floatx4 dz[4]) {
-                if (!valid) return;
-                store_rows(a.rows, l == 0 ? kPsiRows.dz1 : (l == 1 ? kPsiRows.dz2 : kPsiRows.dz3), q, g, n, dz);
-            };
-            mlp_backward_masked(sm, kPsiT, lane, hmask, dh3, store_dz, dx);
+            mlp_backward_masked(sm, kPsiT, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) psi_dx0[i] = dx[0][i];
             // rows 16..21 = w_i, w_o live in tile 1, quarters 0 and 1
@@ -256,9 +231,9 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
             if (valid) {
                 float* R = a.rows;
                 if (q == 0) {
-                    R[(size_t)kPsiRows.dz4 * n + g] = d40;
-                    R[(size_t)(kPsiRows.dz4 + 1) * n + g] = d41;
-                    R[(size_t)(kPsiRows.dz4 + 2) * n + g] = d42;
+                    R[(size_t)kPsiRows.dout * n + g] = d40;
+                    R[(size_t)(kPsiRows.dout + 1) * n + g] = d41;
+                    R[(size_t)(kPsiRows.dout + 2) * n + g] = d42;
                 }
             }
         }
@@ -476,6 +451,202 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(WgArgs a, int chunks) {
 }
 
 // --------------------------------------------------------------------------
+// Weight gradients of Phi and Psi from the small scratch: one workgroup per
+// (run of Gaussians, MLP), 8 waves of 16 Gaussians per step. Each wave
+// recomputes its Gaussians' hidden activations with the forward's split
+// half-precision products (the same routine as the shading adjoint, so the
+// same ReLU patterns) and the hidden pre-activation gradients from the
+// output-layer gradient on float32 products; the workgroup stages each
+// layer's gradient and input for its 128 Gaussians in LDS and adds
+// dW_l += dZ_l IN_l^T (Gaussians as the contraction) on
+// mfma_f32_16x16x4f32. The per-workgroup sums go to the partial buffer in
+// the layout k_wgrad_reduce sums (per layer: O x J weights, then O biases).
+
+constexpr int kWgGroup = 128;          // Gaussians per step (8 waves x 16)
+constexpr int kWgLd = kWgGroup + 4;    // staging row stride (floats)
+
+struct MlpWgArgs {
+    MlpArgs m[2];                      // Phi, Psi
+    int mlp[2];                        // blockIdx.y -> 0 (Phi) or 1 (Psi)
+    int off[2];                        // each MLP's first parameter in the flat partial vector
+    const float* rows;                 // [kMlpRows][n]
+    int n;
+    int total;                         // flat parameter count (partial row length)
+    float* partial;                    // [gridDim.x][total]
+};
+
+constexpr int mlp_wgrad_smem(int kr, int n_out) {
+    return mlp_smem(0, kr, n_out).size + mlp_tsmem(0).size + 2 * 64 * kWgLd;
+}
+constexpr int kMlpWgSmem = mlp_wgrad_smem(kPhiKR, 1) > mlp_wgrad_smem(kPsiKR, 3) ? mlp_wgrad_smem(kPhiKR, 1)
+                                                                                     : mlp_wgrad_smem(kPsiKR, 3);
+static_assert(kMlpWgSmem * 4 <= 160 * 1024, "weight-gradient LDS exceeds 160 KiB");
+static_assert(kWgLd % 4 == 0 && kWgGroup == 128, "staging rows are read as 16-byte vectors, 32 Gaussians per lane group");
+
+// acc += DZ[row0 .. +15][0 .. 127] . IN[col0 .. +15][0 .. 127]^T; rows at
+// or past o_rows read as 0; bias (when given) += the lane's DZ values.
+__device__ inline void wg_tile(const float* dz, const float* in, int row0, int col0, int o_rows, int lane,
+                               floatx4* acc, float* bias) {
+    // lane group kq takes the Gaussians 32 kq .. 32 kq + 31, four per
+    // 16-byte read
+    const int r16 = lane & 15, kq = lane >> 4;
+    const bool row_ok = row0 + r16 < o_rows;
+    const float4* pa = reinterpret_cast<const float4*>(dz + (row0 + r16) * kWgLd + 32 * kq);
+    const float4* pb = reinterpret_cast<const float4*>(in + (col0 + r16) * kWgLd + 32 * kq);
+    float bs = 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float4 av = row_ok ? pa[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 bv = pb[u];
+        bs += (av.x + av.y) + (av.z + av.w);
+        *acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, *acc, 0, 0, 0);
+        *acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, *acc, 0, 0, 0);
+        *acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, *acc, 0, 0, 0);
+        *acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, *acc, 0, 0, 0);
+    }
+    if (bias) *bias += bs;
+}
+
+// The workgroup's sums of one layer (O x J weights at P, then O biases)
+// into its partial row; lane layout of wg_tile's result.
+__device__ inline void wg_store(float* P, int O, int J, int row0, int col0, int lane, const floatx4& acc,
+                                const float* bias) {
+    const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = row0 + 4 * kq + i, j = col0 + r16;
+        if (o < O && j < J) P[o * J + j] = acc[i];
+    }
+    if (bias) {
+        float b = *bias;
+        b += __shfl_xor(b, 16, 64);
+        b += __shfl_xor(b, 32, 64);
+        if (kq == 0 && row0 + r16 < O) P[O * J + row0 + r16] = b;
+    }
+}
+
+template <int KR, int N_IN, int N_OUT>
+__device__ inline void mlp_wgrad(float* sm, const MlpArgs& mw, const float* rows, int n, MlpRows R, float* part) {
+    constexpr MlpSmem S = mlp_smem(0, KR, N_OUT);
+    constexpr MlpTSmem T = mlp_tsmem(S.size);
+    constexpr int kDz = S.size + T.size, kIn = kDz + 64 * kWgLd;
+    static_assert(N_IN <= 32 && N_OUT <= 16, "input rows are staged as two 16-row tiles, outputs as one");
+    load_mlp(sm, S, KR, N_IN, N_OUT, mw);
+    load_mlp_t(sm, T, N_IN, mw);
+    __syncthreads();
+    float* sdz = sm + kDz;
+    float* sin_ = sm + kIn;
+    const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4, l16 = lane & 15;
+    const int col = 16 * w + l16;   // the lane's Gaussian in the staging tiles
+    // accumulators: layer 0 one tile (rows 16 (w/2), input cols 16 (w%2));
+    // layers 1, 2 tiles w and w + 8 of the 4 x 4 grid; layer 3 (waves 0-3)
+    // output rows 0..15, hidden cols 16 w
+    floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1[2], a2[2], a3 = {0.f, 0.f, 0.f, 0.f};
+    float b0 = 0.f, b1[2] = {0.f, 0.f}, b2[2] = {0.f, 0.f}, b3 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) a1[t] = a2[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto put = [&](float* tile, const floatx4 v[4]) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tile[(16 * m + 4 * q + i) * kWgLd + col] = v[m][i];
+    };
+    for (int base = blockIdx.x * kWgGroup; base < n; base += gridDim.x * kWgGroup) {
+        asm volatile("" ::: "memory");
+        const int g_raw = base + col;
+        const bool valid = g_raw < n;
+        const int g = valid ? g_raw : n - 1;
+        auto xin = [&](int k) -> float { return k < N_IN ? rows[(size_t)(R.x + k) * n + g] : 0.f; };
+        floatx4 h[3][4];
+        mlp_hidden_all<KR>(sm, S, lane, xin, h);
+        // output-layer gradient (0 for the padding Gaussians), and dL/dh3 as
+        // the shading adjoint forms it
+        float d4[N_OUT];
+#pragma unroll
+        for (int o = 0; o < N_OUT; ++o) d4[o] = valid ? rows[(size_t)(R.dout + o) * n + g] : 0.f;
+        floatx4 dh3[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * m + 4 * q + i;
+                float v = sm[S.w4 + (N_OUT - 1) * 64 + r] * d4[N_OUT - 1];
+#pragma unroll
+                for (int o = N_OUT - 2; o >= 0; --o) v = fmaf(sm[S.w4 + o * 64 + r], d4[o], v);
+                dh3[m][i] = v;
+            }
+        // layer 3: dW4 = d4 h3^T
+        put(sin_, h[2]);
+        if (q == 0) {
+#pragma unroll
+            for (int o = 0; o < N_OUT; ++o) sdz[o * kWgLd + col] = d4[o];
+        }
+        __syncthreads();
+        if (w < 4) wg_tile(sdz, sin_, 0, 16 * w, N_OUT, lane, &a3, w == 0 ? &b3 : nullptr);
+        __syncthreads();
+        // hidden layers, last to first: dz_l gated by the forward's ReLU
+        // pattern, staged with the layer's input
+        floatx4 dz[4], d[4];
+        auto gate = [&](const floatx4 hl[4], const floatx4 in[4]) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dz[m][i] = hl[m][i] > 0.f ? in[m][i] : 0.f;
+        };
+        gate(h[2], dh3);
+        put(sdz, dz);
+        put(sin_, h[1]);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int tt = w + 8 * t;
+            wg_tile(sdz, sin_, 16 * (tt >> 2), 16 * (tt & 3), 64, lane, &a2[t], (tt & 3) == 0 ? &b2[t] : nullptr);
+        }
+        __syncthreads();
+        mlp_back_layer<4>(sm, T.t3, lane, dz, d);
+        gate(h[1], d);
+        put(sdz, dz);
+        put(sin_, h[0]);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int tt = w + 8 * t;
+            wg_tile(sdz, sin_, 16 * (tt >> 2), 16 * (tt & 3), 64, lane, &a1[t], (tt & 3) == 0 ? &b1[t] : nullptr);
+        }
+        __syncthreads();
+        mlp_back_layer<4>(sm, T.t2, lane, dz, d);
+        gate(h[0], d);
+        put(sdz, dz);
+        // the input rows 0..31 (0 past N_IN)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sin_[(4 * t + q) * kWgLd + col] = xin(4 * t + q);
+        __syncthreads();
+        wg_tile(sdz, sin_, 16 * (w >> 1), 16 * (w & 1), 64, lane, &a0, (w & 1) == 0 ? &b0 : nullptr);
+        __syncthreads();
+    }
+    // partial sums, per layer: O x J weights then O biases
+    constexpr int o1 = 64 * N_IN + 64, o2 = o1 + 64 * 64 + 64, o3 = o2 + 64 * 64 + 64;
+    wg_store(part, 64, N_IN, 16 * (w >> 1), 16 * (w & 1), lane, a0, (w & 1) == 0 ? &b0 : nullptr);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int tt = w + 8 * t;
+        wg_store(part + o1, 64, 64, 16 * (tt >> 2), 16 * (tt & 3), lane, a1[t], (tt & 3) == 0 ? &b1[t] : nullptr);
+        wg_store(part + o2, 64, 64, 16 * (tt >> 2), 16 * (tt & 3), lane, a2[t], (tt & 3) == 0 ? &b2[t] : nullptr);
+    }
+    if (w < 4) wg_store(part + o3, N_OUT, 64, 0, 16 * w, lane, a3, w == 0 ? &b3 : nullptr);
+}
+
+__global__ __launch_bounds__(512) void k_mlp_wgrad(MlpWgArgs a) {
+    __shared__ __align__(16) float sm[kMlpWgSmem];
+    const int which = a.mlp[blockIdx.y];
+    float* part = a.partial + (size_t)blockIdx.x * a.total + a.off[which];
+    if (which == 0)
+        mlp_wgrad<kPhiKR, kPhiIn, 1>(sm, a.m[0], a.rows, a.n, kPhiRows, part);
+    else
+        mlp_wgrad<kPsiKR, kPsiIn, 3>(sm, a.m[1], a.rows, a.n, kPsiRows, part);
+}
+
+// --------------------------------------------------------------------------
 // Projection adjoint (both views), in double like the forward projection.
 
 struct ProjBwdArgs {
@@ -661,25 +832,45 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(512), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!phi && !psi)) return e;
-    // weight gradients
-    WgSpec spec[8];
-    int count = 0;
-    auto add = [&](int dz_row, int in_row, int O, int J, float* dW, float* db) {
-        spec[count++] = WgSpec{dz_row, in_row, O, J, J, dW, db};
+    // weight gradients: per-workgroup partial sums, then one fixed-order
+    // reduction into the gradient buffers
+    MlpWgArgs wa;
+    WgArgs ra;
+    int ny = 0, off = 0;
+    ra.count = 0;
+    auto add_mlp = [&](int which, const gs3_mlp* m, int n_in, int n_out, float* const* gw, float* const* gb) {
+        for (int i = 0; i < 4; ++i) {
+            wa.m[which].w[i] = m->w[i];
+            wa.m[which].b[i] = m->b[i];
+        }
+        wa.mlp[ny++] = which;
+        wa.off[which] = off;
+        const int O[4] = {64, 64, 64, n_out}, J[4] = {n_in, 64, 64, 64};
+        for (int l = 0; l < 4; ++l) {
+            WgProblem& P = ra.p[ra.count++];
+            P.dz_row = P.in_row = 0;
+            P.O = O[l];
+            P.J = J[l];
+            P.off = off;
+            P.ldw = J[l];
+            P.dW = gw[l];
+            P.db = gb[l];
+            off += O[l] * J[l] + O[l];
+        }
     };
-    if (phi) {
-        add(kPhiRows.dz1, kPhiRows.x, 64, kPhiIn, gr->phi_w[0], gr->phi_b[0]);
-        add(kPhiRows.dz2, kPhiRows.h1, 64, 64, gr->phi_w[1], gr->phi_b[1]);
-        add(kPhiRows.dz3, kPhiRows.h2, 64, 64, gr->phi_w[2], gr->phi_b[2]);
-        add(kPhiRows.dz4, kPhiRows.h3, 1, 64, gr->phi_w[3], gr->phi_b[3]);
-    }
-    if (psi) {
-        add(kPsiRows.dz1, kPsiRows.x, 64, kPsiIn, gr->psi_w[0], gr->psi_b[0]);
-        add(kPsiRows.dz2, kPsiRows.h1, 64, 64, gr->psi_w[1], gr->psi_b[1]);
-        add(kPsiRows.dz3, kPsiRows.h2, 64, 64, gr->psi_w[2], gr->psi_b[2]);
-        add(kPsiRows.dz4, kPsiRows.h3, 3, 64, gr->psi_w[3], gr->psi_b[3]);
-    }
-    return launch_wgrad(spec, count, rows, sc.n, partial, st);
+    if (phi) add_mlp(0, phi, kPhiIn, 1, gr->phi_w, gr->phi_b);
+    if (psi) add_mlp(1, psi, kPsiIn, 3, gr->psi_w, gr->psi_b);
+    ra.total = wa.total = off;
+    ra.rows = wa.rows = rows;
+    ra.n = wa.n = sc.n;
+    ra.partial = wa.partial = partial;
+    // one run of Gaussians per workgroup and MLP; at most as many runs as
+    // the partial buffer has rows (one per kWgChunk Gaussians)
+    const int chunks = (sc.n + kWgChunk - 1) / kWgChunk;
+    const int runs = chunks < 128 ? chunks : 128;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(runs, ny), dim3(512), 0, st, wa);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((ra.total + 63) / 64), dim3(256), 0, st, ra, runs);
+    return hipGetLastError();
 }
 
 int wgrad_partial_floats(const WgSpec* specs, int count) {
