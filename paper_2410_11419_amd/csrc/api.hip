@@ -49,6 +49,12 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.tiles_x = (width + kTile - 1) / kTile;
     l.tiles_y = (height + kTile - 1) / kTile;
     l.n_tiles = (int64_t)l.tiles_x * l.tiles_y;
+    {
+        const int64_t groups = (int64_t)((l.tiles_x + kGroupTiles - 1) / kGroupTiles) *
+                               ((l.tiles_y + kGroupTiles - 1) / kGroupTiles);
+        l.n_slots = groups <= kMaxGroups ? 8 * ((groups + 7) / 8) * kGroupTiles * kGroupTiles : l.n_tiles;
+        if (l.n_slots < l.n_tiles) l.n_slots = l.n_tiles;
+    }
     l.capacity = capacity;
     l.nblk_n = (n + kSortItemsN - 1) / kSortItemsN;
     l.nblk_p = (capacity + kSortItems - 1) / kSortItems;
@@ -93,7 +99,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.table = take(sizeof(uint32_t) * l.table_len);
     l.sums = take(sizeof(uint32_t) * l.scan_sums);
     l.ranges = take(sizeof(int2) * l.n_tiles);
-    l.order = take(sizeof(uint32_t) * l.n_tiles);
+    l.order = take(sizeof(uint32_t) * l.n_slots);
     l.total = off;
     *L = l;
     return true;

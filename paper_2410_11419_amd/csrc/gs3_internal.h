@@ -21,6 +21,12 @@ constexpr int kFeat = 16;          // per-Gaussian MLP feature size
 constexpr int kHidden = 64;        // MLP hidden width
 constexpr int kMaxLobes = 16;
 constexpr int kMaxBatch = 8;       // views per batched launch (longer batches run in chunks)
+// Tile-walking kernels take their tiles from a launch order of n_slots
+// entries: slot 8 k + x runs on XCD x (workgroups are dealt to the XCDs
+// round-robin), and kNoTile marks an empty slot.
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+constexpr int kGroupTiles = 8;     // tiles per side of a group kept on one XCD
+constexpr int kMaxGroups = 1024;   // above this many groups the order is LPT alone
 
 // Device-side counters at the head of every view workspace.
 struct ViewHeader {
@@ -42,6 +48,7 @@ struct Layout {
     int64_t n = 0;
     int32_t width = 0, height = 0, tiles_x = 0, tiles_y = 0;
     int64_t n_tiles = 0;
+    int64_t n_slots = 0;   // entries of the tile launch order (>= n_tiles)
     int64_t capacity = 0;
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
     int32_t id_bits = 0;   // > 0: pairs are packed (tile << id_bits) | id while sorting

@@ -71,7 +71,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderBwdArgs a) {
     __shared__ uint32_t s_mask[256];
     __shared__ uint32_t s_id[256];
     __shared__ float s_g[kCamGrads][256];
-    const int tile = (int)a.order[blockIdx.x];
+    const uint32_t ot = a.order[blockIdx.x];
+    if (ot == kNoTile) return;
+    const int tile = (int)ot;
     const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
@@ -226,6 +228,7 @@ struct ShadowBwdArgs {
     const int4* drec;      // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
+    int n_slots;           // entries of order (some may be kNoTile)
     float alpha_max, bias;
     const float* T;        // [n] forward shadow values
     const float* num_den;  // [2][n]
@@ -353,8 +356,10 @@ __global__ __launch_bounds__(64) void k_shadow_bwd(ShadowBwdArgs a) {
     // memory operation that the next load would wait for)
     __shared__ float s_acc[PASS == 1 ? 6 : 1][2 * kBwdBatch];
     int slot, qd;
-    if (!xcd_tile_quadrant(a.n_tiles, &slot, &qd)) return;
-    const int tile = (int)a.order[slot];
+    if (!xcd_tile_quadrant(a.n_slots, &slot, &qd)) return;
+    const uint32_t ot = a.order[slot];
+    if (ot == kNoTile) return;
+    const int tile = (int)ot;
     const int2 rg = a.ranges[tile];
     const int s = rg.x, e = rg.y;
     const int lane = __lane_id();
@@ -610,7 +615,7 @@ hipError_t launch_render_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.dF = dF;
     a.gsplat = gsplat;
     a.gcol = gcol;
-    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)L.n_tiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)L.n_slots), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -632,6 +637,7 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     a.height = L.height;
     a.tiles_x = L.tiles_x;
     a.n_tiles = (int)L.n_tiles;
+    a.n_slots = (int)L.n_slots;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.T = T;
@@ -646,8 +652,8 @@ hipError_t launch_shadow_bwd(const gs3_consts& k, const Layout& L, const void* w
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(gray), 0u, (int64_t)L.width * L.height, st);
     if (e != hipSuccess) return e;
     if (L.n_tiles == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_shadow_bwd<0>, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(k_shadow_bwd<1>, dim3(quadrant_grid(L.n_tiles)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_bwd<0>, dim3(quadrant_grid(L.n_slots)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_shadow_bwd<1>, dim3(quadrant_grid(L.n_slots)), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

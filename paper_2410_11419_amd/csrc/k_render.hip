@@ -23,6 +23,7 @@ struct RenderArgs {
     const ViewHeader* hdr;
     uint32_t n;
     int width, height, tiles_x, n_tiles;
+    int n_slots;             // entries of order (some may be kNoTile)
     float alpha_max, t_min;
     gs3_images out;
 };
@@ -38,12 +39,14 @@ template <bool ONE>
 __global__ __launch_bounds__(256) void k_render(RenderBatch B) {
     // ONE: a single view (static argument offsets)
     const RenderArgs a = ONE ? B.v[0] : B.v[blockIdx.y];
-    if ((int)blockIdx.x >= a.n_tiles) return;
+    if ((int)blockIdx.x >= a.n_slots) return;
+    const uint32_t ot = a.order[blockIdx.x];
+    if (ot == kNoTile) return;
     __shared__ Staged s_rec[256];
     __shared__ float4 s_c0[256];
     __shared__ float4 s_c1[256];
     __shared__ uint32_t s_mask[256];
-    const int tile = (int)a.order[blockIdx.x];
+    const int tile = (int)ot;
     const int tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
@@ -154,6 +157,7 @@ static RenderArgs render_args(const gs3_consts& k, const Layout& L, const void* 
     a.height = L.height;
     a.tiles_x = L.tiles_x;
     a.n_tiles = (int)L.n_tiles;
+    a.n_slots = (int)L.n_slots;
     a.alpha_max = k.alpha_max;
     a.t_min = k.t_min;
     a.out = out;
@@ -168,7 +172,7 @@ hipError_t launch_render_batch(const gs3_consts& k, const Layout* const* Ls, voi
         int64_t gx = 0;
         for (int i = 0; i < m; ++i) {
             B.v[i] = render_args(k, *Ls[v0 + i], wss[v0 + i], outs[v0 + i]);
-            gx = Ls[v0 + i]->n_tiles > gx ? Ls[v0 + i]->n_tiles : gx;
+            gx = Ls[v0 + i]->n_slots > gx ? Ls[v0 + i]->n_slots : gx;
         }
         if (m == 1)
             hipLaunchKernelGGL(k_render<true>, dim3((unsigned)gx), dim3(256), 0, st, B);

@@ -47,6 +47,7 @@ struct ShadowArgs {
     const int4* drec;   // den_ranges per Gaussian (written by the projection)
     uint32_t n;
     int width, height, tiles_x, n_tiles;
+    int n_slots;             // entries of order (some may be kNoTile)
     float alpha_max, bias;
     float* num;
     float* den;
@@ -90,8 +91,10 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowBatch B) {
     __shared__ uint32_t s_id[2 * kShadowBatch];
     __shared__ float s_sum[4][kShadowBatch];     // lead sums of the current batch, per 16-lane row
     int slot, qd;
-    if (!xcd_tile_quadrant(a.n_tiles, &slot, &qd)) return;
-    const int tile = (int)a.order[slot];
+    if (!xcd_tile_quadrant(a.n_slots, &slot, &qd)) return;
+    const uint32_t ot = a.order[slot];
+    if (ot == kNoTile) return;
+    const int tile = (int)ot;
     const int2 rg = a.ranges[tile];
     const int s = rg.x, e = rg.y;
     if (e <= s) return;
@@ -463,6 +466,7 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, void* ws, fl
     a.height = L.height;
     a.tiles_x = L.tiles_x;
     a.n_tiles = (int)L.n_tiles;
+    a.n_slots = (int)L.n_slots;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
     a.num = at<float>(ws, L.num);   // the view's accumulator
@@ -510,8 +514,8 @@ hipError_t launch_shadow_num_batch(const gs3_consts& k, const Layout* const* Ls,
             const Layout& L = *Ls[v0 + i];
             B.v[i] = shadow_args(k, L, wss[v0 + i], num_den[v0 + i]);
             // a view without Gaussians has no list to walk
-            if (L.n == 0) B.v[i].n_tiles = 0;
-            const unsigned g = L.n == 0 ? 0u : quadrant_grid(L.n_tiles);
+            if (L.n == 0) B.v[i].n_slots = 0;
+            const unsigned g = L.n == 0 ? 0u : quadrant_grid(L.n_slots);
             gx = g > gx ? g : gx;
         }
         if (gx == 0) return hipSuccess;

@@ -544,10 +544,19 @@ __global__ __launch_bounds__(256) void k_ranges(Batch<RangesDesc> B) {
     }
 }
 
-// Final per-tile ranges, then the launch order of the tiles: longest list
-// first (lengths bucketed by 8), so the few long tiles start early instead
-// of forming the tail of the splatting kernels. Only the schedule depends on
-// the order, not any result. One workgroup per view.
+// Final per-tile ranges, then the launch order of the tiles. Only the
+// schedule depends on the order, not any result. One workgroup per view.
+// The order has n_slots entries; slot 8 k + x goes to XCD x (workgroups
+// are dealt to the XCDs round-robin):
+// - tiles are grouped in 8x8 blocks; the groups, sorted by their pairs,
+//   are dealt to the eight XCDs in snake order (0..7, 7..0, ...), so each
+//   XCD gets whole neighbourhoods (their splats' records stay in its L2)
+//   and about an eighth of the work;
+// - within an XCD the tiles go longest list first (lengths bucketed by
+//   32), so its few long tiles start early instead of forming the tail;
+// - slots an XCD does not fill hold kNoTile.
+// Views with more than kMaxGroups groups take the longest-first order
+// alone (lengths bucketed by 8) in slots 0 .. n_tiles - 1.
 // With status given, the workgroup also reports the binning's outcome into
 // the caller's host-pinned status word (see gs3_viewbuf.status):
 // (generation mod 2^24) << 40 | overflow << 39 | required pairs, one 64-bit
@@ -557,6 +566,8 @@ struct OrderDesc {
     const ViewHeader* hdr;
     uint32_t* order;
     int32_t n_tiles;
+    int32_t tiles_x;
+    int32_t n_slots;
     unsigned long long* status;
     long long generation;
 };
@@ -564,14 +575,16 @@ struct OrderDesc {
 __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
     __shared__ uint32_t hist[1024];
     __shared__ uint32_t s_wave[16];
+    __shared__ unsigned long long s_key[kMaxGroups];
+    __shared__ uint8_t s_xcd[kMaxGroups];
+    __shared__ uint32_t s_xstart[8];
     const OrderDesc& D = B.d[blockIdx.x];
     int2* ranges = D.ranges;
-    const int n_tiles = D.n_tiles;
+    const int n_tiles = D.n_tiles, tiles_x = D.tiles_x;
     const int tid = threadIdx.x;
-    hist[tid] = 0u;
+    const int lane = __lane_id(), w = tid >> 6;
     // tiles without pairs (still (INT_MAX, 0)) and every tile of an
-    // overflowed binning become empty ranges; each thread later reads back
-    // only the tiles it wrote here
+    // overflowed binning become empty ranges
     const bool overflow = D.hdr->overflow != 0u;
     if (tid == 0 && D.status) {
         const unsigned long long req = D.hdr->required_pairs;
@@ -585,18 +598,56 @@ __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
         const int2 r = ranges[t];
         if (overflow || r.x >= r.y) ranges[t] = make_int2(0, 0);
     }
+    for (int i = tid; i < D.n_slots; i += 1024) D.order[i] = kNoTile;
+    hist[tid] = 0u;
     __syncthreads();
-    auto bucket = [&](int t) -> int {
+    auto len_of = [&](int t) -> uint32_t {
         const int2 r = ranges[t];
-        const int len = r.y - r.x;
-        return 1023 - min(1023, max(len, 0) >> 3);
+        return (uint32_t)max(r.y - r.x, 0);
+    };
+    const int ngx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
+    const int tiles_y = n_tiles / tiles_x;
+    const int n_groups = ngx * ((tiles_y + kGroupTiles - 1) / kGroupTiles);
+    const bool grouped = n_groups <= kMaxGroups;
+    auto group_of = [&](int t) { return (t / tiles_x / kGroupTiles) * ngx + (t % tiles_x) / kGroupTiles; };
+    if (grouped) {
+        // pairs per group, then the groups sorted by them (descending; a
+        // bitonic sort of (~pairs, group) keys) and dealt out in snake order
+        for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&hist[group_of(t)], len_of(t));
+        __syncthreads();
+        s_key[tid] = tid < n_groups ? ((unsigned long long)(~hist[tid]) << 32) | (unsigned)tid : ~0ull;
+        __syncthreads();
+        int span = 2;   // the sort's size: the power of two at or above n_groups
+        while (span < n_groups) span <<= 1;
+        for (int k = 2; k <= span; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int o = tid ^ j;
+                if (tid < span && o > tid) {
+                    const unsigned long long a = s_key[tid], b = s_key[o];
+                    if ((a > b) == ((tid & k) == 0)) {
+                        s_key[tid] = b;
+                        s_key[o] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        if (tid < n_groups) {
+            const int round = tid >> 3, pos = tid & 7;
+            s_xcd[(uint32_t)s_key[tid]] = (uint8_t)((round & 1) ? 7 - pos : pos);
+        }
+        hist[tid] = 0u;
+        __syncthreads();
+    }
+    auto bucket = [&](int t) -> int {
+        const uint32_t len = len_of(t);
+        return grouped ? (int)s_xcd[group_of(t)] * 128 + 127 - (int)min(127u, len >> 5)
+                       : 1023 - (int)min(1023u, len >> 3);
     };
     for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&hist[bucket(t)], 1u);
     __syncthreads();
     // exclusive scan of the 1024 bucket counts
     const uint32_t v = hist[tid];
     uint32_t x = v;
-    const int lane = __lane_id(), w = tid >> 6;
     for (int d = 1; d < 64; d <<= 1) {
         const uint32_t y = __shfl_up(x, d, 64);
         if (lane >= d) x += y;
@@ -607,8 +658,14 @@ __global__ __launch_bounds__(1024) void k_tile_order(Batch<OrderDesc> B) {
     for (int i = 0; i < w; ++i) pre += s_wave[i];
     __syncthreads();
     hist[tid] = pre + x - v;
+    if ((tid & 127) == 0) s_xstart[tid >> 7] = pre + x - v;   // first position of XCD tid / 128
     __syncthreads();
-    for (int t = tid; t < n_tiles; t += 1024) D.order[atomicAdd(&hist[bucket(t)], 1u)] = (uint32_t)t;
+    for (int t = tid; t < n_tiles; t += 1024) {
+        const int b = bucket(t);
+        const uint32_t pos = atomicAdd(&hist[b], 1u);
+        const uint32_t slot = grouped ? 8u * (pos - s_xstart[b >> 7]) + (uint32_t)(b >> 7) : pos;
+        D.order[slot] = (uint32_t)t;
+    }
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st) {
@@ -809,6 +866,8 @@ static hipError_t bin_chunk(const Layout* const* Ls, void* const* wss, const Sta
             d.hdr = at<ViewHeader>(ws, L.hdr);
             d.order = at<uint32_t>(ws, L.order);
             d.n_tiles = (int32_t)L.n_tiles;
+            d.tiles_x = L.tiles_x;
+            d.n_slots = (int32_t)L.n_slots;
             const StatusReq* r = status ? status[v] : nullptr;
             d.status = r ? reinterpret_cast<unsigned long long*>(r->status_dev) : nullptr;
             d.generation = r ? r->generation : 0;
