@@ -299,9 +299,12 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// MLP weight gradients: dW_l = sum_g dz_l[:, g] in_l[:, g]^T and
-// db_l = sum_g dz_l[:, g] over all Gaussians, as split-K partial sums (one
-// workgroup per (chunk of Gaussians, layer)) and one reduction.
+// MLP weight gradients from stored rows: dW_l = sum_g dz_l[:, g] in_l[:, g]^T
+// and db_l = sum_g dz_l[:, g] over all Gaussians, as split-K partial sums
+// (one workgroup per (chunk of Gaussians, layer)) and one reduction. The
+// basis appearance's MLPs use this (their adjoint stores every layer's
+// input and gradient); the lobes model's are recomputed by k_mlp_wgrad
+// below, which shares the reduction.
 
 constexpr int kWgChunk = kWgChunkHost;
 
