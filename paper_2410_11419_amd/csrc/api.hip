@@ -84,7 +84,7 @@ bool make_layout(int64_t n, int32_t width, int32_t height, int64_t capacity, Lay
     l.ext = take(sizeof(int4) * n);
     l.drec = take(sizeof(int4) * n);
     l.cnt = take(sizeof(uint32_t) * n);
-    l.num = take(sizeof(float) * n);
+    l.num = take(sizeof(unsigned long long) * n);
     l.col0 = take(sizeof(float4) * n);
     l.col1 = take(sizeof(float4) * n);
     l.keys_a = take(sizeof(uint32_t) * n);

@@ -21,6 +21,13 @@ constexpr int kFeat = 16;          // per-Gaussian MLP feature size
 constexpr int kHidden = 64;        // MLP hidden width
 constexpr int kMaxLobes = 16;
 constexpr int kMaxBatch = 8;       // views per batched launch (longer batches run in chunks)
+// The shadow numerator is summed as unsigned 64-bit fixed point with 36
+// fraction bits: integer addition does not depend on the order of the
+// atomics, so num (and T) are the same bits on every run. A term is
+// rounded to 2^-36; num_j >= 0 is below 2^28 for any image this library
+// takes (each term is at most alpha_max < 1, one per pixel of at most
+// 16384^2).
+constexpr float kNumScale = 68719476736.0f;   // 2^36
 // Tile-walking kernels take their tiles from a launch order of n_slots
 // entries: slot 8 k + x runs on XCD x (workgroups are dealt to the XCDs
 // round-robin), and kNoTile marks an empty slot.
@@ -53,7 +60,7 @@ struct Layout {
     int64_t nblk_n = 0, nblk_p = 0, table_len = 0, scan_sums = 0;
     int32_t id_bits = 0;   // > 0: pairs are packed (tile << id_bits) | id while sorting
     size_t hdr = 0, rec0 = 0, rec1 = 0, rec2 = 0, depth = 0, ext = 0, drec = 0, cnt = 0, col0 = 0, col1 = 0;
-    size_t num = 0;   // shadow numerator accumulator [n]: cleared by the projection and by the resolve
+    size_t num = 0;   // shadow numerator accumulator [n], u64 fixed point (kNumScale): cleared by the projection and by the resolve
     size_t keys_a = 0, vals_a = 0, keys_b = 0, vals_b = 0, offs = 0;
     size_t pk_a = 0, pv_a = 0, pk_b = 0, pv_b = 0, table = 0, sums = 0, ranges = 0, order = 0;
     size_t total = 0;

@@ -45,7 +45,7 @@ struct ProjDesc {
     uint32_t* cnt;
     uint32_t* keys;
     uint32_t* vals;
-    float* num;
+    unsigned long long* num;
 };
 struct ProjBatch {
     int32_t nv;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, gs3_consts kc, Pro
     const int i = (int)(blockIdx.x - view * B.blocks_per_view) * blockDim.x + threadIdx.x;
     const int n = sc.n;
     if (i >= n) return;
-    D.num[i] = 0.f;   // the shadow numerator's accumulator starts empty for every projection
+    D.num[i] = 0ull;   // the shadow numerator's accumulator starts empty for every projection
     const double mx = sc.mean[i], my = sc.mean[n + i], mz = sc.mean[2 * n + i];
     const double s0 = exp((double)sc.log_scale[i]);
     const double s1 = exp((double)sc.log_scale[n + i]);
@@ -207,7 +207,7 @@ hipError_t launch_project_batch(const SceneDev& sc, const ViewParams* vps, const
             d.cnt = at<uint32_t>(ws, L.cnt);
             d.keys = at<uint32_t>(ws, L.keys_a);
             d.vals = at<uint32_t>(ws, L.vals_a);
-            d.num = at<float>(ws, L.num);
+            d.num = at<unsigned long long>(ws, L.num);
         }
         hipLaunchKernelGGL(k_project, dim3(per * (uint32_t)B.nv), dim3(256), 0, st, sc, k, B);
     }
@@ -234,7 +234,7 @@ hipError_t launch_extent_keys(const int32_t* ix, const int32_t* iy, const int32_
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.rec2), 0u, 4 * L.n, st);
     // no denominator work: the empty range {1, 1, 0, 0} in every word pair
     if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.drec), 1u, 4 * L.n, st);
-    if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.num), 0u, L.n, st);
+    if (e == hipSuccess) e = launch_fill_u32(at<uint32_t>(ws, L.num), 0u, 2 * L.n, st);
     return e != hipSuccess ? e : hipGetLastError();
 }
 

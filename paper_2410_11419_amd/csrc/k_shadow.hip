@@ -49,7 +49,7 @@ struct ShadowArgs {
     int width, height, tiles_x, n_tiles;
     int n_slots;             // entries of order (some may be kNoTile)
     float alpha_max, bias;
-    float* num;
+    unsigned long long* num;   // fixed point (kNumScale)
     float* den;
 };
 
@@ -141,7 +141,10 @@ __global__ __launch_bounds__(64) void k_shadow(ShadowBatch B) {
     auto flush = [&](int base, int m) {
         if (lane < m) {
             const float v = (s_sum[0][lane] + s_sum[1][lane]) + (s_sum[2][lane] + s_sum[3][lane]);
-            if (v != 0.f) atomicAdd(&a.num[s_id[base + lane]], v);
+            // v * 2^36 is exact in float; rounded to an integer it goes into
+            // the fixed-point sum (order-independent)
+            const unsigned long long u = __float2ull_rn(v * kNumScale);
+            if (u != 0ull) atomicAdd(&a.num[s_id[base + lane]], u);
         }
     };
     for (int b = s; b < e; b += kShadowBatch) {
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(256) void k_shadow_den(ShadowBatch B) {
 // tile lists empty, so num is missing every term: T is then NaN, not a
 // plausible value.
 struct FinishArgs {
-    float* acc;
+    unsigned long long* acc;   // fixed point (kNumScale)
     float* num;
     const float* den;
     const ViewHeader* hdr;
@@ -437,15 +440,15 @@ struct FinishBatch {
 };
 __global__ __launch_bounds__(256) void k_shadow_finish(FinishBatch B, int n) {
     const FinishArgs f = B.v[blockIdx.y];
-    float* __restrict__ acc = f.acc;
+    unsigned long long* __restrict__ acc = f.acc;
     float* __restrict__ num = f.num;
     const float* __restrict__ den = f.den;
     const ViewHeader* __restrict__ hdr = f.hdr;
     float* __restrict__ T = f.T;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const float nu = acc[i];
-    acc[i] = 0.f;
+    const float nu = (float)((double)acc[i] * (1.0 / (double)kNumScale));
+    acc[i] = 0ull;
     num[i] = nu;
     const float t = den[i] > 0.f ? nu / den[i] : 1.f;
     T[i] = hdr->overflow ? __builtin_nanf("") : t;
@@ -469,7 +472,7 @@ static ShadowArgs shadow_args(const gs3_consts& k, const Layout& L, void* ws, fl
     a.n_slots = (int)L.n_slots;
     a.alpha_max = k.alpha_max;
     a.bias = k.shadow_bias;
-    a.num = at<float>(ws, L.num);   // the view's accumulator
+    a.num = at<unsigned long long>(ws, L.num);   // the view's accumulator
     a.den = num_den + L.n;
     return a;
 }
@@ -535,7 +538,7 @@ hipError_t launch_shadow_resolve_batch(const Layout* const* Ls, void* const* wss
         for (int i = 0; i < m; ++i) {
             const Layout& L = *Ls[v0 + i];
             void* ws = wss[v0 + i];
-            B.v[i] = FinishArgs{at<float>(ws, L.num), num_den[v0 + i], num_den[v0 + i] + L.n,
+            B.v[i] = FinishArgs{at<unsigned long long>(ws, L.num), num_den[v0 + i], num_den[v0 + i] + L.n,
                                 at<ViewHeader>(ws, L.hdr), T[v0 + i]};
         }
         if (n == 0) return hipSuccess;
