@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--inflight", type=int, default=6,
+    ap.add_argument("--inflight", type=int, default=10,
                     help="frames in flight (one renderer's buffers and stream each)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many frames (for rocprofv3), no JSON")
@@ -646,8 +646,10 @@ def main():
     # `inflight` deep: frame i runs in order on renderer i % inflight (its
     # own buffers) and that renderer's stream, so consecutive frames overlap
     # on the device as a renderer producing a stream of frames would run
-    # them (six frames over the four hardware queues measured best; more
-    # queues or stages split over more streams measured slower). The library
+    # them (ten frames over the four hardware queues measured best and
+    # steadiest: six gave either about the same or a third less from one
+    # process to the next; more queues or stages split over more streams
+    # measured slower). The library
     # launches on the frame's stream, where the frame and numerator events
     # are recorded.
     fp = gs3.FramePipeline(ds, depth=args.inflight, batch_views=bool(args.batch_views))
@@ -847,7 +849,7 @@ def main():
     if args.basis_steps > 0:
         log("shared-basis appearance (the paper's MLP form)")
         with torch.cuda.stream(side):
-            out["paper_appearance"] = basis_bench(args.basis_steps, args.basis_train_steps)
+            out["paper_appearance"] = basis_bench(args.basis_steps, args.basis_train_steps, args.inflight)
     if args.serving_requests > 0:
         log("serving")
         del rnd, fp, single
