@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--env-lights", type=int, default=16,
                     help="directional lights of the environment-light leg (0: skip)")
     ap.add_argument("--env-steps", type=int, default=5, help="timed environment frames")
+    ap.add_argument("--env-slots", type=int, default=4, help="lights in flight in an environment frame")
     ap.add_argument("--basis-steps", type=int, default=30,
                     help="timed frames of the shared-basis appearance scene (0: skip)")
     ap.add_argument("--basis-train-steps", type=int, default=5, help="its timed fwd+bwd steps (0: skip)")
@@ -393,30 +394,32 @@ def serving_bench(ds, requests, loads):
     return out
 
 
-def env_bench(ds, n_lights, steps):
+def env_bench(ds, n_lights, steps, slots=4):
     """Environment lighting (Sec. 4.5): frames of the 300K scene at 800x800
     under `n_lights` directional lights (orthographic 1024x1024 light views
     over a 2.2-unit square, sampled directions and sky weights), each frame
-    one camera preprocess plus per light a shadow splat, shading and camera
-    splat. Reports frames/s and the time per light."""
+    per light a shadow splat, shading and camera splat, `slots` lights in
+    flight (one camera preprocess per slot). Reports frames/s and the time
+    per light."""
     import numpy as np
     import torch
     from paper_2410_11419_amd import gs3, synth
     rng = np.random.default_rng(2)
     cam = synth.make_view(rng.standard_normal(3), 4.0, 800, 800, 40.0)
     lights, w = synth.environment_lights(n_lights, seed=4, width=1024, height=1024, ortho_width=2.2)
-    rnd = gs3.Renderer(ds)
-    rnd.render_env(cam, lights, w, check=True)      # sizes the buffers
+    ep = gs3.EnvPipeline(ds, slots=slots)
+    ep.render(cam, lights, w, check=True)      # sizes the buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        rnd.render_env(cam, lights, w, check=False)
+        ep.render(cam, lights, w, check=False)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    if rnd.overflowed():
+    if any(r.overflowed() for r in ep.renderers):
         raise RuntimeError("environment frame overflowed a view buffer")
     return {"frames_per_s": round(1.0 / dt, 3), "ms_per_frame": round(1e3 * dt, 3),
             "ms_per_light": round(1e3 * dt / n_lights, 4), "lights": n_lights, "steps": steps,
+            "lights_in_flight": slots,
             "config": "300,000 Gaussians, camera 800x800, directional lights 1024x1024 orthographic"}
 
 
@@ -845,7 +848,7 @@ def main():
     if args.env_lights > 0 and args.env_steps > 0:
         log(f"environment light ({args.env_lights} directional lights)")
         with torch.cuda.stream(side):
-            out["environment_light"] = env_bench(ds, args.env_lights, args.env_steps)
+            out["environment_light"] = env_bench(ds, args.env_lights, args.env_steps, args.env_slots)
     if args.basis_steps > 0:
         log("shared-basis appearance (the paper's MLP form)")
         with torch.cuda.stream(side):

@@ -1012,6 +1012,48 @@ def render_batched(renderers: Sequence["Renderer"], cams: Sequence, lights: Sequ
     return outs
 
 
+class EnvPipeline:
+    """Environment frames (Sec. 4.5) with several lights in flight: light l
+    runs on slot l % slots, each slot a Renderer (its own light and camera
+    buffers) on its own stream, so one light's shadow numerator tails off
+    while the next lights' passes fill the device. Each slot runs
+    Renderer.render_env over its lights (one camera preprocess per slot);
+    the slots' weighted sums are added in slot order on the caller's stream,
+    so the result does not depend on timing."""
+
+    def __init__(self, scene: DeviceScene, slots: int = 4, consts: Optional[gs3_consts] = None,
+                 use_mlps: bool = True, pair_capacity: Optional[int] = None):
+        if slots < 1:
+            raise ValueError("at least one slot")
+        self.renderers = [Renderer(scene, consts, use_mlps, pair_capacity) for _ in range(slots)]
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+
+    def render(self, cam, lights: Sequence, weights: Sequence[float], check: bool = True) -> torch.Tensor:
+        """The weighted sum of the relit frames of ``cam`` under ``lights``
+        (as Renderer.render_env). Returns a new [3, H, W] tensor on the
+        caller's stream."""
+        if len(lights) != len(weights) or not len(lights):
+            raise ValueError("one weight per light, at least one light")
+        cur = torch.cuda.current_stream()
+        start = torch.cuda.Event()
+        start.record(cur)
+        S = len(self.renderers)
+        parts = []
+        for k in range(min(S, len(lights))):
+            st = self.streams[k]
+            st.wait_event(start)
+            with torch.cuda.stream(st):
+                part = self.renderers[k].render_env(cam, lights[k::S], weights[k::S], check)
+            parts.append((part, st))
+        for part, st in parts:
+            cur.wait_stream(st)
+            part.record_stream(cur)
+        env = parts[0][0]
+        for part, _ in parts[1:]:
+            gs3_image_accumulate(env, part, 1.0)
+        return env
+
+
 class FramePipeline:
     """A stream of relit frames with `depth` frames in flight: frame i runs
     on renderer i % depth (its own buffers) and its own stream, so the next
