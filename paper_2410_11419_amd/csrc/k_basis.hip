@@ -10,7 +10,7 @@
 //
 // The MLPs are dense contractions over the Gaussians and run on MFMA with
 // the split half-precision products of mlp_common.h (x = hi + lo / 2048,
-// three 16x16x16 products per k-block). Each column (Gaussian) of the
+// three 16x16x32 products per 32-wide k-block). Each column (Gaussian) of the
 // B operand is first scaled by a power of two that brings its largest
 // entry to [128, 256), so the halves keep their precision for any
 // magnitude (gradients included); outputs are scaled back exactly.
@@ -72,30 +72,55 @@ static_assert(kPsiSmem * 4 <= 160 * 1024, "Psi weights exceed the LDS");
 
 // ---------------------------------------------------------------- helpers
 
-// Pack A[r][c] (r < M, c < K, both multiples of 16) as split MFMA A
-// operands: entry (mt, kb, lane) = four floats holding the hi and lo halves
-// of A[16 mt + lane % 16][16 kb + 4 (lane / 16) + i], i = 0..3.
+// A 32-wide k-block pairs two 16-wide ones: slot j (0..7) of lane group g
+// in block kb is column kcol(kb, g, j) = 32 kb + 16 (j / 4) + 4 g + j % 4,
+// the entry that the D layout of tile 2 kb + j / 4 gives the lane. The
+// 16x16x32 product takes slot j of lane group g of A and of B as the same
+// k, so the activations of one layer feed the next one without a shuffle.
+__device__ inline int kcol(int kb, int g, int j) { return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
+
+// Pack A[r][c] (r < M a multiple of 16, c < K a multiple of 32) as split
+// MFMA A operands: entry (mt, kb) holds 512 floats, first the hi halves of
+// every lane (eight per lane, four floats) and then the lo halves, lane l
+// holding A[16 mt + l % 16][kcol(kb, l / 16, j)], j = 0..7.
 template <typename ElemFn>
 __device__ inline void pack_split(float* sm, int M, int K, ElemFn elem) {
-    const int KB = K / 16;
+    const int KB = K / 32;
     for (int idx = threadIdx.x; idx < (M / 16) * KB * 64; idx += blockDim.x) {
         const int l = idx & 63, rest = idx >> 6, kb = rest % KB, mt = rest / KB;
-        _Float16 hv[8];
+        _Float16 hv[16];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) split_half(elem(16 * mt + (l & 15), 16 * kb + 4 * (l >> 4) + i), &hv[i], &hv[4 + i]);
-        float4 v;
-        __builtin_memcpy(&v, hv, sizeof v);
-        *reinterpret_cast<float4*>(sm + 4 * idx) = v;
+        for (int j = 0; j < 8; ++j) split_half(elem(16 * mt + (l & 15), kcol(kb, l >> 4, j)), &hv[j], &hv[8 + j]);
+        float4 v[2];
+        __builtin_memcpy(v, hv, sizeof v);
+        float* e = sm + 512 * rest + 4 * l;
+        *reinterpret_cast<float4*>(e) = v[0];
+        *reinterpret_cast<float4*>(e + 256) = v[1];
     }
 }
 
+// One split product step over a 32-wide k-block: D += A B, the A halves
+// read from the packed entry at sm + off (lane offset included).
+__device__ inline void mfma_split32(const float* sm, int off, halfx8 bh, halfx8 bl, floatx4* d, floatx4* dc) {
+    const float4 vh = *reinterpret_cast<const float4*>(sm + off);
+    const float4 vl = *reinterpret_cast<const float4*>(sm + off + 256);
+    halfx8 ah, al;
+    __builtin_memcpy(&ah, &vh, sizeof ah);
+    __builtin_memcpy(&al, &vl, sizeof al);
+    *d = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, *d, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, *dc, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, *dc, 0, 0, 0);
+}
+
 // The B operand of a split product for the 16 Gaussians of the wave (x in
-// D layout, KB k-blocks): each Gaussian's column scaled by a power of two
-// that brings its largest entry to [128, 256) and split into halves;
-// `down` undoes the scaling.
+// D layout, KB 16-wide k-blocks, KB even): each Gaussian's column scaled by
+// a power of two that brings its largest entry to [128, 256) and split
+// into halves, two 16-wide blocks per 32-wide one; `down` undoes the
+// scaling.
 template <int KB>
 struct SplitB {
-    halfx4 h[KB], l[KB];
+    static_assert(KB % 2 == 0, "k is a multiple of 32");
+    halfx8 h[KB / 2], l[KB / 2];
     float down;
 };
 template <int KB>
@@ -112,24 +137,28 @@ __device__ inline void split_cols(const floatx4* x, SplitB<KB>& b) {
     const float up = ldexpf(1.f, 8 - e);
     b.down = ldexpf(1.f, e - 8);
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-        const float xv[4] = {x[kb][0] * up, x[kb][1] * up, x[kb][2] * up, x[kb][3] * up};
-        split_b(xv, &b.h[kb], &b.l[kb]);
-    }
+    for (int kb = 0; kb < KB / 2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            _Float16 hi, lo;
+            split_half(x[2 * kb + (j >> 2)][j & 3] * up, &hi, &lo);
+            b.h[kb][j] = hi;
+            b.l[kb][j] = lo;
+        }
 }
 
-// Output tiles mt0 .. mt0 + CH - 1 of A x (A packed by pack_split with KB
-// k-blocks per row of tiles), D layout.
+// Output tiles mt0 .. mt0 + CH - 1 of A x (A packed by pack_split from KB
+// 16-wide k-blocks per row of tiles), D layout.
 template <int KB, int CH>
 __device__ inline void split_tiles(const float* sm, int lane, int mt0, const SplitB<KB>& b, floatx4* out) {
     floatx4 cor[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) out[c] = cor[c] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
+    for (int kb = 0; kb < KB / 2; ++kb)
 #pragma unroll
         for (int c = 0; c < CH; ++c)
-            mfma_split(sm, 4 * (((mt0 + c) * KB + kb) * 64 + lane), b.h[kb], b.l[kb], &out[c], &cor[c]);
+            mfma_split32(sm, 512 * ((mt0 + c) * (KB / 2) + kb) + 4 * lane, b.h[kb], b.l[kb], &out[c], &cor[c]);
 #pragma unroll
     for (int c = 0; c < CH; ++c)
 #pragma unroll
@@ -191,6 +220,17 @@ __device__ inline void load_d(const float* rows, int row0, int q, int g, int n, 
         for (int i = 0; i < 4; ++i) v[mt][i] = p[(size_t)(16 * mt + i) * n];
 }
 
+// sin and cos of 2^j pi v. With x = 2^(j - 1) v the angle is 2 pi x; x less
+// its nearest integer (an exact difference) lies in [-1/2, 1/2], where the
+// hardware sine and cosine, which take their argument in revolutions, are
+// accurate to about 1e-7.
+__device__ inline float pe_turns(float v, int j) {
+    const float x = ldexpf(v, j - 1);
+    return x - rintf(x);
+}
+__device__ inline float pe_sin(float v, int j) { return __builtin_amdgcn_sinf(pe_turns(v, j)); }
+__device__ inline float pe_cos(float v, int j) { return __builtin_amdgcn_cosf(pe_turns(v, j)); }
+
 // Entry e (0..26) of the positional encoding of v: v[e] for e < 3, else
 // with t = e - 3, band j = t / 6 and r = t % 6: sin (r < 3) or cos (r >= 3)
 // of 2^j pi v[r % 3].
@@ -198,9 +238,8 @@ __device__ inline float pe_entry(int e, float v0, float v1, float v2) {
     if (e < 3) return e == 0 ? v0 : (e == 1 ? v1 : v2);
     const int t = e - 3, j = t / 6, r = t % 6, c = r % 3;
     const float v = c == 0 ? v0 : (c == 1 ? v1 : v2);
-    float sn, cs;
-    sincospif(ldexpf(v, j), &sn, &cs);
-    return r < 3 ? sn : cs;
+    const float f = pe_turns(v, j);
+    return r < 3 ? __builtin_amdgcn_sinf(f) : __builtin_amdgcn_cosf(f);
 }
 
 // Rotation matrix (row-major) of a quaternion (w, x, y, z), normalised.
@@ -583,8 +622,7 @@ __device__ inline void pe_adjoint(const float* rows, int row0, int n, int g, flo
     for (int j = 0; j < 4; ++j) {
         const float f = ldexpf(3.14159265358979f, j);
         for (int c = 0; c < 3; ++c) {
-            float sn, cs;
-            sincospif(ldexpf(v[c], j), &sn, &cs);
+            const float sn = pe_sin(v[c], j), cs = pe_cos(v[c], j);
             const float ds = rows[(size_t)(row0 + 3 + 6 * j + c) * n + g];
             const float dc = rows[(size_t)(row0 + 6 + 6 * j + c) * n + g];
             dv[c] = fmaf(f, ds * cs - dc * sn, dv[c]);

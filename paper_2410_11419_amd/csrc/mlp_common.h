@@ -28,6 +28,7 @@ namespace gs3 {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 constexpr int kPhiIn = 1 + kFeat;          // [T, feat]
 constexpr int kPsiIn = kFeat + 6;          // [feat, w_i, w_o]
