@@ -4,20 +4,24 @@
 //
 // A wave evaluates 16 Gaussians, four lanes per Gaussian (lane l: Gaussian
 // l % 16, quarter q = l / 16), transposed, H^T = W X^T, so Gaussians are the
-// N dimension. The hidden layers run on v_mfma_f32_16x16x16_f16 with every
+// N dimension. The hidden layers run on half-precision MFMA with every
 // float32 operand split into two halves, x = hi + lo / 2048 (hi = x rounded
 // to half, lo = the remainder scaled by 2048 so that it stays a normal
 // half): W X = Wh Xh + (Wh Xl + Wl Xh) / 2048, the dropped Wl Xl / 2048^2
 // term and the halves' rounding leave a relative error near 2^-22 per
 // product, below the float32 accumulation's own. Three half-precision
 // products cost far less than the four float32 ones (16x16x4) they replace.
-// Operand layout of one 16x16x16 product (k-block kb, output tile mt):
+// Operand layout of one 16x16x16 product (the input layer's first k-block
+// kb, output tile mt):
 //   A: lane l supplies W[16 mt + l%16][16 kb + 4 (l/16) + i], i = 0..3
 //   B: lane l supplies X[g = l%16][16 kb + 4 (l/16) + i]
 //   D: lane l holds H^T[16 mt + 4 (l/16) + i][l%16], i = 0..3,
-// so the D registers of output tile m are exactly the B operand of k-block m
-// of the next layer, with no transposes between layers. Activations above
-// the half range (65504) are outside this scheme's domain.
+// so the D registers of output tile m are exactly a 16-wide B operand of
+// the next layer. The 64x64 hidden layers take 16x16x32 products (twice the
+// rate of 16x16x16 on gfx950) over two 32-wide k-blocks, each pairing the D
+// tiles 2 kb and 2 kb + 1 (kcol below), again with no transposes between
+// layers. Activations above the half range (65504) are outside this
+// scheme's domain.
 // The adjoint recomputes the forward activations with the same routine (so
 // its ReLU masks are the forward's) and runs its own products in float32.
 #pragma once
@@ -38,9 +42,11 @@ constexpr int kPsiIn = kFeat + 6;          // [feat, w_i, w_o]
 constexpr int kPhiKR = (kPhiIn - 16 + 3) / 4;   // float32 k-steps of the input layer
 constexpr int kPsiKR = (kPsiIn - 16 + 3) / 4;
 static_assert(kPhiIn >= 16 && kPsiIn >= 16, "the input layer's first k-block is full");
-// LDS layout (floats) of one packed MLP: per (output tile, k-block, lane)
-// four floats holding the A operand's hi and lo halves; the input layer's
-// float32 remainder per (output tile, k-step, lane) one float
+// LDS layout (floats) of one packed MLP: the input layer's first k-block per
+// (output tile, lane) four floats holding the A operand's hi and lo halves,
+// its float32 remainder per (output tile, k-step, lane) one float; a hidden
+// layer per (output tile, 32-wide k-block) 512 floats (the 64 lanes' hi
+// halves, then their lo halves)
 constexpr int kLH = 4 * 4 * 64 * 4;          // a 64x64 hidden layer
 struct MlpSmem {
     int l1, l1r, l2, l3, w4, b1, b2, b3, b4, size;
@@ -96,6 +102,27 @@ __device__ inline void split_half(float x, _Float16* hi, _Float16* lo) {
     *lo = (_Float16)((x - (float)h) * 2048.f);
 }
 
+// A 32-wide k-block pairs two 16-wide ones: slot j (0..7) of lane group g
+// in block kb is column kcol(kb, g, j) = 32 kb + 16 (j / 4) + 4 g + j % 4,
+// the entry that the D layout of tile 2 kb + j / 4 gives the lane. The
+// 16x16x32 product takes slot j of lane group g of A and of B as the same
+// k, so the activations of one layer feed the next one without a shuffle.
+__device__ inline int kcol(int kb, int g, int j) { return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
+
+// One split product step over a 32-wide k-block: D += A B, the A halves
+// read from a packed entry (hi halves of the 64 lanes, then the lo halves)
+// at sm + off, the lane's offset included.
+__device__ inline void mfma_split32(const float* sm, int off, halfx8 bh, halfx8 bl, floatx4* d, floatx4* dc) {
+    const float4 vh = *reinterpret_cast<const float4*>(sm + off);
+    const float4 vl = *reinterpret_cast<const float4*>(sm + off + 256);
+    halfx8 ah, al;
+    __builtin_memcpy(&ah, &vh, sizeof ah);
+    __builtin_memcpy(&al, &vl, sizeof al);
+    *d = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, *d, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, *dc, 0, 0, 0);
+    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, *dc, 0, 0, 0);
+}
+
 // Copy one MLP into LDS: hidden-layer and input-layer weights as split A
 // operands, the output layer and biases as float32.
 __device__ inline void load_mlp(float* sm, const MlpSmem& S, int kr, int n_in, int n_out, const MlpArgs& m) {
@@ -120,10 +147,21 @@ __device__ inline void load_mlp(float* sm, const MlpSmem& S, int kr, int n_in, i
         const int row = 16 * mt + (l & 15), col = 16 + 4 * kk + (l >> 4);
         sm[S.l1r + idx] = col < n_in ? m.w[0][row * n_in + col] : 0.f;
     }
-    for (int idx = tid; idx < 4 * 4 * 64; idx += nt) {
-        const int mt = idx / 256, rem = idx % 256, kb = rem / 64, l = rem % 64;
-        put(S.l2 + 4 * idx, m.w[1], kHidden, 16 * mt + (l & 15), 16 * kb + 4 * (l >> 4), kHidden);
-        put(S.l3 + 4 * idx, m.w[2], kHidden, 16 * mt + (l & 15), 16 * kb + 4 * (l >> 4), kHidden);
+    // hidden layers as 16x16x32 operands: entry (mt, kb) of 512 floats, the
+    // hi halves of the 64 lanes and then their lo halves
+    auto put32 = [&](int off, const float* W, int row, int kb, int g) {
+        _Float16 hv[16];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) split_half(W[row * kHidden + kcol(kb, g, j)], &hv[j], &hv[8 + j]);
+        float4 v[2];
+        __builtin_memcpy(v, hv, sizeof v);
+        *reinterpret_cast<float4*>(sm + off) = v[0];
+        *reinterpret_cast<float4*>(sm + off + 256) = v[1];
+    };
+    for (int idx = tid; idx < 4 * 2 * 64; idx += nt) {
+        const int l = idx & 63, rest = idx >> 6, kb = rest & 1, mt = rest >> 1;
+        put32(S.l2 + 512 * rest + 4 * l, m.w[1], 16 * mt + (l & 15), kb, l >> 4);
+        put32(S.l3 + 512 * rest + 4 * l, m.w[2], 16 * mt + (l & 15), kb, l >> 4);
     }
     for (int idx = tid; idx < n_out * 64; idx += nt) sm[S.w4 + idx] = m.w[3][idx];
     for (int idx = tid; idx < 64; idx += nt) {
@@ -201,12 +239,17 @@ __device__ inline void mlp_layers(const float* sm, const MlpSmem& S, int lane, I
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) nxt[mt] = ncor[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const float xv[4] = {acc[kb][0], acc[kb][1], acc[kb][2], acc[kb][3]};
-            halfx4 bh, bq;
-            split_b(xv, &bh, &bq);
+        for (int kb = 0; kb < 2; ++kb) {
+            halfx8 bh, bq;
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) mfma_split(sm, wl + 4 * ((mt * 4 + kb) * 64 + lane), bh, bq, &nxt[mt], &ncor[mt]);
+            for (int j = 0; j < 8; ++j) {
+                _Float16 hi, lo;
+                split_half(acc[2 * kb + (j >> 2)][j & 3], &hi, &lo);
+                bh[j] = hi;
+                bq[j] = lo;
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) mfma_split32(sm, wl + 512 * (mt * 2 + kb) + 4 * lane, bh, bq, &nxt[mt], &ncor[mt]);
         }
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
