@@ -72,13 +72,6 @@ static_assert(kPsiSmem * 4 <= 160 * 1024, "Psi weights exceed the LDS");
 
 // ---------------------------------------------------------------- helpers
 
-// A 32-wide k-block pairs two 16-wide ones: slot j (0..7) of lane group g
-// in block kb is column kcol(kb, g, j) = 32 kb + 16 (j / 4) + 4 g + j % 4,
-// the entry that the D layout of tile 2 kb + j / 4 gives the lane. The
-// 16x16x32 product takes slot j of lane group g of A and of B as the same
-// k, so the activations of one layer feed the next one without a shuffle.
-__device__ inline int kcol(int kb, int g, int j) { return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
-
 // Pack A[r][c] (r < M a multiple of 16, c < K a multiple of 32) as split
 // MFMA A operands: entry (mt, kb) holds 512 floats, first the hi halves of
 // every lane (eight per lane, four floats) and then the lo halves, lane l
@@ -97,19 +90,6 @@ __device__ inline void pack_split(float* sm, int M, int K, ElemFn elem) {
         *reinterpret_cast<float4*>(e) = v[0];
         *reinterpret_cast<float4*>(e + 256) = v[1];
     }
-}
-
-// One split product step over a 32-wide k-block: D += A B, the A halves
-// read from the packed entry at sm + off (lane offset included).
-__device__ inline void mfma_split32(const float* sm, int off, halfx8 bh, halfx8 bl, floatx4* d, floatx4* dc) {
-    const float4 vh = *reinterpret_cast<const float4*>(sm + off);
-    const float4 vl = *reinterpret_cast<const float4*>(sm + off + 256);
-    halfx8 ah, al;
-    __builtin_memcpy(&ah, &vh, sizeof ah);
-    __builtin_memcpy(&al, &vl, sizeof al);
-    *d = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, *d, 0, 0, 0);
-    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, *dc, 0, 0, 0);
-    *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, *dc, 0, 0, 0);
 }
 
 // The B operand of a split product for the 16 Gaussians of the wave (x in
