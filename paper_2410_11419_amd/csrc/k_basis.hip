@@ -293,9 +293,68 @@ struct BasisArgs {
     ShadeView v[kMaxBatch];
 };
 
-// Shading c (Eq. 4-7 with the shared basis) and the residual r = Psi(w_o;
-// mu, l) (Sec. 4.3). STORE: no colours; Psi's layer inputs/outputs and its
-// last hidden layer's pre-activation gradient go to the scratch rows.
+// Shading c (Eq. 4-7 with the shared basis) of the view blockIdx.y, one
+// Gaussian per lane; the basis frames and inverse scales are formed once per
+// workgroup in LDS. Writes c to col0.xyz and colour rows 0..2.
+__global__ __launch_bounds__(256) void k_basis_c(BasisArgs a) {
+    const ShadeView vw = a.v[blockIdx.y];
+    __shared__ BasisConst B;
+    const SceneDev& sc = a.sc;
+    const int n = sc.n, K = sc.k;
+    for (int j = threadIdx.x; j < K; j += blockDim.x)
+        load_basis(sc, j, B.R[j], &B.isx2[j], &B.isy2[j], &B.isz2[j], &B.isz[j]);
+    __syncthreads();
+    const float kd = 0.01f * (1.f - 0.36787944117144233f);   // eps (1 - 1/e), Eq. 5
+    const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+        const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
+        float wi[3], wo[3], ri, ro;
+        directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
+        float Rs[9];
+        quat_mat(sc.shade_rot[g], sc.shade_rot[n + g], sc.shade_rot[2 * n + g], sc.shade_rot[3 * n + g], Rs);
+        const float lix = Rs[0] * wi[0] + Rs[1] * wi[1] + Rs[2] * wi[2];
+        const float liy = Rs[3] * wi[0] + Rs[4] * wi[1] + Rs[5] * wi[2];
+        const float liz = Rs[6] * wi[0] + Rs[7] * wi[1] + Rs[8] * wi[2];
+        const float lox = Rs[0] * wo[0] + Rs[1] * wo[1] + Rs[2] * wo[2];
+        const float loy = Rs[3] * wo[0] + Rs[4] * wo[1] + Rs[5] * wo[2];
+        const float loz = Rs[6] * wo[0] + Rs[7] * wo[1] + Rs[8] * wo[2];
+        const float elu = liz > 0.f ? liz : 0.01f * (expf(fminf(liz, 0.f)) - 1.f);
+        const float fd = (elu + kd) * fd_norm;
+        float hx = lix + lox, hy = liy + loy, hz = liz + loz;
+        const float hn2 = hx * hx + hy * hy + hz * hz;
+        if (hn2 > 1e-24f) {
+            const float r = rsqrtf(hn2);
+            hx *= r; hy *= r; hz *= r;
+        } else {
+            hx = 0.f; hy = 0.f; hz = 1.f;
+        }
+        // Eq. 6 over the shared basis
+        float fs = 0.f;
+        for (int j = 0; j < K; ++j) {
+            const float* Rb = B.R[j];
+            const float ba = Rb[0] * hx + Rb[1] * hy + Rb[2] * hz;
+            const float bb = Rb[3] * hx + Rb[4] * hy + Rb[5] * hz;
+            const float bc = Rb[6] * hx + Rb[7] * hy + Rb[8] * hz;
+            const AsgEval ev = asg_eval(ba, bb, bc, B.isx2[j], B.isy2[j], B.isz2[j], B.isz[j]);
+            fs = fmaf(sc.basis_weight[(size_t)j * n + g], ev.G, fs);
+        }
+        const float c0 = fmaf(sc.albedo[g], fd, sc.spec_albedo[g] * fs);
+        const float c1 = fmaf(sc.albedo[n + g], fd, sc.spec_albedo[n + g] * fs);
+        const float c2 = fmaf(sc.albedo[2 * n + g], fd, sc.spec_albedo[2 * n + g] * fs);
+        // col0.w is Phi's T', written by k_basis_phi
+        float* c0p = reinterpret_cast<float*>(vw.col0 + g);
+        c0p[0] = c0;
+        c0p[1] = c1;
+        c0p[2] = c2;
+        vw.colour[g] = c0;
+        vw.colour[(size_t)n + g] = c1;
+        vw.colour[(size_t)2 * n + g] = c2;
+    }
+}
+
+// The residual r = Psi(w_o; mu, l) (Sec. 4.3). STORE: no colours; Psi's
+// layer inputs/outputs and its last hidden layer's pre-activation gradient
+// go to the scratch rows.
 template <bool STORE>
 __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
     const ShadeView vw = a.v[blockIdx.y];
@@ -314,8 +373,6 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
     __syncthreads();
     const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4;
     const int waves = blockDim.x >> 6;
-    const float kd = 0.01f * (1.f - 0.36787944117144233f);   // eps (1 - 1/e), Eq. 5
-    const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
     constexpr int MT = kPsiBasisHidden / 16;
     for (int base = (blockIdx.x * waves + w) * 16; base < n; base += gridDim.x * waves * 16) {
         asm volatile("" ::: "memory");
@@ -325,53 +382,6 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
         float wi[3], wo[3], ri, ro;
         directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
-        float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-        if (!STORE) {
-            float Rs[9];
-            quat_mat(sc.shade_rot[g], sc.shade_rot[n + g], sc.shade_rot[2 * n + g], sc.shade_rot[3 * n + g], Rs);
-            const float lix = Rs[0] * wi[0] + Rs[1] * wi[1] + Rs[2] * wi[2];
-            const float liy = Rs[3] * wi[0] + Rs[4] * wi[1] + Rs[5] * wi[2];
-            const float liz = Rs[6] * wi[0] + Rs[7] * wi[1] + Rs[8] * wi[2];
-            const float lox = Rs[0] * wo[0] + Rs[1] * wo[1] + Rs[2] * wo[2];
-            const float loy = Rs[3] * wo[0] + Rs[4] * wo[1] + Rs[5] * wo[2];
-            const float loz = Rs[6] * wo[0] + Rs[7] * wo[1] + Rs[8] * wo[2];
-            const float elu = liz > 0.f ? liz : 0.01f * (expf(fminf(liz, 0.f)) - 1.f);
-            const float fd = (elu + kd) * fd_norm;
-            float hx = lix + lox, hy = liy + loy, hz = liz + loz;
-            const float hn2 = hx * hx + hy * hy + hz * hz;
-            if (hn2 > 1e-24f) {
-                const float r = rsqrtf(hn2);
-                hx *= r; hy *= r; hz *= r;
-            } else {
-                hx = 0.f; hy = 0.f; hz = 1.f;
-            }
-            // basis j = q, q + 4, ... on this lane (Eq. 6)
-            float fs = 0.f;
-            for (int j = q; j < sc.k; j += 4) {
-                float Rb[9], isx2, isy2, isz2, isz;
-                load_basis(sc, j, Rb, &isx2, &isy2, &isz2, &isz);
-                const float ba = Rb[0] * hx + Rb[1] * hy + Rb[2] * hz;
-                const float bb = Rb[3] * hx + Rb[4] * hy + Rb[5] * hz;
-                const float bc = Rb[6] * hx + Rb[7] * hy + Rb[8] * hz;
-                const AsgEval ev = asg_eval(ba, bb, bc, isx2, isy2, isz2, isz);
-                fs = fmaf(sc.basis_weight[(size_t)j * n + g], ev.G, fs);
-            }
-            fs += __shfl_xor(fs, 16, 64);
-            fs += __shfl_xor(fs, 32, 64);
-            c0 = fmaf(sc.albedo[g], fd, sc.spec_albedo[g] * fs);
-            c1 = fmaf(sc.albedo[n + g], fd, sc.spec_albedo[n + g] * fs);
-            c2 = fmaf(sc.albedo[2 * n + g], fd, sc.spec_albedo[2 * n + g] * fs);
-            // c is written before Psi runs (colour rows 0..2; row 3 is Phi's)
-            if (valid) {
-                if (q == 0) {
-                    float* c0p = reinterpret_cast<float*>(vw.col0 + g);
-                    c0p[0] = c0;
-                    c0p[1] = c1;
-                    c0p[2] = c2;
-                }
-                if (q < 3) vw.colour[(size_t)q * n + g] = q == 0 ? c0 : (q == 1 ? c1 : c2);
-            }
-        }
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
         if (a.use_psi) {
             // inputs [PE(w_o), PE(mu), l], lane's entries 16 kb + 4 q + i
@@ -855,13 +865,16 @@ hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, 
             set_view(a.v[i], sps[v0 + i], T ? T[v0 + i] : nullptr, at<float4>(wss[v0 + i], Ls[v0 + i]->col0),
                      at<float4>(wss[v0 + i], Ls[v0 + i]->col1), colour[v0 + i]);
         if (parts & 1) {
+            hipLaunchKernelGGL(k_basis_c, dim3(grid_for(sc.n, 256, 2048), m), dim3(256), 0, st, a);
             // the Psi weights take the whole LDS: one 512-thread workgroup per CU
             hipLaunchKernelGGL(k_basis_psi<false>, dim3(grid_for(sc.n, 8 * 16, 256), m), dim3(512), 0, st, a);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         if (parts & 2) {
-            hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, 2048), m), dim3(256), 0, st, a);
+            // three 4-wave workgroups per CU (164 registers a lane): one round
+            // of 768 workgroups, each packing the weights once
+            hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, 768), m), dim3(256), 0, st, a);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -955,7 +968,8 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
             return e;
     }
     if (phi) {
-        hipLaunchKernelGGL(k_basis_phi<true>, dim3(grid_for(n, 4 * 16, 2048)), dim3(256), 0, st, a);
+        // two workgroups per CU at this kernel's 224 registers a lane
+        hipLaunchKernelGGL(k_basis_phi<true>, dim3(grid_for(n, 4 * 16, 512)), dim3(256), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         constexpr int P = kPhiBasisHidden / 16;
         if ((e = layer_bwd<P, P, true>(phi->w[2], kPhiBasisHidden, kPhiBasisHidden, rows, kPhiB.dz3, kPhiB.h2,
