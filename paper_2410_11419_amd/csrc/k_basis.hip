@@ -211,15 +211,59 @@ __device__ inline float pe_turns(float v, int j) {
 __device__ inline float pe_sin(float v, int j) { return __builtin_amdgcn_sinf(pe_turns(v, j)); }
 __device__ inline float pe_cos(float v, int j) { return __builtin_amdgcn_cosf(pe_turns(v, j)); }
 
-// Entry e (0..26) of the positional encoding of v: v[e] for e < 3, else
-// with t = e - 3, band j = t / 6 and r = t % 6: sin (r < 3) or cos (r >= 3)
-// of 2^j pi v[r % 3].
-__device__ inline float pe_entry(int e, float v0, float v1, float v2) {
-    if (e < 3) return e == 0 ? v0 : (e == 1 ? v1 : v2);
-    const int t = e - 3, j = t / 6, r = t % 6, c = r % 3;
-    const float v = c == 0 ? v0 : (c == 1 ? v1 : v2);
-    const float f = pe_turns(v, j);
-    return r < 3 ? __builtin_amdgcn_sinf(f) : __builtin_amdgcn_cosf(f);
+// The MLP inputs in the order the lanes form them. Lane group q < 3 takes
+// component q of both encoded vectors: k-block 0 holds the sines of the
+// first vector's bands 0..3, k-block 1 their cosines, k-blocks 2 and 3 the
+// same for mu. Lane group 3 holds the raw entries [T,] v, mu, l and zero
+// padding. Every lane so runs one branch-free sequence; the weights' input
+// columns are packed in the same order. in_index(c) is the position of
+// packed column c in the MLP's own input order ([T,] PE(v), PE(mu), l),
+// -1 for padding; t_first = 1 when T leads the inputs (Phi).
+__device__ inline int in_index(int c, int t_first) {
+    const int kb = c >> 4, q = (c >> 2) & 3, i = c & 3;
+    if (q < 3) return t_first + (kb < 2 ? 0 : kPE) + ((kb & 1) ? 6 : 3) + 6 * i + q;
+    const int r = 4 * kb + i;
+    if (r < t_first) return 0;
+    const int s = r - t_first;
+    if (s < 3) return t_first + s;
+    if (s < 6) return t_first + kPE + s - 3;
+    if (s < 6 + kLatent) return t_first + 2 * kPE + s - 6;
+    return -1;
+}
+
+// The lane's 16 inputs x[kb][i] (packed column 16 kb + 4 q + i) for the
+// encoded vector v, the mean m, the Gaussian's latent and (t_first) T.
+__device__ inline void form_inputs(int q, int t_first, float Tg, const float v[3], const float m[3],
+                                   const SceneDev& sc, int g, floatx4 x[4]) {
+    if (q < 3) {
+        const float vq = q == 0 ? v[0] : (q == 1 ? v[1] : v[2]);
+        const float mq = q == 0 ? m[0] : (q == 1 ? m[1] : m[2]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float fv = pe_turns(vq, i), fm = pe_turns(mq, i);
+            x[0][i] = __builtin_amdgcn_sinf(fv);
+            x[1][i] = __builtin_amdgcn_cosf(fv);
+            x[2][i] = __builtin_amdgcn_sinf(fm);
+            x[3][i] = __builtin_amdgcn_cosf(fm);
+        }
+    } else {
+        float raw[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) raw[r] = 0.f;
+        const int o = t_first;
+        if (o) raw[0] = Tg;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            raw[o + c] = v[c];
+            raw[o + 3 + c] = m[c];
+        }
+#pragma unroll
+        for (int l = 0; l < kLatent; ++l) raw[o + 6 + l] = sc.latent[(size_t)l * sc.n + g];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[kb][i] = raw[4 * kb + i];
+    }
 }
 
 // Rotation matrix (row-major) of a quaternion (w, x, y, z), normalised.
@@ -364,7 +408,10 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
     if (a.use_psi) {
         const MlpArgs& m = a.psi;
         pack_split(sm + kPsiL1, kPsiBasisHidden, kXin,
-                   [&](int r, int c) { return c < kPsiBasisIn ? m.w[0][r * kPsiBasisIn + c] : 0.f; });
+                   [&](int r, int c) {
+                       const int k = in_index(c, 0);
+                       return k >= 0 ? m.w[0][r * kPsiBasisIn + k] : 0.f;
+                   });
         pack_split(sm + kPsiL2, kPsiBasisHidden, kPsiBasisHidden,
                    [&](int r, int c) { return m.w[1][r * kPsiBasisHidden + c]; });
         pack_split(sm + kPsiL3, kPsiBasisHidden, kPsiBasisHidden,
@@ -384,19 +431,10 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
         directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
         if (a.use_psi) {
-            // inputs [PE(w_o), PE(mu), l], lane's entries 16 kb + 4 q + i
+            // inputs [PE(w_o), PE(mu), l] in the lane-grouped order
             floatx4 x[4];
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 16 * kb + 4 * q + i;
-                    float v = 0.f;
-                    if (k < kPE) v = pe_entry(k, wo[0], wo[1], wo[2]);
-                    else if (k < 2 * kPE) v = pe_entry(k - kPE, mx, my, mz);
-                    else if (k < kPsiBasisIn) v = sc.latent[(size_t)(k - 2 * kPE) * n + g];
-                    x[kb][i] = v;
-                }
+            const float mu[3] = {mx, my, mz};
+            form_inputs(q, 0, 0.f, wo, mu, sc, g, x);
             floatx4 h1[MT], h2[MT], h3[MT];
             split_gemm<MT, 4>(sm + kPsiL1, lane, x, h1);
             bias_leaky<MT>(h1, a.psi.b[0], q);
@@ -408,8 +446,8 @@ __global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
                 for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int k = 16 * kb + 4 * q + i;
-                        if (k < kPsiBasisIn) R[(size_t)(kPsiB.x + k) * n + g] = x[kb][i];
+                        const int k = in_index(16 * kb + 4 * q + i, 0);
+                        if (k >= 0) R[(size_t)(kPsiB.x + k) * n + g] = x[kb][i];
                     }
                 store_d<MT>(R, kPsiB.h1, q, g, n, h1);
                 store_d<MT>(R, kPsiB.h2, q, g, n, h2);
@@ -464,7 +502,10 @@ __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
     if (a.use_phi) {
         const MlpArgs& m = a.phi;
         pack_split(sm + kPhiL1, kPhiBasisHidden, kXin,
-                   [&](int r, int c) { return c < kPhiBasisIn ? m.w[0][r * kPhiBasisIn + c] : 0.f; });
+                   [&](int r, int c) {
+                       const int k = in_index(c, 1);
+                       return k >= 0 ? m.w[0][r * kPhiBasisIn + k] : 0.f;
+                   });
         pack_split(sm + kPhiL2, kPhiBasisHidden, kPhiBasisHidden,
                    [&](int r, int c) { return m.w[1][r * kPhiBasisHidden + c]; });
         pack_split(sm + kPhiL3, kPhiBasisHidden, kPhiBasisHidden,
@@ -484,20 +525,10 @@ __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
             const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
             float wi[3], wo[3], ri, ro;
             directions(vw.light, vw.light_dir, vw.eye, mx, my, mz, wi, wo, &ri, &ro);
-            // inputs [T, PE(w_i), PE(mu), l]
+            // inputs [T, PE(w_i), PE(mu), l] in the lane-grouped order
             floatx4 x[4];
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 16 * kb + 4 * q + i;
-                    float v = 0.f;
-                    if (k == 0) v = Tg;
-                    else if (k <= kPE) v = pe_entry(k - 1, wi[0], wi[1], wi[2]);
-                    else if (k <= 2 * kPE) v = pe_entry(k - 1 - kPE, mx, my, mz);
-                    else if (k < kPhiBasisIn) v = sc.latent[(size_t)(k - 1 - 2 * kPE) * n + g];
-                    x[kb][i] = v;
-                }
+            const float mu[3] = {mx, my, mz};
+            form_inputs(q, 1, Tg, wi, mu, sc, g, x);
             floatx4 h1[MT], h2[MT], h3[MT];
             split_gemm<MT, 4>(sm + kPhiL1, lane, x, h1);
             bias_leaky<MT>(h1, a.phi.b[0], q);
@@ -512,8 +543,8 @@ __global__ __launch_bounds__(256) void k_basis_phi(BasisArgs a) {
                 for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int k = 16 * kb + 4 * q + i;
-                        if (k < kPhiBasisIn) R[(size_t)(kPhiB.x + k) * n + g] = x[kb][i];
+                        const int k = in_index(16 * kb + 4 * q + i, 1);
+                        if (k >= 0) R[(size_t)(kPhiB.x + k) * n + g] = x[kb][i];
                     }
                 store_d<MT>(R, kPhiB.h1, q, g, n, h1);
                 store_d<MT>(R, kPhiB.h2, q, g, n, h2);
@@ -854,6 +885,19 @@ static int grid_for(int64_t n, int per, int cap) {
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Workgroups of `threads` threads of a kernel (no dynamic LDS) that the
+// device holds at once: one round of a grid-stride launch, so that each
+// workgroup packs its weights into LDS once.
+template <typename Kernel>
+static int resident_blocks(Kernel kernel, int threads) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+        return 2048;
+    return (per < 1 ? 1 : per) * (cus < 1 ? 1 : cus);
+}
+
 hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, const float* const* T,
                                     const gs3_mlp* phi, const gs3_mlp* psi, const Layout* const* Ls,
                                     void* const* wss, float* const* colour, int parts, int nv, hipStream_t st) {
@@ -872,9 +916,8 @@ hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, 
             if (e != hipSuccess) return e;
         }
         if (parts & 2) {
-            // three 4-wave workgroups per CU (164 registers a lane): one round
-            // of 768 workgroups, each packing the weights once
-            hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, 768), m), dim3(256), 0, st, a);
+            static const int round = resident_blocks(k_basis_phi<false>, 256);
+            hipLaunchKernelGGL(k_basis_phi<false>, dim3(grid_for(sc.n, 4 * 16, round), m), dim3(256), 0, st, a);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -968,8 +1011,8 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
             return e;
     }
     if (phi) {
-        // two workgroups per CU at this kernel's 224 registers a lane
-        hipLaunchKernelGGL(k_basis_phi<true>, dim3(grid_for(n, 4 * 16, 512)), dim3(256), 0, st, a);
+        static const int round = resident_blocks(k_basis_phi<true>, 256);
+        hipLaunchKernelGGL(k_basis_phi<true>, dim3(grid_for(n, 4 * 16, round)), dim3(256), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         constexpr int P = kPhiBasisHidden / 16;
         if ((e = layer_bwd<P, P, true>(phi->w[2], kPhiBasisHidden, kPhiBasisHidden, rows, kPhiB.dz3, kPhiB.h2,
