@@ -399,8 +399,11 @@ __global__ __launch_bounds__(256) void k_basis_c(BasisArgs a) {
 // The residual r = Psi(w_o; mu, l) (Sec. 4.3). STORE: no colours; Psi's
 // layer inputs/outputs and its last hidden layer's pre-activation gradient
 // go to the scratch rows.
+// The forward runs 12 waves a CU (three a SIMD within its register
+// budget); STORE keeps more live and runs 8.
+constexpr int psi_threads(bool store) { return store ? 512 : 768; }
 template <bool STORE>
-__global__ __launch_bounds__(512) void k_basis_psi(BasisArgs a) {
+__global__ __launch_bounds__(psi_threads(STORE)) void k_basis_psi(BasisArgs a) {
     const ShadeView vw = a.v[blockIdx.y];
     __shared__ __align__(16) float sm[kPsiSmem];
     const SceneDev& sc = a.sc;
@@ -910,8 +913,9 @@ hipError_t launch_basis_shade_batch(const SceneDev& sc, const ShadeParams* sps, 
                      at<float4>(wss[v0 + i], Ls[v0 + i]->col1), colour[v0 + i]);
         if (parts & 1) {
             hipLaunchKernelGGL(k_basis_c, dim3(grid_for(sc.n, 256, 2048), m), dim3(256), 0, st, a);
-            // the Psi weights take the whole LDS: one 512-thread workgroup per CU
-            hipLaunchKernelGGL(k_basis_psi<false>, dim3(grid_for(sc.n, 8 * 16, 256), m), dim3(512), 0, st, a);
+            // the Psi weights take the whole LDS: one workgroup per CU
+            constexpr int T = psi_threads(false);
+            hipLaunchKernelGGL(k_basis_psi<false>, dim3(grid_for(sc.n, T / 4, 256), m), dim3(T), 0, st, a);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -997,7 +1001,8 @@ hipError_t launch_basis_shade_bwd(const SceneDev& sc, const ShadeParams& sp, con
     hipError_t e;
     // forward recompute with stored activations, output layers' adjoint
     if (psi) {
-        hipLaunchKernelGGL(k_basis_psi<true>, dim3(grid_for(n, 8 * 16, 256)), dim3(512), 0, st, a);
+        constexpr int T = psi_threads(true);
+        hipLaunchKernelGGL(k_basis_psi<true>, dim3(grid_for(n, T / 4, 256)), dim3(T), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         constexpr int P = kPsiBasisHidden / 16;
         if ((e = layer_bwd<P, P, true>(psi->w[2], kPsiBasisHidden, kPsiBasisHidden, rows, kPsiB.dz3, kPsiB.h2,
