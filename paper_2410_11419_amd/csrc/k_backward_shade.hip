@@ -339,9 +339,12 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     constexpr int CB = R / 16;        // column blocks
     __shared__ float sD[R][KB + 1];
     __shared__ float sH[R][KB + 1];
-    const WgProblem P = a.p[blockIdx.y];
+    // workgroup = chunk * count + problem: the problems of one chunk, which
+    // share its rows, run side by side and meet them in the caches
+    const int chunk = blockIdx.x / a.count;
+    const WgProblem P = a.p[blockIdx.x - chunk * a.count];
     const int n = a.n;
-    const int k0 = blockIdx.x * kWgChunk, k1 = min(n, k0 + kWgChunk);
+    const int k0 = chunk * kWgChunk, k1 = min(n, k0 + kWgChunk);
     const float* D = a.rows + (size_t)P.dz_row * n;
     const float* H = a.rows + (size_t)P.in_row * n;
     const int t = threadIdx.x, lane = __lane_id();
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
         }
         __syncthreads();
     }
-    float* part = a.partial + (size_t)blockIdx.x * a.total + P.off;
+    float* part = a.partial + (size_t)chunk * a.total + P.off;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int row0 = (R / 4) * w + 16 * rt;
@@ -903,10 +906,11 @@ hipError_t launch_wgrad(const WgSpec* specs, int count, const float* rows, int n
     w.n = n;
     w.partial = partial;
     const int chunks = (n + kWgChunk - 1) / kWgChunk;
+    const dim3 grid(chunks * w.count);
     if (widest > 64)
-        hipLaunchKernelGGL(k_wgrad<128>, dim3(chunks, w.count), dim3(256), 0, st, w);
+        hipLaunchKernelGGL(k_wgrad<128>, grid, dim3(256), 0, st, w);
     else
-        hipLaunchKernelGGL(k_wgrad<64>, dim3(chunks, w.count), dim3(256), 0, st, w);
+        hipLaunchKernelGGL(k_wgrad<64>, grid, dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((w.total + 63) / 64), dim3(256), 0, st, w, chunks);
     return hipGetLastError();
 }
