@@ -72,91 +72,6 @@ static_assert(kPsiSmem * 4 <= 160 * 1024, "Psi weights exceed the LDS");
 
 // ---------------------------------------------------------------- helpers
 
-// Pack A[r][c] (r < M a multiple of 16, c < K a multiple of 32) as split
-// MFMA A operands: entry (mt, kb) holds 512 floats, first the hi halves of
-// every lane (eight per lane, four floats) and then the lo halves, lane l
-// holding A[16 mt + l % 16][kcol(kb, l / 16, j)], j = 0..7.
-template <typename ElemFn>
-__device__ inline void pack_split(float* sm, int M, int K, ElemFn elem) {
-    const int KB = K / 32;
-    for (int idx = threadIdx.x; idx < (M / 16) * KB * 64; idx += blockDim.x) {
-        const int l = idx & 63, rest = idx >> 6, kb = rest % KB, mt = rest / KB;
-        _Float16 hv[16];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) split_half(elem(16 * mt + (l & 15), kcol(kb, l >> 4, j)), &hv[j], &hv[8 + j]);
-        float4 v[2];
-        __builtin_memcpy(v, hv, sizeof v);
-        float* e = sm + 512 * rest + 4 * l;
-        *reinterpret_cast<float4*>(e) = v[0];
-        *reinterpret_cast<float4*>(e + 256) = v[1];
-    }
-}
-
-// The B operand of a split product for the 16 Gaussians of the wave (x in
-// D layout, KB 16-wide k-blocks, KB even): each Gaussian's column scaled by
-// a power of two that brings its largest entry to [128, 256) and split
-// into halves, two 16-wide blocks per 32-wide one; `down` undoes the
-// scaling.
-template <int KB>
-struct SplitB {
-    static_assert(KB % 2 == 0, "k is a multiple of 32");
-    halfx8 h[KB / 2], l[KB / 2];
-    float down;
-};
-template <int KB>
-__device__ inline void split_cols(const floatx4* x, SplitB<KB>& b) {
-    float m = 0.f;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) m = fmaxf(m, fabsf(x[kb][i]));
-    m = fmaxf(m, __shfl_xor(m, 16, 64));
-    m = fmaxf(m, __shfl_xor(m, 32, 64));
-    // m = f 2^e with f in [0.5, 1): the scale 2^(8 - e)
-    const int e = m > 0.f ? max(ilogbf(m) + 1, -100) : 0;
-    const float up = ldexpf(1.f, 8 - e);
-    b.down = ldexpf(1.f, e - 8);
-#pragma unroll
-    for (int kb = 0; kb < KB / 2; ++kb)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            _Float16 hi, lo;
-            split_half(x[2 * kb + (j >> 2)][j & 3] * up, &hi, &lo);
-            b.h[kb][j] = hi;
-            b.l[kb][j] = lo;
-        }
-}
-
-// Output tiles mt0 .. mt0 + CH - 1 of A x (A packed by pack_split from KB
-// 16-wide k-blocks per row of tiles), D layout.
-template <int KB, int CH>
-__device__ inline void split_tiles(const float* sm, int lane, int mt0, const SplitB<KB>& b, floatx4* out) {
-    floatx4 cor[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) out[c] = cor[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < KB / 2; ++kb)
-#pragma unroll
-        for (int c = 0; c < CH; ++c)
-            mfma_split32(sm, 512 * ((mt0 + c) * (KB / 2) + kb) + 4 * lane, b.h[kb], b.l[kb], &out[c], &cor[c]);
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[c][i] = fmaf(cor[c][i], 1.f / 2048.f, out[c][i]) * b.down;
-}
-
-// out = A x for the 16 Gaussians of the wave (MT output tiles), two tiles
-// at a time so that only the split operand and two tiles' accumulators are
-// live beside the result.
-template <int MT, int KB>
-__device__ inline void split_gemm(const float* sm, int lane, const floatx4* x, floatx4* out) {
-    SplitB<KB> b;
-    split_cols<KB>(x, b);
-    constexpr int CH = MT % 2 == 0 ? 2 : 1;
-#pragma unroll
-    for (int mt = 0; mt < MT; mt += CH) split_tiles<KB, CH>(sm, lane, mt, b, out + mt);
-}
-
 __device__ inline float leaky(float z) { return z > 0.f ? z : kLeakySlope * z; }
 
 // h = leaky(z + b) in place, b the layer's bias (global memory, tiny and hot)

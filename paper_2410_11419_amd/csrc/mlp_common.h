@@ -23,7 +23,8 @@
 // layers. Activations above the half range (65504) are outside this
 // scheme's domain.
 // The adjoint recomputes the forward activations with the same routine (so
-// its ReLU masks are the forward's) and runs its own products in float32.
+// its ReLU masks are the forward's); its products W^T dz use the same split
+// form, each Gaussian's gradient column first scaled by a power of two.
 #pragma once
 
 #include "gs3_internal.h"
@@ -121,6 +122,91 @@ __device__ inline void mfma_split32(const float* sm, int off, halfx8 bh, halfx8 
     *d = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, *d, 0, 0, 0);
     *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, *dc, 0, 0, 0);
     *dc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, *dc, 0, 0, 0);
+}
+
+// Pack A[r][c] (r < M a multiple of 16, c < K a multiple of 32) as split
+// MFMA A operands: entry (mt, kb) holds 512 floats, first the hi halves of
+// every lane (eight per lane, four floats) and then the lo halves, lane l
+// holding A[16 mt + l % 16][kcol(kb, l / 16, j)], j = 0..7.
+template <typename ElemFn>
+__device__ inline void pack_split(float* sm, int M, int K, ElemFn elem) {
+    const int KB = K / 32;
+    for (int idx = threadIdx.x; idx < (M / 16) * KB * 64; idx += blockDim.x) {
+        const int l = idx & 63, rest = idx >> 6, kb = rest % KB, mt = rest / KB;
+        _Float16 hv[16];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) split_half(elem(16 * mt + (l & 15), kcol(kb, l >> 4, j)), &hv[j], &hv[8 + j]);
+        float4 v[2];
+        __builtin_memcpy(v, hv, sizeof v);
+        float* e = sm + 512 * rest + 4 * l;
+        *reinterpret_cast<float4*>(e) = v[0];
+        *reinterpret_cast<float4*>(e + 256) = v[1];
+    }
+}
+
+// The B operand of a split product for the 16 Gaussians of the wave (x in
+// D layout, KB 16-wide k-blocks, KB even): each Gaussian's column scaled by
+// a power of two that brings its largest entry to [128, 256) and split
+// into halves, two 16-wide blocks per 32-wide one; `down` undoes the
+// scaling.
+template <int KB>
+struct SplitB {
+    static_assert(KB % 2 == 0, "k is a multiple of 32");
+    halfx8 h[KB / 2], l[KB / 2];
+    float down;
+};
+template <int KB>
+__device__ inline void split_cols(const floatx4* x, SplitB<KB>& b) {
+    float m = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m = fmaxf(m, fabsf(x[kb][i]));
+    m = fmaxf(m, __shfl_xor(m, 16, 64));
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    // m = f 2^e with f in [0.5, 1): the scale 2^(8 - e)
+    const int e = m > 0.f ? max(ilogbf(m) + 1, -100) : 0;
+    const float up = ldexpf(1.f, 8 - e);
+    b.down = ldexpf(1.f, e - 8);
+#pragma unroll
+    for (int kb = 0; kb < KB / 2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            _Float16 hi, lo;
+            split_half(x[2 * kb + (j >> 2)][j & 3] * up, &hi, &lo);
+            b.h[kb][j] = hi;
+            b.l[kb][j] = lo;
+        }
+}
+
+// Output tiles mt0 .. mt0 + CH - 1 of A x (A packed by pack_split from KB
+// 16-wide k-blocks per row of tiles), D layout.
+template <int KB, int CH>
+__device__ inline void split_tiles(const float* sm, int lane, int mt0, const SplitB<KB>& b, floatx4* out) {
+    floatx4 cor[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) out[c] = cor[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB / 2; ++kb)
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            mfma_split32(sm, 512 * ((mt0 + c) * (KB / 2) + kb) + 4 * lane, b.h[kb], b.l[kb], &out[c], &cor[c]);
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[c][i] = fmaf(cor[c][i], 1.f / 2048.f, out[c][i]) * b.down;
+}
+
+// out = A x for the 16 Gaussians of the wave (MT output tiles), two tiles
+// at a time so that only the split operand and two tiles' accumulators are
+// live beside the result.
+template <int MT, int KB>
+__device__ inline void split_gemm(const float* sm, int lane, const floatx4* x, floatx4* out) {
+    SplitB<KB> b;
+    split_cols<KB>(x, b);
+    constexpr int CH = MT % 2 == 0 ? 2 : 1;
+#pragma unroll
+    for (int mt = 0; mt < MT; mt += CH) split_tiles<KB, CH>(sm, lane, mt, b, out + mt);
 }
 
 // Copy one MLP into LDS: hidden-layer and input-layer weights as split A
@@ -291,8 +377,9 @@ __device__ inline void mlp_hidden_all(const float* sm, const MlpSmem& S, int lan
     mlp_layers<KR, true>(sm, S, lane, x_of_k, h);
 }
 
-// LDS layout (floats) of one MLP's transposed weights for the adjoint:
-// W1^T as two 16-row tiles (input rows 0..31, zero past n_in), W2^T, W3^T.
+// LDS layout (floats) of one MLP's transposed weights for the adjoint, as
+// split operands packed by pack_split: W1^T as two 16-row tiles (input rows
+// 0..31, zero past n_in), W2^T, W3^T.
 struct MlpTSmem {
     int t1, t2, t3, size;
 };
@@ -300,40 +387,20 @@ __host__ __device__ constexpr MlpTSmem mlp_tsmem(int base) {
     return MlpTSmem{base, base + 2 * 16 * 64, base + 2 * 16 * 64 + kLH, 2 * 16 * 64 + 2 * kLH};
 }
 
-// Copy W^T into LDS in the A-operand order of the adjoint: for output tile
-// mt (rows j = 16 mt + l%16 of the layer's input) and k-step ks = 4 m + i
-// (contraction over the layer's output o = 16 m + 4 (l/16) + i), lane l
-// holds W[o][j].
+// Pack W^T into LDS: row j of the product is the layer's input j, the
+// contraction runs over the layer's outputs o.
 __device__ inline void load_mlp_t(float* sm, const MlpTSmem& T, int n_in, const MlpArgs& m) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int idx = tid; idx < 2 * 16 * 64; idx += nt) {
-        const int mt = idx / 1024, rem = idx % 1024, ks = rem / 64, l = rem % 64;
-        const int j = 16 * mt + (l & 15), o = 16 * (ks >> 2) + 4 * (l >> 4) + (ks & 3);
-        sm[T.t1 + idx] = j < n_in ? m.w[0][o * n_in + j] : 0.f;
-    }
-    for (int idx = tid; idx < kLH; idx += nt) {
-        const int mt = idx / 1024, rem = idx % 1024, ks = rem / 64, l = rem % 64;
-        const int j = 16 * mt + (l & 15), o = 16 * (ks >> 2) + 4 * (l >> 4) + (ks & 3);
-        sm[T.t2 + idx] = m.w[1][o * kHidden + j];
-        sm[T.t3 + idx] = m.w[2][o * kHidden + j];
-    }
+    pack_split(sm + T.t1, 32, kHidden, [&](int j, int o) { return j < n_in ? m.w[0][o * n_in + j] : 0.f; });
+    pack_split(sm + T.t2, kHidden, kHidden, [&](int j, int o) { return m.w[1][o * kHidden + j]; });
+    pack_split(sm + T.t3, kHidden, kHidden, [&](int j, int o) { return m.w[2][o * kHidden + j]; });
 }
 
-// d = W^T g for a 64-wide g in D layout, TILES output tiles of 16 rows.
+// d = W^T g for a 64-wide g in D layout, TILES output tiles of 16 rows: the
+// split product of the forward, each Gaussian's gradient column scaled by a
+// power of two before the split (gradients can be of any size).
 template <int TILES>
 __device__ inline void mlp_back_layer(const float* sm, int off, int lane, const floatx4 g[4], floatx4 d[TILES]) {
-#pragma unroll
-    for (int mt = 0; mt < TILES; ++mt) d[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ks = 4 * m + i;
-#pragma unroll
-            for (int mt = 0; mt < TILES; ++mt)
-                d[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sm[off + (mt * 16 + ks) * 64 + lane], g[m][i], d[mt], 0,
-                                                             0, 0);
-        }
+    split_gemm<TILES, 4>(sm + off, lane, g, d);
 }
 
 // Adjoint of the hidden layers. In: dh3 = dL/dh3 (D layout) and the

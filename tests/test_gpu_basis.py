@@ -3,10 +3,10 @@ anisotropic basis angular Gaussians, Sec. 4.1; Phi {32}^3 and Psi {128}^3
 with positional encoding, latent and leaky ReLU, Sec. 4.2-4.3) against the
 FP64 oracle, through the C-ABI.
 
-- full renders (small cube scene with a point light, a ragged shell scene
-  with a directional light): shadow values, per-Gaussian c, T', r and every
-  pixel of every image within 1e-4, flagged threshold decisions resolved as
-  in the other parity tests;
+- full renders (small cube scene with a point light, the same moved far
+  from the origin, a ragged shell scene with a directional light): shadow
+  values, per-Gaussian c, T', r and every pixel of every image within 1e-4,
+  flagged threshold decisions resolved as in the other parity tests;
 - per-Gaussian c, T', r of all 300,000 Gaussians of the full-size basis
   scene (camera 800^2, light 1024^2), with the GPU's T as Phi's input;
 - the MLPs over hidden activations rescaled by 1e-3 and 1e3 (a
@@ -50,6 +50,19 @@ def test_basis_render_parity_directional_ragged(gs3):
     cam = synth.make_view(rng.standard_normal(3), 4.0, 200, 152, 40.0)     # ragged tiles
     light = synth.make_directional(rng.standard_normal(3), 176, 176, 2.4)
     _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "basis_directional")
+
+
+def test_basis_render_translated_scene(gs3):
+    # the scene, camera and light moved far from the origin: the encoding of
+    # mu then spans tens of turns per band (2^(j-1) mu), which the kernels
+    # reduce to [-1/2, 1/2] turns before the hardware sine and cosine
+    sc, cam, light = synth.scene_basis_small(seed=6, n=3000)
+    off = np.array([24.5, -17.25, 11.0])
+    sc.mean = (sc.mean + off[:, None]).astype(np.float32)
+    cam = synth.View(eye=cam.eye + off, target=cam.target + off, width=cam.width, height=cam.height, fov=cam.fov)
+    light = synth.View(eye=light.eye + off, target=light.target + off, width=light.width, height=light.height,
+                       fov=light.fov)
+    _compare_render(gs3, sc, cam, light, O.Consts(), gs3.default_consts(), True, "basis_translated")
 
 
 def test_basis_render_without_mlps(gs3):
