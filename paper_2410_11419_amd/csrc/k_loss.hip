@@ -59,7 +59,8 @@ __global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ par
     if (threadIdx.x == 0) *loss = (float)(t * (double)scale);
 }
 
-int64_t l1_chunks(int64_t count) { return (count + kL1Chunk - 1) / kL1Chunk; }
+// ceil(count / kL1Chunk) for count >= 0, without overflow near INT64_MAX
+int64_t l1_chunks(int64_t count) { return count / kL1Chunk + (count % kL1Chunk != 0 ? 1 : 0); }
 
 hipError_t launch_l1_loss(const float* pred, const float* target, int64_t count, float scale, float* loss,
                           float* grad, double* partial, hipStream_t st) {
