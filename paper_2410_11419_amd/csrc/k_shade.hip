@@ -1,11 +1,11 @@
 // Per-Gaussian appearance: the first splat (Sec. 4.1, Eq. 4-7), the shadow
 // refinement MLP Phi (Sec. 4.2, Eq. 8) and the residual MLP Psi (Sec. 4.3).
 //
-// A wave handles 16 Gaussians, four lanes per Gaussian: lane l works on
-// Gaussian l % 16 and lobe quarter q = l / 16 (lobes q, q+4, ...), which is
-// the operand layout of the MFMA MLPs (mlp_common.h). The one- and
-// three-wide output layers run on the VALU (16 FMAs per lane and a
-// cross-lane sum over the four quarters).
+// k_shade_c evaluates the shading one Gaussian per lane. k_shade_mlp runs
+// the MLPs: a wave handles 16 Gaussians, four lanes per Gaussian (lane l:
+// Gaussian l % 16, quarter q = l / 16), which is the operand layout of the
+// MFMA MLPs (mlp_common.h). The one- and three-wide output layers run on
+// the VALU (16 FMAs per lane and a cross-lane sum over the four quarters).
 #include "mlp_common.h"
 
 namespace gs3 {
@@ -23,33 +23,23 @@ struct ShadeArgs {
     ShadeView v[kMaxBatch];
 };
 
-__global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
-    __shared__ __align__(16) float sm[kShadeSmem];
+// Shading c (Eq. 4-7) of the view blockIdx.y, one Gaussian per lane over
+// all its lobes. Writes c to col0.xyz and colour rows 0..2; k_shade_mlp
+// adds T' (col0.w, row 3) and r (col1, rows 4..7).
+__global__ __launch_bounds__(256) void k_shade_c(ShadeArgs a) {
     const SceneDev& sc = a.sc;
     const ShadeView vw = a.v[blockIdx.y];
     const int n = sc.n;
-    if (a.use_phi) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
-    if (a.use_psi) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
-    __syncthreads();
-    const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4;
-    const int waves = blockDim.x >> 6;
     const float kd = 0.01f * (1.f - 0.36787944117144233f);   // eps (1 - 1/e), Eq. 5
     const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
-    for (int base = (blockIdx.x * waves + w) * 16; base < n; base += gridDim.x * waves * 16) {
-        const int g_raw = base + (lane & 15);
-        const bool valid = g_raw < n;
-        const int g = valid ? g_raw : n - 1;
-        float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-        float wix = 0.f, wiy = 0.f, wiz = 0.f, wox = 0.f, woy = 0.f, woz = 0.f;
-        if (a.parts & kShadePsi) {
-        // ---- shading (Eq. 4-7)
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
         // w_i: toward a point light, or a directional light's fixed direction
         const float lm = vw.light_dir ? 0.f : 1.f;
-        wix = vw.light[0] - lm * mx; wiy = vw.light[1] - lm * my; wiz = vw.light[2] - lm * mz;
+        float wix = vw.light[0] - lm * mx, wiy = vw.light[1] - lm * my, wiz = vw.light[2] - lm * mz;
         float r = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
         wix *= r; wiy *= r; wiz *= r;
-        wox = vw.eye[0] - mx; woy = vw.eye[1] - my; woz = vw.eye[2] - mz;
+        float wox = vw.eye[0] - mx, woy = vw.eye[1] - my, woz = vw.eye[2] - mz;
         r = rsqrtf(wox * wox + woy * woy + woz * woz);
         wox *= r; woy *= r; woz *= r;
         float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
@@ -79,7 +69,7 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
         // isotropic angular Gaussians (Eq. 7 with sigma_x = sigma_y):
         // G = lambda exp(-(lambda theta)^2 / 2), theta = angle(h', z_k)
         float sp0 = 0.f, sp1 = 0.f, sp2 = 0.f;
-        for (int kl = q; kl < sc.k; kl += 4) {
+        for (int kl = 0; kl < sc.k; ++kl) {
             const float* ax = sc.lobe_axis + (size_t)kl * 3 * n;
             float zx = ax[g], zy = ax[n + g], zz = ax[2 * n + g];
             r = rsqrtf(zx * zx + zy * zy + zz * zz);
@@ -95,12 +85,44 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
             sp1 = fmaf(am[n + g], G, sp1);
             sp2 = fmaf(am[2 * n + g], G, sp2);
         }
-        sp0 += __shfl_xor(sp0, 16, 64); sp0 += __shfl_xor(sp0, 32, 64);
-        sp1 += __shfl_xor(sp1, 16, 64); sp1 += __shfl_xor(sp1, 32, 64);
-        sp2 += __shfl_xor(sp2, 16, 64); sp2 += __shfl_xor(sp2, 32, 64);
-        c0 = fmaf(sc.albedo[g], fd, sp0);
-        c1 = fmaf(sc.albedo[n + g], fd, sp1);
-        c2 = fmaf(sc.albedo[2 * n + g], fd, sp2);
+        const float c0 = fmaf(sc.albedo[g], fd, sp0);
+        const float c1 = fmaf(sc.albedo[n + g], fd, sp1);
+        const float c2 = fmaf(sc.albedo[2 * n + g], fd, sp2);
+        float* c0p = reinterpret_cast<float*>(vw.col0 + g);
+        c0p[0] = c0;
+        c0p[1] = c1;
+        c0p[2] = c2;
+        vw.colour[g] = c0;
+        vw.colour[(size_t)n + g] = c1;
+        vw.colour[(size_t)2 * n + g] = c2;
+    }
+}
+
+__global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
+    __shared__ __align__(16) float sm[kShadeSmem];
+    const SceneDev& sc = a.sc;
+    const ShadeView vw = a.v[blockIdx.y];
+    const int n = sc.n;
+    if (a.use_phi) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
+    if (a.use_psi) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
+    __syncthreads();
+    const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4;
+    const int waves = blockDim.x >> 6;
+    for (int base = (blockIdx.x * waves + w) * 16; base < n; base += gridDim.x * waves * 16) {
+        const int g_raw = base + (lane & 15);
+        const bool valid = g_raw < n;
+        const int g = valid ? g_raw : n - 1;
+        // ---- directions, Psi's inputs (the shading c is k_shade_c's)
+        float wix = 0.f, wiy = 0.f, wiz = 0.f, wox = 0.f, woy = 0.f, woz = 0.f;
+        if ((a.parts & kShadePsi) && a.use_psi) {
+            const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
+            const float lm = vw.light_dir ? 0.f : 1.f;
+            wix = vw.light[0] - lm * mx; wiy = vw.light[1] - lm * my; wiz = vw.light[2] - lm * mz;
+            float r = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
+            wix *= r; wiy *= r; wiz *= r;
+            wox = vw.eye[0] - mx; woy = vw.eye[1] - my; woz = vw.eye[2] - mz;
+            r = rsqrtf(wox * wox + woy * woy + woz * woz);
+            wox *= r; woy *= r; woz *= r;
         }
         // ---- shadow refinement Phi([T, feat]) (Eq. 8)
         float tp = 0.f;
@@ -138,29 +160,13 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
             r2 = mlp_out(sm, kPsiS, lane, h, 2);
         }
         if (valid) {
-            float* c0p = reinterpret_cast<float*>(vw.col0 + g);
-            if (a.parts == (kShadePsi | kShadePhi)) {
-                if (q == 0) {
-                    vw.col0[g] = make_float4(c0, c1, c2, tp);
-                    vw.col1[g] = make_float4(r0, r1, r2, 0.f);
-                }
-                const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
-                const float v1 = q == 0 ? c1 : (q == 1 ? tp : (q == 2 ? r1 : 0.f));
-                vw.colour[(size_t)(2 * q) * n + g] = v0;
-                vw.colour[(size_t)(2 * q + 1) * n + g] = v1;
-            } else if (a.parts == kShadePsi) {
-                // colour rows 0..2 (c), 4..6 (r), 7 (0); col0.w is Phi's
-                if (q == 0) {
-                    c0p[0] = c0;
-                    c0p[1] = c1;
-                    c0p[2] = c2;
-                    vw.col1[g] = make_float4(r0, r1, r2, 0.f);
-                }
-                const float v0 = q == 0 ? c0 : (q == 1 ? c2 : (q == 2 ? r0 : r2));
-                vw.colour[(size_t)(2 * q) * n + g] = v0;
-                if (q != 1) vw.colour[(size_t)(2 * q + 1) * n + g] = q == 0 ? c1 : (q == 2 ? r1 : 0.f);
-            } else if (q == 0) {
-                c0p[3] = tp;
+            // r: col1 and colour rows 4..7 (row 7 = 0); T': col0.w and row 3
+            if (a.parts & kShadePsi) {
+                if (q == 0) vw.col1[g] = make_float4(r0, r1, r2, 0.f);
+                vw.colour[(size_t)(4 + q) * n + g] = q == 0 ? r0 : (q == 1 ? r1 : (q == 2 ? r2 : 0.f));
+            }
+            if ((a.parts & kShadePhi) && q == 0) {
+                reinterpret_cast<float*>(vw.col0 + g)[3] = tp;
                 vw.colour[(size_t)3 * n + g] = tp;
             }
         }
@@ -199,6 +205,10 @@ hipError_t launch_shade_mlp_batch(const SceneDev& sc, const ShadeParams* sps, co
             w.col0 = at<float4>(wss[v0 + i], Ls[v0 + i]->col0);
             w.col1 = at<float4>(wss[v0 + i], Ls[v0 + i]->col1);
             w.colour = colour[v0 + i];
+        }
+        if (parts & kShadePsi) {
+            const int64_t gc = (sc.n + 255) / 256;
+            hipLaunchKernelGGL(k_shade_c, dim3((unsigned)(gc < 2048 ? gc : 2048), m), dim3(256), 0, st, a);
         }
         hipLaunchKernelGGL(k_shade_mlp, dim3(grid, m), dim3(512), 0, st, a);
         hipError_t e = hipGetLastError();
