@@ -103,8 +103,9 @@ __global__ __launch_bounds__(512, 4) void k_shade_mlp(ShadeArgs a) {
     const SceneDev& sc = a.sc;
     const ShadeView vw = a.v[blockIdx.y];
     const int n = sc.n;
-    if (a.use_phi) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
-    if (a.use_psi) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
+    // only the MLPs this launch evaluates
+    if (a.use_phi && (a.parts & kShadePhi)) load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
+    if (a.use_psi && (a.parts & kShadePsi)) load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
     __syncthreads();
     const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4;
     const int waves = blockDim.x >> 6;
