@@ -164,8 +164,9 @@ __device__ inline void split_cols(const floatx4* x, SplitB<KB>& b) {
         for (int i = 0; i < 4; ++i) m = fmaxf(m, fabsf(x[kb][i]));
     m = fmaxf(m, __shfl_xor(m, 16, 64));
     m = fmaxf(m, __shfl_xor(m, 32, 64));
-    // m = f 2^e with f in [0.5, 1): the scale 2^(8 - e)
-    const int e = m > 0.f ? max(ilogbf(m) + 1, -100) : 0;
+    // m = f 2^e with f in [0.5, 1): the scale 2^(8 - e) (none for a zero
+    // or infinite column, which then passes through as in float32)
+    const int e = (m > 0.f && m < __builtin_inff()) ? max(ilogbf(m) + 1, -100) : 0;
     const float up = ldexpf(1.f, 8 - e);
     b.down = ldexpf(1.f, e - 8);
 #pragma unroll
