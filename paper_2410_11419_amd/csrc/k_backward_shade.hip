@@ -20,7 +20,10 @@ __host__ __device__ constexpr MlpRows mlp_rows(int base, int n_in, int n_out) {
 constexpr MlpRows kPhiRows = mlp_rows(0, kPhiIn, 1);
 constexpr MlpRows kPsiRows = mlp_rows(kPhiRows.size, kPsiIn, 3);
 constexpr int kMlpRows = kPhiRows.size + kPsiRows.size;
-int mlp_scratch_rows() { return kMlpRows; }
+// after the MLP rows: dL/dh (3 rows), the lobes' gradient of the normalised
+// half vector, from k_shade_bwd_lobes to k_shade_bwd
+constexpr int kDhRow = kMlpRows;
+int mlp_scratch_rows() { return kMlpRows + 3; }
 
 constexpr MlpTSmem kPhiT = mlp_tsmem(kShadeSmem);
 constexpr MlpTSmem kPsiT = mlp_tsmem(kShadeSmem + kPhiT.size);
@@ -40,6 +43,88 @@ struct ShadeBwdArgs {
     GradDev g;           // += scene gradients (shading part)
     float* rows;         // [kMlpRows][n] MLP scratch (inputs, output-layer gradients)
 };
+
+// The lobes' part of the shading adjoint (Eq. 7), one Gaussian per lane at
+// full occupancy: the gradients of every lobe's amplitude, sharpness and
+// axis, and dL/dh (the normalised half vector's gradient) into the scratch
+// rows for k_shade_bwd, which adds the rest of the shading adjoint.
+__global__ __launch_bounds__(256) void k_shade_bwd_lobes(ShadeBwdArgs a) {
+    const SceneDev& sc = a.sc;
+    const int n = sc.n;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+        // ---- the half vector, recomputed as in the forward
+        const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
+        // w_i: toward a point light, or a directional light's fixed direction
+        const float lm = a.light_dir ? 0.f : 1.f;
+        float wix = a.light[0] - lm * mx, wiy = a.light[1] - lm * my, wiz = a.light[2] - lm * mz;
+        const float ri = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
+        wix *= ri; wiy *= ri; wiz *= ri;
+        float wox = a.eye[0] - mx, woy = a.eye[1] - my, woz = a.eye[2] - mz;
+        const float ro = rsqrtf(wox * wox + woy * woy + woz * woz);
+        wox *= ro; woy *= ro; woz *= ro;
+        float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
+        const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        const float rq = 1.f / qn;
+        qw *= rq; qx *= rq; qy *= rq; qz *= rq;
+        const float R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
+        const float R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
+        const float R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
+        const float lix = R00 * wix + R01 * wiy + R02 * wiz;
+        const float liy = R10 * wix + R11 * wiy + R12 * wiz;
+        const float liz = R20 * wix + R21 * wiy + R22 * wiz;
+        const float lox = R00 * wox + R01 * woy + R02 * woz;
+        const float loy = R10 * wox + R11 * woy + R12 * woz;
+        const float loz = R20 * wox + R21 * woy + R22 * woz;
+        float hx = lix + lox, hy = liy + loy, hz = liz + loz;
+        const float hn2 = hx * hx + hy * hy + hz * hz;
+        if (hn2 > 1e-24f) {
+            const float rh = rsqrtf(hn2);
+            hx *= rh; hy *= rh; hz *= rh;
+        } else {
+            hx = 0.f; hy = 0.f; hz = 1.f;
+        }
+        const float dc0 = a.gcol[g], dc1 = a.gcol[(size_t)n + g], dc2 = a.gcol[(size_t)2 * n + g];
+        // ---- lobes (Eq. 7): G = lambda exp(-(lambda theta)^2 / 2)
+        float dhx = 0.f, dhy = 0.f, dhz = 0.f;
+        for (int kl = 0; kl < sc.k; ++kl) {
+            const size_t ab = (size_t)kl * 3 * n;
+            const float ax = sc.lobe_axis[ab + g], ay = sc.lobe_axis[ab + n + g], az = sc.lobe_axis[ab + 2 * n + g];
+            const float ra = rsqrtf(ax * ax + ay * ay + az * az);
+            const float zx = ax * ra, zy = ay * ra, zz = az * ra;
+            const float cz = hx * zx + hy * zy + hz * zz;
+            const float cx = hy * zz - hz * zy, cy = hz * zx - hx * zz, cw = hx * zy - hy * zx;
+            const float sn = sqrtf(cx * cx + cy * cy + cw * cw);
+            const float theta = atan2f(sn, cz);
+            const float lam = expf(sc.lobe_log_sharp[(size_t)kl * n + g]);
+            const float t = lam * theta;
+            const float ex = expf(-0.5f * t * t);
+            const float G = lam * ex;
+            const float am0 = sc.lobe_amp[ab + g], am1 = sc.lobe_amp[ab + n + g], am2 = sc.lobe_amp[ab + 2 * n + g];
+            const float dG = fmaf(dc0, am0, fmaf(dc1, am1, dc2 * am2));
+            // dtheta/dh = -(z - cz h)/sin(theta); dG/dtheta = -lam^3 theta ex
+            const float ratio = sn > 1e-6f ? theta / sn : 1.f;
+            const float coef = dG * lam * lam * lam * ex * ratio;
+            dhx = fmaf(coef, zx - cz * hx, dhx);
+            dhy = fmaf(coef, zy - cz * hy, dhy);
+            dhz = fmaf(coef, zz - cz * hz, dhz);
+            float dzx = coef * (hx - cz * zx), dzy = coef * (hy - cz * zy), dzz = coef * (hz - cz * zz);
+            const float dzd = dzx * zx + dzy * zy + dzz * zz;
+            dzx = (dzx - dzd * zx) * ra;
+            dzy = (dzy - dzd * zy) * ra;
+            dzz = (dzz - dzd * zz) * ra;
+            a.g.lobe_amp[ab + g] += dc0 * G;
+            a.g.lobe_amp[ab + n + g] += dc1 * G;
+            a.g.lobe_amp[ab + 2 * n + g] += dc2 * G;
+            a.g.lobe_log_sharp[(size_t)kl * n + g] += dG * ex * (1.f - t * t) * lam;
+            a.g.lobe_axis[ab + g] += dzx;
+            a.g.lobe_axis[ab + n + g] += dzy;
+            a.g.lobe_axis[ab + 2 * n + g] += dzz;
+        }
+        a.rows[(size_t)kDhRow * n + g] = dhx;
+        a.rows[(size_t)(kDhRow + 1) * n + g] = dhy;
+        a.rows[(size_t)(kDhRow + 2) * n + g] = dhz;
+    }
+}
 
 __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
     __shared__ __align__(16) float sm[kShadeBwdSmem];
@@ -105,47 +190,10 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         const float dc0 = a.gcol[g], dc1 = a.gcol[(size_t)n + g], dc2 = a.gcol[(size_t)2 * n + g];
         const float dtp = a.gcol[(size_t)3 * n + g];
         const float dr0 = a.gcol[(size_t)4 * n + g], dr1 = a.gcol[(size_t)5 * n + g], dr2 = a.gcol[(size_t)6 * n + g];
-        // ---- lobes (Eq. 7): G = lambda exp(-(lambda theta)^2 / 2)
-        float dhx = 0.f, dhy = 0.f, dhz = 0.f;
-        for (int kl = q; kl < sc.k; kl += 4) {
-            const size_t ab = (size_t)kl * 3 * n;
-            const float ax = sc.lobe_axis[ab + g], ay = sc.lobe_axis[ab + n + g], az = sc.lobe_axis[ab + 2 * n + g];
-            const float ra = rsqrtf(ax * ax + ay * ay + az * az);
-            const float zx = ax * ra, zy = ay * ra, zz = az * ra;
-            const float cz = hx * zx + hy * zy + hz * zz;
-            const float cx = hy * zz - hz * zy, cy = hz * zx - hx * zz, cw = hx * zy - hy * zx;
-            const float sn = sqrtf(cx * cx + cy * cy + cw * cw);
-            const float theta = atan2f(sn, cz);
-            const float lam = expf(sc.lobe_log_sharp[(size_t)kl * n + g]);
-            const float t = lam * theta;
-            const float ex = expf(-0.5f * t * t);
-            const float G = lam * ex;
-            const float am0 = sc.lobe_amp[ab + g], am1 = sc.lobe_amp[ab + n + g], am2 = sc.lobe_amp[ab + 2 * n + g];
-            const float dG = fmaf(dc0, am0, fmaf(dc1, am1, dc2 * am2));
-            // dtheta/dh = -(z - cz h)/sin(theta); dG/dtheta = -lam^3 theta ex
-            const float ratio = sn > 1e-6f ? theta / sn : 1.f;
-            const float coef = dG * lam * lam * lam * ex * ratio;
-            dhx = fmaf(coef, zx - cz * hx, dhx);
-            dhy = fmaf(coef, zy - cz * hy, dhy);
-            dhz = fmaf(coef, zz - cz * hz, dhz);
-            float dzx = coef * (hx - cz * zx), dzy = coef * (hy - cz * zy), dzz = coef * (hz - cz * zz);
-            const float dzd = dzx * zx + dzy * zy + dzz * zz;
-            dzx = (dzx - dzd * zx) * ra;
-            dzy = (dzy - dzd * zy) * ra;
-            dzz = (dzz - dzd * zz) * ra;
-            if (valid) {
-                a.g.lobe_amp[ab + g] += dc0 * G;
-                a.g.lobe_amp[ab + n + g] += dc1 * G;
-                a.g.lobe_amp[ab + 2 * n + g] += dc2 * G;
-                a.g.lobe_log_sharp[(size_t)kl * n + g] += dG * ex * (1.f - t * t) * lam;
-                a.g.lobe_axis[ab + g] += dzx;
-                a.g.lobe_axis[ab + n + g] += dzy;
-                a.g.lobe_axis[ab + 2 * n + g] += dzz;
-            }
-        }
-        dhx += __shfl_xor(dhx, 16, 64); dhx += __shfl_xor(dhx, 32, 64);
-        dhy += __shfl_xor(dhy, 16, 64); dhy += __shfl_xor(dhy, 32, 64);
-        dhz += __shfl_xor(dhz, 16, 64); dhz += __shfl_xor(dhz, 32, 64);
+        // ---- dL/dh of the lobes (Eq. 7), from k_shade_bwd_lobes
+        const float dhx = a.rows[(size_t)kDhRow * n + g];
+        const float dhy = a.rows[(size_t)(kDhRow + 1) * n + g];
+        const float dhz = a.rows[(size_t)(kDhRow + 2) * n + g];
         // ---- Phi([T, feat]) adjoint
         const float Tg = a.T[g];
         float dTg = dtp;
@@ -835,6 +883,8 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     const int per_block = 8 * 16;
     int grid = (int)((sc.n + per_block - 1) / per_block);
     if (grid > 512) grid = 512;
+    const int64_t gl = (sc.n + 255) / 256;
+    hipLaunchKernelGGL(k_shade_bwd_lobes, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(512), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!phi && !psi)) return e;
