@@ -20,10 +20,10 @@ __host__ __device__ constexpr MlpRows mlp_rows(int base, int n_in, int n_out) {
 constexpr MlpRows kPhiRows = mlp_rows(0, kPhiIn, 1);
 constexpr MlpRows kPsiRows = mlp_rows(kPhiRows.size, kPsiIn, 3);
 constexpr int kMlpRows = kPhiRows.size + kPsiRows.size;
-// after the MLP rows: dL/dh (3 rows), the lobes' gradient of the normalised
-// half vector, from k_shade_bwd_lobes to k_shade_bwd
-constexpr int kDhRow = kMlpRows;
-int mlp_scratch_rows() { return kMlpRows + 3; }
+// after the MLP rows: Psi's gradient of its direction inputs w_i, w_o (6
+// rows), from k_shade_bwd to k_shade_bwd_geom
+constexpr int kDwRow = kMlpRows;
+int mlp_scratch_rows() { return kMlpRows + 6; }
 
 constexpr MlpTSmem kPhiT = mlp_tsmem(kShadeSmem);
 constexpr MlpTSmem kPsiT = mlp_tsmem(kShadeSmem + kPhiT.size);
@@ -44,15 +44,18 @@ struct ShadeBwdArgs {
     float* rows;         // [kMlpRows][n] MLP scratch (inputs, output-layer gradients)
 };
 
-// The lobes' part of the shading adjoint (Eq. 7), one Gaussian per lane at
-// full occupancy: the gradients of every lobe's amplitude, sharpness and
-// axis, and dL/dh (the normalised half vector's gradient) into the scratch
-// rows for k_shade_bwd, which adds the rest of the shading adjoint.
-__global__ __launch_bounds__(256) void k_shade_bwd_lobes(ShadeBwdArgs a) {
+// The shading adjoint outside the MLPs, one Gaussian per lane at full
+// occupancy, after k_shade_bwd: the lobes (Eq. 7: amplitude, sharpness and
+// axis gradients), the Lambertian term (Eq. 5, albedo), the half vector and
+// shading frame (Eq. 6, shading quaternion) and the directions, with Psi's
+// gradient of its w_i, w_o inputs from the scratch rows (mean).
+__global__ __launch_bounds__(256) void k_shade_bwd_geom(ShadeBwdArgs a) {
     const SceneDev& sc = a.sc;
     const int n = sc.n;
+    const float kd = 0.01f * (1.f - 0.36787944117144233f);
+    const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-        // ---- the half vector, recomputed as in the forward
+        // ---- forward recompute of the shading inputs
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
         // w_i: toward a point light, or a directional light's fixed direction
         const float lm = a.light_dir ? 0.f : 1.f;
@@ -75,10 +78,15 @@ __global__ __launch_bounds__(256) void k_shade_bwd_lobes(ShadeBwdArgs a) {
         const float lox = R00 * wox + R01 * woy + R02 * woz;
         const float loy = R10 * wox + R11 * woy + R12 * woz;
         const float loz = R20 * wox + R21 * woy + R22 * woz;
+        const float elu = liz > 0.f ? liz : 0.01f * (expf(fminf(liz, 0.f)) - 1.f);
+        const float delu = liz > 0.f ? 1.f : 0.01f * expf(fminf(liz, 0.f));
+        const float fd = (elu + kd) * fd_norm;
         float hx = lix + lox, hy = liy + loy, hz = liz + loz;
         const float hn2 = hx * hx + hy * hy + hz * hz;
-        if (hn2 > 1e-24f) {
-            const float rh = rsqrtf(hn2);
+        const bool hok = hn2 > 1e-24f;
+        float rh = 0.f;
+        if (hok) {
+            rh = rsqrtf(hn2);
             hx *= rh; hy *= rh; hz *= rh;
         } else {
             hx = 0.f; hy = 0.f; hz = 1.f;
@@ -120,9 +128,46 @@ __global__ __launch_bounds__(256) void k_shade_bwd_lobes(ShadeBwdArgs a) {
             a.g.lobe_axis[ab + n + g] += dzy;
             a.g.lobe_axis[ab + 2 * n + g] += dzz;
         }
-        a.rows[(size_t)kDhRow * n + g] = dhx;
-        a.rows[(size_t)(kDhRow + 1) * n + g] = dhy;
-        a.rows[(size_t)(kDhRow + 2) * n + g] = dhz;
+        // ---- Lambertian, half vector, frames and directions
+        const float alb0 = sc.albedo[g], alb1 = sc.albedo[n + g], alb2 = sc.albedo[2 * n + g];
+        const float dfd = fmaf(dc0, alb0, fmaf(dc1, alb1, dc2 * alb2));
+        float dhsx = 0.f, dhsy = 0.f, dhsz = 0.f;
+        if (hok) {
+            const float dd = dhx * hx + dhy * hy + dhz * hz;
+            dhsx = (dhx - dd * hx) * rh;
+            dhsy = (dhy - dd * hy) * rh;
+            dhsz = (dhz - dd * hz) * rh;
+        }
+        const float dlix = dhsx, dliy = dhsy, dliz = dhsz + dfd * fd_norm * delu;
+        const float dlox = dhsx, dloy = dhsy, dloz = dhsz;
+        const float dR[9] = {dlix * wix + dlox * wox, dlix * wiy + dlox * woy, dlix * wiz + dlox * woz,
+                             dliy * wix + dloy * wox, dliy * wiy + dloy * woy, dliy * wiz + dloy * woz,
+                             dliz * wix + dloz * wox, dliz * wiy + dloz * woy, dliz * wiz + dloz * woz};
+        float dq[4];
+        quat_grad(qw, qx, qy, qz, qn, dR, dq);
+        // world directions: R^T dl plus Psi's direct inputs
+        const float* pw = a.rows + (size_t)kDwRow * n + g;
+        const float dwx = R00 * dlix + R10 * dliy + R20 * dliz + pw[0];
+        const float dwy = R01 * dlix + R11 * dliy + R21 * dliz + pw[(size_t)n];
+        const float dwz = R02 * dlix + R12 * dliy + R22 * dliz + pw[(size_t)2 * n];
+        const float dox = R00 * dlox + R10 * dloy + R20 * dloz + pw[(size_t)3 * n];
+        const float doy = R01 * dlox + R11 * dloy + R21 * dloz + pw[(size_t)4 * n];
+        const float doz = R02 * dlox + R12 * dloy + R22 * dloz + pw[(size_t)5 * n];
+        // w = (p - mu)/|p - mu|: dmu = -(dw - (dw.w) w) / |p - mu|; a
+        // directional light's w_i does not depend on mu
+        const float wd = dwx * wix + dwy * wiy + dwz * wiz;
+        const float od = dox * wox + doy * woy + doz * woz;
+        const float rim = lm * ri;
+        a.g.albedo[g] += dc0 * fd;
+        a.g.albedo[n + g] += dc1 * fd;
+        a.g.albedo[2 * n + g] += dc2 * fd;
+        a.g.shade_rot[g] += dq[0];
+        a.g.shade_rot[n + g] += dq[1];
+        a.g.shade_rot[2 * n + g] += dq[2];
+        a.g.shade_rot[3 * n + g] += dq[3];
+        a.g.mean[g] += -(dwx - wd * wix) * rim - (dox - od * wox) * ro;
+        a.g.mean[n + g] += -(dwy - wd * wiy) * rim - (doy - od * woy) * ro;
+        a.g.mean[2 * n + g] += -(dwz - wd * wiz) * rim - (doz - od * woz) * ro;
     }
 }
 
@@ -141,8 +186,6 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
     __syncthreads();
     const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4, l16 = lane & 15;
     const int waves = blockDim.x >> 6;
-    const float kd = 0.01f * (1.f - 0.36787944117144233f);
-    const float fd_norm = 1.f / ((1.f + kd) * 3.14159265358979f);
     for (int base = (blockIdx.x * waves + w) * 16; base < n; base += gridDim.x * waves * 16) {
         // keeps the weight operands' LDS reads inside the loop: hoisted out of
         // it they would need several hundred registers
@@ -150,9 +193,8 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         const int g_raw = base + l16;
         const bool valid = g_raw < n;
         const int g = valid ? g_raw : n - 1;
-        // ---- forward recompute of the shading inputs
+        // ---- directions, Psi's inputs
         const float mx = sc.mean[g], my = sc.mean[n + g], mz = sc.mean[2 * n + g];
-        // w_i: toward a point light, or a directional light's fixed direction
         const float lm = a.light_dir ? 0.f : 1.f;
         float wix = a.light[0] - lm * mx, wiy = a.light[1] - lm * my, wiz = a.light[2] - lm * mz;
         const float ri = rsqrtf(wix * wix + wiy * wiy + wiz * wiz);
@@ -160,40 +202,9 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         float wox = a.eye[0] - mx, woy = a.eye[1] - my, woz = a.eye[2] - mz;
         const float ro = rsqrtf(wox * wox + woy * woy + woz * woz);
         wox *= ro; woy *= ro; woz *= ro;
-        float qw = sc.shade_rot[g], qx = sc.shade_rot[n + g], qy = sc.shade_rot[2 * n + g], qz = sc.shade_rot[3 * n + g];
-        const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-        const float rq = 1.f / qn;
-        qw *= rq; qx *= rq; qy *= rq; qz *= rq;
-        const float R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
-        const float R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
-        const float R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
-        const float lix = R00 * wix + R01 * wiy + R02 * wiz;
-        const float liy = R10 * wix + R11 * wiy + R12 * wiz;
-        const float liz = R20 * wix + R21 * wiy + R22 * wiz;
-        const float lox = R00 * wox + R01 * woy + R02 * woz;
-        const float loy = R10 * wox + R11 * woy + R12 * woz;
-        const float loz = R20 * wox + R21 * woy + R22 * woz;
-        const float elu = liz > 0.f ? liz : 0.01f * (expf(fminf(liz, 0.f)) - 1.f);
-        const float delu = liz > 0.f ? 1.f : 0.01f * expf(fminf(liz, 0.f));
-        const float fd = (elu + kd) * fd_norm;
-        float hx = lix + lox, hy = liy + loy, hz = liz + loz;
-        const float hn2 = hx * hx + hy * hy + hz * hz;
-        const bool hok = hn2 > 1e-24f;
-        float rh = 0.f;
-        if (hok) {
-            rh = rsqrtf(hn2);
-            hx *= rh; hy *= rh; hz *= rh;
-        } else {
-            hx = 0.f; hy = 0.f; hz = 1.f;
-        }
         // ---- upstream gradients
-        const float dc0 = a.gcol[g], dc1 = a.gcol[(size_t)n + g], dc2 = a.gcol[(size_t)2 * n + g];
         const float dtp = a.gcol[(size_t)3 * n + g];
         const float dr0 = a.gcol[(size_t)4 * n + g], dr1 = a.gcol[(size_t)5 * n + g], dr2 = a.gcol[(size_t)6 * n + g];
-        // ---- dL/dh of the lobes (Eq. 7), from k_shade_bwd_lobes
-        const float dhx = a.rows[(size_t)kDhRow * n + g];
-        const float dhy = a.rows[(size_t)(kDhRow + 1) * n + g];
-        const float dhz = a.rows[(size_t)(kDhRow + 2) * n + g];
         // ---- Phi([T, feat]) adjoint
         const float Tg = a.T[g];
         float dTg = dtp;
@@ -298,49 +309,15 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                 }
             }
         }
-        // ---- Lambertian, half vector, frames and directions
-        const float alb0 = sc.albedo[g], alb1 = sc.albedo[n + g], alb2 = sc.albedo[2 * n + g];
-        const float dfd = fmaf(dc0, alb0, fmaf(dc1, alb1, dc2 * alb2));
-        float dhsx = 0.f, dhsy = 0.f, dhsz = 0.f;
-        if (hok) {
-            const float dd = dhx * hx + dhy * hy + dhz * hz;
-            dhsx = (dhx - dd * hx) * rh;
-            dhsy = (dhy - dd * hy) * rh;
-            dhsz = (dhz - dd * hz) * rh;
-        }
-        const float dlix = dhsx, dliy = dhsy, dliz = dhsz + dfd * fd_norm * delu;
-        const float dlox = dhsx, dloy = dhsy, dloz = dhsz;
-        const float dR[9] = {dlix * wix + dlox * wox, dlix * wiy + dlox * woy, dlix * wiz + dlox * woz,
-                             dliy * wix + dloy * wox, dliy * wiy + dloy * woy, dliy * wiz + dloy * woz,
-                             dliz * wix + dloz * wox, dliz * wiy + dloz * woy, dliz * wiz + dloz * woz};
-        float dq[4];
-        quat_grad(qw, qx, qy, qz, qn, dR, dq);
-        // world directions: R^T dl plus Psi's direct inputs
-        const float dwx = R00 * dlix + R10 * dliy + R20 * dliz + pdwx;
-        const float dwy = R01 * dlix + R11 * dliy + R21 * dliz + pdwy;
-        const float dwz = R02 * dlix + R12 * dliy + R22 * dliz + pdwz;
-        const float dox = R00 * dlox + R10 * dloy + R20 * dloz + pdox;
-        const float doy = R01 * dlox + R11 * dloy + R21 * dloz + pdoy;
-        const float doz = R02 * dlox + R12 * dloy + R22 * dloz + pdoz;
-        // w = (p - mu)/|p - mu|: dmu = -(dw - (dw.w) w) / |p - mu|; a
-        // directional light's w_i does not depend on mu
-        const float wd = dwx * wix + dwy * wiy + dwz * wiz;
-        const float od = dox * wox + doy * woy + doz * woz;
-        const float rim = lm * ri;
-        const float dmx = -(dwx - wd * wix) * rim - (dox - od * wox) * ro;
-        const float dmy = -(dwy - wd * wiy) * rim - (doy - od * woy) * ro;
-        const float dmz = -(dwz - wd * wiz) * rim - (doz - od * woz) * ro;
+        // ---- Psi's direction gradients for k_shade_bwd_geom, and dT
         if (valid && q == 0) {
-            a.g.albedo[g] += dc0 * fd;
-            a.g.albedo[n + g] += dc1 * fd;
-            a.g.albedo[2 * n + g] += dc2 * fd;
-            a.g.shade_rot[g] += dq[0];
-            a.g.shade_rot[n + g] += dq[1];
-            a.g.shade_rot[2 * n + g] += dq[2];
-            a.g.shade_rot[3 * n + g] += dq[3];
-            a.g.mean[g] += dmx;
-            a.g.mean[n + g] += dmy;
-            a.g.mean[2 * n + g] += dmz;
+            float* pw = a.rows + (size_t)kDwRow * n + g;
+            pw[0] = pdwx;
+            pw[(size_t)n] = pdwy;
+            pw[(size_t)2 * n] = pdwz;
+            pw[(size_t)3 * n] = pdox;
+            pw[(size_t)4 * n] = pdoy;
+            pw[(size_t)5 * n] = pdoz;
             a.dT[g] = dTg;
         }
     }
@@ -883,9 +860,9 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     const int per_block = 8 * 16;
     int grid = (int)((sc.n + per_block - 1) / per_block);
     if (grid > 512) grid = 512;
-    const int64_t gl = (sc.n + 255) / 256;
-    hipLaunchKernelGGL(k_shade_bwd_lobes, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(512), 0, st, a);
+    const int64_t gl = (sc.n + 255) / 256;
+    hipLaunchKernelGGL(k_shade_bwd_geom, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!phi && !psi)) return e;
     // weight gradients: per-workgroup partial sums, then one fixed-order
