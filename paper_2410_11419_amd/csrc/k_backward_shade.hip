@@ -25,10 +25,16 @@ constexpr int kMlpRows = kPhiRows.size + kPsiRows.size;
 constexpr int kDwRow = kMlpRows;
 int mlp_scratch_rows() { return kMlpRows + 6; }
 
-constexpr MlpTSmem kPhiT = mlp_tsmem(kShadeSmem);
-constexpr MlpTSmem kPsiT = mlp_tsmem(kShadeSmem + kPhiT.size);
-constexpr int kShadeBwdSmem = kShadeSmem + kPhiT.size + kPsiT.size;
-static_assert(kShadeBwdSmem * 4 <= 160 * 1024, "shading adjoint LDS exceeds 160 KiB");
+// LDS of one MLP's adjoint launch (PART 1: Phi, 2: Psi): its packed forward
+// weights, then its transposed ones
+template <int PART>
+struct BwdLds {
+    static constexpr MlpSmem S = PART == 1 ? mlp_smem(0, kPhiKR, 1) : mlp_smem(0, kPsiKR, 3);
+    static constexpr MlpTSmem T = mlp_tsmem(S.size);
+    static constexpr int size = S.size + T.size;
+};
+static_assert(BwdLds<1>::size * 4 <= 80 * 1024 && BwdLds<2>::size * 4 <= 80 * 1024,
+              "each MLP adjoint fits half the LDS (two workgroups per CU)");
 
 struct ShadeBwdArgs {
     SceneDev sc;
@@ -171,17 +177,19 @@ __global__ __launch_bounds__(256) void k_shade_bwd_geom(ShadeBwdArgs a) {
     }
 }
 
-__global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
-    __shared__ __align__(16) float sm[kShadeBwdSmem];
+template <int PART>
+__global__ __launch_bounds__(512, 4) void k_shade_bwd(ShadeBwdArgs a) {
+    using L = BwdLds<PART>;
+    __shared__ __align__(16) float sm[L::size];
     const SceneDev& sc = a.sc;
     const int n = sc.n;
-    if (a.use_phi) {
-        load_mlp(sm, kPhiS, kPhiKR, kPhiIn, 1, a.phi);
-        load_mlp_t(sm, kPhiT, kPhiIn, a.phi);
+    if (PART == 1 && a.use_phi) {
+        load_mlp(sm, L::S, kPhiKR, kPhiIn, 1, a.phi);
+        load_mlp_t(sm, L::T, kPhiIn, a.phi);
     }
-    if (a.use_psi) {
-        load_mlp(sm, kPsiS, kPsiKR, kPsiIn, 3, a.psi);
-        load_mlp_t(sm, kPsiT, kPsiIn, a.psi);
+    if (PART == 2 && a.use_psi) {
+        load_mlp(sm, L::S, kPsiKR, kPsiIn, 3, a.psi);
+        load_mlp_t(sm, L::T, kPsiIn, a.psi);
     }
     __syncthreads();
     const int lane = __lane_id(), w = threadIdx.x >> 6, q = lane >> 4, l16 = lane & 15;
@@ -209,15 +217,15 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         const float Tg = a.T[g];
         float dTg = dtp;
         float phi_dx0[4] = {0.f, 0.f, 0.f, 0.f}, phi_dx1[4] = {0.f, 0.f, 0.f, 0.f};
-        if (a.use_phi) {
+        if (PART == 1 && a.use_phi) {
             floatx4 h[3][4];
             auto xin = [&](int k) -> float {
                 if (k == 0) return Tg;
                 if (k <= kFeat) return sc.feat[(size_t)(k - 1) * n + g];
                 return 0.f;
             };
-            mlp_hidden_all<kPhiKR>(sm, kPhiS, lane, xin, h);
-            const float tp = mlp_out(sm, kPhiS, lane, h[2], 0);
+            mlp_hidden_all<kPhiKR>(sm, L::S, lane, xin, h);
+            const float tp = mlp_out(sm, L::S, lane, h[2], 0);
             // the input goes to the scratch now; the adjoint needs only the
             // ReLU patterns of h (fewer live registers)
             if (valid) {
@@ -230,9 +238,9 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dh3[m][i] = sm[kPhiS.w4 + 16 * m + 4 * q + i] * d4;
+                for (int i = 0; i < 4; ++i) dh3[m][i] = sm[L::S.w4 + 16 * m + 4 * q + i] * d4;
             floatx4 dx[2];
-            mlp_backward_masked(sm, kPhiT, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
+            mlp_backward_masked(sm, L::T, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 phi_dx0[i] = dx[0][i];
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
         // ---- Psi([feat, w_i, w_o]) adjoint
         float psi_dx0[4] = {0.f, 0.f, 0.f, 0.f};
         float pdwx = 0.f, pdwy = 0.f, pdwz = 0.f, pdox = 0.f, pdoy = 0.f, pdoz = 0.f;
-        if (a.use_psi) {
+        if (PART == 2 && a.use_psi) {
             floatx4 h[3][4];
             auto xin = [&](int k) -> float {
                 if (k < kFeat) return sc.feat[(size_t)k * n + g];
@@ -259,10 +267,10 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                     default: return 0.f;
                 }
             };
-            mlp_hidden_all<kPsiKR>(sm, kPsiS, lane, xin, h);
-            const float r0 = mlp_out(sm, kPsiS, lane, h[2], 0);
-            const float r1 = mlp_out(sm, kPsiS, lane, h[2], 1);
-            const float r2 = mlp_out(sm, kPsiS, lane, h[2], 2);
+            mlp_hidden_all<kPsiKR>(sm, L::S, lane, xin, h);
+            const float r0 = mlp_out(sm, L::S, lane, h[2], 0);
+            const float r1 = mlp_out(sm, L::S, lane, h[2], 1);
+            const float r2 = mlp_out(sm, L::S, lane, h[2], 2);
             if (valid) {
                 float* R = a.rows;
                 for (int k = q; k < kPsiIn; k += 4) R[(size_t)(kPsiRows.x + k) * n + g] = xin(k);
@@ -275,11 +283,11 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = 16 * m + 4 * q + i;
-                    dh3[m][i] = fmaf(sm[kPsiS.w4 + r], d40,
-                                     fmaf(sm[kPsiS.w4 + 64 + r], d41, sm[kPsiS.w4 + 128 + r] * d42));
+                    dh3[m][i] = fmaf(sm[L::S.w4 + r], d40,
+                                     fmaf(sm[L::S.w4 + 64 + r], d41, sm[L::S.w4 + 128 + r] * d42));
                 }
             floatx4 dx[2];
-            mlp_backward_masked(sm, kPsiT, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
+            mlp_backward_masked(sm, L::T, lane, hmask, dh3, [](int, const floatx4*) {}, dx);
 #pragma unroll
             for (int i = 0; i < 4; ++i) psi_dx0[i] = dx[0][i];
             // rows 16..21 = w_i, w_o live in tile 1, quarters 0 and 1
@@ -296,29 +304,35 @@ __global__ __launch_bounds__(512) void k_shade_bwd(ShadeBwdArgs a) {
                 }
             }
         }
-        // ---- features: Phi row r + 1 and Psi row r of dx feed feat r
-        {
+        // ---- features: Phi row r + 1 (PART 1) or Psi row r (PART 2) of dx
+        // feeds feat r
+        if (PART == 1 && a.use_phi) {
             const float up0 = __shfl(phi_dx0[0], l16 + 16 * ((q + 1) & 3), 64);
             const float up1 = __shfl(phi_dx1[0], l16, 64);
             const float nxt = q < 3 ? up0 : up1;
             if (valid) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float pf = i < 3 ? phi_dx0[i + 1] : nxt;
-                    a.g.feat[(size_t)(4 * q + i) * n + g] += pf + psi_dx0[i];
-                }
+                for (int i = 0; i < 4; ++i)
+                    a.g.feat[(size_t)(4 * q + i) * n + g] += i < 3 ? phi_dx0[i + 1] : nxt;
             }
         }
-        // ---- Psi's direction gradients for k_shade_bwd_geom, and dT
+        if (PART == 2 && a.use_psi && valid) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a.g.feat[(size_t)(4 * q + i) * n + g] += psi_dx0[i];
+        }
+        // ---- dT (PART 1); Psi's direction gradients for k_shade_bwd_geom
+        // (PART 2)
         if (valid && q == 0) {
-            float* pw = a.rows + (size_t)kDwRow * n + g;
-            pw[0] = pdwx;
-            pw[(size_t)n] = pdwy;
-            pw[(size_t)2 * n] = pdwz;
-            pw[(size_t)3 * n] = pdox;
-            pw[(size_t)4 * n] = pdoy;
-            pw[(size_t)5 * n] = pdoz;
-            a.dT[g] = dTg;
+            if (PART == 1) a.dT[g] = dTg;
+            if (PART == 2) {
+                float* pw = a.rows + (size_t)kDwRow * n + g;
+                pw[0] = pdwx;
+                pw[(size_t)n] = pdwy;
+                pw[(size_t)2 * n] = pdwz;
+                pw[(size_t)3 * n] = pdox;
+                pw[(size_t)4 * n] = pdoy;
+                pw[(size_t)5 * n] = pdoz;
+            }
         }
     }
 }
@@ -855,12 +869,13 @@ hipError_t launch_shade_bwd(const SceneDev& sc, const ShadeParams& sp, const flo
     a.dT = dT;
     a.g = g;
     a.rows = rows;
-    // 161 KB of LDS: one workgroup per CU; 512 threads (two waves per SIMD,
-    // 256 registers each) share the weights
+    // each MLP's adjoint in its own launch with half the LDS: two 512-thread
+    // workgroups per CU (four waves per SIMD, 128 registers each)
     const int per_block = 8 * 16;
     int grid = (int)((sc.n + per_block - 1) / per_block);
     if (grid > 512) grid = 512;
-    hipLaunchKernelGGL(k_shade_bwd, dim3(grid), dim3(512), 0, st, a);
+    hipLaunchKernelGGL(k_shade_bwd<1>, dim3(grid), dim3(512), 0, st, a);
+    hipLaunchKernelGGL(k_shade_bwd<2>, dim3(grid), dim3(512), 0, st, a);
     const int64_t gl = (sc.n + 255) / 256;
     hipLaunchKernelGGL(k_shade_bwd_geom, dim3((unsigned)(gl < 2048 ? gl : 2048)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
